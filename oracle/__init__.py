@@ -1,0 +1,230 @@
+"""FP64 CPU oracle for the direct-summation force path of Phantom-GRAPE
+(arXiv:1203.4037).
+
+TEST INFRASTRUCTURE ONLY: only the test-suite, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The library
+package never does, and the two share no code: the arithmetic lives in
+``pgh_oracle.c`` (plain C, double precision, OpenMP over i-particles as in the
+paper's Sec. 3.5) and is wrapped here with ctypes and numpy.
+
+Every function takes the same FP32 arrays the GPU path receives and widens
+them to float64 (exactly) before the C code runs in double precision;
+finite-difference checks may pass float64 arrays directly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pgh_oracle.c")
+_LIB = os.path.join(_HERE, "libpgh_oracle.so")
+
+SHAPE_S2PP = 0
+SHAPE_PLUMMER_TAPER = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2 -fopenmp, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        l, i, d = ctypes.c_long, ctypes.c_int, ctypes.c_double
+        sig = {
+            "pgo_newton": [l, P, P, P, P, l, P, P, P, P, P, P, P, P, P],
+            "pgo_newton_items": [l, P, P, P, P, P, P, P, P, P, P, P, P, P],
+            "pgo_s2_R": [d, d],
+            "pgo_s2pp_f": [d, d, d],
+            "pgo_shape_h": [i, d, P],
+            "pgo_smax": [i, i],
+            "pgo_node_s": [i, i, l],
+            "pgo_node_r": [i, i, d, l],
+            "pgo_lut_index": [d, i, i, P],
+            "pgo_table_build": [i, i, d, i, P, P],
+            "pgo_lut_eval": [d, i, i, P],
+            "pgo_lut_items": [l, P, P, P, P, P, P, P, P, i, i, d, P, P, P, P, P],
+            "pgo_central_items": [l, P, P, P, P, P, P, P, P, i, P, P, P, P, P],
+            "pgo_newton_bwd": [l, P, P, P, P, l, P, P, P, P, P, P, P, P, P, P, P, P, P, P],
+            "pgo_lut_bwd_items": [l, P, P, P, P, P, P, P, P, P, P, P, i, i, d, P, P, P, l],
+        }
+        ret = {"pgo_s2_R": d, "pgo_s2pp_f": d, "pgo_shape_h": d, "pgo_smax": d,
+               "pgo_node_s": d, "pgo_node_r": d, "pgo_lut_index": l, "pgo_lut_eval": d}
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ret.get(name, None)
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    """Widen to float64 (exact for the FP32 inputs the GPU receives)."""
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _items32(items):
+    return np.ascontiguousarray(np.asarray(items, dtype=np.int32).reshape(-1, 4))
+
+
+# --------------------------------------------------------------------------
+# Newton's force (Eq. newton_force)
+# --------------------------------------------------------------------------
+
+def newton(xi, yi, zi, eps2i, xj, yj, zj, mj, self_j=None):
+    """a_i = sum_j m_j d/(|d|^2+eps_i^2)^{3/2}, phi_i = -sum_j m_j/(|d|^2+eps_i^2)^{1/2}.
+
+    ``self_j``: optional int array, per i the j index to skip (-1 none).
+    Returns (ax, ay, az, phi) as float64 arrays.
+    """
+    xi, yi, zi, eps2i = map(_f64, (xi, yi, zi, eps2i))
+    xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
+    ni, nj = xi.size, xj.size
+    out = [np.zeros(ni) for _ in range(4)]
+    sj = None if self_j is None else np.ascontiguousarray(self_j, dtype=np.int64)
+    lib().pgo_newton(ni, _ptr(xi), _ptr(yi), _ptr(zi), _ptr(eps2i), nj, _ptr(xj), _ptr(yj),
+                     _ptr(zj), _ptr(mj), _ptr(sj), *[_ptr(o) for o in out])
+    return tuple(out)
+
+
+def newton_items(items, xi, yi, zi, eps2i, xj, yj, zj, mj, with_phi=True):
+    it = _items32(items)
+    xi, yi, zi, eps2i = map(_f64, (xi, yi, zi, eps2i))
+    xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
+    ni = xi.size
+    out = [np.full(ni, np.nan) for _ in range(4)]
+    lib().pgo_newton_items(it.shape[0], _ptr(it), _ptr(xi), _ptr(yi), _ptr(zi), _ptr(eps2i),
+                           _ptr(xj), _ptr(yj), _ptr(zj), _ptr(mj), _ptr(out[0]), _ptr(out[1]),
+                           _ptr(out[2]), _ptr(out[3]) if with_phi else None)
+    return tuple(out)
+
+
+# --------------------------------------------------------------------------
+# Force shapes and the bit-binned table (Sec. 3.4, Sec. 4.2)
+# --------------------------------------------------------------------------
+
+def s2_R(r, a):
+    return lib().pgo_s2_R(float(r), float(a))
+
+
+def s2pp_f(r, eps, rcut):
+    return lib().pgo_s2pp_f(float(r), float(eps), float(rcut))
+
+
+def shape_h(shape, r, eps, rcut):
+    p = np.array([eps, rcut], dtype=np.float64)
+    return lib().pgo_shape_h(int(shape), float(r), _ptr(p))
+
+
+def smax(E, F):
+    return lib().pgo_smax(E, F)
+
+
+def node_s(E, F, k):
+    return lib().pgo_node_s(E, F, int(k))
+
+
+def node_r(E, F, rcut, k):
+    return lib().pgo_node_r(E, F, float(rcut), int(k))
+
+
+def lut_index(s, E, F):
+    sk = ctypes.c_double()
+    k = lib().pgo_lut_index(float(s), E, F, ctypes.byref(sk))
+    return int(k), sk.value
+
+
+def table_build(E, F, rcut, shape, eps):
+    """Returns the interleaved FP32 table (G0_0, G1_0, G0_1, ...) of length 2^(E+F+1)."""
+    K = 1 << (E + F)
+    t = np.zeros(2 * K, dtype=np.float32)
+    p = np.array([eps, rcut], dtype=np.float64)
+    lib().pgo_table_build(E, F, float(rcut), int(shape), _ptr(p), _ptr(t))
+    return t
+
+
+def lut_eval(s, E, F, table):
+    t = _f64(table)
+    return lib().pgo_lut_eval(float(s), E, F, _ptr(t))
+
+
+def lut_items(items, xi, yi, zi, xj, yj, zj, mj, E, F, rcut, table):
+    """Table force over interaction lists. Returns (ax, ay, az, absum)."""
+    it = _items32(items)
+    xi, yi, zi = map(_f64, (xi, yi, zi))
+    xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
+    t = _f64(table)
+    ni = xi.size
+    out = [np.full(ni, np.nan) for _ in range(4)]
+    lib().pgo_lut_items(it.shape[0], _ptr(it), _ptr(xi), _ptr(yi), _ptr(zi), _ptr(xj),
+                        _ptr(yj), _ptr(zj), _ptr(mj), E, F, float(rcut), _ptr(t),
+                        *[_ptr(o) for o in out])
+    return tuple(out)
+
+
+def central_items(items, xi, yi, zi, xj, yj, zj, mj, shape, eps, rcut):
+    """Exact central force with the analytic h = f/r. Returns (ax, ay, az, absum)."""
+    it = _items32(items)
+    xi, yi, zi = map(_f64, (xi, yi, zi))
+    xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
+    p = np.array([eps, rcut], dtype=np.float64)
+    ni = xi.size
+    out = [np.full(ni, np.nan) for _ in range(4)]
+    lib().pgo_central_items(it.shape[0], _ptr(it), _ptr(xi), _ptr(yi), _ptr(zi), _ptr(xj),
+                            _ptr(yj), _ptr(zj), _ptr(mj), int(shape), _ptr(p),
+                            *[_ptr(o) for o in out])
+    return tuple(out)
+
+
+# --------------------------------------------------------------------------
+# Adjoints of L = sum_i w_i . a_i
+# --------------------------------------------------------------------------
+
+def newton_bwd(xi, yi, zi, eps2i, xj, yj, zj, mj, wx, wy, wz):
+    """Returns (gxi, gyi, gzi, gxj, gyj, gzj, gmj) as float64 arrays."""
+    xi, yi, zi, eps2i = map(_f64, (xi, yi, zi, eps2i))
+    xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
+    wx, wy, wz = map(_f64, (wx, wy, wz))
+    ni, nj = xi.size, xj.size
+    gi = [np.zeros(ni) for _ in range(3)]
+    gj = [np.zeros(nj) for _ in range(4)]
+    lib().pgo_newton_bwd(ni, _ptr(xi), _ptr(yi), _ptr(zi), _ptr(eps2i), nj, _ptr(xj),
+                         _ptr(yj), _ptr(zj), _ptr(mj), _ptr(wx), _ptr(wy), _ptr(wz),
+                         *[_ptr(o) for o in gi], *[_ptr(o) for o in gj])
+    return tuple(gi) + tuple(gj)
+
+
+def lut_bwd_items(items, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, E, F, rcut, table):
+    """Returns (gtable float64[2K] interleaved like the table, gmj float64[nj])."""
+    it = _items32(items)
+    xi, yi, zi = map(_f64, (xi, yi, zi))
+    xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
+    wx, wy, wz = map(_f64, (wx, wy, wz))
+    t = _f64(table)
+    K = 1 << (E + F)
+    gt = np.zeros(2 * K)
+    gm = np.zeros(xj.size)
+    lib().pgo_lut_bwd_items(it.shape[0], _ptr(it), _ptr(xi), _ptr(yi), _ptr(zi), _ptr(xj),
+                            _ptr(yj), _ptr(zj), _ptr(mj), _ptr(wx), _ptr(wy), _ptr(wz), E, F,
+                            float(rcut), _ptr(t), _ptr(gt), _ptr(gm), xj.size)
+    return gt, gm

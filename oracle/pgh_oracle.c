@@ -1,0 +1,450 @@
+/*
+ * pgh_oracle.c -- FP64 reference implementation of the direct-summation
+ * force path of Phantom-GRAPE (Tanikawa, Yoshikawa, Nitadori & Okamoto,
+ * arXiv:1203.4037).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library package may include,
+ * link, load or call this file; only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark do.  It shares no code, header, table or
+ * constant with the GPU path: every formula here is written out again from the
+ * paper, in double precision, with plain loops.
+ *
+ * Conventions (the readings of the paper this file follows):
+ *   - G = 1: the paper's API carries no gravitational constant (Sec. 3.6), so
+ *     masses carry the units.
+ *   - The potential is phi_i = -sum_j m_j / sqrt(r_ij^2 + eps_i^2): the Newton
+ *     kernel of Sec. 3.3 subtracts m_j/r from the potential register at every
+ *     step (step 7 with the listing's subtract semantics).
+ *   - Softening is per i-particle (the i-particle structure of Sec. 3.1 holds
+ *     eps^2 for each i).
+ *   - A pair at zero softened distance (eps = 0 and coincident particles)
+ *     contributes nothing: the paper does not discuss it and 1/0 is undefined.
+ *   - Every array argument is double.  Callers pass the same FP32 values the
+ *     GPU receives, widened exactly, so the quantisation of the inputs is
+ *     shared and is not counted as error; finite-difference checks perturb
+ *     them in double.
+ *
+ * Parallelism: OpenMP over i-particles (or over independent items), which is
+ * how the paper spreads groups of i-particles over cores (Sec. 3.5).
+ * Compile with -O2 -fopenmp and without -ffast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PGO_EXPORT __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------------ */
+/* Newton's force and potential: Eq. (newton_force), Sec. 3.                 */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * a_i   =  sum_j m_j (r_j - r_i) / (|r_j - r_i|^2 + eps_i^2)^{3/2}
+ * phi_i = -sum_j m_j            / (|r_j - r_i|^2 + eps_i^2)^{1/2}
+ *
+ * self_j: NULL, or for every i the index of the j-particle that is i itself
+ * (-1 for none).  That pair is skipped ("physical" potential, the way the
+ * paper's double-precision reference avoids the self-interaction, Sec. 4.1).
+ * With self_j == NULL every pair is summed, including a coincident j = i,
+ * which leaves the self term -m_i/eps_i in phi_i ("raw" potential, the way the
+ * SIMD kernel accumulates it, Sec. 4.1).
+ */
+PGO_EXPORT void pgo_newton(long ni, const double *xi, const double *yi, const double *zi,
+                           const double *eps2i, long nj, const double *xj, const double *yj,
+                           const double *zj, const double *mj, const long *self_j,
+                           double *ax, double *ay, double *az, double *phi)
+{
+    long i;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (i = 0; i < ni; i++) {
+        double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+        const double px = xi[i], py = yi[i], pz = zi[i], e2 = eps2i[i];
+        const long skip = self_j ? self_j[i] : -1;
+        for (long j = 0; j < nj; j++) {
+            if (j == skip) continue;
+            const double dx = (double)xj[j] - px;
+            const double dy = (double)yj[j] - py;
+            const double dz = (double)zj[j] - pz;
+            const double q = dx * dx + dy * dy + dz * dz + e2;
+            if (q == 0.0) continue;
+            const double rinv = 1.0 / sqrt(q);
+            const double rinv3 = rinv * rinv * rinv;
+            const double m = mj[j];
+            sx += m * dx * rinv3;
+            sy += m * dy * rinv3;
+            sz += m * dz * rinv3;
+            sp -= m * rinv;
+        }
+        ax[i] = sx;
+        ay[i] = sy;
+        az[i] = sz;
+        if (phi) phi[i] = sp;
+    }
+}
+
+/*
+ * Interaction lists: item t couples the i-particles [i_off, i_off+n_i) with the
+ * j-particles [j_off, j_off+n_j) of the given arrays (a tree or cell-list
+ * group sharing one list, Sec. 5.1).  items is int32 [n_items][4] =
+ * {i_off, n_i, j_off, n_j}.  i-ranges are disjoint; rows not covered by an
+ * item are left untouched.
+ */
+PGO_EXPORT void pgo_newton_items(long n_items, const int32_t *items, const double *xi,
+                                 const double *yi, const double *zi, const double *eps2i,
+                                 const double *xj, const double *yj, const double *zj,
+                                 const double *mj, double *ax, double *ay, double *az,
+                                 double *phi)
+{
+    long t;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (t = 0; t < n_items; t++) {
+        const long i0 = items[4 * t + 0], n_i = items[4 * t + 1];
+        const long j0 = items[4 * t + 2], n_j = items[4 * t + 3];
+        pgo_newton(n_i, xi + i0, yi + i0, zi + i0, eps2i + i0, n_j, xj + j0, yj + j0, zj + j0,
+                   mj + j0, NULL, ax + i0, ay + i0, az + i0, phi ? phi + i0 : NULL);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Force shapes f(r) with a finite cutoff: Eq. (arbitrary_force), Sec. 4.2.  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * S2 force profile R(r, a) of Hockney & Eastwood, Eq. (s2), with xi = 2r/a.
+ * Both polynomial branches are divided by 35 a^2: continuity at xi = 1
+ * (both give 97) and at xi = 2 (the second gives 35, i.e. 1/a^2 = 1/r^2)
+ * fixes the denominator that the printed second branch garbles.
+ */
+PGO_EXPORT double pgo_s2_R(double r, double a)
+{
+    const double xi = 2.0 * r / a;
+    if (xi < 1.0) {
+        const double x2 = xi * xi, x3 = x2 * xi, x4 = x3 * xi, x5 = x4 * xi, x6 = x5 * xi;
+        return (224.0 * xi - 224.0 * x3 + 70.0 * x4 + 48.0 * x5 - 21.0 * x6) / (35.0 * a * a);
+    }
+    if (xi < 2.0) {
+        const double x2 = xi * xi, x3 = x2 * xi, x4 = x3 * xi, x5 = x4 * xi, x6 = x5 * xi;
+        return (12.0 / x2 - 224.0 + 896.0 * xi - 840.0 * x2 + 224.0 * x3 + 70.0 * x4
+                - 48.0 * x5 + 7.0 * x6) / (35.0 * a * a);
+    }
+    return 1.0 / (r * r);
+}
+
+/* Particle-particle part of the S2 split, Eq. (s2pp): f = R(r,eps) - R(r,rcut). */
+PGO_EXPORT double pgo_s2pp_f(double r, double eps, double rcut)
+{
+    if (r >= rcut) return 0.0;
+    return pgo_s2_R(r, eps) - pgo_s2_R(r, rcut);
+}
+
+/*
+ * Shapes of h(r) = f(r)/r, the quantity the table holds (G0_k = f(r_k)/r_k,
+ * Sec. 3.4.1).  params = {eps, rcut}.
+ *   PGO_SHAPE_S2PP    f = R(r,eps) - R(r,rcut); h(0) is its analytic limit,
+ *                     R(r,a)/r -> 448/(35 a^3) as r -> 0 (first branch).
+ *   PGO_SHAPE_PLUMMER_TAPER  h = (r^2+eps^2)^{-3/2} T(r/rcut), T = 1 on
+ *                     [0, 1/2], a quintic smoothstep down to 0 at 1: inside
+ *                     rcut/2 this is exactly the softened Newtonian f/r.
+ */
+enum { PGO_SHAPE_S2PP = 0, PGO_SHAPE_PLUMMER_TAPER = 1 };
+
+static double taper(double x)
+{
+    if (x <= 0.5) return 1.0;
+    if (x >= 1.0) return 0.0;
+    const double t = (x - 0.5) / 0.5;
+    return 1.0 - t * t * t * (10.0 - 15.0 * t + 6.0 * t * t);
+}
+
+PGO_EXPORT double pgo_shape_h(int shape, double r, const double *params)
+{
+    const double eps = params[0], rcut = params[1];
+    if (r >= rcut) return 0.0;
+    if (shape == PGO_SHAPE_S2PP) {
+        if (r == 0.0) return 448.0 / (35.0 * eps * eps * eps) - 448.0 / (35.0 * rcut * rcut * rcut);
+        return pgo_s2pp_f(r, eps, rcut) / r;
+    }
+    /* PGO_SHAPE_PLUMMER_TAPER */
+    const double q = r * r + eps * eps;
+    return taper(r / rcut) / (q * sqrt(q));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bit-binned look-up table: Sec. 3.4.1 (Eqs. for s, s_{bE,bF}, G0, G1).    */
+/* ------------------------------------------------------------------------ */
+
+/* s_max = 2^{2^E} (2 - 2^{-F}); s_min = 2. */
+PGO_EXPORT double pgo_smax(int E, int F)
+{
+    return ldexp(1.0, 1 << E) * (2.0 - ldexp(1.0, -F));
+}
+
+/* Node k = 2^F bE + bF sits at s_k = 2^{bE+1} (1 + bF / 2^F). */
+PGO_EXPORT double pgo_node_s(int E, int F, long k)
+{
+    (void)E;
+    const long bE = k / (1L << F), bF = k % (1L << F);
+    return ldexp(1.0, (int)bE + 1) * (1.0 + (double)bF / (double)(1L << F));
+}
+
+/* Radius of node k: s = r^2 (s_max - 2)/rcut^2 + 2 solved for r. */
+PGO_EXPORT double pgo_node_r(int E, int F, double rcut, long k)
+{
+    const double s = pgo_node_s(E, F, k);
+    return rcut * sqrt((s - 2.0) / (pgo_smax(E, F) - 2.0));
+}
+
+/*
+ * Table index of s in [2, s_max], written from the arithmetic meaning of the
+ * extracted bits rather than from the bits: bE = floor(log2 s) - 1 and
+ * bF = floor((s / 2^{bE+1} - 1) 2^F), k = 2^F bE + bF.  frexp gives
+ * s = mant 2^e with mant in [1/2, 1), so floor(log2 s) = e - 1 exactly.
+ * Writes s_k (the node at or below s) to *s_node when non-NULL.
+ */
+PGO_EXPORT long pgo_lut_index(double s, int E, int F, double *s_node)
+{
+    int e;
+    (void)frexp(s, &e);
+    const long bE = (long)(e - 1) - 1;
+    const double scaled = ldexp(s, -(int)(bE + 1)); /* in [1, 2) */
+    const long bF = (long)floor((scaled - 1.0) * ldexp(1.0, F));
+    const long k = bE * (1L << F) + bF;
+    if (s_node) *s_node = pgo_node_s(E, F, k);
+    return k;
+}
+
+/*
+ * Table of (G0_k, G1_k), interleaved as float[2K] (the paper's
+ * Force_table[K][2]).  G0_k = fl32(h(r_k)); G0 at the last node, r = rcut, is
+ * set to 0 because f(rcut) = 0.  G1_k = fl32((G0_{k+1} - G0_k)/(s_{k+1} - s_k))
+ * from the rounded G0, and G1 of the last node is 0.
+ */
+PGO_EXPORT void pgo_table_build(int E, int F, double rcut, int shape, const double *params,
+                                float *table)
+{
+    const long K = 1L << (E + F);
+    for (long k = 0; k < K; k++) {
+        const double r = pgo_node_r(E, F, rcut, k);
+        table[2 * k] = (k == K - 1) ? 0.0f : (float)pgo_shape_h(shape, r, params);
+    }
+    for (long k = 0; k < K - 1; k++) {
+        const double ds = pgo_node_s(E, F, k + 1) - pgo_node_s(E, F, k);
+        table[2 * k + 1] = (float)(((double)table[2 * k + 2] - (double)table[2 * k]) / ds);
+    }
+    table[2 * K - 1] = 0.0f;
+}
+
+/* Linear interpolation of h at affine-transformed distance s (steps 1-5 of
+ * the force procedure, Sec. 3.4.2): g = G0_k + G1_k (s - s_k). */
+PGO_EXPORT double pgo_lut_eval(double s, int E, int F, const double *table)
+{
+    const double smax = pgo_smax(E, F);
+    if (s > smax) s = smax;
+    double sk;
+    const long k = pgo_lut_index(s, E, F, &sk);
+    return (double)table[2 * k] + (double)table[2 * k + 1] * (s - sk);
+}
+
+/*
+ * Central force from the table, Eq. (arbitrary_force) with the force
+ * procedure of Sec. 3.4.2.  absum_i = sum_j m_j |g| |d| (NULL to skip) is the
+ * scale that errors of this sum with cancellation are measured against.  The paper pre-scales positions by
+ * sqrt(s_max-2)/rcut so that s = |dr~|^2 + 2 and rescales the sum at the end;
+ * here s = (s_max-2)/rcut^2 |d|^2 + 2 with unscaled d, which is the same
+ * number in exact arithmetic and needs no rescale.
+ */
+PGO_EXPORT void pgo_lut_items(long n_items, const int32_t *items, const double *xi,
+                              const double *yi, const double *zi, const double *xj,
+                              const double *yj, const double *zj, const double *mj, int E, int F,
+                              double rcut, const double *table, double *ax, double *ay,
+                              double *az, double *absum)
+{
+    const double smax = pgo_smax(E, F);
+    const double c = (smax - 2.0) / (rcut * rcut);
+    long t;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (t = 0; t < n_items; t++) {
+        const long i0 = items[4 * t + 0], n_i = items[4 * t + 1];
+        const long j0 = items[4 * t + 2], n_j = items[4 * t + 3];
+        for (long i = i0; i < i0 + n_i; i++) {
+            double sx = 0.0, sy = 0.0, sz = 0.0, sa = 0.0;
+            for (long j = j0; j < j0 + n_j; j++) {
+                const double dx = (double)xj[j] - (double)xi[i];
+                const double dy = (double)yj[j] - (double)yi[i];
+                const double dz = (double)zj[j] - (double)zi[i];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                double s = c * r2 + 2.0;
+                if (s > smax) s = smax;
+                double sk;
+                const long k = pgo_lut_index(s, E, F, &sk);
+                const double g = (double)table[2 * k] + (double)table[2 * k + 1] * (s - sk);
+                const double m = mj[j];
+                sx += m * g * dx;
+                sy += m * g * dy;
+                sz += m * g * dz;
+                sa += fabs(m * g) * sqrt(r2);
+            }
+            ax[i] = sx;
+            ay[i] = sy;
+            az[i] = sz;
+            if (absum) absum[i] = sa;
+        }
+    }
+}
+
+/*
+ * Analytic companion of the table force: a_i = sum_j m_j h(r_ij) d_ij with the
+ * exact h = f/r, for measuring the table error.  absum_i = sum_j m_j |h| |d|
+ * (the scale used to normalise errors of a sum with cancellation).
+ */
+PGO_EXPORT void pgo_central_items(long n_items, const int32_t *items, const double *xi,
+                                  const double *yi, const double *zi, const double *xj,
+                                  const double *yj, const double *zj, const double *mj, int shape,
+                                  const double *params, double *ax, double *ay, double *az,
+                                  double *absum)
+{
+    long t;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (t = 0; t < n_items; t++) {
+        const long i0 = items[4 * t + 0], n_i = items[4 * t + 1];
+        const long j0 = items[4 * t + 2], n_j = items[4 * t + 3];
+        for (long i = i0; i < i0 + n_i; i++) {
+            double sx = 0.0, sy = 0.0, sz = 0.0, sa = 0.0;
+            for (long j = j0; j < j0 + n_j; j++) {
+                const double dx = (double)xj[j] - (double)xi[i];
+                const double dy = (double)yj[j] - (double)yi[i];
+                const double dz = (double)zj[j] - (double)zi[i];
+                const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                const double h = pgo_shape_h(shape, r, params);
+                const double m = mj[j];
+                sx += m * h * dx;
+                sy += m * h * dy;
+                sz += m * h * dz;
+                sa += fabs(m * h) * r;
+            }
+            ax[i] = sx;
+            ay[i] = sy;
+            az[i] = sz;
+            if (absum) absum[i] = sa;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoints of L = sum_i w_i . a_i (chain rule applied to the two forces).   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Newton, general i/j sets.  With d = r_j - r_i, rho = (|d|^2+eps_i^2)^{-1/2}
+ * and the pair term T = m_j rho^3 (w_i . d):
+ *   dT/dd = m_j [rho^3 w_i - 3 rho^5 (w_i . d) d],  dd/dr_j = I,  dd/dr_i = -I,
+ *   dT/dm_j = rho^3 (w_i . d).
+ * gxi_i = -sum_j dT/dd;  gxj_j = sum_i dT/dd;  gmj_j = sum_i rho^3 (w_i . d).
+ * Any output pointer may be NULL.  Pairs with zero softened distance are
+ * skipped like in the forward sum.
+ */
+PGO_EXPORT void pgo_newton_bwd(long ni, const double *xi, const double *yi, const double *zi,
+                               const double *eps2i, long nj, const double *xj, const double *yj,
+                               const double *zj, const double *mj, const double *wx,
+                               const double *wy, const double *wz, double *gxi, double *gyi,
+                               double *gzi, double *gxj, double *gyj, double *gzj, double *gmj)
+{
+    long i, j;
+    if (gxi) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (i = 0; i < ni; i++) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (long jj = 0; jj < nj; jj++) {
+                const double dx = (double)xj[jj] - xi[i];
+                const double dy = (double)yj[jj] - yi[i];
+                const double dz = (double)zj[jj] - zi[i];
+                const double q = dx * dx + dy * dy + dz * dz + (double)eps2i[i];
+                if (q == 0.0) continue;
+                const double rho = 1.0 / sqrt(q);
+                const double rho3 = rho * rho * rho, rho5 = rho3 * rho * rho;
+                const double wd = (double)wx[i] * dx + (double)wy[i] * dy + (double)wz[i] * dz;
+                const double m = mj[jj];
+                s0 -= m * (rho3 * wx[i] - 3.0 * rho5 * wd * dx);
+                s1 -= m * (rho3 * wy[i] - 3.0 * rho5 * wd * dy);
+                s2 -= m * (rho3 * wz[i] - 3.0 * rho5 * wd * dz);
+            }
+            gxi[i] = s0;
+            gyi[i] = s1;
+            gzi[i] = s2;
+        }
+    }
+    if (gxj || gmj) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (j = 0; j < nj; j++) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, sm = 0.0;
+            for (long ii = 0; ii < ni; ii++) {
+                const double dx = (double)xj[j] - xi[ii];
+                const double dy = (double)yj[j] - yi[ii];
+                const double dz = (double)zj[j] - zi[ii];
+                const double q = dx * dx + dy * dy + dz * dz + (double)eps2i[ii];
+                if (q == 0.0) continue;
+                const double rho = 1.0 / sqrt(q);
+                const double rho3 = rho * rho * rho, rho5 = rho3 * rho * rho;
+                const double wd = (double)wx[ii] * dx + (double)wy[ii] * dy + (double)wz[ii] * dz;
+                const double m = mj[j];
+                s0 += m * (rho3 * wx[ii] - 3.0 * rho5 * wd * dx);
+                s1 += m * (rho3 * wy[ii] - 3.0 * rho5 * wd * dy);
+                s2 += m * (rho3 * wz[ii] - 3.0 * rho5 * wd * dz);
+                sm += rho3 * wd;
+            }
+            if (gxj) {
+                gxj[j] = s0;
+                gyj[j] = s1;
+                gzj[j] = s2;
+            }
+            if (gmj) gmj[j] = sm;
+        }
+    }
+}
+
+/*
+ * Table force adjoint over interaction lists.  With g = G0_k + G1_k (s - s_k)
+ * and the pair term T = m_j g (w_i . d):
+ *   dL/dG0_k = sum over pairs in bin k of m_j (w_i . d)
+ *   dL/dG1_k = sum over pairs in bin k of m_j (s - s_k) (w_i . d)
+ *   dL/dm_j  = sum_i g (w_i . d)
+ * G0 and G1 are treated as independent leaves.  gtab is double[2K]
+ * interleaved like the table; gmj is per j entry of the arrays (an entry used
+ * by several items accumulates over them).  Items run one after another so
+ * that no two threads add into the same j entry or bin.
+ */
+PGO_EXPORT void pgo_lut_bwd_items(long n_items, const int32_t *items, const double *xi,
+                                  const double *yi, const double *zi, const double *xj,
+                                  const double *yj, const double *zj, const double *mj,
+                                  const double *wx, const double *wy, const double *wz, int E,
+                                  int F, double rcut, const double *table, double *gtab,
+                                  double *gmj, long nj_total)
+{
+    const long K = 1L << (E + F);
+    const double smax = pgo_smax(E, F);
+    const double c = (smax - 2.0) / (rcut * rcut);
+    memset(gtab, 0, sizeof(double) * 2 * K);
+    if (gmj) memset(gmj, 0, sizeof(double) * nj_total);
+    for (long t = 0; t < n_items; t++) {
+        const long i0 = items[4 * t + 0], n_i = items[4 * t + 1];
+        const long j0 = items[4 * t + 2], n_j = items[4 * t + 3];
+        for (long i = i0; i < i0 + n_i; i++) {
+            for (long j = j0; j < j0 + n_j; j++) {
+                const double dx = (double)xj[j] - (double)xi[i];
+                const double dy = (double)yj[j] - (double)yi[i];
+                const double dz = (double)zj[j] - (double)zi[i];
+                double s = c * (dx * dx + dy * dy + dz * dz) + 2.0;
+                if (s > smax) s = smax;
+                double sk;
+                const long k = pgo_lut_index(s, E, F, &sk);
+                const double g = (double)table[2 * k] + (double)table[2 * k + 1] * (s - sk);
+                const double wd = (double)wx[i] * dx + (double)wy[i] * dy + (double)wz[i] * dz;
+                const double m = mj[j];
+                gtab[2 * k] += m * wd;
+                gtab[2 * k + 1] += m * (s - sk) * wd;
+                if (gmj) gmj[j] += g * wd;
+            }
+        }
+    }
+}
