@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the direct-summation force path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+
+Headline workload: Newton all-pairs on a Plummer sphere of N = 262144
+particles (scale radius 1, seed 102), equal masses 1/N, softening 0.01,
+FP32, i-set = j-set.  One step is the whole path for one set of positions:
+pgh_set_xmj (pack the j-particles into the library's records) followed by
+pgh_calc_newton (accelerations and potentials), the GRAPE call sequence of
+the paper's sample driver (Sec. 3.6).  Inputs are resident in device memory
+before the timed region.
+
+Prints ONE JSON line with the headline value (interactions per second), the
+roofline object of the dominant kernel (pgh_calc_newton, FP32 ALU bound, 38
+flops per interaction as the paper counts them, against the 157.3 TFLOP/s
+FP32 vector peak), the FP64 oracle timed on a bounded sample on the host
+cores, and secondary measurements of the other force paths.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+PEAK_FP32_TFLOPS = 157.3  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
+NEWTON_FLOPS = 38  # per interaction, the paper's count (Sec. 5.1)
+TABLE_FLOPS = 20  # per interaction, this project's count of the FP32 ops of the table loop
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target wall time of the CPU baseline sample")
+    return ap.parse_args()
+
+
+class KernelTimer:
+    """HIP events around library calls on torch's current stream (the stream
+    the library launches on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = []
+
+    def __enter__(self):
+        self.a = self.torch.cuda.Event(enable_timing=True)
+        self.b = self.torch.cuda.Event(enable_timing=True)
+        self.a.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record()
+        self.pairs.append((self.a, self.b))
+
+    def mean_ms(self):
+        self.torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in self.pairs]))
+
+
+def time_steps(torch, step, steps, warmup):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(x, y, z, m, eps, target_s):
+    """FP64 oracle (plain loops, OpenMP over i) on a sample of i-particles
+    against all j, scaled to interactions per second."""
+    import oracle
+    n = x.size
+    e2 = np.float32(eps) ** 2
+    cal = np.arange(0, n, max(1, n // 256))
+    t0 = time.perf_counter()
+    oracle.newton(x[cal], y[cal], z[cal], np.full(cal.size, e2, np.float32), x, y, z, m)
+    rate = cal.size * n / (time.perf_counter() - t0)
+    ns = int(min(n, max(256, rate * target_s / n)))
+    idx = np.linspace(0, n - 1, ns).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.newton(x[idx], y[idx], z[idx], np.full(ns, e2, np.float32), x, y, z, m)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    return {"value": ns * n / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, {ns} evenly spaced i-particles x all {n} j-particles "
+                      f"({ns * n:.3e} interactions) in {dt:.1f} s"}
+
+
+def newton_allpairs(torch, pgh, synth, args):
+    n = args.n
+    x, y, z = synth.plummer(n, 102)
+    m = synth.equal_masses(n)
+    dev = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+    out = [torch.empty(n, device="cuda") for _ in range(4)]
+    ctx = pgh.Context(0)
+    ctx.set_eps_to_all(0.01)
+    pgh.pgh_set_stream(ctx.h, torch.cuda.current_stream().cuda_stream)
+    timer = KernelTimer(torch)
+    timing = {"on": False}
+
+    def step():
+        pgh.pgh_set_xmj(ctx.h, 0, n, *dev)
+        pgh.pgh_set_n(ctx.h, n)
+        if timing["on"]:
+            with timer:
+                pgh.pgh_calc_newton(ctx.h, n, dev[0], dev[1], dev[2], None, *out)
+        else:
+            pgh.pgh_calc_newton(ctx.h, n, dev[0], dev[1], dev[2], None, *out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    timing["on"] = True
+    sec = time_steps(torch, step, args.steps, 0)
+    kern_ms = timer.mean_ms()
+    variant = pgh.pgh_get_variant(ctx.h, pgh.PGH_FAMILY_NEWTON_ALLPAIRS)
+    ctx.close()
+    return {"n": n, "x": (x, y, z, m), "sec": sec, "kern_ms": kern_ms, "variant": variant}
+
+
+def table_allpairs(torch, pgh, synth):
+    """Secondary: the table force on the same kind of call, N = 65536 uniform
+    particles in a box of side 0.25 with the S2 PP shape (rcut = 3/256,
+    eps = 1/1280, E = 4, F = 6), all pairs evaluated (most beyond rcut)."""
+    n = 65536
+    x, y, z = synth.uniform_box(n, 103, box=0.25)
+    m = synth.equal_masses(n)
+    dev = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+    ctx = pgh.Context(0)
+    ctx.build_table(4, 6, 3.0 / 256, eps=1.0 / 1280)
+    ctx.set_j(*dev)
+    out = [torch.empty(n, device="cuda") for _ in range(3)]
+    timer = KernelTimer(torch)
+
+    def step():
+        with timer:
+            pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out)
+
+    sec = time_steps(torch, step, 10, 2)
+    ms = timer.mean_ms()
+    ctx.close()
+    inter = float(n) * n
+    return {"workload": "table_allpairs_uniform_N65536_E4F6", "interactions_per_s": inter / (ms / 1e3),
+            "kernel_ms": ms, "step_ms": sec * 1e3,
+            "frac_of_peak_20flop": TABLE_FLOPS * inter / (ms / 1e3) / (PEAK_FP32_TFLOPS * 1e12)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1203_4037_amd as pgh
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    r = newton_allpairs(torch, pgh, synth, args)
+    n = r["n"]
+    inter = float(n) * n
+    value = inter / r["sec"]
+    achieved = NEWTON_FLOPS * inter / (r["kern_ms"] / 1e3) / 1e12
+    line = {
+        "metric": "interactions/sec on 1 MI355X (Newton, LUT) + % FP32 VALU peak; batched vs all-pairs; fwd+bwd/fwd",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["sec"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"newton_allpairs_plummer_N{n}_eps0.01", "n_i": n, "n_j": n,
+                   "eps": 0.01, "seed": 102, "interactions_per_step": inter,
+                   "parallelism": "single_gpu", "kernel_variant": r["variant"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_newton_allpairs", "kernel_ms": r["kern_ms"],
+                     "flops_per_interaction": NEWTON_FLOPS,
+                     "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS},
+    }
+    if not args.no_extras:
+        line["extras"] = {"table_allpairs": table_allpairs(torch, pgh, synth)}
+    if not args.no_cpu:
+        x, y, z, m = r["x"]
+        line["cpu_baseline"] = cpu_baseline(x, y, z, m, 0.01, args.cpu_seconds)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,281 @@
+/*
+ * pgh.h -- C ABI of an MI355X (gfx950) direct-summation force library in the
+ * shape of Phantom-GRAPE (Tanikawa, Yoshikawa, Nitadori & Okamoto,
+ * arXiv:1203.4037).
+ *
+ * The library computes, for a set of i-particles and a set of j-particles,
+ *   (1) the Plummer-softened Newtonian acceleration and potential,
+ *       Eq. (newton_force) of Sec. 3, with G = 1;
+ *   (2) a central force of arbitrary shape f(r) with a finite cutoff,
+ *       Eq. (arbitrary_force) of Sec. 3, read from a look-up table of f(r)/r
+ *       whose bins are the low E exponent bits and high F fraction bits of the
+ *       affine-transformed squared distance s (Sec. 3.4.1, Table 4);
+ * for one i-set against one j-set (the GRAPE calls of Sec. 3.6), or for many
+ * (i-group, j-list) interaction lists in one launch (the tree and TreePM use
+ * of Sec. 5.1), plus the adjoints of both forces for a loss L = sum_i w_i.a_i.
+ *
+ * Conventions for every call:
+ *   - Arrays are FP32 structure-of-arrays in DEVICE memory (hipMalloc'd or a
+ *     torch CUDA/HIP tensor), unless a comment says "host".  The caller owns
+ *     every array it passes; the library never frees or keeps them.
+ *   - Calls are asynchronous on the context's stream (pgh_set_stream); none
+ *     synchronises unless it says so.  Inputs must stay valid until the work
+ *     on the stream has finished.
+ *   - Every call returns PGH_OK (0) or a negative status and never aborts;
+ *     pgh_last_error() describes the last failure on that context.
+ *   - ni = 0 or nj = 0 is legal: outputs of the ni rows are written as 0.
+ *   - A NaN in an input propagates to the outputs it touches; inputs are not
+ *     checked for NaN.
+ *   - Units: G = 1 (the paper's API has no G argument, Sec. 3.6).
+ *   - A context is not thread-safe; use one per host thread or stream.
+ */
+#ifndef PGH_H
+#define PGH_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PGH_API __attribute__((visibility("default")))
+
+typedef struct pgh_ctx pgh_ctx;
+typedef struct pgh_plan pgh_plan;
+
+enum pgh_status {
+    PGH_OK = 0,
+    PGH_EINVAL = -1, /* a NULL required pointer or a negative count              */
+    PGH_ESTATE = -2, /* a call out of order, e.g. a table force with no table    */
+    PGH_ENOMEM = -3, /* a device or host allocation failed                       */
+    PGH_EHIP = -4,   /* a HIP runtime call or kernel launch failed               */
+    PGH_ERANGE = -5  /* an argument outside its documented range                 */
+};
+
+/* Force kinds, used by plans and by the tuner. */
+enum pgh_kind {
+    PGH_KIND_NEWTON = 0, /* Eq. (newton_force)                                     */
+    PGH_KIND_TABLE = 1   /* Eq. (arbitrary_force) through the look-up table        */
+};
+
+/* ---------------------------------------------------------------------- */
+/* Context: the GRAPE-5 style set-up calls of Sec. 3.6 (g5_open, g5_close,  */
+/* g5_set_eps_to_all, g5_set_n, g5_set_xmj).                                */
+/* ---------------------------------------------------------------------- */
+
+/* Opens a context on HIP device `device` (g5_open).  `hip_stream` is a
+ * hipStream_t the calls run on (NULL: the default stream).  Nothing of the
+ * approximate-rsqrt bias calibration of g5_open is needed: the kernels use
+ * the hardware rsqrt (about 1 ulp) followed by one Newton-Raphson step.
+ * On failure *out is NULL and the message is available from
+ * pgh_last_error(NULL). */
+PGH_API int pgh_open(pgh_ctx **out, int device, void *hip_stream);
+
+/* Frees the context and its device memory (g5_close).  Waits for the
+ * context's stream first.  pgh_close(NULL) is a no-op. */
+PGH_API int pgh_close(pgh_ctx *c);
+
+/* Message of the last failed call on c (c == NULL: the last failure on this
+ * thread of a call made without a context, such as pgh_open).  The string
+ * lives until the next call on c. */
+PGH_API const char *pgh_last_error(const pgh_ctx *c);
+
+/* Library version as 10000*major + 100*minor + patch. */
+PGH_API int pgh_version(void);
+
+/* Sets the stream later calls run on. */
+PGH_API int pgh_set_stream(pgh_ctx *c, void *hip_stream);
+
+/* Softening length for every i-particle (g5_set_eps_to_all): eps^2 is stored
+ * in FP32 and used when a call passes eps2_i == NULL.  eps >= 0; with eps = 0
+ * a pair at zero distance contributes nothing (the guarded kernel runs). */
+PGH_API int pgh_set_eps_to_all(pgh_ctx *c, float eps);
+
+/* Number of j-particles the all-pairs calls sum over (g5_set_n), 0 <= nj <=
+ * the j-memory size reached by pgh_set_xmj. */
+PGH_API int pgh_set_n(pgh_ctx *c, int nj);
+
+/* Copies nj j-particles (positions x,y,z and masses m, device SoA) into the
+ * context's j-memory at [adr, adr+nj) (g5_set_xmj, Sec. 3.6: the data are
+ * copied into the library's own j-particle records).  The j-memory grows as
+ * needed; growing synchronises the stream.  Records are packed as 16-byte
+ * (x, y, z, m) so one j-particle is one aligned load (the j-particle record
+ * of Sec. 3.1).  Does not change the count set by pgh_set_n. */
+PGH_API int pgh_set_xmj(pgh_ctx *c, int adr, int nj, const float *x, const float *y,
+                const float *z, const float *m);
+
+/* Newton-Raphson refinement of the hardware rsqrt: on (1, default) or off (0).
+ * Sec. 2 of the paper notes that one step on the approximate inverse square
+ * root brings it to full single precision; gfx950's v_rsq_f32 is already
+ * close to that, so the step is kept selectable. */
+PGH_API int pgh_set_rsqrt_refine(pgh_ctx *c, int on);
+
+/* ---------------------------------------------------------------------- */
+/* Newton's force: Eq. (newton_force), the loop of Sec. 3.3.                */
+/* ---------------------------------------------------------------------- */
+
+/* Accelerations and potentials of ni i-particles from the nj = pgh_set_n
+ * j-particles of the j-memory (g5_calculate_force_on_x):
+ *   a_i   =  sum_j m_j (r_j - r_i) / (|r_j - r_i|^2 + eps_i^2)^{3/2}
+ *   phi_i = -sum_j m_j / (|r_j - r_i|^2 + eps_i^2)^{1/2}
+ * xi, yi, zi: ni positions.  eps2_i: ni squared softenings (each > 0), or
+ * NULL to use pgh_set_eps_to_all.  ax, ay, az: ni outputs.  phi: ni outputs,
+ * or NULL to skip the potential.  The sum runs over every j, so when an
+ * i-particle is also a j-particle phi_i includes its self term -m_i/eps_i
+ * (the paper's convention, Sec. 4.1); its force term is zero.  Outputs must
+ * not alias inputs. */
+PGH_API int pgh_calc_newton(pgh_ctx *c, int ni, const float *xi, const float *yi, const float *zi,
+                    const float *eps2_i, float *ax, float *ay, float *az, float *phi);
+
+/* ---------------------------------------------------------------------- */
+/* Central force of arbitrary shape through the bit-binned table (Sec. 3.4) */
+/* ---------------------------------------------------------------------- */
+
+/* Host callback returning h(r) = f(r)/r (the table stores G0_k = f(r_k)/r_k,
+ * Sec. 3.4.1).  It is called at r = 0 for the first node, where it must
+ * return the limit of f(r)/r. */
+typedef double (*pgh_f_over_r)(double r, void *user);
+
+/* Builds the table for exponent bits E (0..6), fraction bits F (0..10),
+ * E + F <= 12, and cutoff rcut > 0 from a host callback (the table setter of
+ * Sec. 3.6) and makes it the context's table.  Node k = 2^F bE + bF sits at
+ * s_k = 2^{bE+1}(1 + bF/2^F) (the node equation of Sec. 3.4.1), i.e. at
+ * r_k = rcut ((s_k - 2)/(s_max - 2))^{1/2} with s_max = 2^{2^E}(2 - 2^-F);
+ * G0_k = fl32(h(r_k)) with G0 of the last node (r = rcut) set to 0;
+ * G1_k = fl32((G0_{k+1} - G0_k)/(s_{k+1} - s_k)) and G1 of the last node 0.
+ * The nodes and quotients are evaluated in double on the host.
+ * table_out: NULL, or host float[2 * 2^(E+F)] receiving (G0_0, G1_0, G0_1, ...).
+ * Synchronous (uploads the table). */
+PGH_API int pgh_build_table(pgh_ctx *c, int E, int F, float rcut, pgh_f_over_r f_over_r, void *user,
+                    float *table_out);
+
+/* The same table computed into host memory only (no context, no device):
+ * table_out is host float[2 * 2^(E+F)].  Returns PGH_EINVAL for a NULL
+ * pointer and PGH_ERANGE for an E, F or rcut out of range. */
+PGH_API int pgh_table_compute(int E, int F, float rcut, pgh_f_over_r f_over_r, void *user,
+                              float *table_out);
+
+/* Sets the context's table from a device array of 2 * 2^(E+F) floats,
+ * interleaved (G0_0, G1_0, G0_1, G1_1, ...) like the paper's
+ * Force_table[K][2]; same E, F, rcut ranges as pgh_build_table.  The values
+ * are copied on the stream. */
+PGH_API int pgh_set_table(pgh_ctx *c, int E, int F, float rcut, const float *table);
+
+/* Built-in f(r)/r of the particle-particle part of the S2 force split,
+ * f = R(r, eps) - R(r, rcut) with R the S2 profile of Hockney & Eastwood
+ * (Eqs. s2pp and s2 of Sec. 4.2), and its analytic limit at r = 0.
+ * user points to double[2] = {eps, rcut}.  Usable as a pgh_f_over_r. */
+PGH_API double pgh_s2pp_f_over_r(double r, void *user);
+
+/* Table-force accelerations of ni i-particles from the nj = pgh_set_n
+ * j-particles of the j-memory: a_i = sum_j m_j g(s_ij) (r_j - r_i) with
+ * s = min((s_max - 2)|r_j - r_i|^2 / rcut^2 + 2, s_max) and
+ * g = G0_k + G1_k (s - s_k), k the bin of s (the force procedure of
+ * Sec. 3.4.2).  Differences are taken on unscaled positions, which gives the
+ * paper's scaled-position result without its final rescale.  No potential
+ * (the table holds forces only).  PGH_ESTATE if no table is set. */
+PGH_API int pgh_calc_table(pgh_ctx *c, int ni, const float *xi, const float *yi, const float *zi,
+                   float *ax, float *ay, float *az);
+
+/* ---------------------------------------------------------------------- */
+/* Interaction lists in one persistent launch (tree / TreePM groups,        */
+/* Sec. 5.1).                                                              */
+/* ---------------------------------------------------------------------- */
+
+/* One interaction list: i-particles [i_off, i_off + n_i) of the i-arrays
+ * against j-particles [j_off, j_off + n_j) of the j-arrays. */
+typedef struct pgh_item {
+    int i_off, n_i, j_off, n_j;
+} pgh_item;
+
+/* Builds an execution plan for n_items lists given in HOST memory: checks
+ * every range against ni_total / nj_total, requires the i-ranges to be
+ * disjoint (PGH_EINVAL otherwise), cuts groups into wavefront tasks, orders
+ * the tasks by decreasing cost and uploads the queue.  A plan is bound to the
+ * context and can be launched any number of times; it is freed by
+ * pgh_plan_free or pgh_close.  Synchronous. */
+PGH_API int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total, int nj_total,
+                    pgh_plan **out);
+PGH_API int pgh_plan_free(pgh_ctx *c, pgh_plan *p);
+
+/* Number of interactions sum n_i n_j of a plan (host value, no sync). */
+PGH_API long long pgh_plan_interactions(const pgh_plan *p);
+
+/* Newton force of every list of the plan in one launch.  Each item writes
+ * ax, ay, az (and phi unless NULL) of its own i-rows; rows in no item are
+ * left untouched.  eps2_i: per-i squared softening (> 0) or NULL for
+ * pgh_set_eps_to_all.  The persistent workgroups take tasks from a device
+ * queue that the launch resets itself, so a captured graph can be replayed. */
+PGH_API int pgh_batch_newton(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
+                     const float *zi, const float *eps2_i, const float *xj, const float *yj,
+                     const float *zj, const float *mj, float *ax, float *ay, float *az,
+                     float *phi);
+
+/* Table force of every list of the plan (the context's table). */
+PGH_API int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
+                    const float *zi, const float *xj, const float *yj, const float *zj,
+                    const float *mj, float *ax, float *ay, float *az);
+
+/* ---------------------------------------------------------------------- */
+/* Adjoints of L = sum_i w_i . a_i (derived from Eq. newton_force and the   */
+/* interpolation of Sec. 3.4.2; pair terms are recomputed, never stored).   */
+/* ---------------------------------------------------------------------- */
+
+/* All-pairs Newton with one shared particle set (i-set = j-set = x, y, z, m,
+ * uniform eps2 > 0): gradients of L for w = (wx, wy, wz) per particle:
+ *   gx_k = sum_l [rho^3 u - 3 rho^5 (u . d) d],  u = m_k w_l - m_l w_k,
+ *   gm_k = -sum_l rho^3 (w_l . d),  d = r_l - r_k, rho = (|d|^2+eps^2)^{-1/2}.
+ * gx, gy, gz, gm: n outputs (gm may be NULL). */
+PGH_API int pgh_newton_allpairs_bwd(pgh_ctx *c, int n, const float *x, const float *y, const float *z,
+                            const float *m, float eps2, const float *wx, const float *wy,
+                            const float *wz, float *gx, float *gy, float *gz, float *gm);
+
+/* Newton adjoint for separate i- and j-sets (eps2_i per i, > 0; NULL for
+ * pgh_set_eps_to_all) with T = m_j rho^3 (w_i . d), d = r_j - r_i:
+ *   gxi_i = -sum_j m_j [rho^3 w_i - 3 rho^5 (w_i . d) d]
+ *   gxj_j =  sum_i m_j [rho^3 w_i - 3 rho^5 (w_i . d) d]
+ *   gmj_j =  sum_i rho^3 (w_i . d)
+ * Any output triple may be NULL (gxi..: NULL skips the i pass; gxj.. and gmj
+ * NULL skip the j pass). */
+PGH_API int pgh_newton_ij_bwd(pgh_ctx *c, int ni, const float *xi, const float *yi, const float *zi,
+                      const float *eps2_i, int nj, const float *xj, const float *yj,
+                      const float *zj, const float *mj, const float *wx, const float *wy,
+                      const float *wz, float *gxi, float *gyi, float *gzi, float *gxj,
+                      float *gyj, float *gzj, float *gmj);
+
+/* Table-force adjoint over a plan, with G0 and G1 independent leaves:
+ *   gtable[2k]   = sum over pairs in bin k of m_j (w_i . d)
+ *   gtable[2k+1] = sum over pairs in bin k of m_j (s - s_k)(w_i . d)
+ *   gmj_j        = sum over pairs with j of g (w_i . d)
+ * gtable: device float[2 * 2^(E+F)], overwritten.  gmj: device float[nj_total]
+ * (or NULL), overwritten; an entry used by several lists accumulates.  The
+ * sums use float atomics, so their order (and last bits) may vary. */
+PGH_API int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
+                        const float *zi, const float *xj, const float *yj, const float *zj,
+                        const float *mj, const float *wx, const float *wy, const float *wz,
+                        float *gtable, float *gmj);
+
+/* ---------------------------------------------------------------------- */
+/* Tuning                                                                   */
+/* ---------------------------------------------------------------------- */
+
+/* Kernel families with tunable tile shapes. */
+enum pgh_family {
+    PGH_FAMILY_NEWTON_ALLPAIRS = 0,
+    PGH_FAMILY_TABLE_ALLPAIRS = 1,
+    PGH_FAMILY_NEWTON_BATCH = 2,
+    PGH_FAMILY_TABLE_BATCH = 3
+};
+
+/* Number of compiled variants of a family, and a host string describing
+ * variant v (e.g. "ki=2 jt=256 u=4"); NULL for an unknown pair. */
+PGH_API int pgh_variant_count(int family);
+PGH_API const char *pgh_variant_name(int family, int v);
+
+/* Selects variant v of a family for later calls on c (-1: the built-in
+ * default). */
+PGH_API int pgh_set_variant(pgh_ctx *c, int family, int v);
+PGH_API int pgh_get_variant(const pgh_ctx *c, int family);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PGH_H */

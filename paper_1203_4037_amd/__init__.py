@@ -1,0 +1,314 @@
+"""Python binding of libpgh, an MI355X (gfx950) direct-summation force library
+in the shape of Phantom-GRAPE (Tanikawa et al., arXiv:1203.4037).
+
+The binding only marshals arguments: every step of the force path runs in the
+HIP kernels of ``libpgh.so`` (built by ``paper_1203_4037_amd/build.py``).  PyTorch
+provides device memory and streams: tensors are passed as device pointers and
+every call runs on torch's current stream.  Importing this package on a
+machine where the library has not been built raises immediately; there is no
+CPU fallback.
+
+Two layers:
+  * ``pgh_*`` functions with the names and argument order of include/pgh.h,
+    taking torch tensors where the C ABI takes device pointers;
+  * ``Context``, a small object-oriented wrapper that allocates outputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # first, so that libpgh binds to the HIP runtime torch has loaded
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpgh.so")
+
+PGH_OK, PGH_EINVAL, PGH_ESTATE, PGH_ENOMEM, PGH_EHIP, PGH_ERANGE = 0, -1, -2, -3, -4, -5
+PGH_KIND_NEWTON, PGH_KIND_TABLE = 0, 1
+PGH_FAMILY_NEWTON_ALLPAIRS, PGH_FAMILY_TABLE_ALLPAIRS = 0, 1
+PGH_FAMILY_NEWTON_BATCH, PGH_FAMILY_TABLE_BATCH = 2, 3
+
+_STATUS = {PGH_EINVAL: "PGH_EINVAL", PGH_ESTATE: "PGH_ESTATE", PGH_ENOMEM: "PGH_ENOMEM",
+           PGH_EHIP: "PGH_EHIP", PGH_ERANGE: "PGH_ERANGE"}
+
+F_OVER_R = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_double, ctypes.c_void_p)
+
+
+class PGHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PghItem(ctypes.Structure):
+    _fields_ = [("i_off", ctypes.c_int), ("n_i", ctypes.c_int), ("j_off", ctypes.c_int),
+                ("n_j", ctypes.c_int)]
+
+
+# The exported symbols of libpgh and their C signatures.
+_P, _I, _F, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
+SIGNATURES = {
+    "pgh_open": (_I, [ctypes.POINTER(_P), _I, _P]),
+    "pgh_close": (_I, [_P]),
+    "pgh_last_error": (ctypes.c_char_p, [_P]),
+    "pgh_version": (_I, []),
+    "pgh_set_stream": (_I, [_P, _P]),
+    "pgh_set_eps_to_all": (_I, [_P, _F]),
+    "pgh_set_n": (_I, [_P, _I]),
+    "pgh_set_xmj": (_I, [_P, _I, _I, _P, _P, _P, _P]),
+    "pgh_set_rsqrt_refine": (_I, [_P, _I]),
+    "pgh_calc_newton": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "pgh_build_table": (_I, [_P, _I, _I, _F, _P, _P, _P]),
+    "pgh_table_compute": (_I, [_I, _I, _F, _P, _P, _P]),
+    "pgh_set_table": (_I, [_P, _I, _I, _F, _P]),
+    "pgh_s2pp_f_over_r": (_D, [_D, _P]),
+    "pgh_calc_table": (_I, [_P, _I, _P, _P, _P, _P, _P, _P]),
+    "pgh_plan_create": (_I, [_P, _I, _P, _I, _I, ctypes.POINTER(_P)]),
+    "pgh_plan_free": (_I, [_P, _P]),
+    "pgh_plan_interactions": (ctypes.c_longlong, [_P]),
+    "pgh_batch_newton": (_I, [_P, _P] + [_P] * 12),
+    "pgh_batch_table": (_I, [_P, _P] + [_P] * 10),
+    "pgh_newton_allpairs_bwd": (_I, [_P, _I, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P, _P]),
+    "pgh_newton_ij_bwd": (_I, [_P, _I, _P, _P, _P, _P, _I] + [_P] * 14),
+    "pgh_batch_table_bwd": (_I, [_P, _P] + [_P] * 12),
+    "pgh_variant_count": (_I, [_I]),
+    "pgh_variant_name": (ctypes.c_char_p, [_I, _I]),
+    "pgh_set_variant": (_I, [_P, _I, _I]),
+    "pgh_get_variant": (_I, [_P, _I]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1203_4037_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+# --------------------------------------------------------------------------
+# argument marshalling
+# --------------------------------------------------------------------------
+
+def _ptr(t, n=None, what="array", device=None):
+    """Device pointer of a float32 contiguous GPU tensor with at least n elements."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{what} must be float32, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be on the GPU")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what} is on device {t.device.index}, the context on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{what} has {t.numel()} elements, {n} needed")
+    return t.data_ptr()
+
+
+def _check(ctx, st):
+    if st != PGH_OK:
+        raise PGHError(st, lib.pgh_last_error(ctx).decode())
+
+
+def _stream(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+# --------------------------------------------------------------------------
+# C-ABI functions (same names and argument order as include/pgh.h)
+# --------------------------------------------------------------------------
+
+def pgh_open(device=0):
+    h = ctypes.c_void_p()
+    _check(None, lib.pgh_open(ctypes.byref(h), device, _stream(device)))
+    return h.value
+
+
+def pgh_close(ctx):
+    _check(ctx, lib.pgh_close(ctx))
+
+
+def pgh_last_error(ctx):
+    return lib.pgh_last_error(ctx).decode()
+
+
+def pgh_version():
+    return lib.pgh_version()
+
+
+def pgh_set_stream(ctx, stream):
+    _check(ctx, lib.pgh_set_stream(ctx, stream))
+
+
+def pgh_set_eps_to_all(ctx, eps):
+    _check(ctx, lib.pgh_set_eps_to_all(ctx, float(eps)))
+
+
+def pgh_set_n(ctx, nj):
+    _check(ctx, lib.pgh_set_n(ctx, int(nj)))
+
+
+def pgh_set_rsqrt_refine(ctx, on):
+    _check(ctx, lib.pgh_set_rsqrt_refine(ctx, int(bool(on))))
+
+
+def pgh_set_xmj(ctx, adr, nj, x, y, z, m):
+    _check(ctx, lib.pgh_set_xmj(ctx, adr, nj, _ptr(x, nj, "x"), _ptr(y, nj, "y"),
+                                _ptr(z, nj, "z"), _ptr(m, nj, "m")))
+
+
+def pgh_calc_newton(ctx, ni, xi, yi, zi, eps2_i, ax, ay, az, phi):
+    _check(ctx, lib.pgh_calc_newton(ctx, ni, _ptr(xi, ni, "xi"), _ptr(yi, ni, "yi"),
+                                    _ptr(zi, ni, "zi"), _ptr(eps2_i, ni, "eps2_i"),
+                                    _ptr(ax, ni, "ax"), _ptr(ay, ni, "ay"), _ptr(az, ni, "az"),
+                                    _ptr(phi, ni, "phi")))
+
+
+def pgh_build_table(ctx, E, F, rcut, f_over_r, user=None, table_out=None):
+    """f_over_r: a ctypes function pointer (F_OVER_R or the library's
+    pgh_s2pp_f_over_r) or a Python callable h(r) -> float.  table_out: an
+    optional host float32 numpy array of 2 * 2^(E+F) entries."""
+    cb = _callback(f_over_r)
+    out = None if table_out is None else table_out.ctypes.data
+    _check(ctx, lib.pgh_build_table(ctx, E, F, float(rcut), ctypes.cast(cb, ctypes.c_void_p),
+                                    user, out))
+
+
+def _callback(f_over_r):
+    if isinstance(f_over_r, F_OVER_R):
+        return f_over_r
+    if callable(f_over_r) and not isinstance(f_over_r, ctypes._CFuncPtr):
+        return F_OVER_R(lambda r, _u: float(f_over_r(r)))
+    return ctypes.cast(f_over_r, ctypes.c_void_p)
+
+
+def pgh_table_compute(E, F, rcut, f_over_r, user, table_out):
+    """Host-only table computation into a float32 numpy array of 2 * 2^(E+F)."""
+    cb = _callback(f_over_r)
+    _check(None, lib.pgh_table_compute(E, F, float(rcut), ctypes.cast(cb, ctypes.c_void_p), user,
+                                       table_out.ctypes.data))
+
+
+def pgh_set_table(ctx, E, F, rcut, table):
+    _check(ctx, lib.pgh_set_table(ctx, E, F, float(rcut), _ptr(table, 2 << (E + F), "table")))
+
+
+def pgh_calc_table(ctx, ni, xi, yi, zi, ax, ay, az):
+    _check(ctx, lib.pgh_calc_table(ctx, ni, _ptr(xi, ni, "xi"), _ptr(yi, ni, "yi"),
+                                   _ptr(zi, ni, "zi"), _ptr(ax, ni, "ax"), _ptr(ay, ni, "ay"),
+                                   _ptr(az, ni, "az")))
+
+
+def pgh_variant_count(family):
+    return lib.pgh_variant_count(family)
+
+
+def pgh_variant_name(family, v):
+    s = lib.pgh_variant_name(family, v)
+    return None if s is None else s.decode()
+
+
+def pgh_set_variant(ctx, family, v):
+    _check(ctx, lib.pgh_set_variant(ctx, family, v))
+
+
+def pgh_get_variant(ctx, family):
+    return lib.pgh_get_variant(ctx, family)
+
+
+def s2pp_callback():
+    """The library's built-in h(r) of the S2 particle-particle force shape
+    (Eqs. s2pp and s2); pass user = ctypes pointer to double[2] {eps, rcut}."""
+    return ctypes.cast(lib.pgh_s2pp_f_over_r, ctypes.c_void_p)
+
+
+# --------------------------------------------------------------------------
+# Object wrapper
+# --------------------------------------------------------------------------
+
+class Context:
+    """One library context on one GPU; calls run on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device).index
+        self.h = pgh_open(self.device)
+        self.nj = 0
+        self.table = None
+
+    def close(self):
+        if self.h:
+            pgh_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        pgh_set_stream(self.h, _stream(self.device))
+
+    def _empty(self, n):
+        return torch.empty(n, dtype=torch.float32, device=torch.device("cuda", self.device))
+
+    def set_eps_to_all(self, eps):
+        pgh_set_eps_to_all(self.h, eps)
+
+    def set_rsqrt_refine(self, on):
+        pgh_set_rsqrt_refine(self.h, on)
+
+    def set_j(self, x, y, z, m, adr=0):
+        """Copies j-particles into the j-memory at adr and sets n to adr + len."""
+        self._sync_stream()
+        n = x.numel()
+        pgh_set_xmj(self.h, adr, n, x, y, z, m)
+        pgh_set_n(self.h, adr + n)
+        self.nj = adr + n
+
+    def newton(self, x, y, z, eps2=None, with_phi=True):
+        """Accelerations (and raw potentials) of the i-particles x, y, z."""
+        self._sync_stream()
+        n = x.numel()
+        ax, ay, az = self._empty(n), self._empty(n), self._empty(n)
+        phi = self._empty(n) if with_phi else None
+        pgh_calc_newton(self.h, n, x, y, z, eps2, ax, ay, az, phi)
+        return ax, ay, az, phi
+
+    def build_table(self, E, F, rcut, f_over_r=None, eps=None):
+        """Builds the table from a Python callable h(r) = f(r)/r, or from the
+        built-in S2 particle-particle shape when f_over_r is None (needs eps)."""
+        import numpy as np
+        out = np.zeros(2 << (E + F), dtype=np.float32)
+        if f_over_r is None:
+            params = (ctypes.c_double * 2)(float(eps), float(rcut))
+            pgh_build_table(self.h, E, F, rcut, s2pp_callback(), ctypes.cast(params, ctypes.c_void_p), out)
+        else:
+            pgh_build_table(self.h, E, F, rcut, f_over_r, None, out)
+        self.table = (E, F, float(rcut))
+        return out
+
+    def set_table(self, E, F, rcut, table):
+        self._sync_stream()
+        pgh_set_table(self.h, E, F, rcut, table)
+        self.table = (E, F, float(rcut))
+
+    def table_force(self, x, y, z):
+        self._sync_stream()
+        n = x.numel()
+        ax, ay, az = self._empty(n), self._empty(n), self._empty(n)
+        pgh_calc_table(self.h, n, x, y, z, ax, ay, az)
+        return ax, ay, az
+
+    def set_variant(self, family, v):
+        pgh_set_variant(self.h, family, v)

@@ -1,0 +1,189 @@
+// All-pairs central force of arbitrary shape from the bit-binned look-up
+// table on gfx950: Eq. (arbitrary_force) of Sec. 3 with the force procedure
+// of Sec. 3.4.2.
+//
+// Per pair (unscaled FP32 positions; the paper pre-scales positions by
+// sqrt(s_max-2)/rcut instead, which rounds every absolute coordinate once
+// more and loses digits for close pairs, so the scale is applied to |d|^2):
+//   d = r_j - r_i                                       3 sub
+//   s = min(c |d|^2 + 2, s_max), c = (s_max-2)/rcut^2    mul, 2 fma, fma, min
+//   k = bits(s)[23-F .. 23+E)  (low E exponent bits and high F fraction bits,
+//       one v_bfe_u32), byte address 8k                  2 int
+//   s_k = bits(s) with the low 23-F bits cleared         1 int
+//   (G0, G1) = T[k], one ds_read_b64 from the LDS copy of the table
+//   g = G0 + G1 (s - s_k)                                sub, fma
+//   a += (m g) d                                         mul, 3 fma
+// The table (2^(E+F) (G0, G1) pairs, at most 32 KiB) is copied into LDS once
+// per workgroup; j-particles stream through LDS tiles exactly as in the
+// Newton kernel.  Pairs beyond the cutoff clamp to s_max, whose node is the
+// last one, where G0 = G1 = 0, so they add exactly zero.
+#include "pgh_internal.h"
+
+namespace pgh {
+namespace {
+
+__device__ __forceinline__ void table_pair(const float4 p, float px, float py, float pz,
+                                           const float2 *__restrict__ stab, float c, float smax,
+                                           unsigned shift, unsigned nbits, unsigned hmask,
+                                           float &sx, float &sy, float &sz)
+{
+    const float dx = p.x - px;
+    const float dy = p.y - py;
+    const float dz = p.z - pz;
+    float r2 = dx * dx;
+    r2 = __builtin_fmaf(dy, dy, r2);
+    r2 = __builtin_fmaf(dz, dz, r2);
+    const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
+    const unsigned u = __float_as_uint(s);
+    const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
+    const float sk = __uint_as_float(u & hmask);
+    const float2 g01 = stab[k];
+    const float g = __builtin_fmaf(g01.y, s - sk, g01.x);
+    const float mg = p.w * g;
+    sx = __builtin_fmaf(mg, dx, sx);
+    sy = __builtin_fmaf(mg, dy, sy);
+    sz = __builtin_fmaf(mg, dz, sz);
+}
+
+template <int KI, int JT, int U>
+__global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
+{
+    static_assert(JT % 256 == 0, "tile must be a multiple of the workgroup");
+    constexpr int PER = JT / 256;
+    extern __shared__ float2 stab[];
+    __shared__ float4 tile[2][JT];
+
+    const int tid = threadIdx.x;
+    const int ibase = blockIdx.x * (256 * KI) + tid;
+    const int K = 1 << (a.E + a.F);
+    const unsigned shift = 23u - (unsigned)a.F;
+    const unsigned nbits = (unsigned)(a.E + a.F);
+    const unsigned hmask = ~((1u << shift) - 1u);
+    const float c = a.c, smax = a.smax;
+
+    for (int k = tid; k < K; k += 256) stab[k] = a.table[k];
+
+    float px[KI], py[KI], pz[KI];
+    float tx[KI], ty[KI], tz[KI];
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        int i = ibase + k * 256;
+        i = i < a.ni ? i : a.ni - 1;
+        px[k] = a.xi[i];
+        py[k] = a.yi[i];
+        pz[k] = a.zi[i];
+        tx[k] = ty[k] = tz[k] = 0.f;
+    }
+
+    const int nj = a.nj;
+    const int ntiles = (nj + JT - 1) / JT;
+    float4 pre[PER];
+    auto load_tile = [&](int t) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int j = t * JT + r * 256 + tid;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < nj) v = a.jmem[j];
+            pre[r] = v;
+        }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) tile[buf][r * 256 + tid] = pre[r];
+    };
+
+    load_tile(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): see the Newton kernel
+    store_tile(0);
+    __syncthreads();
+
+    for (int t = 0; t < ntiles; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < ntiles) load_tile(t + 1);
+        const int cnt = min(JT, nj - t * JT);
+        float sx[KI], sy[KI], sz[KI];
+#pragma unroll
+        for (int k = 0; k < KI; ++k) sx[k] = sy[k] = sz[k] = 0.f;
+        if (cnt == JT) {
+#pragma unroll U
+            for (int jj = 0; jj < JT; ++jj) {
+                const float4 p = tile[cur][jj];
+#pragma unroll
+                for (int k = 0; k < KI; ++k)
+                    table_pair(p, px[k], py[k], pz[k], stab, c, smax, shift, nbits, hmask, sx[k],
+                               sy[k], sz[k]);
+            }
+        } else {
+#pragma unroll 2
+            for (int jj = 0; jj < cnt; ++jj) {
+                const float4 p = tile[cur][jj];
+#pragma unroll
+                for (int k = 0; k < KI; ++k)
+                    table_pair(p, px[k], py[k], pz[k], stab, c, smax, shift, nbits, hmask, sx[k],
+                               sy[k], sz[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            tx[k] += sx[k];
+            ty[k] += sy[k];
+            tz[k] += sz[k];
+        }
+        if (t + 1 < ntiles) store_tile(cur ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        const int i = ibase + k * 256;
+        if (i < a.ni) {
+            a.ax[i] = tx[k];
+            a.ay[i] = ty[k];
+            a.az[i] = tz[k];
+        }
+    }
+}
+
+using TableKernel = void (*)(TableArgs);
+
+struct TableVariant {
+    const char *name;
+    int ki;
+    TableKernel fn;
+};
+
+const TableVariant kTableVariants[] = {
+    {"ki=1 jt=256 u=4", 1, k_table_allpairs<1, 256, 4>},
+    {"ki=2 jt=256 u=4", 2, k_table_allpairs<2, 256, 4>},
+    {"ki=4 jt=256 u=2", 4, k_table_allpairs<4, 256, 2>},
+};
+constexpr int kNumTableVariants = sizeof(kTableVariants) / sizeof(kTableVariants[0]);
+
+}  // namespace
+
+int table_allpairs_variants() { return kNumTableVariants; }
+
+const char *table_allpairs_variant_name(int v)
+{
+    return (v >= 0 && v < kNumTableVariants) ? kTableVariants[v].name : nullptr;
+}
+
+int table_allpairs_default(int ni, int nj, int num_cu)
+{
+    (void)nj;
+    const long waves_ki2 = (long)(ni + 127) / 128;
+    return waves_ki2 >= 4L * num_cu ? 1 : 0;
+}
+
+hipError_t launch_table_allpairs(const TableArgs &a, int variant, hipStream_t s)
+{
+    if (a.ni <= 0) return hipSuccess;
+    const TableVariant &v = kTableVariants[variant];
+    const int per_block = 256 * v.ki;
+    const dim3 grid((a.ni + per_block - 1) / per_block);
+    const size_t lds = sizeof(float2) << (a.E + a.F);
+    hipLaunchKernelGGL(v.fn, grid, dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace pgh

@@ -1,0 +1,272 @@
+// All-pairs Newton force and potential on gfx950: Eq. (newton_force) of
+// Sec. 3 with the loop of Sec. 3.3 (difference, softened square distance,
+// inverse square root, m/r into the potential, m/r^3 times the difference
+// into the acceleration).
+//
+// Mapping.  A workgroup of 256 lanes (four wave64) owns 256*KI i-particles,
+// KI per lane, held in VGPRs for the whole launch.  The j-particles stream
+// through LDS in tiles of JT (x, y, z, m) records: every lane loads JT/256
+// records with one coalesced 16-byte load each, the tile is written to LDS,
+// and the inner loop reads record jj with one ds_read_b128 at a lane-uniform
+// address, which the LDS broadcasts to all 64 lanes without bank conflicts.
+// Tiles are double-buffered: the global loads for tile t+1 are in flight
+// while tile t is consumed, and one barrier per tile separates the phases.
+//
+// Arithmetic per pair (KI independent chains per lane):
+//   3 sub, 3 fma (|d|^2 + eps^2), v_rsq_f32, then either
+//   refine=0: m*y, y*y, (m y)*(y y)                       3 mul
+//   refine=1: one Newton-Raphson step folded into the products:
+//             y2 = y*y, t = q*y2 - 3, u = y*t (= -2 rho), mr = (-m/2)*u
+//             (= m rho), u2 = u*u, mr3 = mr*u2 (= 4 m rho^3); the 4 is
+//             removed by an exact scale of the sums at the end   6 ops
+//   phi -= m rho (1 op), a += mr3 * d (3 fma).
+// The mass in LDS is pre-scaled by -1/2 when refining, so the step costs
+// three VALU ops per pair, not four.
+//
+// Accuracy.  Sums over a tile are formed in fresh registers and added to
+// the running totals once per tile, so FP32 rounding grows with
+// JT + nj/JT rather than nj.
+#include "pgh_internal.h"
+
+namespace pgh {
+
+__global__ void __launch_bounds__(256) k_pack_j(int n, const float *__restrict__ x,
+                                                const float *__restrict__ y,
+                                                const float *__restrict__ z,
+                                                const float *__restrict__ m,
+                                                float4 *__restrict__ dst)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = make_float4(x[i], y[i], z[i], m[i]);
+}
+
+hipError_t launch_pack_j(int n, const float *x, const float *y, const float *z, const float *m,
+                         float4 *dst, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_j, dim3((n + 255) / 256), dim3(256), 0, s, n, x, y, z, m, dst);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_fill_zero(int n, float *a, float *b, float *c, float *d)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        if (a) a[i] = 0.f;
+        if (b) b[i] = 0.f;
+        if (c) c[i] = 0.f;
+        if (d) d[i] = 0.f;
+    }
+}
+
+hipError_t launch_fill_zero(int n, float *a, float *b, float *c, float *d, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_zero, dim3((n + 255) / 256), dim3(256), 0, s, n, a, b, c, d);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <bool REFINE, bool GUARD, bool PHI>
+__device__ __forceinline__ void newton_pair(const float4 p, float px, float py, float pz,
+                                            float pe, float &sx, float &sy, float &sz,
+                                            float &sp)
+{
+    const float dx = p.x - px;
+    const float dy = p.y - py;
+    const float dz = p.z - pz;
+    float q = __builtin_fmaf(dx, dx, pe);
+    q = __builtin_fmaf(dy, dy, q);
+    q = __builtin_fmaf(dz, dz, q);
+    float y = __builtin_amdgcn_rsqf(q);
+    if (GUARD) y = (q > 0.f) ? y : 0.f;
+    float mr, mr3;
+    if (REFINE) {
+        const float y2 = y * y;
+        const float t = __builtin_fmaf(q, y2, -3.0f);
+        const float u = y * t;
+        mr = p.w * u;  // p.w = -m/2
+        const float u2 = u * u;
+        mr3 = mr * u2;
+    } else {
+        mr = p.w * y;
+        const float y2 = y * y;
+        mr3 = mr * y2;
+    }
+    if (PHI) sp -= mr;
+    sx = __builtin_fmaf(mr3, dx, sx);
+    sy = __builtin_fmaf(mr3, dy, sy);
+    sz = __builtin_fmaf(mr3, dz, sz);
+}
+
+template <int KI, int JT, int U, bool REFINE, bool GUARD, bool PHI>
+__global__ void __launch_bounds__(256) k_newton_allpairs(NewtonArgs a)
+{
+    static_assert(JT % 256 == 0, "tile must be a multiple of the workgroup");
+    constexpr int PER = JT / 256;
+    __shared__ float4 tile[2][JT];
+
+    const int tid = threadIdx.x;
+    const int ibase = blockIdx.x * (256 * KI) + tid;
+    const float mscale = REFINE ? -0.5f : 1.0f;
+
+    float px[KI], py[KI], pz[KI], pe[KI];
+    float tx[KI], ty[KI], tz[KI], tp[KI];
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        int i = ibase + k * 256;
+        i = i < a.ni ? i : a.ni - 1;
+        px[k] = a.xi[i];
+        py[k] = a.yi[i];
+        pz[k] = a.zi[i];
+        pe[k] = a.eps2i ? a.eps2i[i] : a.eps2_all;
+        tx[k] = ty[k] = tz[k] = tp[k] = 0.f;
+    }
+
+    const int nj = a.nj;
+    const int ntiles = (nj + JT - 1) / JT;
+    float4 pre[PER];
+
+    auto load_tile = [&](int t) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int j = t * JT + r * 256 + tid;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < nj) v = a.jmem[j];
+            pre[r] = v;  // not touched until stored, so the load stays in flight
+        }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            float4 v = pre[r];
+            v.w *= mscale;
+            tile[buf][r * 256 + tid] = v;
+        }
+    };
+
+    load_tile(0);
+    // Every global load so far (i-particles, first tile) must land before the
+    // tile loop; waiting here, on a path every thread takes, keeps the
+    // compiler from waiting on them (and on the next tile's prefetch queued
+    // behind them) inside the inner loop.
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    store_tile(0);
+    __syncthreads();
+
+    for (int t = 0; t < ntiles; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < ntiles) load_tile(t + 1);
+        const int cnt = min(JT, nj - t * JT);
+
+        float sx[KI], sy[KI], sz[KI], sp[KI];
+#pragma unroll
+        for (int k = 0; k < KI; ++k) sx[k] = sy[k] = sz[k] = sp[k] = 0.f;
+
+        if (cnt == JT) {
+#pragma unroll U
+            for (int jj = 0; jj < JT; ++jj) {
+                const float4 p = tile[cur][jj];
+#pragma unroll
+                for (int k = 0; k < KI; ++k)
+                    newton_pair<REFINE, GUARD, PHI>(p, px[k], py[k], pz[k], pe[k], sx[k], sy[k],
+                                                    sz[k], sp[k]);
+            }
+        } else {
+#pragma unroll 2
+            for (int jj = 0; jj < cnt; ++jj) {
+                const float4 p = tile[cur][jj];
+#pragma unroll
+                for (int k = 0; k < KI; ++k)
+                    newton_pair<REFINE, GUARD, PHI>(p, px[k], py[k], pz[k], pe[k], sx[k], sy[k],
+                                                    sz[k], sp[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            tx[k] += sx[k];
+            ty[k] += sy[k];
+            tz[k] += sz[k];
+            tp[k] += sp[k];
+        }
+        if (t + 1 < ntiles) store_tile(cur ^ 1);
+        __syncthreads();
+    }
+
+    const float ascale = REFINE ? 0.25f : 1.0f;
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        const int i = ibase + k * 256;
+        if (i < a.ni) {
+            a.ax[i] = tx[k] * ascale;
+            a.ay[i] = ty[k] * ascale;
+            a.az[i] = tz[k] * ascale;
+            if (PHI) a.phi[i] = tp[k];
+        }
+    }
+}
+
+using NewtonKernel = void (*)(NewtonArgs);
+
+template <int KI, int JT, int U>
+struct NewtonSet {
+    static NewtonKernel get(bool refine, bool guard, bool phi)
+    {
+        const int sel = (refine ? 4 : 0) | (guard ? 2 : 0) | (phi ? 1 : 0);
+        switch (sel) {
+            case 0: return k_newton_allpairs<KI, JT, U, false, false, false>;
+            case 1: return k_newton_allpairs<KI, JT, U, false, false, true>;
+            case 2: return k_newton_allpairs<KI, JT, U, false, true, false>;
+            case 3: return k_newton_allpairs<KI, JT, U, false, true, true>;
+            case 4: return k_newton_allpairs<KI, JT, U, true, false, false>;
+            case 5: return k_newton_allpairs<KI, JT, U, true, false, true>;
+            case 6: return k_newton_allpairs<KI, JT, U, true, true, false>;
+            default: return k_newton_allpairs<KI, JT, U, true, true, true>;
+        }
+    }
+};
+
+struct NewtonVariant {
+    const char *name;
+    int ki;
+    NewtonKernel (*get)(bool, bool, bool);
+};
+
+const NewtonVariant kNewtonVariants[] = {
+    {"ki=1 jt=256 u=8", 1, &NewtonSet<1, 256, 8>::get},
+    {"ki=2 jt=256 u=4", 2, &NewtonSet<2, 256, 4>::get},
+    {"ki=4 jt=256 u=2", 4, &NewtonSet<4, 256, 2>::get},
+    {"ki=2 jt=512 u=8", 2, &NewtonSet<2, 512, 8>::get},
+};
+constexpr int kNumNewtonVariants = sizeof(kNewtonVariants) / sizeof(kNewtonVariants[0]);
+
+}  // namespace
+
+int newton_allpairs_variants() { return kNumNewtonVariants; }
+
+const char *newton_allpairs_variant_name(int v)
+{
+    return (v >= 0 && v < kNumNewtonVariants) ? kNewtonVariants[v].name : nullptr;
+}
+
+int newton_allpairs_default(int ni, int nj, int num_cu)
+{
+    (void)nj;
+    // Prefer two i per lane when that still gives every SIMD a wave or more.
+    const long waves_ki2 = (long)(ni + 127) / 128;
+    return waves_ki2 >= 4L * num_cu ? 1 : 0;
+}
+
+hipError_t launch_newton_allpairs(const NewtonArgs &a, int variant, bool refine, bool guard,
+                                  hipStream_t s)
+{
+    if (a.ni <= 0) return hipSuccess;
+    const NewtonVariant &v = kNewtonVariants[variant];
+    const int per_block = 256 * v.ki;
+    const dim3 grid((a.ni + per_block - 1) / per_block);
+    hipLaunchKernelGGL(v.get(refine, guard, a.phi != nullptr), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace pgh

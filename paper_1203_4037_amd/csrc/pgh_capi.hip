@@ -1,0 +1,458 @@
+// Host side of the C ABI declared in include/pgh.h: contexts, argument
+// checks, the j-memory, the look-up table builder, plans and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pgh_internal.h"
+
+using namespace pgh;
+
+struct pgh_plan {
+    pgh_ctx *owner;
+    int n_items, n_tasks;
+    int ni_total, nj_total;
+    long long interactions;
+    Task *tasks;        // device
+    unsigned *queue;    // device, 2 counters
+};
+
+struct pgh_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    float eps2_all = 0.f;
+    int nj = 0;
+    int jcap = 0;   // allocated j records
+    int jfill = 0;  // records written so far (the upper bound of pgh_set_n)
+    float4 *jmem = nullptr;
+    int refine = 1;
+    // look-up table
+    int tab_set = 0;
+    int tab_E = 0, tab_F = 0;
+    float tab_rcut = 0.f;
+    float2 *tab = nullptr;  // device, 2^kMaxTableBits entries
+    int variant[4] = {-1, -1, -1, -1};
+    std::vector<pgh_plan *> plans;
+    std::string err;
+};
+
+namespace {
+
+// Message of the last failure of a call made without a context.
+thread_local std::string g_open_error;
+
+int fail(pgh_ctx *c, int code, const std::string &msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_open_error = msg;
+    return code;
+}
+
+int hip_fail(pgh_ctx *c, const char *what, hipError_t e)
+{
+    return fail(c, PGH_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define PGH_HIP(ctx, call)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, #call, e_); \
+    } while (0)
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1, want;
+    explicit DeviceGuard(int dev) : want(dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
+    }
+};
+
+double smax_of(int E, int F) { return std::ldexp(1.0, 1 << E) * (2.0 - std::ldexp(1.0, -F)); }
+
+int check_table_shape(pgh_ctx *c, int E, int F, float rcut)
+{
+    if (E < 0 || E > 6) return fail(c, PGH_ERANGE, "E must be in [0, 6]");
+    if (F < 0 || F > 10) return fail(c, PGH_ERANGE, "F must be in [0, 10]");
+    if (E + F > kMaxTableBits) return fail(c, PGH_ERANGE, "E + F must be <= 12");
+    if (!(rcut > 0.f) || !std::isfinite(rcut)) return fail(c, PGH_ERANGE, "rcut must be > 0");
+    return PGH_OK;
+}
+
+int zero_outputs(pgh_ctx *c, int n, float *a, float *b, float *d, float *e)
+{
+    PGH_HIP(c, launch_fill_zero(n, a, b, d, e, c->stream));
+    return PGH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pgh_version(void) { return 100; }
+
+const char *pgh_last_error(const pgh_ctx *c)
+{
+    return c ? c->err.c_str() : g_open_error.c_str();
+}
+
+int pgh_open(pgh_ctx **out, int device, void *hip_stream)
+{
+    if (!out) {
+        g_open_error = "out is NULL";
+        return PGH_EINVAL;
+    }
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) {
+        g_open_error = std::string("hipGetDeviceCount: ") + hipGetErrorString(e);
+        return PGH_EHIP;
+    }
+    if (device < 0 || device >= ndev) {
+        g_open_error = "device index out of range";
+        return PGH_ERANGE;
+    }
+    pgh_ctx *c = new (std::nothrow) pgh_ctx;
+    if (!c) {
+        g_open_error = "out of host memory";
+        return PGH_ENOMEM;
+    }
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    DeviceGuard g(device);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        ncu > 0)
+        c->num_cu = ncu;
+    e = hipMalloc((void **)&c->tab, sizeof(float2) << kMaxTableBits);
+    if (e != hipSuccess) {
+        g_open_error = std::string("hipMalloc(table): ") + hipGetErrorString(e);
+        delete c;
+        return PGH_ENOMEM;
+    }
+    *out = c;
+    return PGH_OK;
+}
+
+int pgh_close(pgh_ctx *c)
+{
+    if (!c) return PGH_OK;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (pgh_plan *p : c->plans) {
+        (void)hipFree(p->tasks);
+        (void)hipFree(p->queue);
+        delete p;
+    }
+    (void)hipFree(c->jmem);
+    (void)hipFree(c->tab);
+    delete c;
+    return PGH_OK;
+}
+
+int pgh_set_stream(pgh_ctx *c, void *hip_stream)
+{
+    if (!c) return PGH_EINVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return PGH_OK;
+}
+
+int pgh_set_eps_to_all(pgh_ctx *c, float eps)
+{
+    if (!c) return PGH_EINVAL;
+    if (!(eps >= 0.f) || !std::isfinite(eps)) return fail(c, PGH_ERANGE, "eps must be >= 0");
+    c->eps2_all = eps * eps;
+    return PGH_OK;
+}
+
+int pgh_set_n(pgh_ctx *c, int nj)
+{
+    if (!c) return PGH_EINVAL;
+    if (nj < 0 || nj > c->jfill) return fail(c, PGH_ERANGE, "nj exceeds the j-memory filled so far");
+    c->nj = nj;
+    return PGH_OK;
+}
+
+int pgh_set_rsqrt_refine(pgh_ctx *c, int on)
+{
+    if (!c) return PGH_EINVAL;
+    c->refine = on ? 1 : 0;
+    return PGH_OK;
+}
+
+int pgh_set_xmj(pgh_ctx *c, int adr, int nj, const float *x, const float *y, const float *z,
+                const float *m)
+{
+    if (!c) return PGH_EINVAL;
+    if (adr < 0 || nj < 0) return fail(c, PGH_EINVAL, "adr and nj must be >= 0");
+    if (nj == 0) return PGH_OK;
+    if (!x || !y || !z || !m) return fail(c, PGH_EINVAL, "NULL j-particle array");
+    if ((long long)adr + nj > (1LL << 30)) return fail(c, PGH_ERANGE, "j-memory limit is 2^30");
+    DeviceGuard g(c->device);
+    const int need = adr + nj;
+    if (need > c->jcap) {
+        const int cap = std::max(need, std::min(2 * c->jcap, 1 << 30));
+        float4 *nm = nullptr;
+        hipError_t e = hipMalloc((void **)&nm, sizeof(float4) * (size_t)cap);
+        if (e != hipSuccess) return fail(c, PGH_ENOMEM, "hipMalloc(j-memory) failed");
+        if (c->jmem) {
+            PGH_HIP(c, hipMemcpyAsync(nm, c->jmem, sizeof(float4) * (size_t)c->jcap,
+                                      hipMemcpyDeviceToDevice, c->stream));
+            PGH_HIP(c, hipStreamSynchronize(c->stream));
+            (void)hipFree(c->jmem);
+        }
+        c->jmem = nm;
+        c->jcap = cap;
+    }
+    PGH_HIP(c, launch_pack_j(nj, x, y, z, m, c->jmem + adr, c->stream));
+    c->jfill = std::max(c->jfill, need);
+    return PGH_OK;
+}
+
+int pgh_calc_newton(pgh_ctx *c, int ni, const float *xi, const float *yi, const float *zi,
+                    const float *eps2_i, float *ax, float *ay, float *az, float *phi)
+{
+    if (!c) return PGH_EINVAL;
+    if (ni < 0) return fail(c, PGH_EINVAL, "ni must be >= 0");
+    if (ni == 0) return PGH_OK;
+    if (!xi || !yi || !zi || !ax || !ay || !az)
+        return fail(c, PGH_EINVAL, "NULL i-particle or output array");
+    DeviceGuard g(c->device);
+    if (c->nj == 0) return zero_outputs(c, ni, ax, ay, az, phi);
+    NewtonArgs a{ni, xi, yi, zi, eps2_i, c->eps2_all, c->nj, c->jmem, ax, ay, az, phi};
+    const bool guard = (eps2_i == nullptr) && !(c->eps2_all > 0.f);
+    int v = c->variant[PGH_FAMILY_NEWTON_ALLPAIRS];
+    if (v < 0) v = newton_allpairs_default(ni, c->nj, c->num_cu);
+    PGH_HIP(c, launch_newton_allpairs(a, v, c->refine != 0, guard, c->stream));
+    return PGH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Look-up table (Sec. 3.4.1)
+// ---------------------------------------------------------------------------
+
+double pgh_s2pp_f_over_r(double r, void *user)
+{
+    const double *p = (const double *)user;
+    const double eps = p[0], rcut = p[1];
+    if (r >= rcut) return 0.0;
+    // S2 force profile R(r, a), Eq. (s2), with x = 2r/a; both polynomial
+    // branches over 35 a^2 (continuity at x = 1 and x = 2 fixes this).
+    auto R_over_r = [](double rr, double a) {
+        const double x = 2.0 * rr / a;
+        if (x < 1.0) {
+            // (224 x - 224 x^3 + 70 x^4 + 48 x^5 - 21 x^6) / (35 a^2) / r, with x/r = 2/a
+            const double poly = 224.0 + x * x * (-224.0 + x * (70.0 + x * (48.0 - 21.0 * x)));
+            return poly * (2.0 / a) / (35.0 * a * a);
+        }
+        if (x < 2.0) {
+            const double poly =
+                12.0 / (x * x) +
+                (-224.0 + x * (896.0 + x * (-840.0 + x * (224.0 + x * (70.0 + x * (-48.0 + 7.0 * x))))));
+            return poly / (35.0 * a * a) / rr;
+        }
+        return 1.0 / (rr * rr * rr);
+    };
+    return R_over_r(r, eps) - R_over_r(r, rcut);
+}
+
+int pgh_table_compute(int E, int F, float rcut, pgh_f_over_r f_over_r, void *user,
+                      float *table_out)
+{
+    if (!f_over_r || !table_out) return fail(nullptr, PGH_EINVAL, "NULL callback or table");
+    int st = check_table_shape(nullptr, E, F, rcut);
+    if (st) return st;
+    const int K = 1 << (E + F);
+    const double smax = smax_of(E, F);
+    float *t = table_out;
+    // Nodes by stepping the FP32 bit pattern of s from 2.0 by one unit of the
+    // F-th fraction bit: exactly s_k = 2^{bE+1}(1 + bF/2^F).
+    std::vector<double> sk(K);
+    unsigned bits;
+    const float two = 2.0f;
+    std::memcpy(&bits, &two, 4);
+    for (int k = 0; k < K; ++k) {
+        float s;
+        const unsigned b = bits + ((unsigned)k << (23 - F));
+        std::memcpy(&s, &b, 4);
+        sk[k] = s;
+    }
+    for (int k = 0; k < K; ++k) {
+        const double r = (double)rcut * std::sqrt((sk[k] - 2.0) / (smax - 2.0));
+        t[2 * k] = (k == K - 1) ? 0.0f : (float)f_over_r(r, user);
+    }
+    for (int k = 0; k + 1 < K; ++k)
+        t[2 * k + 1] = (float)(((double)t[2 * k + 2] - (double)t[2 * k]) / (sk[k + 1] - sk[k]));
+    t[2 * K - 1] = 0.0f;
+    return PGH_OK;
+}
+
+int pgh_build_table(pgh_ctx *c, int E, int F, float rcut, pgh_f_over_r f_over_r, void *user,
+                    float *table_out)
+{
+    if (!c) return PGH_EINVAL;
+    if (!f_over_r) return fail(c, PGH_EINVAL, "NULL callback");
+    int st = check_table_shape(c, E, F, rcut);
+    if (st) return st;
+    std::vector<float> t(2u << (E + F));
+    st = pgh_table_compute(E, F, rcut, f_over_r, user, t.data());
+    if (st) return fail(c, st, "table computation failed");
+    DeviceGuard g(c->device);
+    PGH_HIP(c, hipMemcpyAsync(c->tab, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice,
+                              c->stream));
+    PGH_HIP(c, hipStreamSynchronize(c->stream));
+    c->tab_set = 1;
+    c->tab_E = E;
+    c->tab_F = F;
+    c->tab_rcut = rcut;
+    if (table_out) std::memcpy(table_out, t.data(), sizeof(float) * t.size());
+    return PGH_OK;
+}
+
+int pgh_set_table(pgh_ctx *c, int E, int F, float rcut, const float *table)
+{
+    if (!c) return PGH_EINVAL;
+    if (!table) return fail(c, PGH_EINVAL, "NULL table");
+    int st = check_table_shape(c, E, F, rcut);
+    if (st) return st;
+    DeviceGuard g(c->device);
+    PGH_HIP(c, hipMemcpyAsync(c->tab, table, sizeof(float2) << (E + F), hipMemcpyDeviceToDevice,
+                              c->stream));
+    c->tab_set = 1;
+    c->tab_E = E;
+    c->tab_F = F;
+    c->tab_rcut = rcut;
+    return PGH_OK;
+}
+
+int pgh_calc_table(pgh_ctx *c, int ni, const float *xi, const float *yi, const float *zi,
+                   float *ax, float *ay, float *az)
+{
+    if (!c) return PGH_EINVAL;
+    if (!c->tab_set) return fail(c, PGH_ESTATE, "no force table set");
+    if (ni < 0) return fail(c, PGH_EINVAL, "ni must be >= 0");
+    if (ni == 0) return PGH_OK;
+    if (!xi || !yi || !zi || !ax || !ay || !az)
+        return fail(c, PGH_EINVAL, "NULL i-particle or output array");
+    DeviceGuard g(c->device);
+    if (c->nj == 0) return zero_outputs(c, ni, ax, ay, az, nullptr);
+    const double smax = smax_of(c->tab_E, c->tab_F);
+    const double rc = c->tab_rcut;
+    TableArgs a{ni, xi, yi, zi, c->nj, c->jmem, c->tab, c->tab_E, c->tab_F,
+                (float)((smax - 2.0) / (rc * rc)), (float)smax, ax, ay, az};
+    int v = c->variant[PGH_FAMILY_TABLE_ALLPAIRS];
+    if (v < 0) v = table_allpairs_default(ni, c->nj, c->num_cu);
+    PGH_HIP(c, launch_table_allpairs(a, v, c->stream));
+    return PGH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plans and batched launches
+// ---------------------------------------------------------------------------
+
+int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total, int nj_total,
+                    pgh_plan **out)
+{
+    (void)n_items, (void)items, (void)ni_total, (void)nj_total;
+    if (out) *out = nullptr;
+    return fail(c, PGH_ESTATE, "batched plans are not available in this build");
+}
+
+int pgh_plan_free(pgh_ctx *c, pgh_plan *p)
+{
+    (void)c, (void)p;
+    return PGH_OK;
+}
+
+long long pgh_plan_interactions(const pgh_plan *p) { return p ? p->interactions : 0; }
+
+int pgh_batch_newton(pgh_ctx *c, const pgh_plan *p, const float *, const float *, const float *,
+                     const float *, const float *, const float *, const float *, const float *,
+                     float *, float *, float *, float *)
+{
+    (void)p;
+    return fail(c, PGH_ESTATE, "batched plans are not available in this build");
+}
+
+int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *, const float *, const float *,
+                    const float *, const float *, const float *, const float *, float *, float *,
+                    float *)
+{
+    (void)p;
+    return fail(c, PGH_ESTATE, "batched plans are not available in this build");
+}
+
+int pgh_newton_allpairs_bwd(pgh_ctx *c, int, const float *, const float *, const float *,
+                            const float *, float, const float *, const float *, const float *,
+                            float *, float *, float *, float *)
+{
+    return fail(c, PGH_ESTATE, "adjoints are not available in this build");
+}
+
+int pgh_newton_ij_bwd(pgh_ctx *c, int, const float *, const float *, const float *, const float *,
+                      int, const float *, const float *, const float *, const float *,
+                      const float *, const float *, const float *, float *, float *, float *,
+                      float *, float *, float *, float *)
+{
+    return fail(c, PGH_ESTATE, "adjoints are not available in this build");
+}
+
+int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *, const float *, const float *,
+                        const float *, const float *, const float *, const float *,
+                        const float *, const float *, const float *, const float *, float *,
+                        float *)
+{
+    return fail(c, PGH_ESTATE, "adjoints are not available in this build");
+}
+
+// ---------------------------------------------------------------------------
+// Variants
+// ---------------------------------------------------------------------------
+
+int pgh_variant_count(int family)
+{
+    switch (family) {
+        case PGH_FAMILY_NEWTON_ALLPAIRS: return newton_allpairs_variants();
+        case PGH_FAMILY_TABLE_ALLPAIRS: return table_allpairs_variants();
+        default: return 0;
+    }
+}
+
+const char *pgh_variant_name(int family, int v)
+{
+    switch (family) {
+        case PGH_FAMILY_NEWTON_ALLPAIRS: return newton_allpairs_variant_name(v);
+        case PGH_FAMILY_TABLE_ALLPAIRS: return table_allpairs_variant_name(v);
+        default: return nullptr;
+    }
+}
+
+int pgh_set_variant(pgh_ctx *c, int family, int v)
+{
+    if (!c) return PGH_EINVAL;
+    if (family < 0 || family > 3) return fail(c, PGH_ERANGE, "unknown kernel family");
+    if (v < -1 || v >= pgh_variant_count(family)) return fail(c, PGH_ERANGE, "unknown variant");
+    c->variant[family] = v;
+    return PGH_OK;
+}
+
+int pgh_get_variant(const pgh_ctx *c, int family)
+{
+    if (!c || family < 0 || family > 3) return -1;
+    return c->variant[family];
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal declarations shared by the host side of the library and the
+// kernel translation units.  Not part of the public ABI (include/pgh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "pgh.h"
+
+namespace pgh {
+
+// Largest table the kernels hold in LDS: 2^12 (G0, G1) pairs = 32 KiB.
+constexpr int kMaxTableBits = 12;
+
+// Arguments of the all-pairs Newton kernels.  jmem holds (x, y, z, m)
+// records; eps2i may be null (then eps2_all applies to every i).
+struct NewtonArgs {
+    int ni;
+    const float *xi, *yi, *zi, *eps2i;
+    float eps2_all;
+    int nj;
+    const float4 *jmem;
+    float *ax, *ay, *az, *phi;
+};
+
+// Arguments of the all-pairs table-force kernels.
+struct TableArgs {
+    int ni;
+    const float *xi, *yi, *zi;
+    int nj;
+    const float4 *jmem;
+    const float2 *table;  // (G0, G1) per node, 2^(E+F) nodes
+    int E, F;
+    float c;     // (s_max - 2) / rcut^2
+    float smax;  // 2^{2^E} (2 - 2^-F)
+    float *ax, *ay, *az;
+};
+
+// One wavefront task of a batch plan: up to 64 i-particles against one j-list.
+struct Task {
+    int i_off, n_i, j_off, n_j;
+};
+
+// Arguments of the persistent batched kernels.
+struct BatchArgs {
+    int n_tasks;
+    const Task *tasks;
+    unsigned *queue;  // [0] = next task, [1] = finished waves (both reset by the launch)
+    int n_waves;      // waves in the grid
+    const float *xi, *yi, *zi, *eps2i;
+    float eps2_all;
+    const float *xj, *yj, *zj, *mj;
+    float *ax, *ay, *az, *phi;
+    // table force only
+    const float2 *table;
+    int E, F;
+    float c, smax;
+};
+
+// Arguments of the adjoint kernels.
+struct NewtonBwdArgs {
+    int ni;
+    const float *xi, *yi, *zi, *eps2i;
+    float eps2_all;
+    int nj;
+    const float *xj, *yj, *zj, *mj;
+    const float *wx, *wy, *wz;
+    float *gxi, *gyi, *gzi;
+    float *gxj, *gyj, *gzj, *gmj;
+};
+
+struct TableBwdArgs {
+    BatchArgs b;
+    const float *wx, *wy, *wz;
+    float *gtable;  // 2K floats
+    float *gmj;
+};
+
+// Variant descriptions for the tuner.
+struct VariantInfo {
+    const char *name;
+};
+
+// Kernel launchers (defined in the .hip files).
+hipError_t launch_pack_j(int n, const float *x, const float *y, const float *z, const float *m,
+                         float4 *dst, hipStream_t s);
+hipError_t launch_fill_zero(int n, float *a, float *b, float *c, float *d, hipStream_t s);
+
+int newton_allpairs_variants();
+const char *newton_allpairs_variant_name(int v);
+int newton_allpairs_default(int ni, int nj, int num_cu);
+hipError_t launch_newton_allpairs(const NewtonArgs &a, int variant, bool refine, bool guard,
+                                  hipStream_t s);
+
+int table_allpairs_variants();
+const char *table_allpairs_variant_name(int v);
+int table_allpairs_default(int ni, int nj, int num_cu);
+hipError_t launch_table_allpairs(const TableArgs &a, int variant, hipStream_t s);
+
+int newton_batch_variants();
+const char *newton_batch_variant_name(int v);
+int batch_waves_per_cu(int variant);
+hipError_t launch_newton_batch(const BatchArgs &a, int variant, bool refine, bool guard,
+                               int num_cu, hipStream_t s);
+
+int table_batch_variants();
+const char *table_batch_variant_name(int v);
+hipError_t launch_table_batch(const BatchArgs &a, int variant, int num_cu, hipStream_t s);
+
+hipError_t launch_newton_allpairs_bwd(int n, const float4 *jm, const float4 *w, float eps2,
+                                      float *gx, float *gy, float *gz, float *gm, hipStream_t s);
+hipError_t launch_pack_w(int n, const float *wx, const float *wy, const float *wz, float4 *dst,
+                         hipStream_t s);
+hipError_t launch_newton_ij_bwd(const NewtonBwdArgs &a, hipStream_t s);
+hipError_t launch_table_batch_bwd(const TableBwdArgs &a, int num_cu, hipStream_t s);
+
+}  // namespace pgh

@@ -1,0 +1,122 @@
+"""Host-side checks of the C-ABI library that need no GPU: every symbol the
+header declares is exported, argument checks return status codes, and the
+host parts of the force path (the table builder and the built-in S2 shape)
+agree with the FP64 oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pgh.h")
+
+
+@pytest.fixture(scope="module")
+def pgh():
+    import paper_1203_4037_amd as p
+    return p
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"PGH_API\s+[\w\s\*]*?\b(pgh_\w+)\s*\(", text)))
+
+
+def test_header_declarations_are_exported(pgh):
+    names = _declared()
+    assert len(names) >= 25
+    lib = ctypes.CDLL(pgh.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding knows the signature of every one of them
+    assert set(names) == set(pgh.SIGNATURES), set(names) ^ set(pgh.SIGNATURES)
+
+
+def test_version_and_variant_tables(pgh):
+    assert pgh.pgh_version() >= 100
+    for fam in range(4):
+        n = pgh.pgh_variant_count(fam)
+        assert n >= 0
+        for v in range(n):
+            assert pgh.pgh_variant_name(fam, v)
+        assert pgh.pgh_variant_name(fam, n) is None
+    assert pgh.pgh_variant_count(99) == 0
+
+
+def test_open_without_gpu_returns_status(pgh):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    st = pgh.lib.pgh_open(ctypes.byref(h), 0, None)
+    assert st in (pgh.PGH_EHIP, pgh.PGH_ERANGE)
+    assert h.value is None
+    assert pgh.lib.pgh_last_error(None)
+    assert pgh.lib.pgh_open(None, 0, None) == pgh.PGH_EINVAL
+
+
+def test_null_context_is_rejected(pgh):
+    assert pgh.lib.pgh_set_n(None, 1) == pgh.PGH_EINVAL
+    assert pgh.lib.pgh_calc_newton(None, 1, *([None] * 8)) == pgh.PGH_EINVAL
+    assert pgh.lib.pgh_close(None) == pgh.PGH_OK
+
+
+@pytest.mark.parametrize("E,F", [(4, 6), (4, 5), (4, 2), (0, 3), (6, 6), (2, 10)])
+def test_host_table_builder_matches_oracle(pgh, E, F):
+    eps, rcut = 1.0 / 1280, np.float32(3.0 / 256)
+    t = np.zeros(2 << (E + F), np.float32)
+    params = (ctypes.c_double * 2)(eps, float(rcut))
+    pgh.pgh_table_compute(E, F, rcut, pgh.s2pp_callback(), ctypes.cast(params, ctypes.c_void_p), t)
+    ref = oracle.table_build(E, F, float(rcut), oracle.SHAPE_S2PP, eps)
+    K = 1 << (E + F)
+    G0, R0 = t[0::2].astype(np.float64), ref[0::2].astype(np.float64)
+    # G0 within one ulp of the oracle's, plus the double-precision rounding of
+    # f = R(r,eps) - R(r,rcut), a difference of two terms ~1/r^2 that cancel
+    # towards rcut (the two sides evaluate the polynomials in different orders)
+    r = np.array([oracle.node_r(E, F, float(rcut), k) for k in range(K)])
+    cancel = 1e-13 / np.maximum(r, eps) ** 3
+    ulp = np.spacing(np.maximum(np.abs(G0), np.abs(R0)).astype(np.float32)).astype(np.float64)
+    bad = np.abs(G0 - R0) > ulp + cancel
+    assert not bad.any(), np.nonzero(bad)[0][:10]
+    # G1 is the paper's difference quotient of the library's own rounded G0
+    sk = np.array([oracle.node_s(E, F, k) for k in range(K)])
+    G1 = ((G0[1:] - G0[:-1]) / (sk[1:] - sk[:-1])).astype(np.float32)
+    assert np.array_equal(t[1:-1:2], G1)
+    assert t[-1] == 0 and t[-2] == 0
+
+
+def test_builtin_s2_shape_matches_oracle(pgh):
+    eps, rcut = 3.125e-3, 4.6875e-2
+    params = (ctypes.c_double * 2)(eps, rcut)
+    f = pgh.lib.pgh_s2pp_f_over_r
+    for r in np.concatenate([[0.0, 1e-9, eps / 2, eps, rcut / 2, rcut * 0.999, rcut, 2 * rcut],
+                             np.linspace(1e-4, rcut, 97)]):
+        got = f(float(r), ctypes.cast(params, ctypes.c_void_p))
+        ref = oracle.shape_h(oracle.SHAPE_S2PP, r, eps, rcut)
+        assert got == pytest.approx(ref, rel=1e-12, abs=1e-12 * abs(oracle.shape_h(oracle.SHAPE_S2PP, 0, eps, rcut)))
+
+
+def test_table_compute_rejects_bad_shapes(pgh):
+    t = np.zeros(1 << 14, np.float32)
+    cb = pgh.s2pp_callback()
+    params = (ctypes.c_double * 2)(1e-3, 0.1)
+    user = ctypes.cast(params, ctypes.c_void_p)
+    for E, F, rc in [(7, 2, 0.1), (4, 11, 0.1), (6, 7, 0.1), (-1, 2, 0.1), (4, 6, 0.0), (4, 6, -1.0)]:
+        with pytest.raises(pgh.PGHError) as e:
+            pgh.pgh_table_compute(E, F, rc, cb, user, t)
+        assert e.value.code == pgh.PGH_ERANGE
+    assert pgh.lib.pgh_table_compute(4, 6, 0.1, None, None, t.ctypes.data) == pgh.PGH_EINVAL
+
+
+def test_python_callback_table(pgh):
+    # a Python callable works as the paper's function-pointer table setter
+    E, F, rcut = 3, 3, 1.0
+    t = np.zeros(2 << (E + F), np.float32)
+    pgh.pgh_table_compute(E, F, rcut, lambda r: 1.0 - r, None, t)
+    K = 1 << (E + F)
+    for k in range(K - 1):
+        assert t[2 * k] == np.float32(1.0 - oracle.node_r(E, F, rcut, k))
