@@ -133,6 +133,77 @@ def newton_allpairs(torch, pgh, synth, args):
     return {"n": n, "x": (x, y, z, m), "sec": sec, "kern_ms": kern_ms, "variant": variant}
 
 
+def graph_ms(torch, fn, reps):
+    """Captures fn() in a graph (a hipGraph under ROCm) and returns the mean
+    replay time in ms, from events on the replay stream."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def batched_newton(torch, pgh, synth):
+    """Tree-style lists: 16384 (i-group, j-list) items over a Morton-sorted
+    Plummer sphere of 2^22 particles, eps = 1e-3, i-groups uniform in
+    [32, 256], j-lists log-normal (median 2000, clipped [200, 20000]),
+    materialised; one persistent launch per step, replayed from a graph."""
+    s = synth.tree_style_items(1 << 22, 16384, 104)
+    di = [torch.from_numpy(a).cuda() for a in (s.xi, s.yi, s.zi)]
+    dj = [torch.from_numpy(a).cuda() for a in (s.xj, s.yj, s.zj, s.mj)]
+    ctx = pgh.Context(0)
+    ctx.set_eps_to_all(1e-3)
+    plan = ctx.plan(s.items, s.xi.size, s.xj.size)
+    out = [torch.empty(s.xi.size, device="cuda") for _ in range(4)]
+    ms = graph_ms(torch, lambda: plan.newton(*di, *dj, out=out), 10)
+    inter = float(plan.interactions)
+    plan.free()
+    ctx.close()
+    rate = inter / (ms / 1e3)
+    return {"workload": "newton_batched_tree_style_16384_lists_N4194304", "interactions": inter,
+            "ms_per_launch": ms, "interactions_per_s": rate,
+            "frac_of_peak_38flop": NEWTON_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12)}
+
+
+def batched_table(torch, pgh, synth):
+    """Cell-grid lists of a TreePM PP step: N = 262144 uniform in the unit
+    periodic box, 64^3 cells, 4^3-cell i-groups with their 6^3-cell halo
+    (4096 lists), S2 PP shape rcut = 3/256, eps = 1/1280, E = 4, F = 6;
+    replayed from a graph."""
+    n = 262144
+    x, y, z = synth.uniform_box(n, 103)
+    m = synth.equal_masses(n)
+    s = synth.cell_grid_items(x, y, z, m, ncell=64, block=4)
+    di = [torch.from_numpy(a).cuda() for a in (s.xi, s.yi, s.zi)]
+    dj = [torch.from_numpy(a).cuda() for a in (s.xj, s.yj, s.zj, s.mj)]
+    ctx = pgh.Context(0)
+    ctx.build_table(4, 6, 3.0 / 256, eps=1.0 / 1280)
+    plan = ctx.plan(s.items, n, s.xj.size)
+    out = [torch.empty(n, device="cuda") for _ in range(3)]
+    ms = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 200)
+    inter = float(plan.interactions)
+    plan.free()
+    ctx.close()
+    rate = inter / (ms / 1e3)
+    return {"workload": "table_batched_cell_lists_N262144_E4F6", "interactions": inter,
+            "ms_per_launch": ms, "interactions_per_s": rate,
+            "frac_of_peak_20flop": TABLE_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12)}
+
+
 def table_allpairs(torch, pgh, synth):
     """Secondary: the table force on the same kind of call, N = 65536 uniform
     particles in a box of side 0.25 with the S2 PP shape (rcut = 3/256,
@@ -201,7 +272,11 @@ def main():
                      "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS},
     }
     if not args.no_extras:
-        line["extras"] = {"table_allpairs": table_allpairs(torch, pgh, synth)}
+        ex = {"table_allpairs": table_allpairs(torch, pgh, synth),
+              "newton_batched": batched_newton(torch, pgh, synth),
+              "table_batched": batched_table(torch, pgh, synth)}
+        ex["batched_over_allpairs"] = ex["newton_batched"]["interactions_per_s"] / value
+        line["extras"] = ex
     if not args.no_cpu:
         x, y, z, m = r["x"]
         line["cpu_baseline"] = cpu_baseline(x, y, z, m, 0.01, args.cpu_seconds)

@@ -60,7 +60,7 @@ def lib():
             "pgo_table_build": [i, i, d, i, P, P],
             "pgo_lut_eval": [d, i, i, P],
             "pgo_lut_items": [l, P, P, P, P, P, P, P, P, i, i, d, P, P, P, P, P],
-            "pgo_central_items": [l, P, P, P, P, P, P, P, P, i, P, P, P, P, P],
+            "pgo_central_items": [l, P, P, P, P, P, P, P, P, i, P, P, P, P, P, P],
             "pgo_newton_bwd": [l, P, P, P, P, l, P, P, P, P, P, P, P, P, P, P, P, P, P, P],
             "pgo_lut_bwd_items": [l, P, P, P, P, P, P, P, P, P, P, P, i, i, d, P, P, P, l],
         }
@@ -183,13 +183,15 @@ def lut_items(items, xi, yi, zi, xj, yj, zj, mj, E, F, rcut, table):
 
 
 def central_items(items, xi, yi, zi, xj, yj, zj, mj, shape, eps, rcut):
-    """Exact central force with the analytic h = f/r. Returns (ax, ay, az, absum)."""
+    """Exact central force with the analytic h = f/r.  Returns (ax, ay, az,
+    absum, fullsum): absum = sum m|h|r, fullsum = sum over 0 < r < rcut of
+    m F(r) with F the whole force of the split (R(r, eps) for S2)."""
     it = _items32(items)
     xi, yi, zi = map(_f64, (xi, yi, zi))
     xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
     p = np.array([eps, rcut], dtype=np.float64)
     ni = xi.size
-    out = [np.full(ni, np.nan) for _ in range(4)]
+    out = [np.full(ni, np.nan) for _ in range(5)]
     lib().pgo_central_items(it.shape[0], _ptr(it), _ptr(xi), _ptr(yi), _ptr(zi), _ptr(xj),
                             _ptr(yj), _ptr(zj), _ptr(mj), int(shape), _ptr(p),
                             *[_ptr(o) for o in out])

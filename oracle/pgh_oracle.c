@@ -295,22 +295,27 @@ PGO_EXPORT void pgo_lut_items(long n_items, const int32_t *items, const double *
 
 /*
  * Analytic companion of the table force: a_i = sum_j m_j h(r_ij) d_ij with the
- * exact h = f/r, for measuring the table error.  absum_i = sum_j m_j |h| |d|
- * (the scale used to normalise errors of a sum with cancellation).
+ * exact h = f/r, for measuring the table error.  Two scales per i (NULL to
+ * skip): absum_i = sum_j m_j |h| |d| (the scale of the PP sum itself), and
+ * fullsum_i = sum over pairs with 0 < r < rcut of m_j F(r), F the whole
+ * force the PP part belongs to: R(r, eps) for the S2 split (PP plus PM,
+ * the quantity the paper's accuracy test of Sec. 4.2 measures errors
+ * against) and r (r^2+eps^2)^{-3/2} for the softened Newtonian shape.
  */
 PGO_EXPORT void pgo_central_items(long n_items, const int32_t *items, const double *xi,
                                   const double *yi, const double *zi, const double *xj,
                                   const double *yj, const double *zj, const double *mj, int shape,
                                   const double *params, double *ax, double *ay, double *az,
-                                  double *absum)
+                                  double *absum, double *fullsum)
 {
+    const double eps = params[0], rcut = params[1];
     long t;
 #pragma omp parallel for schedule(dynamic, 1)
     for (t = 0; t < n_items; t++) {
         const long i0 = items[4 * t + 0], n_i = items[4 * t + 1];
         const long j0 = items[4 * t + 2], n_j = items[4 * t + 3];
         for (long i = i0; i < i0 + n_i; i++) {
-            double sx = 0.0, sy = 0.0, sz = 0.0, sa = 0.0;
+            double sx = 0.0, sy = 0.0, sz = 0.0, sa = 0.0, sf = 0.0;
             for (long j = j0; j < j0 + n_j; j++) {
                 const double dx = (double)xj[j] - (double)xi[i];
                 const double dy = (double)yj[j] - (double)yi[i];
@@ -322,11 +327,18 @@ PGO_EXPORT void pgo_central_items(long n_items, const int32_t *items, const doub
                 sy += m * h * dy;
                 sz += m * h * dz;
                 sa += fabs(m * h) * r;
+                if (r > 0.0 && r < rcut) {
+                    if (shape == PGO_SHAPE_S2PP)
+                        sf += m * pgo_s2_R(r, eps);
+                    else
+                        sf += m * r / pow(r * r + eps * eps, 1.5);
+                }
             }
             ax[i] = sx;
             ay[i] = sy;
             az[i] = sz;
             if (absum) absum[i] = sa;
+            if (fullsum) fullsum[i] = sf;
         }
     }
 }

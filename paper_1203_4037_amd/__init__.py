@@ -209,6 +209,48 @@ def pgh_calc_table(ctx, ni, xi, yi, zi, ax, ay, az):
                                    _ptr(az, ni, "az")))
 
 
+def _items_array(items):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(items, dtype=np.int32).reshape(-1, 4))
+    return a
+
+
+def pgh_plan_create(ctx, n_items, items, ni_total, nj_total):
+    """items: host int32 array [n_items, 4] of (i_off, n_i, j_off, n_j)."""
+    a = _items_array(items)
+    if a.shape[0] < n_items:
+        raise ValueError("fewer items than n_items")
+    h = ctypes.c_void_p()
+    _check(ctx, lib.pgh_plan_create(ctx, int(n_items), a.ctypes.data if a.size else None,
+                                    int(ni_total), int(nj_total), ctypes.byref(h)))
+    return h.value
+
+
+def pgh_plan_free(ctx, plan):
+    _check(ctx, lib.pgh_plan_free(ctx, plan))
+
+
+def pgh_plan_interactions(plan):
+    return lib.pgh_plan_interactions(plan)
+
+
+def pgh_batch_newton(ctx, plan, xi, yi, zi, eps2_i, xj, yj, zj, mj, ax, ay, az, phi):
+    _check(ctx, lib.pgh_batch_newton(ctx, plan, _ptr(xi, None, "xi"), _ptr(yi, None, "yi"),
+                                     _ptr(zi, None, "zi"), _ptr(eps2_i, None, "eps2_i"),
+                                     _ptr(xj, None, "xj"), _ptr(yj, None, "yj"),
+                                     _ptr(zj, None, "zj"), _ptr(mj, None, "mj"),
+                                     _ptr(ax, None, "ax"), _ptr(ay, None, "ay"),
+                                     _ptr(az, None, "az"), _ptr(phi, None, "phi")))
+
+
+def pgh_batch_table(ctx, plan, xi, yi, zi, xj, yj, zj, mj, ax, ay, az):
+    _check(ctx, lib.pgh_batch_table(ctx, plan, _ptr(xi, None, "xi"), _ptr(yi, None, "yi"),
+                                    _ptr(zi, None, "zi"), _ptr(xj, None, "xj"),
+                                    _ptr(yj, None, "yj"), _ptr(zj, None, "zj"),
+                                    _ptr(mj, None, "mj"), _ptr(ax, None, "ax"),
+                                    _ptr(ay, None, "ay"), _ptr(az, None, "az")))
+
+
 def pgh_variant_count(family):
     return lib.pgh_variant_count(family)
 
@@ -312,3 +354,55 @@ class Context:
 
     def set_variant(self, family, v):
         pgh_set_variant(self.h, family, v)
+
+    # interaction lists ------------------------------------------------------
+
+    def plan(self, items, ni_total, nj_total):
+        """A Plan for host items [n, 4] = (i_off, n_i, j_off, n_j)."""
+        return Plan(self, items, ni_total, nj_total)
+
+
+class Plan:
+    """Execution plan of a set of interaction lists (pgh_plan_create)."""
+
+    def __init__(self, ctx, items, ni_total, nj_total):
+        a = _items_array(items)
+        self.ctx = ctx
+        self.ni_total, self.nj_total = int(ni_total), int(nj_total)
+        self.h = pgh_plan_create(ctx.h, a.shape[0], a, ni_total, nj_total)
+        self.interactions = pgh_plan_interactions(self.h)
+
+    def free(self):
+        if self.h and self.ctx.h:
+            pgh_plan_free(self.ctx.h, self.h)
+        self.h = None
+
+    def _check_sizes(self, i_arrays, j_arrays):
+        for t in i_arrays:
+            if t is not None and t.numel() < self.ni_total:
+                raise ValueError("an i-array is shorter than the plan's ni_total")
+        for t in j_arrays:
+            if t is not None and t.numel() < self.nj_total:
+                raise ValueError("a j-array is shorter than the plan's nj_total")
+
+    def newton(self, xi, yi, zi, xj, yj, zj, mj, eps2=None, out=None, with_phi=True):
+        """Newton force of every list; rows outside every item keep the
+        values of `out` (allocated uninitialised when out is None)."""
+        c = self.ctx
+        c._sync_stream()
+        self._check_sizes((xi, yi, zi, eps2), (xj, yj, zj, mj))
+        n = self.ni_total
+        if out is None:
+            out = [c._empty(n) for _ in range(4 if with_phi else 3)]
+        phi = out[3] if with_phi else None
+        pgh_batch_newton(c.h, self.h, xi, yi, zi, eps2, xj, yj, zj, mj, out[0], out[1], out[2], phi)
+        return out
+
+    def table(self, xi, yi, zi, xj, yj, zj, mj, out=None):
+        c = self.ctx
+        c._sync_stream()
+        self._check_sizes((xi, yi, zi), (xj, yj, zj, mj))
+        if out is None:
+            out = [c._empty(self.ni_total) for _ in range(3)]
+        pgh_batch_table(c.h, self.h, xi, yi, zi, xj, yj, zj, mj, out[0], out[1], out[2])
+        return out

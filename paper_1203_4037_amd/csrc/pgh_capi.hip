@@ -18,8 +18,11 @@ struct pgh_plan {
     int n_items, n_tasks;
     int ni_total, nj_total;
     long long interactions;
-    Task *tasks;        // device
-    unsigned *queue;    // device, 2 counters
+    int n_chunks, n_slots;  // chunks whose j-list is split, and their parts
+    Task *tasks;            // device, sorted by decreasing length
+    unsigned *queue;        // device, task counter reset by every launch
+    float4 *partial;        // device, 64 partial sums per slot
+    SplitChunk *chunks;     // device, the split chunks
 };
 
 struct pgh_ctx {
@@ -155,6 +158,8 @@ int pgh_close(pgh_ctx *c)
     for (pgh_plan *p : c->plans) {
         (void)hipFree(p->tasks);
         (void)hipFree(p->queue);
+        (void)hipFree(p->partial);
+        (void)hipFree(p->chunks);
         delete p;
     }
     (void)hipFree(c->jmem);
@@ -366,33 +371,228 @@ int pgh_calc_table(pgh_ctx *c, int ni, const float *xi, const float *yi, const f
 int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total, int nj_total,
                     pgh_plan **out)
 {
-    (void)n_items, (void)items, (void)ni_total, (void)nj_total;
-    if (out) *out = nullptr;
-    return fail(c, PGH_ESTATE, "batched plans are not available in this build");
+    if (!c) return PGH_EINVAL;
+    if (!out) return fail(c, PGH_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_items < 0 || ni_total < 0 || nj_total < 0)
+        return fail(c, PGH_EINVAL, "counts must be >= 0");
+    if (n_items > 0 && !items) return fail(c, PGH_EINVAL, "NULL item array");
+    // ranges and disjointness of the i-groups
+    std::vector<int> order;
+    order.reserve(n_items);
+    long long inter = 0;
+    for (int t = 0; t < n_items; ++t) {
+        const pgh_item &it = items[t];
+        if (it.i_off < 0 || it.n_i < 0 || it.j_off < 0 || it.n_j < 0)
+            return fail(c, PGH_EINVAL, "item " + std::to_string(t) + " has a negative field");
+        if ((long long)it.i_off + it.n_i > ni_total || (long long)it.j_off + it.n_j > nj_total)
+            return fail(c, PGH_ERANGE, "item " + std::to_string(t) + " exceeds the arrays");
+        if (it.n_i > 0) order.push_back(t);
+        inter += (long long)it.n_i * it.n_j;
+    }
+    std::sort(order.begin(), order.end(),
+              [&](int a, int b) { return items[a].i_off < items[b].i_off; });
+    for (size_t k = 1; k < order.size(); ++k) {
+        const pgh_item &p0 = items[order[k - 1]], &p1 = items[order[k]];
+        if (p1.i_off < p0.i_off + p0.n_i)
+            return fail(c, PGH_EINVAL, "i-ranges of items " + std::to_string(order[k - 1]) +
+                                           " and " + std::to_string(order[k]) + " overlap");
+    }
+
+    // wave tasks: chunks of <= 64 i-particles; lanes per i-particle js
+    struct Chunk {
+        int i_off, n_i, j_off, n_j, js;
+    };
+    std::vector<Chunk> chunks;
+    long long total = 0;  // wave-iterations
+    for (int t : order) {
+        const pgh_item &it = items[t];
+        for (int s0 = 0; s0 < it.n_i; s0 += 64) {
+            const int n = std::min(64, it.n_i - s0);
+            const int js = n <= 16 ? 4 : (n <= 32 ? 2 : 1);
+            chunks.push_back({it.i_off + s0, n, it.j_off, it.n_j, js});
+            total += std::max(1LL, (long long)(it.n_j + js - 1) / js);
+        }
+    }
+    // cut j-lists longer than half the average work of a resident wave
+    const int waves = std::max(1, batch_resident_waves(c->num_cu));
+    const long long part_iters = std::max(512LL, (total / waves / 2 + 63) / 64 * 64);
+    std::vector<Task> tasks;
+    std::vector<long long> cost;
+    std::vector<SplitChunk> split;
+    int n_slots = 0;
+    for (const Chunk &ch : chunks) {
+        const long long iters = (ch.n_j + ch.js - 1) / ch.js;
+        int parts = (int)std::max(1LL, (iters + part_iters - 1) / part_iters);
+        long long per = ch.n_j;
+        if (parts > 1) {
+            // equal parts, each a multiple of 64 j-particles except the last
+            per = (ch.n_j + parts - 1) / parts;
+            per = (per + 63) / 64 * 64;
+            parts = (int)((ch.n_j + per - 1) / per);
+        }
+        if (parts <= 1) {
+            tasks.push_back({ch.i_off, ch.n_i, ch.j_off, ch.n_j, 0, 1, 0, 0});
+            cost.push_back(std::max(1LL, iters));
+            continue;
+        }
+        for (int q = 0; q < parts; ++q) {
+            const int j0 = ch.j_off + (int)(q * per);
+            const int nj = (int)std::min<long long>(per, ch.n_j - q * per);
+            tasks.push_back({ch.i_off, ch.n_i, j0, nj, q, parts, n_slots, 0});
+            cost.push_back((nj + ch.js - 1) / ch.js);
+        }
+        split.push_back({ch.i_off, ch.n_i, n_slots, parts});
+        n_slots += parts;
+    }
+    const int n_chunks = (int)split.size();
+    // longest tasks first
+    std::vector<int> idx(tasks.size());
+    for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<Task> sorted(tasks.size());
+    for (size_t k = 0; k < idx.size(); ++k) sorted[k] = tasks[idx[k]];
+
+    pgh_plan *p = new (std::nothrow) pgh_plan;
+    if (!p) return fail(c, PGH_ENOMEM, "out of host memory");
+    p->owner = c;
+    p->n_items = n_items;
+    p->n_tasks = (int)sorted.size();
+    p->ni_total = ni_total;
+    p->nj_total = nj_total;
+    p->interactions = inter;
+    p->n_chunks = n_chunks;
+    p->n_slots = n_slots;
+    p->tasks = nullptr;
+    p->queue = nullptr;
+    p->partial = nullptr;
+    p->chunks = nullptr;
+    DeviceGuard g(c->device);
+    auto cleanup = [&](int code, const char *msg) {
+        (void)hipFree(p->tasks);
+        (void)hipFree(p->queue);
+        (void)hipFree(p->partial);
+        (void)hipFree(p->chunks);
+        delete p;
+        return fail(c, code, msg);
+    };
+    if (hipMalloc((void **)&p->queue, 2 * sizeof(unsigned)) != hipSuccess)
+        return cleanup(PGH_ENOMEM, "hipMalloc(queue) failed");
+    if (!sorted.empty() &&
+        hipMalloc((void **)&p->tasks, sorted.size() * sizeof(Task)) != hipSuccess)
+        return cleanup(PGH_ENOMEM, "hipMalloc(tasks) failed");
+    if (n_slots > 0 &&
+        hipMalloc((void **)&p->partial, (size_t)n_slots * 64 * sizeof(float4)) != hipSuccess)
+        return cleanup(PGH_ENOMEM, "hipMalloc(partial sums) failed");
+    if (n_chunks > 0 &&
+        hipMalloc((void **)&p->chunks, (size_t)n_chunks * sizeof(SplitChunk)) != hipSuccess)
+        return cleanup(PGH_ENOMEM, "hipMalloc(split chunks) failed");
+    if (hipMemsetAsync(p->queue, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
+        (n_chunks > 0 &&
+         hipMemcpyAsync(p->chunks, split.data(), split.size() * sizeof(SplitChunk),
+                        hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+        (!sorted.empty() &&
+         hipMemcpyAsync(p->tasks, sorted.data(), sorted.size() * sizeof(Task),
+                        hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return cleanup(PGH_EHIP, "uploading the plan failed");
+    c->plans.push_back(p);
+    *out = p;
+    return PGH_OK;
 }
 
 int pgh_plan_free(pgh_ctx *c, pgh_plan *p)
 {
-    (void)c, (void)p;
+    if (!c) return PGH_EINVAL;
+    if (!p) return PGH_OK;
+    auto it = std::find(c->plans.begin(), c->plans.end(), p);
+    if (it == c->plans.end()) return fail(c, PGH_EINVAL, "plan does not belong to this context");
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(p->tasks);
+    (void)hipFree(p->queue);
+    (void)hipFree(p->partial);
+    (void)hipFree(p->chunks);
+    c->plans.erase(it);
+    delete p;
     return PGH_OK;
 }
 
 long long pgh_plan_interactions(const pgh_plan *p) { return p ? p->interactions : 0; }
 
-int pgh_batch_newton(pgh_ctx *c, const pgh_plan *p, const float *, const float *, const float *,
-                     const float *, const float *, const float *, const float *, const float *,
-                     float *, float *, float *, float *)
+namespace {
+
+int check_plan(pgh_ctx *c, const pgh_plan *p)
 {
-    (void)p;
-    return fail(c, PGH_ESTATE, "batched plans are not available in this build");
+    if (!p) return fail(c, PGH_EINVAL, "NULL plan");
+    if (p->owner != c) return fail(c, PGH_EINVAL, "plan belongs to another context");
+    return PGH_OK;
 }
 
-int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *, const float *, const float *,
-                    const float *, const float *, const float *, const float *, float *, float *,
-                    float *)
+BatchArgs batch_args(pgh_ctx *c, const pgh_plan *p)
 {
-    (void)p;
-    return fail(c, PGH_ESTATE, "batched plans are not available in this build");
+    BatchArgs a{};
+    a.n_tasks = p->n_tasks;
+    a.tasks = p->tasks;
+    a.queue = p->queue;
+    a.partial = p->partial;
+    a.n_chunks = p->n_chunks;
+    a.chunks = p->chunks;
+    a.eps2_all = c->eps2_all;
+    return a;
+}
+
+}  // namespace
+
+int pgh_batch_newton(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
+                     const float *zi, const float *eps2_i, const float *xj, const float *yj,
+                     const float *zj, const float *mj, float *ax, float *ay, float *az, float *phi)
+{
+    if (!c) return PGH_EINVAL;
+    int st = check_plan(c, p);
+    if (st) return st;
+    if (p->n_tasks == 0) return PGH_OK;
+    if (!xi || !yi || !zi || !ax || !ay || !az)
+        return fail(c, PGH_EINVAL, "NULL i-particle or output array");
+    if (p->nj_total > 0 && (!xj || !yj || !zj || !mj))
+        return fail(c, PGH_EINVAL, "NULL j-particle array");
+    DeviceGuard g(c->device);
+    BatchArgs a = batch_args(c, p);
+    a.xi = xi, a.yi = yi, a.zi = zi, a.eps2i = eps2_i;
+    a.xj = xj, a.yj = yj, a.zj = zj, a.mj = mj;
+    a.ax = ax, a.ay = ay, a.az = az, a.phi = phi;
+    const bool guard = (eps2_i == nullptr) && !(c->eps2_all > 0.f);
+    PGH_HIP(c, launch_newton_batch(a, c->refine != 0, guard, c->num_cu, c->stream));
+    return PGH_OK;
+}
+
+int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
+                    const float *zi, const float *xj, const float *yj, const float *zj,
+                    const float *mj, float *ax, float *ay, float *az)
+{
+    if (!c) return PGH_EINVAL;
+    int st = check_plan(c, p);
+    if (st) return st;
+    if (!c->tab_set) return fail(c, PGH_ESTATE, "no force table set");
+    if (p->n_tasks == 0) return PGH_OK;
+    if (!xi || !yi || !zi || !ax || !ay || !az)
+        return fail(c, PGH_EINVAL, "NULL i-particle or output array");
+    if (p->nj_total > 0 && (!xj || !yj || !zj || !mj))
+        return fail(c, PGH_EINVAL, "NULL j-particle array");
+    DeviceGuard g(c->device);
+    BatchArgs a = batch_args(c, p);
+    a.xi = xi, a.yi = yi, a.zi = zi;
+    a.xj = xj, a.yj = yj, a.zj = zj, a.mj = mj;
+    a.ax = ax, a.ay = ay, a.az = az;
+    const double smax = smax_of(c->tab_E, c->tab_F);
+    const double rc = c->tab_rcut;
+    a.table = c->tab;
+    a.E = c->tab_E;
+    a.F = c->tab_F;
+    a.c = (float)((smax - 2.0) / (rc * rc));
+    a.smax = (float)smax;
+    PGH_HIP(c, launch_table_batch(a, c->num_cu, c->stream));
+    return PGH_OK;
 }
 
 int pgh_newton_allpairs_bwd(pgh_ctx *c, int, const float *, const float *, const float *,

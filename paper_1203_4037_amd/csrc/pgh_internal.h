@@ -38,9 +38,17 @@ struct TableArgs {
     float *ax, *ay, *az;
 };
 
-// One wavefront task of a batch plan: up to 64 i-particles against one j-list.
+// One wavefront task of a batch plan: up to 64 i-particles against one part
+// of one j-list.  A chunk whose j-list is cut into n_parts > 1 parts owns
+// n_parts consecutive slots of 64 partial sums starting at `slot`.
 struct Task {
     int i_off, n_i, j_off, n_j;
+    int part, n_parts, slot, pad;
+};
+
+// A chunk of i-particles whose j-list is split into parts.
+struct SplitChunk {
+    int i_off, n_i, slot, n_parts;
 };
 
 // Arguments of the persistent batched kernels.
@@ -48,7 +56,10 @@ struct BatchArgs {
     int n_tasks;
     const Task *tasks;
     unsigned *queue;  // [0] = next task, [1] = finished waves (both reset by the launch)
-    int n_waves;      // waves in the grid
+    int n_waves;      // waves in the grid (set by the launcher)
+    int n_chunks;     // split chunks
+    const SplitChunk *chunks;
+    float4 *partial;  // 64 partial sums per slot of a split chunk
     const float *xi, *yi, *zi, *eps2i;
     float eps2_all;
     const float *xj, *yj, *zj, *mj;
@@ -69,6 +80,14 @@ struct NewtonBwdArgs {
     const float *wx, *wy, *wz;
     float *gxi, *gyi, *gzi;
     float *gxj, *gyj, *gzj, *gmj;
+};
+
+struct CombineArgs {
+    int n_chunks;
+    const SplitChunk *chunks;
+    const float4 *partial;
+    unsigned *queue;
+    float *ax, *ay, *az, *phi;
 };
 
 struct TableBwdArgs {
@@ -99,15 +118,10 @@ const char *table_allpairs_variant_name(int v);
 int table_allpairs_default(int ni, int nj, int num_cu);
 hipError_t launch_table_allpairs(const TableArgs &a, int variant, hipStream_t s);
 
-int newton_batch_variants();
-const char *newton_batch_variant_name(int v);
-int batch_waves_per_cu(int variant);
-hipError_t launch_newton_batch(const BatchArgs &a, int variant, bool refine, bool guard,
-                               int num_cu, hipStream_t s);
-
-int table_batch_variants();
-const char *table_batch_variant_name(int v);
-hipError_t launch_table_batch(const BatchArgs &a, int variant, int num_cu, hipStream_t s);
+int batch_resident_waves(int num_cu);  // waves of the persistent grid
+hipError_t launch_newton_batch(const BatchArgs &a, bool refine, bool guard, int num_cu,
+                               hipStream_t s);
+hipError_t launch_table_batch(const BatchArgs &a, int num_cu, hipStream_t s);
 
 hipError_t launch_newton_allpairs_bwd(int n, const float4 *jm, const float4 *w, float eps2,
                                       float *gx, float *gy, float *gz, float *gm, hipStream_t s);
