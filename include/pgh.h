@@ -220,21 +220,28 @@ PGH_API int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, cons
 /* ---------------------------------------------------------------------- */
 
 /* All-pairs Newton with one shared particle set (i-set = j-set = x, y, z, m,
- * uniform eps2 > 0): gradients of L for w = (wx, wy, wz) per particle:
- *   gx_k = sum_l [rho^3 u - 3 rho^5 (u . d) d],  u = m_k w_l - m_l w_k,
- *   gm_k = -sum_l rho^3 (w_l . d),  d = r_l - r_k, rho = (|d|^2+eps^2)^{-1/2}.
- * gx, gy, gz, gm: n outputs (gm may be NULL). */
+ * uniform eps2 > 0, else PGH_ERANGE): gradients of L for w = (wx, wy, wz)
+ * per particle, both roles of each particle folded into one gather:
+ *   gx_k = sum_{l != k} [rho^3 u - 3 rho^5 (u . d) d],  u = m_k w_l - m_l w_k,
+ *   gm_k = -sum_{l != k} rho^3 (w_l . d),  d = r_l - r_k,
+ *   rho = (|d|^2 + eps2)^{-1/2}.
+ * The self pair, whose term is identically zero, is skipped.  The particle
+ * records are packed into context scratch (grown on demand, which
+ * synchronises).  gx, gy, gz, gm: n outputs (gm may be NULL). */
 PGH_API int pgh_newton_allpairs_bwd(pgh_ctx *c, int n, const float *x, const float *y, const float *z,
                             const float *m, float eps2, const float *wx, const float *wy,
                             const float *wz, float *gx, float *gy, float *gz, float *gm);
 
 /* Newton adjoint for separate i- and j-sets (eps2_i per i, > 0; NULL for
- * pgh_set_eps_to_all) with T = m_j rho^3 (w_i . d), d = r_j - r_i:
+ * pgh_set_eps_to_all, which must then be > 0) with T = m_j rho^3 (w_i . d),
+ * d = r_j - r_i:
  *   gxi_i = -sum_j m_j [rho^3 w_i - 3 rho^5 (w_i . d) d]
  *   gxj_j =  sum_i m_j [rho^3 w_i - 3 rho^5 (w_i . d) d]
  *   gmj_j =  sum_i rho^3 (w_i . d)
  * Any output triple may be NULL (gxi..: NULL skips the i pass; gxj.. and gmj
- * NULL skip the j pass). */
+ * NULL skip the j pass).  When the two sets are the same particles, each
+ * self pair adds opposite terms m rho^3 w to gxi and gxj that cancel only
+ * when the caller adds them; pgh_newton_allpairs_bwd avoids that. */
 PGH_API int pgh_newton_ij_bwd(pgh_ctx *c, int ni, const float *xi, const float *yi, const float *zi,
                       const float *eps2_i, int nj, const float *xj, const float *yj,
                       const float *zj, const float *mj, const float *wx, const float *wy,
@@ -245,9 +252,11 @@ PGH_API int pgh_newton_ij_bwd(pgh_ctx *c, int ni, const float *xi, const float *
  *   gtable[2k]   = sum over pairs in bin k of m_j (w_i . d)
  *   gtable[2k+1] = sum over pairs in bin k of m_j (s - s_k)(w_i . d)
  *   gmj_j        = sum over pairs with j of g (w_i . d)
- * gtable: device float[2 * 2^(E+F)], overwritten.  gmj: device float[nj_total]
- * (or NULL), overwritten; an entry used by several lists accumulates.  The
- * sums use float atomics, so their order (and last bits) may vary. */
+ * gtable: device float[2 * 2^(E+F)] (or NULL), overwritten.  gmj: device
+ * float[nj_total] (or NULL), overwritten; an entry used by several lists
+ * accumulates.  The sums use float atomics, so their order (and last bits)
+ * may vary from call to call.  Position gradients of the table force are not
+ * provided. */
 PGH_API int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
                         const float *zi, const float *xj, const float *yj, const float *zj,
                         const float *mj, const float *wx, const float *wy, const float *wz,

@@ -61,8 +61,8 @@ def lib():
             "pgo_lut_eval": [d, i, i, P],
             "pgo_lut_items": [l, P, P, P, P, P, P, P, P, i, i, d, P, P, P, P, P],
             "pgo_central_items": [l, P, P, P, P, P, P, P, P, i, P, P, P, P, P, P],
-            "pgo_newton_bwd": [l, P, P, P, P, l, P, P, P, P, P, P, P, P, P, P, P, P, P, P],
-            "pgo_lut_bwd_items": [l, P, P, P, P, P, P, P, P, P, P, P, i, i, d, P, P, P, l],
+            "pgo_newton_bwd": [l, P, P, P, P, l, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P],
+            "pgo_lut_bwd_items": [l, P, P, P, P, P, P, P, P, P, P, P, i, i, d, P, P, P, l, P, P],
         }
         ret = {"pgo_s2_R": d, "pgo_s2pp_f": d, "pgo_shape_h": d, "pgo_smax": d,
                "pgo_node_s": d, "pgo_node_r": d, "pgo_lut_index": l, "pgo_lut_eval": d}
@@ -202,22 +202,28 @@ def central_items(items, xi, yi, zi, xj, yj, zj, mj, shape, eps, rcut):
 # Adjoints of L = sum_i w_i . a_i
 # --------------------------------------------------------------------------
 
-def newton_bwd(xi, yi, zi, eps2i, xj, yj, zj, mj, wx, wy, wz):
-    """Returns (gxi, gyi, gzi, gxj, gyj, gzj, gmj) as float64 arrays."""
+def newton_bwd(xi, yi, zi, eps2i, xj, yj, zj, mj, wx, wy, wz, scales=False):
+    """Adjoint of L = sum_i w_i . a_i.  Returns (gxi, gyi, gzi, gxj, gyj, gzj,
+    gmj), plus (absi, absj, absm) when scales: the sums of the absolute pair
+    terms of the i-side, j-side and mass gradients."""
     xi, yi, zi, eps2i = map(_f64, (xi, yi, zi, eps2i))
     xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
     wx, wy, wz = map(_f64, (wx, wy, wz))
     ni, nj = xi.size, xj.size
     gi = [np.zeros(ni) for _ in range(3)]
     gj = [np.zeros(nj) for _ in range(4)]
+    sc = [np.zeros(ni), np.zeros(nj), np.zeros(nj)]
     lib().pgo_newton_bwd(ni, _ptr(xi), _ptr(yi), _ptr(zi), _ptr(eps2i), nj, _ptr(xj),
                          _ptr(yj), _ptr(zj), _ptr(mj), _ptr(wx), _ptr(wy), _ptr(wz),
-                         *[_ptr(o) for o in gi], *[_ptr(o) for o in gj])
-    return tuple(gi) + tuple(gj)
+                         *[_ptr(o) for o in gi], *[_ptr(o) for o in gj],
+                         *[_ptr(o) for o in sc])
+    out = tuple(gi) + tuple(gj)
+    return out + tuple(sc) if scales else out
 
 
-def lut_bwd_items(items, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, E, F, rcut, table):
-    """Returns (gtable float64[2K] interleaved like the table, gmj float64[nj])."""
+def lut_bwd_items(items, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, E, F, rcut, table, scales=False):
+    """Returns (gtable float64[2K] interleaved like the table, gmj float64[nj]),
+    plus their absolute-term sums when scales."""
     it = _items32(items)
     xi, yi, zi = map(_f64, (xi, yi, zi))
     xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
@@ -226,7 +232,9 @@ def lut_bwd_items(items, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, E, F, rcut, tab
     K = 1 << (E + F)
     gt = np.zeros(2 * K)
     gm = np.zeros(xj.size)
+    ga = np.zeros(2 * K)
+    gma = np.zeros(xj.size)
     lib().pgo_lut_bwd_items(it.shape[0], _ptr(it), _ptr(xi), _ptr(yi), _ptr(zi), _ptr(xj),
                             _ptr(yj), _ptr(zj), _ptr(mj), _ptr(wx), _ptr(wy), _ptr(wz), E, F,
-                            float(rcut), _ptr(t), _ptr(gt), _ptr(gm), xj.size)
-    return gt, gm
+                            float(rcut), _ptr(t), _ptr(gt), _ptr(gm), xj.size, _ptr(ga), _ptr(gma))
+    return (gt, gm, ga, gma) if scales else (gt, gm)

@@ -353,20 +353,23 @@ PGO_EXPORT void pgo_central_items(long n_items, const int32_t *items, const doub
  *   dT/dd = m_j [rho^3 w_i - 3 rho^5 (w_i . d) d],  dd/dr_j = I,  dd/dr_i = -I,
  *   dT/dm_j = rho^3 (w_i . d).
  * gxi_i = -sum_j dT/dd;  gxj_j = sum_i dT/dd;  gmj_j = sum_i rho^3 (w_i . d).
- * Any output pointer may be NULL.  Pairs with zero softened distance are
- * skipped like in the forward sum.
+ * absi_i = sum_j |dT/dd|, absj_j = sum_i |dT/dd| and absm_j = sum_i
+ * |rho^3 (w_i . d)| are the scales of these sums (for error measures).
+ * Any output pointer may be NULL (gxi..gzi together, gxj..gzj together).
+ * Pairs with zero softened distance are skipped like in the forward sum.
  */
 PGO_EXPORT void pgo_newton_bwd(long ni, const double *xi, const double *yi, const double *zi,
                                const double *eps2i, long nj, const double *xj, const double *yj,
                                const double *zj, const double *mj, const double *wx,
                                const double *wy, const double *wz, double *gxi, double *gyi,
-                               double *gzi, double *gxj, double *gyj, double *gzj, double *gmj)
+                               double *gzi, double *gxj, double *gyj, double *gzj, double *gmj,
+                               double *absi, double *absj, double *absm)
 {
     long i, j;
     if (gxi) {
 #pragma omp parallel for schedule(dynamic, 16)
         for (i = 0; i < ni; i++) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, sa = 0.0;
             for (long jj = 0; jj < nj; jj++) {
                 const double dx = (double)xj[jj] - xi[i];
                 const double dy = (double)yj[jj] - yi[i];
@@ -377,19 +380,24 @@ PGO_EXPORT void pgo_newton_bwd(long ni, const double *xi, const double *yi, cons
                 const double rho3 = rho * rho * rho, rho5 = rho3 * rho * rho;
                 const double wd = (double)wx[i] * dx + (double)wy[i] * dy + (double)wz[i] * dz;
                 const double m = mj[jj];
-                s0 -= m * (rho3 * wx[i] - 3.0 * rho5 * wd * dx);
-                s1 -= m * (rho3 * wy[i] - 3.0 * rho5 * wd * dy);
-                s2 -= m * (rho3 * wz[i] - 3.0 * rho5 * wd * dz);
+                const double t0 = m * (rho3 * wx[i] - 3.0 * rho5 * wd * dx);
+                const double t1 = m * (rho3 * wy[i] - 3.0 * rho5 * wd * dy);
+                const double t2 = m * (rho3 * wz[i] - 3.0 * rho5 * wd * dz);
+                s0 -= t0;
+                s1 -= t1;
+                s2 -= t2;
+                sa += sqrt(t0 * t0 + t1 * t1 + t2 * t2);
             }
             gxi[i] = s0;
             gyi[i] = s1;
             gzi[i] = s2;
+            if (absi) absi[i] = sa;
         }
     }
-    if (gxj || gmj) {
+    if (gxj || gmj || absj || absm) {
 #pragma omp parallel for schedule(dynamic, 16)
         for (j = 0; j < nj; j++) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, sm = 0.0;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, sm = 0.0, sa = 0.0, sb = 0.0;
             for (long ii = 0; ii < ni; ii++) {
                 const double dx = (double)xj[j] - xi[ii];
                 const double dy = (double)yj[j] - yi[ii];
@@ -400,10 +408,15 @@ PGO_EXPORT void pgo_newton_bwd(long ni, const double *xi, const double *yi, cons
                 const double rho3 = rho * rho * rho, rho5 = rho3 * rho * rho;
                 const double wd = (double)wx[ii] * dx + (double)wy[ii] * dy + (double)wz[ii] * dz;
                 const double m = mj[j];
-                s0 += m * (rho3 * wx[ii] - 3.0 * rho5 * wd * dx);
-                s1 += m * (rho3 * wy[ii] - 3.0 * rho5 * wd * dy);
-                s2 += m * (rho3 * wz[ii] - 3.0 * rho5 * wd * dz);
+                const double t0 = m * (rho3 * wx[ii] - 3.0 * rho5 * wd * dx);
+                const double t1 = m * (rho3 * wy[ii] - 3.0 * rho5 * wd * dy);
+                const double t2 = m * (rho3 * wz[ii] - 3.0 * rho5 * wd * dz);
+                s0 += t0;
+                s1 += t1;
+                s2 += t2;
                 sm += rho3 * wd;
+                sa += sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+                sb += fabs(rho3 * wd);
             }
             if (gxj) {
                 gxj[j] = s0;
@@ -411,6 +424,8 @@ PGO_EXPORT void pgo_newton_bwd(long ni, const double *xi, const double *yi, cons
                 gzj[j] = s2;
             }
             if (gmj) gmj[j] = sm;
+            if (absj) absj[j] = sa;
+            if (absm) absm[j] = sb;
         }
     }
 }
@@ -421,7 +436,12 @@ PGO_EXPORT void pgo_newton_bwd(long ni, const double *xi, const double *yi, cons
  *   dL/dG0_k = sum over pairs in bin k of m_j (w_i . d)
  *   dL/dG1_k = sum over pairs in bin k of m_j (s - s_k) (w_i . d)
  *   dL/dm_j  = sum_i g (w_i . d)
- * G0 and G1 are treated as independent leaves.  gtab is double[2K]
+ * G0 and G1 are treated as independent leaves.  gtab_abs (2K), when not
+ * NULL, receives the sums of the absolute terms; gmj_abs (nj_total) receives
+ * sum_i |w_i . d| (|G0_k| + |G1_k| (s_{k+1} - s_k)), the size g can take in
+ * its bin (its G1 part scaled by the bin width rather than by s - s_k, which
+ * an FP32 evaluation of s knows only to one rounding of s).
+ * gtab is double[2K]
  * interleaved like the table; gmj is per j entry of the arrays (an entry used
  * by several items accumulates over them).  Items run one after another so
  * that no two threads add into the same j entry or bin.
@@ -431,13 +451,15 @@ PGO_EXPORT void pgo_lut_bwd_items(long n_items, const int32_t *items, const doub
                                   const double *yj, const double *zj, const double *mj,
                                   const double *wx, const double *wy, const double *wz, int E,
                                   int F, double rcut, const double *table, double *gtab,
-                                  double *gmj, long nj_total)
+                                  double *gmj, long nj_total, double *gtab_abs, double *gmj_abs)
 {
     const long K = 1L << (E + F);
     const double smax = pgo_smax(E, F);
     const double c = (smax - 2.0) / (rcut * rcut);
     memset(gtab, 0, sizeof(double) * 2 * K);
     if (gmj) memset(gmj, 0, sizeof(double) * nj_total);
+    if (gtab_abs) memset(gtab_abs, 0, sizeof(double) * 2 * K);
+    if (gmj_abs) memset(gmj_abs, 0, sizeof(double) * nj_total);
     for (long t = 0; t < n_items; t++) {
         const long i0 = items[4 * t + 0], n_i = items[4 * t + 1];
         const long j0 = items[4 * t + 2], n_j = items[4 * t + 3];
@@ -456,6 +478,14 @@ PGO_EXPORT void pgo_lut_bwd_items(long n_items, const int32_t *items, const doub
                 gtab[2 * k] += m * wd;
                 gtab[2 * k + 1] += m * (s - sk) * wd;
                 if (gmj) gmj[j] += g * wd;
+                if (gtab_abs) {
+                    gtab_abs[2 * k] += fabs(m * wd);
+                    gtab_abs[2 * k + 1] += fabs(m * (s - sk) * wd);
+                }
+                if (gmj_abs) {
+                    const double width = (k + 1 < K) ? pgo_node_s(E, F, k + 1) - sk : 0.0;
+                    gmj_abs[j] += fabs(wd) * (fabs(table[2 * k]) + fabs(table[2 * k + 1]) * width);
+                }
             }
         }
     }

@@ -251,6 +251,33 @@ def pgh_batch_table(ctx, plan, xi, yi, zi, xj, yj, zj, mj, ax, ay, az):
                                     _ptr(ay, None, "ay"), _ptr(az, None, "az")))
 
 
+def pgh_newton_allpairs_bwd(ctx, n, x, y, z, m, eps2, wx, wy, wz, gx, gy, gz, gm):
+    _check(ctx, lib.pgh_newton_allpairs_bwd(ctx, n, _ptr(x, n, "x"), _ptr(y, n, "y"),
+                                            _ptr(z, n, "z"), _ptr(m, n, "m"), float(eps2),
+                                            _ptr(wx, n, "wx"), _ptr(wy, n, "wy"),
+                                            _ptr(wz, n, "wz"), _ptr(gx, n, "gx"),
+                                            _ptr(gy, n, "gy"), _ptr(gz, n, "gz"),
+                                            _ptr(gm, n, "gm")))
+
+
+def pgh_newton_ij_bwd(ctx, ni, xi, yi, zi, eps2_i, nj, xj, yj, zj, mj, wx, wy, wz,
+                      gxi, gyi, gzi, gxj, gyj, gzj, gmj):
+    _check(ctx, lib.pgh_newton_ij_bwd(
+        ctx, ni, _ptr(xi, ni, "xi"), _ptr(yi, ni, "yi"), _ptr(zi, ni, "zi"),
+        _ptr(eps2_i, ni, "eps2_i"), nj, _ptr(xj, nj, "xj"), _ptr(yj, nj, "yj"),
+        _ptr(zj, nj, "zj"), _ptr(mj, nj, "mj"), _ptr(wx, ni, "wx"), _ptr(wy, ni, "wy"),
+        _ptr(wz, ni, "wz"), _ptr(gxi, ni, "gxi"), _ptr(gyi, ni, "gyi"), _ptr(gzi, ni, "gzi"),
+        _ptr(gxj, nj, "gxj"), _ptr(gyj, nj, "gyj"), _ptr(gzj, nj, "gzj"), _ptr(gmj, nj, "gmj")))
+
+
+def pgh_batch_table_bwd(ctx, plan, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, gtable, gmj):
+    _check(ctx, lib.pgh_batch_table_bwd(
+        ctx, plan, _ptr(xi, None, "xi"), _ptr(yi, None, "yi"), _ptr(zi, None, "zi"),
+        _ptr(xj, None, "xj"), _ptr(yj, None, "yj"), _ptr(zj, None, "zj"), _ptr(mj, None, "mj"),
+        _ptr(wx, None, "wx"), _ptr(wy, None, "wy"), _ptr(wz, None, "wz"),
+        _ptr(gtable, None, "gtable"), _ptr(gmj, None, "gmj")))
+
+
 def pgh_variant_count(family):
     return lib.pgh_variant_count(family)
 
@@ -406,3 +433,125 @@ class Plan:
             out = [c._empty(self.ni_total) for _ in range(3)]
         pgh_batch_table(c.h, self.h, xi, yi, zi, xj, yj, zj, mj, out[0], out[1], out[2])
         return out
+
+
+# --------------------------------------------------------------------------
+# Differentiable forces (the adjoint kernels behind torch.autograd)
+# --------------------------------------------------------------------------
+
+_default_contexts = {}
+
+
+def default_context(device=None) -> Context:
+    """One library context per device, created on first use."""
+    d = torch.cuda.current_device() if device is None else torch.device("cuda", device).index
+    if d not in _default_contexts:
+        _default_contexts[d] = Context(d)
+    return _default_contexts[d]
+
+
+def _zeros_if_none(g, like):
+    return torch.zeros_like(like) if g is None else g.contiguous()
+
+
+class NewtonAllPairs(torch.autograd.Function):
+    """Accelerations and raw potentials of N particles on each other (i-set =
+    j-set), softening eps.  Gradients flow from the accelerations to the
+    positions and masses through pgh_newton_allpairs_bwd; the potential is
+    returned as a non-differentiable output."""
+
+    @staticmethod
+    def forward(fctx, x, y, z, m, eps, lib_ctx=None):
+        c = lib_ctx or default_context(x.device.index)
+        c.set_eps_to_all(eps)
+        c.set_j(x, y, z, m)
+        ax, ay, az, phi = c.newton(x, y, z)
+        fctx.save_for_backward(x, y, z, m)
+        fctx.eps2 = float(torch.tensor(eps, dtype=torch.float32) ** 2)
+        fctx.lib_ctx = c
+        fctx.mark_non_differentiable(phi)
+        return ax, ay, az, phi
+
+    @staticmethod
+    def backward(fctx, gax, gay, gaz, gphi):
+        x, y, z, m = fctx.saved_tensors
+        c = fctx.lib_ctx
+        c._sync_stream()
+        wx, wy, wz = (_zeros_if_none(g, x) for g in (gax, gay, gaz))
+        n = x.numel()
+        gx, gy, gz, gm = (c._empty(n) for _ in range(4))
+        pgh_newton_allpairs_bwd(c.h, n, x, y, z, m, fctx.eps2, wx, wy, wz, gx, gy, gz, gm)
+        return gx, gy, gz, gm, None, None
+
+
+class NewtonIJ(torch.autograd.Function):
+    """Accelerations of the i-particles from separate j-particles, with
+    gradients to both position sets and the j masses (pgh_newton_ij_bwd)."""
+
+    @staticmethod
+    def forward(fctx, xi, yi, zi, xj, yj, zj, mj, eps, lib_ctx=None):
+        c = lib_ctx or default_context(xi.device.index)
+        c.set_eps_to_all(eps)
+        c.set_j(xj, yj, zj, mj)
+        ax, ay, az, _ = c.newton(xi, yi, zi, with_phi=False)
+        fctx.save_for_backward(xi, yi, zi, xj, yj, zj, mj)
+        fctx.lib_ctx = c
+        fctx.eps = eps
+        return ax, ay, az
+
+    @staticmethod
+    def backward(fctx, gax, gay, gaz):
+        xi, yi, zi, xj, yj, zj, mj = fctx.saved_tensors
+        c = fctx.lib_ctx
+        c.set_eps_to_all(fctx.eps)
+        c._sync_stream()
+        wx, wy, wz = (_zeros_if_none(g, xi) for g in (gax, gay, gaz))
+        ni, nj = xi.numel(), xj.numel()
+        gi = [c._empty(ni) for _ in range(3)]
+        gj = [c._empty(nj) for _ in range(4)]
+        pgh_newton_ij_bwd(c.h, ni, xi, yi, zi, None, nj, xj, yj, zj, mj, wx, wy, wz, *gi, *gj)
+        return (*gi, *gj, None, None)
+
+
+class TableForceBatch(torch.autograd.Function):
+    """Table force of every list of a Plan, differentiable with respect to the
+    table entries (G0 and G1 as independent leaves, interleaved like the
+    table) and the j masses through pgh_batch_table_bwd.  Position
+    gradients of the table force are not provided: asking for them raises."""
+
+    @staticmethod
+    def forward(fctx, plan, E, F, rcut, table, xi, yi, zi, xj, yj, zj, mj):
+        c = plan.ctx
+        c.set_table(E, F, rcut, table)
+        out = plan.table(xi, yi, zi, xj, yj, zj, mj)
+        fctx.save_for_backward(table, xi, yi, zi, xj, yj, zj, mj)
+        fctx.plan = plan
+        fctx.shape = (E, F, float(rcut))
+        return tuple(out)
+
+    @staticmethod
+    def backward(fctx, gax, gay, gaz):
+        if any(fctx.needs_input_grad[5:11]):
+            raise NotImplementedError("position gradients of the table force are not provided")
+        table, xi, yi, zi, xj, yj, zj, mj = fctx.saved_tensors
+        plan = fctx.plan
+        c = plan.ctx
+        E, F, rcut = fctx.shape
+        c.set_table(E, F, rcut, table)
+        wx, wy, wz = (_zeros_if_none(g, xi) for g in (gax, gay, gaz))
+        gt = c._empty(table.numel()) if fctx.needs_input_grad[4] else None
+        gm = c._empty(plan.nj_total) if fctx.needs_input_grad[11] else None
+        pgh_batch_table_bwd(c.h, plan.h, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, gt, gm)
+        return (None, None, None, None, gt, None, None, None, None, None, None, gm)
+
+
+def newton_allpairs(x, y, z, m, eps, lib_ctx=None):
+    return NewtonAllPairs.apply(x, y, z, m, eps, lib_ctx)
+
+
+def newton_ij(xi, yi, zi, xj, yj, zj, mj, eps, lib_ctx=None):
+    return NewtonIJ.apply(xi, yi, zi, xj, yj, zj, mj, eps, lib_ctx)
+
+
+def table_force_batch(plan, E, F, rcut, table, xi, yi, zi, xj, yj, zj, mj):
+    return TableForceBatch.apply(plan, E, F, rcut, table, xi, yi, zi, xj, yj, zj, mj)

@@ -1,0 +1,565 @@
+// Adjoints of L = sum_i w_i . a_i for both forces (derived from
+// Eq. newton_force and from the interpolation of Sec. 3.4.2).  Pair terms are
+// recomputed, never stored.
+//
+// Newton, with d = r_j - r_i, rho = (|d|^2 + eps_i^2)^{-1/2} and the pair
+// term T = m_j rho^3 (w_i . d):
+//   dT/dd = m_j [rho^3 w_i - 3 rho^5 (w_i . d) d],  dd/dr_j = I, dd/dr_i = -I,
+//   dT/dm_j = rho^3 (w_i . d).
+//
+// All-pairs over one shared set (i-set = j-set, one eps): both roles of a
+// particle k fold into one gather over l (d = r_l - r_k):
+//   g_k  = m_k sum_l rho^3 w_l - w_k sum_l m_l rho^3
+//          + 3 sum_l rho^5 [m_l (w_k . d) - m_k (w_l . d)] d
+//   gm_k = -sum_l rho^3 (w_l . d)
+// which is 26 VALU ops and one rsqrt per pair (29 with the Newton-Raphson
+// step), against 13 (16) for the forward pass.  The j-records carry
+// (x, y, z, m) and (wx, wy, wz) in two 16-byte LDS entries.
+//
+// Separate sets: an i-major pass gives gxi, a j-major pass (j in registers,
+// i streamed through LDS) gives gxj and gmj.
+//
+// Table force, with g = G0_k + G1_k (s - s_k), T = m_j g (w_i . d):
+//   dL/dG0_k = sum over pairs in bin k of m_j (w_i . d)
+//   dL/dG1_k = sum over pairs in bin k of m_j (s - s_k) (w_i . d)
+//   dL/dm_j  = sum_i g (w_i . d)
+// The table gradient is accumulated in LDS with float atomics per workgroup
+// and flushed once; pairs clamped to the last node (beyond rcut, where
+// s - s_k = 0) add to a per-lane register instead, so the common
+// out-of-range pair costs no atomic.  dL/dm_j comes from a j-major pass over
+// the same lists.
+#include "pgh_internal.h"
+
+namespace pgh {
+
+// ---------------------------------------------------------------------------
+// packing
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_pack_xw(int n, const float *__restrict__ x,
+                                                 const float *__restrict__ y,
+                                                 const float *__restrict__ z,
+                                                 const float *__restrict__ s, float s_all,
+                                                 const float *__restrict__ wx,
+                                                 const float *__restrict__ wy,
+                                                 const float *__restrict__ wz,
+                                                 float4 *__restrict__ dst)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        dst[2 * i] = make_float4(x[i], y[i], z[i], s ? s[i] : s_all);
+        dst[2 * i + 1] = make_float4(wx[i], wy[i], wz[i], 0.f);
+    }
+}
+
+hipError_t launch_pack_xw(int n, const float *x, const float *y, const float *z, const float *s,
+                          float s_all, const float *wx, const float *wy, const float *wz,
+                          float4 *dst, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_xw, dim3((n + 255) / 256), dim3(256), 0, st, n, x, y, z, s, s_all,
+                       wx, wy, wz, dst);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <bool REFINE>
+__device__ __forceinline__ float rsqrt_of(float q)
+{
+    const float y = __builtin_amdgcn_rsqf(q);
+    if (!REFINE) return y;
+    return y * __builtin_fmaf(-0.5f * q, y * y, 1.5f);
+}
+
+// ---------------------------------------------------------------------------
+// all-pairs Newton adjoint over one shared set
+// ---------------------------------------------------------------------------
+
+template <int JT, bool REFINE>
+__global__ void __launch_bounds__(256) k_newton_allpairs_bwd(int n, const float4 *__restrict__ rec,
+                                                             float eps2, float *__restrict__ gx,
+                                                             float *__restrict__ gy,
+                                                             float *__restrict__ gz,
+                                                             float *__restrict__ gm)
+{
+    static_assert(JT % 256 == 0, "tile must be a multiple of the workgroup");
+    constexpr int PER = JT / 256;
+    __shared__ float4 tile[2][JT][2];
+    const int tid = threadIdx.x;
+    const int k = blockIdx.x * 256 + tid;
+    const int kc = k < n ? k : n - 1;
+    const float4 pk = rec[2 * kc], wk = rec[2 * kc + 1];
+
+    float Ax = 0.f, Ay = 0.f, Az = 0.f, B = 0.f, Cx = 0.f, Cy = 0.f, Cz = 0.f, G = 0.f;
+    const int ntiles = (n + JT - 1) / JT;
+    float4 pre[PER][2];
+    auto load = [&](int t) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int j = t * JT + r * 256 + tid;
+            float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+            if (j < n) {
+                a = rec[2 * j];
+                b = rec[2 * j + 1];
+            }
+            pre[r][0] = a;
+            pre[r][1] = b;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            tile[buf][r * 256 + tid][0] = pre[r][0];
+            tile[buf][r * 256 + tid][1] = pre[r][1];
+        }
+    };
+    load(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    store(0);
+    __syncthreads();
+    for (int t = 0; t < ntiles; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < ntiles) load(t + 1);
+        const int cnt = min(JT, n - t * JT);
+        float ax = 0.f, ay = 0.f, az = 0.f, b = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, gg = 0.f;
+        // The tile holding this workgroup's own particles (tile t == blockIdx.x,
+        // as JT equals the workgroup size) skips each lane's self pair, whose
+        // term is identically zero but would enter A and B as +-m_k w_k/eps^3
+        // and cancel only to rounding.
+        const int self = (t == (int)blockIdx.x) ? tid : -1;
+        auto pair = [&](const float4 p, const float4 w) {
+            const float dx = p.x - pk.x, dy = p.y - pk.y, dz = p.z - pk.z;
+            float q = __builtin_fmaf(dx, dx, eps2);
+            q = __builtin_fmaf(dy, dy, q);
+            q = __builtin_fmaf(dz, dz, q);
+            const float r1 = rsqrt_of<REFINE>(q);
+            const float r2 = r1 * r1;
+            const float r3 = r2 * r1;
+            const float r5 = r3 * r2;
+            ax = __builtin_fmaf(r3, w.x, ax);
+            ay = __builtin_fmaf(r3, w.y, ay);
+            az = __builtin_fmaf(r3, w.z, az);
+            b = __builtin_fmaf(p.w, r3, b);
+            float wld = w.x * dx;
+            wld = __builtin_fmaf(w.y, dy, wld);
+            wld = __builtin_fmaf(w.z, dz, wld);
+            float wkd = wk.x * dx;
+            wkd = __builtin_fmaf(wk.y, dy, wkd);
+            wkd = __builtin_fmaf(wk.z, dz, wkd);
+            const float e = __builtin_fmaf(p.w, wkd, -pk.w * wld);
+            const float f = r5 * e;
+            cx = __builtin_fmaf(f, dx, cx);
+            cy = __builtin_fmaf(f, dy, cy);
+            cz = __builtin_fmaf(f, dz, cz);
+            gg = __builtin_fmaf(r3, wld, gg);
+        };
+        if (self < 0) {
+#pragma unroll 4
+            for (int jj = 0; jj < cnt; ++jj) pair(tile[cur][jj][0], tile[cur][jj][1]);
+        } else {
+            for (int jj = 0; jj < cnt; ++jj) {
+                // a zero-weight, zero-mass stand-in for the self pair adds 0
+                float4 p = tile[cur][jj][0], w = tile[cur][jj][1];
+                if (jj == self) {
+                    p = make_float4(pk.x + 1.f, pk.y, pk.z, 0.f);
+                    w = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                pair(p, w);
+            }
+        }
+        Ax += ax, Ay += ay, Az += az, B += b, Cx += cx, Cy += cy, Cz += cz, G += gg;
+        if (t + 1 < ntiles) store(cur ^ 1);
+        __syncthreads();
+    }
+    if (k < n) {
+        gx[k] = pk.w * Ax - wk.x * B + 3.f * Cx;
+        gy[k] = pk.w * Ay - wk.y * B + 3.f * Cy;
+        gz[k] = pk.w * Az - wk.z * B + 3.f * Cz;
+        if (gm) gm[k] = -G;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// separate sets: i-major pass (gxi) and j-major pass (gxj, gmj)
+// ---------------------------------------------------------------------------
+
+// i-records: (x, y, z, eps2), (wx, wy, wz, -); j-records: (x, y, z, m).
+template <int JT, bool REFINE>
+__global__ void __launch_bounds__(256) k_newton_bwd_i(int ni, const float4 *__restrict__ irec,
+                                                      int nj, const float4 *__restrict__ jmem,
+                                                      float *__restrict__ gx,
+                                                      float *__restrict__ gy,
+                                                      float *__restrict__ gz)
+{
+    constexpr int PER = JT / 256;
+    __shared__ float4 tile[2][JT];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * 256 + tid;
+    const int ic = i < ni ? i : ni - 1;
+    const float4 pi = irec[2 * ic], wi = irec[2 * ic + 1];
+    float B = 0.f, Cx = 0.f, Cy = 0.f, Cz = 0.f;
+    const int ntiles = (nj + JT - 1) / JT;
+    float4 pre[PER];
+    auto load = [&](int t) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int j = t * JT + r * 256 + tid;
+            pre[r] = j < nj ? jmem[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) tile[buf][r * 256 + tid] = pre[r];
+    };
+    load(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    store(0);
+    __syncthreads();
+    for (int t = 0; t < ntiles; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < ntiles) load(t + 1);
+        const int cnt = min(JT, nj - t * JT);
+        float b = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+#pragma unroll 4
+        for (int jj = 0; jj < cnt; ++jj) {
+            const float4 p = tile[cur][jj];
+            const float dx = p.x - pi.x, dy = p.y - pi.y, dz = p.z - pi.z;
+            float q = __builtin_fmaf(dx, dx, pi.w);
+            q = __builtin_fmaf(dy, dy, q);
+            q = __builtin_fmaf(dz, dz, q);
+            const float r1 = rsqrt_of<REFINE>(q);
+            const float r2 = r1 * r1;
+            const float mr3 = p.w * (r2 * r1);
+            b += mr3;
+            float wid = wi.x * dx;
+            wid = __builtin_fmaf(wi.y, dy, wid);
+            wid = __builtin_fmaf(wi.z, dz, wid);
+            const float f = mr3 * r2 * wid;
+            cx = __builtin_fmaf(f, dx, cx);
+            cy = __builtin_fmaf(f, dy, cy);
+            cz = __builtin_fmaf(f, dz, cz);
+        }
+        B += b, Cx += cx, Cy += cy, Cz += cz;
+        if (t + 1 < ntiles) store(cur ^ 1);
+        __syncthreads();
+    }
+    if (i < ni) {
+        gx[i] = 3.f * Cx - wi.x * B;
+        gy[i] = 3.f * Cy - wi.y * B;
+        gz[i] = 3.f * Cz - wi.z * B;
+    }
+}
+
+template <int IT, bool REFINE>
+__global__ void __launch_bounds__(256) k_newton_bwd_j(int nj, const float4 *__restrict__ jmem,
+                                                      int ni, const float4 *__restrict__ irec,
+                                                      float *__restrict__ gx,
+                                                      float *__restrict__ gy,
+                                                      float *__restrict__ gz,
+                                                      float *__restrict__ gm)
+{
+    constexpr int PER = IT / 256;
+    __shared__ float4 tile[2][IT][2];
+    const int tid = threadIdx.x;
+    const int j = blockIdx.x * 256 + tid;
+    const int jc = j < nj ? j : nj - 1;
+    const float4 pj = jmem[jc];
+    float Ax = 0.f, Ay = 0.f, Az = 0.f, Cx = 0.f, Cy = 0.f, Cz = 0.f, G = 0.f;
+    const int ntiles = (ni + IT - 1) / IT;
+    float4 pre[PER][2];
+    auto load = [&](int t) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int i = t * IT + r * 256 + tid;
+            // padding i-records: unit softening, zero weight -> no contribution
+            float4 a = make_float4(0.f, 0.f, 0.f, 1.f), b = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (i < ni) {
+                a = irec[2 * i];
+                b = irec[2 * i + 1];
+            }
+            pre[r][0] = a;
+            pre[r][1] = b;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            tile[buf][r * 256 + tid][0] = pre[r][0];
+            tile[buf][r * 256 + tid][1] = pre[r][1];
+        }
+    };
+    load(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    store(0);
+    __syncthreads();
+    for (int t = 0; t < ntiles; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < ntiles) load(t + 1);
+        const int cnt = min(IT, ni - t * IT);
+        float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, gg = 0.f;
+#pragma unroll 4
+        for (int ii = 0; ii < cnt; ++ii) {
+            const float4 p = tile[cur][ii][0];
+            const float4 w = tile[cur][ii][1];
+            const float dx = pj.x - p.x, dy = pj.y - p.y, dz = pj.z - p.z;
+            float q = __builtin_fmaf(dx, dx, p.w);
+            q = __builtin_fmaf(dy, dy, q);
+            q = __builtin_fmaf(dz, dz, q);
+            const float r1 = rsqrt_of<REFINE>(q);
+            const float r2 = r1 * r1;
+            const float r3 = r2 * r1;
+            ax = __builtin_fmaf(r3, w.x, ax);
+            ay = __builtin_fmaf(r3, w.y, ay);
+            az = __builtin_fmaf(r3, w.z, az);
+            float wid = w.x * dx;
+            wid = __builtin_fmaf(w.y, dy, wid);
+            wid = __builtin_fmaf(w.z, dz, wid);
+            gg = __builtin_fmaf(r3, wid, gg);
+            const float f = r3 * r2 * wid;
+            cx = __builtin_fmaf(f, dx, cx);
+            cy = __builtin_fmaf(f, dy, cy);
+            cz = __builtin_fmaf(f, dz, cz);
+        }
+        Ax += ax, Ay += ay, Az += az, Cx += cx, Cy += cy, Cz += cz, G += gg;
+        if (t + 1 < ntiles) store(cur ^ 1);
+        __syncthreads();
+    }
+    if (j < nj) {
+        if (gx) {
+            gx[j] = pj.w * (Ax - 3.f * Cx);
+            gy[j] = pj.w * (Ay - 3.f * Cy);
+            gz[j] = pj.w * (Az - 3.f * Cz);
+        }
+        if (gm) gm[j] = G;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// table-force adjoint over a plan
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void table_g(float r2, float c, float smax, unsigned shift,
+                                        unsigned nbits, unsigned hmask,
+                                        const float2 *__restrict__ stab, unsigned &k, float &ds,
+                                        float &g)
+{
+    const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
+    const unsigned u = __float_as_uint(s);
+    k = __builtin_amdgcn_ubfe(u, shift, nbits);
+    ds = s - __uint_as_float(u & hmask);
+    const float2 g01 = stab[k];
+    g = __builtin_fmaf(g01.y, ds, g01.x);
+}
+
+// i-major: table gradient.  Uses the plan's tasks (i-chunks x j-parts).
+__global__ void __launch_bounds__(256) k_table_bwd_tab(TableBwdArgs A)
+{
+    extern __shared__ float dyn[];
+    const BatchArgs &a = A.b;
+    const int K = 1 << (a.E + a.F);
+    float2 *stab = (float2 *)dyn;           // K (G0, G1)
+    float *gt = dyn + 2 * K;                // 2K gradient accumulators
+    __shared__ float4 jt[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < K; k += 256) {
+        stab[k] = a.table[k];
+        gt[2 * k] = 0.f;
+        gt[2 * k + 1] = 0.f;
+    }
+    __syncthreads();
+    const unsigned shift = 23u - (unsigned)a.F, nbits = (unsigned)(a.E + a.F);
+    const unsigned hmask = ~((1u << shift) - 1u);
+    const unsigned klast = (unsigned)K - 1u;
+    float last0 = 0.f;  // clamped pairs: dL/dG0 of the last node
+
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0)
+            t = __hip_atomic_fetch_add(&a.queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= (unsigned)a.n_tasks) break;
+        const Task tk = a.tasks[t];
+        // one lane per i-particle here (lanes past n_i carry zero weight)
+        const bool active = lane < tk.n_i;
+        const int i = tk.i_off + (active ? lane : 0);
+        const float px = a.xi[i], py = a.yi[i], pz = a.zi[i];
+        const float wx = active ? A.wx[i] : 0.f, wy = active ? A.wy[i] : 0.f,
+                    wz = active ? A.wz[i] : 0.f;
+        for (int base = 0; base < tk.n_j; base += 64) {
+            const int cnt = min(64, tk.n_j - base);
+            const int j = tk.j_off + base + lane;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (lane < cnt) v = make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j]);
+            jt[wave][lane] = v;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int jj = 0; jj < cnt; ++jj) {
+                const float4 p = jt[wave][jj];
+                const float dx = p.x - px, dy = p.y - py, dz = p.z - pz;
+                float r2 = dx * dx;
+                r2 = __builtin_fmaf(dy, dy, r2);
+                r2 = __builtin_fmaf(dz, dz, r2);
+                unsigned k;
+                float ds, g;
+                table_g(r2, a.c, a.smax, shift, nbits, hmask, stab, k, ds, g);
+                float wd = wx * dx;
+                wd = __builtin_fmaf(wy, dy, wd);
+                wd = __builtin_fmaf(wz, dz, wd);
+                const float v0 = p.w * wd;
+                if (k == klast) {
+                    last0 += v0;
+                } else if (active) {
+                    atomicAdd(&gt[2 * k], v0);
+                    atomicAdd(&gt[2 * k + 1], v0 * ds);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    // wave sum of the clamped-bin register, then flush this workgroup's bins
+    for (int off = 32; off > 0; off >>= 1) last0 += __shfl_xor(last0, off);
+    if (lane == 0 && last0 != 0.f) atomicAdd(&gt[2 * klast], last0);
+    __syncthreads();
+    for (int k = threadIdx.x; k < 2 * K; k += 256)
+        if (gt[k] != 0.f) atomicAdd(&A.gtable[k], gt[k]);
+}
+
+// j-major: dL/dm_j = sum_i g (w_i . d).  Tasks are (j-chunk of <= 64
+// entries, i-range); results go to gmj with float atomics (a j entry used by
+// several lists accumulates over them).
+__global__ void __launch_bounds__(256) k_table_bwd_m(TableBwdArgs A, const Task *jtasks,
+                                                     int n_jtasks, unsigned *jqueue)
+{
+    extern __shared__ float dyn[];
+    const BatchArgs &a = A.b;
+    const int K = 1 << (a.E + a.F);
+    float2 *stab = (float2 *)dyn;
+    __shared__ float4 it[4][64][2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < K; k += 256) stab[k] = a.table[k];
+    __syncthreads();
+    const unsigned shift = 23u - (unsigned)a.F, nbits = (unsigned)(a.E + a.F);
+    const unsigned hmask = ~((1u << shift) - 1u);
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0)
+            t = __hip_atomic_fetch_add(&jqueue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= (unsigned)n_jtasks) break;
+        const Task tk = jtasks[t];  // i_off/n_i: the j-chunk, j_off/n_j: the i-range
+        const bool active = lane < tk.n_i;
+        const int j = tk.i_off + (active ? lane : 0);
+        const float qx = a.xj[j], qy = a.yj[j], qz = a.zj[j];
+        float G = 0.f;
+        for (int base = 0; base < tk.n_j; base += 64) {
+            const int cnt = min(64, tk.n_j - base);
+            const int i = tk.j_off + base + lane;
+            float4 p = make_float4(0.f, 0.f, 0.f, 0.f), w = p;
+            if (lane < cnt) {
+                p = make_float4(a.xi[i], a.yi[i], a.zi[i], 0.f);
+                w = make_float4(A.wx[i], A.wy[i], A.wz[i], 0.f);
+            }
+            it[wave][lane][0] = p;
+            it[wave][lane][1] = w;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int ii = 0; ii < cnt; ++ii) {
+                const float4 pi = it[wave][ii][0];
+                const float4 wi = it[wave][ii][1];
+                const float dx = qx - pi.x, dy = qy - pi.y, dz = qz - pi.z;
+                float r2 = dx * dx;
+                r2 = __builtin_fmaf(dy, dy, r2);
+                r2 = __builtin_fmaf(dz, dz, r2);
+                unsigned k;
+                float ds, g;
+                table_g(r2, a.c, a.smax, shift, nbits, hmask, stab, k, ds, g);
+                float wd = wi.x * dx;
+                wd = __builtin_fmaf(wi.y, dy, wd);
+                wd = __builtin_fmaf(wi.z, dz, wd);
+                G = __builtin_fmaf(g, wd, G);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (active) atomicAdd(&A.gmj[j], G);
+    }
+}
+
+__global__ void k_reset_counter(unsigned *q0, unsigned *q1)
+{
+    if (threadIdx.x == 0) {
+        *q0 = 0u;
+        if (q1) *q1 = 0u;
+    }
+}
+
+int resident(const void *k, size_t lds)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, lds) != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+}  // namespace
+
+hipError_t launch_newton_allpairs_bwd(int n, const float4 *rec, float eps2, bool refine, float *gx,
+                                      float *gy, float *gz, float *gm, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    auto k = refine ? k_newton_allpairs_bwd<256, true> : k_newton_allpairs_bwd<256, false>;
+    hipLaunchKernelGGL(k, dim3((n + 255) / 256), dim3(256), 0, s, n, rec, eps2, gx, gy, gz, gm);
+    return hipGetLastError();
+}
+
+hipError_t launch_newton_bwd_i(int ni, const float4 *irec, int nj, const float4 *jmem,
+                               bool refine, float *gx, float *gy, float *gz, hipStream_t s)
+{
+    if (ni <= 0) return hipSuccess;
+    auto k = refine ? k_newton_bwd_i<256, true> : k_newton_bwd_i<256, false>;
+    hipLaunchKernelGGL(k, dim3((ni + 255) / 256), dim3(256), 0, s, ni, irec, nj, jmem, gx, gy, gz);
+    return hipGetLastError();
+}
+
+hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 *irec,
+                               bool refine, float *gx, float *gy, float *gz, float *gm,
+                               hipStream_t s)
+{
+    if (nj <= 0) return hipSuccess;
+    auto k = refine ? k_newton_bwd_j<256, true> : k_newton_bwd_j<256, false>;
+    hipLaunchKernelGGL(k, dim3((nj + 255) / 256), dim3(256), 0, s, nj, jmem, ni, irec, gx, gy, gz,
+                       gm);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int n_jtasks,
+                                  unsigned *jqueue, int num_cu, hipStream_t s)
+{
+    const int K = 1 << (A.b.E + A.b.F);
+    hipError_t e;
+    if (A.gtable && A.b.n_tasks > 0) {
+        const size_t lds = (size_t)K * 4 * sizeof(float);
+        const int blocks = num_cu * resident((const void *)k_table_bwd_tab, lds);
+        hipLaunchKernelGGL(k_table_bwd_tab, dim3(blocks), dim3(256), lds, s, A);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, A.b.queue, (unsigned *)nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (A.gmj && n_jtasks > 0) {
+        const size_t lds = (size_t)K * 2 * sizeof(float);
+        const int blocks = num_cu * resident((const void *)k_table_bwd_m, lds);
+        hipLaunchKernelGGL(k_table_bwd_m, dim3(blocks), dim3(256), lds, s, A, jtasks, n_jtasks,
+                           jqueue);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, jqueue, (unsigned *)nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace pgh

@@ -23,6 +23,9 @@ struct pgh_plan {
     unsigned *queue;        // device, task counter reset by every launch
     float4 *partial;        // device, 64 partial sums per slot
     SplitChunk *chunks;     // device, the split chunks
+    int n_jtasks;           // j-major tasks (adjoint of the masses)
+    Task *jtasks;           // device
+    unsigned *jqueue;       // device, counter of the j-major tasks
 };
 
 struct pgh_ctx {
@@ -41,6 +44,9 @@ struct pgh_ctx {
     float tab_rcut = 0.f;
     float2 *tab = nullptr;  // device, 2^kMaxTableBits entries
     int variant[4] = {-1, -1, -1, -1};
+    // scratch records of the adjoints (grown on demand)
+    float4 *scr_a = nullptr, *scr_b = nullptr;
+    size_t scr_a_cap = 0, scr_b_cap = 0;
     std::vector<pgh_plan *> plans;
     std::string err;
 };
@@ -91,6 +97,33 @@ int check_table_shape(pgh_ctx *c, int E, int F, float rcut)
     if (F < 0 || F > 10) return fail(c, PGH_ERANGE, "F must be in [0, 10]");
     if (E + F > kMaxTableBits) return fail(c, PGH_ERANGE, "E + F must be <= 12");
     if (!(rcut > 0.f) || !std::isfinite(rcut)) return fail(c, PGH_ERANGE, "rcut must be > 0");
+    return PGH_OK;
+}
+
+void free_plan_memory(pgh_plan *p)
+{
+    (void)hipFree(p->tasks);
+    (void)hipFree(p->queue);
+    (void)hipFree(p->partial);
+    (void)hipFree(p->chunks);
+    (void)hipFree(p->jtasks);
+    (void)hipFree(p->jqueue);
+}
+
+// Grows a scratch buffer of float4 records (synchronises before freeing).
+int ensure_scratch(pgh_ctx *c, float4 **buf, size_t *cap, size_t n)
+{
+    if (n <= *cap) return PGH_OK;
+    const size_t want = std::max(n, *cap * 2);
+    float4 *nb = nullptr;
+    if (hipMalloc((void **)&nb, want * sizeof(float4)) != hipSuccess)
+        return fail(c, PGH_ENOMEM, "hipMalloc(scratch) failed");
+    if (*buf) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(*buf);
+    }
+    *buf = nb;
+    *cap = want;
     return PGH_OK;
 }
 
@@ -156,12 +189,11 @@ int pgh_close(pgh_ctx *c)
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (pgh_plan *p : c->plans) {
-        (void)hipFree(p->tasks);
-        (void)hipFree(p->queue);
-        (void)hipFree(p->partial);
-        (void)hipFree(p->chunks);
+        free_plan_memory(p);
         delete p;
     }
+    (void)hipFree(c->scr_a);
+    (void)hipFree(c->scr_b);
     (void)hipFree(c->jmem);
     (void)hipFree(c->tab);
     delete c;
@@ -467,12 +499,20 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     p->queue = nullptr;
     p->partial = nullptr;
     p->chunks = nullptr;
+    p->jtasks = nullptr;
+    p->jqueue = nullptr;
+    // j-major tasks: chunks of <= 64 j-entries of a list against its i-group
+    std::vector<Task> jt;
+    for (int t : order) {
+        const pgh_item &it = items[t];
+        for (int s0 = 0; s0 < it.n_j; s0 += 64)
+            jt.push_back({it.j_off + s0, std::min(64, it.n_j - s0), it.i_off, it.n_i, 0, 1, 0, 0});
+    }
+    std::stable_sort(jt.begin(), jt.end(), [](const Task &a, const Task &b) { return a.n_j > b.n_j; });
+    p->n_jtasks = (int)jt.size();
     DeviceGuard g(c->device);
     auto cleanup = [&](int code, const char *msg) {
-        (void)hipFree(p->tasks);
-        (void)hipFree(p->queue);
-        (void)hipFree(p->partial);
-        (void)hipFree(p->chunks);
+        free_plan_memory(p);
         delete p;
         return fail(c, code, msg);
     };
@@ -487,6 +527,14 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     if (n_chunks > 0 &&
         hipMalloc((void **)&p->chunks, (size_t)n_chunks * sizeof(SplitChunk)) != hipSuccess)
         return cleanup(PGH_ENOMEM, "hipMalloc(split chunks) failed");
+    if (hipMalloc((void **)&p->jqueue, 2 * sizeof(unsigned)) != hipSuccess)
+        return cleanup(PGH_ENOMEM, "hipMalloc(queue) failed");
+    if (!jt.empty() && hipMalloc((void **)&p->jtasks, jt.size() * sizeof(Task)) != hipSuccess)
+        return cleanup(PGH_ENOMEM, "hipMalloc(tasks) failed");
+    if (hipMemsetAsync(p->jqueue, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
+        (!jt.empty() && hipMemcpyAsync(p->jtasks, jt.data(), jt.size() * sizeof(Task),
+                                       hipMemcpyHostToDevice, c->stream) != hipSuccess))
+        return cleanup(PGH_EHIP, "uploading the plan failed");
     if (hipMemsetAsync(p->queue, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
         (n_chunks > 0 &&
          hipMemcpyAsync(p->chunks, split.data(), split.size() * sizeof(SplitChunk),
@@ -509,10 +557,7 @@ int pgh_plan_free(pgh_ctx *c, pgh_plan *p)
     if (it == c->plans.end()) return fail(c, PGH_EINVAL, "plan does not belong to this context");
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(p->tasks);
-    (void)hipFree(p->queue);
-    (void)hipFree(p->partial);
-    (void)hipFree(p->chunks);
+    free_plan_memory(p);
     c->plans.erase(it);
     delete p;
     return PGH_OK;
@@ -595,27 +640,98 @@ int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, const float 
     return PGH_OK;
 }
 
-int pgh_newton_allpairs_bwd(pgh_ctx *c, int, const float *, const float *, const float *,
-                            const float *, float, const float *, const float *, const float *,
-                            float *, float *, float *, float *)
+int pgh_newton_allpairs_bwd(pgh_ctx *c, int n, const float *x, const float *y, const float *z,
+                            const float *m, float eps2, const float *wx, const float *wy,
+                            const float *wz, float *gx, float *gy, float *gz, float *gm)
 {
-    return fail(c, PGH_ESTATE, "adjoints are not available in this build");
+    if (!c) return PGH_EINVAL;
+    if (n < 0) return fail(c, PGH_EINVAL, "n must be >= 0");
+    if (n == 0) return PGH_OK;
+    if (!x || !y || !z || !m || !wx || !wy || !wz || !gx || !gy || !gz)
+        return fail(c, PGH_EINVAL, "NULL array");
+    if (!(eps2 > 0.f) || !std::isfinite(eps2)) return fail(c, PGH_ERANGE, "eps2 must be > 0");
+    DeviceGuard g(c->device);
+    int st = ensure_scratch(c, &c->scr_a, &c->scr_a_cap, 2 * (size_t)n);
+    if (st) return st;
+    PGH_HIP(c, launch_pack_xw(n, x, y, z, m, 0.f, wx, wy, wz, c->scr_a, c->stream));
+    PGH_HIP(c, launch_newton_allpairs_bwd(n, c->scr_a, eps2, c->refine != 0, gx, gy, gz, gm,
+                                          c->stream));
+    return PGH_OK;
 }
 
-int pgh_newton_ij_bwd(pgh_ctx *c, int, const float *, const float *, const float *, const float *,
-                      int, const float *, const float *, const float *, const float *,
-                      const float *, const float *, const float *, float *, float *, float *,
-                      float *, float *, float *, float *)
+int pgh_newton_ij_bwd(pgh_ctx *c, int ni, const float *xi, const float *yi, const float *zi,
+                      const float *eps2_i, int nj, const float *xj, const float *yj,
+                      const float *zj, const float *mj, const float *wx, const float *wy,
+                      const float *wz, float *gxi, float *gyi, float *gzi, float *gxj,
+                      float *gyj, float *gzj, float *gmj)
 {
-    return fail(c, PGH_ESTATE, "adjoints are not available in this build");
+    if (!c) return PGH_EINVAL;
+    if (ni < 0 || nj < 0) return fail(c, PGH_EINVAL, "counts must be >= 0");
+    const bool want_i = gxi || gyi || gzi;
+    const bool want_j = gxj || gyj || gzj;
+    if (want_i && !(gxi && gyi && gzi)) return fail(c, PGH_EINVAL, "gxi, gyi, gzi: all or none");
+    if (want_j && !(gxj && gyj && gzj)) return fail(c, PGH_EINVAL, "gxj, gyj, gzj: all or none");
+    if (ni > 0 && (!xi || !yi || !zi || !wx || !wy || !wz))
+        return fail(c, PGH_EINVAL, "NULL i-particle or weight array");
+    if (nj > 0 && (!xj || !yj || !zj || !mj)) return fail(c, PGH_EINVAL, "NULL j-particle array");
+    if (!eps2_i && !(c->eps2_all > 0.f))
+        return fail(c, PGH_ERANGE, "the softening must be > 0 for the adjoint");
+    DeviceGuard g(c->device);
+    if (ni == 0 || nj == 0) {
+        if (want_i) {
+            int st = zero_outputs(c, ni, gxi, gyi, gzi, nullptr);
+            if (st) return st;
+        }
+        return zero_outputs(c, nj, gxj, gyj, gzj, gmj);
+    }
+    int st = ensure_scratch(c, &c->scr_a, &c->scr_a_cap, 2 * (size_t)ni);
+    if (st) return st;
+    st = ensure_scratch(c, &c->scr_b, &c->scr_b_cap, (size_t)nj);
+    if (st) return st;
+    PGH_HIP(c, launch_pack_xw(ni, xi, yi, zi, eps2_i, c->eps2_all, wx, wy, wz, c->scr_a, c->stream));
+    PGH_HIP(c, launch_pack_j(nj, xj, yj, zj, mj, c->scr_b, c->stream));
+    const bool rf = c->refine != 0;
+    if (want_i) PGH_HIP(c, launch_newton_bwd_i(ni, c->scr_a, nj, c->scr_b, rf, gxi, gyi, gzi, c->stream));
+    if (want_j || gmj)
+        PGH_HIP(c, launch_newton_bwd_j(nj, c->scr_b, ni, c->scr_a, rf, gxj, gyj, gzj, gmj,
+                                       c->stream));
+    return PGH_OK;
 }
 
-int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *, const float *, const float *,
-                        const float *, const float *, const float *, const float *,
-                        const float *, const float *, const float *, const float *, float *,
-                        float *)
+int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
+                        const float *zi, const float *xj, const float *yj, const float *zj,
+                        const float *mj, const float *wx, const float *wy, const float *wz,
+                        float *gtable, float *gmj)
 {
-    return fail(c, PGH_ESTATE, "adjoints are not available in this build");
+    if (!c) return PGH_EINVAL;
+    int st = check_plan(c, p);
+    if (st) return st;
+    if (!c->tab_set) return fail(c, PGH_ESTATE, "no force table set");
+    if (!gtable && !gmj) return PGH_OK;
+    if (p->ni_total > 0 && (!xi || !yi || !zi || !wx || !wy || !wz))
+        return fail(c, PGH_EINVAL, "NULL i-particle or weight array");
+    if (p->nj_total > 0 && (!xj || !yj || !zj || !mj))
+        return fail(c, PGH_EINVAL, "NULL j-particle array");
+    DeviceGuard g(c->device);
+    const int K = 1 << (c->tab_E + c->tab_F);
+    if (gtable) PGH_HIP(c, launch_fill_zero(2 * K, gtable, nullptr, nullptr, nullptr, c->stream));
+    if (gmj) PGH_HIP(c, launch_fill_zero(p->nj_total, gmj, nullptr, nullptr, nullptr, c->stream));
+    TableBwdArgs A{};
+    A.b = batch_args(c, p);
+    A.b.xi = xi, A.b.yi = yi, A.b.zi = zi;
+    A.b.xj = xj, A.b.yj = yj, A.b.zj = zj, A.b.mj = mj;
+    const double smax = smax_of(c->tab_E, c->tab_F);
+    const double rc = c->tab_rcut;
+    A.b.table = c->tab;
+    A.b.E = c->tab_E;
+    A.b.F = c->tab_F;
+    A.b.c = (float)((smax - 2.0) / (rc * rc));
+    A.b.smax = (float)smax;
+    A.wx = wx, A.wy = wy, A.wz = wz;
+    A.gtable = gtable;
+    A.gmj = gmj;
+    PGH_HIP(c, launch_table_batch_bwd(A, p->jtasks, p->n_jtasks, p->jqueue, c->num_cu, c->stream));
+    return PGH_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -70,18 +70,6 @@ struct BatchArgs {
     float c, smax;
 };
 
-// Arguments of the adjoint kernels.
-struct NewtonBwdArgs {
-    int ni;
-    const float *xi, *yi, *zi, *eps2i;
-    float eps2_all;
-    int nj;
-    const float *xj, *yj, *zj, *mj;
-    const float *wx, *wy, *wz;
-    float *gxi, *gyi, *gzi;
-    float *gxj, *gyj, *gzj, *gmj;
-};
-
 struct CombineArgs {
     int n_chunks;
     const SplitChunk *chunks;
@@ -123,11 +111,18 @@ hipError_t launch_newton_batch(const BatchArgs &a, bool refine, bool guard, int 
                                hipStream_t s);
 hipError_t launch_table_batch(const BatchArgs &a, int num_cu, hipStream_t s);
 
-hipError_t launch_newton_allpairs_bwd(int n, const float4 *jm, const float4 *w, float eps2,
-                                      float *gx, float *gy, float *gz, float *gm, hipStream_t s);
-hipError_t launch_pack_w(int n, const float *wx, const float *wy, const float *wz, float4 *dst,
-                         hipStream_t s);
-hipError_t launch_newton_ij_bwd(const NewtonBwdArgs &a, hipStream_t s);
-hipError_t launch_table_batch_bwd(const TableBwdArgs &a, int num_cu, hipStream_t s);
+// Records of two float4: (x, y, z, s or s_all) and (wx, wy, wz, 0).
+hipError_t launch_pack_xw(int n, const float *x, const float *y, const float *z, const float *s,
+                          float s_all, const float *wx, const float *wy, const float *wz,
+                          float4 *dst, hipStream_t st);
+hipError_t launch_newton_allpairs_bwd(int n, const float4 *rec, float eps2, bool refine, float *gx,
+                                      float *gy, float *gz, float *gm, hipStream_t s);
+hipError_t launch_newton_bwd_i(int ni, const float4 *irec, int nj, const float4 *jmem,
+                               bool refine, float *gx, float *gy, float *gz, hipStream_t s);
+hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 *irec,
+                               bool refine, float *gx, float *gy, float *gz, float *gm,
+                               hipStream_t s);
+hipError_t launch_table_batch_bwd(const TableBwdArgs &a, const Task *jtasks, int n_jtasks,
+                                  unsigned *jqueue, int num_cu, hipStream_t s);
 
 }  // namespace pgh

@@ -1,0 +1,211 @@
+"""GPU parity of the adjoint kernels (L = sum_i w_i . a_i) against the FP64
+oracle's gradients and against FP64 central finite differences, through the
+C ABI and through torch.autograd.
+
+Gate (per particle or per table bin, normalised by the sum of absolute pair
+terms, with s - s_k bounded by the bin width for the G1 bins): rms <= 1e-5,
+max <= 1e-3."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _helpers import rms, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pgh():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_1203_4037_amd as p
+    return p
+
+
+@pytest.fixture()
+def ctx(pgh):
+    c = pgh.Context(0)
+    yield c
+    c.close()
+
+
+def _gate(got, ref, scale, what):
+    got = np.atleast_2d(got)
+    ref = np.atleast_2d(ref)
+    err = np.sqrt(np.sum((got - ref) ** 2, axis=0)) / np.maximum(scale, 1e-300)
+    err = err[scale > 0]
+    assert rms(err) <= 1e-5 and err.max() <= 1e-3, (what, rms(err), err.max())
+    return err
+
+
+def _table_gate(gt, rt, at, E, F, what):
+    """G0 bins against their absolute-term sums; G1 bins against the bin
+    width times the G0 scale: s is an FP32 number in the method (its bits
+    pick the bin), so s - s_k carries an FP32 rounding of s that the FP64
+    reference does not have, and |s - s_k| < s_{k+1} - s_k bounds each term."""
+    K = 1 << (E + F)
+    sk = np.array([oracle.node_s(E, F, k) for k in range(K)] + [oracle.smax(E, F)])
+    width = np.maximum(np.diff(sk), 1.0)  # the last bin (s = s_max) has no width
+    _gate(gt[0::2], rt[0::2], at[0::2], what + " G0")
+    _gate(gt[1::2], rt[1::2], at[0::2] * width, what + " G1")
+
+
+def _allpairs_gpu(pgh, ctx, x, y, z, m, eps2, w):
+    import torch
+    n = x.size
+    d = to_dev(x, y, z, m, *w)
+    out = [torch.empty(n, device="cuda") for _ in range(4)]
+    pgh.pgh_newton_allpairs_bwd(ctx.h, n, d[0], d[1], d[2], d[3], eps2, d[4], d[5], d[6], *out)
+    return to_host(*out)
+
+
+@pytest.mark.parametrize("refine", [1, 0])
+def test_allpairs_adjoint_vs_oracle(pgh, ctx, refine):
+    n = 2048
+    x, y, z = synth.plummer(n, 105)
+    m = synth.equal_masses(n)
+    eps2 = np.float32(0.01) ** 2
+    w = synth.weights(n, 205)
+    ctx.set_rsqrt_refine(refine)
+    gx, gy, gz, gm = _allpairs_gpu(pgh, ctx, x, y, z, m, eps2, w)
+    e2 = np.full(n, eps2, np.float32)
+    r = oracle.newton_bwd(x, y, z, e2, x, y, z, m, *w, scales=True)
+    gref = np.stack(r[0:3]) + np.stack(r[3:6])
+    _gate(np.stack([gx, gy, gz]), gref, r[7] + r[8], "gx")
+    _gate(gm, r[6], r[9], "gm")
+
+
+def test_allpairs_adjoint_full_size_sampled(pgh, ctx):
+    """N = 65536 Plummer sphere (seed 105), eps = 0.01: full GPU launch; the
+    oracle recomputes both roles of 256 sampled particles."""
+    n = 65536
+    x, y, z = synth.plummer(n, 105)
+    m = synth.equal_masses(n)
+    eps2 = np.float32(0.01) ** 2
+    w = synth.weights(n, 205)
+    gx, gy, gz, gm = _allpairs_gpu(pgh, ctx, x, y, z, m, eps2, w)
+    rng = np.random.default_rng(3)
+    k = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, 254)]))
+    e2 = np.full(n, eps2, np.float32)
+    ri = oracle.newton_bwd(x[k], y[k], z[k], e2[k], x, y, z, m, w[0][k], w[1][k], w[2][k], scales=True)
+    rj = oracle.newton_bwd(x, y, z, e2, x[k], y[k], z[k], m[k], *w, scales=True)
+    gref = np.stack(ri[0:3]) + np.stack(rj[3:6])
+    _gate(np.stack([gx[k], gy[k], gz[k]]), gref, ri[7] + rj[8], "gx")
+    _gate(gm[k], rj[6], rj[9], "gm")
+
+
+@pytest.mark.parametrize("ni,nj", [(1, 1), (65, 257), (1000, 777), (300, 4100)])
+def test_ij_adjoint_vs_oracle(pgh, ctx, ni, nj):
+    import torch
+    xi, yi, zi = synth.plummer(ni, 500 + ni)
+    xj, yj, zj = synth.plummer(nj, 600 + nj)
+    rng = np.random.default_rng(ni + nj)
+    mj = rng.uniform(0.1, 1.0, nj).astype(np.float32)
+    eps2 = rng.uniform(1e-4, 1e-2, ni).astype(np.float32)
+    w = synth.weights(ni, 7)
+    di = to_dev(xi, yi, zi, eps2, *w)
+    dj = to_dev(xj, yj, zj, mj)
+    gi = [torch.empty(ni, device="cuda") for _ in range(3)]
+    gj = [torch.empty(nj, device="cuda") for _ in range(4)]
+    pgh.pgh_newton_ij_bwd(ctx.h, ni, di[0], di[1], di[2], di[3], nj, *dj, di[4], di[5], di[6],
+                          *gi, *gj)
+    r = oracle.newton_bwd(xi, yi, zi, eps2, xj, yj, zj, mj, *w, scales=True)
+    _gate(np.stack(to_host(*gi)), np.stack(r[0:3]), r[7], "gxi")
+    _gate(np.stack(to_host(*gj[:3])), np.stack(r[3:6]), r[8], "gxj")
+    _gate(to_host(gj[3])[0], r[6], r[9], "gmj")
+
+
+def test_autograd_newton_vs_finite_differences(pgh):
+    """torch.autograd through the library's adjoint against FP64 central
+    differences of the oracle's forward sum."""
+    import torch
+    n = 96
+    x, y, z = synth.plummer(n, 42)
+    m = np.linspace(0.5, 1.5, n).astype(np.float32) / n
+    eps = np.float32(0.05)
+    w = synth.weights(n, 43)
+    t = [torch.tensor(a, device="cuda", requires_grad=True) for a in (x, y, z, m)]
+    ax, ay, az, phi = pgh.newton_allpairs(*t, float(eps))
+    wt = to_dev(*w)
+    loss = (ax * wt[0] + ay * wt[1] + az * wt[2]).sum()
+    loss.backward()
+    g = np.stack([to_host(tt.grad)[0] for tt in t])
+
+    X = [a.astype(np.float64) for a in (x, y, z)]
+    e2 = np.full(n, np.float64(eps) ** 2)
+
+    def L(P, M):
+        a = oracle.newton(*P, e2, *P, M)
+        return float(sum(np.sum(w[k] * a[k]) for k in range(3)))
+
+    h = 1e-6
+    fd = np.zeros((4, n))
+    for ax_ in range(3):
+        for k in range(n):
+            p = [a.copy() for a in X]; q = [a.copy() for a in X]
+            p[ax_][k] += h; q[ax_][k] -= h
+            fd[ax_, k] = (L(p, m) - L(q, m)) / (2 * h)
+    M = m.astype(np.float64)
+    for k in range(n):
+        p = M.copy(); p[k] += 1e-3
+        q = M.copy(); q[k] -= 1e-3
+        fd[3, k] = (L(X, p) - L(X, q)) / 2e-3
+    for r in range(4):
+        err = np.abs(g[r] - fd[r]) / np.abs(fd[r]).max()
+        assert err.max() < 1e-4, (r, err.max())
+
+
+def test_table_adjoint_cell_lists(pgh, ctx):
+    """The table-force adjoint on cell lists: N = 65536 uniform in the unit
+    periodic box, 64^3 cells, 8^3-cell groups, S2 PP shape (rcut = 3/256,
+    eps = 1/1280, E = 4, F = 6); gradients with respect to every (G0, G1)
+    entry and to the j masses."""
+    import torch
+    n = 65536
+    x, y, z = synth.uniform_box(n, 105)
+    m = synth.equal_masses(n)
+    rcut, eps = 3.0 / 256, 1.0 / 1280
+    s = synth.cell_grid_items(x, y, z, m, ncell=64, block=8)
+    table = ctx.build_table(4, 6, rcut, eps=eps)
+    w = synth.weights(n, 305)
+    plan = ctx.plan(s.items, n, s.xj.size)
+    di = to_dev(s.xi, s.yi, s.zi, *w)
+    dj = to_dev(s.xj, s.yj, s.zj, s.mj)
+    gt = torch.empty(table.size, device="cuda")
+    gm = torch.empty(s.xj.size, device="cuda")
+    pgh.pgh_batch_table_bwd(ctx.h, plan.h, di[0], di[1], di[2], *dj, di[3], di[4], di[5], gt, gm)
+    rt, rm, at, am = oracle.lut_bwd_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, *w,
+                                          4, 6, float(np.float32(rcut)), table, scales=True)
+    _table_gate(to_host(gt)[0], rt, at, 4, 6, "gtable")
+    _gate(to_host(gm)[0], rm, am, "gmj")
+
+
+def test_autograd_table_force(pgh, ctx):
+    """TableForceBatch: gradients of the table and masses equal the direct
+    adjoint call; asking for position gradients raises."""
+    import torch
+    n = 8192
+    x, y, z = synth.uniform_box(n, 9)
+    m = synth.equal_masses(n)
+    rcut, eps, E, F = 1.0 / 16, 1.0 / 16 / 15, 4, 5
+    s = synth.cell_grid_items(x, y, z, m, ncell=16, block=4)
+    table = ctx.build_table(E, F, rcut, eps=eps)
+    plan = ctx.plan(s.items, n, s.xj.size)
+    tab = torch.tensor(table, device="cuda", requires_grad=True)
+    mj = torch.tensor(s.mj, device="cuda", requires_grad=True)
+    di = to_dev(s.xi, s.yi, s.zi)
+    dj = to_dev(s.xj, s.yj, s.zj)
+    w = to_dev(*synth.weights(n, 1))
+    ax, ay, az = pgh.table_force_batch(plan, E, F, rcut, tab, *di, *dj, mj)
+    (ax * w[0] + ay * w[1] + az * w[2]).sum().backward()
+    rt, rm, at, am = oracle.lut_bwd_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj,
+                                          *[to_host(t)[0] for t in w], E, F,
+                                          float(np.float32(rcut)), table, scales=True)
+    _table_gate(to_host(tab.grad)[0], rt, at, E, F, "gtable")
+    _gate(to_host(mj.grad)[0], rm, am, "gmj")
+    xr = di[0].clone().requires_grad_(True)
+    ax, ay, az = pgh.table_force_batch(plan, E, F, rcut, tab, xr, di[1], di[2], *dj, mj)
+    with pytest.raises(NotImplementedError):
+        ax.sum().backward()

@@ -1,0 +1,99 @@
+"""Pins of the FP64 oracle's adjoints of L = sum_i w_i . a_i against central
+finite differences of the oracle's own forward sums (which are pinned
+against the paper in the other oracle tests)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def _loss_newton(xi, yi, zi, e2, xj, yj, zj, mj, w):
+    ax, ay, az, _ = oracle.newton(xi, yi, zi, e2, xj, yj, zj, mj)
+    return float(np.sum(w[0] * ax + w[1] * ay + w[2] * az))
+
+
+def _setup(ni=7, nj=9, seed=3):
+    rng = np.random.default_rng(seed)
+    xi = [a.astype(np.float64) for a in synth.plummer(ni, seed)]
+    xj = [a.astype(np.float64) for a in synth.plummer(nj, seed + 1)]
+    mj = rng.uniform(0.2, 1.0, nj)
+    e2 = rng.uniform(0.01, 0.04, ni)
+    w = [rng.standard_normal(ni) for _ in range(3)]
+    return xi, xj, mj, e2, w
+
+
+def test_newton_position_gradients_match_central_differences():
+    xi, xj, mj, e2, w = _setup()
+    g = oracle.newton_bwd(*xi, e2, *xj, mj, *w)
+    gxi, gxj = np.stack(g[0:3]), np.stack(g[3:6])
+    h = 1e-5
+    for ax in range(3):
+        for i in range(len(xi[0])):
+            p = [a.copy() for a in xi]; m = [a.copy() for a in xi]
+            p[ax][i] += h; m[ax][i] -= h
+            fd = (_loss_newton(*p, e2, *xj, mj, w) - _loss_newton(*m, e2, *xj, mj, w)) / (2 * h)
+            assert fd == pytest.approx(gxi[ax, i], rel=1e-7, abs=1e-7 * np.abs(gxi).max())
+        for j in range(len(xj[0])):
+            p = [a.copy() for a in xj]; m = [a.copy() for a in xj]
+            p[ax][j] += h; m[ax][j] -= h
+            fd = (_loss_newton(*xi, e2, *p, mj, w) - _loss_newton(*xi, e2, *m, mj, w)) / (2 * h)
+            assert fd == pytest.approx(gxj[ax, j], rel=1e-7, abs=1e-7 * np.abs(gxj).max())
+
+
+def test_newton_mass_gradient_is_exact_for_a_linear_loss():
+    xi, xj, mj, e2, w = _setup(5, 6, 11)
+    gmj = oracle.newton_bwd(*xi, e2, *xj, mj, *w)[6]
+    for j in range(len(mj)):
+        p = mj.copy(); p[j] += 0.5
+        m = mj.copy(); m[j] -= 0.5
+        fd = (_loss_newton(*xi, e2, *xj, p, w) - _loss_newton(*xi, e2, *xj, m, w)) / 1.0
+        assert fd == pytest.approx(gmj[j], rel=1e-11, abs=1e-12 * np.abs(gmj).max())
+
+
+def test_shared_set_gradient_is_sum_of_both_roles():
+    """With i-set = j-set (all pairs, one eps) moving particle k moves it as a
+    target and as a source: dL/dx_k = gxi_k + gxj_k (the quantity the fused
+    all-pairs adjoint computes)."""
+    n = 8
+    x = [a.astype(np.float64) for a in synth.plummer(n, 5)]
+    m = np.linspace(0.3, 1.1, n)
+    e2 = np.full(n, 0.02)
+    w = [np.random.default_rng(2).standard_normal(n) for _ in range(3)]
+    g = oracle.newton_bwd(*x, e2, *x, m, *w)
+    tot = np.stack(g[0:3]) + np.stack(g[3:6])
+    h = 1e-5
+    for ax in range(3):
+        for k in range(n):
+            p = [a.copy() for a in x]; q = [a.copy() for a in x]
+            p[ax][k] += h; q[ax][k] -= h
+            fd = (_loss_newton(*p, e2, *p, m, w) - _loss_newton(*q, e2, *q, m, w)) / (2 * h)
+            assert fd == pytest.approx(tot[ax, k], rel=1e-7, abs=1e-7 * np.abs(tot).max())
+
+
+def test_table_gradients_are_exact_for_a_linear_loss():
+    E, F, rcut, eps = 3, 3, 0.3, 0.02
+    t = oracle.table_build(E, F, rcut, oracle.SHAPE_S2PP, eps).astype(np.float64)
+    n = 40
+    x, y, z = [a.astype(np.float64) for a in synth.uniform_box(n, 8, box=0.5)]
+    mj = np.linspace(0.5, 1.5, n)
+    w = [np.random.default_rng(4).standard_normal(n) for _ in range(3)]
+    items = np.array([[0, 20, 0, 40], [20, 20, 10, 25]], np.int32)
+    gt, gm = oracle.lut_bwd_items(items, x, y, z, x, y, z, mj, *w, E, F, rcut, t)
+
+    def loss(tab, m):
+        ax, ay, az, _ = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rcut, tab)
+        return float(np.sum(w[0] * ax + w[1] * ay + w[2] * az))
+
+    scale_t = np.abs(gt).max()
+    for k in range(t.size):
+        p = t.copy(); p[k] += 1.0
+        q = t.copy(); q[k] -= 1.0
+        fd = (loss(p, mj) - loss(q, mj)) / 2.0
+        assert fd == pytest.approx(gt[k], rel=1e-9, abs=1e-12 * scale_t)
+    assert np.any(gt[0::2] != 0) and np.any(gt[1::2] != 0)
+    for j in range(n):
+        p = mj.copy(); p[j] += 0.25
+        q = mj.copy(); q[j] -= 0.25
+        fd = (loss(t, p) - loss(t, q)) / 0.5
+        assert fd == pytest.approx(gm[j], rel=1e-9, abs=1e-12 * np.abs(gm).max())
