@@ -204,6 +204,78 @@ def batched_table(torch, pgh, synth):
             "frac_of_peak_20flop": TABLE_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12)}
 
 
+def adjoint_newton(torch, pgh, synth):
+    """Forward + backward of L = sum_i w_i . a_i over all pairs of a Plummer
+    sphere of N = 65536 (seed 105), eps = 0.01, w ~ N(0, 1)^3: kernel-only
+    times of pgh_calc_newton and pgh_newton_allpairs_bwd, and the time of the
+    same through torch.autograd."""
+    n = 65536
+    x, y, z = synth.plummer(n, 105)
+    m = synth.equal_masses(n)
+    w = [torch.from_numpy(a).cuda() for a in synth.weights(n, 205)]
+    dev = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+    ctx = pgh.Context(0)
+    ctx.set_eps_to_all(0.01)
+    ctx.set_j(*dev)
+    out = [torch.empty(n, device="cuda") for _ in range(4)]
+    grads = [torch.empty(n, device="cuda") for _ in range(4)]
+    eps2 = float(np.float32(0.01) ** 2)
+    tf, tb = KernelTimer(torch), KernelTimer(torch)
+    for it in range(8):
+        with tf:
+            pgh.pgh_calc_newton(ctx.h, n, dev[0], dev[1], dev[2], None, *out)
+        with tb:
+            pgh.pgh_newton_allpairs_bwd(ctx.h, n, *dev, eps2, *w, *grads)
+    fwd, bwd = tf.mean_ms(), tb.mean_ms()
+    # through torch.autograd (includes packing and allocation)
+    req = [t.clone().requires_grad_(True) for t in dev]
+
+    def fwd_only():
+        with torch.no_grad():
+            pgh.newton_allpairs(*req, 0.01, ctx)
+
+    def fwd_bwd():
+        ax, ay, az, _ = pgh.newton_allpairs(*req, 0.01, ctx)
+        (ax * w[0] + ay * w[1] + az * w[2]).sum().backward()
+
+    t_f = time_steps(torch, fwd_only, 5, 2)
+    t_fb = time_steps(torch, fwd_bwd, 5, 2)
+    ctx.close()
+    inter = float(n) * n
+    return {"workload": "newton_allpairs_adjoint_plummer_N65536_eps0.01",
+            "fwd_kernel_ms": fwd, "bwd_kernel_ms": bwd,
+            "fwd_plus_bwd_over_fwd_kernel": (fwd + bwd) / fwd,
+            "fwd_plus_bwd_over_fwd_autograd": t_fb / t_f,
+            "bwd_interactions_per_s": inter / (bwd / 1e3)}
+
+
+def adjoint_table(torch, pgh, synth):
+    """Table-force forward and adjoint (table entries and masses) on cell
+    lists: N = 65536 uniform in the unit periodic box, 64^3 cells, 8^3-cell
+    groups, S2 PP shape (rcut = 3/256, eps = 1/1280, E = 4, F = 6)."""
+    n = 65536
+    x, y, z = synth.uniform_box(n, 105)
+    m = synth.equal_masses(n)
+    s = synth.cell_grid_items(x, y, z, m, ncell=64, block=8)
+    di = [torch.from_numpy(a).cuda() for a in (s.xi, s.yi, s.zi)]
+    dj = [torch.from_numpy(a).cuda() for a in (s.xj, s.yj, s.zj, s.mj)]
+    w = [torch.from_numpy(a).cuda() for a in synth.weights(n, 305)]
+    ctx = pgh.Context(0)
+    table = ctx.build_table(4, 6, 3.0 / 256, eps=1.0 / 1280)
+    plan = ctx.plan(s.items, n, s.xj.size)
+    out = [torch.empty(n, device="cuda") for _ in range(3)]
+    gt = torch.empty(table.size, device="cuda")
+    gm = torch.empty(s.xj.size, device="cuda")
+    f_ms = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 50)
+    b_ms = graph_ms(torch, lambda: pgh.pgh_batch_table_bwd(ctx.h, plan.h, *di, *dj, *w, gt, gm), 50)
+    inter = float(plan.interactions)
+    plan.free()
+    ctx.close()
+    return {"workload": "table_adjoint_cell_lists_N65536_8cube_groups_E4F6",
+            "interactions": inter, "fwd_ms": f_ms, "bwd_ms": b_ms,
+            "fwd_plus_bwd_over_fwd": (f_ms + b_ms) / f_ms}
+
+
 def table_allpairs(torch, pgh, synth):
     """Secondary: the table force on the same kind of call, N = 65536 uniform
     particles in a box of side 0.25 with the S2 PP shape (rcut = 3/256,
@@ -274,7 +346,9 @@ def main():
     if not args.no_extras:
         ex = {"table_allpairs": table_allpairs(torch, pgh, synth),
               "newton_batched": batched_newton(torch, pgh, synth),
-              "table_batched": batched_table(torch, pgh, synth)}
+              "table_batched": batched_table(torch, pgh, synth),
+              "adjoint_newton": adjoint_newton(torch, pgh, synth),
+              "adjoint_table": adjoint_table(torch, pgh, synth)}
         ex["batched_over_allpairs"] = ex["newton_batched"]["interactions_per_s"] / value
         line["extras"] = ex
     if not args.no_cpu:

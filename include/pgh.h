@@ -284,6 +284,18 @@ PGH_API const char *pgh_variant_name(int family, int v);
 PGH_API int pgh_set_variant(pgh_ctx *c, int family, int v);
 PGH_API int pgh_get_variant(const pgh_ctx *c, int family);
 
+/* Tunes an all-pairs family (PGH_FAMILY_NEWTON_ALLPAIRS or
+ * PGH_FAMILY_TABLE_ALLPAIRS) on the caller's workload: times every variant
+ * (one warm-up, then `reps` calls, hipEvents on the context stream) for the
+ * ni i-particles xi, yi, zi (device) against the current j-memory (and
+ * table), selects the fastest for later calls on c and returns its index
+ * (>= 0), or a negative status.  *best_ms (may be NULL) receives its time per
+ * call.  Synchronous; allocates and frees temporary outputs.  Persisting
+ * the choice across runs is left to the caller (the Python binding keeps a
+ * JSON cache keyed by device, family and problem shape). */
+PGH_API int pgh_autotune(pgh_ctx *c, int family, int ni, const float *xi, const float *yi,
+                         const float *zi, int reps, float *best_ms);
+
 #ifdef __cplusplus
 }
 #endif

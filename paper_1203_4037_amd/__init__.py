@@ -75,6 +75,7 @@ SIGNATURES = {
     "pgh_variant_name": (ctypes.c_char_p, [_I, _I]),
     "pgh_set_variant": (_I, [_P, _I, _I]),
     "pgh_get_variant": (_I, [_P, _I]),
+    "pgh_autotune": (_I, [_P, _I, _I, _P, _P, _P, _I, ctypes.POINTER(_F)]),
 }
 
 
@@ -295,6 +296,16 @@ def pgh_get_variant(ctx, family):
     return lib.pgh_get_variant(ctx, family)
 
 
+def pgh_autotune(ctx, family, ni, xi, yi, zi, reps=3):
+    """Returns (best variant, ms per call); the context keeps the choice."""
+    ms = ctypes.c_float()
+    v = lib.pgh_autotune(ctx, family, ni, _ptr(xi, ni, "xi"), _ptr(yi, ni, "yi"),
+                         _ptr(zi, ni, "zi"), int(reps), ctypes.byref(ms))
+    if v < 0:
+        _check(ctx, v)
+    return v, ms.value
+
+
 def s2pp_callback():
     """The library's built-in h(r) of the S2 particle-particle force shape
     (Eqs. s2pp and s2); pass user = ctypes pointer to double[2] {eps, rcut}."""
@@ -313,6 +324,7 @@ class Context:
         self.h = pgh_open(self.device)
         self.nj = 0
         self.table = None
+        self.refine = 1
 
     def close(self):
         if self.h:
@@ -336,6 +348,7 @@ class Context:
 
     def set_rsqrt_refine(self, on):
         pgh_set_rsqrt_refine(self.h, on)
+        self.refine = int(bool(on))
 
     def set_j(self, x, y, z, m, adr=0):
         """Copies j-particles into the j-memory at adr and sets n to adr + len."""
@@ -381,6 +394,36 @@ class Context:
 
     def set_variant(self, family, v):
         pgh_set_variant(self.h, family, v)
+
+    def autotune(self, family, x, y, z, reps=3, cache=None):
+        """Chooses the fastest variant of an all-pairs family for the i-particles
+        x, y, z against the current j-memory (and table).  With a cache path
+        (JSON) a previous choice for the same device, family and shape is
+        reused without timing.  Returns the variant index."""
+        import json
+        self._sync_stream()
+        key = None
+        if cache:
+            props = torch.cuda.get_device_properties(self.device)
+            key = "|".join(str(k) for k in (props.name, family, x.numel(), self.nj,
+                                             self.table if family == PGH_FAMILY_TABLE_ALLPAIRS else "",
+                                             self.refine))
+            try:
+                with open(cache) as f:
+                    table = json.load(f)
+            except (OSError, ValueError):
+                table = {}
+            if key in table and 0 <= table[key] < pgh_variant_count(family):
+                pgh_set_variant(self.h, family, table[key])
+                return table[key]
+        v, _ = pgh_autotune(self.h, family, x.numel(), x, y, z, reps)
+        if cache:
+            table[key] = v
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return v
 
     # interaction lists ------------------------------------------------------
 

@@ -28,6 +28,8 @@
 // s - s_k = 0) add to a per-lane register instead, so the common
 // out-of-range pair costs no atomic.  dL/dm_j comes from a j-major pass over
 // the same lists.
+#include <algorithm>
+
 #include "pgh_internal.h"
 
 namespace pgh {
@@ -76,12 +78,36 @@ __device__ __forceinline__ float rsqrt_of(float q)
 // all-pairs Newton adjoint over one shared set
 // ---------------------------------------------------------------------------
 
+// Output of a (possibly j-split) adjoint launch: with one share the four
+// results go to their arrays, with several to partial sums [S][4][n].
+struct Out4 {
+    float *a, *b, *c, *d;
+    float *part;
+    int jchunk;
+};
+
+__device__ __forceinline__ void store4(const Out4 &o, int n, int i, float va, float vb, float vc,
+                                       float vd)
+{
+    if (gridDim.y > 1) {
+        float *p = o.part + (size_t)blockIdx.y * 4 * n;
+        p[i] = va;
+        p[n + i] = vb;
+        p[2 * n + i] = vc;
+        p[3 * n + i] = vd;
+    } else {
+        if (o.a) {
+            o.a[i] = va;
+            o.b[i] = vb;
+            o.c[i] = vc;
+        }
+        if (o.d) o.d[i] = vd;
+    }
+}
+
 template <int JT, bool REFINE>
 __global__ void __launch_bounds__(256) k_newton_allpairs_bwd(int n, const float4 *__restrict__ rec,
-                                                             float eps2, float *__restrict__ gx,
-                                                             float *__restrict__ gy,
-                                                             float *__restrict__ gz,
-                                                             float *__restrict__ gm)
+                                                             float eps2, Out4 o)
 {
     static_assert(JT % 256 == 0, "tile must be a multiple of the workgroup");
     constexpr int PER = JT / 256;
@@ -92,16 +118,19 @@ __global__ void __launch_bounds__(256) k_newton_allpairs_bwd(int n, const float4
     const float4 pk = rec[2 * kc], wk = rec[2 * kc + 1];
 
     float Ax = 0.f, Ay = 0.f, Az = 0.f, B = 0.f, Cx = 0.f, Cy = 0.f, Cz = 0.f, G = 0.f;
-    const int ntiles = (n + JT - 1) / JT;
+    const int jbase = blockIdx.y * o.jchunk;
+    const int nj = max(0, min(o.jchunk, n - jbase));
+    const float4 *__restrict__ jrec = rec + 2 * (size_t)jbase;
+    const int ntiles = (nj + JT - 1) / JT;
     float4 pre[PER][2];
     auto load = [&](int t) {
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
             const int j = t * JT + r * 256 + tid;
             float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
-            if (j < n) {
-                a = rec[2 * j];
-                b = rec[2 * j + 1];
+            if (j < nj) {
+                a = jrec[2 * j];
+                b = jrec[2 * j + 1];
             }
             pre[r][0] = a;
             pre[r][1] = b;
@@ -121,13 +150,14 @@ __global__ void __launch_bounds__(256) k_newton_allpairs_bwd(int n, const float4
     for (int t = 0; t < ntiles; ++t) {
         const int cur = t & 1;
         if (t + 1 < ntiles) load(t + 1);
-        const int cnt = min(JT, n - t * JT);
+        const int cnt = min(JT, nj - t * JT);
         float ax = 0.f, ay = 0.f, az = 0.f, b = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, gg = 0.f;
-        // The tile holding this workgroup's own particles (tile t == blockIdx.x,
-        // as JT equals the workgroup size) skips each lane's self pair, whose
-        // term is identically zero but would enter A and B as +-m_k w_k/eps^3
-        // and cancel only to rounding.
-        const int self = (t == (int)blockIdx.x) ? tid : -1;
+        // The tile holding this workgroup's own particles (global tile index
+        // == blockIdx.x, as JT equals the workgroup size and shares start on
+        // tile boundaries) skips each lane's self pair, whose term is
+        // identically zero but would enter A and B as +-m_k w_k/eps^3 and
+        // cancel only to rounding.
+        const int self = (jbase / JT + t == (int)blockIdx.x) ? tid : -1;
         auto pair = [&](const float4 p, const float4 w) {
             const float dx = p.x - pk.x, dy = p.y - pk.y, dz = p.z - pk.z;
             float q = __builtin_fmaf(dx, dx, eps2);
@@ -172,12 +202,9 @@ __global__ void __launch_bounds__(256) k_newton_allpairs_bwd(int n, const float4
         if (t + 1 < ntiles) store(cur ^ 1);
         __syncthreads();
     }
-    if (k < n) {
-        gx[k] = pk.w * Ax - wk.x * B + 3.f * Cx;
-        gy[k] = pk.w * Ay - wk.y * B + 3.f * Cy;
-        gz[k] = pk.w * Az - wk.z * B + 3.f * Cz;
-        if (gm) gm[k] = -G;
-    }
+    if (k < n)
+        store4(o, n, k, pk.w * Ax - wk.x * B + 3.f * Cx, pk.w * Ay - wk.y * B + 3.f * Cy,
+               pk.w * Az - wk.z * B + 3.f * Cz, -G);
 }
 
 // ---------------------------------------------------------------------------
@@ -187,10 +214,8 @@ __global__ void __launch_bounds__(256) k_newton_allpairs_bwd(int n, const float4
 // i-records: (x, y, z, eps2), (wx, wy, wz, -); j-records: (x, y, z, m).
 template <int JT, bool REFINE>
 __global__ void __launch_bounds__(256) k_newton_bwd_i(int ni, const float4 *__restrict__ irec,
-                                                      int nj, const float4 *__restrict__ jmem,
-                                                      float *__restrict__ gx,
-                                                      float *__restrict__ gy,
-                                                      float *__restrict__ gz)
+                                                      int nj_all, const float4 *__restrict__ jall,
+                                                      Out4 o)
 {
     constexpr int PER = JT / 256;
     __shared__ float4 tile[2][JT];
@@ -199,6 +224,9 @@ __global__ void __launch_bounds__(256) k_newton_bwd_i(int ni, const float4 *__re
     const int ic = i < ni ? i : ni - 1;
     const float4 pi = irec[2 * ic], wi = irec[2 * ic + 1];
     float B = 0.f, Cx = 0.f, Cy = 0.f, Cz = 0.f;
+    const int jbase = blockIdx.y * o.jchunk;
+    const int nj = max(0, min(o.jchunk, nj_all - jbase));
+    const float4 *__restrict__ jmem = jall + jbase;
     const int ntiles = (nj + JT - 1) / JT;
     float4 pre[PER];
     auto load = [&](int t) {
@@ -244,20 +272,13 @@ __global__ void __launch_bounds__(256) k_newton_bwd_i(int ni, const float4 *__re
         if (t + 1 < ntiles) store(cur ^ 1);
         __syncthreads();
     }
-    if (i < ni) {
-        gx[i] = 3.f * Cx - wi.x * B;
-        gy[i] = 3.f * Cy - wi.y * B;
-        gz[i] = 3.f * Cz - wi.z * B;
-    }
+    if (i < ni) store4(o, ni, i, 3.f * Cx - wi.x * B, 3.f * Cy - wi.y * B, 3.f * Cz - wi.z * B, 0.f);
 }
 
 template <int IT, bool REFINE>
 __global__ void __launch_bounds__(256) k_newton_bwd_j(int nj, const float4 *__restrict__ jmem,
-                                                      int ni, const float4 *__restrict__ irec,
-                                                      float *__restrict__ gx,
-                                                      float *__restrict__ gy,
-                                                      float *__restrict__ gz,
-                                                      float *__restrict__ gm)
+                                                      int ni_all, const float4 *__restrict__ iall,
+                                                      Out4 o)
 {
     constexpr int PER = IT / 256;
     __shared__ float4 tile[2][IT][2];
@@ -266,6 +287,9 @@ __global__ void __launch_bounds__(256) k_newton_bwd_j(int nj, const float4 *__re
     const int jc = j < nj ? j : nj - 1;
     const float4 pj = jmem[jc];
     float Ax = 0.f, Ay = 0.f, Az = 0.f, Cx = 0.f, Cy = 0.f, Cz = 0.f, G = 0.f;
+    const int ibase = blockIdx.y * o.jchunk;
+    const int ni = max(0, min(o.jchunk, ni_all - ibase));
+    const float4 *__restrict__ irec = iall + 2 * (size_t)ibase;
     const int ntiles = (ni + IT - 1) / IT;
     float4 pre[PER][2];
     auto load = [&](int t) {
@@ -325,14 +349,8 @@ __global__ void __launch_bounds__(256) k_newton_bwd_j(int nj, const float4 *__re
         if (t + 1 < ntiles) store(cur ^ 1);
         __syncthreads();
     }
-    if (j < nj) {
-        if (gx) {
-            gx[j] = pj.w * (Ax - 3.f * Cx);
-            gy[j] = pj.w * (Ay - 3.f * Cy);
-            gz[j] = pj.w * (Az - 3.f * Cz);
-        }
-        if (gm) gm[j] = G;
-    }
+    if (j < nj)
+        store4(o, nj, j, pj.w * (Ax - 3.f * Cx), pj.w * (Ay - 3.f * Cy), pj.w * (Az - 3.f * Cz), G);
 }
 
 // ---------------------------------------------------------------------------
@@ -508,33 +526,61 @@ int resident(const void *k, size_t lds)
 
 }  // namespace
 
+namespace {
+
+// Launches an adjoint kernel over n outputs with its other index range m split
+// into S shares, then adds the shares.
+template <typename Kern, typename... Args>
+hipError_t launch_split(Kern k, int n, int m, int S, float *part, float *a, float *b, float *c,
+                        float *d, hipStream_t s, Args... args)
+{
+    S = std::max(1, S);
+    const int chunk = (int)(((long)m + (long)S * 256 - 1) / ((long)S * 256) * 256);
+    S = std::max(1, (m + chunk - 1) / chunk);
+    Out4 o{a, b, c, d, part, std::max(chunk, 1)};
+    hipLaunchKernelGGL(k, dim3((n + 255) / 256, S), dim3(256), 0, s, args..., o);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || S == 1) return e;
+    if (a) e = launch_combine_split(n, S, part, a, b, c, d, s);
+    else if (d) {
+        // only the fourth result: combine into it through its own slot
+        e = launch_combine_split(n, S, part, nullptr, nullptr, nullptr, d, s);
+    }
+    return e;
+}
+
+}  // namespace
+
+int adjoint_split(int n, int m, size_t part_cap)
+{
+    return split_count(n, m, 1, 256, kSplitTargetWaves, part_cap);
+}
+
 hipError_t launch_newton_allpairs_bwd(int n, const float4 *rec, float eps2, bool refine, float *gx,
-                                      float *gy, float *gz, float *gm, hipStream_t s)
+                                      float *gy, float *gz, float *gm, int S, float *part,
+                                      hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     auto k = refine ? k_newton_allpairs_bwd<256, true> : k_newton_allpairs_bwd<256, false>;
-    hipLaunchKernelGGL(k, dim3((n + 255) / 256), dim3(256), 0, s, n, rec, eps2, gx, gy, gz, gm);
-    return hipGetLastError();
+    return launch_split(k, n, n, S, part, gx, gy, gz, gm, s, n, rec, eps2);
 }
 
 hipError_t launch_newton_bwd_i(int ni, const float4 *irec, int nj, const float4 *jmem,
-                               bool refine, float *gx, float *gy, float *gz, hipStream_t s)
+                               bool refine, float *gx, float *gy, float *gz, int S, float *part,
+                               hipStream_t s)
 {
     if (ni <= 0) return hipSuccess;
     auto k = refine ? k_newton_bwd_i<256, true> : k_newton_bwd_i<256, false>;
-    hipLaunchKernelGGL(k, dim3((ni + 255) / 256), dim3(256), 0, s, ni, irec, nj, jmem, gx, gy, gz);
-    return hipGetLastError();
+    return launch_split(k, ni, nj, S, part, gx, gy, gz, (float *)nullptr, s, ni, irec, nj, jmem);
 }
 
 hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 *irec,
-                               bool refine, float *gx, float *gy, float *gz, float *gm,
-                               hipStream_t s)
+                               bool refine, float *gx, float *gy, float *gz, float *gm, int S,
+                               float *part, hipStream_t s)
 {
     if (nj <= 0) return hipSuccess;
     auto k = refine ? k_newton_bwd_j<256, true> : k_newton_bwd_j<256, false>;
-    hipLaunchKernelGGL(k, dim3((nj + 255) / 256), dim3(256), 0, s, nj, jmem, ni, irec, gx, gy, gz,
-                       gm);
-    return hipGetLastError();
+    return launch_split(k, nj, ni, S, part, gx, gy, gz, gm, s, nj, jmem, ni, irec);
 }
 
 hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int n_jtasks,

@@ -17,6 +17,8 @@
 // per workgroup; j-particles stream through LDS tiles exactly as in the
 // Newton kernel.  Pairs beyond the cutoff clamp to s_max, whose node is the
 // last one, where G0 = G1 = 0, so they add exactly zero.
+#include <algorithm>
+
 #include "pgh_internal.h"
 
 namespace pgh {
@@ -75,7 +77,10 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
         tx[k] = ty[k] = tz[k] = 0.f;
     }
 
-    const int nj = a.nj;
+    // this workgroup's share of the j-particles (blockIdx.y splits them)
+    const int jbase = blockIdx.y * a.jchunk;
+    const int nj = max(0, min(a.jchunk, a.nj - jbase));
+    const float4 *__restrict__ jm = a.jmem + jbase;
     const int ntiles = (nj + JT - 1) / JT;
     float4 pre[PER];
     auto load_tile = [&](int t) {
@@ -83,7 +88,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
         for (int r = 0; r < PER; ++r) {
             const int j = t * JT + r * 256 + tid;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (j < nj) v = a.jmem[j];
+            if (j < nj) v = jm[j];
             pre[r] = v;
         }
     };
@@ -133,13 +138,19 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
         __syncthreads();
     }
 
+    float *ox = a.ax, *oy = a.ay, *oz = a.az;
+    if (gridDim.y > 1) {
+        ox = a.part + (size_t)blockIdx.y * 4 * a.ni;
+        oy = ox + a.ni;
+        oz = oy + a.ni;
+    }
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
         const int i = ibase + k * 256;
         if (i < a.ni) {
-            a.ax[i] = tx[k];
-            a.ay[i] = ty[k];
-            a.az[i] = tz[k];
+            ox[i] = tx[k];
+            oy[i] = ty[k];
+            oz[i] = tz[k];
         }
     }
 }
@@ -148,14 +159,14 @@ using TableKernel = void (*)(TableArgs);
 
 struct TableVariant {
     const char *name;
-    int ki;
+    int ki, jt;
     TableKernel fn;
 };
 
 const TableVariant kTableVariants[] = {
-    {"ki=1 jt=256 u=4", 1, k_table_allpairs<1, 256, 4>},
-    {"ki=2 jt=256 u=4", 2, k_table_allpairs<2, 256, 4>},
-    {"ki=4 jt=256 u=2", 4, k_table_allpairs<4, 256, 2>},
+    {"ki=1 jt=256 u=4", 1, 256, k_table_allpairs<1, 256, 4>},
+    {"ki=2 jt=256 u=4", 2, 256, k_table_allpairs<2, 256, 4>},
+    {"ki=4 jt=256 u=2", 4, 256, k_table_allpairs<4, 256, 2>},
 };
 constexpr int kNumTableVariants = sizeof(kTableVariants) / sizeof(kTableVariants[0]);
 
@@ -175,15 +186,27 @@ int table_allpairs_default(int ni, int nj, int num_cu)
     return waves_ki2 >= 4L * num_cu ? 1 : 0;
 }
 
-hipError_t launch_table_allpairs(const TableArgs &a, int variant, hipStream_t s)
+int table_allpairs_split(int ni, int nj, int variant, size_t part_cap)
 {
-    if (a.ni <= 0) return hipSuccess;
     const TableVariant &v = kTableVariants[variant];
+    return split_count(ni, nj, v.ki, v.jt, 4 * kSplitTargetWaves, part_cap);
+}
+
+hipError_t launch_table_allpairs(const TableArgs &a0, int variant, int S, hipStream_t s)
+{
+    if (a0.ni <= 0) return hipSuccess;
+    const TableVariant &v = kTableVariants[variant];
+    TableArgs a = a0;
+    S = std::max(1, S);
+    a.jchunk = (int)(((long)a.nj + (long)S * v.jt - 1) / ((long)S * v.jt) * v.jt);
+    S = std::max(1, (a.nj + a.jchunk - 1) / a.jchunk);
     const int per_block = 256 * v.ki;
-    const dim3 grid((a.ni + per_block - 1) / per_block);
+    const dim3 grid((a.ni + per_block - 1) / per_block, S);
     const size_t lds = sizeof(float2) << (a.E + a.F);
     hipLaunchKernelGGL(v.fn, grid, dim3(256), lds, s, a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || S == 1) return e;
+    return launch_combine_split(a.ni, S, a.part, a0.ax, a0.ay, a0.az, nullptr, s);
 }
 
 }  // namespace pgh

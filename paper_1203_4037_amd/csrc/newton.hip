@@ -21,11 +21,16 @@
 //             removed by an exact scale of the sums at the end   6 ops
 //   phi -= m rho (1 op), a += mr3 * d (3 fma).
 // The mass in LDS is pre-scaled by -1/2 when refining, so the step costs
-// three VALU ops per pair, not four.
+// three VALU ops per pair, not four.  The "rcp" variants take rho^2 = 1/q
+// from v_rcp_f32 instead of squaring (mr3 = m rho * rcp(q)): the
+// transcendental unit issues beside the VALU, so this trades one VALU op
+// per pair for a second transcendental.
 //
 // Accuracy.  Sums over a tile are formed in fresh registers and added to
 // the running totals once per tile, so FP32 rounding grows with
 // JT + nj/JT rather than nj.
+#include <algorithm>
+
 #include "pgh_internal.h"
 
 namespace pgh {
@@ -48,6 +53,49 @@ hipError_t launch_pack_j(int n, const float *x, const float *y, const float *z, 
     return hipGetLastError();
 }
 
+// Adds the S partial sums [S][4][n] of a j-split launch in split order
+// (ax..az and phi each optional).
+__global__ void __launch_bounds__(256) k_combine_split(int n, int S, const float *__restrict__ part,
+                                                       float *ax, float *ay, float *az, float *phi)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;
+    for (int s = 0; s < S; ++s) {
+        const float *p = part + (size_t)s * 4 * n;
+        if (ax) {
+            sx += p[i];
+            sy += p[n + i];
+            sz += p[2 * n + i];
+        }
+        if (phi) sp += p[3 * n + i];
+    }
+    if (ax) {
+        ax[i] = sx;
+        ay[i] = sy;
+        az[i] = sz;
+    }
+    if (phi) phi[i] = sp;
+}
+
+hipError_t launch_combine_split(int n, int S, const float *part, float *ax, float *ay, float *az,
+                                float *phi, hipStream_t s)
+{
+    if (n <= 0 || S <= 1) return hipSuccess;
+    hipLaunchKernelGGL(k_combine_split, dim3((n + 255) / 256), dim3(256), 0, s, n, S, part, ax, ay,
+                       az, phi);
+    return hipGetLastError();
+}
+
+int split_count(int ni, int nj, int ki, int jt, int target_waves, size_t part_cap)
+{
+    const long waves = ((long)ni + 64L * ki - 1) / (64L * ki);
+    long S = (target_waves + waves - 1) / waves;
+    S = std::min(S, std::max(1L, (long)nj / (2L * jt)));  // at least two tiles per share
+    if (ni > 0) S = std::min(S, (long)(part_cap / (4 * (size_t)ni)));
+    return (int)std::max(1L, S);
+}
+
 __global__ void __launch_bounds__(256) k_fill_zero(int n, float *a, float *b, float *c, float *d)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -68,7 +116,16 @@ hipError_t launch_fill_zero(int n, float *a, float *b, float *c, float *d, hipSt
 
 namespace {
 
-template <bool REFINE, bool GUARD, bool PHI>
+// 1/q from the transcendental unit (v_rcp_f32), which issues alongside the
+// VALU; with GUARD a zero q gives 0 instead of inf.
+template <bool GUARD>
+__device__ __forceinline__ float rcp_of(float q)
+{
+    const float r = __builtin_amdgcn_rcpf(q);
+    return GUARD ? ((q > 0.f) ? r : 0.f) : r;
+}
+
+template <bool REFINE, bool GUARD, bool PHI, bool RCP>
 __device__ __forceinline__ void newton_pair(const float4 p, float px, float py, float pz,
                                             float pe, float &sx, float &sy, float &sz,
                                             float &sp)
@@ -87,12 +144,20 @@ __device__ __forceinline__ void newton_pair(const float4 p, float px, float py, 
         const float t = __builtin_fmaf(q, y2, -3.0f);
         const float u = y * t;
         mr = p.w * u;  // p.w = -m/2
-        const float u2 = u * u;
-        mr3 = mr * u2;
+        if (RCP) {
+            mr3 = mr * rcp_of<GUARD>(q);  // m rho / q
+        } else {
+            const float u2 = u * u;
+            mr3 = mr * u2;  // 4 m rho^3
+        }
     } else {
         mr = p.w * y;
-        const float y2 = y * y;
-        mr3 = mr * y2;
+        if (RCP) {
+            mr3 = mr * rcp_of<GUARD>(q);
+        } else {
+            const float y2 = y * y;
+            mr3 = mr * y2;
+        }
     }
     if (PHI) sp -= mr;
     sx = __builtin_fmaf(mr3, dx, sx);
@@ -100,7 +165,7 @@ __device__ __forceinline__ void newton_pair(const float4 p, float px, float py, 
     sz = __builtin_fmaf(mr3, dz, sz);
 }
 
-template <int KI, int JT, int U, bool REFINE, bool GUARD, bool PHI>
+template <int KI, int JT, int U, bool RCP, bool REFINE, bool GUARD, bool PHI>
 __global__ void __launch_bounds__(256) k_newton_allpairs(NewtonArgs a)
 {
     static_assert(JT % 256 == 0, "tile must be a multiple of the workgroup");
@@ -124,7 +189,10 @@ __global__ void __launch_bounds__(256) k_newton_allpairs(NewtonArgs a)
         tx[k] = ty[k] = tz[k] = tp[k] = 0.f;
     }
 
-    const int nj = a.nj;
+    // this workgroup's share of the j-particles (blockIdx.y splits them)
+    const int jbase = blockIdx.y * a.jchunk;
+    const int nj = max(0, min(a.jchunk, a.nj - jbase));
+    const float4 *__restrict__ jm = a.jmem + jbase;
     const int ntiles = (nj + JT - 1) / JT;
     float4 pre[PER];
 
@@ -133,7 +201,7 @@ __global__ void __launch_bounds__(256) k_newton_allpairs(NewtonArgs a)
         for (int r = 0; r < PER; ++r) {
             const int j = t * JT + r * 256 + tid;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (j < nj) v = a.jmem[j];
+            if (j < nj) v = jm[j];
             pre[r] = v;  // not touched until stored, so the load stays in flight
         }
     };
@@ -170,7 +238,7 @@ __global__ void __launch_bounds__(256) k_newton_allpairs(NewtonArgs a)
                 const float4 p = tile[cur][jj];
 #pragma unroll
                 for (int k = 0; k < KI; ++k)
-                    newton_pair<REFINE, GUARD, PHI>(p, px[k], py[k], pz[k], pe[k], sx[k], sy[k],
+                    newton_pair<REFINE, GUARD, PHI, RCP>(p, px[k], py[k], pz[k], pe[k], sx[k], sy[k],
                                                     sz[k], sp[k]);
             }
         } else {
@@ -179,7 +247,7 @@ __global__ void __launch_bounds__(256) k_newton_allpairs(NewtonArgs a)
                 const float4 p = tile[cur][jj];
 #pragma unroll
                 for (int k = 0; k < KI; ++k)
-                    newton_pair<REFINE, GUARD, PHI>(p, px[k], py[k], pz[k], pe[k], sx[k], sy[k],
+                    newton_pair<REFINE, GUARD, PHI, RCP>(p, px[k], py[k], pz[k], pe[k], sx[k], sy[k],
                                                     sz[k], sp[k]);
             }
         }
@@ -194,50 +262,61 @@ __global__ void __launch_bounds__(256) k_newton_allpairs(NewtonArgs a)
         __syncthreads();
     }
 
-    const float ascale = REFINE ? 0.25f : 1.0f;
+    const float ascale = (REFINE && !RCP) ? 0.25f : 1.0f;
+    // one j-share: write the outputs; several: partial sums for k_combine_split
+    float *ox = a.ax, *oy = a.ay, *oz = a.az, *op = a.phi;
+    if (gridDim.y > 1) {
+        ox = a.part + (size_t)blockIdx.y * 4 * a.ni;
+        oy = ox + a.ni;
+        oz = oy + a.ni;
+        op = oz + a.ni;
+    }
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
         const int i = ibase + k * 256;
         if (i < a.ni) {
-            a.ax[i] = tx[k] * ascale;
-            a.ay[i] = ty[k] * ascale;
-            a.az[i] = tz[k] * ascale;
-            if (PHI) a.phi[i] = tp[k];
+            ox[i] = tx[k] * ascale;
+            oy[i] = ty[k] * ascale;
+            oz[i] = tz[k] * ascale;
+            if (PHI) op[i] = tp[k];
         }
     }
 }
 
 using NewtonKernel = void (*)(NewtonArgs);
 
-template <int KI, int JT, int U>
+template <int KI, int JT, int U, bool RCP>
 struct NewtonSet {
     static NewtonKernel get(bool refine, bool guard, bool phi)
     {
         const int sel = (refine ? 4 : 0) | (guard ? 2 : 0) | (phi ? 1 : 0);
         switch (sel) {
-            case 0: return k_newton_allpairs<KI, JT, U, false, false, false>;
-            case 1: return k_newton_allpairs<KI, JT, U, false, false, true>;
-            case 2: return k_newton_allpairs<KI, JT, U, false, true, false>;
-            case 3: return k_newton_allpairs<KI, JT, U, false, true, true>;
-            case 4: return k_newton_allpairs<KI, JT, U, true, false, false>;
-            case 5: return k_newton_allpairs<KI, JT, U, true, false, true>;
-            case 6: return k_newton_allpairs<KI, JT, U, true, true, false>;
-            default: return k_newton_allpairs<KI, JT, U, true, true, true>;
+            case 0: return k_newton_allpairs<KI, JT, U, RCP, false, false, false>;
+            case 1: return k_newton_allpairs<KI, JT, U, RCP, false, false, true>;
+            case 2: return k_newton_allpairs<KI, JT, U, RCP, false, true, false>;
+            case 3: return k_newton_allpairs<KI, JT, U, RCP, false, true, true>;
+            case 4: return k_newton_allpairs<KI, JT, U, RCP, true, false, false>;
+            case 5: return k_newton_allpairs<KI, JT, U, RCP, true, false, true>;
+            case 6: return k_newton_allpairs<KI, JT, U, RCP, true, true, false>;
+            default: return k_newton_allpairs<KI, JT, U, RCP, true, true, true>;
         }
     }
 };
 
 struct NewtonVariant {
     const char *name;
-    int ki;
+    int ki, jt;
     NewtonKernel (*get)(bool, bool, bool);
 };
 
 const NewtonVariant kNewtonVariants[] = {
-    {"ki=1 jt=256 u=8", 1, &NewtonSet<1, 256, 8>::get},
-    {"ki=2 jt=256 u=4", 2, &NewtonSet<2, 256, 4>::get},
-    {"ki=4 jt=256 u=2", 4, &NewtonSet<4, 256, 2>::get},
-    {"ki=2 jt=512 u=8", 2, &NewtonSet<2, 512, 8>::get},
+    {"ki=1 jt=256 u=8", 1, 256, &NewtonSet<1, 256, 8, false>::get},
+    {"ki=2 jt=256 u=4", 2, 256, &NewtonSet<2, 256, 4, false>::get},
+    {"ki=4 jt=256 u=2", 4, 256, &NewtonSet<4, 256, 2, false>::get},
+    {"ki=2 jt=512 u=8", 2, 512, &NewtonSet<2, 512, 8, false>::get},
+    {"ki=1 jt=256 u=8 rcp", 1, 256, &NewtonSet<1, 256, 8, true>::get},
+    {"ki=2 jt=256 u=4 rcp", 2, 256, &NewtonSet<2, 256, 4, true>::get},
+    {"ki=4 jt=256 u=2 rcp", 4, 256, &NewtonSet<4, 256, 2, true>::get},
 };
 constexpr int kNumNewtonVariants = sizeof(kNewtonVariants) / sizeof(kNewtonVariants[0]);
 
@@ -258,15 +337,27 @@ int newton_allpairs_default(int ni, int nj, int num_cu)
     return waves_ki2 >= 4L * num_cu ? 1 : 0;
 }
 
-hipError_t launch_newton_allpairs(const NewtonArgs &a, int variant, bool refine, bool guard,
-                                  hipStream_t s)
+int newton_allpairs_split(int ni, int nj, int variant, size_t part_cap)
 {
-    if (a.ni <= 0) return hipSuccess;
     const NewtonVariant &v = kNewtonVariants[variant];
+    return split_count(ni, nj, v.ki, v.jt, kSplitTargetWaves, part_cap);
+}
+
+hipError_t launch_newton_allpairs(const NewtonArgs &a0, int variant, bool refine, bool guard,
+                                  int S, hipStream_t s)
+{
+    if (a0.ni <= 0) return hipSuccess;
+    const NewtonVariant &v = kNewtonVariants[variant];
+    NewtonArgs a = a0;
+    S = std::max(1, S);
+    a.jchunk = (int)(((long)a.nj + (long)S * v.jt - 1) / ((long)S * v.jt) * v.jt);
+    S = std::max(1, (a.nj + a.jchunk - 1) / a.jchunk);
     const int per_block = 256 * v.ki;
-    const dim3 grid((a.ni + per_block - 1) / per_block);
+    const dim3 grid((a.ni + per_block - 1) / per_block, S);
     hipLaunchKernelGGL(v.get(refine, guard, a.phi != nullptr), grid, dim3(256), 0, s, a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || S == 1) return e;
+    return launch_combine_split(a.ni, S, a.part, a0.ax, a0.ay, a0.az, a0.phi, s);
 }
 
 }  // namespace pgh

@@ -44,6 +44,9 @@ struct pgh_ctx {
     float tab_rcut = 0.f;
     float2 *tab = nullptr;  // device, 2^kMaxTableBits entries
     int variant[4] = {-1, -1, -1, -1};
+    // partial sums of j-split all-pairs launches (grown on demand)
+    float *part = nullptr;
+    size_t part_cap = 0;
     // scratch records of the adjoints (grown on demand)
     float4 *scr_a = nullptr, *scr_b = nullptr;
     size_t scr_a_cap = 0, scr_b_cap = 0;
@@ -127,6 +130,24 @@ int ensure_scratch(pgh_ctx *c, float4 **buf, size_t *cap, size_t n)
     return PGH_OK;
 }
 
+// Upper bound of the partial-sum buffer of j-split launches (floats).
+constexpr size_t kMaxSplitFloats = (size_t)64 << 20;
+
+int ensure_part(pgh_ctx *c, size_t n)
+{
+    if (n <= c->part_cap) return PGH_OK;
+    float *nb = nullptr;
+    if (hipMalloc((void **)&nb, n * sizeof(float)) != hipSuccess)
+        return fail(c, PGH_ENOMEM, "hipMalloc(partial sums) failed");
+    if (c->part) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->part);
+    }
+    c->part = nb;
+    c->part_cap = n;
+    return PGH_OK;
+}
+
 int zero_outputs(pgh_ctx *c, int n, float *a, float *b, float *d, float *e)
 {
     PGH_HIP(c, launch_fill_zero(n, a, b, d, e, c->stream));
@@ -194,6 +215,7 @@ int pgh_close(pgh_ctx *c)
     }
     (void)hipFree(c->scr_a);
     (void)hipFree(c->scr_b);
+    (void)hipFree(c->part);
     (void)hipFree(c->jmem);
     (void)hipFree(c->tab);
     delete c;
@@ -269,11 +291,17 @@ int pgh_calc_newton(pgh_ctx *c, int ni, const float *xi, const float *yi, const 
         return fail(c, PGH_EINVAL, "NULL i-particle or output array");
     DeviceGuard g(c->device);
     if (c->nj == 0) return zero_outputs(c, ni, ax, ay, az, phi);
-    NewtonArgs a{ni, xi, yi, zi, eps2_i, c->eps2_all, c->nj, c->jmem, ax, ay, az, phi};
+    NewtonArgs a{ni, xi, yi, zi, eps2_i, c->eps2_all, c->nj, c->jmem, ax, ay, az, phi, 0, nullptr};
     const bool guard = (eps2_i == nullptr) && !(c->eps2_all > 0.f);
     int v = c->variant[PGH_FAMILY_NEWTON_ALLPAIRS];
     if (v < 0) v = newton_allpairs_default(ni, c->nj, c->num_cu);
-    PGH_HIP(c, launch_newton_allpairs(a, v, c->refine != 0, guard, c->stream));
+    const int S = newton_allpairs_split(ni, c->nj, v, kMaxSplitFloats);
+    if (S > 1) {
+        int st = ensure_part(c, (size_t)S * 4 * ni);
+        if (st) return st;
+        a.part = c->part;
+    }
+    PGH_HIP(c, launch_newton_allpairs(a, v, c->refine != 0, guard, S, c->stream));
     return PGH_OK;
 }
 
@@ -389,10 +417,16 @@ int pgh_calc_table(pgh_ctx *c, int ni, const float *xi, const float *yi, const f
     const double smax = smax_of(c->tab_E, c->tab_F);
     const double rc = c->tab_rcut;
     TableArgs a{ni, xi, yi, zi, c->nj, c->jmem, c->tab, c->tab_E, c->tab_F,
-                (float)((smax - 2.0) / (rc * rc)), (float)smax, ax, ay, az};
+                (float)((smax - 2.0) / (rc * rc)), (float)smax, ax, ay, az, 0, nullptr};
     int v = c->variant[PGH_FAMILY_TABLE_ALLPAIRS];
     if (v < 0) v = table_allpairs_default(ni, c->nj, c->num_cu);
-    PGH_HIP(c, launch_table_allpairs(a, v, c->stream));
+    const int S = table_allpairs_split(ni, c->nj, v, kMaxSplitFloats);
+    if (S > 1) {
+        int st = ensure_part(c, (size_t)S * 4 * ni);
+        if (st) return st;
+        a.part = c->part;
+    }
+    PGH_HIP(c, launch_table_allpairs(a, v, S, c->stream));
     return PGH_OK;
 }
 
@@ -654,8 +688,10 @@ int pgh_newton_allpairs_bwd(pgh_ctx *c, int n, const float *x, const float *y, c
     int st = ensure_scratch(c, &c->scr_a, &c->scr_a_cap, 2 * (size_t)n);
     if (st) return st;
     PGH_HIP(c, launch_pack_xw(n, x, y, z, m, 0.f, wx, wy, wz, c->scr_a, c->stream));
-    PGH_HIP(c, launch_newton_allpairs_bwd(n, c->scr_a, eps2, c->refine != 0, gx, gy, gz, gm,
-                                          c->stream));
+    const int S = adjoint_split(n, n, kMaxSplitFloats);
+    if (S > 1 && (st = ensure_part(c, (size_t)S * 4 * n))) return st;
+    PGH_HIP(c, launch_newton_allpairs_bwd(n, c->scr_a, eps2, c->refine != 0, gx, gy, gz, gm, S,
+                                          c->part, c->stream));
     return PGH_OK;
 }
 
@@ -691,10 +727,18 @@ int pgh_newton_ij_bwd(pgh_ctx *c, int ni, const float *xi, const float *yi, cons
     PGH_HIP(c, launch_pack_xw(ni, xi, yi, zi, eps2_i, c->eps2_all, wx, wy, wz, c->scr_a, c->stream));
     PGH_HIP(c, launch_pack_j(nj, xj, yj, zj, mj, c->scr_b, c->stream));
     const bool rf = c->refine != 0;
-    if (want_i) PGH_HIP(c, launch_newton_bwd_i(ni, c->scr_a, nj, c->scr_b, rf, gxi, gyi, gzi, c->stream));
-    if (want_j || gmj)
-        PGH_HIP(c, launch_newton_bwd_j(nj, c->scr_b, ni, c->scr_a, rf, gxj, gyj, gzj, gmj,
+    // the two passes run one after the other on the stream and share the
+    // partial-sum buffer
+    const int Si = adjoint_split(ni, nj, kMaxSplitFloats);
+    const int Sj = adjoint_split(nj, ni, kMaxSplitFloats);
+    const size_t need = std::max(Si > 1 ? (size_t)Si * 4 * ni : 0, Sj > 1 ? (size_t)Sj * 4 * nj : 0);
+    if (need && (st = ensure_part(c, need))) return st;
+    if (want_i)
+        PGH_HIP(c, launch_newton_bwd_i(ni, c->scr_a, nj, c->scr_b, rf, gxi, gyi, gzi, Si, c->part,
                                        c->stream));
+    if (want_j || gmj)
+        PGH_HIP(c, launch_newton_bwd_j(nj, c->scr_b, ni, c->scr_a, rf, gxj, gyj, gzj, gmj, Sj,
+                                       c->part, c->stream));
     return PGH_OK;
 }
 
@@ -769,6 +813,67 @@ int pgh_get_variant(const pgh_ctx *c, int family)
 {
     if (!c || family < 0 || family > 3) return -1;
     return c->variant[family];
+}
+
+int pgh_autotune(pgh_ctx *c, int family, int ni, const float *xi, const float *yi,
+                 const float *zi, int reps, float *best_ms)
+{
+    if (!c) return PGH_EINVAL;
+    if (family != PGH_FAMILY_NEWTON_ALLPAIRS && family != PGH_FAMILY_TABLE_ALLPAIRS)
+        return fail(c, PGH_ERANGE, "only the all-pairs families are tuned by pgh_autotune");
+    if (ni <= 0 || !xi || !yi || !zi) return fail(c, PGH_EINVAL, "need ni > 0 i-particles");
+    if (c->nj <= 0) return fail(c, PGH_ESTATE, "set j-particles (pgh_set_xmj, pgh_set_n) first");
+    if (family == PGH_FAMILY_TABLE_ALLPAIRS && !c->tab_set)
+        return fail(c, PGH_ESTATE, "no force table set");
+    reps = std::max(1, reps);
+    DeviceGuard g(c->device);
+    float *out = nullptr;
+    if (hipMalloc((void **)&out, 4 * sizeof(float) * (size_t)ni) != hipSuccess)
+        return fail(c, PGH_ENOMEM, "hipMalloc(tuning outputs) failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = -1;
+    float best_t = 0.f;
+    const int saved = c->variant[family];
+    int status = PGH_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        status = fail(c, PGH_EHIP, "hipEventCreate failed");
+    } else {
+        const int nv = pgh_variant_count(family);
+        for (int v = 0; v < nv && status == PGH_OK; ++v) {
+            c->variant[family] = v;
+            auto call = [&]() {
+                if (family == PGH_FAMILY_NEWTON_ALLPAIRS)
+                    return pgh_calc_newton(c, ni, xi, yi, zi, nullptr, out, out + ni, out + 2 * ni,
+                                           out + 3 * (size_t)ni);
+                return pgh_calc_table(c, ni, xi, yi, zi, out, out + ni, out + 2 * ni);
+            };
+            if ((status = call()) != PGH_OK) break;  // warm-up
+            if (hipEventRecord(e0, c->stream) != hipSuccess) status = PGH_EHIP;
+            for (int r = 0; r < reps && status == PGH_OK; ++r) status = call();
+            if (status == PGH_OK && (hipEventRecord(e1, c->stream) != hipSuccess ||
+                                     hipEventSynchronize(e1) != hipSuccess))
+                status = fail(c, PGH_EHIP, "timing the variants failed");
+            float ms = 0.f;
+            if (status == PGH_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+                ms /= reps;
+                if (best < 0 || ms < best_t) {
+                    best = v;
+                    best_t = ms;
+                }
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(out);
+    if (status != PGH_OK || best < 0) {
+        c->variant[family] = saved;
+        return status != PGH_OK ? status : fail(c, PGH_EHIP, "no variant could be timed");
+    }
+    c->variant[family] = best;
+    if (best_ms) *best_ms = best_t;
+    return best;
 }
 
 }  // extern "C"

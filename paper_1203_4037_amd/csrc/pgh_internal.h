@@ -23,6 +23,8 @@ struct NewtonArgs {
     int nj;
     const float4 *jmem;
     float *ax, *ay, *az, *phi;
+    int jchunk;   // j-particles per workgroup share (set by the launcher)
+    float *part;  // partial sums [S][4][ni] when the j-range is split
 };
 
 // Arguments of the all-pairs table-force kernels.
@@ -36,6 +38,8 @@ struct TableArgs {
     float c;     // (s_max - 2) / rcut^2
     float smax;  // 2^{2^E} (2 - 2^-F)
     float *ax, *ay, *az;
+    int jchunk;
+    float *part;
 };
 
 // One wavefront task of a batch plan: up to 64 i-particles against one part
@@ -95,16 +99,29 @@ hipError_t launch_pack_j(int n, const float *x, const float *y, const float *z, 
                          float4 *dst, hipStream_t s);
 hipError_t launch_fill_zero(int n, float *a, float *b, float *c, float *d, hipStream_t s);
 
+// All-pairs launches split the j-range over S workgroup rows when the i-range
+// alone gives too few waves; the shares write partial sums [S][4][ni] that
+// k_combine_split adds in order.  Waves the split aims for: 2 per SIMD for the
+// Newton kernels (their j-tile reads are issued ahead of use, so two waves
+// keep a SIMD busy), 8 per SIMD for the table kernels, whose table gather
+// sits inside each pair's dependency chain.
+constexpr int kSplitTargetWaves = 2048;
+int split_count(int ni, int nj, int ki, int jt, int target_waves, size_t part_cap);
+hipError_t launch_combine_split(int n, int S, const float *part, float *ax, float *ay, float *az,
+                                float *phi, hipStream_t s);
+
 int newton_allpairs_variants();
 const char *newton_allpairs_variant_name(int v);
 int newton_allpairs_default(int ni, int nj, int num_cu);
+int newton_allpairs_split(int ni, int nj, int variant, size_t part_cap);
 hipError_t launch_newton_allpairs(const NewtonArgs &a, int variant, bool refine, bool guard,
-                                  hipStream_t s);
+                                  int S, hipStream_t s);
 
 int table_allpairs_variants();
 const char *table_allpairs_variant_name(int v);
 int table_allpairs_default(int ni, int nj, int num_cu);
-hipError_t launch_table_allpairs(const TableArgs &a, int variant, hipStream_t s);
+int table_allpairs_split(int ni, int nj, int variant, size_t part_cap);
+hipError_t launch_table_allpairs(const TableArgs &a, int variant, int S, hipStream_t s);
 
 int batch_resident_waves(int num_cu);  // waves of the persistent grid
 hipError_t launch_newton_batch(const BatchArgs &a, bool refine, bool guard, int num_cu,
@@ -115,13 +132,17 @@ hipError_t launch_table_batch(const BatchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_pack_xw(int n, const float *x, const float *y, const float *z, const float *s,
                           float s_all, const float *wx, const float *wy, const float *wz,
                           float4 *dst, hipStream_t st);
+// Adjoint launches: S shares of the summed-over index (see split_count).
+int adjoint_split(int n, int m, size_t part_cap);
 hipError_t launch_newton_allpairs_bwd(int n, const float4 *rec, float eps2, bool refine, float *gx,
-                                      float *gy, float *gz, float *gm, hipStream_t s);
+                                      float *gy, float *gz, float *gm, int S, float *part,
+                                      hipStream_t s);
 hipError_t launch_newton_bwd_i(int ni, const float4 *irec, int nj, const float4 *jmem,
-                               bool refine, float *gx, float *gy, float *gz, hipStream_t s);
-hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 *irec,
-                               bool refine, float *gx, float *gy, float *gz, float *gm,
+                               bool refine, float *gx, float *gy, float *gz, int S, float *part,
                                hipStream_t s);
+hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 *irec,
+                               bool refine, float *gx, float *gy, float *gz, float *gm, int S,
+                               float *part, hipStream_t s);
 hipError_t launch_table_batch_bwd(const TableBwdArgs &a, const Task *jtasks, int n_jtasks,
                                   unsigned *jqueue, int num_cu, hipStream_t s);
 

@@ -161,3 +161,26 @@ def test_error_distribution_like_paper(pgh, ctx):
         # the paper reports most errors below 1e-4 with a 12-bit rsqrt
         assert np.quantile(ea, 0.99) < 1e-4
         assert np.median(ep) < 1e-4
+
+
+def test_autotuner_choice_and_cache(pgh, ctx, tmp_path):
+    """pgh_autotune times every variant on the caller's workload, keeps the
+    fastest, and the binding's JSON cache reuses the choice."""
+    n = 32768
+    x, y, z = synth.plummer(n, 17)
+    m = synth.equal_masses(n)
+    d = to_dev(x, y, z, m)
+    ctx.set_eps_to_all(0.01)
+    ctx.set_j(*d)
+    cache = str(tmp_path / "tune.json")
+    v = ctx.autotune(pgh.PGH_FAMILY_NEWTON_ALLPAIRS, d[0], d[1], d[2], reps=2, cache=cache)
+    assert 0 <= v < pgh.pgh_variant_count(pgh.PGH_FAMILY_NEWTON_ALLPAIRS)
+    assert pgh.pgh_get_variant(ctx.h, pgh.PGH_FAMILY_NEWTON_ALLPAIRS) == v
+    pgh.pgh_set_variant(ctx.h, pgh.PGH_FAMILY_NEWTON_ALLPAIRS, -1)
+    assert ctx.autotune(pgh.PGH_FAMILY_NEWTON_ALLPAIRS, d[0], d[1], d[2], cache=cache) == v
+    ax, ay, az, phi = ctx.newton(d[0], d[1], d[2])
+    idx = np.arange(0, n, 97)
+    ref = oracle.newton(x[idx], y[idx], z[idx], np.full(idx.size, np.float32(0.01) ** 2, np.float32),
+                        x, y, z, m)
+    a = np.stack(to_host(ax, ay, az))[:, idx]
+    _check(a, to_host(phi)[0][idx], ref, f"tuned variant {v}")

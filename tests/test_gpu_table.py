@@ -145,3 +145,16 @@ def test_set_table_from_device_and_state_errors(pgh, ctx):
     assert pgh.lib.pgh_set_table(ctx.h, 7, 6, rcut, dt.data_ptr()) == pgh.PGH_ERANGE
     assert pgh.lib.pgh_set_table(ctx.h, 4, 6, -1.0, dt.data_ptr()) == pgh.PGH_ERANGE
     assert pgh.lib.pgh_set_table(ctx.h, 4, 6, rcut, None) == pgh.PGH_EINVAL
+
+
+def test_table_autotuner(pgh, ctx):
+    n = 16384
+    x, y, z = synth.uniform_box(n, 5, box=0.2)
+    m = synth.equal_masses(n)
+    d = to_dev(x, y, z, m)
+    ctx.build_table(4, 6, 3.0 / 256, eps=1.0 / 1280)
+    ctx.set_j(*d)
+    v, ms = pgh.pgh_autotune(ctx.h, pgh.PGH_FAMILY_TABLE_ALLPAIRS, n, d[0], d[1], d[2], 2)
+    assert 0 <= v < pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_ALLPAIRS) and ms > 0
+    with pytest.raises(pgh.PGHError):
+        pgh.pgh_autotune(ctx.h, pgh.PGH_FAMILY_NEWTON_BATCH, n, d[0], d[1], d[2], 1)
