@@ -41,8 +41,16 @@ def parse():
     ap.add_argument("--n", type=int, default=262144)
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the built-in default variant instead of the autotuned one")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target wall time of the CPU baseline sample")
+    ap.add_argument("--replays", type=int, default=0,
+                    help="graph replays per secondary measurement (0: the built-in counts; "
+                         "profiler runs use a few)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of MIB MiB (a known-size "
+                         "reference for the HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
@@ -110,6 +118,11 @@ def newton_allpairs(torch, pgh, synth, args):
     ctx = pgh.Context(0)
     ctx.set_eps_to_all(0.01)
     pgh.pgh_set_stream(ctx.h, torch.cuda.current_stream().cuda_stream)
+    tuned = None
+    if not args.no_tune:
+        # the library's autotuner picks the tile shape on this very workload
+        ctx.set_j(*dev)
+        tuned = ctx.autotune(pgh.PGH_FAMILY_NEWTON_ALLPAIRS, dev[0], dev[1], dev[2], reps=2)
     timer = KernelTimer(torch)
     timing = {"on": False}
 
@@ -129,13 +142,19 @@ def newton_allpairs(torch, pgh, synth, args):
     sec = time_steps(torch, step, args.steps, 0)
     kern_ms = timer.mean_ms()
     variant = pgh.pgh_get_variant(ctx.h, pgh.PGH_FAMILY_NEWTON_ALLPAIRS)
+    name = pgh.pgh_variant_name(pgh.PGH_FAMILY_NEWTON_ALLPAIRS, variant) if variant >= 0 else "default"
     ctx.close()
-    return {"n": n, "x": (x, y, z, m), "sec": sec, "kern_ms": kern_ms, "variant": variant}
+    return {"n": n, "x": (x, y, z, m), "sec": sec, "kern_ms": kern_ms, "variant": variant,
+            "variant_name": name, "autotuned": tuned is not None}
+
+
+REPLAYS = {"override": 0}
 
 
 def graph_ms(torch, fn, reps):
     """Captures fn() in a graph (a hipGraph under ROCm) and returns the mean
     replay time in ms, from events on the replay stream."""
+    reps = REPLAYS["override"] or reps
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -169,6 +188,12 @@ def batched_newton(torch, pgh, synth):
     ctx.set_eps_to_all(1e-3)
     plan = ctx.plan(s.items, s.xi.size, s.xj.size)
     out = [torch.empty(s.xi.size, device="cuda") for _ in range(4)]
+    fam = pgh.PGH_FAMILY_NEWTON_BATCH
+    per = {}
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        per[pgh.pgh_variant_name(fam, v)] = graph_ms(torch, lambda: plan.newton(*di, *dj, out=out), 10)
+    tuned = plan.autotune(fam, *di, *dj, reps=3)
     ms = graph_ms(torch, lambda: plan.newton(*di, *dj, out=out), 10)
     inter = float(plan.interactions)
     plan.free()
@@ -176,7 +201,8 @@ def batched_newton(torch, pgh, synth):
     rate = inter / (ms / 1e3)
     return {"workload": "newton_batched_tree_style_16384_lists_N4194304", "interactions": inter,
             "ms_per_launch": ms, "interactions_per_s": rate,
-            "frac_of_peak_38flop": NEWTON_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12)}
+            "frac_of_peak_38flop": NEWTON_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12),
+            "autotuned_variant": pgh.pgh_variant_name(fam, tuned), "ms_per_variant": per}
 
 
 def batched_table(torch, pgh, synth):
@@ -194,6 +220,13 @@ def batched_table(torch, pgh, synth):
     ctx.build_table(4, 6, 3.0 / 256, eps=1.0 / 1280)
     plan = ctx.plan(s.items, n, s.xj.size)
     out = [torch.empty(n, device="cuda") for _ in range(3)]
+    fam = pgh.PGH_FAMILY_TABLE_BATCH
+    per = {}
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        per[pgh.pgh_variant_name(fam, v)] = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 200)
+    # the paper's (G0, G1) form is the default; the timings of both are above
+    ctx.set_variant(fam, 0)
     ms = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 200)
     inter = float(plan.interactions)
     plan.free()
@@ -201,7 +234,8 @@ def batched_table(torch, pgh, synth):
     rate = inter / (ms / 1e3)
     return {"workload": "table_batched_cell_lists_N262144_E4F6", "interactions": inter,
             "ms_per_launch": ms, "interactions_per_s": rate,
-            "frac_of_peak_20flop": TABLE_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12)}
+            "frac_of_peak_20flop": TABLE_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12),
+            "variant": pgh.pgh_variant_name(fam, 0), "ms_per_variant": per}
 
 
 def adjoint_newton(torch, pgh, synth):
@@ -288,6 +322,16 @@ def table_allpairs(torch, pgh, synth):
     ctx.build_table(4, 6, 3.0 / 256, eps=1.0 / 1280)
     ctx.set_j(*dev)
     out = [torch.empty(n, device="cuda") for _ in range(3)]
+    fam = pgh.PGH_FAMILY_TABLE_ALLPAIRS
+    per = {}
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        t = KernelTimer(torch)
+        for _ in range(4):
+            with t:
+                pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out)
+        per[pgh.pgh_variant_name(fam, v)] = t.mean_ms()
+    ctx.set_variant(fam, -1)  # the built-in default (the paper's table form)
     timer = KernelTimer(torch)
 
     def step():
@@ -300,7 +344,8 @@ def table_allpairs(torch, pgh, synth):
     inter = float(n) * n
     return {"workload": "table_allpairs_uniform_N65536_E4F6", "interactions_per_s": inter / (ms / 1e3),
             "kernel_ms": ms, "step_ms": sec * 1e3,
-            "frac_of_peak_20flop": TABLE_FLOPS * inter / (ms / 1e3) / (PEAK_FP32_TFLOPS * 1e12)}
+            "frac_of_peak_20flop": TABLE_FLOPS * inter / (ms / 1e3) / (PEAK_FP32_TFLOPS * 1e12),
+            "ms_per_variant": per}
 
 
 def main():
@@ -316,7 +361,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    REPLAYS["override"] = args.replays
     r = newton_allpairs(torch, pgh, synth, args)
+    if args.copy_calibration > 0:
+        src = torch.empty(args.copy_calibration << 18, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n = r["n"]
     inter = float(n) * n
     value = inter / r["sec"]
@@ -336,7 +389,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"newton_allpairs_plummer_N{n}_eps0.01", "n_i": n, "n_j": n,
                    "eps": 0.01, "seed": 102, "interactions_per_step": inter,
-                   "parallelism": "single_gpu", "kernel_variant": r["variant"]},
+                   "parallelism": "single_gpu", "kernel_variant": r["variant_name"],
+                   "autotuned": r["autotuned"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "k_newton_allpairs", "kernel_ms": r["kern_ms"],

@@ -296,6 +296,18 @@ PGH_API int pgh_get_variant(const pgh_ctx *c, int family);
 PGH_API int pgh_autotune(pgh_ctx *c, int family, int ni, const float *xi, const float *yi,
                          const float *zi, int reps, float *best_ms);
 
+/* Tunes a batched family (PGH_FAMILY_NEWTON_BATCH or PGH_FAMILY_TABLE_BATCH)
+ * on plan p of c with the caller's particle arrays (device, as for
+ * pgh_batch_newton / pgh_batch_table; the Newton family runs with the
+ * context's eps_to_all), the same way as pgh_autotune: returns the fastest
+ * variant's index (>= 0) and selects it, or a negative status (PGH_EINVAL
+ * for a plan of another context or with no work, PGH_ESTATE without a table
+ * for the table family).  Synchronous; allocates temporary outputs. */
+PGH_API int pgh_autotune_plan(pgh_ctx *c, int family, const pgh_plan *p, const float *xi,
+                              const float *yi, const float *zi, const float *xj,
+                              const float *yj, const float *zj, const float *mj, int reps,
+                              float *best_ms);
+
 #ifdef __cplusplus
 }
 #endif

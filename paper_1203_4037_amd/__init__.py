@@ -76,6 +76,7 @@ SIGNATURES = {
     "pgh_set_variant": (_I, [_P, _I, _I]),
     "pgh_get_variant": (_I, [_P, _I]),
     "pgh_autotune": (_I, [_P, _I, _I, _P, _P, _P, _I, ctypes.POINTER(_F)]),
+    "pgh_autotune_plan": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _I, ctypes.POINTER(_F)]),
 }
 
 
@@ -306,6 +307,18 @@ def pgh_autotune(ctx, family, ni, xi, yi, zi, reps=3):
     return v, ms.value
 
 
+def pgh_autotune_plan(ctx, family, plan, xi, yi, zi, xj, yj, zj, mj, reps=3):
+    """Returns (best variant, ms per call) of a batched family on a plan."""
+    ms = ctypes.c_float()
+    v = lib.pgh_autotune_plan(ctx, family, plan, _ptr(xi, None, "xi"), _ptr(yi, None, "yi"),
+                              _ptr(zi, None, "zi"), _ptr(xj, None, "xj"), _ptr(yj, None, "yj"),
+                              _ptr(zj, None, "zj"), _ptr(mj, None, "mj"), int(reps),
+                              ctypes.byref(ms))
+    if v < 0:
+        _check(ctx, v)
+    return v, ms.value
+
+
 def s2pp_callback():
     """The library's built-in h(r) of the S2 particle-particle force shape
     (Eqs. s2pp and s2); pass user = ctypes pointer to double[2] {eps, rcut}."""
@@ -476,6 +489,15 @@ class Plan:
             out = [c._empty(self.ni_total) for _ in range(3)]
         pgh_batch_table(c.h, self.h, xi, yi, zi, xj, yj, zj, mj, out[0], out[1], out[2])
         return out
+
+    def autotune(self, family, xi, yi, zi, xj, yj, zj, mj, reps=3):
+        """Selects the fastest variant of a batched family on this plan
+        (PGH_FAMILY_NEWTON_BATCH uses the context's eps_to_all) and returns
+        its index."""
+        self.ctx._sync_stream()
+        self._check_sizes((xi, yi, zi), (xj, yj, zj, mj))
+        v, _ = pgh_autotune_plan(self.ctx.h, family, self.h, xi, yi, zi, xj, yj, zj, mj, reps)
+        return v
 
 
 # --------------------------------------------------------------------------

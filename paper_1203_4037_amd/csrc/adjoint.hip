@@ -391,13 +391,14 @@ __global__ void __launch_bounds__(256) k_table_bwd_tab(TableBwdArgs A)
     const unsigned klast = (unsigned)K - 1u;
     float last0 = 0.f;  // clamped pairs: dL/dG0 of the last node
 
-    for (;;) {
-        unsigned t = 0;
-        if (lane == 0)
-            t = __hip_atomic_fetch_add(&a.queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= (unsigned)a.n_tasks) break;
+    // static first round, then one atomic per task (as in the forward kernel)
+    const unsigned n_waves = gridDim.x * 4;
+    for (unsigned t = blockIdx.x * 4 + wave; t < (unsigned)a.n_tasks;) {
         const Task tk = a.tasks[t];
+        unsigned tn = (unsigned)a.n_tasks;
+        if ((unsigned)a.n_tasks > n_waves && lane == 0)
+            tn = n_waves +
+                 __hip_atomic_fetch_add(&a.queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // one lane per i-particle here (lanes past n_i carry zero weight)
         const bool active = lane < tk.n_i;
         const int i = tk.i_off + (active ? lane : 0);
@@ -437,6 +438,7 @@ __global__ void __launch_bounds__(256) k_table_bwd_tab(TableBwdArgs A)
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        t = __builtin_amdgcn_readfirstlane(tn);
     }
     // wave sum of the clamped-bin register, then flush this workgroup's bins
     for (int off = 32; off > 0; off >>= 1) last0 += __shfl_xor(last0, off);
@@ -462,13 +464,13 @@ __global__ void __launch_bounds__(256) k_table_bwd_m(TableBwdArgs A, const Task 
     __syncthreads();
     const unsigned shift = 23u - (unsigned)a.F, nbits = (unsigned)(a.E + a.F);
     const unsigned hmask = ~((1u << shift) - 1u);
-    for (;;) {
-        unsigned t = 0;
-        if (lane == 0)
-            t = __hip_atomic_fetch_add(&jqueue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= (unsigned)n_jtasks) break;
+    const unsigned n_waves = gridDim.x * 4;
+    for (unsigned t = blockIdx.x * 4 + wave; t < (unsigned)n_jtasks;) {
         const Task tk = jtasks[t];  // i_off/n_i: the j-chunk, j_off/n_j: the i-range
+        unsigned tn = (unsigned)n_jtasks;
+        if ((unsigned)n_jtasks > n_waves && lane == 0)
+            tn = n_waves +
+                 __hip_atomic_fetch_add(&jqueue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const bool active = lane < tk.n_i;
         const int j = tk.i_off + (active ? lane : 0);
         const float qx = a.xj[j], qy = a.yj[j], qz = a.zj[j];
@@ -506,6 +508,7 @@ __global__ void __launch_bounds__(256) k_table_bwd_m(TableBwdArgs A, const Task 
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         if (active) atomicAdd(&A.gmj[j], G);
+        t = __builtin_amdgcn_readfirstlane(tn);
     }
 }
 

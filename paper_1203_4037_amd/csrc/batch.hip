@@ -12,9 +12,10 @@
 //     (deterministic) and writes the outputs;
 //   * tasks are sorted by decreasing length (longest-processing-time first).
 // Execution: a grid sized to fill every CU; each wave64 runs independently,
-// taking the next task index from a device counter with one atomic.  The
-// second kernel also resets the counter, so the next launch (or a replay of
-// a captured graph) starts from zero without a memset.
+// taking its first task by its index and later ones from a device counter
+// with one atomic each.  The second kernel also resets the counter, so the
+// next launch (or a replay of a captured graph) starts from zero without a
+// memset.
 //
 // Each wave stages its j-list through its own LDS slice, 64 records per
 // tile (one coalesced load per coordinate array), double-buffered in
@@ -24,6 +25,7 @@
 #include <mutex>
 #include <utility>
 
+#include "pairs.h"
 #include "pgh_internal.h"
 
 namespace pgh {
@@ -40,63 +42,9 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool REFINE, bool GUARD, bool PHI>
-__device__ __forceinline__ void newton_pair(const float4 p, float px, float py, float pz,
-                                            float pe, float &sx, float &sy, float &sz,
-                                            float &sp)
-{
-    const float dx = p.x - px;
-    const float dy = p.y - py;
-    const float dz = p.z - pz;
-    float q = __builtin_fmaf(dx, dx, pe);
-    q = __builtin_fmaf(dy, dy, q);
-    q = __builtin_fmaf(dz, dz, q);
-    float y = __builtin_amdgcn_rsqf(q);
-    if (GUARD) y = (q > 0.f) ? y : 0.f;
-    float mr, mr3;
-    if (REFINE) {
-        const float y2 = y * y;
-        const float t = __builtin_fmaf(q, y2, -3.0f);
-        const float u = y * t;
-        mr = p.w * u;  // p.w = -m/2
-        const float u2 = u * u;
-        mr3 = mr * u2;
-    } else {
-        mr = p.w * y;
-        const float y2 = y * y;
-        mr3 = mr * y2;
-    }
-    if (PHI) sp -= mr;
-    sx = __builtin_fmaf(mr3, dx, sx);
-    sy = __builtin_fmaf(mr3, dy, sy);
-    sz = __builtin_fmaf(mr3, dz, sz);
-}
-
-__device__ __forceinline__ void table_pair(const float4 p, float px, float py, float pz,
-                                           const float2 *__restrict__ stab, float c, float smax,
-                                           unsigned shift, unsigned nbits, unsigned hmask,
-                                           float &sx, float &sy, float &sz)
-{
-    const float dx = p.x - px;
-    const float dy = p.y - py;
-    const float dz = p.z - pz;
-    float r2 = dx * dx;
-    r2 = __builtin_fmaf(dy, dy, r2);
-    r2 = __builtin_fmaf(dz, dz, r2);
-    const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
-    const unsigned u = __float_as_uint(s);
-    const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
-    const float sk = __uint_as_float(u & hmask);
-    const float2 g01 = stab[k];
-    const float g = __builtin_fmaf(g01.y, s - sk, g01.x);
-    const float mg = p.w * g;
-    sx = __builtin_fmaf(mg, dx, sx);
-    sy = __builtin_fmaf(mg, dy, sy);
-    sz = __builtin_fmaf(mg, dz, sz);
-}
-
-// KIND 0: Newton (REFINE, GUARD, PHI apply); KIND 1: table force.
-template <int KIND, bool REFINE, bool GUARD, bool PHI>
+// KIND 0: Newton (REFINE, GUARD, PHI apply; ALT = the rcp form);
+// KIND 1: table force (ALT = the (H, G1) table form).
+template <int KIND, bool ALT, bool REFINE, bool GUARD, bool PHI>
 __global__ void __launch_bounds__(256) k_batch(BatchArgs a)
 {
     extern __shared__ float2 stab[];  // table force only: 2^(E+F) entries
@@ -109,20 +57,27 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a)
     unsigned shift = 0, nbits = 0, hmask = 0;
     if (KIND == 1) {
         const int K = 1 << (a.E + a.F);
-        for (int k = threadIdx.x; k < K; k += 256) stab[k] = a.table[k];
         shift = 23u - (unsigned)a.F;
+        table_to_lds<ALT>(stab, a.table, K, shift);
         nbits = (unsigned)(a.E + a.F);
         hmask = ~((1u << shift) - 1u);
         __syncthreads();  // the only workgroup barrier: waves are independent after it
     }
 
-    for (;;) {
-        unsigned t = 0;
-        if (lane == 0)
-            t = __hip_atomic_fetch_add(&a.queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= (unsigned)a.n_tasks) break;
+    // The first round of tasks is assigned statically (wave w takes task w),
+    // so a launch with no more tasks than waves issues no atomic at all; the
+    // later tasks come from the counter, one atomic per task, taken at the
+    // start of the previous task so its latency overlaps that task.  (All
+    // waves hitting one counter at once serialises at the memory side.)
+    const unsigned n_tasks = (unsigned)a.n_tasks;
+    const bool dynamic = n_tasks > (unsigned)a.n_waves;
+    unsigned t = blockIdx.x * kWaves + wave;
+    while (t < n_tasks) {
         const Task tk = a.tasks[t];
+        unsigned tn = n_tasks;
+        if (dynamic && lane == 0)
+            tn = (unsigned)a.n_waves +
+                 __hip_atomic_fetch_add(&a.queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         // lanes per i-particle (js) and the lane's i slot and j phase
         const int js = tk.n_i <= 16 ? 4 : (tk.n_i <= 32 ? 2 : 1);
@@ -167,9 +122,9 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a)
                 for (int it = 0; it < 64; ++it) {
                     const float4 p = jt[wave][cur][it];
                     if (KIND == 0)
-                        newton_pair<REFINE, GUARD, PHI>(p, px, py, pz, pe, sx, sy, sz, sp);
+                        newton_pair<REFINE, GUARD, PHI, ALT>(p, px, py, pz, pe, sx, sy, sz, sp);
                     else
-                        table_pair(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask, sx, sy,
+                        table_pair<ALT>(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask, sx, sy,
                                    sz);
                 }
             } else {
@@ -177,9 +132,9 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a)
                 for (int it = 0; it < trips; ++it) {
                     const float4 p = jt[wave][cur][it * js + ph];
                     if (KIND == 0)
-                        newton_pair<REFINE, GUARD, PHI>(p, px, py, pz, pe, sx, sy, sz, sp);
+                        newton_pair<REFINE, GUARD, PHI, ALT>(p, px, py, pz, pe, sx, sy, sz, sp);
                     else
-                        table_pair(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask, sx, sy,
+                        table_pair<ALT>(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask, sx, sy,
                                    sz);
                 }
             }
@@ -208,7 +163,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a)
             tz += __shfl_xor(tz, 32);
             tp += __shfl_xor(tp, 32);
         }
-        const float ascale = (KIND == 0 && REFINE) ? 0.25f : 1.0f;
+        const float ascale = (KIND == 0 && REFINE && !ALT) ? 0.25f : 1.0f;
         tx *= ascale;
         ty *= ascale;
         tz *= ascale;
@@ -225,6 +180,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a)
             // parts of the chunk in order after this launch
             a.partial[(size_t)(tk.slot + tk.part) * 64 + lane] = make_float4(tx, ty, tz, tp);
         }
+        t = __builtin_amdgcn_readfirstlane(tn);
     }
 }
 
@@ -256,19 +212,25 @@ __global__ void __launch_bounds__(64) k_combine(CombineArgs a)
 
 using BatchKernel = void (*)(BatchArgs);
 
-BatchKernel newton_kernel(bool refine, bool guard, bool phi)
+template <bool ALT>
+BatchKernel newton_kernel_t(bool refine, bool guard, bool phi)
 {
     const int sel = (refine ? 4 : 0) | (guard ? 2 : 0) | (phi ? 1 : 0);
     switch (sel) {
-        case 0: return k_batch<0, false, false, false>;
-        case 1: return k_batch<0, false, false, true>;
-        case 2: return k_batch<0, false, true, false>;
-        case 3: return k_batch<0, false, true, true>;
-        case 4: return k_batch<0, true, false, false>;
-        case 5: return k_batch<0, true, false, true>;
-        case 6: return k_batch<0, true, true, false>;
-        default: return k_batch<0, true, true, true>;
+        case 0: return k_batch<0, ALT, false, false, false>;
+        case 1: return k_batch<0, ALT, false, false, true>;
+        case 2: return k_batch<0, ALT, false, true, false>;
+        case 3: return k_batch<0, ALT, false, true, true>;
+        case 4: return k_batch<0, ALT, true, false, false>;
+        case 5: return k_batch<0, ALT, true, false, true>;
+        case 6: return k_batch<0, ALT, true, true, false>;
+        default: return k_batch<0, ALT, true, true, true>;
     }
+}
+
+BatchKernel newton_kernel(bool refine, bool guard, bool phi, bool rcp = false)
+{
+    return rcp ? newton_kernel_t<true>(refine, guard, phi) : newton_kernel_t<false>(refine, guard, phi);
 }
 
 // Workgroups that fit on one CU at once (registers, LDS), so the persistent
@@ -310,17 +272,29 @@ int batch_resident_waves(int num_cu)
     return num_cu * kWaves * resident_blocks(newton_kernel(true, false, true), 0);
 }
 
-hipError_t launch_newton_batch(const BatchArgs &a, bool refine, bool guard, int num_cu,
-                               hipStream_t s)
+const char *const kNewtonBatchNames[] = {"lds j-tiles", "lds j-tiles rcp"};
+const char *const kTableBatchNames[] = {"lds j-tiles", "lds j-tiles htab"};
+
+int batch_variants(int family) { return 2; }
+
+const char *batch_variant_name(int family, int v)
 {
-    return launch(newton_kernel(refine, guard, a.phi != nullptr), a, 0, num_cu, s,
+    if (v < 0 || v > 1) return nullptr;
+    return family == 2 ? kNewtonBatchNames[v] : kTableBatchNames[v];
+}
+
+hipError_t launch_newton_batch(const BatchArgs &a, int variant, bool refine, bool guard,
+                               int num_cu, hipStream_t s)
+{
+    return launch(newton_kernel(refine, guard, a.phi != nullptr, variant == 1), a, 0, num_cu, s,
                   a.phi != nullptr);
 }
 
-hipError_t launch_table_batch(const BatchArgs &a, int num_cu, hipStream_t s)
+hipError_t launch_table_batch(const BatchArgs &a, int variant, int num_cu, hipStream_t s)
 {
-    return launch(k_batch<1, false, false, false>, a, sizeof(float2) << (a.E + a.F), num_cu, s,
-                  false);
+    const size_t lds = sizeof(float2) << (a.E + a.F);
+    if (variant == 1) return launch(k_batch<1, true, false, false, false>, a, lds, num_cu, s, false);
+    return launch(k_batch<1, false, false, false, false>, a, lds, num_cu, s, false);
 }
 
 }  // namespace pgh

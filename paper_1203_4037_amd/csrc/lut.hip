@@ -19,35 +19,13 @@
 // last one, where G0 = G1 = 0, so they add exactly zero.
 #include <algorithm>
 
+#include "pairs.h"
 #include "pgh_internal.h"
 
 namespace pgh {
 namespace {
 
-__device__ __forceinline__ void table_pair(const float4 p, float px, float py, float pz,
-                                           const float2 *__restrict__ stab, float c, float smax,
-                                           unsigned shift, unsigned nbits, unsigned hmask,
-                                           float &sx, float &sy, float &sz)
-{
-    const float dx = p.x - px;
-    const float dy = p.y - py;
-    const float dz = p.z - pz;
-    float r2 = dx * dx;
-    r2 = __builtin_fmaf(dy, dy, r2);
-    r2 = __builtin_fmaf(dz, dz, r2);
-    const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
-    const unsigned u = __float_as_uint(s);
-    const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
-    const float sk = __uint_as_float(u & hmask);
-    const float2 g01 = stab[k];
-    const float g = __builtin_fmaf(g01.y, s - sk, g01.x);
-    const float mg = p.w * g;
-    sx = __builtin_fmaf(mg, dx, sx);
-    sy = __builtin_fmaf(mg, dy, sy);
-    sz = __builtin_fmaf(mg, dz, sz);
-}
-
-template <int KI, int JT, int U>
+template <int KI, int JT, int U, bool HT>
 __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
 {
     static_assert(JT % 256 == 0, "tile must be a multiple of the workgroup");
@@ -63,7 +41,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
     const unsigned hmask = ~((1u << shift) - 1u);
     const float c = a.c, smax = a.smax;
 
-    for (int k = tid; k < K; k += 256) stab[k] = a.table[k];
+    table_to_lds<HT>(stab, a.table, K, shift);
 
     float px[KI], py[KI], pz[KI];
     float tx[KI], ty[KI], tz[KI];
@@ -115,7 +93,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
                 const float4 p = tile[cur][jj];
 #pragma unroll
                 for (int k = 0; k < KI; ++k)
-                    table_pair(p, px[k], py[k], pz[k], stab, c, smax, shift, nbits, hmask, sx[k],
+                    table_pair<HT>(p, px[k], py[k], pz[k], stab, c, smax, shift, nbits, hmask, sx[k],
                                sy[k], sz[k]);
             }
         } else {
@@ -124,7 +102,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
                 const float4 p = tile[cur][jj];
 #pragma unroll
                 for (int k = 0; k < KI; ++k)
-                    table_pair(p, px[k], py[k], pz[k], stab, c, smax, shift, nbits, hmask, sx[k],
+                    table_pair<HT>(p, px[k], py[k], pz[k], stab, c, smax, shift, nbits, hmask, sx[k],
                                sy[k], sz[k]);
             }
         }
@@ -164,9 +142,11 @@ struct TableVariant {
 };
 
 const TableVariant kTableVariants[] = {
-    {"ki=1 jt=256 u=4", 1, 256, k_table_allpairs<1, 256, 4>},
-    {"ki=2 jt=256 u=4", 2, 256, k_table_allpairs<2, 256, 4>},
-    {"ki=4 jt=256 u=2", 4, 256, k_table_allpairs<4, 256, 2>},
+    {"ki=1 jt=256 u=4", 1, 256, k_table_allpairs<1, 256, 4, false>},
+    {"ki=2 jt=256 u=4", 2, 256, k_table_allpairs<2, 256, 4, false>},
+    {"ki=4 jt=256 u=2", 4, 256, k_table_allpairs<4, 256, 2, false>},
+    {"ki=1 jt=256 u=4 htab", 1, 256, k_table_allpairs<1, 256, 4, true>},
+    {"ki=2 jt=256 u=4 htab", 2, 256, k_table_allpairs<2, 256, 4, true>},
 };
 constexpr int kNumTableVariants = sizeof(kTableVariants) / sizeof(kTableVariants[0]);
 

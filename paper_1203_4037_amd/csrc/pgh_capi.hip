@@ -641,7 +641,8 @@ int pgh_batch_newton(pgh_ctx *c, const pgh_plan *p, const float *xi, const float
     a.xj = xj, a.yj = yj, a.zj = zj, a.mj = mj;
     a.ax = ax, a.ay = ay, a.az = az, a.phi = phi;
     const bool guard = (eps2_i == nullptr) && !(c->eps2_all > 0.f);
-    PGH_HIP(c, launch_newton_batch(a, c->refine != 0, guard, c->num_cu, c->stream));
+    const int v = std::max(0, c->variant[PGH_FAMILY_NEWTON_BATCH]);
+    PGH_HIP(c, launch_newton_batch(a, v, c->refine != 0, guard, c->num_cu, c->stream));
     return PGH_OK;
 }
 
@@ -670,7 +671,8 @@ int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, const float 
     a.F = c->tab_F;
     a.c = (float)((smax - 2.0) / (rc * rc));
     a.smax = (float)smax;
-    PGH_HIP(c, launch_table_batch(a, c->num_cu, c->stream));
+    const int v = std::max(0, c->variant[PGH_FAMILY_TABLE_BATCH]);
+    PGH_HIP(c, launch_table_batch(a, v, c->num_cu, c->stream));
     return PGH_OK;
 }
 
@@ -787,6 +789,8 @@ int pgh_variant_count(int family)
     switch (family) {
         case PGH_FAMILY_NEWTON_ALLPAIRS: return newton_allpairs_variants();
         case PGH_FAMILY_TABLE_ALLPAIRS: return table_allpairs_variants();
+        case PGH_FAMILY_NEWTON_BATCH:
+        case PGH_FAMILY_TABLE_BATCH: return batch_variants(family);
         default: return 0;
     }
 }
@@ -796,6 +800,8 @@ const char *pgh_variant_name(int family, int v)
     switch (family) {
         case PGH_FAMILY_NEWTON_ALLPAIRS: return newton_allpairs_variant_name(v);
         case PGH_FAMILY_TABLE_ALLPAIRS: return table_allpairs_variant_name(v);
+        case PGH_FAMILY_NEWTON_BATCH:
+        case PGH_FAMILY_TABLE_BATCH: return batch_variant_name(family, v);
         default: return nullptr;
     }
 }
@@ -815,21 +821,17 @@ int pgh_get_variant(const pgh_ctx *c, int family)
     return c->variant[family];
 }
 
-int pgh_autotune(pgh_ctx *c, int family, int ni, const float *xi, const float *yi,
-                 const float *zi, int reps, float *best_ms)
+}  // extern "C"
+
+namespace {
+
+// Times every variant of `family` (one warm-up, then `reps` calls between
+// hipEvents on the context stream), keeps the fastest in c->variant and
+// returns its index, or restores the previous choice and returns a status.
+template <class Call>
+int tune_family(pgh_ctx *c, int family, int reps, float *best_ms, Call call)
 {
-    if (!c) return PGH_EINVAL;
-    if (family != PGH_FAMILY_NEWTON_ALLPAIRS && family != PGH_FAMILY_TABLE_ALLPAIRS)
-        return fail(c, PGH_ERANGE, "only the all-pairs families are tuned by pgh_autotune");
-    if (ni <= 0 || !xi || !yi || !zi) return fail(c, PGH_EINVAL, "need ni > 0 i-particles");
-    if (c->nj <= 0) return fail(c, PGH_ESTATE, "set j-particles (pgh_set_xmj, pgh_set_n) first");
-    if (family == PGH_FAMILY_TABLE_ALLPAIRS && !c->tab_set)
-        return fail(c, PGH_ESTATE, "no force table set");
     reps = std::max(1, reps);
-    DeviceGuard g(c->device);
-    float *out = nullptr;
-    if (hipMalloc((void **)&out, 4 * sizeof(float) * (size_t)ni) != hipSuccess)
-        return fail(c, PGH_ENOMEM, "hipMalloc(tuning outputs) failed");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = -1;
     float best_t = 0.f;
@@ -841,12 +843,6 @@ int pgh_autotune(pgh_ctx *c, int family, int ni, const float *xi, const float *y
         const int nv = pgh_variant_count(family);
         for (int v = 0; v < nv && status == PGH_OK; ++v) {
             c->variant[family] = v;
-            auto call = [&]() {
-                if (family == PGH_FAMILY_NEWTON_ALLPAIRS)
-                    return pgh_calc_newton(c, ni, xi, yi, zi, nullptr, out, out + ni, out + 2 * ni,
-                                           out + 3 * (size_t)ni);
-                return pgh_calc_table(c, ni, xi, yi, zi, out, out + ni, out + 2 * ni);
-            };
             if ((status = call()) != PGH_OK) break;  // warm-up
             if (hipEventRecord(e0, c->stream) != hipSuccess) status = PGH_EHIP;
             for (int r = 0; r < reps && status == PGH_OK; ++r) status = call();
@@ -866,7 +862,6 @@ int pgh_autotune(pgh_ctx *c, int family, int ni, const float *xi, const float *y
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(out);
     if (status != PGH_OK || best < 0) {
         c->variant[family] = saved;
         return status != PGH_OK ? status : fail(c, PGH_EHIP, "no variant could be timed");
@@ -874,6 +869,62 @@ int pgh_autotune(pgh_ctx *c, int family, int ni, const float *xi, const float *y
     c->variant[family] = best;
     if (best_ms) *best_ms = best_t;
     return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pgh_autotune(pgh_ctx *c, int family, int ni, const float *xi, const float *yi,
+                 const float *zi, int reps, float *best_ms)
+{
+    if (!c) return PGH_EINVAL;
+    if (family != PGH_FAMILY_NEWTON_ALLPAIRS && family != PGH_FAMILY_TABLE_ALLPAIRS)
+        return fail(c, PGH_ERANGE, "pgh_autotune tunes the all-pairs families");
+    if (ni <= 0 || !xi || !yi || !zi) return fail(c, PGH_EINVAL, "need ni > 0 i-particles");
+    if (c->nj <= 0) return fail(c, PGH_ESTATE, "set j-particles (pgh_set_xmj, pgh_set_n) first");
+    if (family == PGH_FAMILY_TABLE_ALLPAIRS && !c->tab_set)
+        return fail(c, PGH_ESTATE, "no force table set");
+    DeviceGuard g(c->device);
+    float *out = nullptr;
+    if (hipMalloc((void **)&out, 4 * sizeof(float) * (size_t)ni) != hipSuccess)
+        return fail(c, PGH_ENOMEM, "hipMalloc(tuning outputs) failed");
+    const int r = tune_family(c, family, reps, best_ms, [&]() {
+        if (family == PGH_FAMILY_NEWTON_ALLPAIRS)
+            return pgh_calc_newton(c, ni, xi, yi, zi, nullptr, out, out + ni, out + 2 * ni,
+                                   out + 3 * (size_t)ni);
+        return pgh_calc_table(c, ni, xi, yi, zi, out, out + ni, out + 2 * ni);
+    });
+    (void)hipFree(out);
+    return r;
+}
+
+int pgh_autotune_plan(pgh_ctx *c, int family, const pgh_plan *p, const float *xi,
+                      const float *yi, const float *zi, const float *xj, const float *yj,
+                      const float *zj, const float *mj, int reps, float *best_ms)
+{
+    if (!c) return PGH_EINVAL;
+    if (family != PGH_FAMILY_NEWTON_BATCH && family != PGH_FAMILY_TABLE_BATCH)
+        return fail(c, PGH_ERANGE, "pgh_autotune_plan tunes the batched families");
+    if (!p || p->owner != c) return fail(c, PGH_EINVAL, "plan does not belong to this context");
+    if (p->ni_total > 0 && (!xi || !yi || !zi)) return fail(c, PGH_EINVAL, "null i-arrays");
+    if (p->nj_total > 0 && (!xj || !yj || !zj || !mj)) return fail(c, PGH_EINVAL, "null j-arrays");
+    if (family == PGH_FAMILY_TABLE_BATCH && !c->tab_set)
+        return fail(c, PGH_ESTATE, "no force table set");
+    if (p->n_tasks == 0) return fail(c, PGH_EINVAL, "the plan holds no work to time");
+    DeviceGuard g(c->device);
+    const size_t ni = (size_t)p->ni_total;
+    float *out = nullptr;
+    if (hipMalloc((void **)&out, 4 * sizeof(float) * ni) != hipSuccess)
+        return fail(c, PGH_ENOMEM, "hipMalloc(tuning outputs) failed");
+    const int r = tune_family(c, family, reps, best_ms, [&]() {
+        if (family == PGH_FAMILY_NEWTON_BATCH)
+            return pgh_batch_newton(c, p, xi, yi, zi, nullptr, xj, yj, zj, mj, out, out + ni,
+                                    out + 2 * ni, out + 3 * ni);
+        return pgh_batch_table(c, p, xi, yi, zi, xj, yj, zj, mj, out, out + ni, out + 2 * ni);
+    });
+    (void)hipFree(out);
+    return r;
 }
 
 }  // extern "C"

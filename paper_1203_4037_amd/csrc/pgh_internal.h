@@ -124,9 +124,11 @@ int table_allpairs_split(int ni, int nj, int variant, size_t part_cap);
 hipError_t launch_table_allpairs(const TableArgs &a, int variant, int S, hipStream_t s);
 
 int batch_resident_waves(int num_cu);  // waves of the persistent grid
-hipError_t launch_newton_batch(const BatchArgs &a, bool refine, bool guard, int num_cu,
-                               hipStream_t s);
-hipError_t launch_table_batch(const BatchArgs &a, int num_cu, hipStream_t s);
+int batch_variants(int family);
+const char *batch_variant_name(int family, int v);
+hipError_t launch_newton_batch(const BatchArgs &a, int variant, bool refine, bool guard,
+                               int num_cu, hipStream_t s);
+hipError_t launch_table_batch(const BatchArgs &a, int variant, int num_cu, hipStream_t s);
 
 // Records of two float4: (x, y, z, s or s_all) and (wx, wy, wz, 0).
 hipError_t launch_pack_xw(int n, const float *x, const float *y, const float *z, const float *s,

@@ -57,16 +57,23 @@ def _newton_case(pgh, ctx, s, eps, sample_items=None):
     return plan, di, dj, out, got
 
 
-def test_tree_style_small(pgh, ctx):
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("refine", [1, 0])
+def test_tree_style_small(pgh, ctx, variant, refine):
     """A small instance of the batched tree workload: Morton-sorted Plummer
-    sphere, i-groups of 32..256, log-normal j-list lengths."""
+    sphere, i-groups of 32..256, log-normal j-list lengths; every variant of
+    the batched Newton kernel, with and without the Newton step."""
     s = synth.tree_style_items(1 << 16, 400, 104, nj_median=600, nj_lo=50, nj_hi=6000)
+    ctx.set_variant(pgh.PGH_FAMILY_NEWTON_BATCH, variant)
+    ctx.set_rsqrt_refine(refine)
     _newton_case(pgh, ctx, s, 1e-3)
 
 
-def test_group_size_edges_and_split_lists(pgh, ctx):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_group_size_edges_and_split_lists(pgh, ctx, variant):
     """Group sizes around the lane-sharing thresholds (16, 32, 64) and j-lists
     of 0, 1, 63, 64, 65 and long ones that the plan cuts into parts."""
+    ctx.set_variant(pgh.PGH_FAMILY_NEWTON_BATCH, variant)
     rng = np.random.default_rng(8)
     n = 20000
     x, y, z = synth.plummer(n, 44)
@@ -145,9 +152,12 @@ def test_graph_capture_replays(pgh, ctx):
         torch.cuda.synchronize()
 
 
-def test_cell_list_table_force(pgh, ctx):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_cell_list_table_force(pgh, ctx, variant):
     """Cell-grid neighbour lists in a periodic unit box (the PP part of a
-    TreePM step) with the S2 table: N = 32768, 32^3 cells, 4^3-cell groups."""
+    TreePM step) with the S2 table: N = 32768, 32^3 cells, 4^3-cell groups;
+    both table forms of the batched kernel."""
+    ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, variant)
     n = 32768
     x, y, z = synth.uniform_box(n, 103)
     m = synth.equal_masses(n)
@@ -209,3 +219,22 @@ def test_tree_style_config_full(pgh, ctx):
     pick = np.unique(np.concatenate([[np.argmax(cost), np.argmin(cost), np.argmax(s.items[:, 3])],
                                      rng.integers(0, len(s.items), 45)]))
     _newton_case(pgh, ctx, s, 1e-3, sample_items=pick)
+
+
+def test_plan_autotuner(pgh, ctx):
+    """pgh_autotune_plan times both batched variants on a plan, keeps the
+    fastest, and the chosen kernel still meets the parity gate."""
+    s = synth.tree_style_items(1 << 15, 200, 11, nj_median=500, nj_lo=50, nj_hi=5000)
+    di, dj = _dev_set(s)
+    ctx.set_eps_to_all(1e-3)
+    plan = ctx.plan(s.items, s.xi.size, s.xj.size)
+    v = plan.autotune(pgh.PGH_FAMILY_NEWTON_BATCH, *di, *dj, reps=2)
+    assert 0 <= v < pgh.pgh_variant_count(pgh.PGH_FAMILY_NEWTON_BATCH)
+    assert pgh.pgh_get_variant(ctx.h, pgh.PGH_FAMILY_NEWTON_BATCH) == v
+    _newton_case(pgh, ctx, s, 1e-3)
+    with pytest.raises(pgh.PGHError) as e:  # the table family needs a table
+        plan.autotune(pgh.PGH_FAMILY_TABLE_BATCH, *di, *dj)
+    assert e.value.code == pgh.PGH_ESTATE
+    with pytest.raises(pgh.PGHError) as e:
+        plan.autotune(pgh.PGH_FAMILY_NEWTON_ALLPAIRS, *di, *dj)
+    assert e.value.code == pgh.PGH_ERANGE
