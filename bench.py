@@ -33,6 +33,35 @@ NEWTON_FLOPS = 38  # per interaction, the paper's count (Sec. 5.1)
 TABLE_FLOPS = 20  # per interaction, this project's count of the FP32 ops of the table loop
 
 
+# HBM traffic of the headline kernel, from two rocprofv3 --pmc runs of
+# `bench.py --no-extras --no-cpu --copy-calibration 256` (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads for a
+# 256 MiB device-to-device copy (FETCH_SIZE 131093 KiB -> x2.0, WRITE_SIZE
+# 262144 KiB -> x1.0).  Valid only for the variant and kernel sources the
+# counters were taken on; otherwise the bench reports traffic as null.
+MEASURED_TRAFFIC = {
+    "variant": "ki=1 jt=256 u=8",
+    "sources_sha256": "3d0305d138cbc5509f71873d81fe5f736f139d4ae3494d7aa5f3464940ba6681",
+    "fetch_kib": 22370, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
+}
+KERNEL_SOURCES = ("paper_1203_4037_amd/csrc/newton.hip", "paper_1203_4037_amd/csrc/pairs.h")
+
+
+def measured_traffic(variant_name):
+    """HBM bytes per launch of the headline kernel, or None when the counters
+    were taken on another variant or on other kernel sources."""
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    t = MEASURED_TRAFFIC
+    if variant_name != t["variant"] or h.hexdigest() != t["sources_sha256"]:
+        return None
+    return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,37 +234,60 @@ def batched_newton(torch, pgh, synth):
             "autotuned_variant": pgh.pgh_variant_name(fam, tuned), "ms_per_variant": per}
 
 
+def useful_pairs(s, rcut):
+    """Pairs of the lists closer than rcut (the ones with a non-zero force),
+    counted on the host."""
+    r2 = rcut * rcut
+    count = 0
+    for i0, ni, j0, nj in s.items:
+        if ni == 0 or nj == 0:
+            continue
+        dx = s.xj[j0:j0 + nj][None, :] - s.xi[i0:i0 + ni][:, None]
+        dy = s.yj[j0:j0 + nj][None, :] - s.yi[i0:i0 + ni][:, None]
+        dz = s.zj[j0:j0 + nj][None, :] - s.zi[i0:i0 + ni][:, None]
+        count += int(np.count_nonzero(dx * dx + dy * dy + dz * dz < r2))
+    return count
+
+
 def batched_table(torch, pgh, synth):
     """Cell-grid lists of a TreePM PP step: N = 262144 uniform in the unit
-    periodic box, 64^3 cells, 4^3-cell i-groups with their 6^3-cell halo
-    (4096 lists), S2 PP shape rcut = 3/256, eps = 1/1280, E = 4, F = 6;
-    replayed from a graph."""
+    periodic box, 64^3 cells, i-groups of 4^3 cells with their 6^3-cell halo
+    (4096 lists; and 8^3-cell groups with a 10^3-cell halo, 512 lists),
+    S2 PP shape rcut = 3/256, eps = 1/1280, E = 4, F = 6; replayed from a
+    graph.  Also the rate of useful pairs (closer than rcut)."""
     n = 262144
+    rcut = 3.0 / 256
     x, y, z = synth.uniform_box(n, 103)
     m = synth.equal_masses(n)
-    s = synth.cell_grid_items(x, y, z, m, ncell=64, block=4)
-    di = [torch.from_numpy(a).cuda() for a in (s.xi, s.yi, s.zi)]
-    dj = [torch.from_numpy(a).cuda() for a in (s.xj, s.yj, s.zj, s.mj)]
-    ctx = pgh.Context(0)
-    ctx.build_table(4, 6, 3.0 / 256, eps=1.0 / 1280)
-    plan = ctx.plan(s.items, n, s.xj.size)
-    out = [torch.empty(n, device="cuda") for _ in range(3)]
-    fam = pgh.PGH_FAMILY_TABLE_BATCH
-    per = {}
-    for v in range(pgh.pgh_variant_count(fam)):
-        ctx.set_variant(fam, v)
-        per[pgh.pgh_variant_name(fam, v)] = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 200)
-    # the paper's (G0, G1) form is the default; the timings of both are above
-    ctx.set_variant(fam, 0)
-    ms = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 200)
-    inter = float(plan.interactions)
-    plan.free()
-    ctx.close()
-    rate = inter / (ms / 1e3)
-    return {"workload": "table_batched_cell_lists_N262144_E4F6", "interactions": inter,
+    res = {}
+    for block in (4, 8):
+        s = synth.cell_grid_items(x, y, z, m, ncell=64, block=block)
+        di = [torch.from_numpy(a).cuda() for a in (s.xi, s.yi, s.zi)]
+        dj = [torch.from_numpy(a).cuda() for a in (s.xj, s.yj, s.zj, s.mj)]
+        ctx = pgh.Context(0)
+        ctx.build_table(4, 6, rcut, eps=1.0 / 1280)
+        plan = ctx.plan(s.items, n, s.xj.size)
+        out = [torch.empty(n, device="cuda") for _ in range(3)]
+        fam = pgh.PGH_FAMILY_TABLE_BATCH
+        per = {}
+        for v in range(pgh.pgh_variant_count(fam)):
+            ctx.set_variant(fam, v)
+            per[pgh.pgh_variant_name(fam, v)] = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 200)
+        tuned = plan.autotune(fam, *di, *dj, reps=20)
+        ms = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 200)
+        inter = float(plan.interactions)
+        plan.free()
+        ctx.close()
+        rate = inter / (ms / 1e3)
+        useful = useful_pairs(s, rcut)
+        res[f"block{block}"] = {
+            "workload": f"table_batched_cell_lists_N262144_E4F6_block{block}",
+            "lists": int(len(s.items)), "interactions": inter, "useful_pairs": useful,
             "ms_per_launch": ms, "interactions_per_s": rate,
+            "useful_pairs_per_s": useful / (ms / 1e3),
             "frac_of_peak_20flop": TABLE_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12),
-            "variant": pgh.pgh_variant_name(fam, 0), "ms_per_variant": per}
+            "autotuned_variant": pgh.pgh_variant_name(fam, tuned), "ms_per_variant": per}
+    return res
 
 
 def adjoint_newton(torch, pgh, synth):
@@ -392,7 +444,8 @@ def main():
                    "parallelism": "single_gpu", "kernel_variant": r["variant_name"],
                    "autotuned": r["autotuned"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic(r["variant_name"]), "traffic_unit": "bytes/launch",
                      "kernel": "k_newton_allpairs", "kernel_ms": r["kern_ms"],
                      "flops_per_interaction": NEWTON_FLOPS,
                      "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS},

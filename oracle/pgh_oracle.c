@@ -353,8 +353,13 @@ PGO_EXPORT void pgo_central_items(long n_items, const int32_t *items, const doub
  *   dT/dd = m_j [rho^3 w_i - 3 rho^5 (w_i . d) d],  dd/dr_j = I,  dd/dr_i = -I,
  *   dT/dm_j = rho^3 (w_i . d).
  * gxi_i = -sum_j dT/dd;  gxj_j = sum_i dT/dd;  gmj_j = sum_i rho^3 (w_i . d).
- * absi_i = sum_j |dT/dd|, absj_j = sum_i |dT/dd| and absm_j = sum_i
- * |rho^3 (w_i . d)| are the scales of these sums (for error measures).
+ * absi_i, absj_j and absm_j are the scales of these sums for error measures:
+ * the sums of the magnitudes of every product the pair terms expand into,
+ * with the dot product w_i . d counted as |w_x d_x| + |w_y d_y| + |w_z d_z|
+ * (an FP32 evaluation of w_i . d errs by a rounding of those, not of
+ * |w_i . d|, which can cancel to nothing):
+ *   absi_i = sum_j m_j (rho^3 |w_i| + 3 rho^5 a_ij |d|),  absj_j likewise
+ *   over i,  absm_j = sum_i rho^3 a_ij,  a_ij = sum_c |w_i,c d_c|.
  * Any output pointer may be NULL (gxi..gzi together, gxj..gzj together).
  * Pairs with zero softened distance are skipped like in the forward sum.
  */
@@ -383,10 +388,14 @@ PGO_EXPORT void pgo_newton_bwd(long ni, const double *xi, const double *yi, cons
                 const double t0 = m * (rho3 * wx[i] - 3.0 * rho5 * wd * dx);
                 const double t1 = m * (rho3 * wy[i] - 3.0 * rho5 * wd * dy);
                 const double t2 = m * (rho3 * wz[i] - 3.0 * rho5 * wd * dz);
+                const double awd = fabs((double)wx[i] * dx) + fabs((double)wy[i] * dy) +
+                                   fabs((double)wz[i] * dz);
+                const double wn = sqrt((double)wx[i] * wx[i] + (double)wy[i] * wy[i] +
+                                       (double)wz[i] * wz[i]);
                 s0 -= t0;
                 s1 -= t1;
                 s2 -= t2;
-                sa += sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+                sa += fabs(m) * (rho3 * wn + 3.0 * rho5 * awd * sqrt(dx * dx + dy * dy + dz * dz));
             }
             gxi[i] = s0;
             gyi[i] = s1;
@@ -411,12 +420,16 @@ PGO_EXPORT void pgo_newton_bwd(long ni, const double *xi, const double *yi, cons
                 const double t0 = m * (rho3 * wx[ii] - 3.0 * rho5 * wd * dx);
                 const double t1 = m * (rho3 * wy[ii] - 3.0 * rho5 * wd * dy);
                 const double t2 = m * (rho3 * wz[ii] - 3.0 * rho5 * wd * dz);
+                const double awd = fabs((double)wx[ii] * dx) + fabs((double)wy[ii] * dy) +
+                                   fabs((double)wz[ii] * dz);
+                const double wn = sqrt((double)wx[ii] * wx[ii] + (double)wy[ii] * wy[ii] +
+                                       (double)wz[ii] * wz[ii]);
                 s0 += t0;
                 s1 += t1;
                 s2 += t2;
                 sm += rho3 * wd;
-                sa += sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-                sb += fabs(rho3 * wd);
+                sa += fabs(m) * (rho3 * wn + 3.0 * rho5 * awd * sqrt(dx * dx + dy * dy + dz * dz));
+                sb += rho3 * awd;
             }
             if (gxj) {
                 gxj[j] = s0;
@@ -438,9 +451,12 @@ PGO_EXPORT void pgo_newton_bwd(long ni, const double *xi, const double *yi, cons
  *   dL/dm_j  = sum_i g (w_i . d)
  * G0 and G1 are treated as independent leaves.  gtab_abs (2K), when not
  * NULL, receives the sums of the absolute terms; gmj_abs (nj_total) receives
- * sum_i |w_i . d| (|G0_k| + |G1_k| (s_{k+1} - s_k)), the size g can take in
- * its bin (its G1 part scaled by the bin width rather than by s - s_k, which
- * an FP32 evaluation of s knows only to one rounding of s).
+ * sum_i a_ij (|G0_k| + |G1_k| (s_{k+1} - s_k)), the size g can take in its
+ * bin (its G1 part scaled by the bin width rather than by s - s_k, which an
+ * FP32 evaluation of s knows only to one rounding of s).  Here, and in
+ * gtab_abs, the dot product counts as a_ij = sum_c |w_i,c d_c|: an FP32
+ * evaluation of w_i . d errs by a rounding of those products, not of
+ * |w_i . d|, which can cancel to nothing.
  * gtab is double[2K]
  * interleaved like the table; gmj is per j entry of the arrays (an entry used
  * by several items accumulates over them).  Items run one after another so
@@ -478,13 +494,15 @@ PGO_EXPORT void pgo_lut_bwd_items(long n_items, const int32_t *items, const doub
                 gtab[2 * k] += m * wd;
                 gtab[2 * k + 1] += m * (s - sk) * wd;
                 if (gmj) gmj[j] += g * wd;
+                const double awd = fabs((double)wx[i] * dx) + fabs((double)wy[i] * dy) +
+                                   fabs((double)wz[i] * dz);
                 if (gtab_abs) {
-                    gtab_abs[2 * k] += fabs(m * wd);
-                    gtab_abs[2 * k + 1] += fabs(m * (s - sk) * wd);
+                    gtab_abs[2 * k] += fabs(m) * awd;
+                    gtab_abs[2 * k + 1] += fabs(m * (s - sk)) * awd;
                 }
                 if (gmj_abs) {
                     const double width = (k + 1 < K) ? pgo_node_s(E, F, k + 1) - sk : 0.0;
-                    gmj_abs[j] += fabs(wd) * (fabs(table[2 * k]) + fabs(table[2 * k + 1]) * width);
+                    gmj_abs[j] += awd * (fabs(table[2 * k]) + fabs(table[2 * k + 1]) * width);
                 }
             }
         }

@@ -357,31 +357,42 @@ __global__ void __launch_bounds__(256) k_newton_bwd_j(int nj, const float4 *__re
 // table-force adjoint over a plan
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void table_g(float r2, float c, float smax, unsigned shift,
-                                        unsigned nbits, unsigned hmask,
-                                        const float2 *__restrict__ stab, unsigned &k, float &ds,
-                                        float &g)
+__device__ __forceinline__ void wave_sync()
 {
-    const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
-    const unsigned u = __float_as_uint(s);
-    k = __builtin_amdgcn_ubfe(u, shift, nbits);
-    ds = s - __uint_as_float(u & hmask);
-    const float2 g01 = stab[k];
-    g = __builtin_fmaf(g01.y, ds, g01.x);
+    // LDS operations of one wave complete in order; the fences keep the
+    // compiler from moving tile reads across the writes of other lanes.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// i-major: table gradient.  Uses the plan's tasks (i-chunks x j-parts).
-__global__ void __launch_bounds__(256) k_table_bwd_tab(TableBwdArgs A)
+// Both passes of the table-force adjoint in one persistent launch.  The task
+// index space is [0, n_tab): i-major tasks of the plan (an i-chunk against a
+// part of its j-list), giving the table gradient; then [n_tab, n_tab + n_m):
+// j-major tasks (a chunk of <= 64 j-entries against its item's i-range),
+// giving the mass gradient.  Tasks of each kind are sorted longest first.
+//
+//   table gradient: for a pair with bin k and offset ds = s - s_k,
+//     dL/dG0_k += m_j (w_i . d),  dL/dG1_k += m_j (w_i . d) ds
+//   accumulated in LDS (float atomics; pairs clamped to s_max, the common
+//   case, go to one register instead) and added to gtable at the end with
+//   one global atomic per non-zero bin and workgroup;
+//   mass gradient: dL/dm_j = sum_i g(s) (w_i . d), one lane per j-entry.
+//
+// j (or i) records stream through a per-wave LDS tile of 64, the next tile
+// prefetched into registers while the current one is consumed.
+__global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *jtasks, int n_tab,
+                                                   int n_m, unsigned *queue)
 {
     extern __shared__ float dyn[];
     const BatchArgs &a = A.b;
     const int K = 1 << (a.E + a.F);
-    float2 *stab = (float2 *)dyn;           // K (G0, G1)
-    float *gt = dyn + 2 * K;                // 2K gradient accumulators
-    __shared__ float4 jt[4][64];
+    float2 *stab = (float2 *)dyn;  // K (G0, G1): mass tasks
+    float *gt = dyn + 2 * K;       // 2K gradient accumulators: table tasks
+    __shared__ float4 buf[4][128];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k = threadIdx.x; k < K; k += 256) {
-        stab[k] = a.table[k];
+        if (n_m > 0) stab[k] = a.table[k];
         gt[2 * k] = 0.f;
         gt[2 * k + 1] = 0.f;
     }
@@ -389,40 +400,51 @@ __global__ void __launch_bounds__(256) k_table_bwd_tab(TableBwdArgs A)
     const unsigned shift = 23u - (unsigned)a.F, nbits = (unsigned)(a.E + a.F);
     const unsigned hmask = ~((1u << shift) - 1u);
     const unsigned klast = (unsigned)K - 1u;
+    const float c = a.c, smax = a.smax;
+    float4 *tile = buf[wave];
     float last0 = 0.f;  // clamped pairs: dL/dG0 of the last node
 
-    // static first round, then one atomic per task (as in the forward kernel)
+    const unsigned n_all = (unsigned)(n_tab + n_m);
     const unsigned n_waves = gridDim.x * 4;
-    for (unsigned t = blockIdx.x * 4 + wave; t < (unsigned)a.n_tasks;) {
-        const Task tk = a.tasks[t];
-        unsigned tn = (unsigned)a.n_tasks;
-        if ((unsigned)a.n_tasks > n_waves && lane == 0)
-            tn = n_waves +
-                 __hip_atomic_fetch_add(&a.queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // one lane per i-particle here (lanes past n_i carry zero weight)
-        const bool active = lane < tk.n_i;
-        const int i = tk.i_off + (active ? lane : 0);
-        const float px = a.xi[i], py = a.yi[i], pz = a.zi[i];
-        const float wx = active ? A.wx[i] : 0.f, wy = active ? A.wy[i] : 0.f,
-                    wz = active ? A.wz[i] : 0.f;
-        for (int base = 0; base < tk.n_j; base += 64) {
-            const int cnt = min(64, tk.n_j - base);
-            const int j = tk.j_off + base + lane;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (lane < cnt) v = make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j]);
-            jt[wave][lane] = v;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (int jj = 0; jj < cnt; ++jj) {
-                const float4 p = jt[wave][jj];
+    for (unsigned t = blockIdx.x * 4 + wave; t < n_all;) {
+        unsigned tn = n_all;
+        if (n_all > n_waves && lane == 0) {
+            // one pop per task executed: the pop that draws n_all-1 is the
+            // launch's last and puts the counter back to zero
+            const unsigned k =
+                __hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (k == n_all - 1u) __hip_atomic_store(queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tn = n_waves + k;
+        }
+        if (t < (unsigned)n_tab) {
+            // ---- table gradient: lane = i-particle, loop over j.  A paired
+            // task runs its two chunks side by side (lanes [0, n_i) on the
+            // first list, [n_i, n_i + n_i2) on the second).
+            const Task tk = a.tasks[t];
+            const bool paired = tk.n_i2 > 0;
+            const bool second = paired && lane >= tk.n_i;
+            const int il = second ? lane - tk.n_i : lane;
+            const bool active = il < (second ? tk.n_i2 : tk.n_i);
+            const int i = (second ? tk.i_off2 : tk.i_off) + (active ? il : 0);
+            const float px = a.xi[i], py = a.yi[i], pz = a.zi[i];
+            const float wx = active ? A.wx[i] : 0.f, wy = active ? A.wy[i] : 0.f,
+                        wz = active ? A.wz[i] : 0.f;
+            const int nj = paired ? max(tk.n_j, tk.n_j2) : tk.n_j;
+            // records past a list's end: zero mass, far away (clamped bin)
+            auto load = [&](int off, int n, int base) {
+                float4 v = make_float4(1.0e10f, 1.0e10f, 1.0e10f, 0.f);
+                const int j = off + base + lane;
+                if (base + lane < n) v = make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j]);
+                return v;
+            };
+            auto pair = [&](const float4 p) {
                 const float dx = p.x - px, dy = p.y - py, dz = p.z - pz;
                 float r2 = dx * dx;
                 r2 = __builtin_fmaf(dy, dy, r2);
                 r2 = __builtin_fmaf(dz, dz, r2);
-                unsigned k;
-                float ds, g;
-                table_g(r2, a.c, a.smax, shift, nbits, hmask, stab, k, ds, g);
+                const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
+                const unsigned u = __float_as_uint(s);
+                const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
                 float wd = wx * dx;
                 wd = __builtin_fmaf(wy, dy, wd);
                 wd = __builtin_fmaf(wz, dz, wd);
@@ -430,13 +452,79 @@ __global__ void __launch_bounds__(256) k_table_bwd_tab(TableBwdArgs A)
                 if (k == klast) {
                     last0 += v0;
                 } else if (active) {
+                    const float ds = s - __uint_as_float(u & hmask);
                     atomicAdd(&gt[2 * k], v0);
                     atomicAdd(&gt[2 * k + 1], v0 * ds);
                 }
+            };
+            const float4 *src = tile + (second ? 64 : 0);
+            float4 pre = load(tk.j_off, tk.n_j, 0), pre2 = pre;
+            if (paired) pre2 = load(tk.j_off2, tk.n_j2, 0);
+            for (int base = 0; base < nj; base += 64) {
+                wave_sync();
+                tile[lane] = pre;
+                if (paired) tile[64 + lane] = pre2;
+                wave_sync();
+                if (base + 64 < nj) {
+                    pre = load(tk.j_off, tk.n_j, base + 64);
+                    if (paired) pre2 = load(tk.j_off2, tk.n_j2, base + 64);
+                }
+                const int cnt = min(64, nj - base);
+                if (cnt == 64) {
+#pragma unroll 4
+                    for (int jj = 0; jj < 64; ++jj) pair(src[jj]);
+                } else {
+                    for (int jj = 0; jj < cnt; ++jj) pair(src[jj]);
+                }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            // ---- mass gradient: lane = j-entry, loop over the item's i-range
+            const Task tk = jtasks[t - (unsigned)n_tab];  // i_off/n_i: j-chunk; j_off/n_j: i-range
+            const bool active = lane < tk.n_i;
+            const int j = tk.i_off + (active ? lane : 0);
+            const float qx = a.xj[j], qy = a.yj[j], qz = a.zj[j];
+            float G = 0.f;
+            float4 pp, pw;
+            auto load = [&](int base) {
+                pp = make_float4(0.f, 0.f, 0.f, 0.f);
+                pw = pp;
+                const int i = tk.j_off + base + lane;
+                if (base + lane < tk.n_j) {
+                    pp = make_float4(a.xi[i], a.yi[i], a.zi[i], A.wx[i]);
+                    pw = make_float4(A.wy[i], A.wz[i], 0.f, 0.f);
+                }
+            };
+            auto pair = [&](const float4 p, const float4 w) {
+                const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+                float r2 = dx * dx;
+                r2 = __builtin_fmaf(dy, dy, r2);
+                r2 = __builtin_fmaf(dz, dz, r2);
+                const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
+                const unsigned u = __float_as_uint(s);
+                const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
+                const float2 g01 = stab[k];
+                const float g = __builtin_fmaf(g01.y, s - __uint_as_float(u & hmask), g01.x);
+                float wd = p.w * dx;
+                wd = __builtin_fmaf(w.x, dy, wd);
+                wd = __builtin_fmaf(w.y, dz, wd);
+                G = __builtin_fmaf(g, wd, G);
+            };
+            load(0);
+            for (int base = 0; base < tk.n_j; base += 64) {
+                wave_sync();
+                tile[lane] = pp;
+                tile[64 + lane] = pw;
+                wave_sync();
+                if (base + 64 < tk.n_j) load(base + 64);
+                const int cnt = min(64, tk.n_j - base);
+                if (cnt == 64) {
+#pragma unroll 4
+                    for (int ii = 0; ii < 64; ++ii) pair(tile[ii], tile[64 + ii]);
+                } else {
+                    for (int ii = 0; ii < cnt; ++ii) pair(tile[ii], tile[64 + ii]);
+                }
+            }
+            if (active) atomicAdd(&A.gmj[j], G);
         }
         t = __builtin_amdgcn_readfirstlane(tn);
     }
@@ -444,80 +532,23 @@ __global__ void __launch_bounds__(256) k_table_bwd_tab(TableBwdArgs A)
     for (int off = 32; off > 0; off >>= 1) last0 += __shfl_xor(last0, off);
     if (lane == 0 && last0 != 0.f) atomicAdd(&gt[2 * klast], last0);
     __syncthreads();
-    for (int k = threadIdx.x; k < 2 * K; k += 256)
-        if (gt[k] != 0.f) atomicAdd(&A.gtable[k], gt[k]);
+    if (n_tab > 0)
+        for (int k = threadIdx.x; k < 2 * K; k += 256)
+            if (gt[k] != 0.f) atomicAdd(&A.gtable[k], gt[k]);
 }
 
-// j-major: dL/dm_j = sum_i g (w_i . d).  Tasks are (j-chunk of <= 64
-// entries, i-range); results go to gmj with float atomics (a j entry used by
-// several lists accumulates over them).
-__global__ void __launch_bounds__(256) k_table_bwd_m(TableBwdArgs A, const Task *jtasks,
-                                                     int n_jtasks, unsigned *jqueue)
+// Zeroes the gradient outputs and the task counter ahead of k_table_bwd (a
+// kernel rather than memsets, so the pair can be captured in a graph).
+__global__ void __launch_bounds__(256) k_table_bwd_prologue(float *gtable, int n1, float *gmj,
+                                                            int n2, unsigned *queue)
 {
-    extern __shared__ float dyn[];
-    const BatchArgs &a = A.b;
-    const int K = 1 << (a.E + a.F);
-    float2 *stab = (float2 *)dyn;
-    __shared__ float4 it[4][64][2];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = threadIdx.x; k < K; k += 256) stab[k] = a.table[k];
-    __syncthreads();
-    const unsigned shift = 23u - (unsigned)a.F, nbits = (unsigned)(a.E + a.F);
-    const unsigned hmask = ~((1u << shift) - 1u);
-    const unsigned n_waves = gridDim.x * 4;
-    for (unsigned t = blockIdx.x * 4 + wave; t < (unsigned)n_jtasks;) {
-        const Task tk = jtasks[t];  // i_off/n_i: the j-chunk, j_off/n_j: the i-range
-        unsigned tn = (unsigned)n_jtasks;
-        if ((unsigned)n_jtasks > n_waves && lane == 0)
-            tn = n_waves +
-                 __hip_atomic_fetch_add(&jqueue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const bool active = lane < tk.n_i;
-        const int j = tk.i_off + (active ? lane : 0);
-        const float qx = a.xj[j], qy = a.yj[j], qz = a.zj[j];
-        float G = 0.f;
-        for (int base = 0; base < tk.n_j; base += 64) {
-            const int cnt = min(64, tk.n_j - base);
-            const int i = tk.j_off + base + lane;
-            float4 p = make_float4(0.f, 0.f, 0.f, 0.f), w = p;
-            if (lane < cnt) {
-                p = make_float4(a.xi[i], a.yi[i], a.zi[i], 0.f);
-                w = make_float4(A.wx[i], A.wy[i], A.wz[i], 0.f);
-            }
-            it[wave][lane][0] = p;
-            it[wave][lane][1] = w;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (int ii = 0; ii < cnt; ++ii) {
-                const float4 pi = it[wave][ii][0];
-                const float4 wi = it[wave][ii][1];
-                const float dx = qx - pi.x, dy = qy - pi.y, dz = qz - pi.z;
-                float r2 = dx * dx;
-                r2 = __builtin_fmaf(dy, dy, r2);
-                r2 = __builtin_fmaf(dz, dz, r2);
-                unsigned k;
-                float ds, g;
-                table_g(r2, a.c, a.smax, shift, nbits, hmask, stab, k, ds, g);
-                float wd = wi.x * dx;
-                wd = __builtin_fmaf(wi.y, dy, wd);
-                wd = __builtin_fmaf(wi.z, dz, wd);
-                G = __builtin_fmaf(g, wd, G);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-        if (active) atomicAdd(&A.gmj[j], G);
-        t = __builtin_amdgcn_readfirstlane(tn);
-    }
-}
-
-__global__ void k_reset_counter(unsigned *q0, unsigned *q1)
-{
-    if (threadIdx.x == 0) {
-        *q0 = 0u;
-        if (q1) *q1 = 0u;
-    }
+    const int stride = gridDim.x * 256;
+    const int t0 = blockIdx.x * 256 + threadIdx.x;
+    if (t0 == 0) *queue = 0u;
+    if (gtable)
+        for (int k = t0; k < n1; k += stride) gtable[k] = 0.f;
+    if (gmj)
+        for (int k = t0; k < n2; k += stride) gmj[k] = 0.f;
 }
 
 int resident(const void *k, size_t lds)
@@ -587,28 +618,22 @@ hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 
 }
 
 hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int n_jtasks,
-                                  unsigned *jqueue, int num_cu, hipStream_t s)
+                                  int nj_total, unsigned *queue, int num_cu, hipStream_t s)
 {
     const int K = 1 << (A.b.E + A.b.F);
-    hipError_t e;
-    if (A.gtable && A.b.n_tasks > 0) {
-        const size_t lds = (size_t)K * 4 * sizeof(float);
-        const int blocks = num_cu * resident((const void *)k_table_bwd_tab, lds);
-        hipLaunchKernelGGL(k_table_bwd_tab, dim3(blocks), dim3(256), lds, s, A);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, A.b.queue, (unsigned *)nullptr);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (A.gmj && n_jtasks > 0) {
-        const size_t lds = (size_t)K * 2 * sizeof(float);
-        const int blocks = num_cu * resident((const void *)k_table_bwd_m, lds);
-        hipLaunchKernelGGL(k_table_bwd_m, dim3(blocks), dim3(256), lds, s, A, jtasks, n_jtasks,
-                           jqueue);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, jqueue, (unsigned *)nullptr);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const int n_tab = A.gtable ? A.b.n_tasks : 0;
+    const int n_m = A.gmj ? n_jtasks : 0;
+    const int n2 = A.gmj ? nj_total : 0;
+    const int zb = std::max(1, std::min(1024, (std::max(2 * K, n2) + 255) / 256));
+    hipLaunchKernelGGL(k_table_bwd_prologue, dim3(zb), dim3(256), 0, s, A.gtable, 2 * K, A.gmj,
+                       n2, queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_tab + n_m == 0) return e;
+    const size_t lds = (size_t)K * 4 * sizeof(float);
+    const int cap = num_cu * resident((const void *)k_table_bwd, lds);
+    const int blocks = std::max(1, std::min(cap, (n_tab + n_m + 3) / 4));
+    hipLaunchKernelGGL(k_table_bwd, dim3(blocks), dim3(256), lds, s, A, jtasks, n_tab, n_m, queue);
+    return hipGetLastError();
 }
 
 }  // namespace pgh

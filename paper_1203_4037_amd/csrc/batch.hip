@@ -11,11 +11,16 @@
 //     the plan's scratch, and a small second kernel adds them in part order
 //     (deterministic) and writes the outputs;
 //   * tasks are sorted by decreasing length (longest-processing-time first).
-// Execution: a grid sized to fill every CU; each wave64 runs independently,
-// taking its first task by its index and later ones from a device counter
-// with one atomic each.  The second kernel also resets the counter, so the
-// next launch (or a replay of a captured graph) starts from zero without a
-// memset.
+// Execution: a grid sized to fill every CU (or smaller, when there are fewer
+// tasks than resident waves); the task list is dealt into up to 16
+// sublists, each served by the workgroups b = q mod nq through its own
+// counter.  Each wave64 runs independently, taking its first task of the
+// sublist by its index and later ones from the sublist's counter with one
+// atomic each.  Every task executed pops exactly once, so the pops of a
+// sublist return 0 .. n-1; the wave that draws n-1 knows no pop follows and
+// puts the counter back to zero, so the next launch (or a replay of a
+// captured graph) starts from zero with no reset kernel or memset.  The
+// second kernel runs only when some list is split.
 //
 // Each wave stages its j-list through its own LDS slice, 64 records per
 // tile (one coalesced load per coordinate array), double-buffered in
@@ -31,7 +36,11 @@
 namespace pgh {
 namespace {
 
-constexpr int kWaves = 4;  // wave64s per workgroup
+constexpr int kWaves = kBatchWaves;
+// coordinate of padding records: far enough that every pair term with them
+// is finite and multiplied by a zero mass, small enough that its square
+// stays finite in FP32
+constexpr float kFar = 1.0e10f;
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -45,10 +54,13 @@ __device__ __forceinline__ void wave_sync()
 // KIND 0: Newton (REFINE, GUARD, PHI apply; ALT = the rcp form);
 // KIND 1: table force (ALT = the (H, G1) table form).
 template <int KIND, bool ALT, bool REFINE, bool GUARD, bool PHI>
-__global__ void __launch_bounds__(256) k_batch(BatchArgs a)
+__global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
 {
     extern __shared__ float2 stab[];  // table force only: 2^(E+F) entries
-    __shared__ float4 jt[kWaves][2][64];
+    // [wave][buffer][list][record]: the Newton kernel double-buffers its
+    // tiles; the table kernel, whose table also sits in LDS, uses one buffer
+    constexpr int NB = KIND == 0 ? 2 : 1;
+    __shared__ float4 jt[kWaves][NB][2][64];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -69,85 +81,127 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a)
     // later tasks come from the counter, one atomic per task, taken at the
     // start of the previous task so its latency overlaps that task.  (All
     // waves hitting one counter at once serialises at the memory side.)
-    const unsigned n_tasks = (unsigned)a.n_tasks;
-    const bool dynamic = n_tasks > (unsigned)a.n_waves;
-    unsigned t = blockIdx.x * kWaves + wave;
+    // this workgroup serves task sublist q with the other workgroups b = q mod nq
+    const unsigned nq = (unsigned)a.nq;
+    const unsigned q = blockIdx.x % nq;
+    const unsigned nw_q = ((gridDim.x - q + nq - 1) / nq) * kWaves;  // waves serving q
+    const Task *tasks = a.tasks + a.q_begin[q];
+    const unsigned n_tasks = (unsigned)(a.q_begin[q + 1] - a.q_begin[q]);
+    unsigned *counter = a.queue + q * kQueueStride;
+    const bool dynamic = n_tasks > nw_q;
+    // (readfirstlane: the index is wave-uniform, so task fields load as scalars)
+    unsigned t = __builtin_amdgcn_readfirstlane((blockIdx.x / nq) * kWaves + wave);
     while (t < n_tasks) {
-        const Task tk = a.tasks[t];
+        const Task tk = tasks[t];
         unsigned tn = n_tasks;
-        if (dynamic && lane == 0)
-            tn = (unsigned)a.n_waves +
-                 __hip_atomic_fetch_add(&a.queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (dynamic && lane == 0) {
+            const unsigned k =
+                __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (k == n_tasks - 1u)  // the sublist's last pop in this launch
+                __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tn = nw_q + k;
+        }
 
-        // lanes per i-particle (js) and the lane's i slot and j phase
-        const int js = tk.n_i <= 16 ? 4 : (tk.n_i <= 32 ? 2 : 1);
-        const int wlog = js == 4 ? 4 : (js == 2 ? 5 : 6);
-        const int il = lane & ((1 << wlog) - 1);
-        const int ph = lane >> wlog;
-        const bool active = il < tk.n_i;
-        const int i = tk.i_off + (active ? il : 0);
+        // lane -> (list, i slot, j phase).  A plain task runs js lanes per
+        // i-particle (js = 4, 2 for chunks of <= 16, <= 32) taking alternate
+        // j-particles; a paired task runs its two chunks side by side, one
+        // lane per i-particle, each lane over its own list.
+        const bool paired = tk.n_i2 > 0;
+        int jlog = 0, il = lane, ph = 0;  // js = 1 << jlog
+        const bool second = paired && lane >= tk.n_i;
+        if (paired) {
+            il = second ? lane - tk.n_i : lane;
+        } else {
+            jlog = tk.n_i <= 16 ? 2 : (tk.n_i <= 32 ? 1 : 0);
+            il = lane & (63 >> jlog);
+            ph = lane >> (6 - jlog);
+        }
+        const int js = 1 << jlog;
+        const bool active = il < (second ? tk.n_i2 : tk.n_i);
+        const int i = (second ? tk.i_off2 : tk.i_off) + (active ? il : 0);
 
         const float px = a.xi[i], py = a.yi[i], pz = a.zi[i];
         const float pe = (KIND == 0) ? (a.eps2i ? a.eps2i[i] : a.eps2_all) : 0.f;
 
         float tx = 0.f, ty = 0.f, tz = 0.f, tp = 0.f;
-        const int nj = tk.n_j;
+        const int nj = paired ? max(tk.n_j, tk.n_j2) : tk.n_j;
         const int ntiles = (nj + 63) >> 6;
 
-        float4 pre;
+        // j records of a tile, one per lane (and one of the second list);
+        // entries past a list's end are zero-mass records far away, whose
+        // terms are exactly zero even for zero softening
+        float4 pre, pre2;
         auto load = [&](int tile) {
-            const int j = tk.j_off + tile * 64 + lane;
-            pre = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (tile * 64 + lane < nj) pre = make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j]);
+            const int jj = tile * 64 + lane;
+            pre = make_float4(kFar, kFar, kFar, 0.f);
+            if (jj < tk.n_j) {
+                const int j = tk.j_off + jj;
+                pre = make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j] * mscale);
+            }
+            if (paired) {
+                pre2 = make_float4(kFar, kFar, kFar, 0.f);
+                if (jj < tk.n_j2) {
+                    const int j = tk.j_off2 + jj;
+                    pre2 = make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j] * mscale);
+                }
+            }
         };
+        auto store = [&](int b) {
+            jt[wave][b][0][lane] = pre;
+            if (paired) jt[wave][b][1][lane] = pre2;
+        };
+        const int list = second ? 1 : 0;  // this lane's list
         load(0);
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): i-particle and first tile loads
-        {
-            float4 v = pre;
-            v.w *= mscale;
-            jt[wave][0][lane] = v;
+        // vmcnt(0): the i-particle and first-tile loads.  Waiting here keeps
+        // the compiler from placing a full wait inside the pair loop, where
+        // it would also wait for the prefetch of the next tile.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        if (NB == 2) {
+            store(0);
+            wave_sync();
         }
-        wave_sync();
-
         for (int tile = 0; tile < ntiles; ++tile) {
-            const int cur = tile & 1;
+            const int cur = NB == 2 ? (tile & 1) : 0;
+            if (NB == 1) {
+                wave_sync();  // the previous tile's reads are done
+                store(0);
+                wave_sync();
+            }
             if (tile + 1 < ntiles) load(tile + 1);
+            const float4 *src = jt[wave][cur][list];
             const int cnt = min(64, nj - tile * 64);
-            // every lane runs the same trip count; records past cnt are the
-            // zero-mass padding written above
-            const int trips = (cnt + js - 1) / js;
+            // every lane runs the same trip count; records past cnt are padding
+            const int trips = (cnt + js - 1) >> jlog;
             float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;
             if (trips == 64) {
 #pragma unroll 4
                 for (int it = 0; it < 64; ++it) {
-                    const float4 p = jt[wave][cur][it];
+                    const float4 p = src[it];
                     if (KIND == 0)
                         newton_pair<REFINE, GUARD, PHI, ALT>(p, px, py, pz, pe, sx, sy, sz, sp);
                     else
-                        table_pair<ALT>(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask, sx, sy,
-                                   sz);
+                        table_pair<ALT>(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask, sx,
+                                        sy, sz);
                 }
             } else {
 #pragma unroll 2
                 for (int it = 0; it < trips; ++it) {
-                    const float4 p = jt[wave][cur][it * js + ph];
+                    const float4 p = src[it * js + ph];
                     if (KIND == 0)
                         newton_pair<REFINE, GUARD, PHI, ALT>(p, px, py, pz, pe, sx, sy, sz, sp);
                     else
-                        table_pair<ALT>(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask, sx, sy,
-                                   sz);
+                        table_pair<ALT>(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask, sx,
+                                        sy, sz);
                 }
             }
             tx += sx;
             ty += sy;
             tz += sz;
             tp += sp;
-            if (tile + 1 < ntiles) {
-                float4 v = pre;
-                v.w *= mscale;
-                jt[wave][cur ^ 1][lane] = v;
+            if (NB == 2) {
+                if (tile + 1 < ntiles) store(cur ^ 1);
+                wave_sync();
             }
-            wave_sync();
         }
 
         // combine the j phases of each i-particle
@@ -185,17 +239,16 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a)
 }
 
 // Runs after k_batch on the same stream: adds the partial sums of every split
-// chunk in part order (deterministic) and writes its outputs, and resets the
-// task counter for the next launch.  One wave per split chunk.
+// chunk in part order (deterministic) and writes its outputs.  One wave per
+// split chunk.
 __global__ void __launch_bounds__(64) k_combine(CombineArgs a)
 {
     const int lane = threadIdx.x;
-    if (blockIdx.x == 0 && lane == 0) a.queue[0] = 0u;
     if ((int)blockIdx.x >= a.n_chunks) return;
     const SplitChunk ch = a.chunks[blockIdx.x];
     if (lane >= ch.n_i) return;
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 *p = a.partial + (size_t)ch.slot * 64 + lane;
+    const float4 *p = a.partial + (size_t)ch.slot * 64 + ch.lane0 + lane;
     for (int q = 0; q < ch.n_parts; ++q) {
         const float4 v = p[(size_t)q * 64];
         s.x += v.x;
@@ -254,14 +307,19 @@ hipError_t launch(BatchKernel k, const BatchArgs &a0, size_t lds, int num_cu, hi
 {
     if (a0.n_tasks <= 0) return hipSuccess;
     BatchArgs a = a0;
-    const int blocks = num_cu * resident_blocks(k, lds);
+    // one resident wave of workgroups, or fewer when there are fewer tasks
+    // than waves (then every wave runs at most one task and the counter is
+    // never touched)
+    const int cap = num_cu * resident_blocks(k, lds);
+    // at least one workgroup per task sublist
+    const int blocks = std::max(a.nq, std::min(cap, (a.n_tasks + kWaves - 1) / kWaves));
     a.n_waves = blocks * kWaves;
     hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    CombineArgs c{a.n_chunks, a.chunks, a.partial, a.queue, a.ax, a.ay, a.az,
-                  phi ? a.phi : nullptr};
-    hipLaunchKernelGGL(k_combine, dim3(std::max(1, a.n_chunks)), dim3(64), 0, s, c);
+    if (a.n_chunks == 0) return hipSuccess;
+    CombineArgs c{a.n_chunks, a.chunks, a.partial, a.ax, a.ay, a.az, phi ? a.phi : nullptr};
+    hipLaunchKernelGGL(k_combine, dim3(a.n_chunks), dim3(64), 0, s, c);
     return hipGetLastError();
 }
 

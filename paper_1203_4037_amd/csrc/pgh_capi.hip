@@ -19,8 +19,10 @@ struct pgh_plan {
     int ni_total, nj_total;
     long long interactions;
     int n_chunks, n_slots;  // chunks whose j-list is split, and their parts
-    Task *tasks;            // device, sorted by decreasing length
-    unsigned *queue;        // device, task counter reset by every launch
+    Task *tasks;            // device, sublist-major, each sublist longest first
+    int nq;                 // task sublists
+    int q_begin[kQueues + 1];
+    unsigned *queue;        // device, one counter per sublist, zero between launches
     float4 *partial;        // device, 64 partial sums per slot
     SplitChunk *chunks;     // device, the split chunks
     int n_jtasks;           // j-major tasks (adjoint of the masses)
@@ -480,35 +482,83 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
             total += std::max(1LL, (long long)(it.n_j + js - 1) / js);
         }
     }
-    // cut j-lists longer than half the average work of a resident wave
+    // Cut j-lists longer than an eighth of the average work of a resident
+    // wave, so each wave takes several tasks and the longest-first queue
+    // ends with short ones.  (Equal tasks of half a wave's work leave the
+    // last round of the queue mostly idle whenever the task count is just
+    // above a multiple of the wave count.)
     const int waves = std::max(1, batch_resident_waves(c->num_cu));
-    const long long part_iters = std::max(512LL, (total / waves / 2 + 63) / 64 * 64);
+    const long long part_iters = std::max(256LL, (total / waves / 8 + 63) / 64 * 64);
     std::vector<Task> tasks;
     std::vector<long long> cost;
     std::vector<SplitChunk> split;
     int n_slots = 0;
-    for (const Chunk &ch : chunks) {
-        const long long iters = (ch.n_j + ch.js - 1) / ch.js;
+    // Pair partly filled chunks: in order of j-list length, each takes the
+    // first later one (within a short window) whose i-particles fit beside
+    // its own in 64 lanes, when one wavefront running the longer list costs
+    // fewer lane-iterations than the two apart.  A pair is cut along j like
+    // any long list (both lists at the same offsets).
+    struct Work {
+        Chunk a, b;  // b.n_i == 0: a single chunk
+    };
+    std::vector<Work> work;
+    {
+        auto lane_iters = [](const Chunk &ch) {
+            return 64LL * std::max(1LL, (long long)(ch.n_j + ch.js - 1) / ch.js);
+        };
+        std::vector<char> taken(chunks.size(), 0);
+        std::vector<int> cand;
+        for (size_t k = 0; k < chunks.size(); ++k)
+            if (chunks[k].n_i < 64 && chunks[k].n_j > 0) cand.push_back((int)k);
+        std::stable_sort(cand.begin(), cand.end(),
+                         [&](int a, int b) { return chunks[a].n_j < chunks[b].n_j; });
+        constexpr size_t kWindow = 64;
+        for (size_t u = 0; u < cand.size(); ++u) {
+            const Chunk &a = chunks[cand[u]];
+            if (taken[cand[u]]) continue;
+            for (size_t v = u + 1; v < std::min(cand.size(), u + 1 + kWindow); ++v) {
+                const Chunk &b = chunks[cand[v]];
+                if (taken[cand[v]] || a.n_i + b.n_i > 64) continue;
+                if (64LL * std::max(a.n_j, b.n_j) >= lane_iters(a) + lane_iters(b)) continue;
+                taken[cand[u]] = taken[cand[v]] = 1;
+                work.push_back({a, b});
+                break;
+            }
+        }
+        for (size_t k = 0; k < chunks.size(); ++k)
+            if (!taken[k]) work.push_back({chunks[k], Chunk{0, 0, 0, 0, 1}});
+    }
+    for (const Work &w : work) {
+        const Chunk &ch = w.a;
+        const bool pair = w.b.n_i > 0;
+        const int js = pair ? 1 : ch.js;
+        const int njm = pair ? std::max(ch.n_j, w.b.n_j) : ch.n_j;
+        const long long iters = (njm + js - 1) / js;
         int parts = (int)std::max(1LL, (iters + part_iters - 1) / part_iters);
-        long long per = ch.n_j;
+        long long per = njm;
         if (parts > 1) {
             // equal parts, each a multiple of 64 j-particles except the last
-            per = (ch.n_j + parts - 1) / parts;
+            per = (njm + parts - 1) / parts;
             per = (per + 63) / 64 * 64;
-            parts = (int)((ch.n_j + per - 1) / per);
+            parts = (int)((njm + per - 1) / per);
         }
+        auto cut = [&](int n_j, int q) {
+            return (int)std::max(0LL, std::min<long long>(per, n_j - q * per));
+        };
         if (parts <= 1) {
-            tasks.push_back({ch.i_off, ch.n_i, ch.j_off, ch.n_j, 0, 1, 0, 0});
+            tasks.push_back({ch.i_off, ch.n_i, ch.j_off, ch.n_j, 0, 1, 0, w.b.i_off, w.b.n_i,
+                             w.b.j_off, w.b.n_j, 0});
             cost.push_back(std::max(1LL, iters));
             continue;
         }
         for (int q = 0; q < parts; ++q) {
-            const int j0 = ch.j_off + (int)(q * per);
-            const int nj = (int)std::min<long long>(per, ch.n_j - q * per);
-            tasks.push_back({ch.i_off, ch.n_i, j0, nj, q, parts, n_slots, 0});
-            cost.push_back((nj + ch.js - 1) / ch.js);
+            const int nja = cut(ch.n_j, q), njb = pair ? cut(w.b.n_j, q) : 0;
+            tasks.push_back({ch.i_off, ch.n_i, ch.j_off + (int)(q * per), nja, q, parts, n_slots,
+                             w.b.i_off, w.b.n_i, w.b.j_off + (int)(q * per), njb, 0});
+            cost.push_back((std::max(nja, njb) + js - 1) / js);
         }
-        split.push_back({ch.i_off, ch.n_i, n_slots, parts});
+        split.push_back({ch.i_off, ch.n_i, n_slots, parts, 0});
+        if (pair) split.push_back({w.b.i_off, w.b.n_i, n_slots, parts, ch.n_i});
         n_slots += parts;
     }
     const int n_chunks = (int)split.size();
@@ -516,14 +566,31 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     std::vector<int> idx(tasks.size());
     for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    std::vector<Task> sorted(tasks.size());
-    for (size_t k = 0; k < idx.size(); ++k) sorted[k] = tasks[idx[k]];
+    // Deal the longest-first list into nq sublists, a group of kBatchWaves
+    // consecutive tasks at a time, round-robin: each sublist stays longest
+    // first with an equal share of every size class, and workgroup b (which
+    // serves sublist b mod nq) takes tasks 4b .. 4b+3 of the whole list in
+    // its first round, one of similar length per SIMD.
+    const int nq = (int)std::min<size_t>(
+        kQueues, std::max<size_t>(1, (idx.size() + kBatchWaves - 1) / kBatchWaves));
+    std::vector<Task> sorted;
+    sorted.reserve(tasks.size());
+    int q_begin[kQueues + 1] = {0};
+    for (int q = 0; q < nq; ++q) {
+        q_begin[q] = (int)sorted.size();
+        for (size_t g0 = (size_t)q * kBatchWaves; g0 < idx.size(); g0 += (size_t)nq * kBatchWaves)
+            for (size_t k = g0; k < std::min(idx.size(), g0 + kBatchWaves); ++k)
+                sorted.push_back(tasks[idx[k]]);
+    }
+    q_begin[nq] = (int)sorted.size();
 
     pgh_plan *p = new (std::nothrow) pgh_plan;
     if (!p) return fail(c, PGH_ENOMEM, "out of host memory");
     p->owner = c;
     p->n_items = n_items;
     p->n_tasks = (int)sorted.size();
+    p->nq = nq;
+    std::copy(q_begin, q_begin + kQueues + 1, p->q_begin);
     p->ni_total = ni_total;
     p->nj_total = nj_total;
     p->interactions = inter;
@@ -540,7 +607,8 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     for (int t : order) {
         const pgh_item &it = items[t];
         for (int s0 = 0; s0 < it.n_j; s0 += 64)
-            jt.push_back({it.j_off + s0, std::min(64, it.n_j - s0), it.i_off, it.n_i, 0, 1, 0, 0});
+            jt.push_back({it.j_off + s0, std::min(64, it.n_j - s0), it.i_off, it.n_i, 0, 1, 0, 0, 0,
+                          0, 0, 0});
     }
     std::stable_sort(jt.begin(), jt.end(), [](const Task &a, const Task &b) { return a.n_j > b.n_j; });
     p->n_jtasks = (int)jt.size();
@@ -550,7 +618,8 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
         delete p;
         return fail(c, code, msg);
     };
-    if (hipMalloc((void **)&p->queue, 2 * sizeof(unsigned)) != hipSuccess)
+    const size_t queue_bytes = (size_t)kQueues * kQueueStride * sizeof(unsigned);
+    if (hipMalloc((void **)&p->queue, queue_bytes) != hipSuccess)
         return cleanup(PGH_ENOMEM, "hipMalloc(queue) failed");
     if (!sorted.empty() &&
         hipMalloc((void **)&p->tasks, sorted.size() * sizeof(Task)) != hipSuccess)
@@ -569,7 +638,7 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
         (!jt.empty() && hipMemcpyAsync(p->jtasks, jt.data(), jt.size() * sizeof(Task),
                                        hipMemcpyHostToDevice, c->stream) != hipSuccess))
         return cleanup(PGH_EHIP, "uploading the plan failed");
-    if (hipMemsetAsync(p->queue, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
+    if (hipMemsetAsync(p->queue, 0, queue_bytes, c->stream) != hipSuccess ||
         (n_chunks > 0 &&
          hipMemcpyAsync(p->chunks, split.data(), split.size() * sizeof(SplitChunk),
                         hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
@@ -613,6 +682,8 @@ BatchArgs batch_args(pgh_ctx *c, const pgh_plan *p)
     BatchArgs a{};
     a.n_tasks = p->n_tasks;
     a.tasks = p->tasks;
+    a.nq = p->nq;
+    std::copy(p->q_begin, p->q_begin + kQueues + 1, a.q_begin);
     a.queue = p->queue;
     a.partial = p->partial;
     a.n_chunks = p->n_chunks;
@@ -759,9 +830,6 @@ int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const fl
     if (p->nj_total > 0 && (!xj || !yj || !zj || !mj))
         return fail(c, PGH_EINVAL, "NULL j-particle array");
     DeviceGuard g(c->device);
-    const int K = 1 << (c->tab_E + c->tab_F);
-    if (gtable) PGH_HIP(c, launch_fill_zero(2 * K, gtable, nullptr, nullptr, nullptr, c->stream));
-    if (gmj) PGH_HIP(c, launch_fill_zero(p->nj_total, gmj, nullptr, nullptr, nullptr, c->stream));
     TableBwdArgs A{};
     A.b = batch_args(c, p);
     A.b.xi = xi, A.b.yi = yi, A.b.zi = zi;
@@ -776,7 +844,8 @@ int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const fl
     A.wx = wx, A.wy = wy, A.wz = wz;
     A.gtable = gtable;
     A.gmj = gmj;
-    PGH_HIP(c, launch_table_batch_bwd(A, p->jtasks, p->n_jtasks, p->jqueue, c->num_cu, c->stream));
+    PGH_HIP(c, launch_table_batch_bwd(A, p->jtasks, p->n_jtasks, p->nj_total, p->jqueue, c->num_cu,
+                                      c->stream));
     return PGH_OK;
 }
 

@@ -45,22 +45,39 @@ struct TableArgs {
 // One wavefront task of a batch plan: up to 64 i-particles against one part
 // of one j-list.  A chunk whose j-list is cut into n_parts > 1 parts owns
 // n_parts consecutive slots of 64 partial sums starting at `slot`.
+// A paired task (n_i2 > 0) also carries a second, unsplit chunk: lanes
+// [0, n_i) take the first list and lanes [n_i, n_i + n_i2) the second
+// (i_off2, j_off2, n_j2), one lane per i-particle, so two partly filled
+// chunks share one wavefront.
 struct Task {
     int i_off, n_i, j_off, n_j;
-    int part, n_parts, slot, pad;
+    int part, n_parts, slot;
+    int i_off2, n_i2, j_off2, n_j2;
+    int pad;
 };
 
-// A chunk of i-particles whose j-list is split into parts.
+// A chunk of i-particles whose j-list is split into parts; its partial sums
+// sit in lanes [lane0, lane0 + n_i) of its slots (lane0 > 0 for the second
+// chunk of a paired task).
 struct SplitChunk {
-    int i_off, n_i, slot, n_parts;
+    int i_off, n_i, slot, n_parts, lane0;
 };
 
 // Arguments of the persistent batched kernels.
+// Task queues of a plan: the longest-first task list is dealt round-robin
+// into kQueues sublists, each with its own counter on its own 128-byte line
+// (one device-scope counter saturates at some tens of pops per microsecond).
+constexpr int kQueues = 16;
+constexpr int kQueueStride = 32;  // unsigned words between counters
+constexpr int kBatchWaves = 4;    // wave64s per workgroup of the persistent kernels
+
 struct BatchArgs {
     int n_tasks;
-    const Task *tasks;
-    unsigned *queue;  // [0] = next task, [1] = finished waves (both reset by the launch)
-    int n_waves;      // waves in the grid (set by the launcher)
+    const Task *tasks;  // sublist-major: sublist q is tasks[q_begin[q] .. q_begin[q+1])
+    int nq;             // sublists in use (<= kQueues, <= n_tasks)
+    int q_begin[kQueues + 1];
+    unsigned *queue;    // counter of sublist q at queue[q * kQueueStride]; zero between launches
+    int n_waves;        // waves in the grid (set by the launcher)
     int n_chunks;     // split chunks
     const SplitChunk *chunks;
     float4 *partial;  // 64 partial sums per slot of a split chunk
@@ -78,7 +95,6 @@ struct CombineArgs {
     int n_chunks;
     const SplitChunk *chunks;
     const float4 *partial;
-    unsigned *queue;
     float *ax, *ay, *az, *phi;
 };
 
@@ -87,11 +103,6 @@ struct TableBwdArgs {
     const float *wx, *wy, *wz;
     float *gtable;  // 2K floats
     float *gmj;
-};
-
-// Variant descriptions for the tuner.
-struct VariantInfo {
-    const char *name;
 };
 
 // Kernel launchers (defined in the .hip files).
@@ -145,7 +156,9 @@ hipError_t launch_newton_bwd_i(int ni, const float4 *irec, int nj, const float4 
 hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 *irec,
                                bool refine, float *gx, float *gy, float *gz, float *gm, int S,
                                float *part, hipStream_t s);
+// Zeroes gtable / gmj and `queue`, then runs both adjoint passes in one
+// persistent launch that takes tasks from `queue`.
 hipError_t launch_table_batch_bwd(const TableBwdArgs &a, const Task *jtasks, int n_jtasks,
-                                  unsigned *jqueue, int num_cu, hipStream_t s);
+                                  int nj_total, unsigned *queue, int num_cu, hipStream_t s);
 
 }  // namespace pgh

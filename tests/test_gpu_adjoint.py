@@ -209,3 +209,35 @@ def test_autograd_table_force(pgh, ctx):
     ax, ay, az = pgh.table_force_batch(plan, E, F, rcut, tab, xr, di[1], di[2], *dj, mj)
     with pytest.raises(NotImplementedError):
         ax.sum().backward()
+
+
+def test_table_adjoint_partial_outputs_and_repeats(pgh, ctx):
+    """Asking for only the table gradient, or only the mass gradient, gives
+    what the combined call gives (up to the order of float atomics), and
+    repeated calls on one plan restart from zero."""
+    import torch
+    n = 16384
+    x, y, z = synth.uniform_box(n, 21)
+    m = synth.equal_masses(n)
+    rcut, eps, E, F = 1.0 / 32, 1.0 / 32 / 15, 4, 6
+    s = synth.cell_grid_items(x, y, z, m, ncell=32, block=4)
+    table = ctx.build_table(E, F, rcut, eps=eps)
+    w = synth.weights(n, 22)
+    plan = ctx.plan(s.items, n, s.xj.size)
+    di = to_dev(s.xi, s.yi, s.zi, *w)
+    dj = to_dev(s.xj, s.yj, s.zj, s.mj)
+    gt = torch.empty(table.size, device="cuda")
+    gm = torch.empty(s.xj.size, device="cuda")
+    both = []
+    for _ in range(2):
+        pgh.pgh_batch_table_bwd(ctx.h, plan.h, di[0], di[1], di[2], *dj, di[3], di[4], di[5], gt, gm)
+        both.append((to_host(gt)[0], to_host(gm)[0]))
+    gt2 = torch.full((table.size,), 7.0, device="cuda")
+    gm2 = torch.full((s.xj.size,), 7.0, device="cuda")
+    pgh.pgh_batch_table_bwd(ctx.h, plan.h, di[0], di[1], di[2], *dj, di[3], di[4], di[5], gt2, None)
+    pgh.pgh_batch_table_bwd(ctx.h, plan.h, di[0], di[1], di[2], *dj, di[3], di[4], di[5], None, gm2)
+    rt, rm, at, am = oracle.lut_bwd_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, *w,
+                                          E, F, float(np.float32(rcut)), table, scales=True)
+    for g_t, g_m in both + [(to_host(gt2)[0], to_host(gm2)[0])]:
+        _table_gate(g_t, rt, at, E, F, "gtable")
+        _gate(g_m, rm, am, "gmj")

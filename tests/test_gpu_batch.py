@@ -106,6 +106,30 @@ def test_group_size_edges_and_split_lists(pgh, ctx, variant):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("n_items", [1, 3, 17, 40])
+def test_few_tasks_and_repeats(pgh, ctx, n_items):
+    """Plans with fewer tasks than task sublists, and a few more; each run
+    twice on the same plan with identical bits (every sublist counter puts
+    itself back to zero)."""
+    import torch
+    n = 4000
+    x, y, z = synth.plummer(n, 61)
+    m = synth.equal_masses(n)
+    rng = np.random.default_rng(n_items)
+    items, i_off = [], 0
+    for k in range(n_items):
+        ni = int(rng.integers(1, 90))
+        items.append((i_off, ni, int(rng.integers(0, n - 3000)), int(rng.integers(0, 3000))))
+        i_off += ni
+    s = synth.ItemSet(items=np.array(items, np.int32), xi=x, yi=y, zi=z, xj=x, yj=y, zj=z, mj=m,
+                      jsrc=None, iperm=None)
+    plan, di, dj, out, got = _newton_case(pgh, ctx, s, 1e-2)
+    out2 = [torch.full((n,), 12345.0, device="cuda") for _ in range(4)]
+    plan.newton(*di, *dj, out=out2)
+    for a, b in zip(got, to_host(*out2)):
+        assert np.array_equal(a, b)
+
+
 def test_plan_validation(pgh, ctx):
     with pytest.raises(pgh.PGHError) as e:
         ctx.plan([[0, 10, 0, 5], [5, 10, 0, 5]], 100, 100)  # overlapping i-ranges

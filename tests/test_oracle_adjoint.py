@@ -97,3 +97,35 @@ def test_table_gradients_are_exact_for_a_linear_loss():
         q = mj.copy(); q[j] -= 0.25
         fd = (loss(t, p) - loss(t, q)) / 0.5
         assert fd == pytest.approx(gm[j], rel=1e-9, abs=1e-12 * np.abs(gm).max())
+
+
+def test_error_scales_bound_the_sums_and_see_inside_the_dot_product():
+    """The absolute-term scales used by the GPU error gates bound their sums
+    (triangle inequality), and they stay of the size of the products even
+    when w_i . d cancels: a weight perpendicular to d gives w . d = 0 but a
+    scale of |w_x d_x| + |w_y d_y| + |w_z d_z|."""
+    xi, xj, mj, e2, w = _setup(ni=6, nj=8, seed=11)
+    r = oracle.newton_bwd(*xi, e2, *xj, mj, *w, scales=True)
+    gi, gj, gm, si, sj, sm = np.stack(r[0:3]), np.stack(r[3:6]), r[6], r[7], r[8], r[9]
+    assert np.all(np.linalg.norm(gi, axis=0) <= si * (1 + 1e-12))
+    assert np.all(np.linalg.norm(gj, axis=0) <= sj * (1 + 1e-12))
+    assert np.all(np.abs(gm) <= sm * (1 + 1e-12))
+    # one i, one j; w perpendicular to d = (1, 1, 0): w = (1, -1, 0)
+    one = [np.array([0.0]) for _ in range(3)]
+    r = oracle.newton_bwd(*one, np.array([0.0]), np.array([1.0]), np.array([1.0]),
+                          np.array([0.0]), np.array([2.0]), np.array([1.0]), np.array([-1.0]),
+                          np.array([0.0]), scales=True)
+    rho3 = 2.0 ** -1.5
+    assert r[6][0] == 0.0 and r[9][0] == pytest.approx(2 * rho3, rel=1e-14)
+    # table adjoint
+    E, F, rcut, eps = 3, 3, 0.3, 0.02
+    t = oracle.table_build(E, F, rcut, oracle.SHAPE_S2PP, eps).astype(np.float64)
+    n = 40
+    x, y, z = [a.astype(np.float64) for a in synth.uniform_box(n, 8, box=0.5)]
+    m = np.linspace(0.5, 1.5, n)
+    wt = [np.random.default_rng(4).standard_normal(n) for _ in range(3)]
+    items = np.array([[0, 20, 0, 40], [20, 20, 10, 25]], np.int32)
+    gt, gmj, at, am = oracle.lut_bwd_items(items, x, y, z, x, y, z, m, *wt, E, F, rcut, t,
+                                           scales=True)
+    assert np.all(np.abs(gt) <= at * (1 + 1e-12))
+    assert np.all(np.abs(gmj) <= am * (1 + 1e-12))
