@@ -30,6 +30,7 @@
 // the same lists.
 #include <algorithm>
 
+#include "pairs.h"
 #include "pgh_internal.h"
 
 namespace pgh {
@@ -391,8 +392,8 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
     float *gt = dyn + 2 * K;       // 2K gradient accumulators: table tasks
     __shared__ float4 buf[4][128];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (n_m > 0) table_to_lds<false>(stab, a.table, K, 0u);
     for (int k = threadIdx.x; k < K; k += 256) {
-        if (n_m > 0) stab[k] = a.table[k];
         gt[2 * k] = 0.f;
         gt[2 * k + 1] = 0.f;
     }

@@ -66,21 +66,6 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
     const int wave = threadIdx.x >> 6;
     const float mscale = (KIND == 0 && REFINE) ? -0.5f : 1.0f;
 
-    unsigned shift = 0, nbits = 0, hmask = 0;
-    if (KIND == 1) {
-        const int K = 1 << (a.E + a.F);
-        shift = 23u - (unsigned)a.F;
-        table_to_lds<ALT>(stab, a.table, K, shift);
-        nbits = (unsigned)(a.E + a.F);
-        hmask = ~((1u << shift) - 1u);
-        __syncthreads();  // the only workgroup barrier: waves are independent after it
-    }
-
-    // The first round of tasks is assigned statically (wave w takes task w),
-    // so a launch with no more tasks than waves issues no atomic at all; the
-    // later tasks come from the counter, one atomic per task, taken at the
-    // start of the previous task so its latency overlaps that task.  (All
-    // waves hitting one counter at once serialises at the memory side.)
     // this workgroup serves task sublist q with the other workgroups b = q mod nq
     const unsigned nq = (unsigned)a.nq;
     const unsigned q = blockIdx.x % nq;
@@ -91,8 +76,28 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
     const bool dynamic = n_tasks > nw_q;
     // (readfirstlane: the index is wave-uniform, so task fields load as scalars)
     unsigned t = __builtin_amdgcn_readfirstlane((blockIdx.x / nq) * kWaves + wave);
+    // the first task's fields are fetched before the table copy, whose
+    // latency they share
+    Task tk_next{};
+    if (t < n_tasks) tk_next = tasks[t];
+
+    unsigned shift = 0, nbits = 0, hmask = 0;
+    if (KIND == 1) {
+        const int K = 1 << (a.E + a.F);
+        shift = 23u - (unsigned)a.F;
+        table_to_lds<ALT>(stab, a.table, K, shift);
+        nbits = (unsigned)(a.E + a.F);
+        hmask = ~((1u << shift) - 1u);
+        __syncthreads();  // the only workgroup barrier: waves are independent after it
+    }
+
+    // The first round of a sublist is assigned statically (its w-th wave
+    // takes its w-th task), so a sublist with no more tasks than waves issues
+    // no atomic at all; later tasks come from the sublist's counter, one
+    // atomic per task, taken at the start of the previous task so that its
+    // latency overlaps that task.
     while (t < n_tasks) {
-        const Task tk = tasks[t];
+        const Task tk = tk_next;
         unsigned tn = n_tasks;
         if (dynamic && lane == 0) {
             const unsigned k =
@@ -235,6 +240,7 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
             a.partial[(size_t)(tk.slot + tk.part) * 64 + lane] = make_float4(tx, ty, tz, tp);
         }
         t = __builtin_amdgcn_readfirstlane(tn);
+        if (t < n_tasks) tk_next = tasks[t];
     }
 }
 

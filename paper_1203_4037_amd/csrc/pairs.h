@@ -94,18 +94,32 @@ __device__ __forceinline__ void table_pair(const float4 p, float px, float py, f
 
 // Copies the 2^(E+F) (G0, G1) table into LDS (all threads of the
 // workgroup), converting to (H, G1) for the HT form.  shift = 23 - F.
+// Four loads per thread are in flight at once (a table of 1024 entries is
+// one round for 256 threads), so the copy costs one memory latency.
 template <bool HT>
 __device__ __forceinline__ void table_to_lds(float2 *stab, const float2 *__restrict__ table, int K,
                                              unsigned shift)
 {
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-        float2 e = table[k];
-        if (HT) {
-            // node s_k: the FP32 bits of 2.0 stepped by k units of the F-th fraction bit
-            const float sk = __uint_as_float(0x40000000u + ((unsigned)k << shift));
-            e.x = __builtin_fmaf(-e.y, sk, e.x);
+    const int nt = blockDim.x;
+    for (int k0 = threadIdx.x; k0 < K; k0 += 4 * nt) {
+        float2 e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * nt;
+            e[u] = k < K ? table[k] : make_float2(0.f, 0.f);
         }
-        stab[k] = e;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * nt;
+            if (k < K) {
+                if (HT) {
+                    // node s_k: the FP32 bits of 2.0 stepped by k units of the F-th fraction bit
+                    const float sk = __uint_as_float(0x40000000u + ((unsigned)k << shift));
+                    e[u].x = __builtin_fmaf(-e[u].y, sk, e[u].x);
+                }
+                stab[k] = e[u];
+            }
+        }
     }
 }
 

@@ -488,7 +488,7 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     // last round of the queue mostly idle whenever the task count is just
     // above a multiple of the wave count.)
     const int waves = std::max(1, batch_resident_waves(c->num_cu));
-    const long long part_iters = std::max(256LL, (total / waves / 8 + 63) / 64 * 64);
+    const long long part_iters = std::max(512LL, (total / waves / 8 + 63) / 64 * 64);
     std::vector<Task> tasks;
     std::vector<long long> cost;
     std::vector<SplitChunk> split;
