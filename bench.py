@@ -36,20 +36,20 @@ TABLE_FLOPS = 20  # per interaction, this project's count of the FP32 ops of the
 # HBM traffic of the headline kernel, from two rocprofv3 --pmc runs of
 # `bench.py --no-extras --no-cpu --copy-calibration 256` (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads for a
-# 256 MiB device-to-device copy (FETCH_SIZE 131093 KiB -> x2.0, WRITE_SIZE
+# 256 MiB device-to-device copy (FETCH_SIZE 131094 KiB -> x2.0, WRITE_SIZE
 # 262144 KiB -> x1.0).  Valid only for the variant and kernel sources the
 # counters were taken on; otherwise the bench reports traffic as null.
 MEASURED_TRAFFIC = {
-    "variant": "ki=1 jt=256 u=8",
+    "variant": "ki=1 jt=256 u=8", "rsqrt_refine": 0,
     "sources_sha256": "a59cb5971cb6553d9a7ed28e92d2f4de7b3fd7ab0566d7e8324173ac98b008b3",
-    "fetch_kib": 22363, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
+    "fetch_kib": 22719, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
 }
 KERNEL_SOURCES = ("paper_1203_4037_amd/csrc/newton.hip", "paper_1203_4037_amd/csrc/pairs.h")
 
 
-def measured_traffic(variant_name):
+def measured_traffic(variant_name, refine):
     """HBM bytes per launch of the headline kernel, or None when the counters
-    were taken on another variant or on other kernel sources."""
+    were taken on another variant, rsqrt mode or kernel sources."""
     import hashlib
     h = hashlib.sha256()
     root = os.path.dirname(os.path.abspath(__file__))
@@ -57,7 +57,8 @@ def measured_traffic(variant_name):
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
     t = MEASURED_TRAFFIC
-    if variant_name != t["variant"] or h.hexdigest() != t["sources_sha256"]:
+    if (variant_name != t["variant"] or refine != t["rsqrt_refine"]
+            or h.hexdigest() != t["sources_sha256"]):
         return None
     return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0
 
@@ -172,9 +173,10 @@ def newton_allpairs(torch, pgh, synth, args):
     kern_ms = timer.mean_ms()
     variant = pgh.pgh_get_variant(ctx.h, pgh.PGH_FAMILY_NEWTON_ALLPAIRS)
     name = pgh.pgh_variant_name(pgh.PGH_FAMILY_NEWTON_ALLPAIRS, variant) if variant >= 0 else "default"
+    refine = ctx.refine
     ctx.close()
     return {"n": n, "x": (x, y, z, m), "sec": sec, "kern_ms": kern_ms, "variant": variant,
-            "variant_name": name, "autotuned": tuned is not None}
+            "variant_name": name, "autotuned": tuned is not None, "refine": refine}
 
 
 REPLAYS = {"override": 0}
@@ -442,10 +444,11 @@ def main():
         "config": {"workload": f"newton_allpairs_plummer_N{n}_eps0.01", "n_i": n, "n_j": n,
                    "eps": 0.01, "seed": 102, "interactions_per_step": inter,
                    "parallelism": "single_gpu", "kernel_variant": r["variant_name"],
-                   "autotuned": r["autotuned"]},
+                   "autotuned": r["autotuned"], "rsqrt_refine": r["refine"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(r["variant_name"]), "traffic_unit": "bytes/launch",
+                     "traffic": measured_traffic(r["variant_name"], r["refine"]),
+                     "traffic_unit": "bytes/launch",
                      "kernel": "k_newton_allpairs", "kernel_ms": r["kern_ms"],
                      "flops_per_interaction": NEWTON_FLOPS,
                      "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS},

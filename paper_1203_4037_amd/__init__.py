@@ -337,7 +337,7 @@ class Context:
         self.h = pgh_open(self.device)
         self.nj = 0
         self.table = None
-        self.refine = 1
+        self.refine = 0
 
     def close(self):
         if self.h:

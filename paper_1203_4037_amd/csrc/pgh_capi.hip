@@ -39,7 +39,7 @@ struct pgh_ctx {
     int jcap = 0;   // allocated j records
     int jfill = 0;  // records written so far (the upper bound of pgh_set_n)
     float4 *jmem = nullptr;
-    int refine = 1;
+    int refine = 0;  // Newton-Raphson step after v_rsq_f32 (pgh_set_rsqrt_refine)
     // look-up table
     int tab_set = 0;
     int tab_E = 0, tab_F = 0;
