@@ -102,9 +102,12 @@ class KernelTimer:
         self.b.record()
         self.pairs.append((self.a, self.b))
 
-    def mean_ms(self):
+    def times_ms(self):
         self.torch.cuda.synchronize()
-        return float(np.mean([a.elapsed_time(b) for a, b in self.pairs]))
+        return np.array([a.elapsed_time(b) for a, b in self.pairs])
+
+    def mean_ms(self):
+        return float(np.mean(self.times_ms()))
 
 
 def time_steps(torch, step, steps, warmup):
@@ -134,9 +137,49 @@ def cpu_baseline(x, y, z, m, eps, target_s):
     oracle.newton(x[idx], y[idx], z[idx], np.full(ns, e2, np.float32), x, y, z, m)
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    one = one_core_rate(x, y, z, m, eps, rate / max(1, threads))
     return {"value": ns * n / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle, {ns} evenly spaced i-particles x all {n} j-particles "
-                      f"({ns * n:.3e} interactions) in {dt:.1f} s"}
+                      f"({ns * n:.3e} interactions) in {dt:.1f} s",
+            "value_1core": one, "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def one_core_rate(x, y, z, m, eps, guess):
+    """The oracle's rate on one thread (a child process with OMP_NUM_THREADS=1),
+    on about 3 s of work; None when the child fails."""
+    import subprocess
+    import tempfile
+    n = x.size
+    ns = int(min(n, max(16, guess * 3.0 / n)))
+    with tempfile.TemporaryDirectory() as d:
+        np.savez(os.path.join(d, "in.npz"), x=x, y=y, z=z, m=m)
+        code = ("import sys, time, numpy as np, oracle\n"
+                f"a = np.load({os.path.join(d, 'in.npz')!r})\n"
+                "x, y, z, m = a['x'], a['y'], a['z'], a['m']\n"
+                f"ns, e2 = {ns}, np.float32({eps}) ** 2\n"
+                "idx = np.linspace(0, x.size - 1, ns).astype(np.int64)\n"
+                "t0 = time.perf_counter()\n"
+                "oracle.newton(x[idx], y[idx], z[idx], np.full(ns, e2, np.float32), x, y, z, m)\n"
+                "print(ns * x.size / (time.perf_counter() - t0))\n")
+        env = dict(os.environ, OMP_NUM_THREADS="1",
+                   PYTHONPATH=os.path.dirname(os.path.abspath(__file__)))
+        try:
+            out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                                 text=True, timeout=120)
+            return float(out.stdout.strip().splitlines()[-1])
+        except (subprocess.SubprocessError, ValueError, IndexError):
+            return None
 
 
 def newton_allpairs(torch, pgh, synth, args):
@@ -171,12 +214,14 @@ def newton_allpairs(torch, pgh, synth, args):
     timing["on"] = True
     sec = time_steps(torch, step, args.steps, 0)
     kern_ms = timer.mean_ms()
+    kern_all = timer.times_ms()
     variant = pgh.pgh_get_variant(ctx.h, pgh.PGH_FAMILY_NEWTON_ALLPAIRS)
     name = pgh.pgh_variant_name(pgh.PGH_FAMILY_NEWTON_ALLPAIRS, variant) if variant >= 0 else "default"
     refine = ctx.refine
     ctx.close()
     return {"n": n, "x": (x, y, z, m), "sec": sec, "kern_ms": kern_ms, "variant": variant,
-            "variant_name": name, "autotuned": tuned is not None, "refine": refine}
+            "variant_name": name, "autotuned": tuned is not None, "refine": refine,
+            "kern_ms_median": float(np.median(kern_all)), "kern_ms_min": float(np.min(kern_all))}
 
 
 REPLAYS = {"override": 0}
@@ -205,6 +250,27 @@ def graph_ms(torch, fn, reps):
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / reps
+
+
+def newton_small(torch, pgh, synth):
+    """Newton all-pairs at N = 1024 (Plummer, seed 101, eps = 1/64): a
+    launch-bound size; the set_xmj + calc_newton pair replayed from a graph."""
+    n = 1024
+    x, y, z = synth.plummer(n, 101)
+    m = synth.equal_masses(n)
+    dev = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+    ctx = pgh.Context(0)
+    ctx.set_eps_to_all(1.0 / 64)
+    out = [torch.empty(n, device="cuda") for _ in range(4)]
+
+    def call():
+        ctx.set_j(*dev)
+        pgh.pgh_calc_newton(ctx.h, n, dev[0], dev[1], dev[2], None, *out)
+
+    ms = graph_ms(torch, call, 200)
+    ctx.close()
+    return {"workload": "newton_allpairs_plummer_N1024_eps1/64", "ms_per_call": ms,
+            "interactions_per_s": n * n / (ms / 1e3)}
 
 
 def batched_newton(torch, pgh, synth):
@@ -262,12 +328,12 @@ def batched_table(torch, pgh, synth):
     x, y, z = synth.uniform_box(n, 103)
     m = synth.equal_masses(n)
     res = {}
-    for block in (4, 8):
+    for block, F in ((4, 6), (8, 6), (4, 5)):
         s = synth.cell_grid_items(x, y, z, m, ncell=64, block=block)
         di = [torch.from_numpy(a).cuda() for a in (s.xi, s.yi, s.zi)]
         dj = [torch.from_numpy(a).cuda() for a in (s.xj, s.yj, s.zj, s.mj)]
         ctx = pgh.Context(0)
-        ctx.build_table(4, 6, rcut, eps=1.0 / 1280)
+        ctx.build_table(4, F, rcut, eps=1.0 / 1280)
         plan = ctx.plan(s.items, n, s.xj.size)
         out = [torch.empty(n, device="cuda") for _ in range(3)]
         fam = pgh.PGH_FAMILY_TABLE_BATCH
@@ -282,8 +348,8 @@ def batched_table(torch, pgh, synth):
         ctx.close()
         rate = inter / (ms / 1e3)
         useful = useful_pairs(s, rcut)
-        res[f"block{block}"] = {
-            "workload": f"table_batched_cell_lists_N262144_E4F6_block{block}",
+        res[f"block{block}" + ("" if F == 6 else f"_F{F}")] = {
+            "workload": f"table_batched_cell_lists_N262144_E4F{F}_block{block}",
             "lists": int(len(s.items)), "interactions": inter, "useful_pairs": useful,
             "ms_per_launch": ms, "interactions_per_s": rate,
             "useful_pairs_per_s": useful / (ms / 1e3),
@@ -450,11 +516,13 @@ def main():
                      "traffic": measured_traffic(r["variant_name"], r["refine"]),
                      "traffic_unit": "bytes/launch",
                      "kernel": "k_newton_allpairs", "kernel_ms": r["kern_ms"],
+                     "kernel_ms_median": r["kern_ms_median"], "kernel_ms_min": r["kern_ms_min"],
                      "flops_per_interaction": NEWTON_FLOPS,
                      "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS},
     }
     if not args.no_extras:
-        ex = {"table_allpairs": table_allpairs(torch, pgh, synth),
+        ex = {"newton_small": newton_small(torch, pgh, synth),
+              "table_allpairs": table_allpairs(torch, pgh, synth),
               "newton_batched": batched_newton(torch, pgh, synth),
               "table_batched": batched_table(torch, pgh, synth),
               "adjoint_newton": adjoint_newton(torch, pgh, synth),

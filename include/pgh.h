@@ -265,6 +265,28 @@ PGH_API int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, 
                         const float *mj, const float *wx, const float *wy, const float *wz,
                         float *gtable, float *gmj);
 
+/* Removes the self term from raw potentials (Sec. 4.1): phi[i] += m[i] /
+ * eps_i for i in [0, n), with eps_i^2 from eps2_i (device, may be NULL: the
+ * context's pgh_set_eps_to_all value).  For i-particles that are also
+ * j-particles, whose raw potential from pgh_calc_newton contains -m_i/eps_i.
+ * Entries with eps_i = 0 are left as they are (the guarded kernel gives the
+ * zero-distance pair nothing).  m, phi: device float[n]; phi is updated in
+ * place.  Asynchronous on the context stream. */
+PGH_API int pgh_correct_self_potential(pgh_ctx *c, int n, const float *m, const float *eps2_i,
+                                       float *phi);
+
+/* Chains a table gradient to the node values (derived from the table
+ * definition of Sec. 3.4.1, where G1_k = (G0_{k+1} - G0_k) / (s_{k+1} - s_k)
+ * for k < K-1 and G1_{K-1} = 0).  gtable: device float[2K], the gradient with
+ * respect to the table entries as independent leaves, interleaved like the
+ * table (as pgh_batch_table_bwd writes it).  g0: device float[K], receives
+ *   g0_k = dL/dG0_k + dL/dG1_{k-1} / (s_k - s_{k-1}) - dL/dG1_k / (s_{k+1} - s_k),
+ * each term present where its index exists: the gradient with respect to
+ * the node values G0_k = f(r_k)/r_k when the slopes follow them.  (The
+ * builder fixes G0_{K-1} = 0; its entry is still written.)  K = 2^(E+F);
+ * PGH_ERANGE for E, F outside the table limits.  Asynchronous. */
+PGH_API int pgh_table_grad_chain(pgh_ctx *c, int E, int F, const float *gtable, float *g0);
+
 /* ---------------------------------------------------------------------- */
 /* Tuning                                                                   */
 /* ---------------------------------------------------------------------- */

@@ -63,6 +63,7 @@ def lib():
             "pgo_central_items": [l, P, P, P, P, P, P, P, P, i, P, P, P, P, P, P],
             "pgo_newton_bwd": [l, P, P, P, P, l, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P],
             "pgo_lut_bwd_items": [l, P, P, P, P, P, P, P, P, P, P, P, i, i, d, P, P, P, l, P, P],
+            "pgo_table_grad_chain": [i, i, P, P],
         }
         ret = {"pgo_s2_R": d, "pgo_s2pp_f": d, "pgo_shape_h": d, "pgo_smax": d,
                "pgo_node_s": d, "pgo_node_r": d, "pgo_lut_index": l, "pgo_lut_eval": d}
@@ -238,3 +239,12 @@ def lut_bwd_items(items, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, E, F, rcut, tab
                             _ptr(yj), _ptr(zj), _ptr(mj), _ptr(wx), _ptr(wy), _ptr(wz), E, F,
                             float(rcut), _ptr(t), _ptr(gt), _ptr(gm), xj.size, _ptr(ga), _ptr(gma))
     return (gt, gm, ga, gma) if scales else (gt, gm)
+
+
+def table_grad_chain(E, F, gtab):
+    """dL/dG0 (total) for a table whose slopes follow its node values, from
+    the gradient of the interleaved (G0, G1) entries."""
+    g = _f64(gtab)
+    out = np.zeros(1 << (E + F))
+    lib().pgo_table_grad_chain(E, F, _ptr(g), _ptr(out))
+    return out

@@ -508,3 +508,24 @@ PGO_EXPORT void pgo_lut_bwd_items(long n_items, const int32_t *items, const doub
         }
     }
 }
+
+/*
+ * Gradient with respect to the node values of a table whose slopes follow
+ * them: with G1_k = (G0_{k+1} - G0_k) / (s_{k+1} - s_k) for k < K-1 and
+ * G1_{K-1} = 0 (the table of Sec. 3.4.1), the chain rule on
+ * L(G0, G1(G0)) gives
+ *   dL/dG0_k (total) = dL/dG0_k + dL/dG1_{k-1} / (s_k - s_{k-1})
+ *                                - dL/dG1_k / (s_{k+1} - s_k),
+ * each term present where its index exists.  gtab: double[2K] (interleaved
+ * G0, G1 gradients); g0: double[K].
+ */
+PGO_EXPORT void pgo_table_grad_chain(int E, int F, const double *gtab, double *g0)
+{
+    const long K = 1L << (E + F);
+    for (long k = 0; k < K; k++) {
+        double v = gtab[2 * k];
+        if (k >= 1) v += gtab[2 * (k - 1) + 1] / (pgo_node_s(E, F, k) - pgo_node_s(E, F, k - 1));
+        if (k + 1 < K) v -= gtab[2 * k + 1] / (pgo_node_s(E, F, k + 1) - pgo_node_s(E, F, k));
+        g0[k] = v;
+    }
+}

@@ -77,6 +77,8 @@ SIGNATURES = {
     "pgh_get_variant": (_I, [_P, _I]),
     "pgh_autotune": (_I, [_P, _I, _I, _P, _P, _P, _I, ctypes.POINTER(_F)]),
     "pgh_autotune_plan": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _I, ctypes.POINTER(_F)]),
+    "pgh_correct_self_potential": (_I, [_P, _I, _P, _P, _P]),
+    "pgh_table_grad_chain": (_I, [_P, _I, _I, _P, _P]),
 }
 
 
@@ -278,6 +280,29 @@ def pgh_batch_table_bwd(ctx, plan, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, gtabl
         _ptr(xj, None, "xj"), _ptr(yj, None, "yj"), _ptr(zj, None, "zj"), _ptr(mj, None, "mj"),
         _ptr(wx, None, "wx"), _ptr(wy, None, "wy"), _ptr(wz, None, "wz"),
         _ptr(gtable, None, "gtable"), _ptr(gmj, None, "gmj")))
+
+
+def pgh_correct_self_potential(ctx, n, m, eps2_i, phi):
+    _check(ctx, lib.pgh_correct_self_potential(ctx, n, _ptr(m, n, "m"), _ptr(eps2_i, n, "eps2_i"),
+                                               _ptr(phi, n, "phi")))
+
+
+def pgh_table_grad_chain(ctx, E, F, gtable, g0):
+    K = 1 << (E + F)
+    _check(ctx, lib.pgh_table_grad_chain(ctx, E, F, _ptr(gtable, 2 * K, "gtable"),
+                                         _ptr(g0, K, "g0")))
+
+
+def correct_self_potential(phi, m, eps=None, eps2=None, lib_ctx=None):
+    """Adds m_i/eps_i to raw potentials in place (pgh_correct_self_potential):
+    the physical potential of i-particles that are also j-particles.  eps is
+    a scalar softening (or eps2 a per-particle eps^2 tensor)."""
+    c = lib_ctx or default_context(phi.device.index)
+    c._sync_stream()
+    if eps2 is None:
+        c.set_eps_to_all(eps)
+    pgh_correct_self_potential(c.h, phi.numel(), m, eps2, phi)
+    return phi
 
 
 def pgh_variant_count(family):

@@ -189,4 +189,36 @@ hipError_t launch_table_allpairs(const TableArgs &a0, int variant, int S, hipStr
     return launch_combine_split(a.ni, S, a.part, a0.ax, a0.ay, a0.az, nullptr, s);
 }
 
+namespace {
+
+// Gradient with respect to the node values when the slopes are derived from
+// them, G1_k = (G0_{k+1} - G0_k) / (s_{k+1} - s_k) for k < K-1 (the table
+// definition of Sec. 3.4.1), given the gradients with respect to G0 and G1
+// as independent entries (interleaved like the table):
+//   dL/dG0_k (total) = dL/dG0_k + dL/dG1_{k-1} / ds_{k-1} - dL/dG1_k / ds_k,
+// each term present where its index exists (G1_{K-1} is the constant 0).
+__global__ void __launch_bounds__(256) k_table_grad_chain(int K, unsigned shift,
+                                                          const float *__restrict__ g,
+                                                          float *__restrict__ out)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= K) return;
+    // node s_k: the FP32 bits of 2.0 stepped by k units of the F-th fraction bit
+    auto node = [&](int q) { return __uint_as_float(0x40000000u + ((unsigned)q << shift)); };
+    float v = g[2 * k];
+    if (k >= 1) v += g[2 * (k - 1) + 1] / (node(k) - node(k - 1));
+    if (k + 1 < K) v -= g[2 * k + 1] / (node(k + 1) - node(k));
+    out[k] = v;
+}
+
+}  // namespace
+
+hipError_t launch_table_grad_chain(int E, int F, const float *g, float *out, hipStream_t s)
+{
+    const int K = 1 << (E + F);
+    hipLaunchKernelGGL(k_table_grad_chain, dim3((K + 255) / 256), dim3(256), 0, s, K,
+                       23u - (unsigned)F, g, out);
+    return hipGetLastError();
+}
+
 }  // namespace pgh

@@ -432,6 +432,29 @@ int pgh_calc_table(pgh_ctx *c, int ni, const float *xi, const float *yi, const f
     return PGH_OK;
 }
 
+int pgh_correct_self_potential(pgh_ctx *c, int n, const float *m, const float *eps2_i,
+                               float *phi)
+{
+    if (!c) return PGH_EINVAL;
+    if (n < 0) return fail(c, PGH_EINVAL, "n must be >= 0");
+    if (n == 0) return PGH_OK;
+    if (!m || !phi) return fail(c, PGH_EINVAL, "NULL mass or potential array");
+    DeviceGuard g(c->device);
+    PGH_HIP(c, launch_self_potential(n, m, eps2_i, c->eps2_all, phi, c->stream));
+    return PGH_OK;
+}
+
+int pgh_table_grad_chain(pgh_ctx *c, int E, int F, const float *gtable, float *g0)
+{
+    if (!c) return PGH_EINVAL;
+    int st = check_table_shape(c, E, F, 1.0f);
+    if (st) return st;
+    if (!gtable || !g0) return fail(c, PGH_EINVAL, "NULL gradient array");
+    DeviceGuard g(c->device);
+    PGH_HIP(c, launch_table_grad_chain(E, F, gtable, g0, c->stream));
+    return PGH_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Plans and batched launches
 // ---------------------------------------------------------------------------

@@ -109,6 +109,9 @@ struct TableBwdArgs {
 hipError_t launch_pack_j(int n, const float *x, const float *y, const float *z, const float *m,
                          float4 *dst, hipStream_t s);
 hipError_t launch_fill_zero(int n, float *a, float *b, float *c, float *d, hipStream_t s);
+hipError_t launch_self_potential(int n, const float *m, const float *eps2i, float eps2_all,
+                                 float *phi, hipStream_t s);
+hipError_t launch_table_grad_chain(int E, int F, const float *g, float *out, hipStream_t s);
 
 // All-pairs launches split the j-range over S workgroup rows when the i-range
 // alone gives too few waves; the shares write partial sums [S][4][ni] that

@@ -241,3 +241,48 @@ def test_table_adjoint_partial_outputs_and_repeats(pgh, ctx):
     for g_t, g_m in both + [(to_host(gt2)[0], to_host(gm2)[0])]:
         _table_gate(g_t, rt, at, E, F, "gtable")
         _gate(g_m, rm, am, "gmj")
+
+
+@pytest.mark.parametrize("E,F", [(4, 6), (2, 3), (0, 4)])
+def test_table_grad_chain_kernel(pgh, ctx, E, F):
+    """pgh_table_grad_chain against the oracle's chain rule on the same
+    gradient entries (and, for E = 4, F = 6, on the adjoint's own output)."""
+    import torch
+    K = 1 << (E + F)
+    g = np.random.default_rng(E * 16 + F).standard_normal(2 * K).astype(np.float32)
+    out = torch.empty(K, device="cuda")
+    pgh.pgh_table_grad_chain(ctx.h, E, F, to_dev(g)[0], out)
+    ref = oracle.table_grad_chain(E, F, g)
+    nodes = np.array([oracle.node_s(E, F, k) for k in range(K)])
+    ds = np.diff(nodes)
+    scale = np.abs(g[0::2]).astype(np.float64)
+    scale[1:] += np.abs(g[1:2 * K - 2:2]) / ds
+    scale[:-1] += np.abs(g[1:2 * K - 2:2]) / ds
+    err = np.abs(to_host(out)[0] - ref) / scale
+    assert err.max() < 4e-7, err.max()
+
+
+def test_self_potential_correction(pgh, ctx):
+    """Raw potentials plus pgh_correct_self_potential equal the oracle's
+    potential with the self pair skipped (Sec. 4.1), for one eps and for
+    per-particle eps^2."""
+    import torch
+    n = 2048
+    x, y, z = synth.plummer(n, 31)
+    m = np.linspace(0.5, 1.5, n).astype(np.float32) / n
+    d = to_dev(x, y, z, m)
+    ctx.set_j(*d)
+    for e2 in (None, np.random.default_rng(3).uniform(1e-4, 4e-4, n).astype(np.float32)):
+        if e2 is None:
+            ctx.set_eps_to_all(0.01)
+            e2h = np.full(n, np.float32(0.01) ** 2, np.float32)
+            e2d = None
+        else:
+            e2h, e2d = e2, to_dev(e2)[0]
+        ax, ay, az, phi = ctx.newton(d[0], d[1], d[2], eps2=e2d)
+        pgh.pgh_correct_self_potential(ctx.h, n, d[3], e2d, phi)
+        ref = oracle.newton(x, y, z, e2h, x, y, z, m, self_j=np.arange(n))
+        ep = np.abs(to_host(phi)[0] - ref[3]) / np.abs(ref[3])
+        assert rms(ep) <= 1e-5 and ep.max() <= 1e-3, (rms(ep), ep.max())
+    phi2 = pgh.correct_self_potential(torch.zeros(n, device="cuda"), d[3], eps=0.5, lib_ctx=ctx)
+    assert np.allclose(to_host(phi2)[0], m / np.float32(0.5), rtol=1e-6)

@@ -129,3 +129,41 @@ def test_error_scales_bound_the_sums_and_see_inside_the_dot_product():
                                            scales=True)
     assert np.all(np.abs(gt) <= at * (1 + 1e-12))
     assert np.all(np.abs(gmj) <= am * (1 + 1e-12))
+
+
+def test_table_gradient_chain_to_node_values_matches_central_differences():
+    """A table parametrised by its node values G0_k, slopes G1_k = chord to
+    the next node (Sec. 3.4.1) and G1_{K-1} = 0: the loss is linear in G0,
+    so central differences through oracle.lut_items are exact, and they must
+    equal table_grad_chain applied to the (G0, G1) gradient."""
+    E, F, rcut = 2, 2, 0.4
+    K = 1 << (E + F)
+    nodes = np.array([oracle.node_s(E, F, k) for k in range(K)])
+    rng = np.random.default_rng(12)
+    g0 = rng.uniform(-1.0, 1.0, K)
+
+    def table_of(v):
+        t = np.zeros(2 * K)
+        t[0::2] = v
+        t[1:2 * K - 2:2] = (v[1:] - v[:-1]) / (nodes[1:] - nodes[:-1])
+        return t
+
+    n = 30
+    x, y, z = [a.astype(np.float64) for a in synth.uniform_box(n, 13, box=0.6)]
+    m = np.linspace(0.5, 1.5, n)
+    w = [rng.standard_normal(n) for _ in range(3)]
+    items = np.array([[0, 15, 0, 30], [15, 15, 5, 20]], np.int32)
+
+    def loss(v):
+        ax, ay, az, _ = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rcut, table_of(v))
+        return float(np.sum(w[0] * ax + w[1] * ay + w[2] * az))
+
+    gt, _ = oracle.lut_bwd_items(items, x, y, z, x, y, z, m, *w, E, F, rcut, table_of(g0))
+    chained = oracle.table_grad_chain(E, F, gt)
+    fd = np.zeros(K)
+    for k in range(K):
+        p = g0.copy(); p[k] += 0.5
+        q = g0.copy(); q[k] -= 0.5
+        fd[k] = loss(p) - loss(q)
+    assert np.allclose(chained, fd, rtol=1e-9, atol=1e-12 * np.abs(fd).max())
+    assert np.any(gt[1::2] != 0)  # the slope terms take part
