@@ -23,11 +23,11 @@
 //   dL/dG0_k = sum over pairs in bin k of m_j (w_i . d)
 //   dL/dG1_k = sum over pairs in bin k of m_j (s - s_k) (w_i . d)
 //   dL/dm_j  = sum_i g (w_i . d)
-// The table gradient is accumulated in LDS with float atomics per workgroup
-// and flushed once; pairs clamped to the last node (beyond rcut, where
-// s - s_k = 0) add to a per-lane register instead, so the common
-// out-of-range pair costs no atomic.  dL/dm_j comes from a j-major pass over
-// the same lists.
+// One j-major pass over the lists gives both: the table gradient is
+// accumulated in LDS with float atomics per workgroup and flushed once
+// (pairs clamped to the last node, beyond rcut where s - s_k = 0, add to a
+// per-lane register instead, so the common out-of-range pair costs no
+// atomic), and dL/dm_j is each lane's own sum.
 #include <algorithm>
 
 #include "pairs.h"
@@ -367,36 +367,37 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Both passes of the table-force adjoint in one persistent launch.  The task
-// index space is [0, n_tab): i-major tasks of the plan (an i-chunk against a
-// part of its j-list), giving the table gradient; then [n_tab, n_tab + n_m):
-// j-major tasks (a chunk of <= 64 j-entries against its item's i-range),
-// giving the mass gradient.  Tasks of each kind are sorted longest first.
-//
-//   table gradient: for a pair with bin k and offset ds = s - s_k,
-//     dL/dG0_k += m_j (w_i . d),  dL/dG1_k += m_j (w_i . d) ds
-//   accumulated in LDS (float atomics; pairs clamped to s_max, the common
-//   case, go to one register instead) and added to gtable at the end with
-//   one global atomic per non-zero bin and workgroup;
-//   mass gradient: dL/dm_j = sum_i g(s) (w_i . d), one lane per j-entry.
-//
-// j (or i) records stream through a per-wave LDS tile of 64, the next tile
-// prefetched into registers while the current one is consumed.
-__global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *jtasks, int n_tab,
-                                                   int n_m, unsigned *queue)
+// The table-force adjoint in one pass over the pairs, j-major: a task is a
+// chunk of <= 64 j-entries of a list (one per lane) against its item's
+// i-range, streamed through a per-wave LDS tile of 64 i-records (position
+// and weight), the next tile prefetched into registers.  Each pair with bin
+// k and offset ds = s - s_k adds
+//   dL/dm_j   += g(s) (w_i . d)                        (a register per lane)
+//   dL/dG0_k  += m_j (w_i . d),  dL/dG1_k += m_j (w_i . d) ds
+// the table terms into LDS bins with float atomics (pairs clamped to s_max,
+// the common case, into one register instead), flushed with one global
+// atomic per non-zero bin and workgroup into one of kGradCopies copies, which
+// a last small kernel adds; dL/dm_j goes to gmj with one atomic per entry and
+// task (an entry can belong to several lists).
+// Tasks are sorted longest first; the first round is taken by index, later
+// ones from the counter, which the launch's last pop puts back to zero.
+__global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *jtasks, int n_m,
+                                                   unsigned *queue)
 {
     extern __shared__ float dyn[];
     const BatchArgs &a = A.b;
     const int K = 1 << (a.E + a.F);
-    float2 *stab = (float2 *)dyn;  // K (G0, G1): mass tasks
-    float *gt = dyn + 2 * K;       // 2K gradient accumulators: table tasks
+    float2 *stab = (float2 *)dyn;  // K (G0, G1)
+    float *gt = dyn + 2 * K;       // 2K gradient accumulators
     __shared__ float4 buf[4][128];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (n_m > 0) table_to_lds<false>(stab, a.table, K, 0u);
-    for (int k = threadIdx.x; k < K; k += 256) {
-        gt[2 * k] = 0.f;
-        gt[2 * k + 1] = 0.f;
-    }
+    const bool want_tab = A.gtable != nullptr, want_m = A.gmj != nullptr;
+    if (want_m) table_to_lds<false>(stab, a.table, K, 0u);
+    if (want_tab)
+        for (int k = threadIdx.x; k < K; k += 256) {
+            gt[2 * k] = 0.f;
+            gt[2 * k + 1] = 0.f;
+        }
     __syncthreads();
     const unsigned shift = 23u - (unsigned)a.F, nbits = (unsigned)(a.E + a.F);
     const unsigned hmask = ~((1u << shift) - 1u);
@@ -405,9 +406,9 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
     float4 *tile = buf[wave];
     float last0 = 0.f;  // clamped pairs: dL/dG0 of the last node
 
-    const unsigned n_all = (unsigned)(n_tab + n_m);
+    const unsigned n_all = (unsigned)n_m;
     const unsigned n_waves = gridDim.x * 4;
-    for (unsigned t = blockIdx.x * 4 + wave; t < n_all;) {
+    for (unsigned t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wave); t < n_all;) {
         unsigned tn = n_all;
         if (n_all > n_waves && lane == 0) {
             // one pop per task executed: the pop that draws n_all-1 is the
@@ -417,129 +418,109 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
             if (k == n_all - 1u) __hip_atomic_store(queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tn = n_waves + k;
         }
-        if (t < (unsigned)n_tab) {
-            // ---- table gradient: lane = i-particle, loop over j.  A paired
-            // task runs its two chunks side by side (lanes [0, n_i) on the
-            // first list, [n_i, n_i + n_i2) on the second).
-            const Task tk = a.tasks[t];
-            const bool paired = tk.n_i2 > 0;
-            const bool second = paired && lane >= tk.n_i;
-            const int il = second ? lane - tk.n_i : lane;
-            const bool active = il < (second ? tk.n_i2 : tk.n_i);
-            const int i = (second ? tk.i_off2 : tk.i_off) + (active ? il : 0);
-            const float px = a.xi[i], py = a.yi[i], pz = a.zi[i];
-            const float wx = active ? A.wx[i] : 0.f, wy = active ? A.wy[i] : 0.f,
-                        wz = active ? A.wz[i] : 0.f;
-            const int nj = paired ? max(tk.n_j, tk.n_j2) : tk.n_j;
-            // records past a list's end: zero mass, far away (clamped bin)
-            auto load = [&](int off, int n, int base) {
-                float4 v = make_float4(1.0e10f, 1.0e10f, 1.0e10f, 0.f);
-                const int j = off + base + lane;
-                if (base + lane < n) v = make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j]);
-                return v;
-            };
-            auto pair = [&](const float4 p) {
-                const float dx = p.x - px, dy = p.y - py, dz = p.z - pz;
-                float r2 = dx * dx;
-                r2 = __builtin_fmaf(dy, dy, r2);
-                r2 = __builtin_fmaf(dz, dz, r2);
-                const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
-                const unsigned u = __float_as_uint(s);
-                const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
-                float wd = wx * dx;
-                wd = __builtin_fmaf(wy, dy, wd);
-                wd = __builtin_fmaf(wz, dz, wd);
-                const float v0 = p.w * wd;
+        const Task tk = jtasks[t];  // i_off/n_i: the j-chunk; j_off/n_j: the i-range
+        // a chunk of <= 32 (<= 16) j-entries runs 2 (4) lanes per entry on
+        // alternate i-records, added inside the wave at the end
+        const int jlog = tk.n_i <= 16 ? 2 : (tk.n_i <= 32 ? 1 : 0);
+        const int js = 1 << jlog;
+        const int jl = lane & (63 >> jlog), ph = lane >> (6 - jlog);
+        const bool active = jl < tk.n_i;
+        const int j = tk.i_off + (active ? jl : 0);
+        const float qx = a.xj[j], qy = a.yj[j], qz = a.zj[j];
+        const float mj = active ? a.mj[j] : 0.f;
+        float G = 0.f;
+        float4 pp, pw;
+        // i-records past the range: far away with zero weight (their terms vanish)
+        auto load = [&](int base) {
+            pp = make_float4(1.0e10f, 1.0e10f, 1.0e10f, 0.f);
+            pw = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int i = tk.j_off + base + lane;
+            if (base + lane < tk.n_j) {
+                pp = make_float4(a.xi[i], a.yi[i], a.zi[i], A.wx[i]);
+                pw = make_float4(A.wy[i], A.wz[i], 0.f, 0.f);
+            }
+        };
+        auto pair = [&](const float4 p, const float4 w) {
+            const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+            float r2 = dx * dx;
+            r2 = __builtin_fmaf(dy, dy, r2);
+            r2 = __builtin_fmaf(dz, dz, r2);
+            const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
+            const unsigned u = __float_as_uint(s);
+            const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
+            const float ds = s - __uint_as_float(u & hmask);
+            float wd = p.w * dx;
+            wd = __builtin_fmaf(w.x, dy, wd);
+            wd = __builtin_fmaf(w.y, dz, wd);
+            if (want_m) {
+                const float2 g01 = stab[k];
+                G = __builtin_fmaf(__builtin_fmaf(g01.y, ds, g01.x), wd, G);
+            }
+            if (want_tab) {
+                const float v0 = mj * wd;
                 if (k == klast) {
                     last0 += v0;
                 } else if (active) {
-                    const float ds = s - __uint_as_float(u & hmask);
                     atomicAdd(&gt[2 * k], v0);
                     atomicAdd(&gt[2 * k + 1], v0 * ds);
                 }
-            };
-            const float4 *src = tile + (second ? 64 : 0);
-            float4 pre = load(tk.j_off, tk.n_j, 0), pre2 = pre;
-            if (paired) pre2 = load(tk.j_off2, tk.n_j2, 0);
-            for (int base = 0; base < nj; base += 64) {
-                wave_sync();
-                tile[lane] = pre;
-                if (paired) tile[64 + lane] = pre2;
-                wave_sync();
-                if (base + 64 < nj) {
-                    pre = load(tk.j_off, tk.n_j, base + 64);
-                    if (paired) pre2 = load(tk.j_off2, tk.n_j2, base + 64);
-                }
-                const int cnt = min(64, nj - base);
-                if (cnt == 64) {
+            }
+        };
+        load(0);
+        for (int base = 0; base < tk.n_j; base += 64) {
+            wave_sync();
+            tile[lane] = pp;
+            tile[64 + lane] = pw;
+            wave_sync();
+            if (base + 64 < tk.n_j) load(base + 64);
+            const int cnt = min(64, tk.n_j - base);
+            if (cnt == 64) {
+                const int full = 64 >> jlog;
 #pragma unroll 4
-                    for (int jj = 0; jj < 64; ++jj) pair(src[jj]);
-                } else {
-                    for (int jj = 0; jj < cnt; ++jj) pair(src[jj]);
+                for (int ii = 0; ii < full; ++ii) {
+                    const int r = (ii << jlog) + ph;
+                    pair(tile[r], tile[64 + r]);
+                }
+            } else {
+                // records past cnt are zero-weight padding
+                const int trips = (cnt + js - 1) >> jlog;
+                for (int ii = 0; ii < trips; ++ii) {
+                    const int r = (ii << jlog) + ph;
+                    pair(tile[r], tile[64 + r]);
                 }
             }
-        } else {
-            // ---- mass gradient: lane = j-entry, loop over the item's i-range
-            const Task tk = jtasks[t - (unsigned)n_tab];  // i_off/n_i: j-chunk; j_off/n_j: i-range
-            const bool active = lane < tk.n_i;
-            const int j = tk.i_off + (active ? lane : 0);
-            const float qx = a.xj[j], qy = a.yj[j], qz = a.zj[j];
-            float G = 0.f;
-            float4 pp, pw;
-            auto load = [&](int base) {
-                pp = make_float4(0.f, 0.f, 0.f, 0.f);
-                pw = pp;
-                const int i = tk.j_off + base + lane;
-                if (base + lane < tk.n_j) {
-                    pp = make_float4(a.xi[i], a.yi[i], a.zi[i], A.wx[i]);
-                    pw = make_float4(A.wy[i], A.wz[i], 0.f, 0.f);
-                }
-            };
-            auto pair = [&](const float4 p, const float4 w) {
-                const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
-                float r2 = dx * dx;
-                r2 = __builtin_fmaf(dy, dy, r2);
-                r2 = __builtin_fmaf(dz, dz, r2);
-                const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
-                const unsigned u = __float_as_uint(s);
-                const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
-                const float2 g01 = stab[k];
-                const float g = __builtin_fmaf(g01.y, s - __uint_as_float(u & hmask), g01.x);
-                float wd = p.w * dx;
-                wd = __builtin_fmaf(w.x, dy, wd);
-                wd = __builtin_fmaf(w.y, dz, wd);
-                G = __builtin_fmaf(g, wd, G);
-            };
-            load(0);
-            for (int base = 0; base < tk.n_j; base += 64) {
-                wave_sync();
-                tile[lane] = pp;
-                tile[64 + lane] = pw;
-                wave_sync();
-                if (base + 64 < tk.n_j) load(base + 64);
-                const int cnt = min(64, tk.n_j - base);
-                if (cnt == 64) {
-#pragma unroll 4
-                    for (int ii = 0; ii < 64; ++ii) pair(tile[ii], tile[64 + ii]);
-                } else {
-                    for (int ii = 0; ii < cnt; ++ii) pair(tile[ii], tile[64 + ii]);
-                }
-            }
-            if (active) atomicAdd(&A.gmj[j], G);
         }
+        if (jlog >= 2) G += __shfl_xor(G, 16);
+        if (jlog >= 1) G += __shfl_xor(G, 32);
+        if (want_m && active && ph == 0) atomicAdd(&A.gmj[j], G);
         t = __builtin_amdgcn_readfirstlane(tn);
     }
-    // wave sum of the clamped-bin register, then flush this workgroup's bins
-    for (int off = 32; off > 0; off >>= 1) last0 += __shfl_xor(last0, off);
-    if (lane == 0 && last0 != 0.f) atomicAdd(&gt[2 * klast], last0);
-    __syncthreads();
-    if (n_tab > 0)
+    if (want_tab) {
+        // wave sum of the clamped-bin register, then flush this workgroup's bins
+        for (int off = 32; off > 0; off >>= 1) last0 += __shfl_xor(last0, off);
+        if (lane == 0 && last0 != 0.f) atomicAdd(&gt[2 * klast], last0);
+        __syncthreads();
+        float *dst = A.gcopies + (size_t)(blockIdx.x % kGradCopies) * 2 * K;
         for (int k = threadIdx.x; k < 2 * K; k += 256)
-            if (gt[k] != 0.f) atomicAdd(&A.gtable[k], gt[k]);
+            if (gt[k] != 0.f) atomicAdd(&dst[k], gt[k]);
+    }
 }
 
-// Zeroes the gradient outputs and the task counter ahead of k_table_bwd (a
-// kernel rather than memsets, so the pair can be captured in a graph).
+// gtable[k] = sum of the kGradCopies partial copies, in copy order.
+__global__ void __launch_bounds__(256) k_table_bwd_sum(int n, const float *__restrict__ copies,
+                                                       float *__restrict__ gtable)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    float v = 0.f;
+#pragma unroll
+    for (int q = 0; q < kGradCopies; ++q) v += copies[(size_t)q * n + k];
+    gtable[k] = v;
+}
+
+// Zeroes the gradient copies, the mass gradient and the task counter ahead
+// of k_table_bwd (a kernel rather than memsets, so the sequence can be
+// captured in a graph).
 __global__ void __launch_bounds__(256) k_table_bwd_prologue(float *gtable, int n1, float *gmj,
                                                             int n2, unsigned *queue)
 {
@@ -622,19 +603,27 @@ hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int
                                   int nj_total, unsigned *queue, int num_cu, hipStream_t s)
 {
     const int K = 1 << (A.b.E + A.b.F);
-    const int n_tab = A.gtable ? A.b.n_tasks : 0;
-    const int n_m = A.gmj ? n_jtasks : 0;
+    const int n1 = A.gtable ? kGradCopies * 2 * K : 0;
     const int n2 = A.gmj ? nj_total : 0;
-    const int zb = std::max(1, std::min(1024, (std::max(2 * K, n2) + 255) / 256));
-    hipLaunchKernelGGL(k_table_bwd_prologue, dim3(zb), dim3(256), 0, s, A.gtable, 2 * K, A.gmj,
-                       n2, queue);
+    const int zb = std::max(1, std::min(1024, (std::max(n1, n2) + 255) / 256));
+    hipLaunchKernelGGL(k_table_bwd_prologue, dim3(zb), dim3(256), 0, s,
+                       A.gtable ? A.gcopies : nullptr, n1, A.gmj, n2, queue);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n_tab + n_m == 0) return e;
-    const size_t lds = (size_t)K * 4 * sizeof(float);
-    const int cap = num_cu * resident((const void *)k_table_bwd, lds);
-    const int blocks = std::max(1, std::min(cap, (n_tab + n_m + 3) / 4));
-    hipLaunchKernelGGL(k_table_bwd, dim3(blocks), dim3(256), lds, s, A, jtasks, n_tab, n_m, queue);
-    return hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (n_jtasks > 0) {
+        const size_t lds = (size_t)K * 4 * sizeof(float);
+        const int cap = num_cu * resident((const void *)k_table_bwd, lds);
+        const int blocks = std::max(1, std::min(cap, (n_jtasks + 3) / 4));
+        hipLaunchKernelGGL(k_table_bwd, dim3(blocks), dim3(256), lds, s, A, jtasks, n_jtasks,
+                           queue);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (A.gtable) {
+        hipLaunchKernelGGL(k_table_bwd_sum, dim3((2 * K + 255) / 256), dim3(256), 0, s, 2 * K,
+                           (const float *)A.gcopies, A.gtable);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 }  // namespace pgh

@@ -178,10 +178,12 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
             // every lane runs the same trip count; records past cnt are padding
             const int trips = (cnt + js - 1) >> jlog;
             float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;
-            if (trips == 64) {
+            if (cnt == 64) {
+                // a full tile: 64 / js records per lane, this lane's phase
+                const int full = 64 >> jlog;
 #pragma unroll 4
-                for (int it = 0; it < 64; ++it) {
-                    const float4 p = src[it];
+                for (int it = 0; it < full; ++it) {
+                    const float4 p = src[(it << jlog) + ph];
                     if (KIND == 0)
                         newton_pair<REFINE, GUARD, PHI, ALT>(p, px, py, pz, pe, sx, sy, sz, sp);
                     else

@@ -45,6 +45,7 @@ struct pgh_ctx {
     int tab_E = 0, tab_F = 0;
     float tab_rcut = 0.f;
     float2 *tab = nullptr;  // device, 2^kMaxTableBits entries
+    float *gcopy = nullptr;  // device, kGradCopies x 2^(kMaxTableBits+1): table-adjoint scratch
     int variant[4] = {-1, -1, -1, -1};
     // partial sums of j-split all-pairs launches (grown on demand)
     float *part = nullptr;
@@ -197,8 +198,11 @@ int pgh_open(pgh_ctx **out, int device, void *hip_stream)
         ncu > 0)
         c->num_cu = ncu;
     e = hipMalloc((void **)&c->tab, sizeof(float2) << kMaxTableBits);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&c->gcopy, (sizeof(float2) << kMaxTableBits) * kGradCopies);
     if (e != hipSuccess) {
         g_open_error = std::string("hipMalloc(table): ") + hipGetErrorString(e);
+        (void)hipFree(c->tab);
         delete c;
         return PGH_ENOMEM;
     }
@@ -220,6 +224,7 @@ int pgh_close(pgh_ctx *c)
     (void)hipFree(c->part);
     (void)hipFree(c->jmem);
     (void)hipFree(c->tab);
+    (void)hipFree(c->gcopy);
     delete c;
     return PGH_OK;
 }
@@ -490,16 +495,29 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
                                            " and " + std::to_string(order[k]) + " overlap");
     }
 
-    // wave tasks: chunks of <= 64 i-particles; lanes per i-particle js
+    // Wave tasks: chunks of <= 64 i-particles; a chunk of <= 32 (<= 16) runs
+    // js = 2 (4) lanes per i-particle.  When chunks of 64 fill less than half
+    // of the waves the device holds (a small plan), the groups are cut into
+    // chunks of 32 or 16 instead: more waves to hide latency, each lane's
+    // j-list shorter, and no partial sums (the lanes of an i-particle are
+    // added inside the wave).
     struct Chunk {
         int i_off, n_i, j_off, n_j, js;
     };
+    const int waves = std::max(1, batch_resident_waves(c->num_cu));
+    int csize = 64;
+    for (;;) {
+        long long n = 0;
+        for (int t : order) n += (items[t].n_i + csize - 1) / csize;
+        if (2 * n >= waves || csize == 16) break;
+        csize /= 2;
+    }
     std::vector<Chunk> chunks;
     long long total = 0;  // wave-iterations
     for (int t : order) {
         const pgh_item &it = items[t];
-        for (int s0 = 0; s0 < it.n_i; s0 += 64) {
-            const int n = std::min(64, it.n_i - s0);
+        for (int s0 = 0; s0 < it.n_i; s0 += csize) {
+            const int n = std::min(csize, it.n_i - s0);
             const int js = n <= 16 ? 4 : (n <= 32 ? 2 : 1);
             chunks.push_back({it.i_off + s0, n, it.j_off, it.n_j, js});
             total += std::max(1LL, (long long)(it.n_j + js - 1) / js);
@@ -510,7 +528,6 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     // ends with short ones.  (Equal tasks of half a wave's work leave the
     // last round of the queue mostly idle whenever the task count is just
     // above a multiple of the wave count.)
-    const int waves = std::max(1, batch_resident_waves(c->num_cu));
     const long long part_iters = std::max(512LL, (total / waves / 8 + 63) / 64 * 64);
     std::vector<Task> tasks;
     std::vector<long long> cost;
@@ -625,12 +642,21 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     p->chunks = nullptr;
     p->jtasks = nullptr;
     p->jqueue = nullptr;
-    // j-major tasks: chunks of <= 64 j-entries of a list against its i-group
+    // j-major tasks of the table adjoint: chunks of <= 64 j-entries of a
+    // list against its i-group (chunks of 32 or 16, 2 or 4 lanes per entry,
+    // when chunks of 64 would fill less than half of the resident waves)
+    int jc = 64;
+    for (;;) {
+        long long n = 0;
+        for (int t : order) n += (items[t].n_j + jc - 1) / jc;
+        if (2 * n >= waves || jc == 16) break;
+        jc /= 2;
+    }
     std::vector<Task> jt;
     for (int t : order) {
         const pgh_item &it = items[t];
-        for (int s0 = 0; s0 < it.n_j; s0 += 64)
-            jt.push_back({it.j_off + s0, std::min(64, it.n_j - s0), it.i_off, it.n_i, 0, 1, 0, 0, 0,
+        for (int s0 = 0; s0 < it.n_j; s0 += jc)
+            jt.push_back({it.j_off + s0, std::min(jc, it.n_j - s0), it.i_off, it.n_i, 0, 1, 0, 0, 0,
                           0, 0, 0});
     }
     std::stable_sort(jt.begin(), jt.end(), [](const Task &a, const Task &b) { return a.n_j > b.n_j; });
@@ -657,6 +683,7 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
         return cleanup(PGH_ENOMEM, "hipMalloc(queue) failed");
     if (!jt.empty() && hipMalloc((void **)&p->jtasks, jt.size() * sizeof(Task)) != hipSuccess)
         return cleanup(PGH_ENOMEM, "hipMalloc(tasks) failed");
+
     if (hipMemsetAsync(p->jqueue, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
         (!jt.empty() && hipMemcpyAsync(p->jtasks, jt.data(), jt.size() * sizeof(Task),
                                        hipMemcpyHostToDevice, c->stream) != hipSuccess))
@@ -867,6 +894,7 @@ int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const fl
     A.wx = wx, A.wy = wy, A.wz = wz;
     A.gtable = gtable;
     A.gmj = gmj;
+    A.gcopies = c->gcopy;
     PGH_HIP(c, launch_table_batch_bwd(A, p->jtasks, p->n_jtasks, p->nj_total, p->jqueue, c->num_cu,
                                       c->stream));
     return PGH_OK;

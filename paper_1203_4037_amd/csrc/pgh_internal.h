@@ -98,11 +98,17 @@ struct CombineArgs {
     float *ax, *ay, *az, *phi;
 };
 
+// Copies of the table gradient that the workgroups of the adjoint add into
+// (workgroup b into copy b mod kGradCopies), summed in a fixed order at the
+// end: one copy would take every workgroup's atomics on the same few bins.
+constexpr int kGradCopies = 16;
+
 struct TableBwdArgs {
     BatchArgs b;
     const float *wx, *wy, *wz;
-    float *gtable;  // 2K floats
+    float *gtable;   // 2K floats
     float *gmj;
+    float *gcopies;  // kGradCopies x 2K floats (context scratch)
 };
 
 // Kernel launchers (defined in the .hip files).
