@@ -251,19 +251,27 @@ PGH_API int pgh_newton_ij_bwd(pgh_ctx *c, int ni, const float *xi, const float *
                       const float *wz, float *gxi, float *gyi, float *gzi, float *gxj,
                       float *gyj, float *gzj, float *gmj);
 
-/* Table-force adjoint over a plan, with G0 and G1 independent leaves:
+/* Table-force adjoint over a plan (derived from the interpolation of
+ * Sec. 3.4.2), with G0 and G1 independent leaves; with g = G0_k + G1_k (s - s_k)
+ * and s = c |d|^2 + 2 (g is linear in s inside a bin, dg/ds = G1_k, and 0 on
+ * the clamp):
  *   gtable[2k]   = sum over pairs in bin k of m_j (w_i . d)
  *   gtable[2k+1] = sum over pairs in bin k of m_j (s - s_k)(w_i . d)
  *   gmj_j        = sum over pairs with j of g (w_i . d)
- * gtable: device float[2 * 2^(E+F)] (or NULL), overwritten.  gmj: device
- * float[nj_total] (or NULL), overwritten; an entry used by several lists
- * accumulates.  The sums use float atomics, so their order (and last bits)
- * may vary from call to call.  Position gradients of the table force are not
- * provided. */
+ *   g{x,y,z}j_j  = sum over pairs with j of m_j [ g w_i + 2c G1_k (w_i . d) d ]
+ *   g{x,y,z}i_i  = - the same sum over the pairs of i
+ * gtable: device float[2 * 2^(E+F)] (or NULL), overwritten.  gmj and
+ * g{x,y,z}j: device float[nj_total] (or NULL), overwritten; an entry used by
+ * several lists accumulates.  g{x,y,z}i: device float[ni_total] (or NULL),
+ * overwritten; rows in no list get 0.  Position gradients come in triples
+ * (PGH_EINVAL otherwise).  The sums use float atomics, so their order (and
+ * last bits) may vary from call to call.  Allocates nothing. */
 PGH_API int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
-                        const float *zi, const float *xj, const float *yj, const float *zj,
-                        const float *mj, const float *wx, const float *wy, const float *wz,
-                        float *gtable, float *gmj);
+                                const float *zi, const float *xj, const float *yj,
+                                const float *zj, const float *mj, const float *wx,
+                                const float *wy, const float *wz, float *gtable, float *gmj,
+                                float *gxi, float *gyi, float *gzi, float *gxj, float *gyj,
+                                float *gzj);
 
 /* Removes the self term from raw potentials (Sec. 4.1): phi[i] += m[i] /
  * eps_i for i in [0, n), with eps_i^2 from eps2_i (device, may be NULL: the

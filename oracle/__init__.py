@@ -64,6 +64,8 @@ def lib():
             "pgo_newton_bwd": [l, P, P, P, P, l, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P],
             "pgo_lut_bwd_items": [l, P, P, P, P, P, P, P, P, P, P, P, i, i, d, P, P, P, l, P, P],
             "pgo_table_grad_chain": [i, i, P, P],
+            "pgo_lut_bwd_pos_items": [l, P, P, P, P, P, P, P, P, P, P, P, i, i, d, P, l, l,
+                                      P, P, P, P, P, P, P, P],
         }
         ret = {"pgo_s2_R": d, "pgo_s2pp_f": d, "pgo_shape_h": d, "pgo_smax": d,
                "pgo_node_s": d, "pgo_node_r": d, "pgo_lut_index": l, "pgo_lut_eval": d}
@@ -248,3 +250,21 @@ def table_grad_chain(E, F, gtab):
     out = np.zeros(1 << (E + F))
     lib().pgo_table_grad_chain(E, F, _ptr(g), _ptr(out))
     return out
+
+
+def lut_bwd_pos_items(items, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, E, F, rcut, table,
+                      scales=False):
+    """Position gradients of L = sum_i w_i . a_i for the table force:
+    (gxi, gyi, gzi, gxj, gyj, gzj), plus (absi, absj) when scales."""
+    it = _items32(items)
+    xi, yi, zi = map(_f64, (xi, yi, zi))
+    xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
+    wx, wy, wz = map(_f64, (wx, wy, wz))
+    t = _f64(table)
+    out = [np.zeros(xi.size) for _ in range(3)] + [np.zeros(xj.size) for _ in range(3)]
+    sc = [np.zeros(xi.size), np.zeros(xj.size)]
+    lib().pgo_lut_bwd_pos_items(it.shape[0], _ptr(it), _ptr(xi), _ptr(yi), _ptr(zi), _ptr(xj),
+                                _ptr(yj), _ptr(zj), _ptr(mj), _ptr(wx), _ptr(wy), _ptr(wz), E, F,
+                                float(rcut), _ptr(t), xi.size, xj.size, *[_ptr(a) for a in out],
+                                _ptr(sc[0]), _ptr(sc[1]))
+    return tuple(out) + (tuple(sc) if scales else ())

@@ -529,3 +529,79 @@ PGO_EXPORT void pgo_table_grad_chain(int E, int F, const double *gtab, double *g
         g0[k] = v;
     }
 }
+
+/*
+ * Position gradients of L = sum_i w_i . a_i for the table force over
+ * interaction lists.  The interpolant g(s) = G0_k + G1_k (s - s_k) is linear
+ * in s inside bin k, so dg/ds = G1_k there (and 0 on the clamp s = s_max),
+ * with s = c |d|^2 + 2, ds/dd = 2 c d.  For the pair term
+ * T = m_j g (w_i . d), d = r_j - r_i:
+ *   dT/dd = m_j [ g w_i + 2 c G1_k (w_i . d) d ]
+ * gxi_i = -sum_j dT/dd, gxj_j = sum_i dT/dd (an entry used by several lists
+ * accumulates).  absi / absj (may be NULL) receive the sums of the
+ * magnitudes of the products: m_j (|g| |w_i| + 2 c |G1_k| a_ij |d|),
+ * a_ij = sum_c |w_i,c d_c|, with |g| <= |G0_k| + |G1_k| (s_{k+1} - s_k).
+ */
+PGO_EXPORT void pgo_lut_bwd_pos_items(long n_items, const int32_t *items, const double *xi,
+                                      const double *yi, const double *zi, const double *xj,
+                                      const double *yj, const double *zj, const double *mj,
+                                      const double *wx, const double *wy, const double *wz,
+                                      int E, int F, double rcut, const double *table,
+                                      long ni_total, long nj_total, double *gxi, double *gyi,
+                                      double *gzi, double *gxj, double *gyj, double *gzj,
+                                      double *absi, double *absj)
+{
+    const long K = 1L << (E + F);
+    const double smax = pgo_smax(E, F);
+    const double c = (smax - 2.0) / (rcut * rcut);
+    memset(gxi, 0, sizeof(double) * ni_total);
+    memset(gyi, 0, sizeof(double) * ni_total);
+    memset(gzi, 0, sizeof(double) * ni_total);
+    memset(gxj, 0, sizeof(double) * nj_total);
+    memset(gyj, 0, sizeof(double) * nj_total);
+    memset(gzj, 0, sizeof(double) * nj_total);
+    if (absi) memset(absi, 0, sizeof(double) * ni_total);
+    if (absj) memset(absj, 0, sizeof(double) * nj_total);
+    for (long t = 0; t < n_items; t++) {
+        const long i0 = items[4 * t + 0], n_i = items[4 * t + 1];
+        const long j0 = items[4 * t + 2], n_j = items[4 * t + 3];
+        for (long i = i0; i < i0 + n_i; i++) {
+            for (long j = j0; j < j0 + n_j; j++) {
+                const double dx = (double)xj[j] - (double)xi[i];
+                const double dy = (double)yj[j] - (double)yi[i];
+                const double dz = (double)zj[j] - (double)zi[i];
+                double s = c * (dx * dx + dy * dy + dz * dz) + 2.0;
+                const int clamped = s >= smax;
+                if (clamped) s = smax;
+                double sk;
+                const long k = pgo_lut_index(s, E, F, &sk);
+                const double G0 = table[2 * k], G1 = table[2 * k + 1];
+                const double g = G0 + G1 * (s - sk);
+                const double dgds = clamped ? 0.0 : G1;
+                const double wd = (double)wx[i] * dx + (double)wy[i] * dy + (double)wz[i] * dz;
+                const double m = mj[j];
+                const double t0 = m * (g * wx[i] + 2.0 * c * dgds * wd * dx);
+                const double t1 = m * (g * wy[i] + 2.0 * c * dgds * wd * dy);
+                const double t2 = m * (g * wz[i] + 2.0 * c * dgds * wd * dz);
+                gxi[i] -= t0;
+                gyi[i] -= t1;
+                gzi[i] -= t2;
+                gxj[j] += t0;
+                gyj[j] += t1;
+                gzj[j] += t2;
+                if (absi || absj) {
+                    const double width = (k + 1 < K) ? pgo_node_s(E, F, k + 1) - sk : 0.0;
+                    const double awd = fabs((double)wx[i] * dx) + fabs((double)wy[i] * dy) +
+                                       fabs((double)wz[i] * dz);
+                    const double wn = sqrt((double)wx[i] * wx[i] + (double)wy[i] * wy[i] +
+                                           (double)wz[i] * wz[i]);
+                    const double a = fabs(m) * ((fabs(G0) + fabs(G1) * width) * wn +
+                                                2.0 * c * fabs(dgds) * awd *
+                                                    sqrt(dx * dx + dy * dy + dz * dz));
+                    if (absi) absi[i] += a;
+                    if (absj) absj[j] += a;
+                }
+            }
+        }
+    }
+}

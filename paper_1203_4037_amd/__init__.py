@@ -70,7 +70,7 @@ SIGNATURES = {
     "pgh_batch_table": (_I, [_P, _P] + [_P] * 10),
     "pgh_newton_allpairs_bwd": (_I, [_P, _I, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P, _P]),
     "pgh_newton_ij_bwd": (_I, [_P, _I, _P, _P, _P, _P, _I] + [_P] * 14),
-    "pgh_batch_table_bwd": (_I, [_P, _P] + [_P] * 12),
+    "pgh_batch_table_bwd": (_I, [_P, _P] + [_P] * 18),
     "pgh_variant_count": (_I, [_I]),
     "pgh_variant_name": (ctypes.c_char_p, [_I, _I]),
     "pgh_set_variant": (_I, [_P, _I, _I]),
@@ -274,12 +274,15 @@ def pgh_newton_ij_bwd(ctx, ni, xi, yi, zi, eps2_i, nj, xj, yj, zj, mj, wx, wy, w
         _ptr(gxj, nj, "gxj"), _ptr(gyj, nj, "gyj"), _ptr(gzj, nj, "gzj"), _ptr(gmj, nj, "gmj")))
 
 
-def pgh_batch_table_bwd(ctx, plan, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, gtable, gmj):
+def pgh_batch_table_bwd(ctx, plan, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, gtable, gmj,
+                        gxi=None, gyi=None, gzi=None, gxj=None, gyj=None, gzj=None):
     _check(ctx, lib.pgh_batch_table_bwd(
         ctx, plan, _ptr(xi, None, "xi"), _ptr(yi, None, "yi"), _ptr(zi, None, "zi"),
         _ptr(xj, None, "xj"), _ptr(yj, None, "yj"), _ptr(zj, None, "zj"), _ptr(mj, None, "mj"),
         _ptr(wx, None, "wx"), _ptr(wy, None, "wy"), _ptr(wz, None, "wz"),
-        _ptr(gtable, None, "gtable"), _ptr(gmj, None, "gmj")))
+        _ptr(gtable, None, "gtable"), _ptr(gmj, None, "gmj"),
+        _ptr(gxi, None, "gxi"), _ptr(gyi, None, "gyi"), _ptr(gzi, None, "gzi"),
+        _ptr(gxj, None, "gxj"), _ptr(gyj, None, "gyj"), _ptr(gzj, None, "gzj")))
 
 
 def pgh_correct_self_potential(ctx, n, m, eps2_i, phi):
@@ -606,8 +609,9 @@ class NewtonIJ(torch.autograd.Function):
 class TableForceBatch(torch.autograd.Function):
     """Table force of every list of a Plan, differentiable with respect to the
     table entries (G0 and G1 as independent leaves, interleaved like the
-    table) and the j masses through pgh_batch_table_bwd.  Position
-    gradients of the table force are not provided: asking for them raises."""
+    table), the j masses and the i- and j-positions through
+    pgh_batch_table_bwd (the interpolant is linear in s inside a bin, so its
+    s-derivative is the bin's G1; zero beyond the cutoff)."""
 
     @staticmethod
     def forward(fctx, plan, E, F, rcut, table, xi, yi, zi, xj, yj, zj, mj):
@@ -621,18 +625,19 @@ class TableForceBatch(torch.autograd.Function):
 
     @staticmethod
     def backward(fctx, gax, gay, gaz):
-        if any(fctx.needs_input_grad[5:11]):
-            raise NotImplementedError("position gradients of the table force are not provided")
         table, xi, yi, zi, xj, yj, zj, mj = fctx.saved_tensors
         plan = fctx.plan
         c = plan.ctx
         E, F, rcut = fctx.shape
         c.set_table(E, F, rcut, table)
         wx, wy, wz = (_zeros_if_none(g, xi) for g in (gax, gay, gaz))
-        gt = c._empty(table.numel()) if fctx.needs_input_grad[4] else None
-        gm = c._empty(plan.nj_total) if fctx.needs_input_grad[11] else None
-        pgh_batch_table_bwd(c.h, plan.h, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, gt, gm)
-        return (None, None, None, None, gt, None, None, None, None, None, None, gm)
+        need = fctx.needs_input_grad
+        gt = c._empty(table.numel()) if need[4] else None
+        gm = c._empty(plan.nj_total) if need[11] else None
+        gi = [c._empty(plan.ni_total) for _ in range(3)] if any(need[5:8]) else [None] * 3
+        gj = [c._empty(plan.nj_total) for _ in range(3)] if any(need[8:11]) else [None] * 3
+        pgh_batch_table_bwd(c.h, plan.h, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, gt, gm, *gi, *gj)
+        return (None, None, None, None, gt, *gi, *gj, gm)
 
 
 def newton_allpairs(x, y, z, m, eps, lib_ctx=None):

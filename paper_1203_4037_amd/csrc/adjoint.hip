@@ -367,22 +367,32 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The table-force adjoint in one pass over the pairs, j-major: a task is a
-// chunk of <= 64 j-entries of a list (one per lane) against its item's
-// i-range, streamed through a per-wave LDS tile of 64 i-records (position
-// and weight), the next tile prefetched into registers.  Each pair with bin
-// k and offset ds = s - s_k adds
-//   dL/dm_j   += g(s) (w_i . d)                        (a register per lane)
+// The table-force adjoint over the lists of a plan.  Task kinds (one queue):
+//
+// [0, n_m): j-major tasks, a chunk of <= 64 j-entries of a list (one per
+// lane; chunks of <= 32 or <= 16 run 2 or 4 lanes per entry on alternate
+// i-records) against its item's i-range, streamed through a per-wave LDS
+// tile of 64 i-records (position and weight), the next tile prefetched into
+// registers.  With g = G0_k + G1_k ds, ds = s - s_k, each pair adds
+//   dL/dm_j   += g (w_i . d)
 //   dL/dG0_k  += m_j (w_i . d),  dL/dG1_k += m_j (w_i . d) ds
+//   dL/dr_j   += m_j [ g w_i + 2c G1_k (w_i . d) d ]
 // the table terms into LDS bins with float atomics (pairs clamped to s_max,
 // the common case, into one register instead), flushed with one global
-// atomic per non-zero bin and workgroup into one of kGradCopies copies, which
-// a last small kernel adds; dL/dm_j goes to gmj with one atomic per entry and
-// task (an entry can belong to several lists).
-// Tasks are sorted longest first; the first round is taken by index, later
-// ones from the counter, which the launch's last pop puts back to zero.
+// atomic per non-zero bin and workgroup into one of kGradCopies copies,
+// which a last small kernel adds; the per-entry sums go to gmj and gxj with
+// one atomic per entry and task (an entry can belong to several lists).
+//
+// [n_m, n_m + n_i): i-major tasks (only for the i-side position gradient),
+// an i-chunk of <= 64 against a part of its j-list, j-records streamed:
+//   dL/dr_i   -= m_j [ g w_i + 2c G1_k (w_i . d) d ]
+// summed per lane and added to gxi with one atomic per i and task.
+//
+// Tasks of each kind are sorted longest first; the first round is taken by
+// index, later ones from the counter, which the launch's last pop puts back
+// to zero.
 __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *jtasks, int n_m,
-                                                   unsigned *queue)
+                                                   const Task *itasks, int n_i, unsigned *queue)
 {
     extern __shared__ float dyn[];
     const BatchArgs &a = A.b;
@@ -392,7 +402,9 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
     __shared__ float4 buf[4][128];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool want_tab = A.gtable != nullptr, want_m = A.gmj != nullptr;
-    if (want_m) table_to_lds<false>(stab, a.table, K, 0u);
+    const bool want_xj = A.gxj != nullptr;
+    const bool need_g = want_m || want_xj || n_i > 0;
+    if (need_g) table_to_lds<false>(stab, a.table, K, 0u);
     if (want_tab)
         for (int k = threadIdx.x; k < K; k += 256) {
             gt[2 * k] = 0.f;
@@ -402,11 +414,11 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
     const unsigned shift = 23u - (unsigned)a.F, nbits = (unsigned)(a.E + a.F);
     const unsigned hmask = ~((1u << shift) - 1u);
     const unsigned klast = (unsigned)K - 1u;
-    const float c = a.c, smax = a.smax;
+    const float c = a.c, smax = a.smax, c2 = 2.0f * a.c;
     float4 *tile = buf[wave];
     float last0 = 0.f;  // clamped pairs: dL/dG0 of the last node
 
-    const unsigned n_all = (unsigned)n_m;
+    const unsigned n_all = (unsigned)(n_m + n_i);
     const unsigned n_waves = gridDim.x * 4;
     for (unsigned t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wave); t < n_all;) {
         unsigned tn = n_all;
@@ -418,81 +430,169 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
             if (k == n_all - 1u) __hip_atomic_store(queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tn = n_waves + k;
         }
-        const Task tk = jtasks[t];  // i_off/n_i: the j-chunk; j_off/n_j: the i-range
-        // a chunk of <= 32 (<= 16) j-entries runs 2 (4) lanes per entry on
-        // alternate i-records, added inside the wave at the end
+        const bool jmajor = t < (unsigned)n_m;
+        // jmajor: i_off/n_i = the j-chunk, j_off/n_j = the i-range; else an
+        // i-chunk and a part of its j-list
+        const Task tk = jmajor ? jtasks[t] : itasks[t - (unsigned)n_m];
+        // a chunk of <= 32 (<= 16) entries runs 2 (4) lanes per entry on
+        // alternate records, added inside the wave at the end
         const int jlog = tk.n_i <= 16 ? 2 : (tk.n_i <= 32 ? 1 : 0);
         const int js = 1 << jlog;
-        const int jl = lane & (63 >> jlog), ph = lane >> (6 - jlog);
-        const bool active = jl < tk.n_i;
-        const int j = tk.i_off + (active ? jl : 0);
-        const float qx = a.xj[j], qy = a.yj[j], qz = a.zj[j];
-        const float mj = active ? a.mj[j] : 0.f;
-        float G = 0.f;
-        float4 pp, pw;
-        // i-records past the range: far away with zero weight (their terms vanish)
-        auto load = [&](int base) {
-            pp = make_float4(1.0e10f, 1.0e10f, 1.0e10f, 0.f);
-            pw = make_float4(0.f, 0.f, 0.f, 0.f);
-            const int i = tk.j_off + base + lane;
-            if (base + lane < tk.n_j) {
-                pp = make_float4(a.xi[i], a.yi[i], a.zi[i], A.wx[i]);
-                pw = make_float4(A.wy[i], A.wz[i], 0.f, 0.f);
-            }
-        };
-        auto pair = [&](const float4 p, const float4 w) {
-            const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
-            float r2 = dx * dx;
-            r2 = __builtin_fmaf(dy, dy, r2);
-            r2 = __builtin_fmaf(dz, dz, r2);
-            const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
-            const unsigned u = __float_as_uint(s);
-            const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
-            const float ds = s - __uint_as_float(u & hmask);
-            float wd = p.w * dx;
-            wd = __builtin_fmaf(w.x, dy, wd);
-            wd = __builtin_fmaf(w.y, dz, wd);
-            if (want_m) {
-                const float2 g01 = stab[k];
-                G = __builtin_fmaf(__builtin_fmaf(g01.y, ds, g01.x), wd, G);
-            }
-            if (want_tab) {
-                const float v0 = mj * wd;
-                if (k == klast) {
-                    last0 += v0;
-                } else if (active) {
-                    atomicAdd(&gt[2 * k], v0);
-                    atomicAdd(&gt[2 * k + 1], v0 * ds);
+        const int el = lane & (63 >> jlog), ph = lane >> (6 - jlog);
+        const bool active = el < tk.n_i;
+        const int e = tk.i_off + (active ? el : 0);  // this lane's entry
+        if (jmajor) {
+            const int j = e;
+            const float qx = a.xj[j], qy = a.yj[j], qz = a.zj[j];
+            const float mj = active ? a.mj[j] : 0.f;
+            float G = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, Vx = 0.f, Vy = 0.f, Vz = 0.f;
+            float4 pp, pw;
+            // i-records past the range: far away with zero weight
+            auto load = [&](int base) {
+                pp = make_float4(1.0e10f, 1.0e10f, 1.0e10f, 0.f);
+                pw = make_float4(0.f, 0.f, 0.f, 0.f);
+                const int i = tk.j_off + base + lane;
+                if (base + lane < tk.n_j) {
+                    pp = make_float4(a.xi[i], a.yi[i], a.zi[i], A.wx[i]);
+                    pw = make_float4(A.wy[i], A.wz[i], 0.f, 0.f);
                 }
-            }
-        };
-        load(0);
-        for (int base = 0; base < tk.n_j; base += 64) {
-            wave_sync();
-            tile[lane] = pp;
-            tile[64 + lane] = pw;
-            wave_sync();
-            if (base + 64 < tk.n_j) load(base + 64);
-            const int cnt = min(64, tk.n_j - base);
-            if (cnt == 64) {
-                const int full = 64 >> jlog;
+            };
+            auto pair = [&](const float4 p, const float4 w) {
+                const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+                float r2 = dx * dx;
+                r2 = __builtin_fmaf(dy, dy, r2);
+                r2 = __builtin_fmaf(dz, dz, r2);
+                const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
+                const unsigned u = __float_as_uint(s);
+                const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
+                const float ds = s - __uint_as_float(u & hmask);
+                float wd = p.w * dx;
+                wd = __builtin_fmaf(w.x, dy, wd);
+                wd = __builtin_fmaf(w.y, dz, wd);
+                if (want_m || want_xj) {
+                    const float2 g01 = stab[k];
+                    const float g = __builtin_fmaf(g01.y, ds, g01.x);
+                    if (want_m) G = __builtin_fmaf(g, wd, G);
+                    if (want_xj) {
+                        Ux = __builtin_fmaf(g, p.w, Ux);
+                        Uy = __builtin_fmaf(g, w.x, Uy);
+                        Uz = __builtin_fmaf(g, w.y, Uz);
+                        const float q = g01.y * wd;
+                        Vx = __builtin_fmaf(q, dx, Vx);
+                        Vy = __builtin_fmaf(q, dy, Vy);
+                        Vz = __builtin_fmaf(q, dz, Vz);
+                    }
+                }
+                if (want_tab) {
+                    const float v0 = mj * wd;
+                    if (k == klast) {
+                        last0 += v0;
+                    } else if (active) {
+                        atomicAdd(&gt[2 * k], v0);
+                        atomicAdd(&gt[2 * k + 1], v0 * ds);
+                    }
+                }
+            };
+            load(0);
+            for (int base = 0; base < tk.n_j; base += 64) {
+                wave_sync();
+                tile[lane] = pp;
+                tile[64 + lane] = pw;
+                wave_sync();
+                if (base + 64 < tk.n_j) load(base + 64);
+                const int cnt = min(64, tk.n_j - base);
+                if (cnt == 64) {
+                    const int full = 64 >> jlog;
 #pragma unroll 4
-                for (int ii = 0; ii < full; ++ii) {
-                    const int r = (ii << jlog) + ph;
-                    pair(tile[r], tile[64 + r]);
+                    for (int ii = 0; ii < full; ++ii) {
+                        const int r = (ii << jlog) + ph;
+                        pair(tile[r], tile[64 + r]);
+                    }
+                } else {
+                    // records past cnt are zero-weight padding
+                    const int trips = (cnt + js - 1) >> jlog;
+                    for (int ii = 0; ii < trips; ++ii) {
+                        const int r = (ii << jlog) + ph;
+                        pair(tile[r], tile[64 + r]);
+                    }
                 }
-            } else {
-                // records past cnt are zero-weight padding
-                const int trips = (cnt + js - 1) >> jlog;
-                for (int ii = 0; ii < trips; ++ii) {
-                    const int r = (ii << jlog) + ph;
-                    pair(tile[r], tile[64 + r]);
+            }
+            auto lanes_sum = [&](float &v) {
+                if (jlog >= 2) v += __shfl_xor(v, 16);
+                if (jlog >= 1) v += __shfl_xor(v, 32);
+            };
+            if (want_m) {
+                lanes_sum(G);
+                if (active && ph == 0) atomicAdd(&A.gmj[j], G);
+            }
+            if (want_xj) {
+                lanes_sum(Ux), lanes_sum(Uy), lanes_sum(Uz);
+                lanes_sum(Vx), lanes_sum(Vy), lanes_sum(Vz);
+                if (active && ph == 0) {
+                    atomicAdd(&A.gxj[j], mj * __builtin_fmaf(c2, Vx, Ux));
+                    atomicAdd(&A.gyj[j], mj * __builtin_fmaf(c2, Vy, Uy));
+                    atomicAdd(&A.gzj[j], mj * __builtin_fmaf(c2, Vz, Uz));
                 }
+            }
+        } else {
+            // i-side position gradient: lane = i-particle, j-records streamed
+            const int i = e;
+            const float px = a.xi[i], py = a.yi[i], pz = a.zi[i];
+            const float wx = A.wx[i], wy = A.wy[i], wz = A.wz[i];
+            float S = 0.f, Vx = 0.f, Vy = 0.f, Vz = 0.f;
+            float4 pre;
+            auto load = [&](int base) {
+                pre = make_float4(1.0e10f, 1.0e10f, 1.0e10f, 0.f);
+                const int j = tk.j_off + base + lane;
+                if (base + lane < tk.n_j) pre = make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j]);
+            };
+            auto pair = [&](const float4 p) {
+                const float dx = p.x - px, dy = p.y - py, dz = p.z - pz;
+                float r2 = dx * dx;
+                r2 = __builtin_fmaf(dy, dy, r2);
+                r2 = __builtin_fmaf(dz, dz, r2);
+                const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
+                const unsigned u = __float_as_uint(s);
+                const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
+                const float ds = s - __uint_as_float(u & hmask);
+                const float2 g01 = stab[k];
+                const float g = __builtin_fmaf(g01.y, ds, g01.x);
+                float wd = wx * dx;
+                wd = __builtin_fmaf(wy, dy, wd);
+                wd = __builtin_fmaf(wz, dz, wd);
+                S = __builtin_fmaf(p.w, g, S);
+                const float q = p.w * g01.y * wd;
+                Vx = __builtin_fmaf(q, dx, Vx);
+                Vy = __builtin_fmaf(q, dy, Vy);
+                Vz = __builtin_fmaf(q, dz, Vz);
+            };
+            load(0);
+            for (int base = 0; base < tk.n_j; base += 64) {
+                wave_sync();
+                tile[lane] = pre;
+                wave_sync();
+                if (base + 64 < tk.n_j) load(base + 64);
+                const int cnt = min(64, tk.n_j - base);
+                if (cnt == 64) {
+                    const int full = 64 >> jlog;
+#pragma unroll 4
+                    for (int jj = 0; jj < full; ++jj) pair(tile[(jj << jlog) + ph]);
+                } else {
+                    const int trips = (cnt + js - 1) >> jlog;
+                    for (int jj = 0; jj < trips; ++jj) pair(tile[(jj << jlog) + ph]);
+                }
+            }
+            auto lanes_sum = [&](float &v) {
+                if (jlog >= 2) v += __shfl_xor(v, 16);
+                if (jlog >= 1) v += __shfl_xor(v, 32);
+            };
+            lanes_sum(S), lanes_sum(Vx), lanes_sum(Vy), lanes_sum(Vz);
+            if (active && ph == 0) {
+                atomicAdd(&A.gxi[i], -__builtin_fmaf(c2, Vx, S * wx));
+                atomicAdd(&A.gyi[i], -__builtin_fmaf(c2, Vy, S * wy));
+                atomicAdd(&A.gzi[i], -__builtin_fmaf(c2, Vz, S * wz));
             }
         }
-        if (jlog >= 2) G += __shfl_xor(G, 16);
-        if (jlog >= 1) G += __shfl_xor(G, 32);
-        if (want_m && active && ph == 0) atomicAdd(&A.gmj[j], G);
         t = __builtin_amdgcn_readfirstlane(tn);
     }
     if (want_tab) {
@@ -518,19 +618,23 @@ __global__ void __launch_bounds__(256) k_table_bwd_sum(int n, const float *__res
     gtable[k] = v;
 }
 
-// Zeroes the gradient copies, the mass gradient and the task counter ahead
-// of k_table_bwd (a kernel rather than memsets, so the sequence can be
-// captured in a graph).
-__global__ void __launch_bounds__(256) k_table_bwd_prologue(float *gtable, int n1, float *gmj,
-                                                            int n2, unsigned *queue)
+// Zeroes the gradient copies, the per-entry gradients and the task counter
+// ahead of k_table_bwd (a kernel rather than memsets, so the sequence can be
+// captured in a graph).  Up to 8 arrays of the given lengths (NULL: skipped).
+struct ZeroList {
+    float *p[8];
+    int n[8];
+};
+
+__global__ void __launch_bounds__(256) k_table_bwd_prologue(ZeroList z, unsigned *queue)
 {
     const int stride = gridDim.x * 256;
     const int t0 = blockIdx.x * 256 + threadIdx.x;
     if (t0 == 0) *queue = 0u;
-    if (gtable)
-        for (int k = t0; k < n1; k += stride) gtable[k] = 0.f;
-    if (gmj)
-        for (int k = t0; k < n2; k += stride) gmj[k] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (z.p[q])
+            for (int k = t0; k < z.n[q]; k += stride) z.p[q][k] = 0.f;
 }
 
 int resident(const void *k, size_t lds)
@@ -600,22 +704,35 @@ hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 
 }
 
 hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int n_jtasks,
-                                  int nj_total, unsigned *queue, int num_cu, hipStream_t s)
+                                  const Task *itasks, int n_itasks, unsigned *queue, int num_cu,
+                                  hipStream_t s)
 {
     const int K = 1 << (A.b.E + A.b.F);
-    const int n1 = A.gtable ? kGradCopies * 2 * K : 0;
-    const int n2 = A.gmj ? nj_total : 0;
-    const int zb = std::max(1, std::min(1024, (std::max(n1, n2) + 255) / 256));
-    hipLaunchKernelGGL(k_table_bwd_prologue, dim3(zb), dim3(256), 0, s,
-                       A.gtable ? A.gcopies : nullptr, n1, A.gmj, n2, queue);
+    ZeroList z{};
+    int nz = 0, longest = 0;
+    auto add = [&](float *p, int n) {
+        if (!p || n <= 0) return;
+        z.p[nz] = p;
+        z.n[nz++] = n;
+        longest = std::max(longest, n);
+    };
+    add(A.gtable ? A.gcopies : nullptr, kGradCopies * 2 * K);
+    add(A.gmj, A.nj_total);
+    add(A.gxj, A.nj_total), add(A.gyj, A.nj_total), add(A.gzj, A.nj_total);
+    add(A.gxi, A.ni_total), add(A.gyi, A.ni_total), add(A.gzi, A.ni_total);
+    const int zb = std::max(1, std::min(1024, (longest + 255) / 256));
+    hipLaunchKernelGGL(k_table_bwd_prologue, dim3(zb), dim3(256), 0, s, z, queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (n_jtasks > 0) {
+    const bool jside = A.gtable || A.gmj || A.gxj;
+    const int n_m = jside ? n_jtasks : 0;
+    const int n_i = A.gxi ? n_itasks : 0;
+    if (n_m + n_i > 0) {
         const size_t lds = (size_t)K * 4 * sizeof(float);
         const int cap = num_cu * resident((const void *)k_table_bwd, lds);
-        const int blocks = std::max(1, std::min(cap, (n_jtasks + 3) / 4));
-        hipLaunchKernelGGL(k_table_bwd, dim3(blocks), dim3(256), lds, s, A, jtasks, n_jtasks,
-                           queue);
+        const int blocks = std::max(1, std::min(cap, (n_m + n_i + 3) / 4));
+        hipLaunchKernelGGL(k_table_bwd, dim3(blocks), dim3(256), lds, s, A, jtasks, n_m, itasks,
+                           n_i, queue);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (A.gtable) {

@@ -25,8 +25,10 @@ struct pgh_plan {
     unsigned *queue;        // device, one counter per sublist, zero between launches
     float4 *partial;        // device, 64 partial sums per slot
     SplitChunk *chunks;     // device, the split chunks
-    int n_jtasks;           // j-major tasks (adjoint of the masses)
+    int n_jtasks;           // j-major tasks of the table adjoint
     Task *jtasks;           // device
+    int n_itasks;           // i-major tasks of the table adjoint (i-side positions)
+    Task *itasks;           // device
     unsigned *jqueue;       // device, counter of the j-major tasks
 };
 
@@ -114,6 +116,7 @@ void free_plan_memory(pgh_plan *p)
     (void)hipFree(p->chunks);
     (void)hipFree(p->jtasks);
     (void)hipFree(p->jqueue);
+    (void)hipFree(p->itasks);
 }
 
 // Grows a scratch buffer of float4 records (synchronises before freeing).
@@ -642,6 +645,22 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     p->chunks = nullptr;
     p->jtasks = nullptr;
     p->jqueue = nullptr;
+    p->itasks = nullptr;
+    // i-major tasks of the table adjoint (the i-side position gradient, its
+    // own list independent of the forward's chunking): i-chunks of <= 64
+    // against j-ranges of <= 512, added with atomics, so no partial sums
+    std::vector<Task> it_tasks;
+    for (int t : order) {
+        const pgh_item &it = items[t];
+        for (int s0 = 0; s0 < it.n_i; s0 += 64)
+            for (int q0 = 0; q0 < it.n_j; q0 += 512)
+                it_tasks.push_back({it.i_off + s0, std::min(64, it.n_i - s0), it.j_off + q0,
+                                    std::min(512, it.n_j - q0), 0, 1, 0, 0, 0, 0, 0, 0});
+    }
+    std::stable_sort(it_tasks.begin(), it_tasks.end(), [](const Task &a, const Task &b) {
+        return (long long)a.n_j * ((a.n_i + 15) / 16) > (long long)b.n_j * ((b.n_i + 15) / 16);
+    });
+    p->n_itasks = (int)it_tasks.size();
     // j-major tasks of the table adjoint: chunks of <= 64 j-entries of a
     // list against its i-group (chunks of 32 or 16, 2 or 4 lanes per entry,
     // when chunks of 64 would fill less than half of the resident waves)
@@ -683,6 +702,13 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
         return cleanup(PGH_ENOMEM, "hipMalloc(queue) failed");
     if (!jt.empty() && hipMalloc((void **)&p->jtasks, jt.size() * sizeof(Task)) != hipSuccess)
         return cleanup(PGH_ENOMEM, "hipMalloc(tasks) failed");
+    if (!it_tasks.empty() &&
+        hipMalloc((void **)&p->itasks, it_tasks.size() * sizeof(Task)) != hipSuccess)
+        return cleanup(PGH_ENOMEM, "hipMalloc(tasks) failed");
+    if (!it_tasks.empty() &&
+        hipMemcpyAsync(p->itasks, it_tasks.data(), it_tasks.size() * sizeof(Task),
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return cleanup(PGH_EHIP, "uploading the plan failed");
 
     if (hipMemsetAsync(p->jqueue, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
         (!jt.empty() && hipMemcpyAsync(p->jtasks, jt.data(), jt.size() * sizeof(Task),
@@ -868,13 +894,16 @@ int pgh_newton_ij_bwd(pgh_ctx *c, int ni, const float *xi, const float *yi, cons
 int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
                         const float *zi, const float *xj, const float *yj, const float *zj,
                         const float *mj, const float *wx, const float *wy, const float *wz,
-                        float *gtable, float *gmj)
+                        float *gtable, float *gmj, float *gxi, float *gyi, float *gzi,
+                        float *gxj, float *gyj, float *gzj)
 {
     if (!c) return PGH_EINVAL;
     int st = check_plan(c, p);
     if (st) return st;
     if (!c->tab_set) return fail(c, PGH_ESTATE, "no force table set");
-    if (!gtable && !gmj) return PGH_OK;
+    if ((!gxi) != (!gyi) || (!gxi) != (!gzi) || (!gxj) != (!gyj) || (!gxj) != (!gzj))
+        return fail(c, PGH_EINVAL, "position gradients come in x, y, z triples");
+    if (!gtable && !gmj && !gxi && !gxj) return PGH_OK;
     if (p->ni_total > 0 && (!xi || !yi || !zi || !wx || !wy || !wz))
         return fail(c, PGH_EINVAL, "NULL i-particle or weight array");
     if (p->nj_total > 0 && (!xj || !yj || !zj || !mj))
@@ -895,8 +924,12 @@ int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const fl
     A.gtable = gtable;
     A.gmj = gmj;
     A.gcopies = c->gcopy;
-    PGH_HIP(c, launch_table_batch_bwd(A, p->jtasks, p->n_jtasks, p->nj_total, p->jqueue, c->num_cu,
-                                      c->stream));
+    A.gxi = gxi, A.gyi = gyi, A.gzi = gzi;
+    A.gxj = gxj, A.gyj = gyj, A.gzj = gzj;
+    A.ni_total = p->ni_total;
+    A.nj_total = p->nj_total;
+    PGH_HIP(c, launch_table_batch_bwd(A, p->jtasks, p->n_jtasks, p->itasks, p->n_itasks, p->jqueue,
+                                      c->num_cu, c->stream));
     return PGH_OK;
 }
 

@@ -109,6 +109,9 @@ struct TableBwdArgs {
     float *gtable;   // 2K floats
     float *gmj;
     float *gcopies;  // kGradCopies x 2K floats (context scratch)
+    float *gxi, *gyi, *gzi;  // i-side position gradient (or NULL)
+    float *gxj, *gyj, *gzj;  // j-side position gradient (or NULL)
+    int ni_total, nj_total;
 };
 
 // Kernel launchers (defined in the .hip files).
@@ -168,6 +171,7 @@ hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 
 // Zeroes gtable / gmj and `queue`, then runs both adjoint passes in one
 // persistent launch that takes tasks from `queue`.
 hipError_t launch_table_batch_bwd(const TableBwdArgs &a, const Task *jtasks, int n_jtasks,
-                                  int nj_total, unsigned *queue, int num_cu, hipStream_t s);
+                                  const Task *itasks, int n_itasks, unsigned *queue, int num_cu,
+                                  hipStream_t s);
 
 }  // namespace pgh

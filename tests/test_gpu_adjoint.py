@@ -183,8 +183,8 @@ def test_table_adjoint_cell_lists(pgh, ctx):
 
 
 def test_autograd_table_force(pgh, ctx):
-    """TableForceBatch: gradients of the table and masses equal the direct
-    adjoint call; asking for position gradients raises."""
+    """TableForceBatch: gradients of the table, the masses and the i- and
+    j-positions against the oracle."""
     import torch
     n = 8192
     x, y, z = synth.uniform_box(n, 9)
@@ -205,10 +205,16 @@ def test_autograd_table_force(pgh, ctx):
                                           float(np.float32(rcut)), table, scales=True)
     _table_gate(to_host(tab.grad)[0], rt, at, E, F, "gtable")
     _gate(to_host(mj.grad)[0], rm, am, "gmj")
-    xr = di[0].clone().requires_grad_(True)
-    ax, ay, az = pgh.table_force_batch(plan, E, F, rcut, tab, xr, di[1], di[2], *dj, mj)
-    with pytest.raises(NotImplementedError):
-        ax.sum().backward()
+    # position gradients through autograd
+    xi_ = [t.clone().requires_grad_(True) for t in di]
+    xj_ = [t.clone().requires_grad_(True) for t in dj]
+    ax, ay, az = pgh.table_force_batch(plan, E, F, rcut, tab.detach(), *xi_, *xj_, mj.detach())
+    (ax * w[0] + ay * w[1] + az * w[2]).sum().backward()
+    r = oracle.lut_bwd_pos_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj,
+                                 *[to_host(t)[0] for t in w], E, F, float(np.float32(rcut)), table,
+                                 scales=True)
+    _gate(np.stack([to_host(t.grad)[0] for t in xi_]), np.stack(r[0:3]), r[6], "gxi")
+    _gate(np.stack([to_host(t.grad)[0] for t in xj_]), np.stack(r[3:6]), r[7], "gxj")
 
 
 def test_table_adjoint_partial_outputs_and_repeats(pgh, ctx):
@@ -286,3 +292,42 @@ def test_self_potential_correction(pgh, ctx):
         assert rms(ep) <= 1e-5 and ep.max() <= 1e-3, (rms(ep), ep.max())
     phi2 = pgh.correct_self_potential(torch.zeros(n, device="cuda"), d[3], eps=0.5, lib_ctx=ctx)
     assert np.allclose(to_host(phi2)[0], m / np.float32(0.5), rtol=1e-6)
+
+
+@pytest.mark.parametrize("block", [4, 8])
+def test_table_position_gradients_cell_lists(pgh, ctx, block):
+    """i- and j-side position gradients of the table force on cell lists
+    (N = 16384 uniform in the unit periodic box, 32^3 cells, S2 table with
+    rcut = 1/32, E = 4, F = 6), alone and together with the table and mass
+    gradients, against the oracle."""
+    import torch
+    n = 16384
+    x, y, z = synth.uniform_box(n, 41)
+    m = synth.equal_masses(n)
+    rcut, eps, E, F = 1.0 / 32, 1.0 / 32 / 15, 4, 6
+    s = synth.cell_grid_items(x, y, z, m, ncell=32, block=block)
+    table = ctx.build_table(E, F, rcut, eps=eps)
+    w = synth.weights(n, 42)
+    plan = ctx.plan(s.items, n, s.xj.size)
+    di = to_dev(s.xi, s.yi, s.zi, *w)
+    dj = to_dev(s.xj, s.yj, s.zj, s.mj)
+    r = oracle.lut_bwd_pos_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, *w, E, F,
+                                 float(np.float32(rcut)), table, scales=True)
+    rt, rm, at, am = oracle.lut_bwd_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, *w,
+                                          E, F, float(np.float32(rcut)), table, scales=True)
+    for with_rest in (False, True):
+        gi = [torch.full((n,), 7.0, device="cuda") for _ in range(3)]
+        gj = [torch.full((s.xj.size,), 7.0, device="cuda") for _ in range(3)]
+        gt = torch.empty(table.size, device="cuda") if with_rest else None
+        gm = torch.empty(s.xj.size, device="cuda") if with_rest else None
+        pgh.pgh_batch_table_bwd(ctx.h, plan.h, di[0], di[1], di[2], *dj, di[3], di[4], di[5],
+                                gt, gm, *gi, *gj)
+        _gate(np.stack(to_host(*gi)), np.stack(r[0:3]), r[6], "gxi")
+        _gate(np.stack(to_host(*gj)), np.stack(r[3:6]), r[7], "gxj")
+        assert np.all(np.isfinite(np.stack(to_host(*gi))))
+        if with_rest:
+            _table_gate(to_host(gt)[0], rt, at, E, F, "gtable")
+            _gate(to_host(gm)[0], rm, am, "gmj")
+    with pytest.raises(pgh.PGHError):  # triples only
+        pgh.pgh_batch_table_bwd(ctx.h, plan.h, di[0], di[1], di[2], *dj, di[3], di[4], di[5],
+                                None, None, gi[0], None, None)

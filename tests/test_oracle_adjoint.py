@@ -167,3 +167,35 @@ def test_table_gradient_chain_to_node_values_matches_central_differences():
         fd[k] = loss(p) - loss(q)
     assert np.allclose(chained, fd, rtol=1e-9, atol=1e-12 * np.abs(fd).max())
     assert np.any(gt[1::2] != 0)  # the slope terms take part
+
+
+def test_table_position_gradients_match_central_differences():
+    """The table force is piecewise smooth in the positions (g is linear in
+    s inside a bin, s = c |d|^2 + 2): central differences of the oracle's
+    forward sum, with h small enough that no pair crosses a node, equal
+    gxi + gxj of a particle that is both an i- and a j-particle."""
+    E, F, rcut, eps = 3, 3, 0.3, 0.02
+    t = oracle.table_build(E, F, rcut, oracle.SHAPE_S2PP, eps).astype(np.float64)
+    n = 40
+    x, y, z = [a.astype(np.float64) for a in synth.uniform_box(n, 8, box=0.5)]
+    m = np.linspace(0.5, 1.5, n)
+    w = [np.random.default_rng(4).standard_normal(n) for _ in range(3)]
+    items = np.array([[0, 20, 0, 40], [20, 20, 10, 25]], np.int32)
+    g = oracle.lut_bwd_pos_items(items, x, y, z, x, y, z, m, *w, E, F, rcut, t, scales=True)
+    tot = np.stack(g[0:3]) + np.stack(g[3:6])
+    scale = g[6] + g[7]
+
+    def loss(P):
+        ax, ay, az, _ = oracle.lut_items(items, *P, *P, m, E, F, rcut, t)
+        return float(np.sum(w[0] * ax + w[1] * ay + w[2] * az))
+
+    h = 1e-8
+    X = [x, y, z]
+    for ax_ in range(3):
+        for k in range(n):
+            p = [a.copy() for a in X]; q = [a.copy() for a in X]
+            p[ax_][k] += h; q[ax_][k] -= h
+            fd = (loss(p) - loss(q)) / (2 * h)
+            assert abs(fd - tot[ax_, k]) <= 1e-6 * max(scale[k], 1e-12), (ax_, k, fd, tot[ax_, k])
+    assert np.abs(tot).max() > 0
+    assert np.all(np.linalg.norm(np.stack(g[0:3]), axis=0) <= g[6] * (1 + 1e-12))
