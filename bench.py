@@ -273,6 +273,51 @@ def newton_small(torch, pgh, synth):
             "interactions_per_s": n * n / (ms / 1e3)}
 
 
+def ni_nj_sweep(torch, pgh, synth):
+    """Throughput against group and list size (the small N_i / N_j regime of
+    tree codes with individual time steps): lists of n_i i-particles (a
+    Plummer sphere of 2^21, consecutive groups) against n_j j-particles
+    (consecutive windows of the same sphere), eps = 1e-3, about 2^31
+    interactions per launch (at most 131072 lists).  Each point runs the
+    lists two ways: GRAPE-style, one pgh_set_n + pgh_calc_newton per list
+    against a j-memory holding the whole pool (timed over a sample of
+    lists), and all lists in one persistent batched launch (graph replay)."""
+    n = 1 << 21
+    x, y, z = synth.plummer(n, 106)
+    m = synth.equal_masses(n)
+    d = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+    ctx = pgh.Context(0)
+    ctx.set_eps_to_all(1e-3)
+    out = [torch.empty(n, device="cuda") for _ in range(4)]
+    res = []
+    for ni in (16, 64, 256, 1024):
+        for nj in (64, 512, 4096):
+            n_items = int(min(131072, n // ni, max(1, (1 << 31) // (ni * nj))))
+            items = np.array([[k * ni, ni, (k * 7919) % (n - nj), nj] for k in range(n_items)],
+                             np.int32)
+            plan = ctx.plan(items, n, n)
+            ms = graph_ms(torch, lambda: plan.newton(*d[:3], *d, out=out), 5)
+            inter = float(plan.interactions)
+            plan.free()
+            # GRAPE-style calls: one list per call, j-memory = that list's window
+            sample = min(n_items, 256)
+            t = KernelTimer(torch)
+            with t:
+                for k in range(sample):
+                    i0, _, j0, _ = items[k]
+                    pgh.pgh_set_xmj(ctx.h, 0, nj, d[0][j0:], d[1][j0:], d[2][j0:], d[3][j0:])
+                    pgh.pgh_set_n(ctx.h, nj)
+                    pgh.pgh_calc_newton(ctx.h, ni, d[0][i0:], d[1][i0:], d[2][i0:], None,
+                                        out[0][i0:], out[1][i0:], out[2][i0:], out[3][i0:])
+            call_ms = t.mean_ms() / sample
+            res.append({"n_i": ni, "n_j": nj, "lists": n_items,
+                        "batched_interactions_per_s": inter / (ms / 1e3),
+                        "per_call_interactions_per_s": ni * nj / (call_ms / 1e3),
+                        "per_call_us": call_ms * 1e3})
+    ctx.close()
+    return res
+
+
 def batched_newton(torch, pgh, synth):
     """Tree-style lists: 16384 (i-group, j-list) items over a Morton-sorted
     Plummer sphere of 2^22 particles, eps = 1e-3, i-groups uniform in
@@ -404,9 +449,10 @@ def adjoint_newton(torch, pgh, synth):
 
 
 def adjoint_table(torch, pgh, synth):
-    """Table-force forward and adjoint (table entries and masses) on cell
-    lists: N = 65536 uniform in the unit periodic box, 64^3 cells, 8^3-cell
-    groups, S2 PP shape (rcut = 3/256, eps = 1/1280, E = 4, F = 6)."""
+    """Table-force forward and adjoint on cell lists: N = 65536 uniform in the
+    unit periodic box, 64^3 cells, 8^3-cell groups, S2 PP shape (rcut = 3/256,
+    eps = 1/1280, E = 4, F = 6); the adjoint with respect to the table entries
+    and masses, and also with the i- and j-position gradients."""
     n = 65536
     x, y, z = synth.uniform_box(n, 105)
     m = synth.equal_masses(n)
@@ -422,12 +468,18 @@ def adjoint_table(torch, pgh, synth):
     gm = torch.empty(s.xj.size, device="cuda")
     f_ms = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 50)
     b_ms = graph_ms(torch, lambda: pgh.pgh_batch_table_bwd(ctx.h, plan.h, *di, *dj, *w, gt, gm), 50)
+    gi = [torch.empty(n, device="cuda") for _ in range(3)]
+    gj = [torch.empty(s.xj.size, device="cuda") for _ in range(3)]
+    bx_ms = graph_ms(torch, lambda: pgh.pgh_batch_table_bwd(ctx.h, plan.h, *di, *dj, *w, gt, gm,
+                                                            *gi, *gj), 50)
     inter = float(plan.interactions)
     plan.free()
     ctx.close()
     return {"workload": "table_adjoint_cell_lists_N65536_8cube_groups_E4F6",
             "interactions": inter, "fwd_ms": f_ms, "bwd_ms": b_ms,
-            "fwd_plus_bwd_over_fwd": (f_ms + b_ms) / f_ms}
+            "fwd_plus_bwd_over_fwd": (f_ms + b_ms) / f_ms,
+            "bwd_with_positions_ms": bx_ms,
+            "fwd_plus_bwd_with_positions_over_fwd": (f_ms + bx_ms) / f_ms}
 
 
 def table_allpairs(torch, pgh, synth):
@@ -526,7 +578,8 @@ def main():
               "newton_batched": batched_newton(torch, pgh, synth),
               "table_batched": batched_table(torch, pgh, synth),
               "adjoint_newton": adjoint_newton(torch, pgh, synth),
-              "adjoint_table": adjoint_table(torch, pgh, synth)}
+              "adjoint_table": adjoint_table(torch, pgh, synth),
+              "ni_nj_sweep": ni_nj_sweep(torch, pgh, synth)}
         ex["batched_over_allpairs"] = ex["newton_batched"]["interactions_per_s"] / value
         line["extras"] = ex
     if not args.no_cpu:
