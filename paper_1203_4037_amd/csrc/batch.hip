@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 #include "pairs.h"
@@ -179,17 +180,29 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
             const int trips = (cnt + js - 1) >> jlog;
             float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;
             if (cnt == 64) {
-                // a full tile: 64 / js records per lane, this lane's phase
-                const int full = 64 >> jlog;
+                // a full tile: 64 / js records per lane from this lane's
+                // phase, with the stride a compile-time constant so the LDS
+                // reads take immediate offsets
+                auto full_tile = [&](auto stride) {
+                    constexpr int S = decltype(stride)::value;
+                    const float4 *b = src + ph;
 #pragma unroll 4
-                for (int it = 0; it < full; ++it) {
-                    const float4 p = src[(it << jlog) + ph];
-                    if (KIND == 0)
-                        newton_pair<REFINE, GUARD, PHI, ALT>(p, px, py, pz, pe, sx, sy, sz, sp);
-                    else
-                        table_pair<ALT>(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask, sx,
-                                        sy, sz);
-                }
+                    for (int it = 0; it < 64 / S; ++it) {
+                        const float4 p = b[it * S];
+                        if (KIND == 0)
+                            newton_pair<REFINE, GUARD, PHI, ALT>(p, px, py, pz, pe, sx, sy, sz,
+                                                                 sp);
+                        else
+                            table_pair<ALT>(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask,
+                                            sx, sy, sz);
+                    }
+                };
+                if (jlog == 0)
+                    full_tile(std::integral_constant<int, 1>{});
+                else if (jlog == 1)
+                    full_tile(std::integral_constant<int, 2>{});
+                else
+                    full_tile(std::integral_constant<int, 4>{});
             } else {
 #pragma unroll 2
                 for (int it = 0; it < trips; ++it) {
