@@ -283,10 +283,11 @@ const char *newton_allpairs_variant_name(int v)
 
 int newton_allpairs_default(int ni, int nj, int num_cu)
 {
-    (void)nj;
-    // Prefer two i per lane when that still gives every SIMD a wave or more.
-    const long waves_ki2 = (long)(ni + 127) / 128;
-    return waves_ki2 >= 4L * num_cu ? 1 : 0;
+    (void)ni, (void)nj, (void)num_cu;
+    // One i per lane, 256-record tiles, unrolled by 8: the fastest measured
+    // at every size (small ni is spread over the j-split); pgh_autotune
+    // confirms or replaces it for a given workload.
+    return 0;
 }
 
 int newton_allpairs_split(int ni, int nj, int variant, size_t part_cap)

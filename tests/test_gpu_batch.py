@@ -218,7 +218,6 @@ def test_cell_list_table_config_full(pgh, ctx):
     table = ctx.build_table(4, 6, rcut, eps=eps)
     di, dj = _dev_set(s)
     plan = ctx.plan(s.items, n, s.xj.size)
-    a = np.stack(to_host(*plan.table(*di, *dj)))
     rng = np.random.default_rng(0)
     pick = np.unique(np.concatenate([[0, len(s.items) - 1], rng.integers(0, len(s.items), 94)]))
     items = s.items[pick]
@@ -226,10 +225,13 @@ def test_cell_list_table_config_full(pgh, ctx):
                           float(np.float32(rcut)), table)
     rows = np.concatenate([np.arange(i0, i0 + ni) for i0, ni, _, _ in items])
     has = rt[3][rows] > 0
-    e1 = norm_vec_err(a[:, rows][:, has], np.stack(rt[:3])[:, rows][:, has], rt[3][rows][has])
-    assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (rms(e1), e1.max())
-    assert np.all(a[:, rows][:, ~has] == 0.0)
-    assert np.all(np.isfinite(a))
+    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH)):
+        ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, v)
+        a = np.stack(to_host(*plan.table(*di, *dj)))
+        e1 = norm_vec_err(a[:, rows][:, has], np.stack(rt[:3])[:, rows][:, has], rt[3][rows][has])
+        assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (v, rms(e1), e1.max())
+        assert np.all(a[:, rows][:, ~has] == 0.0)
+        assert np.all(np.isfinite(a))
 
 
 def test_tree_style_config_full(pgh, ctx):
@@ -242,7 +244,9 @@ def test_tree_style_config_full(pgh, ctx):
     rng = np.random.default_rng(1)
     pick = np.unique(np.concatenate([[np.argmax(cost), np.argmin(cost), np.argmax(s.items[:, 3])],
                                      rng.integers(0, len(s.items), 45)]))
-    _newton_case(pgh, ctx, s, 1e-3, sample_items=pick)
+    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_NEWTON_BATCH)):
+        ctx.set_variant(pgh.PGH_FAMILY_NEWTON_BATCH, v)
+        _newton_case(pgh, ctx, s, 1e-3, sample_items=pick)
 
 
 def test_plan_autotuner(pgh, ctx):

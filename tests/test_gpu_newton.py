@@ -70,19 +70,24 @@ def test_plummer_1k_all_variants(pgh, ctx, refine):
 
 
 def test_plummer_256k_sampled(pgh, ctx):
-    """N = 262144 Plummer sphere (seed 102), eps = 0.01, full GPU launch; the
-    oracle recomputes a sample of 384 i-particles against all j."""
+    """N = 262144 Plummer sphere (seed 102), eps = 0.01, full GPU launch of
+    every variant (so whichever the autotuner picks for this workload is
+    covered) and the built-in default; the oracle recomputes a sample of 384
+    i-particles against all j."""
     n = 262144
     x, y, z = synth.plummer(n, 102)
     m = synth.equal_masses(n)
     eps = np.float32(0.01)
-    a, phi = _gpu_newton(ctx, x, y, z, x, y, z, m, eps=eps)
     rng = np.random.default_rng(5)
     idx = np.unique(np.concatenate([[0, 1, 255, 256, n - 257, n - 1], rng.integers(0, n, 378)]))
     e2 = np.full(idx.size, eps * eps, np.float32)
     ref = oracle.newton(x[idx], y[idx], z[idx], e2, x, y, z, m)
-    _check(a[:, idx], phi[idx], ref, "N=262144 sample")
-    assert np.all(np.isfinite(a)) and np.all(np.isfinite(phi))
+    fam = pgh.PGH_FAMILY_NEWTON_ALLPAIRS
+    for v in [-1] + list(range(pgh.pgh_variant_count(fam))):
+        ctx.set_variant(fam, v)
+        a, phi = _gpu_newton(ctx, x, y, z, x, y, z, m, eps=eps)
+        _check(a[:, idx], phi[idx], ref, f"N=262144 sample, variant {v}")
+        assert np.all(np.isfinite(a)) and np.all(np.isfinite(phi))
 
 
 @pytest.mark.parametrize("ni,nj", [(1, 1), (3, 3), (63, 255), (65, 257), (257, 1), (1000, 1000),
