@@ -273,6 +273,34 @@ def newton_small(torch, pgh, synth):
             "interactions_per_s": n * n / (ms / 1e3)}
 
 
+def grape5_host(torch, pgh, synth, n=262144):
+    """The GRAPE-5-compatible host interface on the headline workload
+    (Plummer N = 262144, eps = 0.01): g5_set_xmj + g5_calculate_force_on_x on
+    host double arrays, wall-clock time per step including the conversions
+    and PCIe transfers (the device-array entry points avoid those)."""
+    x, y, z = synth.plummer(n, 102)
+    xs = np.ascontiguousarray(np.stack([x, y, z], axis=1).astype(np.float64))
+    m = synth.equal_masses(n).astype(np.float64)
+    a = np.zeros((n, 3))
+    p = np.zeros(n)
+    pgh.g5_open()
+    pgh.g5_set_eps_to_all(0.01)
+    pgh.g5_set_n(n)
+
+    def step():
+        pgh.g5_set_xmj(0, n, xs, m)
+        pgh.g5_calculate_force_on_x(xs, a, p, n)
+
+    step()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        step()
+    sec = (time.perf_counter() - t0) / 3
+    pgh.g5_close()
+    return {"workload": "grape5_host_arrays_plummer_N262144_eps0.01", "ms_per_step": sec * 1e3,
+            "interactions_per_s_incl_pcie": float(n) * n / sec}
+
+
 def ni_nj_sweep(torch, pgh, synth):
     """Throughput against group and list size (the small N_i / N_j regime of
     tree codes with individual time steps): lists of n_i i-particles (a
@@ -579,7 +607,8 @@ def main():
               "table_batched": batched_table(torch, pgh, synth),
               "adjoint_newton": adjoint_newton(torch, pgh, synth),
               "adjoint_table": adjoint_table(torch, pgh, synth),
-              "ni_nj_sweep": ni_nj_sweep(torch, pgh, synth)}
+              "ni_nj_sweep": ni_nj_sweep(torch, pgh, synth),
+              "grape5_host": grape5_host(torch, pgh, synth)}
         ex["batched_over_allpairs"] = ex["newton_batched"]["interactions_per_s"] / value
         line["extras"] = ex
     if not args.no_cpu:

@@ -64,7 +64,8 @@ enum pgh_kind {
 /* Opens a context on HIP device `device` (g5_open).  `hip_stream` is a
  * hipStream_t the calls run on (NULL: the default stream).  Nothing of the
  * approximate-rsqrt bias calibration of g5_open is needed: the kernels use
- * the hardware rsqrt (about 1 ulp) followed by one Newton-Raphson step.
+ * the hardware rsqrt, accurate to about 1 ulp (pgh_set_rsqrt_refine adds a
+ * Newton-Raphson step).
  * On failure *out is NULL and the message is available from
  * pgh_last_error(NULL). */
 PGH_API int pgh_open(pgh_ctx **out, int device, void *hip_stream);

@@ -79,6 +79,16 @@ SIGNATURES = {
     "pgh_autotune_plan": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _I, ctypes.POINTER(_F)]),
     "pgh_correct_self_potential": (_I, [_P, _I, _P, _P, _P]),
     "pgh_table_grad_chain": (_I, [_P, _I, _I, _P, _P]),
+    # GRAPE-5-compatible host interface (include/grape5.h)
+    "g5_open": (None, []),
+    "g5_close": (None, []),
+    "g5_set_eps_to_all": (None, [ctypes.c_double]),
+    "g5_set_n": (None, [_I]),
+    "g5_set_xmj": (None, [_I, _I, _P, _P]),
+    "g5_calculate_force_on_x": (None, [_P, _P, _P, _I]),
+    "g5_set_force_table": (_I, [_I, _I, ctypes.c_double, _P]),
+    "g5_use_newton": (None, []),
+    "g5_last_error": (ctypes.c_char_p, []),
 }
 
 
@@ -345,6 +355,75 @@ def pgh_autotune_plan(ctx, family, plan, xi, yi, zi, xj, yj, zj, mj, reps=3):
     if v < 0:
         _check(ctx, v)
     return v, ms.value
+
+
+# --------------------------------------------------------------------------
+# GRAPE-5-compatible host interface (host numpy arrays in double precision)
+# --------------------------------------------------------------------------
+
+G5_F_OVER_R = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_double)
+
+
+def _host_f64(a, shape_tail, what):
+    import numpy as np
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise TypeError(f"{what} must be a C-contiguous float64 numpy array")
+    if a.shape[1:] != shape_tail:
+        raise ValueError(f"{what} has shape {a.shape}")
+    return a.ctypes.data
+
+
+def _g5_check():
+    e = lib.g5_last_error()
+    if e:
+        raise PGHError(PGH_EHIP, e.decode())
+
+
+def g5_open():
+    lib.g5_open()
+    _g5_check()
+
+
+def g5_close():
+    lib.g5_close()
+
+
+def g5_set_eps_to_all(eps):
+    lib.g5_set_eps_to_all(float(eps))
+    _g5_check()
+
+
+def g5_set_n(nj):
+    lib.g5_set_n(int(nj))
+    _g5_check()
+
+
+def g5_set_xmj(adr, nj, xj, mj):
+    """xj: float64 (n, 3), mj: float64 (n,), host arrays."""
+    if xj.shape[0] < nj or mj.shape[0] < nj:
+        raise ValueError("arrays shorter than nj")
+    lib.g5_set_xmj(int(adr), int(nj), _host_f64(xj, (3,), "xj"), _host_f64(mj, (), "mj"))
+    _g5_check()
+
+
+def g5_calculate_force_on_x(xi, ai, pi, ni):
+    """xi, ai: float64 (n, 3); pi: float64 (n,) or None; host arrays."""
+    if xi.shape[0] < ni or ai.shape[0] < ni or (pi is not None and pi.shape[0] < ni):
+        raise ValueError("arrays shorter than ni")
+    lib.g5_calculate_force_on_x(_host_f64(xi, (3,), "xi"), _host_f64(ai, (3,), "ai"),
+                                None if pi is None else _host_f64(pi, (), "pi"), int(ni))
+    _g5_check()
+
+
+def g5_set_force_table(E, F, rcut, f_over_r):
+    """f_over_r: a G5_F_OVER_R (keep a reference while the table is built)."""
+    st = lib.g5_set_force_table(int(E), int(F), float(rcut), ctypes.cast(f_over_r, ctypes.c_void_p))
+    if st != PGH_OK:
+        raise PGHError(st, (lib.g5_last_error() or b"").decode())
+
+
+def g5_use_newton():
+    lib.g5_use_newton()
 
 
 def s2pp_callback():

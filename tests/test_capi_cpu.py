@@ -3,6 +3,7 @@ header declares is exported, argument checks return status codes, and the
 host parts of the force path (the table builder and the built-in S2 shape)
 agree with the FP64 oracle."""
 import ctypes
+import glob
 import os
 import re
 
@@ -12,7 +13,7 @@ import pytest
 import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "pgh.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 @pytest.fixture(scope="module")
@@ -22,13 +23,18 @@ def pgh():
 
 
 def _declared():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"PGH_API\s+[\w\s\*]*?\b(pgh_\w+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        names |= set(re.findall(r"PGH_API\s+[\w\s\*]*?\b((?:pgh|g5)_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declarations_are_exported(pgh):
+    """Every entry point that include/*.h declares (pgh.h, grape5.h) is
+    exported by the library and known to the binding."""
     names = _declared()
-    assert len(names) >= 25
+    assert len(names) >= 40 and "g5_calculate_force_on_x" in names
     lib = ctypes.CDLL(pgh.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
@@ -120,3 +126,16 @@ def test_python_callback_table(pgh):
     K = 1 << (E + F)
     for k in range(K - 1):
         assert t[2 * k] == np.float32(1.0 - oracle.node_r(E, F, rcut, k))
+
+
+def test_grape5_calls_without_a_gpu_report_errors(pgh):
+    """The GRAPE-5 calls never abort: without g5_open (or without a GPU)
+    they leave outputs untouched and g5_last_error() says why."""
+    import numpy as np
+    pgh.lib.g5_close()
+    a = np.full((4, 3), 5.0)
+    pgh.lib.g5_calculate_force_on_x(np.zeros((4, 3)).ctypes.data, a.ctypes.data, None, 4)
+    assert pgh.lib.g5_last_error() is not None
+    assert np.all(a == 5.0)
+    pgh.lib.g5_set_eps_to_all(0.1)
+    assert b"g5_open" in pgh.lib.g5_last_error()
