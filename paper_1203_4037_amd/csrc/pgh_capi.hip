@@ -512,7 +512,7 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     for (;;) {
         long long n = 0;
         for (int t : order) n += (items[t].n_i + csize - 1) / csize;
-        if (2 * n >= waves || csize == 16) break;
+        if (n >= waves || csize == 16) break;
         csize /= 2;
     }
     std::vector<Chunk> chunks;
