@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "libpgh_oracle.so")
 
 SHAPE_S2PP = 0
 SHAPE_PLUMMER_TAPER = 1
+SHAPE_SOFT_CUT = 2
 
 
 def build(force: bool = True) -> str:
@@ -64,10 +65,13 @@ def lib():
             "pgo_newton_bwd": [l, P, P, P, P, l, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P],
             "pgo_lut_bwd_items": [l, P, P, P, P, P, P, P, P, P, P, P, i, i, d, P, P, P, l, P, P],
             "pgo_table_grad_chain": [i, i, P, P],
+            "pgo_shape_p": [i, d, P],
+            "pgo_pot_table_build": [i, i, d, i, P, P],
+            "pgo_lut_pot_items": [l, P, P, P, P, P, P, P, P, i, i, d, P, l, P, P],
             "pgo_lut_bwd_pos_items": [l, P, P, P, P, P, P, P, P, P, P, P, i, i, d, P, l, l,
                                       P, P, P, P, P, P, P, P],
         }
-        ret = {"pgo_s2_R": d, "pgo_s2pp_f": d, "pgo_shape_h": d, "pgo_smax": d,
+        ret = {"pgo_s2_R": d, "pgo_s2pp_f": d, "pgo_shape_h": d, "pgo_shape_p": d, "pgo_smax": d,
                "pgo_node_s": d, "pgo_node_r": d, "pgo_lut_index": l, "pgo_lut_eval": d}
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -268,3 +272,32 @@ def lut_bwd_pos_items(items, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, E, F, rcut,
                                 float(rcut), _ptr(t), xi.size, xj.size, *[_ptr(a) for a in out],
                                 _ptr(sc[0]), _ptr(sc[1]))
     return tuple(out) + (tuple(sc) if scales else ())
+
+
+
+def shape_p(shape, r, eps, rcut):
+    p = np.array([eps, rcut], dtype=np.float64)
+    return lib().pgo_shape_p(int(shape), float(r), _ptr(p))
+
+
+def pot_table_build(E, F, rcut, shape, eps):
+    """Interleaved FP32 potential table (P0_0, P1_0, ...) of length 2^(E+F+1)."""
+    K = 1 << (E + F)
+    t = np.zeros(2 * K, dtype=np.float32)
+    p = np.array([eps, rcut], dtype=np.float64)
+    lib().pgo_pot_table_build(E, F, float(rcut), int(shape), _ptr(p), _ptr(t))
+    return t
+
+
+def lut_pot_items(items, xi, yi, zi, xj, yj, zj, mj, E, F, rcut, ptable):
+    """(phi, absum) over the lists from a potential table."""
+    it = _items32(items)
+    xi, yi, zi = map(_f64, (xi, yi, zi))
+    xj, yj, zj, mj = map(_f64, (xj, yj, zj, mj))
+    t = _f64(ptable)
+    phi = np.zeros(xi.size)
+    sa = np.zeros(xi.size)
+    lib().pgo_lut_pot_items(it.shape[0], _ptr(it), _ptr(xi), _ptr(yi), _ptr(zi), _ptr(xj),
+                            _ptr(yj), _ptr(zj), _ptr(mj), E, F, float(rcut), _ptr(t), xi.size,
+                            _ptr(phi), _ptr(sa))
+    return phi, sa

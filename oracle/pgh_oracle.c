@@ -146,8 +146,14 @@ PGO_EXPORT double pgo_s2pp_f(double r, double eps, double rcut)
  *   PGO_SHAPE_PLUMMER_TAPER  h = (r^2+eps^2)^{-3/2} T(r/rcut), T = 1 on
  *                     [0, 1/2], a quintic smoothstep down to 0 at 1: inside
  *                     rcut/2 this is exactly the softened Newtonian f/r.
+ *   PGO_SHAPE_SOFT_CUT  the pair potential p(r) = -u^3 / sqrt(q), u = 1 -
+ *                     r^2/rcut^2, q = r^2 + eps^2 (zero with its derivative
+ *                     at rcut), and h = p'(r)/r = 6 u^2/(rcut^2 sqrt q) +
+ *                     u^3 q^{-3/2}, the f/r of the force a_i = sum_j m_j h d
+ *                     that goes with phi_i = sum_j m_j p (for p = -1/r,
+ *                     h = 1/r^3: Newton).
  */
-enum { PGO_SHAPE_S2PP = 0, PGO_SHAPE_PLUMMER_TAPER = 1 };
+enum { PGO_SHAPE_S2PP = 0, PGO_SHAPE_PLUMMER_TAPER = 1, PGO_SHAPE_SOFT_CUT = 2 };
 
 static double taper(double x)
 {
@@ -165,9 +171,23 @@ PGO_EXPORT double pgo_shape_h(int shape, double r, const double *params)
         if (r == 0.0) return 448.0 / (35.0 * eps * eps * eps) - 448.0 / (35.0 * rcut * rcut * rcut);
         return pgo_s2pp_f(r, eps, rcut) / r;
     }
+    if (shape == PGO_SHAPE_SOFT_CUT) {
+        const double u = 1.0 - r * r / (rcut * rcut), q = r * r + eps * eps;
+        return 6.0 * u * u / (rcut * rcut * sqrt(q)) + u * u * u / (q * sqrt(q));
+    }
     /* PGO_SHAPE_PLUMMER_TAPER */
     const double q = r * r + eps * eps;
     return taper(r / rcut) / (q * sqrt(q));
+}
+
+/* Pair potential p(r) of the shapes that define one (PGO_SHAPE_SOFT_CUT);
+ * 0 at and beyond rcut. */
+PGO_EXPORT double pgo_shape_p(int shape, double r, const double *params)
+{
+    const double eps = params[0], rcut = params[1];
+    if (r >= rcut || shape != PGO_SHAPE_SOFT_CUT) return 0.0;
+    const double u = 1.0 - r * r / (rcut * rcut);
+    return -u * u * u / sqrt(r * r + eps * eps);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -602,6 +622,70 @@ PGO_EXPORT void pgo_lut_bwd_pos_items(long n_items, const int32_t *items, const 
                     if (absj) absj[j] += a;
                 }
             }
+        }
+    }
+}
+
+/*
+ * Potential table on the bins of the force table (the node equation of
+ * Sec. 3.4.1 applied to a pair potential p instead of f/r): P0_k = p(r_k),
+ * 0 at the last node (p vanishes at rcut), P1_k the chord to the next node
+ * from the rounded P0 values; interleaved (P0_0, P1_0, P0_1, ...).
+ */
+PGO_EXPORT void pgo_pot_table_build(int E, int F, double rcut, int shape, const double *params,
+                                    float *table)
+{
+    const long K = 1L << (E + F);
+    for (long k = 0; k < K; k++) {
+        const double r = pgo_node_r(E, F, rcut, k);
+        table[2 * k] = (k == K - 1) ? 0.0f : (float)pgo_shape_p(shape, r, params);
+    }
+    for (long k = 0; k < K - 1; k++) {
+        const double ds = pgo_node_s(E, F, k + 1) - pgo_node_s(E, F, k);
+        table[2 * k + 1] = (float)(((double)table[2 * k + 2] - (double)table[2 * k]) / ds);
+    }
+    table[2 * K - 1] = 0.0f;
+}
+
+/*
+ * Potential from a potential table over interaction lists:
+ * phi_i = sum_j m_j (P0_k + P1_k (s - s_k)), with s and k as for the force
+ * (steps 1-5 of Sec. 3.4.2 on the second table).  absum_i (may be NULL) =
+ * sum_j |m_j| (|P0_k| + |P1_k| (s_{k+1} - s_k)), the scale of the sum.
+ * phi and absum: double[ni_total], zeroed first.
+ */
+PGO_EXPORT void pgo_lut_pot_items(long n_items, const int32_t *items, const double *xi,
+                                  const double *yi, const double *zi, const double *xj,
+                                  const double *yj, const double *zj, const double *mj, int E,
+                                  int F, double rcut, const double *ptable, long ni_total,
+                                  double *phi, double *absum)
+{
+    const long K = 1L << (E + F);
+    const double smax = pgo_smax(E, F);
+    const double c = (smax - 2.0) / (rcut * rcut);
+    memset(phi, 0, sizeof(double) * ni_total);
+    if (absum) memset(absum, 0, sizeof(double) * ni_total);
+    for (long t = 0; t < n_items; t++) {
+        const long i0 = items[4 * t + 0], n_i = items[4 * t + 1];
+        const long j0 = items[4 * t + 2], n_j = items[4 * t + 3];
+#pragma omp parallel for schedule(static)
+        for (long i = i0; i < i0 + n_i; i++) {
+            double sp = 0.0, sa = 0.0;
+            for (long j = j0; j < j0 + n_j; j++) {
+                const double dx = (double)xj[j] - (double)xi[i];
+                const double dy = (double)yj[j] - (double)yi[i];
+                const double dz = (double)zj[j] - (double)zi[i];
+                double s = c * (dx * dx + dy * dy + dz * dz) + 2.0;
+                if (s > smax) s = smax;
+                double sk;
+                const long k = pgo_lut_index(s, E, F, &sk);
+                const double P0 = ptable[2 * k], P1 = ptable[2 * k + 1];
+                sp += mj[j] * (P0 + P1 * (s - sk));
+                const double width = (k + 1 < K) ? pgo_node_s(E, F, k + 1) - sk : 0.0;
+                sa += fabs(mj[j]) * (fabs(P0) + fabs(P1) * width);
+            }
+            phi[i] += sp;
+            if (absum) absum[i] += sa;
         }
     }
 }

@@ -201,3 +201,51 @@ def test_lut_items_match_exact_shape_within_table_error():
     # particles with no neighbour inside rcut feel exactly zero
     lonely = a_ex[3] == 0
     assert np.all(a_tab[0][lonely] == 0) and np.all(a_tab[1][lonely] == 0)
+
+
+# ---- potential tables (a second table on the force table's bins) ----
+
+def test_soft_cut_shape_pair_is_consistent():
+    """h = p'(r)/r for the soft-cut shape (central differences of p in FP64),
+    p and h vanish at rcut, and the small-r limits are finite."""
+    eps, rcut = 0.01, 0.2
+    rng = np.random.default_rng(21)
+    for r in np.concatenate([rng.uniform(1e-3, rcut * 0.999, 200), [1e-6, 0.5 * rcut]]):
+        d = 1e-5 * max(r, 1e-2)
+        dp = (oracle.shape_p(2, r + d, eps, rcut) - oracle.shape_p(2, r - d, eps, rcut)) / (2 * d)
+        hr = oracle.shape_h(2, r, eps, rcut) * r
+        assert abs(dp - hr) <= 1e-6 * abs(oracle.shape_h(2, 0.0, eps, rcut) * r) + 1e-9, (r, dp, hr)
+    assert oracle.shape_p(2, rcut, eps, rcut) == 0.0 and oracle.shape_h(2, rcut, eps, rcut) == 0.0
+    assert oracle.shape_p(2, 0.0, eps, rcut) == pytest.approx(-1.0 / eps, rel=1e-15)
+
+
+@pytest.mark.parametrize("E,F", [(4, 6), (3, 5)])
+def test_potential_table_nodes_continuity_and_accuracy(E, F):
+    """The potential table holds fl32(p(r_k)) at the nodes, is continuous
+    (P0_k + P1_k ds_k = P0_{k+1}), gives 0 beyond rcut, and its
+    interpolation over 4096 log-uniform single pairs stays within 1e-3 of
+    the exact potential, measured against the whole softened potential
+    1/sqrt(r^2 + eps^2) the cut one is part of (near rcut the cut potential
+    itself goes to 0, as the force does in the paper's error measure)."""
+    eps, rcut = 0.01, 0.2
+    K = 1 << (E + F)
+    t = oracle.pot_table_build(E, F, rcut, oracle.SHAPE_SOFT_CUT, eps)
+    for k in range(0, K - 1, 37):
+        rk = oracle.node_r(E, F, rcut, k)
+        assert t[2 * k] == np.float32(oracle.shape_p(2, rk, eps, rcut))
+    nodes = np.array([oracle.node_s(E, F, k) for k in range(K)])
+    cont = t[0:-2:2].astype(np.float64) + t[1:-2:2] * np.diff(nodes)
+    assert np.allclose(cont, t[2::2], rtol=3e-7, atol=3e-7 * abs(t[0]))
+    rng = np.random.default_rng(22)
+    r = rcut * 10.0 ** rng.uniform(-2.5, 0.0, 4096)
+    n = r.size
+    xi = np.zeros(n); yi = np.zeros(n); zi = np.zeros(n)
+    items = np.array([[k, 1, k, 1] for k in range(n)], np.int32)
+    phi, _ = oracle.lut_pot_items(items, xi, yi, zi, r, np.zeros(n), np.zeros(n), np.ones(n),
+                                  E, F, rcut, t)
+    exact = np.array([oracle.shape_p(2, rr, eps, rcut) for rr in r])
+    err = np.abs(phi - exact) * np.sqrt(r * r + eps * eps)
+    assert err.max() < 1e-3, err.max()
+    far, _ = oracle.lut_pot_items(np.array([[0, 1, 0, 1]], np.int32), [0.0], [0.0], [0.0],
+                                  [1.5 * rcut], [0.0], [0.0], [2.0], E, F, rcut, t)
+    assert far[0] == 0.0
