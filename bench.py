@@ -529,14 +529,14 @@ def table_allpairs(torch, pgh, synth):
         t = KernelTimer(torch)
         for _ in range(4):
             with t:
-                pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out)
+                pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out, None)
         per[pgh.pgh_variant_name(fam, v)] = t.mean_ms()
     ctx.set_variant(fam, -1)  # the built-in default (the paper's table form)
     timer = KernelTimer(torch)
 
     def step():
         with timer:
-            pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out)
+            pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out, None)
 
     sec = time_steps(torch, step, 10, 2)
     ms = timer.mean_ms()

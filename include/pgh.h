@@ -169,15 +169,29 @@ PGH_API int pgh_set_table(pgh_ctx *c, int E, int F, float rcut, const float *tab
  * user points to double[2] = {eps, rcut}.  Usable as a pgh_f_over_r. */
 PGH_API double pgh_s2pp_f_over_r(double r, void *user);
 
+/* Potential table on the bins of the current force table (same E, F and
+ * rcut; the force procedure of Sec. 3.4.2 applied to a second table): from
+ * a host callback returning the pair potential p(r) (called at r = 0 for
+ * the first node; p must vanish at rcut: the last node is set to 0), nodes
+ * P0_k = fl32(p(r_k)) and chords P1_k as for the force table.  table_out:
+ * NULL or host float[2 * 2^(E+F)].  PGH_ESTATE before a force table is set;
+ * setting a new force table discards the potential table.  Synchronous. */
+PGH_API int pgh_build_pot_table(pgh_ctx *c, pgh_f_over_r pot, void *user, float *table_out);
+
+/* The potential table from a device array of 2 * 2^(E+F) floats (P0_0,
+ * P1_0, P0_1, ...), on the current force table's bins. */
+PGH_API int pgh_set_pot_table(pgh_ctx *c, const float *table);
+
 /* Table-force accelerations of ni i-particles from the nj = pgh_set_n
  * j-particles of the j-memory: a_i = sum_j m_j g(s_ij) (r_j - r_i) with
  * s = min((s_max - 2)|r_j - r_i|^2 / rcut^2 + 2, s_max) and
  * g = G0_k + G1_k (s - s_k), k the bin of s (the force procedure of
  * Sec. 3.4.2).  Differences are taken on unscaled positions, which gives the
- * paper's scaled-position result without its final rescale.  No potential
- * (the table holds forces only).  PGH_ESTATE if no table is set. */
+ * paper's scaled-position result without its final rescale.  phi (or NULL):
+ * the potential phi_i = sum_j m_j (P0_k + P1_k (s - s_k)) from the potential
+ * table (PGH_ESTATE if none is set).  PGH_ESTATE if no force table is set. */
 PGH_API int pgh_calc_table(pgh_ctx *c, int ni, const float *xi, const float *yi, const float *zi,
-                   float *ax, float *ay, float *az);
+                           float *ax, float *ay, float *az, float *phi);
 
 /* ---------------------------------------------------------------------- */
 /* Interaction lists in one persistent launch (tree / TreePM groups,        */
@@ -213,10 +227,11 @@ PGH_API int pgh_batch_newton(pgh_ctx *c, const pgh_plan *p, const float *xi, con
                      const float *zj, const float *mj, float *ax, float *ay, float *az,
                      float *phi);
 
-/* Table force of every list of the plan (the context's table). */
+/* Table force of every list of the plan (the context's table), and the
+ * potential from the potential table when phi is not NULL. */
 PGH_API int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
-                    const float *zi, const float *xj, const float *yj, const float *zj,
-                    const float *mj, float *ax, float *ay, float *az);
+                            const float *zi, const float *xj, const float *yj, const float *zj,
+                            const float *mj, float *ax, float *ay, float *az, float *phi);
 
 /* ---------------------------------------------------------------------- */
 /* Adjoints of L = sum_i w_i . a_i (derived from Eq. newton_force and the   */

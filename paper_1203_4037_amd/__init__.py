@@ -62,12 +62,14 @@ SIGNATURES = {
     "pgh_table_compute": (_I, [_I, _I, _F, _P, _P, _P]),
     "pgh_set_table": (_I, [_P, _I, _I, _F, _P]),
     "pgh_s2pp_f_over_r": (_D, [_D, _P]),
-    "pgh_calc_table": (_I, [_P, _I, _P, _P, _P, _P, _P, _P]),
+    "pgh_calc_table": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P]),
+    "pgh_build_pot_table": (_I, [_P, _P, _P, _P]),
+    "pgh_set_pot_table": (_I, [_P, _P]),
     "pgh_plan_create": (_I, [_P, _I, _P, _I, _I, ctypes.POINTER(_P)]),
     "pgh_plan_free": (_I, [_P, _P]),
     "pgh_plan_interactions": (ctypes.c_longlong, [_P]),
     "pgh_batch_newton": (_I, [_P, _P] + [_P] * 12),
-    "pgh_batch_table": (_I, [_P, _P] + [_P] * 10),
+    "pgh_batch_table": (_I, [_P, _P] + [_P] * 11),
     "pgh_newton_allpairs_bwd": (_I, [_P, _I, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P, _P]),
     "pgh_newton_ij_bwd": (_I, [_P, _I, _P, _P, _P, _P, _I] + [_P] * 14),
     "pgh_batch_table_bwd": (_I, [_P, _P] + [_P] * 18),
@@ -217,10 +219,22 @@ def pgh_set_table(ctx, E, F, rcut, table):
     _check(ctx, lib.pgh_set_table(ctx, E, F, float(rcut), _ptr(table, 2 << (E + F), "table")))
 
 
-def pgh_calc_table(ctx, ni, xi, yi, zi, ax, ay, az):
+def pgh_build_pot_table(ctx, pot, user=None, table_out=None):
+    """Potential table from a callable p(r) (or an F_OVER_R callback) on the
+    bins of the context's force table."""
+    cb = _callback(pot)
+    out = None if table_out is None else table_out.ctypes.data
+    _check(ctx, lib.pgh_build_pot_table(ctx, ctypes.cast(cb, ctypes.c_void_p), user, out))
+
+
+def pgh_set_pot_table(ctx, table):
+    _check(ctx, lib.pgh_set_pot_table(ctx, _ptr(table, None, "table")))
+
+
+def pgh_calc_table(ctx, ni, xi, yi, zi, ax, ay, az, phi=None):
     _check(ctx, lib.pgh_calc_table(ctx, ni, _ptr(xi, ni, "xi"), _ptr(yi, ni, "yi"),
                                    _ptr(zi, ni, "zi"), _ptr(ax, ni, "ax"), _ptr(ay, ni, "ay"),
-                                   _ptr(az, ni, "az")))
+                                   _ptr(az, ni, "az"), _ptr(phi, ni, "phi")))
 
 
 def _items_array(items):
@@ -257,12 +271,12 @@ def pgh_batch_newton(ctx, plan, xi, yi, zi, eps2_i, xj, yj, zj, mj, ax, ay, az, 
                                      _ptr(az, None, "az"), _ptr(phi, None, "phi")))
 
 
-def pgh_batch_table(ctx, plan, xi, yi, zi, xj, yj, zj, mj, ax, ay, az):
+def pgh_batch_table(ctx, plan, xi, yi, zi, xj, yj, zj, mj, ax, ay, az, phi=None):
     _check(ctx, lib.pgh_batch_table(ctx, plan, _ptr(xi, None, "xi"), _ptr(yi, None, "yi"),
-                                    _ptr(zi, None, "zi"), _ptr(xj, None, "xj"),
-                                    _ptr(yj, None, "yj"), _ptr(zj, None, "zj"),
-                                    _ptr(mj, None, "mj"), _ptr(ax, None, "ax"),
-                                    _ptr(ay, None, "ay"), _ptr(az, None, "az")))
+                                    _ptr(zi, None, "zi"), _ptr(xj, None, "xj"), _ptr(yj, None, "yj"),
+                                    _ptr(zj, None, "zj"), _ptr(mj, None, "mj"), _ptr(ax, None, "ax"),
+                                    _ptr(ay, None, "ay"), _ptr(az, None, "az"),
+                                    _ptr(phi, None, "phi")))
 
 
 def pgh_newton_allpairs_bwd(ctx, n, x, y, z, m, eps2, wx, wy, wz, gx, gy, gz, gm):
@@ -505,12 +519,22 @@ class Context:
         pgh_set_table(self.h, E, F, rcut, table)
         self.table = (E, F, float(rcut))
 
-    def table_force(self, x, y, z):
+    def build_pot_table(self, pot):
+        """Potential table of a callable p(r) on the force table's bins; returns
+        the host copy (float32, interleaved P0, P1)."""
+        import numpy as np
+        E, F, _ = self.table
+        out = np.zeros(2 << (E + F), dtype=np.float32)
+        pgh_build_pot_table(self.h, pot, None, out)
+        return out
+
+    def table_force(self, x, y, z, with_phi=False):
         self._sync_stream()
         n = x.numel()
         ax, ay, az = self._empty(n), self._empty(n), self._empty(n)
-        pgh_calc_table(self.h, n, x, y, z, ax, ay, az)
-        return ax, ay, az
+        phi = self._empty(n) if with_phi else None
+        pgh_calc_table(self.h, n, x, y, z, ax, ay, az, phi)
+        return (ax, ay, az, phi) if with_phi else (ax, ay, az)
 
     def set_variant(self, family, v):
         pgh_set_variant(self.h, family, v)
@@ -588,13 +612,16 @@ class Plan:
         pgh_batch_newton(c.h, self.h, xi, yi, zi, eps2, xj, yj, zj, mj, out[0], out[1], out[2], phi)
         return out
 
-    def table(self, xi, yi, zi, xj, yj, zj, mj, out=None):
+    def table(self, xi, yi, zi, xj, yj, zj, mj, out=None, with_phi=False):
+        """Table force (and the potential from the potential table when
+        with_phi, out then holding 4 arrays)."""
         c = self.ctx
         c._sync_stream()
         self._check_sizes((xi, yi, zi), (xj, yj, zj, mj))
         if out is None:
-            out = [c._empty(self.ni_total) for _ in range(3)]
-        pgh_batch_table(c.h, self.h, xi, yi, zi, xj, yj, zj, mj, out[0], out[1], out[2])
+            out = [c._empty(self.ni_total) for _ in range(4 if with_phi else 3)]
+        phi = out[3] if with_phi else None
+        pgh_batch_table(c.h, self.h, xi, yi, zi, xj, yj, zj, mj, out[0], out[1], out[2], phi)
         return out
 
     def autotune(self, family, xi, yi, zi, xj, yj, zj, mj, reps=3):

@@ -53,11 +53,14 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // KIND 0: Newton (REFINE, GUARD, PHI apply; ALT = the rcp form);
-// KIND 1: table force (ALT = the (H, G1) table form).
+// KIND 1: table force (ALT = the (H, G1) table form; PHI = also the
+// potential from the second table, a.ptable).
 template <int KIND, bool ALT, bool REFINE, bool GUARD, bool PHI>
 __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
 {
-    extern __shared__ float2 stab[];  // table force only: 2^(E+F) entries
+    extern __shared__ float4 dyn4[];  // table force only: 2^(E+F) entries
+    float2 *stab = (float2 *)dyn4;    // (G0, G1)
+    float4 *stab4 = dyn4;             // (G0, G1, P0, P1), with PHI
     // [wave][buffer][list][record]: the Newton kernel double-buffers its
     // tiles; the table kernel, whose table also sits in LDS, uses one buffer
     constexpr int NB = KIND == 0 ? 2 : 1;
@@ -86,7 +89,10 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
     if (KIND == 1) {
         const int K = 1 << (a.E + a.F);
         shift = 23u - (unsigned)a.F;
-        table_to_lds<ALT>(stab, a.table, K, shift);
+        if (PHI)
+            tables_to_lds<ALT>(stab4, a.table, a.ptable, K, shift);
+        else
+            table_to_lds<ALT>(stab, a.table, K, shift);
         nbits = (unsigned)(a.E + a.F);
         hmask = ~((1u << shift) - 1u);
         __syncthreads();  // the only workgroup barrier: waves are independent after it
@@ -192,6 +198,9 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
                         if (KIND == 0)
                             newton_pair<REFINE, GUARD, PHI, ALT>(p, px, py, pz, pe, sx, sy, sz,
                                                                  sp);
+                        else if (PHI)
+                            table_pair_pot<ALT>(p, px, py, pz, stab4, a.c, a.smax, shift, nbits,
+                                                hmask, sx, sy, sz, sp);
                         else
                             table_pair<ALT>(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask,
                                             sx, sy, sz);
@@ -209,6 +218,9 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
                     const float4 p = src[it * js + ph];
                     if (KIND == 0)
                         newton_pair<REFINE, GUARD, PHI, ALT>(p, px, py, pz, pe, sx, sy, sz, sp);
+                    else if (PHI)
+                        table_pair_pot<ALT>(p, px, py, pz, stab4, a.c, a.smax, shift, nbits, hmask,
+                                            sx, sy, sz, sp);
                     else
                         table_pair<ALT>(p, px, py, pz, stab, a.c, a.smax, shift, nbits, hmask, sx,
                                         sy, sz);
@@ -247,7 +259,7 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
                 a.ax[i] = tx;
                 a.ay[i] = ty;
                 a.az[i] = tz;
-                if (KIND == 0 && PHI) a.phi[i] = tp;
+                if (PHI) a.phi[i] = tp;
             }
         } else if (ph == 0) {
             // partial sums of one part of a split j-list; k_combine adds the
@@ -371,9 +383,14 @@ hipError_t launch_newton_batch(const BatchArgs &a, int variant, bool refine, boo
 
 hipError_t launch_table_batch(const BatchArgs &a, int variant, int num_cu, hipStream_t s)
 {
-    const size_t lds = sizeof(float2) << (a.E + a.F);
-    if (variant == 1) return launch(k_batch<1, true, false, false, false>, a, lds, num_cu, s, false);
-    return launch(k_batch<1, false, false, false, false>, a, lds, num_cu, s, false);
+    const bool phi = a.phi && a.ptable;
+    const size_t lds = (phi ? sizeof(float4) : sizeof(float2)) << (a.E + a.F);
+    BatchKernel k;
+    if (variant == 1)
+        k = phi ? k_batch<1, true, false, false, true> : k_batch<1, true, false, false, false>;
+    else
+        k = phi ? k_batch<1, false, false, false, true> : k_batch<1, false, false, false, false>;
+    return launch(k, a, lds, num_cu, s, phi);
 }
 
 }  // namespace pgh

@@ -164,7 +164,7 @@ void g5_calculate_force_on_x(double (*xi)[3], double (*ai)[3], double *pi, int n
     int st;
     if (g5.table)
         st = pgh_calc_table(g5.ctx, ni, d, d + cap, d + 2 * cap, d + 3 * cap, d + 4 * cap,
-                            d + 5 * cap);
+                            d + 5 * cap, nullptr);
     else
         st = pgh_calc_newton(g5.ctx, ni, d, d + cap, d + 2 * cap, nullptr, d + 3 * cap,
                              d + 4 * cap, d + 5 * cap, pi ? d + 6 * cap : nullptr);

@@ -25,12 +25,16 @@
 namespace pgh {
 namespace {
 
-template <int KI, int JT, int U, bool HT>
+// PHI: also the potential from the second table (a.ptable, a.phi); the LDS
+// table then holds (G0, G1, P0, P1) per node.
+template <int KI, int JT, int U, bool HT, bool PHI>
 __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
 {
     static_assert(JT % 256 == 0, "tile must be a multiple of the workgroup");
     constexpr int PER = JT / 256;
-    extern __shared__ float2 stab[];
+    extern __shared__ float4 dyn4[];
+    float2 *stab = (float2 *)dyn4;  // (G0, G1) per node
+    float4 *stab4 = dyn4;           // (G0, G1, P0, P1) per node, with PHI
     __shared__ float4 tile[2][JT];
 
     const int tid = threadIdx.x;
@@ -41,10 +45,13 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
     const unsigned hmask = ~((1u << shift) - 1u);
     const float c = a.c, smax = a.smax;
 
-    table_to_lds<HT>(stab, a.table, K, shift);
+    if (PHI)
+        tables_to_lds<HT>(stab4, a.table, a.ptable, K, shift);
+    else
+        table_to_lds<HT>(stab, a.table, K, shift);
 
     float px[KI], py[KI], pz[KI];
-    float tx[KI], ty[KI], tz[KI];
+    float tx[KI], ty[KI], tz[KI], tp[KI];
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
         int i = ibase + k * 256;
@@ -52,7 +59,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
         px[k] = a.xi[i];
         py[k] = a.yi[i];
         pz[k] = a.zi[i];
-        tx[k] = ty[k] = tz[k] = 0.f;
+        tx[k] = ty[k] = tz[k] = tp[k] = 0.f;
     }
 
     // this workgroup's share of the j-particles (blockIdx.y splits them)
@@ -84,43 +91,44 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
         const int cur = t & 1;
         if (t + 1 < ntiles) load_tile(t + 1);
         const int cnt = min(JT, nj - t * JT);
-        float sx[KI], sy[KI], sz[KI];
+        float sx[KI], sy[KI], sz[KI], sp[KI];
 #pragma unroll
-        for (int k = 0; k < KI; ++k) sx[k] = sy[k] = sz[k] = 0.f;
+        for (int k = 0; k < KI; ++k) sx[k] = sy[k] = sz[k] = sp[k] = 0.f;
+        auto pair = [&](const float4 p) {
+#pragma unroll
+            for (int k = 0; k < KI; ++k) {
+                if (PHI)
+                    table_pair_pot<HT>(p, px[k], py[k], pz[k], stab4, c, smax, shift, nbits, hmask,
+                                       sx[k], sy[k], sz[k], sp[k]);
+                else
+                    table_pair<HT>(p, px[k], py[k], pz[k], stab, c, smax, shift, nbits, hmask,
+                                   sx[k], sy[k], sz[k]);
+            }
+        };
         if (cnt == JT) {
 #pragma unroll U
-            for (int jj = 0; jj < JT; ++jj) {
-                const float4 p = tile[cur][jj];
-#pragma unroll
-                for (int k = 0; k < KI; ++k)
-                    table_pair<HT>(p, px[k], py[k], pz[k], stab, c, smax, shift, nbits, hmask, sx[k],
-                               sy[k], sz[k]);
-            }
+            for (int jj = 0; jj < JT; ++jj) pair(tile[cur][jj]);
         } else {
 #pragma unroll 2
-            for (int jj = 0; jj < cnt; ++jj) {
-                const float4 p = tile[cur][jj];
-#pragma unroll
-                for (int k = 0; k < KI; ++k)
-                    table_pair<HT>(p, px[k], py[k], pz[k], stab, c, smax, shift, nbits, hmask, sx[k],
-                               sy[k], sz[k]);
-            }
+            for (int jj = 0; jj < cnt; ++jj) pair(tile[cur][jj]);
         }
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
             tx[k] += sx[k];
             ty[k] += sy[k];
             tz[k] += sz[k];
+            tp[k] += sp[k];
         }
         if (t + 1 < ntiles) store_tile(cur ^ 1);
         __syncthreads();
     }
 
-    float *ox = a.ax, *oy = a.ay, *oz = a.az;
+    float *ox = a.ax, *oy = a.ay, *oz = a.az, *op = a.phi;
     if (gridDim.y > 1) {
         ox = a.part + (size_t)blockIdx.y * 4 * a.ni;
         oy = ox + a.ni;
         oz = oy + a.ni;
+        op = oz + a.ni;
     }
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
@@ -129,6 +137,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
             ox[i] = tx[k];
             oy[i] = ty[k];
             oz[i] = tz[k];
+            if (PHI) op[i] = tp[k];
         }
     }
 }
@@ -138,16 +147,19 @@ using TableKernel = void (*)(TableArgs);
 struct TableVariant {
     const char *name;
     int ki, jt;
-    TableKernel fn;
+    TableKernel fn, fn_phi;  // force only; force and potential
 };
 
+#define PGH_TABLE_VARIANT(name, KI, JT, U, HT) \
+    {name, KI, JT, k_table_allpairs<KI, JT, U, HT, false>, k_table_allpairs<KI, JT, U, HT, true>}
 const TableVariant kTableVariants[] = {
-    {"ki=1 jt=256 u=4", 1, 256, k_table_allpairs<1, 256, 4, false>},
-    {"ki=2 jt=256 u=4", 2, 256, k_table_allpairs<2, 256, 4, false>},
-    {"ki=4 jt=256 u=2", 4, 256, k_table_allpairs<4, 256, 2, false>},
-    {"ki=1 jt=256 u=4 htab", 1, 256, k_table_allpairs<1, 256, 4, true>},
-    {"ki=2 jt=256 u=4 htab", 2, 256, k_table_allpairs<2, 256, 4, true>},
+    PGH_TABLE_VARIANT("ki=1 jt=256 u=4", 1, 256, 4, false),
+    PGH_TABLE_VARIANT("ki=2 jt=256 u=4", 2, 256, 4, false),
+    PGH_TABLE_VARIANT("ki=4 jt=256 u=2", 4, 256, 2, false),
+    PGH_TABLE_VARIANT("ki=1 jt=256 u=4 htab", 1, 256, 4, true),
+    PGH_TABLE_VARIANT("ki=2 jt=256 u=4 htab", 2, 256, 4, true),
 };
+#undef PGH_TABLE_VARIANT
 constexpr int kNumTableVariants = sizeof(kTableVariants) / sizeof(kTableVariants[0]);
 
 }  // namespace
@@ -182,11 +194,12 @@ hipError_t launch_table_allpairs(const TableArgs &a0, int variant, int S, hipStr
     S = std::max(1, (a.nj + a.jchunk - 1) / a.jchunk);
     const int per_block = 256 * v.ki;
     const dim3 grid((a.ni + per_block - 1) / per_block, S);
-    const size_t lds = sizeof(float2) << (a.E + a.F);
-    hipLaunchKernelGGL(v.fn, grid, dim3(256), lds, s, a);
+    const bool phi = a.phi && a.ptable;
+    const size_t lds = (phi ? sizeof(float4) : sizeof(float2)) << (a.E + a.F);
+    hipLaunchKernelGGL(phi ? v.fn_phi : v.fn, grid, dim3(256), lds, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || S == 1) return e;
-    return launch_combine_split(a.ni, S, a.part, a0.ax, a0.ay, a0.az, nullptr, s);
+    return launch_combine_split(a.ni, S, a.part, a0.ax, a0.ay, a0.az, phi ? a0.phi : nullptr, s);
 }
 
 namespace {

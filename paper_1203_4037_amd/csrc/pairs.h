@@ -123,4 +123,60 @@ __device__ __forceinline__ void table_to_lds(float2 *stab, const float2 *__restr
     }
 }
 
+// The table force with the potential from a second table on the same bins
+// (P0_k = p(r_k) and chords P1_k): the LDS copy holds (G0, G1, P0, P1) per
+// node (in the HT form (H, G1, PH, P1) with PH_k = P0_k - P1_k s_k), read
+// with one ds_read_b128; phi_i += m_j (P0 + P1 (s - s_k)).
+template <bool HT>
+__device__ __forceinline__ void table_pair_pot(const float4 p, float px, float py, float pz,
+                                               const float4 *__restrict__ stab, float c,
+                                               float smax, unsigned shift, unsigned nbits,
+                                               unsigned hmask, float &sx, float &sy, float &sz,
+                                               float &sp)
+{
+    const float dx = p.x - px;
+    const float dy = p.y - py;
+    const float dz = p.z - pz;
+    float r2 = dx * dx;
+    r2 = __builtin_fmaf(dy, dy, r2);
+    r2 = __builtin_fmaf(dz, dz, r2);
+    const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
+    const unsigned u = __float_as_uint(s);
+    const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
+    const float4 t = stab[k];
+    float g, q;
+    if (HT) {
+        g = __builtin_fmaf(t.y, s, t.x);
+        q = __builtin_fmaf(t.w, s, t.z);
+    } else {
+        const float ds = s - __uint_as_float(u & hmask);
+        g = __builtin_fmaf(t.y, ds, t.x);
+        q = __builtin_fmaf(t.w, ds, t.z);
+    }
+    const float mg = p.w * g;
+    sx = __builtin_fmaf(mg, dx, sx);
+    sy = __builtin_fmaf(mg, dy, sy);
+    sz = __builtin_fmaf(mg, dz, sz);
+    sp = __builtin_fmaf(p.w, q, sp);
+}
+
+// Copies the force and potential tables into one LDS array of (G0, G1, P0,
+// P1) per node (HT: the constant terms in the (H, G1) form).  shift = 23 - F.
+template <bool HT>
+__device__ __forceinline__ void tables_to_lds(float4 *stab, const float2 *__restrict__ table,
+                                              const float2 *__restrict__ ptable, int K,
+                                              unsigned shift)
+{
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const float2 g = table[k], q = ptable[k];
+        float4 e = make_float4(g.x, g.y, q.x, q.y);
+        if (HT) {
+            const float sk = __uint_as_float(0x40000000u + ((unsigned)k << shift));
+            e.x = __builtin_fmaf(-e.y, sk, e.x);
+            e.z = __builtin_fmaf(-e.w, sk, e.z);
+        }
+        stab[k] = e;
+    }
+}
+
 }  // namespace pgh

@@ -48,6 +48,8 @@ struct pgh_ctx {
     float tab_rcut = 0.f;
     float2 *tab = nullptr;  // device, 2^kMaxTableBits entries
     float *gcopy = nullptr;  // device, kGradCopies x 2^(kMaxTableBits+1): table-adjoint scratch
+    float2 *ptab = nullptr;  // device, potential table on the force table's bins
+    int pot_set = 0;         // ptab matches the current force table
     int variant[4] = {-1, -1, -1, -1};
     // partial sums of j-split all-pairs launches (grown on demand)
     float *part = nullptr;
@@ -203,9 +205,11 @@ int pgh_open(pgh_ctx **out, int device, void *hip_stream)
     e = hipMalloc((void **)&c->tab, sizeof(float2) << kMaxTableBits);
     if (e == hipSuccess)
         e = hipMalloc((void **)&c->gcopy, (sizeof(float2) << kMaxTableBits) * kGradCopies);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->ptab, sizeof(float2) << kMaxTableBits);
     if (e != hipSuccess) {
         g_open_error = std::string("hipMalloc(table): ") + hipGetErrorString(e);
         (void)hipFree(c->tab);
+        (void)hipFree(c->gcopy);
         delete c;
         return PGH_ENOMEM;
     }
@@ -228,6 +232,7 @@ int pgh_close(pgh_ctx *c)
     (void)hipFree(c->jmem);
     (void)hipFree(c->tab);
     (void)hipFree(c->gcopy);
+    (void)hipFree(c->ptab);
     delete c;
     return PGH_OK;
 }
@@ -390,6 +395,7 @@ int pgh_build_table(pgh_ctx *c, int E, int F, float rcut, pgh_f_over_r f_over_r,
                               c->stream));
     PGH_HIP(c, hipStreamSynchronize(c->stream));
     c->tab_set = 1;
+    c->pot_set = 0;
     c->tab_E = E;
     c->tab_F = F;
     c->tab_rcut = rcut;
@@ -407,27 +413,60 @@ int pgh_set_table(pgh_ctx *c, int E, int F, float rcut, const float *table)
     PGH_HIP(c, hipMemcpyAsync(c->tab, table, sizeof(float2) << (E + F), hipMemcpyDeviceToDevice,
                               c->stream));
     c->tab_set = 1;
+    c->pot_set = 0;
     c->tab_E = E;
     c->tab_F = F;
     c->tab_rcut = rcut;
     return PGH_OK;
 }
 
+int pgh_build_pot_table(pgh_ctx *c, pgh_f_over_r pot, void *user, float *table_out)
+{
+    if (!c) return PGH_EINVAL;
+    if (!pot) return fail(c, PGH_EINVAL, "NULL callback");
+    if (!c->tab_set) return fail(c, PGH_ESTATE, "set the force table first");
+    std::vector<float> t(2u << (c->tab_E + c->tab_F));
+    // the same nodes and chords as the force table, from p(r) instead of f/r
+    int st = pgh_table_compute(c->tab_E, c->tab_F, c->tab_rcut, pot, user, t.data());
+    if (st) return fail(c, st, "potential table computation failed");
+    DeviceGuard g(c->device);
+    PGH_HIP(c, hipMemcpyAsync(c->ptab, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice,
+                              c->stream));
+    PGH_HIP(c, hipStreamSynchronize(c->stream));
+    c->pot_set = 1;
+    if (table_out) std::memcpy(table_out, t.data(), sizeof(float) * t.size());
+    return PGH_OK;
+}
+
+int pgh_set_pot_table(pgh_ctx *c, const float *table)
+{
+    if (!c) return PGH_EINVAL;
+    if (!table) return fail(c, PGH_EINVAL, "NULL table");
+    if (!c->tab_set) return fail(c, PGH_ESTATE, "set the force table first");
+    DeviceGuard g(c->device);
+    PGH_HIP(c, hipMemcpyAsync(c->ptab, table, sizeof(float2) << (c->tab_E + c->tab_F),
+                              hipMemcpyDeviceToDevice, c->stream));
+    c->pot_set = 1;
+    return PGH_OK;
+}
+
 int pgh_calc_table(pgh_ctx *c, int ni, const float *xi, const float *yi, const float *zi,
-                   float *ax, float *ay, float *az)
+                   float *ax, float *ay, float *az, float *phi)
 {
     if (!c) return PGH_EINVAL;
     if (!c->tab_set) return fail(c, PGH_ESTATE, "no force table set");
+    if (phi && !c->pot_set) return fail(c, PGH_ESTATE, "no potential table set");
     if (ni < 0) return fail(c, PGH_EINVAL, "ni must be >= 0");
     if (ni == 0) return PGH_OK;
     if (!xi || !yi || !zi || !ax || !ay || !az)
         return fail(c, PGH_EINVAL, "NULL i-particle or output array");
     DeviceGuard g(c->device);
-    if (c->nj == 0) return zero_outputs(c, ni, ax, ay, az, nullptr);
+    if (c->nj == 0) return zero_outputs(c, ni, ax, ay, az, phi);
     const double smax = smax_of(c->tab_E, c->tab_F);
     const double rc = c->tab_rcut;
     TableArgs a{ni, xi, yi, zi, c->nj, c->jmem, c->tab, c->tab_E, c->tab_F,
-                (float)((smax - 2.0) / (rc * rc)), (float)smax, ax, ay, az, 0, nullptr};
+                (float)((smax - 2.0) / (rc * rc)), (float)smax, ax, ay, az, 0, nullptr,
+                phi ? c->ptab : nullptr, phi};
     int v = c->variant[PGH_FAMILY_TABLE_ALLPAIRS];
     if (v < 0) v = table_allpairs_default(ni, c->nj, c->num_cu);
     const int S = table_allpairs_split(ni, c->nj, v, kMaxSplitFloats);
@@ -795,12 +834,13 @@ int pgh_batch_newton(pgh_ctx *c, const pgh_plan *p, const float *xi, const float
 
 int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
                     const float *zi, const float *xj, const float *yj, const float *zj,
-                    const float *mj, float *ax, float *ay, float *az)
+                    const float *mj, float *ax, float *ay, float *az, float *phi)
 {
     if (!c) return PGH_EINVAL;
     int st = check_plan(c, p);
     if (st) return st;
     if (!c->tab_set) return fail(c, PGH_ESTATE, "no force table set");
+    if (phi && !c->pot_set) return fail(c, PGH_ESTATE, "no potential table set");
     if (p->n_tasks == 0) return PGH_OK;
     if (!xi || !yi || !zi || !ax || !ay || !az)
         return fail(c, PGH_EINVAL, "NULL i-particle or output array");
@@ -811,6 +851,8 @@ int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, const float 
     a.xi = xi, a.yi = yi, a.zi = zi;
     a.xj = xj, a.yj = yj, a.zj = zj, a.mj = mj;
     a.ax = ax, a.ay = ay, a.az = az;
+    a.phi = phi;
+    a.ptable = phi ? c->ptab : nullptr;
     const double smax = smax_of(c->tab_E, c->tab_F);
     const double rc = c->tab_rcut;
     a.table = c->tab;
@@ -1046,7 +1088,7 @@ int pgh_autotune(pgh_ctx *c, int family, int ni, const float *xi, const float *y
         if (family == PGH_FAMILY_NEWTON_ALLPAIRS)
             return pgh_calc_newton(c, ni, xi, yi, zi, nullptr, out, out + ni, out + 2 * ni,
                                    out + 3 * (size_t)ni);
-        return pgh_calc_table(c, ni, xi, yi, zi, out, out + ni, out + 2 * ni);
+        return pgh_calc_table(c, ni, xi, yi, zi, out, out + ni, out + 2 * ni, nullptr);
     });
     (void)hipFree(out);
     return r;
@@ -1074,7 +1116,8 @@ int pgh_autotune_plan(pgh_ctx *c, int family, const pgh_plan *p, const float *xi
         if (family == PGH_FAMILY_NEWTON_BATCH)
             return pgh_batch_newton(c, p, xi, yi, zi, nullptr, xj, yj, zj, mj, out, out + ni,
                                     out + 2 * ni, out + 3 * ni);
-        return pgh_batch_table(c, p, xi, yi, zi, xj, yj, zj, mj, out, out + ni, out + 2 * ni);
+        return pgh_batch_table(c, p, xi, yi, zi, xj, yj, zj, mj, out, out + ni, out + 2 * ni,
+                               nullptr);
     });
     (void)hipFree(out);
     return r;

@@ -40,6 +40,8 @@ struct TableArgs {
     float *ax, *ay, *az;
     int jchunk;
     float *part;
+    const float2 *ptable;  // (P0, P1) per node of the potential table, or NULL
+    float *phi;            // potential output (with ptable), or NULL
 };
 
 // One wavefront task of a batch plan: up to 64 i-particles against one part
@@ -89,6 +91,7 @@ struct BatchArgs {
     const float2 *table;
     int E, F;
     float c, smax;
+    const float2 *ptable;  // potential table (with phi), or NULL
 };
 
 struct CombineArgs {

@@ -124,7 +124,7 @@ def test_set_table_from_device_and_state_errors(pgh, ctx):
     # no table yet -> PGH_ESTATE
     x = torch.zeros(4, device="cuda")
     with pytest.raises(pgh.PGHError) as e:
-        pgh.pgh_calc_table(ctx.h, 4, x, x, x, x, x, x)
+        pgh.pgh_calc_table(ctx.h, 4, x, x, x, x, x, x, None)
     assert e.value.code == pgh.PGH_ESTATE
     E, F, rcut, eps = 4, 6, 0.05, 1e-3
     t = np.zeros(2 << (E + F), np.float32)
@@ -158,3 +158,94 @@ def test_table_autotuner(pgh, ctx):
     assert 0 <= v < pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_ALLPAIRS) and ms > 0
     with pytest.raises(pgh.PGHError):
         pgh.pgh_autotune(ctx.h, pgh.PGH_FAMILY_NEWTON_BATCH, n, d[0], d[1], d[2], 1)
+
+
+def _soft_cut_tables(ctx, E, F, rcut, eps):
+    h = lambda r: oracle.shape_h(oracle.SHAPE_SOFT_CUT, r, eps, rcut)
+    p = lambda r: oracle.shape_p(oracle.SHAPE_SOFT_CUT, r, eps, rcut)
+    ft = ctx.build_table(E, F, rcut, f_over_r=h)
+    pt = ctx.build_pot_table(p)
+    # the library's host builder against the oracle's own tables (pinned on the CPU)
+    of = oracle.table_build(E, F, float(np.float32(rcut)), oracle.SHAPE_SOFT_CUT, eps)
+    op = oracle.pot_table_build(E, F, float(np.float32(rcut)), oracle.SHAPE_SOFT_CUT, eps)
+    assert np.allclose(ft, of, rtol=2e-6, atol=2e-6 * np.abs(of).max())
+    assert np.allclose(pt, op, rtol=2e-6, atol=2e-6 * np.abs(op).max())
+    return ft, pt
+
+
+def test_potential_table_allpairs(pgh, ctx):
+    """Force and potential from the (G0, G1) and (P0, P1) tables of the soft-cut
+    shape pair (N = 4096 uniform in a box of side 0.5, rcut = 0.2,
+    eps = 0.01, E = 4, F = 6), every all-pairs variant, against the oracle."""
+    import torch
+    n = 4096
+    E, F, rcut, eps = 4, 6, 0.2, 0.01
+    x, y, z = synth.uniform_box(n, 71, box=0.5)
+    m = np.linspace(0.5, 1.5, n).astype(np.float32) / n
+    ft, pt = _soft_cut_tables(ctx, E, F, rcut, eps)
+    d = to_dev(x, y, z, m)
+    ctx.set_j(*d)
+    items = np.array([[0, n, 0, n]], np.int32)
+    rc = float(np.float32(rcut))
+    ra = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rc, ft)
+    rp, sp = oracle.lut_pot_items(items, x, y, z, x, y, z, m, E, F, rc, pt)
+    fam = pgh.PGH_FAMILY_TABLE_ALLPAIRS
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        ax, ay, az, phi = ctx.table_force(d[0], d[1], d[2], with_phi=True)
+        a = np.stack(to_host(ax, ay, az))
+        has = ra[3] > 0
+        e = norm_vec_err(a[:, has], np.stack(ra[:3])[:, has], ra[3][has])
+        assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
+        ep = np.abs(to_host(phi)[0] - rp)[sp > 0] / sp[sp > 0]
+        assert rms(ep) <= 1e-5 and ep.max() <= 1e-3, (v, rms(ep), ep.max())
+        # the force alone is unchanged by asking for the potential
+        bx, by, bz = ctx.table_force(d[0], d[1], d[2])
+        assert np.array_equal(np.stack(to_host(bx, by, bz)), a)
+
+
+def test_potential_table_cell_lists(pgh, ctx):
+    """The same shape pair on cell lists (N = 16384 in the unit periodic box,
+    32^3 cells, rcut = 1/32, eps = rcut/15), both batched table forms."""
+    n = 16384
+    E, F, rcut, eps = 4, 6, 1.0 / 32, 1.0 / 32 / 15
+    x, y, z = synth.uniform_box(n, 72)
+    m = synth.equal_masses(n)
+    s = synth.cell_grid_items(x, y, z, m, ncell=32, block=4)
+    ft, pt = _soft_cut_tables(ctx, E, F, rcut, eps)
+    di = to_dev(s.xi, s.yi, s.zi)
+    dj = to_dev(s.xj, s.yj, s.zj, s.mj)
+    plan = ctx.plan(s.items, n, s.xj.size)
+    rc = float(np.float32(rcut))
+    ra = oracle.lut_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, E, F, rc, ft)
+    rp, sp = oracle.lut_pot_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, E, F, rc, pt)
+    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH)):
+        ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, v)
+        out = plan.table(*di, *dj, with_phi=True)
+        a = np.stack(to_host(*out[:3]))
+        has = ra[3] > 0
+        e = norm_vec_err(a[:, has], np.stack(ra[:3])[:, has], ra[3][has])
+        assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
+        phi = to_host(out[3])[0]
+        ep = np.abs(phi - rp)[sp > 0] / sp[sp > 0]
+        assert rms(ep) <= 1e-5 and ep.max() <= 1e-3, (v, rms(ep), ep.max())
+        assert np.all(phi[sp == 0] == 0.0)
+
+
+def test_potential_table_state_errors(pgh, ctx):
+    import torch
+    x = torch.zeros(4, device="cuda")
+    with pytest.raises(pgh.PGHError) as e:  # no force table yet
+        pgh.pgh_build_pot_table(ctx.h, lambda r: 0.0)
+    assert e.value.code == pgh.PGH_ESTATE
+    ctx.build_table(3, 4, 0.5, f_over_r=lambda r: 1.0)
+    ctx.set_j(x, x, x, x)
+    with pytest.raises(pgh.PGHError) as e:  # a potential without a potential table
+        ctx.table_force(x, x, x, with_phi=True)
+    assert e.value.code == pgh.PGH_ESTATE
+    ctx.build_pot_table(lambda r: 1.0 - 2.0 * r)
+    ctx.table_force(x, x, x, with_phi=True)
+    ctx.build_table(3, 4, 0.5, f_over_r=lambda r: 1.0)  # a new force table drops it
+    with pytest.raises(pgh.PGHError) as e:
+        ctx.table_force(x, x, x, with_phi=True)
+    assert e.value.code == pgh.PGH_ESTATE
