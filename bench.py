@@ -36,13 +36,13 @@ TABLE_FLOPS = 20  # per interaction, this project's count of the FP32 ops of the
 # HBM traffic of the headline kernel, from two rocprofv3 --pmc runs of
 # `bench.py --no-extras --no-cpu --copy-calibration 256` (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads for a
-# 256 MiB device-to-device copy (FETCH_SIZE 131094 KiB -> x2.0, WRITE_SIZE
+# 256 MiB device-to-device copy (FETCH_SIZE 131093 KiB -> x2.0, WRITE_SIZE
 # 262144 KiB -> x1.0).  Valid only for the variant and kernel sources the
 # counters were taken on; otherwise the bench reports traffic as null.
 MEASURED_TRAFFIC = {
     "variant": "ki=1 jt=256 u=8", "rsqrt_refine": 0,
-    "sources_sha256": "a59cb5971cb6553d9a7ed28e92d2f4de7b3fd7ab0566d7e8324173ac98b008b3",
-    "fetch_kib": 22719, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
+    "sources_sha256": "45767ac6423b39e480e1c3d03f700d07d892f8f3123becd602779e5c99a40e2b",
+    "fetch_kib": 22721, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
 }
 KERNEL_SOURCES = ("paper_1203_4037_amd/csrc/newton.hip", "paper_1203_4037_amd/csrc/pairs.h")
 
@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the built-in default variant instead of the autotuned one")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target wall time of the CPU baseline sample")
     ap.add_argument("--replays", type=int, default=0,
                     help="graph replays per secondary measurement (0: the built-in counts; "

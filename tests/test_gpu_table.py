@@ -160,16 +160,28 @@ def test_table_autotuner(pgh, ctx):
         pgh.pgh_autotune(ctx.h, pgh.PGH_FAMILY_NEWTON_BATCH, n, d[0], d[1], d[2], 1)
 
 
+def _same_table(t, ref, E, F):
+    """Node values within 2 FP32 ulps; chords within those ulps over the bin
+    width (a chord divides a difference of rounded node values by it)."""
+    K = 1 << (E + F)
+    v, rv = t[0::2].astype(np.float64), ref[0::2].astype(np.float64)
+    ulp = 2.0 ** -23
+    assert np.all(np.abs(v - rv) <= 2 * ulp * np.abs(rv) + 1e-30), np.abs(v - rv).max()
+    nodes = np.array([oracle.node_s(E, F, k) for k in range(K)])
+    tol = 3 * ulp * (np.abs(rv[:-1]) + np.abs(rv[1:])) / np.diff(nodes)
+    d1 = np.abs(t[1:-2:2].astype(np.float64) - ref[1:-2:2])
+    assert np.all(d1 <= tol + 2 * ulp * np.abs(ref[1:-2:2])), (d1 / (tol + 1e-300)).max()
+
+
 def _soft_cut_tables(ctx, E, F, rcut, eps):
-    h = lambda r: oracle.shape_h(oracle.SHAPE_SOFT_CUT, r, eps, rcut)
-    p = lambda r: oracle.shape_p(oracle.SHAPE_SOFT_CUT, r, eps, rcut)
+    rc = float(np.float32(rcut))  # the FP32 cutoff both table builders use
+    h = lambda r: oracle.shape_h(oracle.SHAPE_SOFT_CUT, r, eps, rc)
+    p = lambda r: oracle.shape_p(oracle.SHAPE_SOFT_CUT, r, eps, rc)
     ft = ctx.build_table(E, F, rcut, f_over_r=h)
     pt = ctx.build_pot_table(p)
     # the library's host builder against the oracle's own tables (pinned on the CPU)
-    of = oracle.table_build(E, F, float(np.float32(rcut)), oracle.SHAPE_SOFT_CUT, eps)
-    op = oracle.pot_table_build(E, F, float(np.float32(rcut)), oracle.SHAPE_SOFT_CUT, eps)
-    assert np.allclose(ft, of, rtol=2e-6, atol=2e-6 * np.abs(of).max())
-    assert np.allclose(pt, op, rtol=2e-6, atol=2e-6 * np.abs(op).max())
+    _same_table(ft, oracle.table_build(E, F, rc, oracle.SHAPE_SOFT_CUT, eps), E, F)
+    _same_table(pt, oracle.pot_table_build(E, F, rc, oracle.SHAPE_SOFT_CUT, eps), E, F)
     return ft, pt
 
 
@@ -249,3 +261,42 @@ def test_potential_table_state_errors(pgh, ctx):
     with pytest.raises(pgh.PGHError) as e:
         ctx.table_force(x, x, x, with_phi=True)
     assert e.value.code == pgh.PGH_ESTATE
+
+
+@pytest.mark.parametrize("E,F", [(6, 6), (4, 8)])
+def test_largest_tables_with_potential(pgh, ctx, E, F):
+    """E + F = 12 (4096 nodes, 64 KiB of force and potential table in LDS),
+    all-pairs and batched, both table forms, against the oracle."""
+    n = 4096
+    rcut, eps = 0.2, 0.01
+    x, y, z = synth.uniform_box(n, 73, box=0.4)
+    m = synth.equal_masses(n)
+    ft, pt = _soft_cut_tables(ctx, E, F, rcut, eps)
+    d = to_dev(x, y, z, m)
+    ctx.set_j(*d)
+    rc = float(np.float32(rcut))
+    items = np.array([[0, n // 2, 0, n], [n // 2, n // 2, n // 4, n // 2]], np.int32)
+    ra = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rc, ft)
+    rp, sp = oracle.lut_pot_items(items, x, y, z, x, y, z, m, E, F, rc, pt)
+    plan = ctx.plan(items, n, n)
+    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH)):
+        ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, v)
+        out = plan.table(*d[:3], *d, with_phi=True)
+        a = np.stack(to_host(*out[:3]))
+        has = ra[3] > 0
+        e = norm_vec_err(a[:, has], np.stack(ra[:3])[:, has], ra[3][has])
+        assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
+        ep = np.abs(to_host(out[3])[0] - rp)[sp > 0] / sp[sp > 0]
+        assert rms(ep) <= 1e-5 and ep.max() <= 1e-3, (v, rms(ep), ep.max())
+    whole = np.array([[0, n, 0, n]], np.int32)
+    ra = oracle.lut_items(whole, x, y, z, x, y, z, m, E, F, rc, ft)
+    rp, sp = oracle.lut_pot_items(whole, x, y, z, x, y, z, m, E, F, rc, pt)
+    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_ALLPAIRS)):
+        ctx.set_variant(pgh.PGH_FAMILY_TABLE_ALLPAIRS, v)
+        ax, ay, az, phi = ctx.table_force(d[0], d[1], d[2], with_phi=True)
+        a = np.stack(to_host(ax, ay, az))
+        has = ra[3] > 0
+        e = norm_vec_err(a[:, has], np.stack(ra[:3])[:, has], ra[3][has])
+        assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
+        ep = np.abs(to_host(phi)[0] - rp)[sp > 0] / sp[sp > 0]
+        assert rms(ep) <= 1e-5 and ep.max() <= 1e-3, (v, rms(ep), ep.max())
