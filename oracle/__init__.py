@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pgh_oracle.c")
+_SRCS = (_SRC, os.path.join(_HERE, "tree_oracle.c"))
 _LIB = os.path.join(_HERE, "libpgh_oracle.so")
 
 SHAPE_S2PP = 0
@@ -30,10 +31,12 @@ SHAPE_SOFT_CUT = 2
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2 -fopenmp, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(
+        os.path.getmtime(_LIB) < os.path.getmtime(src) for src in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
-                               "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-Wall", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -70,9 +73,19 @@ def lib():
             "pgo_lut_pot_items": [l, P, P, P, P, P, P, P, P, i, i, d, P, l, P, P],
             "pgo_lut_bwd_pos_items": [l, P, P, P, P, P, P, P, P, P, P, P, i, i, d, P, l, l,
                                       P, P, P, P, P, P, P, P],
+            "pgo_tree_frame": [l, P, P, P, P],
+            "pgo_tree_keys": [l, P, P, P, P, P],
+            "pgo_tree_sort": [l, P, P],
+            "pgo_tree_build": [l, P, i, l, P, P, P, P, P, P],
+            "pgo_tree_moments": [l, P, P, P, P, P, P, P, P, P],
+            "pgo_sym3_eigen": [P, P, P],
+            "pgo_tree_pseudo": [l, P, P, P, i, P, P, P, P],
+            "pgo_tree_groups": [l, P, P, P, P, i, P],
+            "pgo_tree_walk": [l, P, P, P, P, P, P, d, P, P, P, l, d, i, l, P, P],
         }
         ret = {"pgo_s2_R": d, "pgo_s2pp_f": d, "pgo_shape_h": d, "pgo_shape_p": d, "pgo_smax": d,
-               "pgo_node_s": d, "pgo_node_r": d, "pgo_lut_index": l, "pgo_lut_eval": d}
+               "pgo_node_s": d, "pgo_node_r": d, "pgo_lut_index": l, "pgo_lut_eval": d,
+               "pgo_tree_build": l, "pgo_tree_groups": l, "pgo_tree_walk": l}
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
@@ -301,3 +314,137 @@ def lut_pot_items(items, xi, yi, zi, xj, yj, zj, mj, E, F, rcut, ptable):
                             _ptr(yj), _ptr(zj), _ptr(mj), E, F, float(rcut), _ptr(t), xi.size,
                             _ptr(phi), _ptr(sa))
     return phi, sa
+
+
+# --------------------------------------------------------------------------
+# Barnes-Hut tree and its interaction lists (the tree code of Sec. 5);
+# the definitions are stated in tree_oracle.c.
+# --------------------------------------------------------------------------
+
+class Tree:
+    """Octree of one particle set with its node moments and pseudo-particles.
+
+    Fields: frame (lo[3], extent, scale in FP32), keys (sorted), perm (rank ->
+    original index), x, y, z, m (sorted, float64 holding the FP32 inputs),
+    node arrays begin, count, level, first_child, n_child, parent, moments
+    mass, com [n, 3], S [n, 6] (xx, yy, zz, xy, xz, yz), pseudo-particles px,
+    py, pz, pm (n_pp per node, node-major), and groups (node ids in key
+    order) once ``groups(n_crit)`` has run.
+    """
+
+    def __init__(self, x, y, z, m, n_leaf, quad):
+        x, y, z = (np.ascontiguousarray(a, dtype=np.float32) for a in (x, y, z))
+        n = x.size
+        self.n, self.n_leaf, self.quad = n, int(n_leaf), bool(quad)
+        self.npp = 3 if quad else 1
+        L = lib()
+        self.frame = np.zeros(5, np.float32)
+        L.pgo_tree_frame(n, _ptr(x), _ptr(y), _ptr(z), _ptr(self.frame))
+        keys = np.zeros(n, np.uint64)
+        L.pgo_tree_keys(n, _ptr(x), _ptr(y), _ptr(z), _ptr(self.frame), _ptr(keys))
+        self.perm = np.zeros(n, np.int64)
+        L.pgo_tree_sort(n, _ptr(keys), _ptr(self.perm))
+        self.keys = np.ascontiguousarray(keys[self.perm])
+        self.x, self.y, self.z = (_f64(a[self.perm]) for a in (x, y, z))
+        self.m = _f64(np.asarray(m, dtype=np.float32)[self.perm])
+        cap = max(16, 2 * n + 16)
+        while True:
+            arrs = [np.zeros(cap, np.int64), np.zeros(cap, np.int64), np.zeros(cap, np.int32),
+                    np.zeros(cap, np.int64), np.zeros(cap, np.int32), np.zeros(cap, np.int64)]
+            nn = L.pgo_tree_build(n, _ptr(self.keys), self.n_leaf, cap, *[_ptr(a) for a in arrs])
+            if nn >= 0:
+                break
+            cap *= 2
+        (self.begin, self.count, self.level, self.first_child, self.n_child,
+         self.parent) = (a[:nn].copy() for a in arrs)
+        self.n_nodes = nn
+        self.mass = np.zeros(nn)
+        self.com = np.zeros((nn, 3))
+        self.S = np.zeros((nn, 6))
+        L.pgo_tree_moments(nn, _ptr(self.begin), _ptr(self.count), _ptr(self.x), _ptr(self.y),
+                           _ptr(self.z), _ptr(self.m), _ptr(self.mass), _ptr(self.com),
+                           _ptr(self.S))
+        k = nn * self.npp
+        self.px, self.py, self.pz, self.pm = (np.zeros(k) for _ in range(4))
+        L.pgo_tree_pseudo(nn, _ptr(self.mass), _ptr(self.com), _ptr(self.S), int(self.quad),
+                          _ptr(self.px), _ptr(self.py), _ptr(self.pz), _ptr(self.pm))
+        self.groups = None
+
+    @property
+    def extent(self):
+        return float(self.frame[3])
+
+    def find_groups(self, n_crit):
+        g = np.zeros(max(1, self.n_nodes), np.int64)
+        ng = lib().pgo_tree_groups(self.n_nodes, _ptr(self.begin), _ptr(self.count),
+                                   _ptr(self.n_child), _ptr(self.parent), int(n_crit), _ptr(g))
+        self.groups = g[:ng].copy()
+        return self.groups
+
+    def walk(self, g, theta):
+        """(src, margin) of group node g: src as in pgo_tree_walk."""
+        args = (self.n_nodes, _ptr(self.begin), _ptr(self.count), _ptr(self.level),
+                _ptr(self.first_child), _ptr(self.n_child), _ptr(self.com), self.extent,
+                _ptr(self.x), _ptr(self.y), _ptr(self.z), int(g), float(theta), int(self.quad))
+        L = lib()
+        n = L.pgo_tree_walk(*args, 0, None, None)
+        src = np.zeros(max(1, n), np.int64)
+        mg = ctypes.c_double(0.0)
+        L.pgo_tree_walk(*args, n, _ptr(src), ctypes.byref(mg))
+        return src[:n], mg.value
+
+    def list_arrays(self, src):
+        """(xj, yj, zj, mj) float64 of a list given by its src entries."""
+        part = src >= 0
+        q = np.where(part, 0, -1 - src)
+        r = np.where(part, src, 0)
+        xj = np.where(part, self.x[r], self.px[q])
+        yj = np.where(part, self.y[r], self.py[q])
+        zj = np.where(part, self.z[r], self.pz[q])
+        mj = np.where(part, self.m[r], self.pm[q])
+        return xj, yj, zj, mj
+
+    def lists(self, groups, theta):
+        """Lists of the given group nodes: (items [k, 4] int64 in sorted
+        particle ranks, src, xj, yj, zj, mj, margins)."""
+        items, srcs, margins = [], [], []
+        off = 0
+        for g in groups:
+            src, mg = self.walk(g, theta)
+            items.append((self.begin[g], self.count[g], off, src.size))
+            srcs.append(src)
+            margins.append(mg)
+            off += src.size
+        src = np.concatenate(srcs) if srcs else np.zeros(0, np.int64)
+        xj, yj, zj, mj = self.list_arrays(src)
+        return (np.array(items, dtype=np.int64).reshape(-1, 4), src, xj, yj, zj, mj,
+                np.array(margins))
+
+
+def tree_build(x, y, z, m, n_leaf=8, quad=False):
+    """Octree, moments and pseudo-particles of FP32 positions x, y, z."""
+    return Tree(x, y, z, m, n_leaf, quad)
+
+
+def sym3_eigen(S6):
+    """Eigenvalues (descending) and eigenvectors (columns) of a symmetric 3x3
+    given as (xx, yy, zz, xy, xz, yz)."""
+    s = _f64(S6)
+    w = np.zeros(3)
+    V = np.zeros(9)
+    lib().pgo_sym3_eigen(_ptr(s), _ptr(w), _ptr(V))
+    return w, V.reshape(3, 3)
+
+
+def tree_force(tree, theta, n_crit, eps, groups=None):
+    """Tree force and potential on the sorted particles of the chosen groups
+    (all by default): the direct sum over each group's list with softening
+    eps (Eq. newton_force).  Returns (items, src, margins, ax, ay, az, phi)
+    with rows in sorted order (rows outside the groups are zero)."""
+    if tree.groups is None or groups is None:
+        tree.find_groups(n_crit)
+    gs = tree.groups if groups is None else np.asarray(groups)
+    items, src, xj, yj, zj, mj, margins = tree.lists(gs, theta)
+    e2 = np.full(tree.n, float(np.float32(eps)) ** 2)
+    ax, ay, az, phi = newton_items(items, tree.x, tree.y, tree.z, e2, xj, yj, zj, mj)
+    return items, src, margins, ax, ay, az, phi
