@@ -331,3 +331,52 @@ def test_table_position_gradients_cell_lists(pgh, ctx, block):
     with pytest.raises(pgh.PGHError):  # triples only
         pgh.pgh_batch_table_bwd(ctx.h, plan.h, di[0], di[1], di[2], *dj, di[3], di[4], di[5],
                                 None, None, gi[0], None, None)
+
+
+def test_table_adjoint_graph_replays(pgh, ctx):
+    """The table adjoint (zeroing prologue, persistent kernel, summing kernel)
+    captured in a graph and replayed several times with eager work in
+    between: every replay matches the eager call (float atomics: to rounding)."""
+    import torch
+    n = 16384
+    x, y, z = synth.uniform_box(n, 81)
+    m = synth.equal_masses(n)
+    s = synth.cell_grid_items(x, y, z, m, ncell=32, block=4)
+    table = ctx.build_table(4, 6, 1.0 / 32, eps=1.0 / 480)
+    plan = ctx.plan(s.items, n, s.xj.size)
+    di = to_dev(s.xi, s.yi, s.zi, *synth.weights(n, 82))
+    dj = to_dev(s.xj, s.yj, s.zj, s.mj)
+    gt = torch.empty(table.size, device="cuda")
+    gm = torch.empty(s.xj.size, device="cuda")
+    gi = [torch.empty(n, device="cuda") for _ in range(3)]
+
+    def call():
+        pgh.pgh_batch_table_bwd(ctx.h, plan.h, di[0], di[1], di[2], *dj, di[3], di[4], di[5],
+                                gt, gm, *gi)
+
+    ctx._sync_stream()
+    call()
+    torch.cuda.synchronize()
+    ref = [to_host(t)[0].copy() for t in (gt, gm, *gi)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ctx._sync_stream()
+        call()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx._sync_stream()
+        call()
+    for rep in range(3):
+        for t in (gt, gm, *gi):
+            t.fill_(123.0)
+        g.replay()
+        torch.cuda.synchronize()
+        for r, t in zip(ref, (gt, gm, *gi)):
+            got = to_host(t)[0]
+            tol = 1e-4 * (np.abs(r) + np.abs(r).max())  # float atomics add in any order
+            assert np.all(np.abs(got - r) <= tol), rep
+        ctx._sync_stream()
+        call()  # eager work between replays
+        torch.cuda.synchronize()

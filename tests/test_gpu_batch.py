@@ -266,3 +266,56 @@ def test_plan_autotuner(pgh, ctx):
     with pytest.raises(pgh.PGHError) as e:
         plan.autotune(pgh.PGH_FAMILY_NEWTON_ALLPAIRS, *di, *dj)
     assert e.value.code == pgh.PGH_ERANGE
+
+
+def test_plan_autotuner_table_family(pgh, ctx):
+    """pgh_autotune_plan on the table family picks one of its variants, and
+    the chosen kernel meets the gate against the oracle."""
+    n = 16384
+    x, y, z = synth.uniform_box(n, 91)
+    m = synth.equal_masses(n)
+    rcut = 1.0 / 32
+    s = synth.cell_grid_items(x, y, z, m, ncell=32, block=4)
+    table = ctx.build_table(4, 6, rcut, eps=rcut / 15)
+    di, dj = _dev_set(s)
+    plan = ctx.plan(s.items, n, s.xj.size)
+    v = plan.autotune(pgh.PGH_FAMILY_TABLE_BATCH, *di, *dj, reps=2)
+    assert pgh.pgh_get_variant(ctx.h, pgh.PGH_FAMILY_TABLE_BATCH) == v
+    a = np.stack(to_host(*plan.table(*di, *dj)))
+    rt = oracle.lut_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, 4, 6,
+                          float(np.float32(rcut)), table)
+    has = rt[3] > 0
+    e = norm_vec_err(a[:, has], np.stack(rt[:3])[:, has], rt[3][has])
+    assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
+
+
+def test_two_contexts_on_two_streams(pgh):
+    """Two contexts, each on its own stream with its own j-memory, table and
+    plans, launched interleaved: no state leaks from one to the other."""
+    import torch
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ca, cb = pgh.Context(0), pgh.Context(0)
+    n = 4096
+    xa = synth.plummer(n, 93)
+    xb = synth.plummer(n, 94)
+    m = synth.equal_masses(n)
+    da, db = to_dev(*xa, m), to_dev(*xb, m)
+    torch.cuda.synchronize()
+    outs = {}
+    for rep in range(3):
+        with torch.cuda.stream(sa):
+            ca.set_eps_to_all(0.01)
+            ca.set_j(*da)
+            outs["a"] = ca.newton(da[0], da[1], da[2])
+        with torch.cuda.stream(sb):
+            cb.set_eps_to_all(0.05)
+            cb.set_j(*db)
+            outs["b"] = cb.newton(db[0], db[1], db[2])
+    torch.cuda.synchronize()
+    for key, x, eps in (("a", xa, 0.01), ("b", xb, 0.05)):
+        ref = oracle.newton(*x, np.full(n, np.float32(eps) ** 2, np.float32), *x, m)
+        a = np.stack(to_host(*outs[key][:3]))
+        ea = rel_vec_err(a, np.stack(ref[:3]))
+        assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, (key, rms(ea), ea.max())
+    ca.close()
+    cb.close()
