@@ -357,6 +357,115 @@ PGH_API int pgh_autotune_plan(pgh_ctx *c, int family, const pgh_plan *p, const f
                               const float *yj, const float *zj, const float *mj, int reps,
                               float *best_ms);
 
+/* ---------------------------------------------------------------------- */
+/* Barnes-Hut tree producing the interaction lists of the tree code of      */
+/* Sec. 5: groups of i-particles that share one list (Barnes' modification),*/
+/* opening parameter theta (the paper uses 0.75), monopole moments or       */
+/* quadrupole moments carried by pseudo-particles (Kawai & Makino), all     */
+/* built on the device and fed to the batched Newton kernel.                */
+/*                                                                          */
+/* The paper fixes the method only in outline; this library's definitions: */
+/*   - a Morton-ordered octree over the bounding cube of the particles (the */
+/*     componentwise minimum and the largest axis range, 21 key bits per    */
+/*     axis computed in FP32), particles sorted by (key, input index);      */
+/*   - a node splits into its non-empty octants while it holds more than    */
+/*     n_leaf particles (at most 21 levels); node size = extent / 2^level;  */
+/*   - FP64 moments per node; pseudo-particles: monopole, one of mass M at  */
+/*     the centre of mass; quadrupole, three of mass M/3 in the plane of    */
+/*     the two largest principal axes of the second moment, which carry    */
+/*     the node's mass, zero dipole and its traceless quadrupole;           */
+/*   - the i-groups are the nodes that hold at most n_crit particles (or    */
+/*     are leaves) and whose parent holds more, in key order;               */
+/*   - a group's list: walking breadth first from the root, a node that is  */
+/*     the group or one of its ancestors is opened; any other node is       */
+/*     accepted when its size l < theta d, d the distance from its centre   */
+/*     of mass to the bounding box of the group's particles, and adds its   */
+/*     pseudo-particles; an opened leaf adds its particles.  The group's    */
+/*     own particles are in its list (so the raw potential includes the     */
+/*     self term, as for every other call here).                            */
+/* ---------------------------------------------------------------------- */
+
+typedef struct pgh_tree pgh_tree;
+
+/* Creates an empty tree owned by context c (freed with it at pgh_close). */
+PGH_API int pgh_tree_create(pgh_ctx *c, pgh_tree **out);
+/* Frees the tree's device memory; waits for the context's stream first. */
+PGH_API int pgh_tree_free(pgh_ctx *c, pgh_tree *t);
+
+/* Builds the octree of n particles (device arrays, read during the call),
+ * their moments, pseudo-particles (quad != 0: three per node) and the
+ * i-groups.  Synchronous: waits for the stream once per tree level.
+ * n_leaf in [1, 64], n_crit >= n_leaf (PGH_ERANGE otherwise); positions must
+ * be finite (PGH_ERANGE).  Invalidates the lists of an earlier walk. */
+PGH_API int pgh_tree_build(pgh_ctx *c, pgh_tree *t, int n, const float *x, const float *y,
+                           const float *z, const float *m, int n_leaf, int n_crit, int quad);
+
+/* Walks the tree for every group with opening parameter theta >= 0 and
+ * writes the lists (device memory owned by the tree) and a batched plan for
+ * them.  record_src != 0 also keeps each entry's source (PGH_TREE_LIST_SRC).
+ * Synchronous.  PGH_ESTATE before a build; PGH_ERANGE when theta is too
+ * small for the walk's frontier (more than 4096 nodes to test on one level
+ * for one group) or the lists exceed 2^31 - 1 entries. */
+PGH_API int pgh_tree_walk(pgh_ctx *c, pgh_tree *t, float theta, int record_src);
+
+/* Newton's force and raw potential on every particle from the lists of the
+ * last walk, with the context's eps (pgh_set_eps_to_all): the batched kernel
+ * in key order, then scattered back to the input order into ax, ay, az, phi
+ * (device float[n]; phi may be NULL).  Asynchronous.  PGH_ESTATE before a
+ * walk. */
+PGH_API int pgh_tree_newton(pgh_ctx *c, pgh_tree *t, float *ax, float *ay, float *az,
+                            float *phi);
+
+typedef struct pgh_tree_stats {
+    int n, n_nodes, n_leaves, depth, n_groups, max_level_nodes;
+    int n_leaf, n_crit, quad, walked;
+    float theta;
+    float frame[5];          /* lo x, y, z, extent, key scale (2^21 / extent) */
+    long long n_entries;     /* list entries of the last walk */
+    long long interactions;  /* sum over groups of n_i n_j */
+} pgh_tree_stats;
+
+/* Counts of the last build and walk (host struct). */
+PGH_API int pgh_tree_stats_get(const pgh_tree *t, pgh_tree_stats *out);
+
+/* The plan of the last walk (owned by the tree; NULL before a walk), for
+ * pgh_batch_newton / pgh_batch_table with the arrays of pgh_tree_get. */
+PGH_API const pgh_plan *pgh_tree_plan(const pgh_tree *t);
+
+/* Arrays of a tree, for pgh_tree_get: element type and count. */
+enum pgh_tree_field {
+    PGH_TREE_PERM = 0,        /* int32[n]: input index of the particle of rank r */
+    PGH_TREE_KEYS = 1,        /* uint64[n]: sorted keys */
+    PGH_TREE_X = 2,           /* float[n]: positions and masses in key order */
+    PGH_TREE_Y = 3,
+    PGH_TREE_Z = 4,
+    PGH_TREE_M = 5,
+    PGH_TREE_NODE_BEGIN = 6,  /* int32[n_nodes]: first particle rank */
+    PGH_TREE_NODE_COUNT = 7,  /* int32[n_nodes] */
+    PGH_TREE_NODE_LEVEL = 8,  /* int32[n_nodes] */
+    PGH_TREE_NODE_FIRST_CHILD = 9, /* int32[n_nodes], -1 for a leaf */
+    PGH_TREE_NODE_N_CHILD = 10,    /* int32[n_nodes] */
+    PGH_TREE_NODE_PARENT = 11,     /* int32[n_nodes], -1 for the root */
+    PGH_TREE_MOMENTS = 12,    /* double[n_nodes][10]: M, com x y z, S xx yy zz xy xz yz */
+    PGH_TREE_PSEUDO = 13,     /* float[n_nodes * (quad ? 3 : 1)][4]: x, y, z, m */
+    PGH_TREE_GROUPS = 14,     /* int32[n_groups]: node of each group, key order */
+    PGH_TREE_ITEMS = 15,      /* pgh_item[n_groups]: i-range in key order, j-range */
+    PGH_TREE_LIST_X = 16,     /* float[n_entries]: the lists, group after group */
+    PGH_TREE_LIST_Y = 17,
+    PGH_TREE_LIST_Z = 18,
+    PGH_TREE_LIST_M = 19,
+    PGH_TREE_LIST_SRC = 20    /* int32[n_entries] (walk with record_src): the
+                                 particle rank, or -(1 + q) for pseudo-particle q */
+};
+
+/* Copies field `field` into dst (device or host memory) of `capacity`
+ * elements; *count (may be NULL) receives the element count.  dst NULL with
+ * capacity 0 only reports the count.  Synchronous.
+ * PGH_ERANGE if capacity is too small or the field is unknown; PGH_ESTATE
+ * for list fields before a walk (or LIST_SRC without record_src). */
+PGH_API int pgh_tree_get(pgh_ctx *c, const pgh_tree *t, int field, void *dst,
+                         long long capacity, long long *count);
+
 #ifdef __cplusplus
 }
 #endif

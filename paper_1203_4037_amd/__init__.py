@@ -18,6 +18,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch  # first, so that libpgh binds to the HIP runtime torch has loaded
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,6 +39,31 @@ class PGHError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{_STATUS.get(code, code)}: {msg}")
         self.code = code
+
+
+class PghTreeStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("n_nodes", ctypes.c_int), ("n_leaves", ctypes.c_int),
+                ("depth", ctypes.c_int), ("n_groups", ctypes.c_int),
+                ("max_level_nodes", ctypes.c_int), ("n_leaf", ctypes.c_int),
+                ("n_crit", ctypes.c_int), ("quad", ctypes.c_int), ("walked", ctypes.c_int),
+                ("theta", ctypes.c_float), ("frame", ctypes.c_float * 5),
+                ("n_entries", ctypes.c_longlong), ("interactions", ctypes.c_longlong)]
+
+
+# Tree fields of pgh_tree_get: (enum value, numpy dtype, trailing shape)
+PGH_TREE_FIELDS = {
+    "perm": (0, np.int32, ()), "keys": (1, np.uint64, ()),
+    "x": (2, np.float32, ()), "y": (3, np.float32, ()), "z": (4, np.float32, ()),
+    "m": (5, np.float32, ()),
+    "node_begin": (6, np.int32, ()), "node_count": (7, np.int32, ()),
+    "node_level": (8, np.int32, ()), "node_first_child": (9, np.int32, ()),
+    "node_n_child": (10, np.int32, ()), "node_parent": (11, np.int32, ()),
+    "moments": (12, np.float64, (10,)), "pseudo": (13, np.float32, (4,)),
+    "groups": (14, np.int32, ()), "items": (15, np.int32, (4,)),
+    "list_x": (16, np.float32, ()), "list_y": (17, np.float32, ()),
+    "list_z": (18, np.float32, ()), "list_m": (19, np.float32, ()),
+    "list_src": (20, np.int32, ()),
+}
 
 
 class PghItem(ctypes.Structure):
@@ -81,6 +107,14 @@ SIGNATURES = {
     "pgh_autotune_plan": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _I, ctypes.POINTER(_F)]),
     "pgh_correct_self_potential": (_I, [_P, _I, _P, _P, _P]),
     "pgh_table_grad_chain": (_I, [_P, _I, _I, _P, _P]),
+    "pgh_tree_create": (_I, [_P, ctypes.POINTER(_P)]),
+    "pgh_tree_free": (_I, [_P, _P]),
+    "pgh_tree_build": (_I, [_P, _P, _I, _P, _P, _P, _P, _I, _I, _I]),
+    "pgh_tree_walk": (_I, [_P, _P, _F, _I]),
+    "pgh_tree_newton": (_I, [_P, _P, _P, _P, _P, _P]),
+    "pgh_tree_stats_get": (_I, [_P, _P]),
+    "pgh_tree_plan": (_P, [_P]),
+    "pgh_tree_get": (_I, [_P, _P, _I, _P, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),
     # GRAPE-5-compatible host interface (include/grape5.h)
     "g5_open": (None, []),
     "g5_close": (None, []),
@@ -238,7 +272,6 @@ def pgh_calc_table(ctx, ni, xi, yi, zi, ax, ay, az, phi=None):
 
 
 def _items_array(items):
-    import numpy as np
     a = np.ascontiguousarray(np.asarray(items, dtype=np.int32).reshape(-1, 4))
     return a
 
@@ -372,6 +405,104 @@ def pgh_autotune_plan(ctx, family, plan, xi, yi, zi, xj, yj, zj, mj, reps=3):
 
 
 # --------------------------------------------------------------------------
+# Barnes-Hut tree (pgh_tree_*): lists of the tree code built on the device
+# --------------------------------------------------------------------------
+
+def pgh_tree_create(ctx):
+    h = ctypes.c_void_p()
+    _check(ctx, lib.pgh_tree_create(ctx, ctypes.byref(h)))
+    return h.value
+
+
+def pgh_tree_free(ctx, tree):
+    _check(ctx, lib.pgh_tree_free(ctx, tree))
+
+
+def pgh_tree_build(ctx, tree, n, x, y, z, m, n_leaf=8, n_crit=64, quad=0):
+    _check(ctx, lib.pgh_tree_build(ctx, tree, int(n), _ptr(x, n, "x"), _ptr(y, n, "y"),
+                                   _ptr(z, n, "z"), _ptr(m, n, "m"), int(n_leaf), int(n_crit),
+                                   int(quad)))
+
+
+def pgh_tree_walk(ctx, tree, theta, record_src=0):
+    _check(ctx, lib.pgh_tree_walk(ctx, tree, float(theta), int(record_src)))
+
+
+def pgh_tree_newton(ctx, tree, ax, ay, az, phi=None):
+    _check(ctx, lib.pgh_tree_newton(ctx, tree, _ptr(ax, None, "ax"), _ptr(ay, None, "ay"),
+                                    _ptr(az, None, "az"), _ptr(phi, None, "phi")))
+
+
+def pgh_tree_stats_get(tree):
+    st = PghTreeStats()
+    rc = lib.pgh_tree_stats_get(tree, ctypes.byref(st))
+    if rc != PGH_OK:
+        raise PGHError(rc, "pgh_tree_stats_get failed")
+    d = {k: getattr(st, k) for k, _ in PghTreeStats._fields_}
+    d["frame"] = np.array(list(st.frame), dtype=np.float32)
+    return d
+
+
+def pgh_tree_plan(tree):
+    return lib.pgh_tree_plan(tree)
+
+
+def pgh_tree_get(ctx, tree, field):
+    """Host numpy copy of a tree field (a name of PGH_TREE_FIELDS)."""
+    code, dtype, tail = PGH_TREE_FIELDS[field]
+    cnt = ctypes.c_longlong()
+    _check(ctx, lib.pgh_tree_get(ctx, tree, code, None, 0, ctypes.byref(cnt)))
+    out = np.empty((cnt.value,) + tail, dtype=dtype)
+    if cnt.value:
+        _check(ctx, lib.pgh_tree_get(ctx, tree, code, out.ctypes.data, cnt.value,
+                                     ctypes.byref(cnt)))
+    return out
+
+
+class Tree:
+    """A device Barnes-Hut tree of one context (pgh_tree_*)."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+        self.h = pgh_tree_create(ctx.h)
+        self.n = 0
+
+    def free(self):
+        if self.h and self.ctx.h:
+            pgh_tree_free(self.ctx.h, self.h)
+        self.h = None
+
+    def build(self, x, y, z, m, n_leaf=8, n_crit=64, quad=False):
+        self.ctx._sync_stream()
+        self.n = x.numel()
+        pgh_tree_build(self.ctx.h, self.h, self.n, x, y, z, m, n_leaf, n_crit, int(bool(quad)))
+        return self
+
+    def walk(self, theta=0.75, record_src=False):
+        self.ctx._sync_stream()
+        pgh_tree_walk(self.ctx.h, self.h, theta, int(bool(record_src)))
+        return self
+
+    def newton(self, out=None, with_phi=True):
+        """Tree force (and raw potential) on every particle, input order."""
+        c = self.ctx
+        c._sync_stream()
+        if out is None:
+            out = [c._empty(self.n) for _ in range(4 if with_phi else 3)]
+        for o in out[:4 if with_phi else 3]:
+            _ptr(o, self.n, "output")
+        pgh_tree_newton(c.h, self.h, out[0], out[1], out[2], out[3] if with_phi else None)
+        return out
+
+    def stats(self):
+        return pgh_tree_stats_get(self.h)
+
+    def get(self, field):
+        self.ctx._sync_stream()
+        return pgh_tree_get(self.ctx.h, self.h, field)
+
+
+# --------------------------------------------------------------------------
 # GRAPE-5-compatible host interface (host numpy arrays in double precision)
 # --------------------------------------------------------------------------
 
@@ -379,7 +510,6 @@ G5_F_OVER_R = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_double)
 
 
 def _host_f64(a, shape_tail, what):
-    import numpy as np
     if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous:
         raise TypeError(f"{what} must be a C-contiguous float64 numpy array")
     if a.shape[1:] != shape_tail:
@@ -504,7 +634,6 @@ class Context:
     def build_table(self, E, F, rcut, f_over_r=None, eps=None):
         """Builds the table from a Python callable h(r) = f(r)/r, or from the
         built-in S2 particle-particle shape when f_over_r is None (needs eps)."""
-        import numpy as np
         out = np.zeros(2 << (E + F), dtype=np.float32)
         if f_over_r is None:
             params = (ctypes.c_double * 2)(float(eps), float(rcut))
@@ -522,7 +651,6 @@ class Context:
     def build_pot_table(self, pot):
         """Potential table of a callable p(r) on the force table's bins; returns
         the host copy (float32, interleaved P0, P1)."""
-        import numpy as np
         E, F, _ = self.table
         out = np.zeros(2 << (E + F), dtype=np.float32)
         pgh_build_pot_table(self.h, pot, None, out)
@@ -574,6 +702,10 @@ class Context:
     def plan(self, items, ni_total, nj_total):
         """A Plan for host items [n, 4] = (i_off, n_i, j_off, n_j)."""
         return Plan(self, items, ni_total, nj_total)
+
+    def tree(self):
+        """An empty device Barnes-Hut tree of this context."""
+        return Tree(self)
 
 
 class Plan:

@@ -58,7 +58,14 @@ struct pgh_ctx {
     float4 *scr_a = nullptr, *scr_b = nullptr;
     size_t scr_a_cap = 0, scr_b_cap = 0;
     std::vector<pgh_plan *> plans;
+    std::vector<pgh_tree *> trees;
     std::string err;
+};
+
+struct pgh_tree {
+    pgh_ctx *owner;
+    TreeState st;
+    pgh_plan *plan;  // batched plan of the last walk (in owner->plans)
 };
 
 namespace {
@@ -222,6 +229,10 @@ int pgh_close(pgh_ctx *c)
     if (!c) return PGH_OK;
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
+    for (pgh_tree *t : c->trees) {
+        tree_release(t->st);
+        delete t;
+    }
     for (pgh_plan *p : c->plans) {
         free_plan_memory(p);
         delete p;
@@ -1121,6 +1132,191 @@ int pgh_autotune_plan(pgh_ctx *c, int family, const pgh_plan *p, const float *xi
     });
     (void)hipFree(out);
     return r;
+}
+
+// ---------------------------------------------------------------------------
+// Barnes-Hut tree
+// ---------------------------------------------------------------------------
+
+namespace {
+
+int check_tree(pgh_ctx *c, const pgh_tree *t)
+{
+    if (!t) return fail(c, PGH_EINVAL, "NULL tree");
+    if (t->owner != c) return fail(c, PGH_EINVAL, "tree belongs to another context");
+    return PGH_OK;
+}
+
+}  // namespace
+
+int pgh_tree_create(pgh_ctx *c, pgh_tree **out)
+{
+    if (!c) return PGH_EINVAL;
+    if (!out) return fail(c, PGH_EINVAL, "out is NULL");
+    pgh_tree *t = new (std::nothrow) pgh_tree;
+    if (!t) return fail(c, PGH_ENOMEM, "out of host memory");
+    t->owner = c;
+    t->plan = nullptr;
+    c->trees.push_back(t);
+    *out = t;
+    return PGH_OK;
+}
+
+int pgh_tree_free(pgh_ctx *c, pgh_tree *t)
+{
+    if (!c) return PGH_EINVAL;
+    if (!t) return PGH_OK;
+    auto it = std::find(c->trees.begin(), c->trees.end(), t);
+    if (it == c->trees.end()) return fail(c, PGH_EINVAL, "tree does not belong to this context");
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (t->plan) (void)pgh_plan_free(c, t->plan);
+    tree_release(t->st);
+    c->trees.erase(it);
+    delete t;
+    return PGH_OK;
+}
+
+int pgh_tree_build(pgh_ctx *c, pgh_tree *t, int n, const float *x, const float *y,
+                   const float *z, const float *m, int n_leaf, int n_crit, int quad)
+{
+    if (!c) return PGH_EINVAL;
+    int st = check_tree(c, t);
+    if (st) return st;
+    if (n < 0) return fail(c, PGH_EINVAL, "n must be >= 0");
+    if (n > 0 && (!x || !y || !z || !m)) return fail(c, PGH_EINVAL, "NULL particle array");
+    if (n_leaf < 1 || n_leaf > 64) return fail(c, PGH_ERANGE, "n_leaf must be in [1, 64]");
+    if (n_crit < n_leaf) return fail(c, PGH_ERANGE, "n_crit must be >= n_leaf");
+    DeviceGuard g(c->device);
+    if (t->plan) {
+        (void)pgh_plan_free(c, t->plan);
+        t->plan = nullptr;
+    }
+    std::string err;
+    st = tree_build(t->st, n, x, y, z, m, n_leaf, n_crit, quad, c->num_cu, c->stream, err);
+    if (st) return fail(c, st, err);
+    return PGH_OK;
+}
+
+int pgh_tree_walk(pgh_ctx *c, pgh_tree *t, float theta, int record_src)
+{
+    if (!c) return PGH_EINVAL;
+    int st = check_tree(c, t);
+    if (st) return st;
+    if (!t->st.built) return fail(c, PGH_ESTATE, "build the tree first");
+    if (!(theta >= 0.f) || !std::isfinite(theta)) return fail(c, PGH_ERANGE, "theta must be >= 0");
+    DeviceGuard g(c->device);
+    if (t->plan) {
+        (void)pgh_plan_free(c, t->plan);
+        t->plan = nullptr;
+    }
+    std::string err;
+    st = tree_walk(t->st, theta, record_src, c->num_cu, c->stream, err);
+    if (st) return fail(c, st, err);
+    const TreeState &s = t->st;
+    if (s.n_groups > 0) {
+        st = pgh_plan_create(c, s.n_groups, s.host_items.data(), s.n, (int)s.n_entries, &t->plan);
+        if (st) {
+            t->st.walked = 0;
+            return st;
+        }
+    }
+    return PGH_OK;
+}
+
+int pgh_tree_newton(pgh_ctx *c, pgh_tree *t, float *ax, float *ay, float *az, float *phi)
+{
+    if (!c) return PGH_EINVAL;
+    int st = check_tree(c, t);
+    if (st) return st;
+    if (!t->st.walked) return fail(c, PGH_ESTATE, "walk the tree first");
+    const TreeState &s = t->st;
+    if (s.n == 0) return PGH_OK;
+    if (!ax || !ay || !az) return fail(c, PGH_EINVAL, "NULL output array");
+    DeviceGuard g(c->device);
+    st = pgh_batch_newton(c, t->plan, s.xs, s.ys, s.zs, nullptr, s.xj, s.yj, s.zj, s.mj, s.axs,
+                          s.ays, s.azs, phi ? s.phs : nullptr);
+    if (st) return st;
+    PGH_HIP(c, launch_unpermute(s.n, s.perm, s.axs, s.ays, s.azs, phi ? s.phs : nullptr, ax, ay,
+                                az, phi, c->stream));
+    return PGH_OK;
+}
+
+int pgh_tree_stats_get(const pgh_tree *t, pgh_tree_stats *out)
+{
+    if (!t || !out) return PGH_EINVAL;
+    const TreeState &s = t->st;
+    out->n = s.n;
+    out->n_nodes = s.n_nodes;
+    out->n_leaves = s.n_leaves;
+    out->depth = s.depth;
+    out->n_groups = s.n_groups;
+    out->max_level_nodes = s.max_level_nodes;
+    out->n_leaf = s.n_leaf;
+    out->n_crit = s.n_crit;
+    out->quad = s.quad;
+    out->walked = s.walked;
+    out->theta = s.theta;
+    std::copy(s.frame, s.frame + 5, out->frame);
+    out->n_entries = s.walked ? s.n_entries : -1;
+    out->interactions = s.walked ? s.interactions : 0;
+    return PGH_OK;
+}
+
+const pgh_plan *pgh_tree_plan(const pgh_tree *t) { return t ? t->plan : nullptr; }
+
+int pgh_tree_get(pgh_ctx *c, const pgh_tree *t, int field, void *dst, long long capacity,
+                 long long *count)
+{
+    if (!c) return PGH_EINVAL;
+    int st = check_tree(c, t);
+    if (st) return st;
+    const TreeState &s = t->st;
+    if (!s.built) return fail(c, PGH_ESTATE, "build the tree first");
+    const void *src = nullptr;
+    long long n = 0;
+    size_t elem = 4;
+    const long long npp = s.quad ? 3 : 1;
+    const bool list = field >= PGH_TREE_LIST_X && field <= PGH_TREE_LIST_SRC;
+    if (list && !s.walked) return fail(c, PGH_ESTATE, "walk the tree first");
+    switch (field) {
+    case PGH_TREE_PERM: src = s.perm, n = s.n; break;
+    case PGH_TREE_KEYS: src = s.key, n = s.n, elem = 8; break;
+    case PGH_TREE_X: src = s.xs, n = s.n; break;
+    case PGH_TREE_Y: src = s.ys, n = s.n; break;
+    case PGH_TREE_Z: src = s.zs, n = s.n; break;
+    case PGH_TREE_M: src = s.ms, n = s.n; break;
+    case PGH_TREE_NODE_BEGIN: src = s.begin, n = s.n_nodes; break;
+    case PGH_TREE_NODE_COUNT: src = s.count, n = s.n_nodes; break;
+    case PGH_TREE_NODE_LEVEL: src = s.level, n = s.n_nodes; break;
+    case PGH_TREE_NODE_FIRST_CHILD: src = s.first_child, n = s.n_nodes; break;
+    case PGH_TREE_NODE_N_CHILD: src = s.n_child, n = s.n_nodes; break;
+    case PGH_TREE_NODE_PARENT: src = s.parent, n = s.n_nodes; break;
+    case PGH_TREE_MOMENTS: src = s.mom, n = s.n_nodes, elem = sizeof(NodeMoments); break;
+    case PGH_TREE_PSEUDO: src = s.pp, n = s.n_nodes * npp, elem = sizeof(float4); break;
+    case PGH_TREE_GROUPS: src = s.groups, n = s.n_groups; break;
+    case PGH_TREE_ITEMS:
+        if (!s.walked) return fail(c, PGH_ESTATE, "walk the tree first");
+        src = s.items, n = s.n_groups, elem = sizeof(pgh_item);
+        break;
+    case PGH_TREE_LIST_X: src = s.xj, n = s.n_entries; break;
+    case PGH_TREE_LIST_Y: src = s.yj, n = s.n_entries; break;
+    case PGH_TREE_LIST_Z: src = s.zj, n = s.n_entries; break;
+    case PGH_TREE_LIST_M: src = s.mj, n = s.n_entries; break;
+    case PGH_TREE_LIST_SRC:
+        if (!s.record_src) return fail(c, PGH_ESTATE, "walk with record_src to keep sources");
+        src = s.src, n = s.n_entries;
+        break;
+    default: return fail(c, PGH_ERANGE, "unknown tree field");
+    }
+    if (count) *count = n;
+    if (n == 0 || (!dst && capacity == 0)) return PGH_OK;  // a size query
+    if (capacity < n) return fail(c, PGH_ERANGE, "destination too small for the tree field");
+    if (!dst) return fail(c, PGH_EINVAL, "NULL destination");
+    DeviceGuard g(c->device);
+    PGH_HIP(c, hipMemcpyAsync(dst, src, elem * (size_t)n, hipMemcpyDefault, c->stream));
+    PGH_HIP(c, hipStreamSynchronize(c->stream));
+    return PGH_OK;
 }
 
 }  // extern "C"

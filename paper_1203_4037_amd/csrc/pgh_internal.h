@@ -177,4 +177,77 @@ hipError_t launch_table_batch_bwd(const TableBwdArgs &a, const Task *jtasks, int
                                   const Task *itasks, int n_itasks, unsigned *queue, int num_cu,
                                   hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Barnes-Hut tree (tree.hip): device state and the host steps that drive it.
+// ---------------------------------------------------------------------------
+
+constexpr int kTreeMaxLevel = 21;   // 21 key bits per axis, 63-bit Morton keys
+constexpr int kWalkFrontier = 4096; // nodes per frontier buffer of a walking wave
+
+// FP64 moments of a node about its centre of mass: mass, com, and the second
+// moment S = sum m (x - com)(x - com)^T as (xx, yy, zz, xy, xz, yz).
+struct NodeMoments {
+    double m, cx, cy, cz, sxx, syy, szz, sxy, sxz, syz;
+};
+
+struct TreeState {
+    // particle arrays, capacity n_cap
+    int n_cap = 0;
+    unsigned long long *key = nullptr, *key_in = nullptr;
+    int *perm = nullptr, *iota = nullptr;
+    float *xs = nullptr, *ys = nullptr, *zs = nullptr, *ms = nullptr;
+    int *mark = nullptr;  // group id at the first particle of each group, else -1
+    // sorted-order outputs of the force (scattered back through perm)
+    float *axs = nullptr, *ays = nullptr, *azs = nullptr, *phs = nullptr;
+    // nodes, capacity node_cap (breadth first, each level in key order)
+    int node_cap = 0;
+    int *begin = nullptr, *count = nullptr, *level = nullptr, *first_child = nullptr,
+        *n_child = nullptr, *parent = nullptr;
+    int *nc = nullptr;        // children per node of one level, then their scan
+    int nc_cap = 0;
+    NodeMoments *mom = nullptr;
+    float4 *com = nullptr;    // FP32 centre of mass per node (w unused)
+    float4 *pp = nullptr;     // pseudo-particles (x, y, z, m), npp per node
+    int pp_cap = 0;
+    // groups, capacity group_cap
+    int group_cap = 0;
+    int *groups = nullptr;
+    float4 *glo = nullptr, *ghi = nullptr;  // bounding boxes of the groups
+    long long *glen = nullptr, *goff = nullptr;  // list lengths and offsets (n_groups + 1)
+    pgh_item *items = nullptr;  // device copy of the items
+    // interaction lists, capacity entry_cap
+    long long entry_cap = 0;
+    float *xj = nullptr, *yj = nullptr, *zj = nullptr, *mj = nullptr;
+    int *src = nullptr;  // entry source (with record_src), capacity src_cap
+    long long src_cap = 0;
+    // scratch of the library scans and sorts
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    unsigned *word = nullptr;  // 8 words: min/max frame, leaf count, walk overflow
+    int *count_out = nullptr;
+    float *rc2 = nullptr;      // (l_L / theta)^2 per level for the walk
+    // results of the last build / walk
+    int n = 0, n_nodes = 0, n_leaves = 0, depth = 0, n_groups = 0, max_level_nodes = 0;
+    int level_off[kTreeMaxLevel + 2] = {0};
+    float frame[5] = {0, 0, 0, 0, 0};
+    int n_leaf = 8, n_crit = 64, quad = 0;
+    int built = 0, walked = 0;
+    float theta = 0.f;
+    int record_src = 0;
+    long long n_entries = 0, interactions = 0;
+    std::vector<pgh_item> host_items;
+};
+
+// Each returns PGH_OK or a status with a message in `err`.  Every step runs on
+// stream s and waits for it where a count has to come back to the host.
+int tree_build(TreeState &t, int n, const float *x, const float *y, const float *z,
+               const float *m, int n_leaf, int n_crit, int quad, int num_cu, hipStream_t s,
+               std::string &err);
+int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t s,
+              std::string &err);
+void tree_release(TreeState &t);
+hipError_t launch_unpermute(int n, const int *perm, const float *a, const float *b,
+                            const float *c, const float *d, float *oa, float *ob, float *oc,
+                            float *od, hipStream_t s);
+
 }  // namespace pgh

@@ -1,0 +1,955 @@
+// Barnes-Hut tree on gfx950 that produces the (i-group, j-list) interaction
+// lists of the tree code of Sec. 5 (Barnes' shared lists for groups of
+// i-particles; opening parameter theta; monopole moments, or quadrupole
+// moments carried by pseudo-particles after Kawai & Makino) for the batched
+// force kernels.
+//
+// Definitions (shared with the FP64 reference the tests compare against):
+//   frame   lo = componentwise minimum of the positions, extent = the largest
+//           axis range, scale = 2^21 / extent, all FP32;
+//   keys    per axis min(floor((x - lo) * scale), 2^21 - 1) (FP32 subtract and
+//           multiply, no contraction), 3-bit digits x|y|z from the top;
+//   order   sort by (key, original index) -- a stable radix sort of the keys;
+//   octree  a node of level L holds the particles sharing its first 3L key
+//           bits; it splits into its non-empty octants when it holds more than
+//           n_leaf particles and L < 21; nodes numbered breadth first, each
+//           level in key order; node size extent / 2^L;
+//   moments FP64 mass, centre of mass (plain mean when the mass is zero) and
+//           second moment about it;
+//   pseudo  monopole: (com, M); quadrupole: three particles of mass M/3 at
+//           com + a cos(2 pi k/3) e1 + b sin(2 pi k/3) e2 from the principal
+//           axes of S (a^2 = 2 (l1 - l3)/M, b^2 = 2 (l2 - l3)/M): the node's
+//           mass, zero dipole and the traceless part of S;
+//   groups  nodes holding at most n_crit particles (or leaves) whose parent
+//           holds more, in key order;
+//   walk    breadth first from the root per group; g and its ancestors are
+//           opened; another node is accepted when (l/theta)^2 < d^2, d the
+//           distance from its com to the group's bounding box, and adds its
+//           pseudo-particles; an opened leaf adds its particles.
+//
+// Host-driven: the build waits for the stream once per level (a level's node
+// count sizes the next launch), so it is not meant for graph capture.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+
+#include "pgh_internal.h"
+
+namespace pgh {
+namespace {
+
+constexpr unsigned long long kMask21 = (1ull << 21) - 1;
+
+__device__ inline unsigned ord_of(float f)
+{
+    const unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+float float_of_ord(unsigned o)
+{
+    const unsigned u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    float f;
+    std::memcpy(&f, &u, sizeof f);
+    return f;
+}
+
+__global__ void k_init_words(unsigned *w)
+{
+    const int i = threadIdx.x;
+    if (i < 8) w[i] = (i < 3) ? 0xffffffffu : 0u;  // min ords, max ords, counters
+}
+
+// Componentwise min / max of the positions into w[0..2] / w[3..5] as ordered
+// integers (atomics on the order-preserving image of the float).
+__global__ void __launch_bounds__(256) k_frame(int n, const float *__restrict__ x,
+                                               const float *__restrict__ y,
+                                               const float *__restrict__ z, unsigned *w)
+{
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const float v[3] = {x[i], y[i], z[i]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], v[a]);
+            hi[a] = fmaxf(hi[a], v[a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+        }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&w[a], ord_of(lo[a]));
+            atomicMax(&w[3 + a], ord_of(hi[a]));
+        }
+    }
+}
+
+// 21-bit integer -> bits at positions 0, 3, 6, ... (shift-and-mask spreading)
+__device__ inline unsigned long long spread3(unsigned long long v)
+{
+    v &= kMask21;
+    v = (v | (v << 32)) & 0x001F00000000FFFFull;
+    v = (v | (v << 16)) & 0x001F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ inline unsigned long long cell_of(float v, float lo, float scale)
+{
+    const float t = __fmul_rn(__fsub_rn(v, lo), scale);
+    const float f = fminf(fmaxf(floorf(t), 0.f), 2097151.f);
+    return (unsigned long long)f;
+}
+
+__global__ void __launch_bounds__(256) k_keys(int n, const float *__restrict__ x,
+                                              const float *__restrict__ y,
+                                              const float *__restrict__ z, float lox, float loy,
+                                              float loz, float scale,
+                                              unsigned long long *__restrict__ key,
+                                              int *__restrict__ iota)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long kx = cell_of(x[i], lox, scale), ky = cell_of(y[i], loy, scale),
+                             kz = cell_of(z[i], loz, scale);
+    key[i] = (spread3(kx) << 2) | (spread3(ky) << 1) | spread3(kz);
+    iota[i] = i;
+}
+
+__global__ void __launch_bounds__(256) k_gather(int n, const int *__restrict__ perm,
+                                                const float *__restrict__ x,
+                                                const float *__restrict__ y,
+                                                const float *__restrict__ z,
+                                                const float *__restrict__ m, float *xs, float *ys,
+                                                float *zs, float *ms)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const int i = perm[r];
+    xs[r] = x[i];
+    ys[r] = y[i];
+    zs[r] = z[i];
+    ms[r] = m[i];
+}
+
+__global__ void k_root(int n, int *begin, int *count, int *level, int *parent)
+{
+    begin[0] = 0;
+    count[0] = n;
+    level[0] = 0;
+    parent[0] = -1;
+}
+
+__device__ inline int digit_of(unsigned long long k, int L)
+{
+    return (int)((k >> (3 * (kTreeMaxLevel - L))) & 7ull);
+}
+
+// First r in [lo, hi) whose digit at level L is >= d (keys sorted and sharing
+// the digits above L, so the digit is non-decreasing in r).
+__device__ inline int lower_digit(const unsigned long long *key, int lo, int hi, int d, int L)
+{
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (digit_of(key[mid], L) < d)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// nc[i] = non-empty children of node off + i (0 for a leaf); nc[n_level] = 0.
+// w[6] counts the leaves.
+__global__ void __launch_bounds__(256) k_split_count(int n_level, int off, int L, int n_leaf,
+                                                     const int *__restrict__ begin,
+                                                     const int *__restrict__ count,
+                                                     const unsigned long long *__restrict__ key,
+                                                     int *__restrict__ nc, unsigned *w)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i > n_level) return;
+    if (i == n_level) {
+        nc[i] = 0;
+        return;
+    }
+    const int b = begin[off + i], c = count[off + i];
+    int k = 0;
+    if (c > n_leaf && L < kTreeMaxLevel) {
+        int prev = b;
+        for (int d = 1; d <= 8; ++d) {
+            const int p = (d == 8) ? b + c : lower_digit(key, prev, b + c, d, L + 1);
+            k += p > prev;
+            prev = p;
+        }
+    }
+    nc[i] = k;
+    if (k == 0) atomicAdd(&w[6], 1u);
+}
+
+__global__ void __launch_bounds__(256) k_split_write(int n_level, int off, int L, int n_leaf,
+                                                     int next_off,
+                                                     const unsigned long long *__restrict__ key,
+                                                     const int *__restrict__ scan, int *begin,
+                                                     int *count, int *level, int *first_child,
+                                                     int *n_child, int *parent)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_level) return;
+    const int node = off + i;
+    const int b = begin[node], c = count[node];
+    const int fc = next_off + scan[i];
+    int k = 0;
+    if (c > n_leaf && L < kTreeMaxLevel) {
+        int prev = b;
+        for (int d = 1; d <= 8; ++d) {
+            const int p = (d == 8) ? b + c : lower_digit(key, prev, b + c, d, L + 1);
+            if (p > prev) {
+                const int ch = fc + k;
+                begin[ch] = prev;
+                count[ch] = p - prev;
+                level[ch] = L + 1;
+                parent[ch] = node;
+                ++k;
+            }
+            prev = p;
+        }
+    }
+    first_child[node] = k ? fc : -1;
+    n_child[node] = k;
+}
+
+// Moments of the nodes of one level: a leaf from its particles, an internal
+// node from its children (parallel-axis theorem), all in FP64.
+__global__ void __launch_bounds__(256) k_moments(int n_level, int off,
+                                                 const int *__restrict__ begin,
+                                                 const int *__restrict__ count,
+                                                 const int *__restrict__ first_child,
+                                                 const int *__restrict__ n_child,
+                                                 const float *__restrict__ xs,
+                                                 const float *__restrict__ ys,
+                                                 const float *__restrict__ zs,
+                                                 const float *__restrict__ ms, NodeMoments *mom)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_level) return;
+    const int node = off + i;
+    const int nch = n_child[node];
+    NodeMoments r;
+    if (nch == 0) {
+        const int b = begin[node], c = count[node];
+        double M = 0, sx = 0, sy = 0, sz = 0;
+        for (int k = b; k < b + c; ++k) {
+            const double m = ms[k];
+            M += m;
+            sx += m * xs[k];
+            sy += m * ys[k];
+            sz += m * zs[k];
+        }
+        if (M != 0.0) {
+            sx /= M, sy /= M, sz /= M;
+        } else {
+            sx = sy = sz = 0.0;
+            for (int k = b; k < b + c; ++k) sx += xs[k], sy += ys[k], sz += zs[k];
+            sx /= c, sy /= c, sz /= c;
+        }
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+        for (int k = b; k < b + c; ++k) {
+            const double m = ms[k];
+            const double dx = xs[k] - sx, dy = ys[k] - sy, dz = zs[k] - sz;
+            a0 += m * dx * dx, a1 += m * dy * dy, a2 += m * dz * dz;
+            a3 += m * dx * dy, a4 += m * dx * dz, a5 += m * dy * dz;
+        }
+        r = {M, sx, sy, sz, a0, a1, a2, a3, a4, a5};
+    } else {
+        const int fc = first_child[node];
+        double M = 0, sx = 0, sy = 0, sz = 0, np = 0, px = 0, py = 0, pz = 0;
+        for (int k = fc; k < fc + nch; ++k) {
+            const NodeMoments &q = mom[k];
+            M += q.m;
+            sx += q.m * q.cx, sy += q.m * q.cy, sz += q.m * q.cz;
+            const double cnt = count[k];
+            np += cnt;
+            px += cnt * q.cx, py += cnt * q.cy, pz += cnt * q.cz;
+        }
+        if (M != 0.0)
+            sx /= M, sy /= M, sz /= M;
+        else
+            sx = px / np, sy = py / np, sz = pz / np;
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+        for (int k = fc; k < fc + nch; ++k) {
+            const NodeMoments &q = mom[k];
+            const double dx = q.cx - sx, dy = q.cy - sy, dz = q.cz - sz;
+            a0 += q.sxx + q.m * dx * dx, a1 += q.syy + q.m * dy * dy, a2 += q.szz + q.m * dz * dz;
+            a3 += q.sxy + q.m * dx * dy, a4 += q.sxz + q.m * dx * dz, a5 += q.syz + q.m * dy * dz;
+        }
+        r = {M, sx, sy, sz, a0, a1, a2, a3, a4, a5};
+    }
+    mom[node] = r;
+}
+
+// Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (the symmetric
+// Schur rotation of Golub & Van Loan, Sec. 8.5): eigenvalues in descending
+// order in w, eigenvectors as the columns of V.
+__device__ void jacobi3(const NodeMoments &q, double w[3], double V[3][3])
+{
+    double A[3][3] = {{q.sxx, q.sxy, q.sxz}, {q.sxy, q.syy, q.syz}, {q.sxz, q.syz, q.szz}};
+    double Q[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int sweep = 0; sweep < 32; ++sweep) {
+        const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (off == 0.0 || off <= 1e-40 * dia) break;
+        for (int p = 0; p < 2; ++p)
+            for (int r = p + 1; r < 3; ++r) {
+                const double apr = A[p][r];
+                if (apr == 0.0) continue;
+                const double tau = (A[r][r] - A[p][p]) / (2.0 * apr);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+                for (int k = 0; k < 3; ++k) {
+                    const double u = A[k][p], v = A[k][r];
+                    A[k][p] = c * u - s * v;
+                    A[k][r] = s * u + c * v;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double u = A[p][k], v = A[r][k];
+                    A[p][k] = c * u - s * v;
+                    A[r][k] = s * u + c * v;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double u = Q[k][p], v = Q[k][r];
+                    Q[k][p] = c * u - s * v;
+                    Q[k][r] = s * u + c * v;
+                }
+            }
+    }
+    int o[3] = {0, 1, 2};
+    if (A[o[1]][o[1]] > A[o[0]][o[0]]) { const int t = o[0]; o[0] = o[1]; o[1] = t; }
+    if (A[o[2]][o[2]] > A[o[1]][o[1]]) { const int t = o[1]; o[1] = o[2]; o[2] = t; }
+    if (A[o[1]][o[1]] > A[o[0]][o[0]]) { const int t = o[0]; o[0] = o[1]; o[1] = t; }
+    for (int c = 0; c < 3; ++c) {
+        w[c] = A[o[c]][o[c]];
+        for (int r = 0; r < 3; ++r) V[r][c] = Q[r][o[c]];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pseudo(int n_nodes, const NodeMoments *__restrict__ mom,
+                                                int quad, float4 *__restrict__ pp,
+                                                float4 *__restrict__ com)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_nodes) return;
+    const NodeMoments q = mom[t];
+    com[t] = make_float4((float)q.cx, (float)q.cy, (float)q.cz, 0.f);
+    if (!quad) {
+        pp[t] = make_float4((float)q.cx, (float)q.cy, (float)q.cz, (float)q.m);
+        return;
+    }
+    double w[3], V[3][3];
+    jacobi3(q, w, V);
+    double a2 = 0.0, b2 = 0.0;
+    if (q.m > 0.0) {
+        a2 = 2.0 * (w[0] - w[2]) / q.m;
+        b2 = 2.0 * (w[1] - w[2]) / q.m;
+    }
+    const double a = sqrt(fmax(a2, 0.0)), b = sqrt(fmax(b2, 0.0));
+    const double h = 0.86602540378443864676;  // sin(2 pi / 3)
+    const double cs[3] = {1.0, -0.5, -0.5}, sn[3] = {0.0, h, -h};
+    for (int k = 0; k < 3; ++k) {
+        const double u = a * cs[k], v = b * sn[k];
+        pp[3 * t + k] = make_float4((float)(q.cx + u * V[0][0] + v * V[0][1]),
+                                    (float)(q.cy + u * V[1][0] + v * V[1][1]),
+                                    (float)(q.cz + u * V[2][0] + v * V[2][1]), (float)(q.m / 3.0));
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fill_int(int n, int *a, int v)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_group_mark(int n_nodes, const int *__restrict__ begin,
+                                                    const int *__restrict__ count,
+                                                    const int *__restrict__ n_child,
+                                                    const int *__restrict__ parent, int n_crit,
+                                                    int *__restrict__ mark)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_nodes) return;
+    const bool small = count[t] <= n_crit || n_child[t] == 0;
+    const int p = parent[t];
+    const bool top = p < 0 || count[p] > n_crit;
+    if (small && top) mark[begin[t]] = t;
+}
+
+struct NonNegative {
+    __host__ __device__ bool operator()(const int &v) const { return v >= 0; }
+};
+
+// One wave per group: bounding box of its particles and the i-side of its item.
+__global__ void __launch_bounds__(256) k_group_info(int n_groups, const int *__restrict__ groups,
+                                                    const int *__restrict__ begin,
+                                                    const int *__restrict__ count,
+                                                    const float *__restrict__ xs,
+                                                    const float *__restrict__ ys,
+                                                    const float *__restrict__ zs, float4 *glo,
+                                                    float4 *ghi, pgh_item *items)
+{
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= n_groups) return;
+    const int t = groups[g];
+    const int b = begin[t], c = count[t];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = b + lane; k < b + c; k += 64) {
+        const float v[3] = {xs[k], ys[k], zs[k]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], v[a]);
+            hi[a] = fmaxf(hi[a], v[a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+        }
+    if (lane == 0) {
+        glo[g] = make_float4(lo[0], lo[1], lo[2], 0.f);
+        ghi[g] = make_float4(hi[0], hi[1], hi[2], 0.f);
+        items[g].i_off = b;
+        items[g].n_i = c;
+    }
+}
+
+struct WalkArgs {
+    int n_groups;
+    const int *groups;
+    const float4 *glo, *ghi;
+    const int *begin, *count, *level, *first_child, *n_child;
+    const float4 *com, *pp;
+    int npp;
+    const float *rc2;  // (l_L / theta)^2 per level, device
+    const float *xs, *ys, *zs, *ms;
+    long long *glen;        // pass 1 output: list length per group
+    const long long *goff;  // pass 2 input: list offset per group
+    float *xj, *yj, *zj, *mj;
+    int *src;               // pass 2, optional
+    unsigned *overflow;
+};
+
+__device__ inline int wave_incl_scan(int v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// LDS written by some lanes of a wave and then read by others.
+__device__ inline void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+constexpr int kWalkWaves = 2;  // waves per workgroup, each walking its own groups
+
+// Breadth-first walk of one group per wave.  The 64 lanes test 64 frontier
+// nodes at a time; wave prefix sums place each lane's contributions in the
+// list and its opened children in the next frontier (double-buffered in LDS).
+// Pass 1 (WRITE = false) only counts; pass 2 writes the entries at the
+// offsets of the scanned counts, in the same order.
+template <bool WRITE>
+__global__ void __launch_bounds__(64 * kWalkWaves) k_walk(WalkArgs a)
+{
+    __shared__ int fr[kWalkWaves][2][kWalkFrontier];
+    __shared__ float rc2[kTreeMaxLevel + 1];
+    if (threadIdx.x <= kTreeMaxLevel) rc2[threadIdx.x] = a.rc2[threadIdx.x];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n_waves = gridDim.x * kWalkWaves;
+    for (int g = blockIdx.x * kWalkWaves + w; g < a.n_groups; g += n_waves) {
+        const int gn = a.groups[g];
+        const float4 lo = a.glo[g], hi = a.ghi[g];
+        const int gb = a.begin[gn], glev = a.level[gn];
+        const long long out = WRITE ? a.goff[g] : 0;
+        long long len = 0;
+        int cur = 0, ncur = 1;
+        bool over = false;
+        if (lane == 0) fr[w][0][0] = 0;
+        wave_sync_lds();
+        while (ncur > 0) {
+            int nnext = 0;
+            for (int c0 = 0; c0 < ncur; c0 += 64) {
+                const int idx = c0 + lane;
+                int emit = 0, push = 0, t = 0, nb = 0, fc = 0;
+                bool acc = false;
+                if (idx < ncur) {
+                    t = fr[w][cur][idx];
+                    const int b = a.begin[t], c = a.count[t], L = a.level[t], nch = a.n_child[t];
+                    const bool anc = L <= glev && b <= gb && gb < b + c;
+                    if (!anc) {
+                        const float4 cm = a.com[t];
+                        const float ex = fmaxf(fmaxf(lo.x - cm.x, cm.x - hi.x), 0.f);
+                        const float ey = fmaxf(fmaxf(lo.y - cm.y, cm.y - hi.y), 0.f);
+                        const float ez = fmaxf(fmaxf(lo.z - cm.z, cm.z - hi.z), 0.f);
+                        acc = rc2[L] < ex * ex + ey * ey + ez * ez;
+                    }
+                    if (acc)
+                        emit = a.npp;
+                    else if (nch == 0)
+                        emit = c;
+                    else
+                        push = nch;
+                    nb = b;
+                    fc = a.first_child[t];
+                }
+                const int e_inc = wave_incl_scan(emit, lane);
+                const int p_inc = wave_incl_scan(push, lane);
+                const int e_tot = __shfl(e_inc, 63, 64), p_tot = __shfl(p_inc, 63, 64);
+                if (nnext + p_tot > kWalkFrontier) {
+                    over = true;
+                    break;
+                }
+                for (int k = 0; k < push; ++k) fr[w][cur ^ 1][nnext + p_inc - push + k] = fc + k;
+                if (WRITE && emit > 0) {
+                    const long long base = out + len + (e_inc - emit);
+                    if (acc) {
+                        for (int k = 0; k < emit; ++k) {
+                            const float4 q = a.pp[(long long)t * emit + k];
+                            a.xj[base + k] = q.x;
+                            a.yj[base + k] = q.y;
+                            a.zj[base + k] = q.z;
+                            a.mj[base + k] = q.w;
+                            if (a.src) a.src[base + k] = -(1 + t * emit + k);
+                        }
+                    } else {
+                        for (int k = 0; k < emit; ++k) {
+                            const int r = nb + k;
+                            a.xj[base + k] = a.xs[r];
+                            a.yj[base + k] = a.ys[r];
+                            a.zj[base + k] = a.zs[r];
+                            a.mj[base + k] = a.ms[r];
+                            if (a.src) a.src[base + k] = r;
+                        }
+                    }
+                }
+                len += e_tot;
+                nnext += p_tot;
+            }
+            if (over) break;
+            wave_sync_lds();
+            cur ^= 1;
+            ncur = nnext;
+        }
+        if (over) {
+            if (lane == 0) atomicOr(a.overflow, 1u);
+            len = 0;
+        }
+        if (!WRITE && lane == 0) a.glen[g] = len;
+        wave_sync_lds();
+    }
+}
+
+__global__ void k_tail_zero(long long *p) { *p = 0; }
+
+__global__ void __launch_bounds__(256) k_items_j(int n_groups, const long long *__restrict__ goff,
+                                                 const long long *__restrict__ glen,
+                                                 pgh_item *items)
+{
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= n_groups) return;
+    items[g].j_off = (int)goff[g];
+    items[g].n_j = (int)glen[g];
+}
+
+__global__ void __launch_bounds__(256) k_unpermute(int n, const int *__restrict__ perm,
+                                                   const float *__restrict__ a,
+                                                   const float *__restrict__ b,
+                                                   const float *__restrict__ c,
+                                                   const float *__restrict__ d, float *oa,
+                                                   float *ob, float *oc, float *od)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const int i = perm[r];
+    oa[i] = a[r];
+    ob[i] = b[r];
+    oc[i] = c[r];
+    if (od) od[i] = d[r];
+}
+
+int blocks_of(long long n, int per) { return (int)std::max(1LL, (n + per - 1) / per); }
+
+template <class T>
+bool grow(T **p, long long *cap_now, long long cap_new)
+{
+    T *q = nullptr;
+    if (hipMalloc((void **)&q, sizeof(T) * (size_t)std::max(1LL, cap_new)) != hipSuccess)
+        return false;
+    (void)hipFree(*p);
+    *p = q;
+    *cap_now = cap_new;
+    return true;
+}
+
+// Reallocates a node array keeping its first `keep` entries.
+template <class T>
+bool grow_keep(T **p, long long keep, long long cap_new, hipStream_t s)
+{
+    T *q = nullptr;
+    if (hipMalloc((void **)&q, sizeof(T) * (size_t)cap_new) != hipSuccess) return false;
+    if (keep > 0 &&
+        hipMemcpyAsync(q, *p, sizeof(T) * (size_t)keep, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return false;
+    if (hipStreamSynchronize(s) != hipSuccess) return false;
+    (void)hipFree(*p);
+    *p = q;
+    return true;
+}
+
+#define TREE_HIP(call)                                                    \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) {                                           \
+            err = std::string(#call) + ": " + hipGetErrorString(e_);      \
+            return PGH_EHIP;                                              \
+        }                                                                 \
+    } while (0)
+
+#define TREE_ALLOC(ok)                                                    \
+    do {                                                                  \
+        if (!(ok)) {                                                      \
+            err = "tree: device allocation failed";                       \
+            return PGH_ENOMEM;                                            \
+        }                                                                 \
+    } while (0)
+
+size_t temp_bytes_for(int n, int ngroups)
+{
+    size_t a = 0, b = 0, c = 0, d = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, a, (unsigned long long *)nullptr,
+                                             (unsigned long long *)nullptr, (int *)nullptr,
+                                             (int *)nullptr, n, 0, 63);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int *)nullptr, (int *)nullptr, n + 1);
+    (void)hipcub::DeviceSelect::If(nullptr, c, (int *)nullptr, (int *)nullptr, (int *)nullptr, n,
+                                   NonNegative());
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, d, (long long *)nullptr,
+                                           (long long *)nullptr, ngroups + 1);
+    return std::max(std::max(a, b), std::max(c, d));
+}
+
+int ensure_tmp(TreeState &t, int n, std::string &err)
+{
+    const size_t want = temp_bytes_for(n, n);
+    if (want <= t.tmp_bytes) return PGH_OK;
+    (void)hipFree(t.tmp);
+    t.tmp = nullptr;
+    t.tmp_bytes = 0;
+    TREE_ALLOC(hipMalloc(&t.tmp, want) == hipSuccess);
+    t.tmp_bytes = want;
+    return PGH_OK;
+}
+
+}  // namespace
+
+void tree_release(TreeState &t)
+{
+    void *ps[] = {t.key, t.key_in, t.perm, t.iota, t.xs, t.ys, t.zs, t.ms, t.mark, t.axs,
+                  t.ays, t.azs, t.phs, t.begin, t.count, t.level, t.first_child, t.n_child,
+                  t.parent, t.nc, t.mom, t.com, t.pp, t.groups, t.glo, t.ghi, t.glen, t.goff,
+                  t.items, t.xj, t.yj, t.zj, t.mj, t.src, t.tmp, t.word, t.count_out, t.rc2};
+    for (void *p : ps) (void)hipFree(p);
+    t = TreeState();
+}
+
+int tree_build(TreeState &t, int n, const float *x, const float *y, const float *z,
+               const float *m, int n_leaf, int n_crit, int quad, int num_cu, hipStream_t s,
+               std::string &err)
+{
+    t.built = t.walked = 0;
+    t.n = n;
+    t.n_leaf = n_leaf;
+    t.n_crit = n_crit;
+    t.quad = quad ? 1 : 0;
+    t.n_nodes = t.n_leaves = t.depth = t.n_groups = t.max_level_nodes = 0;
+    t.n_entries = t.interactions = 0;
+    std::fill(t.level_off, t.level_off + kTreeMaxLevel + 2, 0);
+    std::fill(t.frame, t.frame + 5, 0.f);
+    t.host_items.clear();
+    if (!t.word) {
+        TREE_ALLOC(hipMalloc((void **)&t.word, 8 * sizeof(unsigned)) == hipSuccess);
+        TREE_ALLOC(hipMalloc((void **)&t.count_out, sizeof(int)) == hipSuccess);
+        TREE_ALLOC(hipMalloc((void **)&t.rc2, (kTreeMaxLevel + 1) * sizeof(float)) == hipSuccess);
+    }
+    if (n == 0) {
+        t.built = 1;
+        return PGH_OK;
+    }
+    if (n > t.n_cap) {
+        const long long cap = std::max(n, 1024);
+        long long dummy = 0;
+        bool ok = grow(&t.key, &dummy, cap) && grow(&t.key_in, &dummy, cap) &&
+                  grow(&t.perm, &dummy, cap) && grow(&t.iota, &dummy, cap) &&
+                  grow(&t.xs, &dummy, cap) && grow(&t.ys, &dummy, cap) &&
+                  grow(&t.zs, &dummy, cap) && grow(&t.ms, &dummy, cap) &&
+                  grow(&t.mark, &dummy, cap) && grow(&t.axs, &dummy, cap) &&
+                  grow(&t.ays, &dummy, cap) && grow(&t.azs, &dummy, cap) &&
+                  grow(&t.phs, &dummy, cap);
+        if (!ok) {
+            t.n_cap = 0;
+            err = "tree: device allocation failed";
+            return PGH_ENOMEM;
+        }
+        t.n_cap = (int)cap;
+        int st = ensure_tmp(t, (int)cap, err);
+        if (st) return st;
+    }
+    // 1. frame
+    hipLaunchKernelGGL(k_init_words, dim3(1), dim3(64), 0, s, t.word);
+    hipLaunchKernelGGL(k_frame, dim3(std::min(blocks_of(n, 256), 4 * num_cu)), dim3(256), 0, s, n,
+                       x, y, z, t.word);
+    TREE_HIP(hipGetLastError());
+    unsigned wv[6];
+    TREE_HIP(hipMemcpyAsync(wv, t.word, sizeof wv, hipMemcpyDeviceToHost, s));
+    TREE_HIP(hipStreamSynchronize(s));
+    float lo[3], hi[3], ext = 0.f;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = float_of_ord(wv[a]);
+        hi[a] = float_of_ord(wv[3 + a]);
+        const float e = hi[a] - lo[a];
+        if (e > ext) ext = e;
+    }
+    if (!std::isfinite(ext)) {
+        err = "tree: positions must be finite";
+        return PGH_ERANGE;
+    }
+    const float scale = ext > 0.f ? 2097152.0f / ext : 0.f;
+    t.frame[0] = lo[0], t.frame[1] = lo[1], t.frame[2] = lo[2], t.frame[3] = ext;
+    t.frame[4] = scale;
+    // 2. keys, sort, gather
+    hipLaunchKernelGGL(k_keys, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, x, y, z, lo[0], lo[1],
+                       lo[2], scale, t.key_in, t.iota);
+    TREE_HIP(hipGetLastError());
+    size_t tb = t.tmp_bytes;
+    TREE_HIP(hipcub::DeviceRadixSort::SortPairs(t.tmp, tb, t.key_in, t.key, t.iota, t.perm, n, 0,
+                                                63, s));
+    hipLaunchKernelGGL(k_gather, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, t.perm, x, y, z, m,
+                       t.xs, t.ys, t.zs, t.ms);
+    TREE_HIP(hipGetLastError());
+    // 3. octree, level by level
+    if (t.node_cap < 1) {
+        const long long cap = std::max(1024, n / 2 + 1024);
+        long long dummy = 0;
+        TREE_ALLOC(grow(&t.begin, &dummy, cap) && grow(&t.count, &dummy, cap) &&
+                   grow(&t.level, &dummy, cap) && grow(&t.first_child, &dummy, cap) &&
+                   grow(&t.n_child, &dummy, cap) && grow(&t.parent, &dummy, cap));
+        t.node_cap = (int)cap;
+    }
+    hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, n, t.begin, t.count, t.level, t.parent);
+    TREE_HIP(hipGetLastError());
+    int off = 0, n_level = 1, L = 0;
+    t.level_off[0] = 0;
+    for (;;) {
+        t.max_level_nodes = std::max(t.max_level_nodes, n_level);
+        if (2 * (n_level + 1) > t.nc_cap) {
+            long long cap = 2LL * std::max(n_level + 1, 1024), dummy = 0;
+            TREE_ALLOC(grow(&t.nc, &dummy, cap));
+            t.nc_cap = (int)cap;
+        }
+        int *cnt = t.nc, *scan = t.nc + (n_level + 1);
+        hipLaunchKernelGGL(k_split_count, dim3(blocks_of(n_level + 1, 256)), dim3(256), 0, s,
+                           n_level, off, L, n_leaf, t.begin, t.count, t.key, cnt, t.word);
+        TREE_HIP(hipGetLastError());
+        tb = t.tmp_bytes;
+        TREE_HIP(hipcub::DeviceScan::ExclusiveSum(t.tmp, tb, cnt, scan, n_level + 1, s));
+        int total = 0;
+        TREE_HIP(hipMemcpyAsync(&total, scan + n_level, sizeof(int), hipMemcpyDeviceToHost, s));
+        TREE_HIP(hipStreamSynchronize(s));
+        const int next_off = off + n_level;
+        if ((long long)next_off + total > t.node_cap) {
+            const long long cap = std::max<long long>((long long)t.node_cap * 3 / 2,
+                                                      (long long)next_off + total + 1024);
+            if (cap > INT_MAX) {
+                err = "tree: too many nodes";
+                return PGH_ERANGE;
+            }
+            TREE_ALLOC(grow_keep(&t.begin, next_off, cap, s) &&
+                       grow_keep(&t.count, next_off, cap, s) &&
+                       grow_keep(&t.level, next_off, cap, s) &&
+                       grow_keep(&t.first_child, next_off, cap, s) &&
+                       grow_keep(&t.n_child, next_off, cap, s) &&
+                       grow_keep(&t.parent, next_off, cap, s));
+            t.node_cap = (int)cap;
+        }
+        hipLaunchKernelGGL(k_split_write, dim3(blocks_of(n_level, 256)), dim3(256), 0, s, n_level,
+                           off, L, n_leaf, next_off, t.key, scan, t.begin, t.count, t.level,
+                           t.first_child, t.n_child, t.parent);
+        TREE_HIP(hipGetLastError());
+        t.level_off[L + 1] = next_off;  // level L is [level_off[L], level_off[L + 1])
+        if (total == 0) break;
+        off = next_off;
+        n_level = total;
+        ++L;
+    }
+    t.depth = L;
+    t.n_nodes = t.level_off[L + 1];
+    // 4. moments bottom-up, then pseudo-particles
+    if (t.n_nodes > t.pp_cap) {  // mom, com: pp_cap entries; pp: 3 pp_cap
+        const long long cap = (long long)t.n_nodes * 3 / 2 + 1024;
+        long long dummy = 0;
+        TREE_ALLOC(grow(&t.mom, &dummy, cap) && grow(&t.com, &dummy, cap) &&
+                   grow(&t.pp, &dummy, 3 * cap));
+        t.pp_cap = (int)cap;
+    }
+    for (int l = t.depth; l >= 0; --l) {
+        const int o = t.level_off[l], k = t.level_off[l + 1] - o;
+        hipLaunchKernelGGL(k_moments, dim3(blocks_of(k, 256)), dim3(256), 0, s, k, o, t.begin,
+                           t.count, t.first_child, t.n_child, t.xs, t.ys, t.zs, t.ms, t.mom);
+    }
+    hipLaunchKernelGGL(k_pseudo, dim3(blocks_of(t.n_nodes, 256)), dim3(256), 0, s, t.n_nodes,
+                       t.mom, t.quad, t.pp, t.com);
+    TREE_HIP(hipGetLastError());
+    // 5. groups in key order
+    hipLaunchKernelGGL(k_fill_int, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, t.mark, -1);
+    hipLaunchKernelGGL(k_group_mark, dim3(blocks_of(t.n_nodes, 256)), dim3(256), 0, s, t.n_nodes,
+                       t.begin, t.count, t.n_child, t.parent, n_crit, t.mark);
+    TREE_HIP(hipGetLastError());
+    if (n > t.group_cap) {
+        const long long cap = std::max(n, 1024);
+        long long dummy = 0;
+        TREE_ALLOC(grow(&t.groups, &dummy, cap) && grow(&t.glo, &dummy, cap) &&
+                   grow(&t.ghi, &dummy, cap) && grow(&t.glen, &dummy, cap + 1) &&
+                   grow(&t.goff, &dummy, cap + 1) && grow(&t.items, &dummy, cap));
+        t.group_cap = (int)cap;
+    }
+    tb = t.tmp_bytes;
+    TREE_HIP(hipcub::DeviceSelect::If(t.tmp, tb, t.mark, t.groups, t.count_out, n, NonNegative(),
+                                      s));
+    unsigned leaves = 0;
+    TREE_HIP(hipMemcpyAsync(&t.n_groups, t.count_out, sizeof(int), hipMemcpyDeviceToHost, s));
+    TREE_HIP(hipMemcpyAsync(&leaves, t.word + 6, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    TREE_HIP(hipStreamSynchronize(s));
+    t.n_leaves = (int)leaves;
+    hipLaunchKernelGGL(k_group_info, dim3(blocks_of(t.n_groups, 4)), dim3(256), 0, s, t.n_groups,
+                       t.groups, t.begin, t.count, t.xs, t.ys, t.zs, t.glo, t.ghi, t.items);
+    TREE_HIP(hipGetLastError());
+    t.built = 1;
+    return PGH_OK;
+}
+
+int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t s,
+              std::string &err)
+{
+    t.walked = 0;
+    t.theta = theta;
+    t.record_src = record_src ? 1 : 0;
+    t.n_entries = t.interactions = 0;
+    t.host_items.clear();
+    if (t.n_groups == 0) {
+        t.walked = 1;
+        return PGH_OK;
+    }
+    // (l_L / theta)^2 per level, rounded once from double
+    float rc2[kTreeMaxLevel + 1];
+    for (int L = 0; L <= kTreeMaxLevel; ++L) {
+        const double l = std::ldexp((double)t.frame[3], -L);
+        rc2[L] = theta > 0.f ? (float)((l / theta) * (l / theta)) : INFINITY;
+    }
+    TREE_HIP(hipMemcpyAsync(t.rc2, rc2, sizeof rc2, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_init_words, dim3(1), dim3(64), 0, s, t.word);
+    WalkArgs a{};
+    a.n_groups = t.n_groups;
+    a.groups = t.groups;
+    a.glo = t.glo;
+    a.ghi = t.ghi;
+    a.begin = t.begin;
+    a.count = t.count;
+    a.level = t.level;
+    a.first_child = t.first_child;
+    a.n_child = t.n_child;
+    a.com = t.com;
+    a.pp = t.pp;
+    a.npp = t.quad ? 3 : 1;
+    a.rc2 = t.rc2;
+    a.xs = t.xs, a.ys = t.ys, a.zs = t.zs, a.ms = t.ms;
+    a.glen = t.glen;
+    a.goff = t.goff;
+    a.overflow = t.word + 7;
+    const int grid = std::min(blocks_of(t.n_groups, kWalkWaves), 2 * num_cu);
+    hipLaunchKernelGGL(k_walk<false>, dim3(grid), dim3(64 * kWalkWaves), 0, s, a);
+    hipLaunchKernelGGL(k_tail_zero, dim3(1), dim3(1), 0, s, t.glen + t.n_groups);
+    TREE_HIP(hipGetLastError());
+    size_t tb = t.tmp_bytes;
+    TREE_HIP(hipcub::DeviceScan::ExclusiveSum(t.tmp, tb, t.glen, t.goff, t.n_groups + 1, s));
+    long long total = 0;
+    unsigned over = 0;
+    TREE_HIP(hipMemcpyAsync(&total, t.goff + t.n_groups, sizeof total, hipMemcpyDeviceToHost, s));
+    TREE_HIP(hipMemcpyAsync(&over, t.word + 7, sizeof over, hipMemcpyDeviceToHost, s));
+    TREE_HIP(hipStreamSynchronize(s));
+    if (over) {
+        err = "tree walk: a frontier exceeded " + std::to_string(kWalkFrontier) +
+              " nodes (theta too small for this tree)";
+        return PGH_ERANGE;
+    }
+    if (total > INT_MAX) {
+        err = "tree walk: the lists exceed 2^31 - 1 entries";
+        return PGH_ERANGE;
+    }
+    if (total > t.entry_cap) {
+        const long long cap = total + total / 4 + 1024;
+        long long c1 = 0;
+        TREE_ALLOC(grow(&t.xj, &c1, cap) && grow(&t.yj, &c1, cap) &&
+                   grow(&t.zj, &c1, cap) && grow(&t.mj, &c1, cap));
+        t.entry_cap = cap;
+    }
+    if (record_src && total > t.src_cap) {
+        const long long cap = total + total / 4 + 1024;
+        TREE_ALLOC(grow(&t.src, &t.src_cap, cap));
+    }
+    a.xj = t.xj, a.yj = t.yj, a.zj = t.zj, a.mj = t.mj;
+    a.src = record_src ? t.src : nullptr;
+    hipLaunchKernelGGL(k_walk<true>, dim3(grid), dim3(64 * kWalkWaves), 0, s, a);
+    hipLaunchKernelGGL(k_items_j, dim3(blocks_of(t.n_groups, 256)), dim3(256), 0, s, t.n_groups,
+                       t.goff, t.glen, t.items);
+    TREE_HIP(hipGetLastError());
+    t.host_items.resize(t.n_groups);
+    TREE_HIP(hipMemcpyAsync(t.host_items.data(), t.items, sizeof(pgh_item) * t.n_groups,
+                            hipMemcpyDeviceToHost, s));
+    TREE_HIP(hipStreamSynchronize(s));
+    long long inter = 0;
+    for (const pgh_item &it : t.host_items) inter += (long long)it.n_i * it.n_j;
+    t.n_entries = total;
+    t.interactions = inter;
+    t.walked = 1;
+    return PGH_OK;
+}
+
+hipError_t launch_unpermute(int n, const int *perm, const float *a, const float *b,
+                            const float *c, const float *d, float *oa, float *ob, float *oc,
+                            float *od, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpermute, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, perm, a, b, c, d,
+                       oa, ob, oc, od);
+    return hipGetLastError();
+}
+
+}  // namespace pgh
