@@ -556,6 +556,64 @@ def table_allpairs(torch, pgh, synth):
             "ms_per_variant": per, "kernel_ms_with_potential_last_variant": tp.mean_ms()}
 
 
+def tree_code(torch, pgh, synth, sizes=(1 << 20, 1 << 22), n_crit=64):
+    """The tree code of Sec. 5 (Fig. 10): forces and potentials of every
+    particle of a Plummer sphere with the device Barnes-Hut tree, theta =
+    0.75, leaves of at most 8 particles, i-groups of at most n_crit, eps = 1/512,
+    monopole and quadrupole pseudo-particles.  Wall-clock per phase, each
+    call synchronous except the force (timed with events, then waited for):
+    build (keys, sort, octree, moments, groups), walk (both passes and the
+    batched plan of the lists), force (batched Newton + scatter to input
+    order).  Median of 3 after one warm-up."""
+    res = {}
+    ctx = pgh.Context(0)
+    ctx.set_eps_to_all(1.0 / 512)
+    for n in sizes:
+        x, y, z = synth.plummer(n, 330)
+        m = synth.equal_masses(n)
+        d = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+        t = ctx.tree()
+        per_n = {}
+        for quad in (False, True):
+            t.build(*d, n_leaf=8, n_crit=n_crit, quad=quad)
+            t.walk(0.75)
+            out = t.newton()
+            torch.cuda.synchronize()
+            tb, tw, tf, tt = [], [], [], []
+            timer = KernelTimer(torch)
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                t.build(*d, n_leaf=8, n_crit=n_crit, quad=quad)
+                t1 = time.perf_counter()
+                t.walk(0.75)
+                t2 = time.perf_counter()
+                with timer:
+                    t.newton(out=out)
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                tb.append(t1 - t0)
+                tw.append(t2 - t1)
+                tt.append(t3 - t0)
+            tf = timer.times_ms()
+            st = t.stats()
+            inter = float(st["interactions"])
+            f_ms = float(np.median(tf))
+            rate = inter / (f_ms / 1e3)
+            per_n["quadrupole" if quad else "monopole"] = {
+                "build_ms": 1e3 * float(np.median(tb)), "walk_and_plan_ms": 1e3 * float(np.median(tw)),
+                "force_ms": f_ms, "total_ms": 1e3 * float(np.median(tt)),
+                "n_nodes": st["n_nodes"], "n_groups": st["n_groups"], "depth": st["depth"],
+                "list_entries": st["n_entries"], "mean_list_length": st["n_entries"] / max(1, st["n_groups"]),
+                "interactions": inter, "force_interactions_per_s": rate,
+                "force_frac_of_peak_38flop": NEWTON_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12)}
+        t.free()
+        res[f"plummer_N{n}"] = per_n
+        del d
+    ctx.close()
+    return {"workload": f"tree_code_plummer_theta0.75_nleaf8_ncrit{n_crit}_eps1/512", **res}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -616,7 +674,8 @@ def main():
               "adjoint_newton": adjoint_newton(torch, pgh, synth),
               "adjoint_table": adjoint_table(torch, pgh, synth),
               "ni_nj_sweep": ni_nj_sweep(torch, pgh, synth),
-              "grape5_host": grape5_host(torch, pgh, synth)}
+              "grape5_host": grape5_host(torch, pgh, synth),
+              "tree_code": tree_code(torch, pgh, synth)}
         ex["batched_over_allpairs"] = ex["newton_batched"]["interactions_per_s"] / value
         line["extras"] = ex
     if not args.no_cpu:

@@ -281,7 +281,9 @@ PGH_API int pgh_newton_ij_bwd(pgh_ctx *c, int ni, const float *xi, const float *
  * several lists accumulates.  g{x,y,z}i: device float[ni_total] (or NULL),
  * overwritten; rows in no list get 0.  Position gradients come in triples
  * (PGH_EINVAL otherwise).  The sums use float atomics, so their order (and
- * last bits) may vary from call to call.  Allocates nothing. */
+ * last bits) may vary from call to call.  The first call on a plan builds
+ * the plan's adjoint task lists (allocates, uploads and waits for the
+ * stream); later calls allocate nothing and may be captured in a graph. */
 PGH_API int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
                                 const float *zi, const float *xj, const float *yj,
                                 const float *zj, const float *mj, const float *wx,

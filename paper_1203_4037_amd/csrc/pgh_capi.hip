@@ -25,6 +25,10 @@ struct pgh_plan {
     unsigned *queue;        // device, one counter per sublist, zero between launches
     float4 *partial;        // device, 64 partial sums per slot
     SplitChunk *chunks;     // device, the split chunks
+    // Task lists of the table adjoint, built by its first call on the plan
+    // (a forward-only plan never pays for them).
+    bool adj_built;
+    std::vector<pgh_item> ordered;  // the items with n_i > 0, by i_off
     int n_jtasks;           // j-major tasks of the table adjoint
     Task *jtasks;           // device
     int n_itasks;           // i-major tasks of the table adjoint (i-side positions)
@@ -696,40 +700,10 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     p->jtasks = nullptr;
     p->jqueue = nullptr;
     p->itasks = nullptr;
-    // i-major tasks of the table adjoint (the i-side position gradient, its
-    // own list independent of the forward's chunking): i-chunks of <= 64
-    // against j-ranges of <= 512, added with atomics, so no partial sums
-    std::vector<Task> it_tasks;
-    for (int t : order) {
-        const pgh_item &it = items[t];
-        for (int s0 = 0; s0 < it.n_i; s0 += 64)
-            for (int q0 = 0; q0 < it.n_j; q0 += 512)
-                it_tasks.push_back({it.i_off + s0, std::min(64, it.n_i - s0), it.j_off + q0,
-                                    std::min(512, it.n_j - q0), 0, 1, 0, 0, 0, 0, 0, 0});
-    }
-    std::stable_sort(it_tasks.begin(), it_tasks.end(), [](const Task &a, const Task &b) {
-        return (long long)a.n_j * ((a.n_i + 15) / 16) > (long long)b.n_j * ((b.n_i + 15) / 16);
-    });
-    p->n_itasks = (int)it_tasks.size();
-    // j-major tasks of the table adjoint: chunks of <= 64 j-entries of a
-    // list against its i-group (chunks of 32 or 16, 2 or 4 lanes per entry,
-    // when chunks of 64 would fill less than half of the resident waves)
-    int jc = 64;
-    for (;;) {
-        long long n = 0;
-        for (int t : order) n += (items[t].n_j + jc - 1) / jc;
-        if (2 * n >= waves || jc == 16) break;
-        jc /= 2;
-    }
-    std::vector<Task> jt;
-    for (int t : order) {
-        const pgh_item &it = items[t];
-        for (int s0 = 0; s0 < it.n_j; s0 += jc)
-            jt.push_back({it.j_off + s0, std::min(jc, it.n_j - s0), it.i_off, it.n_i, 0, 1, 0, 0, 0,
-                          0, 0, 0});
-    }
-    std::stable_sort(jt.begin(), jt.end(), [](const Task &a, const Task &b) { return a.n_j > b.n_j; });
-    p->n_jtasks = (int)jt.size();
+    p->adj_built = false;
+    p->n_jtasks = p->n_itasks = 0;
+    p->ordered.reserve(order.size());
+    for (int t : order) p->ordered.push_back(items[t]);
     DeviceGuard g(c->device);
     auto cleanup = [&](int code, const char *msg) {
         free_plan_memory(p);
@@ -748,22 +722,6 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     if (n_chunks > 0 &&
         hipMalloc((void **)&p->chunks, (size_t)n_chunks * sizeof(SplitChunk)) != hipSuccess)
         return cleanup(PGH_ENOMEM, "hipMalloc(split chunks) failed");
-    if (hipMalloc((void **)&p->jqueue, 2 * sizeof(unsigned)) != hipSuccess)
-        return cleanup(PGH_ENOMEM, "hipMalloc(queue) failed");
-    if (!jt.empty() && hipMalloc((void **)&p->jtasks, jt.size() * sizeof(Task)) != hipSuccess)
-        return cleanup(PGH_ENOMEM, "hipMalloc(tasks) failed");
-    if (!it_tasks.empty() &&
-        hipMalloc((void **)&p->itasks, it_tasks.size() * sizeof(Task)) != hipSuccess)
-        return cleanup(PGH_ENOMEM, "hipMalloc(tasks) failed");
-    if (!it_tasks.empty() &&
-        hipMemcpyAsync(p->itasks, it_tasks.data(), it_tasks.size() * sizeof(Task),
-                       hipMemcpyHostToDevice, c->stream) != hipSuccess)
-        return cleanup(PGH_EHIP, "uploading the plan failed");
-
-    if (hipMemsetAsync(p->jqueue, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
-        (!jt.empty() && hipMemcpyAsync(p->jtasks, jt.data(), jt.size() * sizeof(Task),
-                                       hipMemcpyHostToDevice, c->stream) != hipSuccess))
-        return cleanup(PGH_EHIP, "uploading the plan failed");
     if (hipMemsetAsync(p->queue, 0, queue_bytes, c->stream) != hipSuccess ||
         (n_chunks > 0 &&
          hipMemcpyAsync(p->chunks, split.data(), split.size() * sizeof(SplitChunk),
@@ -800,6 +758,68 @@ int check_plan(pgh_ctx *c, const pgh_plan *p)
 {
     if (!p) return fail(c, PGH_EINVAL, "NULL plan");
     if (p->owner != c) return fail(c, PGH_EINVAL, "plan belongs to another context");
+    return PGH_OK;
+}
+
+// Builds the table adjoint's task lists of a plan (once; allocates and
+// waits for the stream).
+int build_adjoint_tasks(pgh_ctx *c, pgh_plan *p)
+{
+    if (p->adj_built) return PGH_OK;
+    const std::vector<pgh_item> &ord = p->ordered;
+    const int waves = std::max(1, batch_resident_waves(c->num_cu));
+    // i-major tasks of the table adjoint (the i-side position gradient, its
+    // own list independent of the forward's chunking): i-chunks of <= 64
+    // against j-ranges of <= 512, added with atomics, so no partial sums
+    std::vector<Task> it_tasks;
+    for (const pgh_item &it : ord) {
+        for (int s0 = 0; s0 < it.n_i; s0 += 64)
+            for (int q0 = 0; q0 < it.n_j; q0 += 512)
+                it_tasks.push_back({it.i_off + s0, std::min(64, it.n_i - s0), it.j_off + q0,
+                                    std::min(512, it.n_j - q0), 0, 1, 0, 0, 0, 0, 0, 0});
+    }
+    std::stable_sort(it_tasks.begin(), it_tasks.end(), [](const Task &a, const Task &b) {
+        return (long long)a.n_j * ((a.n_i + 15) / 16) > (long long)b.n_j * ((b.n_i + 15) / 16);
+    });
+    // j-major tasks of the table adjoint: chunks of <= 64 j-entries of a
+    // list against its i-group (chunks of 32 or 16, 2 or 4 lanes per entry,
+    // when chunks of 64 would fill less than half of the resident waves)
+    int jc = 64;
+    for (;;) {
+        long long n = 0;
+        for (const pgh_item &it : ord) n += (it.n_j + jc - 1) / jc;
+        if (2 * n >= waves || jc == 16) break;
+        jc /= 2;
+    }
+    std::vector<Task> jt;
+    for (const pgh_item &it : ord) {
+        for (int s0 = 0; s0 < it.n_j; s0 += jc)
+            jt.push_back({it.j_off + s0, std::min(jc, it.n_j - s0), it.i_off, it.n_i, 0, 1, 0, 0, 0,
+                          0, 0, 0});
+    }
+    std::stable_sort(jt.begin(), jt.end(), [](const Task &a, const Task &b) { return a.n_j > b.n_j; });
+    if (hipMalloc((void **)&p->jqueue, 2 * sizeof(unsigned)) != hipSuccess ||
+        (!jt.empty() && hipMalloc((void **)&p->jtasks, jt.size() * sizeof(Task)) != hipSuccess) ||
+        (!it_tasks.empty() &&
+         hipMalloc((void **)&p->itasks, it_tasks.size() * sizeof(Task)) != hipSuccess)) {
+        (void)hipFree(p->jqueue);
+        (void)hipFree(p->jtasks);
+        (void)hipFree(p->itasks);
+        p->jqueue = nullptr;
+        p->jtasks = p->itasks = nullptr;
+        return fail(c, PGH_ENOMEM, "hipMalloc(adjoint tasks) failed");
+    }
+    if (hipMemsetAsync(p->jqueue, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
+        (!jt.empty() && hipMemcpyAsync(p->jtasks, jt.data(), jt.size() * sizeof(Task),
+                                       hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+        (!it_tasks.empty() &&
+         hipMemcpyAsync(p->itasks, it_tasks.data(), it_tasks.size() * sizeof(Task),
+                        hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, PGH_EHIP, "uploading the adjoint tasks failed");
+    p->n_jtasks = (int)jt.size();
+    p->n_itasks = (int)it_tasks.size();
+    p->adj_built = true;
     return PGH_OK;
 }
 
@@ -962,6 +982,8 @@ int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const fl
     if (p->nj_total > 0 && (!xj || !yj || !zj || !mj))
         return fail(c, PGH_EINVAL, "NULL j-particle array");
     DeviceGuard g(c->device);
+    st = build_adjoint_tasks(c, const_cast<pgh_plan *>(p));
+    if (st) return st;
     TableBwdArgs A{};
     A.b = batch_args(c, p);
     A.b.xi = xi, A.b.yi = yi, A.b.zi = zi;

@@ -84,12 +84,21 @@ __global__ void __launch_bounds__(256) k_frame(int n, const float *__restrict__ 
             lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
             hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
         }
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(&w[a], ord_of(lo[a]));
-            atomicMax(&w[3 + a], ord_of(hi[a]));
-        }
+    // the workgroup's four waves, then one atomic per workgroup and value
+    // (one per wave would queue thousands on the same six words)
+    __shared__ float part[4][6];
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) part[wv][a] = lo[a], part[wv][3 + a] = hi[a];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        float v = part[0][a];
+        for (int k = 1; k < 4; ++k) v = a < 3 ? fminf(v, part[k][a]) : fmaxf(v, part[k][a]);
+        if (a < 3)
+            atomicMin(&w[a], ord_of(v));
+        else
+            atomicMax(&w[a], ord_of(v));
     }
 }
 
@@ -724,7 +733,7 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
     }
     // 1. frame
     hipLaunchKernelGGL(k_init_words, dim3(1), dim3(64), 0, s, t.word);
-    hipLaunchKernelGGL(k_frame, dim3(std::min(blocks_of(n, 256), 4 * num_cu)), dim3(256), 0, s, n,
+    hipLaunchKernelGGL(k_frame, dim3(std::min(blocks_of(n, 256), num_cu)), dim3(256), 0, s, n,
                        x, y, z, t.word);
     TREE_HIP(hipGetLastError());
     unsigned wv[6];
