@@ -604,6 +604,7 @@ def tree_code(torch, pgh, synth, sizes=(1 << 20, 1 << 22), n_crit=64):
                 "build_ms": 1e3 * float(np.median(tb)), "walk_and_plan_ms": 1e3 * float(np.median(tw)),
                 "force_ms": f_ms, "total_ms": 1e3 * float(np.median(tt)),
                 "n_nodes": st["n_nodes"], "n_groups": st["n_groups"], "depth": st["depth"],
+                "max_frontier": st["max_frontier"],
                 "list_entries": st["n_entries"], "mean_list_length": st["n_entries"] / max(1, st["n_groups"]),
                 "interactions": inter, "force_interactions_per_s": rate,
                 "force_frac_of_peak_38flop": NEWTON_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12)}
@@ -675,7 +676,7 @@ def main():
               "adjoint_table": adjoint_table(torch, pgh, synth),
               "ni_nj_sweep": ni_nj_sweep(torch, pgh, synth),
               "grape5_host": grape5_host(torch, pgh, synth),
-              "tree_code": tree_code(torch, pgh, synth)}
+              "tree_code": tree_code(torch, pgh, synth, n_crit=256)}
         ex["batched_over_allpairs"] = ex["newton_batched"]["interactions_per_s"] / value
         line["extras"] = ex
     if not args.no_cpu:

@@ -420,6 +420,7 @@ PGH_API int pgh_tree_newton(pgh_ctx *c, pgh_tree *t, float *ax, float *ay, float
 
 typedef struct pgh_tree_stats {
     int n, n_nodes, n_leaves, depth, n_groups, max_level_nodes;
+    int max_frontier;        /* most nodes one group tested on one level */
     int n_leaf, n_crit, quad, walked;
     float theta;
     float frame[5];          /* lo x, y, z, extent, key scale (2^21 / extent) */

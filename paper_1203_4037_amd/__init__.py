@@ -44,7 +44,8 @@ class PGHError(RuntimeError):
 class PghTreeStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("n_nodes", ctypes.c_int), ("n_leaves", ctypes.c_int),
                 ("depth", ctypes.c_int), ("n_groups", ctypes.c_int),
-                ("max_level_nodes", ctypes.c_int), ("n_leaf", ctypes.c_int),
+                ("max_level_nodes", ctypes.c_int), ("max_frontier", ctypes.c_int),
+                ("n_leaf", ctypes.c_int),
                 ("n_crit", ctypes.c_int), ("quad", ctypes.c_int), ("walked", ctypes.c_int),
                 ("theta", ctypes.c_float), ("frame", ctypes.c_float * 5),
                 ("n_entries", ctypes.c_longlong), ("interactions", ctypes.c_longlong)]

@@ -173,6 +173,42 @@ int zero_outputs(pgh_ctx *c, int n, float *a, float *b, float *d, float *e)
     return PGH_OK;
 }
 
+// Orders idx stably by key(idx) (descending if asked): a counting sort when
+// the keys are small non-negative integers (list lengths, wave-iterations),
+// else a comparison sort.
+template <class Key>
+void stable_order(std::vector<int> &idx, Key key, bool descending)
+{
+    long long kmax = 0;
+    bool small = true;
+    for (int k : idx) {
+        const long long v = key(k);
+        if (v < 0 || v > (1LL << 22)) {
+            small = false;
+            break;
+        }
+        kmax = std::max(kmax, v);
+    }
+    if (!small) {
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+            return descending ? key(a) > key(b) : key(a) < key(b);
+        });
+        return;
+    }
+    std::vector<int> start((size_t)kmax + 2, 0);
+    for (int k : idx) {
+        const long long v = key(k);
+        ++start[(size_t)(descending ? kmax - v : v) + 1];
+    }
+    for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
+    std::vector<int> out(idx.size());
+    for (int k : idx) {
+        const long long v = key(k);
+        out[(size_t)start[(size_t)(descending ? kmax - v : v)]++] = k;
+    }
+    idx.swap(out);
+}
+
 }  // namespace
 
 extern "C" {
@@ -607,18 +643,29 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
         std::vector<int> cand;
         for (size_t k = 0; k < chunks.size(); ++k)
             if (chunks[k].n_i < 64 && chunks[k].n_j > 0) cand.push_back((int)k);
-        std::stable_sort(cand.begin(), cand.end(),
-                         [&](int a, int b) { return chunks[a].n_j < chunks[b].n_j; });
+        stable_order(cand, [&](int k) { return (long long)chunks[k].n_j; }, false);
+        // the scan reads candidates in this order: keep their fields contiguous
+        const size_t nc = cand.size();
+        std::vector<int> c_ni(nc), c_nj(nc);
+        std::vector<long long> c_it(nc);
+        std::vector<char> c_taken(nc, 0);
+        for (size_t u = 0; u < nc; ++u) {
+            const Chunk &ch = chunks[cand[u]];
+            c_ni[u] = ch.n_i;
+            c_nj[u] = ch.n_j;
+            c_it[u] = lane_iters(ch);
+        }
         constexpr size_t kWindow = 64;
-        for (size_t u = 0; u < cand.size(); ++u) {
-            const Chunk &a = chunks[cand[u]];
-            if (taken[cand[u]]) continue;
-            for (size_t v = u + 1; v < std::min(cand.size(), u + 1 + kWindow); ++v) {
-                const Chunk &b = chunks[cand[v]];
-                if (taken[cand[v]] || a.n_i + b.n_i > 64) continue;
-                if (64LL * std::max(a.n_j, b.n_j) >= lane_iters(a) + lane_iters(b)) continue;
+        for (size_t u = 0; u < nc; ++u) {
+            if (c_taken[u]) continue;
+            const int room = 64 - c_ni[u];
+            const size_t v_end = std::min(nc, u + 1 + kWindow);
+            for (size_t v = u + 1; v < v_end; ++v) {
+                if (c_taken[v] || c_ni[v] > room) continue;
+                if (64LL * std::max(c_nj[u], c_nj[v]) >= c_it[u] + c_it[v]) continue;
+                c_taken[u] = c_taken[v] = 1;
                 taken[cand[u]] = taken[cand[v]] = 1;
-                work.push_back({a, b});
+                work.push_back({chunks[cand[u]], chunks[cand[v]]});
                 break;
             }
         }
@@ -662,7 +709,7 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     // longest tasks first
     std::vector<int> idx(tasks.size());
     for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    stable_order(idx, [&](int k) { return cost[k]; }, true);
     // Deal the longest-first list into nq sublists, a group of kBatchWaves
     // consecutive tasks at a time, round-robin: each sublist stays longest
     // first with an equal share of every size class, and workgroup b (which
@@ -1274,6 +1321,7 @@ int pgh_tree_stats_get(const pgh_tree *t, pgh_tree_stats *out)
     out->depth = s.depth;
     out->n_groups = s.n_groups;
     out->max_level_nodes = s.max_level_nodes;
+    out->max_frontier = s.walked ? s.max_frontier : 0;
     out->n_leaf = s.n_leaf;
     out->n_crit = s.n_crit;
     out->quad = s.quad;

@@ -196,6 +196,7 @@ struct TreeState {
     unsigned long long *key = nullptr, *key_in = nullptr;
     int *perm = nullptr, *iota = nullptr;
     float *xs = nullptr, *ys = nullptr, *zs = nullptr, *ms = nullptr;
+    float4 *xm = nullptr;  // the same particles packed (x, y, z, m)
     int *mark = nullptr;  // group id at the first particle of each group, else -1
     // sorted-order outputs of the force (scattered back through perm)
     float *axs = nullptr, *ays = nullptr, *azs = nullptr, *phs = nullptr;
@@ -207,6 +208,7 @@ struct TreeState {
     int nc_cap = 0;
     NodeMoments *mom = nullptr;
     float4 *com = nullptr;    // FP32 centre of mass per node (w unused)
+    int4 *nrec = nullptr;     // walk record per node: begin, count, first child, n_child | level << 16
     float4 *pp = nullptr;     // pseudo-particles (x, y, z, m), npp per node
     int pp_cap = 0;
     // groups, capacity group_cap
@@ -223,11 +225,12 @@ struct TreeState {
     // scratch of the library scans and sorts
     void *tmp = nullptr;
     size_t tmp_bytes = 0;
-    unsigned *word = nullptr;  // 8 words: min/max frame, leaf count, walk overflow
+    unsigned *word = nullptr;  // 16 words: min/max frame, leaf count, walk overflow, frontier
     int *count_out = nullptr;
     float *rc2 = nullptr;      // (l_L / theta)^2 per level for the walk
     // results of the last build / walk
     int n = 0, n_nodes = 0, n_leaves = 0, depth = 0, n_groups = 0, max_level_nodes = 0;
+    int max_frontier = 0;  // largest walk frontier of the last walk
     int level_off[kTreeMaxLevel + 2] = {0};
     float frame[5] = {0, 0, 0, 0, 0};
     int n_leaf = 8, n_crit = 64, quad = 0;

@@ -60,7 +60,7 @@ float float_of_ord(unsigned o)
 __global__ void k_init_words(unsigned *w)
 {
     const int i = threadIdx.x;
-    if (i < 8) w[i] = (i < 3) ? 0xffffffffu : 0u;  // min ords, max ords, counters
+    if (i < 16) w[i] = (i < 3) ? 0xffffffffu : 0u;  // min ords, max ords, counters
 }
 
 // Componentwise min / max of the positions into w[0..2] / w[3..5] as ordered
@@ -141,15 +141,17 @@ __global__ void __launch_bounds__(256) k_gather(int n, const int *__restrict__ p
                                                 const float *__restrict__ y,
                                                 const float *__restrict__ z,
                                                 const float *__restrict__ m, float *xs, float *ys,
-                                                float *zs, float *ms)
+                                                float *zs, float *ms, float4 *xm)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= n) return;
     const int i = perm[r];
-    xs[r] = x[i];
-    ys[r] = y[i];
-    zs[r] = z[i];
-    ms[r] = m[i];
+    const float4 v = make_float4(x[i], y[i], z[i], m[i]);
+    xs[r] = v.x;
+    ys[r] = v.y;
+    zs[r] = v.z;
+    ms[r] = v.w;
+    xm[r] = v;
 }
 
 __global__ void k_root(int n, int *begin, int *count, int *level, int *parent)
@@ -383,6 +385,19 @@ __global__ void __launch_bounds__(256) k_pseudo(int n_nodes, const NodeMoments *
     }
 }
 
+// Walk record of a node: (begin, count, first child, n_child | level << 16).
+__global__ void __launch_bounds__(256) k_pack_nodes(int n_nodes, const int *__restrict__ begin,
+                                                    const int *__restrict__ count,
+                                                    const int *__restrict__ first_child,
+                                                    const int *__restrict__ n_child,
+                                                    const int *__restrict__ level,
+                                                    int4 *__restrict__ rec)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_nodes) return;
+    rec[t] = make_int4(begin[t], count[t], first_child[t], n_child[t] | (level[t] << 16));
+}
+
 __global__ void __launch_bounds__(256) k_fill_int(int n, int *a, int v)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -448,16 +463,17 @@ struct WalkArgs {
     int n_groups;
     const int *groups;
     const float4 *glo, *ghi;
-    const int *begin, *count, *level, *first_child, *n_child;
+    const int4 *node;  // walk records (k_pack_nodes)
     const float4 *com, *pp;
     int npp;
     const float *rc2;  // (l_L / theta)^2 per level, device
-    const float *xs, *ys, *zs, *ms;
+    const float4 *xm;  // particles (x, y, z, m) in key order
     long long *glen;        // pass 1 output: list length per group
     const long long *goff;  // pass 2 input: list offset per group
     float *xj, *yj, *zj, *mj;
     int *src;               // pass 2, optional
     unsigned *overflow;
+    unsigned *max_frontier; // pass 1: the largest frontier met
 };
 
 __device__ inline int wave_incl_scan(int v, int lane)
@@ -484,20 +500,26 @@ constexpr int kWalkWaves = 2;  // waves per workgroup, each walking its own grou
 // nodes at a time; wave prefix sums place each lane's contributions in the
 // list and its opened children in the next frontier (double-buffered in LDS).
 // Pass 1 (WRITE = false) only counts; pass 2 writes the entries at the
-// offsets of the scanned counts, in the same order.
-template <bool WRITE>
+// offsets of the scanned counts, in the same order: the contributions of 64
+// nodes form one contiguous block of the list, which the lanes write entry
+// by entry (coalesced), each finding its entry's node by a binary search over
+// the wave's inclusive counts.
+template <bool WRITE, int FCAP>
 __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(WalkArgs a)
 {
-    __shared__ int fr[kWalkWaves][2][kWalkFrontier];
+    __shared__ int fr[kWalkWaves][2][FCAP];
+    __shared__ int s_inc[kWalkWaves][64], s_src[kWalkWaves][64];
     __shared__ float rc2[kTreeMaxLevel + 1];
     if (threadIdx.x <= kTreeMaxLevel) rc2[threadIdx.x] = a.rc2[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int n_waves = gridDim.x * kWalkWaves;
+    int maxf = 0;  // largest frontier this wave met (one atomic at the end)
     for (int g = blockIdx.x * kWalkWaves + w; g < a.n_groups; g += n_waves) {
         const int gn = a.groups[g];
         const float4 lo = a.glo[g], hi = a.ghi[g];
-        const int gb = a.begin[gn], glev = a.level[gn];
+        const int4 grec = a.node[gn];
+        const int gb = grec.x, glev = grec.w >> 16;
         const long long out = WRITE ? a.goff[g] : 0;
         long long len = 0;
         int cur = 0, ncur = 1;
@@ -508,12 +530,14 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(WalkArgs a)
             int nnext = 0;
             for (int c0 = 0; c0 < ncur; c0 += 64) {
                 const int idx = c0 + lane;
-                int emit = 0, push = 0, t = 0, nb = 0, fc = 0;
-                bool acc = false;
+                int emit = 0, push = 0, code = 0, fc = 0;
                 if (idx < ncur) {
-                    t = fr[w][cur][idx];
-                    const int b = a.begin[t], c = a.count[t], L = a.level[t], nch = a.n_child[t];
+                    const int t = fr[w][cur][idx];
+                    const int4 r = a.node[t];
+                    const int b = r.x, c = r.y, nch = r.w & 0xffff, L = r.w >> 16;
+                    fc = r.z;
                     const bool anc = L <= glev && b <= gb && gb < b + c;
+                    bool acc = false;
                     if (!anc) {
                         const float4 cm = a.com[t];
                         const float ex = fmaxf(fmaxf(lo.x - cm.x, cm.x - hi.x), 0.f);
@@ -521,49 +545,54 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(WalkArgs a)
                         const float ez = fmaxf(fmaxf(lo.z - cm.z, cm.z - hi.z), 0.f);
                         acc = rc2[L] < ex * ex + ey * ey + ez * ez;
                     }
-                    if (acc)
+                    if (acc) {
                         emit = a.npp;
-                    else if (nch == 0)
+                        code = t * a.npp;  // first pseudo-particle
+                    } else if (nch == 0) {
                         emit = c;
-                    else
+                        code = -1 - b;     // first particle
+                    } else {
                         push = nch;
-                    nb = b;
-                    fc = a.first_child[t];
+                    }
                 }
                 const int e_inc = wave_incl_scan(emit, lane);
                 const int p_inc = wave_incl_scan(push, lane);
                 const int e_tot = __shfl(e_inc, 63, 64), p_tot = __shfl(p_inc, 63, 64);
-                if (nnext + p_tot > kWalkFrontier) {
+                if (nnext + p_tot > FCAP) {
                     over = true;
                     break;
                 }
                 for (int k = 0; k < push; ++k) fr[w][cur ^ 1][nnext + p_inc - push + k] = fc + k;
-                if (WRITE && emit > 0) {
-                    const long long base = out + len + (e_inc - emit);
-                    if (acc) {
-                        for (int k = 0; k < emit; ++k) {
-                            const float4 q = a.pp[(long long)t * emit + k];
-                            a.xj[base + k] = q.x;
-                            a.yj[base + k] = q.y;
-                            a.zj[base + k] = q.z;
-                            a.mj[base + k] = q.w;
-                            if (a.src) a.src[base + k] = -(1 + t * emit + k);
+                if (WRITE && e_tot > 0) {
+                    s_inc[w][lane] = e_inc;
+                    s_src[w][lane] = code;
+                    wave_sync_lds();
+                    const long long base = out + len;
+                    for (int e = lane; e < e_tot; e += 64) {
+                        int l0 = 0, l1 = 63;  // first lane whose inclusive count exceeds e
+                        while (l0 < l1) {
+                            const int mid = (l0 + l1) >> 1;
+                            if (s_inc[w][mid] > e)
+                                l1 = mid;
+                            else
+                                l0 = mid + 1;
                         }
-                    } else {
-                        for (int k = 0; k < emit; ++k) {
-                            const int r = nb + k;
-                            a.xj[base + k] = a.xs[r];
-                            a.yj[base + k] = a.ys[r];
-                            a.zj[base + k] = a.zs[r];
-                            a.mj[base + k] = a.ms[r];
-                            if (a.src) a.src[base + k] = r;
-                        }
+                        const int k = e - (l0 ? s_inc[w][l0 - 1] : 0);
+                        const int cd = s_src[w][l0];
+                        const float4 q = cd >= 0 ? a.pp[cd + k] : a.xm[-1 - cd + k];
+                        a.xj[base + e] = q.x;
+                        a.yj[base + e] = q.y;
+                        a.zj[base + e] = q.z;
+                        a.mj[base + e] = q.w;
+                        if (a.src) a.src[base + e] = cd >= 0 ? -(1 + cd + k) : -1 - cd + k;
                     }
+                    wave_sync_lds();
                 }
                 len += e_tot;
                 nnext += p_tot;
             }
             if (over) break;
+            maxf = max(maxf, nnext);
             wave_sync_lds();
             cur ^= 1;
             ncur = nnext;
@@ -575,6 +604,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(WalkArgs a)
         if (!WRITE && lane == 0) a.glen[g] = len;
         wave_sync_lds();
     }
+    if (!WRITE && lane == 0 && maxf > 0) atomicMax(a.max_frontier, (unsigned)maxf);
 }
 
 __global__ void k_tail_zero(long long *p) { *p = 0; }
@@ -684,7 +714,8 @@ void tree_release(TreeState &t)
     void *ps[] = {t.key, t.key_in, t.perm, t.iota, t.xs, t.ys, t.zs, t.ms, t.mark, t.axs,
                   t.ays, t.azs, t.phs, t.begin, t.count, t.level, t.first_child, t.n_child,
                   t.parent, t.nc, t.mom, t.com, t.pp, t.groups, t.glo, t.ghi, t.glen, t.goff,
-                  t.items, t.xj, t.yj, t.zj, t.mj, t.src, t.tmp, t.word, t.count_out, t.rc2};
+                  t.items, t.xj, t.yj, t.zj, t.mj, t.src, t.tmp, t.word, t.count_out, t.rc2,
+                  t.xm, t.nrec};
     for (void *p : ps) (void)hipFree(p);
     t = TreeState();
 }
@@ -704,7 +735,7 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
     std::fill(t.frame, t.frame + 5, 0.f);
     t.host_items.clear();
     if (!t.word) {
-        TREE_ALLOC(hipMalloc((void **)&t.word, 8 * sizeof(unsigned)) == hipSuccess);
+        TREE_ALLOC(hipMalloc((void **)&t.word, 16 * sizeof(unsigned)) == hipSuccess);
         TREE_ALLOC(hipMalloc((void **)&t.count_out, sizeof(int)) == hipSuccess);
         TREE_ALLOC(hipMalloc((void **)&t.rc2, (kTreeMaxLevel + 1) * sizeof(float)) == hipSuccess);
     }
@@ -721,7 +752,7 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
                   grow(&t.zs, &dummy, cap) && grow(&t.ms, &dummy, cap) &&
                   grow(&t.mark, &dummy, cap) && grow(&t.axs, &dummy, cap) &&
                   grow(&t.ays, &dummy, cap) && grow(&t.azs, &dummy, cap) &&
-                  grow(&t.phs, &dummy, cap);
+                  grow(&t.phs, &dummy, cap) && grow(&t.xm, &dummy, cap);
         if (!ok) {
             t.n_cap = 0;
             err = "tree: device allocation failed";
@@ -761,7 +792,7 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
     TREE_HIP(hipcub::DeviceRadixSort::SortPairs(t.tmp, tb, t.key_in, t.key, t.iota, t.perm, n, 0,
                                                 63, s));
     hipLaunchKernelGGL(k_gather, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, t.perm, x, y, z, m,
-                       t.xs, t.ys, t.zs, t.ms);
+                       t.xs, t.ys, t.zs, t.ms, t.xm);
     TREE_HIP(hipGetLastError());
     // 3. octree, level by level
     if (t.node_cap < 1) {
@@ -825,7 +856,7 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
         const long long cap = (long long)t.n_nodes * 3 / 2 + 1024;
         long long dummy = 0;
         TREE_ALLOC(grow(&t.mom, &dummy, cap) && grow(&t.com, &dummy, cap) &&
-                   grow(&t.pp, &dummy, 3 * cap));
+                   grow(&t.pp, &dummy, 3 * cap) && grow(&t.nrec, &dummy, cap));
         t.pp_cap = (int)cap;
     }
     for (int l = t.depth; l >= 0; --l) {
@@ -835,6 +866,8 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
     }
     hipLaunchKernelGGL(k_pseudo, dim3(blocks_of(t.n_nodes, 256)), dim3(256), 0, s, t.n_nodes,
                        t.mom, t.quad, t.pp, t.com);
+    hipLaunchKernelGGL(k_pack_nodes, dim3(blocks_of(t.n_nodes, 256)), dim3(256), 0, s, t.n_nodes,
+                       t.begin, t.count, t.first_child, t.n_child, t.level, t.nrec);
     TREE_HIP(hipGetLastError());
     // 5. groups in key order
     hipLaunchKernelGGL(k_fill_int, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, t.mark, -1);
@@ -868,6 +901,7 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
               std::string &err)
 {
     t.walked = 0;
+    t.max_frontier = 0;
     t.theta = theta;
     t.record_src = record_src ? 1 : 0;
     t.n_entries = t.interactions = 0;
@@ -889,35 +923,50 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
     a.groups = t.groups;
     a.glo = t.glo;
     a.ghi = t.ghi;
-    a.begin = t.begin;
-    a.count = t.count;
-    a.level = t.level;
-    a.first_child = t.first_child;
-    a.n_child = t.n_child;
+    a.node = t.nrec;
     a.com = t.com;
     a.pp = t.pp;
     a.npp = t.quad ? 3 : 1;
     a.rc2 = t.rc2;
-    a.xs = t.xs, a.ys = t.ys, a.zs = t.zs, a.ms = t.ms;
+    a.xm = t.xm;
     a.glen = t.glen;
     a.goff = t.goff;
     a.overflow = t.word + 7;
-    const int grid = std::min(blocks_of(t.n_groups, kWalkWaves), 2 * num_cu);
-    hipLaunchKernelGGL(k_walk<false>, dim3(grid), dim3(64 * kWalkWaves), 0, s, a);
-    hipLaunchKernelGGL(k_tail_zero, dim3(1), dim3(1), 0, s, t.glen + t.n_groups);
-    TREE_HIP(hipGetLastError());
-    size_t tb = t.tmp_bytes;
-    TREE_HIP(hipcub::DeviceScan::ExclusiveSum(t.tmp, tb, t.glen, t.goff, t.n_groups + 1, s));
-    long long total = 0;
-    unsigned over = 0;
-    TREE_HIP(hipMemcpyAsync(&total, t.goff + t.n_groups, sizeof total, hipMemcpyDeviceToHost, s));
-    TREE_HIP(hipMemcpyAsync(&over, t.word + 7, sizeof over, hipMemcpyDeviceToHost, s));
-    TREE_HIP(hipStreamSynchronize(s));
+    a.max_frontier = t.word + 8;
+    // Pass 1 with the small frontier (LDS for 2 walking waves per SIMD); if
+    // a group's frontier outgrows it, again with the large one (1 per SIMD).
+    const int grid_small = std::min(blocks_of(t.n_groups, kWalkWaves), 4 * num_cu);
+    const int grid_large = std::min(blocks_of(t.n_groups, kWalkWaves), 2 * num_cu);
+    bool large = false;
+    unsigned over = 0, maxf = 0;
+    for (;;) {
+        if (large)
+            hipLaunchKernelGGL((k_walk<false, kWalkFrontier>), dim3(grid_large),
+                               dim3(64 * kWalkWaves), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_walk<false, kWalkFrontier / 2>), dim3(grid_small),
+                               dim3(64 * kWalkWaves), 0, s, a);
+        TREE_HIP(hipGetLastError());
+        TREE_HIP(hipMemcpyAsync(&over, t.word + 7, sizeof over, hipMemcpyDeviceToHost, s));
+        TREE_HIP(hipStreamSynchronize(s));
+        if (!over || large) break;
+        large = true;
+        hipLaunchKernelGGL(k_init_words, dim3(1), dim3(64), 0, s, t.word);
+    }
     if (over) {
         err = "tree walk: a frontier exceeded " + std::to_string(kWalkFrontier) +
               " nodes (theta too small for this tree)";
         return PGH_ERANGE;
     }
+    hipLaunchKernelGGL(k_tail_zero, dim3(1), dim3(1), 0, s, t.glen + t.n_groups);
+    TREE_HIP(hipGetLastError());
+    size_t tb = t.tmp_bytes;
+    TREE_HIP(hipcub::DeviceScan::ExclusiveSum(t.tmp, tb, t.glen, t.goff, t.n_groups + 1, s));
+    long long total = 0;
+    TREE_HIP(hipMemcpyAsync(&total, t.goff + t.n_groups, sizeof total, hipMemcpyDeviceToHost, s));
+    TREE_HIP(hipMemcpyAsync(&maxf, t.word + 8, sizeof maxf, hipMemcpyDeviceToHost, s));
+    TREE_HIP(hipStreamSynchronize(s));
+    t.max_frontier = (int)maxf;
     if (total > INT_MAX) {
         err = "tree walk: the lists exceed 2^31 - 1 entries";
         return PGH_ERANGE;
@@ -935,7 +984,12 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
     }
     a.xj = t.xj, a.yj = t.yj, a.zj = t.zj, a.mj = t.mj;
     a.src = record_src ? t.src : nullptr;
-    hipLaunchKernelGGL(k_walk<true>, dim3(grid), dim3(64 * kWalkWaves), 0, s, a);
+    if (large)
+        hipLaunchKernelGGL((k_walk<true, kWalkFrontier>), dim3(grid_large),
+                           dim3(64 * kWalkWaves), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_walk<true, kWalkFrontier / 2>), dim3(grid_small),
+                           dim3(64 * kWalkWaves), 0, s, a);
     hipLaunchKernelGGL(k_items_j, dim3(blocks_of(t.n_groups, 256)), dim3(256), 0, s, t.n_groups,
                        t.goff, t.glen, t.items);
     TREE_HIP(hipGetLastError());
