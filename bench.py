@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
+    ap.add_argument("--only-extra", default=None, metavar="NAME",
+                    help="run only the named secondary workload (e.g. tree_code) and print "
+                         "its JSON; for profiling one workload")
     return ap.parse_args()
 
 
@@ -556,10 +559,12 @@ def table_allpairs(torch, pgh, synth):
             "ms_per_variant": per, "kernel_ms_with_potential_last_variant": tp.mean_ms()}
 
 
-def tree_code(torch, pgh, synth, sizes=(1 << 20, 1 << 22), n_crit=64):
+def tree_code(torch, pgh, synth, sizes=(1 << 20, 1 << 22), n_crit=64,
+              models=("plummer", "king9")):
     """The tree code of Sec. 5 (Fig. 10): forces and potentials of every
-    particle of a Plummer sphere with the device Barnes-Hut tree, theta =
-    0.75, leaves of at most 8 particles, i-groups of at most n_crit, eps = 1/512,
+    particle of a Plummer sphere (scale radius 1) and of a King model with
+    W0 = 9 (King radius 1) with the device Barnes-Hut tree, theta = 0.75,
+    leaves of at most 8 particles, i-groups of at most n_crit, eps = 1/512,
     monopole and quadrupole pseudo-particles.  Wall-clock per phase, each
     call synchronous except the force (timed with events, then waited for):
     build (keys, sort, octree, moments, groups), walk (both passes and the
@@ -568,8 +573,9 @@ def tree_code(torch, pgh, synth, sizes=(1 << 20, 1 << 22), n_crit=64):
     res = {}
     ctx = pgh.Context(0)
     ctx.set_eps_to_all(1.0 / 512)
-    for n in sizes:
-        x, y, z = synth.plummer(n, 330)
+    cases = [(model, n) for model in models for n in sizes]
+    for model, n in cases:
+        x, y, z = synth.plummer(n, 330) if model == "plummer" else synth.king(n, 331, 9.0)
         m = synth.equal_masses(n)
         d = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
         t = ctx.tree()
@@ -579,7 +585,7 @@ def tree_code(torch, pgh, synth, sizes=(1 << 20, 1 << 22), n_crit=64):
             t.walk(0.75)
             out = t.newton()
             torch.cuda.synchronize()
-            tb, tw, tf, tt = [], [], [], []
+            tb, tw, tt = [], [], []
             timer = KernelTimer(torch)
             for _ in range(3):
                 torch.cuda.synchronize()
@@ -609,10 +615,10 @@ def tree_code(torch, pgh, synth, sizes=(1 << 20, 1 << 22), n_crit=64):
                 "interactions": inter, "force_interactions_per_s": rate,
                 "force_frac_of_peak_38flop": NEWTON_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12)}
         t.free()
-        res[f"plummer_N{n}"] = per_n
+        res[f"{model}_N{n}"] = per_n
         del d
     ctx.close()
-    return {"workload": f"tree_code_plummer_theta0.75_nleaf8_ncrit{n_crit}_eps1/512", **res}
+    return {"workload": f"tree_code_theta0.75_nleaf8_ncrit{n_crit}_eps1/512", **res}
 
 
 def main():
@@ -629,6 +635,17 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     REPLAYS["override"] = args.replays
+    if args.only_extra:
+        extras = {"newton_small": newton_small, "table_allpairs": table_allpairs,
+                  "newton_batched": batched_newton, "table_batched": batched_table,
+                  "adjoint_newton": adjoint_newton, "adjoint_table": adjoint_table,
+                  "ni_nj_sweep": ni_nj_sweep, "grape5_host": grape5_host,
+                  "tree_code": lambda t, p, s: tree_code(t, p, s, n_crit=256)}
+        if args.only_extra not in extras:
+            print(f"unknown workload {args.only_extra}; one of {sorted(extras)}", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({args.only_extra: extras[args.only_extra](torch, pgh, synth)}))
+        return
     r = newton_allpairs(torch, pgh, synth, args)
     if args.copy_calibration > 0:
         src = torch.empty(args.copy_calibration << 18, device="cuda")

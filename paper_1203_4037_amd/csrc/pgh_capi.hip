@@ -655,12 +655,18 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
             c_nj[u] = ch.n_j;
             c_it[u] = lane_iters(ch);
         }
+        // beside a chunk of more than 32 only one of at most 31 fits: such
+        // chunks scan the later small ones only (next_small skips the rest)
+        std::vector<size_t> next_small(nc + 1, nc);
+        for (size_t v = nc; v-- > 0;) next_small[v] = c_ni[v] <= 31 ? v : next_small[v + 1];
         constexpr size_t kWindow = 64;
         for (size_t u = 0; u < nc; ++u) {
             if (c_taken[u]) continue;
             const int room = 64 - c_ni[u];
             const size_t v_end = std::min(nc, u + 1 + kWindow);
-            for (size_t v = u + 1; v < v_end; ++v) {
+            const bool big = room <= 31;
+            for (size_t v = big ? next_small[u + 1] : u + 1; v < v_end;
+                 v = big ? next_small[v + 1] : v + 1) {
                 if (c_taken[v] || c_ni[v] > room) continue;
                 if (64LL * std::max(c_nj[u], c_nj[v]) >= c_it[u] + c_it[v]) continue;
                 c_taken[u] = c_taken[v] = 1;

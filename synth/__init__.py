@@ -2,7 +2,7 @@
 
 Both the library's tests/benchmark and the FP64 oracle consume these arrays;
 this module holds none of the force arithmetic.  It draws particle
-distributions (Plummer sphere, uniform periodic box), builds interaction lists
+distributions (Plummer sphere, King model, uniform periodic box), builds interaction lists
 (cell-grid neighbour lists, tree-style batched groups) and loss weights.
 
 All generators use numpy's PCG64 (``default_rng(seed)``), draw in float64 and
@@ -39,6 +39,60 @@ def plummer(n: int, seed: int, b: float = 1.0):
 def plummer_virial_radius(b: float = 1.0) -> float:
     """r_v = 16 b / (3 pi) for the Plummer model (G = M = 1)."""
     return 16.0 * b / (3.0 * np.pi)
+
+
+def king_density(W):
+    """Density of the King (1966) model at dimensionless potential W =
+    Psi/sigma^2, in units of rho_1 (the DF f(E) = rho_1 (2 pi sigma^2)^{-3/2}
+    (e^{E/sigma^2} - 1) integrated over velocities; Binney & Tremaine 2008,
+    Eq. 4.114): e^W erf(sqrt W) - sqrt(4W/pi) (1 + 2W/3), zero for W <= 0."""
+    from scipy.special import erf
+    W = np.maximum(np.asarray(W, dtype=np.float64), 0.0)
+    return np.exp(W) * erf(np.sqrt(W)) - np.sqrt(4.0 * W / np.pi) * (1.0 + 2.0 * W / 3.0)
+
+
+def king_profile(W0: float):
+    """Radial profile of a King model of central potential W0 in units of the
+    King radius r_0 = sqrt(9 sigma^2 / (4 pi G rho_0)): Poisson's equation
+    W'' + (2/r) W' = -9 rho(W)/rho(W0), W(0) = W0, W'(0) = 0, integrated out
+    to the tidal radius r_t where W = 0.  Returns (r grid, enclosed mass
+    fraction M(<r)/M, r_t); M(<r) is proportional to -r^2 W'(r)."""
+    from scipy.integrate import solve_ivp
+    rho0 = float(king_density(W0))
+
+    def rhs(r, y):
+        return [y[1], -9.0 * float(king_density(y[0])) / rho0 - 2.0 * y[1] / r]
+
+    def edge(r, y):
+        return y[0]
+
+    edge.terminal = True
+    edge.direction = -1
+    r_start = 1e-6  # series start: W = W0 - (3/2) r^2 near the centre
+    grid = np.concatenate([[r_start], np.logspace(-5.5, 6, 4000)])
+    sol = solve_ivp(rhs, [r_start, 1e6], [W0 - 1.5 * r_start ** 2, -3.0 * r_start],
+                    events=edge, dense_output=True, rtol=1e-11, atol=1e-13, method="DOP853")
+    rt = float(sol.t_events[0][0])
+    r = np.concatenate([grid[grid < rt], [rt]])
+    dW = sol.sol(r)[1]
+    mass = np.maximum.accumulate(-r * r * dW)  # the interpolant may dip by 1e-12 at r_t
+    return r, mass / mass[-1], rt
+
+
+def king(n: int, seed: int, W0: float = 9.0):
+    """King-model positions (the paper's second tree-code distribution,
+    Sec. 5, with W0 = 9) in units of the King radius: radii by inverting the
+    enclosed-mass profile of king_profile(W0), directions isotropic.  Returns
+    float32 (x, y, z)."""
+    r_grid, frac, _ = king_profile(W0)
+    rng = np.random.default_rng(seed)
+    X = rng.random(n)
+    r = np.interp(X, frac, r_grid)
+    cth = rng.uniform(-1.0, 1.0, n)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    sth = np.sqrt(1.0 - cth * cth)
+    return ((r * sth * np.cos(ph)).astype(np.float32), (r * sth * np.sin(ph)).astype(np.float32),
+            (r * cth).astype(np.float32))
 
 
 def uniform_box(n: int, seed: int, box: float = 1.0):

@@ -357,3 +357,37 @@ def test_full_size_plummer_sampled(pgh, ctx):
             checked += 1
         assert checked >= 48
         t.free()
+
+
+def test_king_model_sampled(pgh, ctx):
+    """King model with W0 = 9 (the paper's second tree-code distribution),
+    N = 2^18, groups of at most 256: sampled groups against the oracle's tree
+    force, both moment orders."""
+    n, eps = 1 << 18, 1.0 / 512
+    x, y, z = synth.king(n, 331, 9.0)
+    m = synth.equal_masses(n)
+    d = to_dev(x, y, z, m)
+    ctx.set_eps_to_all(eps)
+    for quad in (False, True):
+        t = ctx.tree()
+        t.build(*d, n_leaf=8, n_crit=256, quad=quad)
+        t.walk(0.75)
+        got = np.stack(to_host(*t.newton()))
+        o = oracle.tree_build(x, y, z, m, n_leaf=8, quad=quad)
+        g = o.find_groups(256)
+        assert np.array_equal(t.get("groups"), g)
+        assert np.array_equal(t.get("node_count"), o.count)
+        rng = np.random.default_rng(9)
+        pick = np.unique(rng.integers(0, len(g), 40))
+        _, _, mg, ax, ay, az, _ = oracle.tree_force(o, 0.75, 256, eps, groups=g[pick])
+        checked = 0
+        for k, gi in enumerate(pick):
+            if mg[k] <= BORDER:
+                continue
+            gn = g[gi]
+            r = np.arange(o.begin[gn], o.begin[gn] + o.count[gn])
+            ea = rel_vec_err(got[:3, o.perm[r]], np.stack([ax[r], ay[r], az[r]]))
+            assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, (quad, gi, rms(ea), ea.max())
+            checked += 1
+        assert checked >= 30
+        t.free()
