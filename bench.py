@@ -124,10 +124,12 @@ def time_steps(torch, step, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def cpu_baseline(x, y, z, m, eps, target_s):
+def cpu_baseline(x, y, z, m, eps, target_s, synth=None):
     """FP64 oracle (plain loops, OpenMP over i) on a sample of i-particles
-    against all j, scaled to interactions per second."""
+    against all j, scaled to interactions per second; with synth, also the
+    oracle's rate on the other configs (oracle_configs)."""
     import oracle
+    configs = oracle_configs(synth) if synth is not None else None
     n = x.size
     e2 = np.float32(eps) ** 2
     cal = np.arange(0, n, max(1, n // 256))
@@ -144,7 +146,72 @@ def cpu_baseline(x, y, z, m, eps, target_s):
     return {"value": ns * n / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle, {ns} evenly spaced i-particles x all {n} j-particles "
                       f"({ns * n:.3e} interactions) in {dt:.1f} s",
-            "value_1core": one, "cpu_model": cpu_model()}
+            "value_1core": one, "cpu_model": cpu_model(), "configs": configs}
+
+
+def oracle_configs(synth):
+    """The FP64 oracle on every config with all host threads: config 1 full
+    (Newton, N = 1024), config 3 full (table force on the 4^3-cell lists),
+    config 4 on a stratified sample of 512 of its 16384 lists (the longest
+    and the shortest by work, the rest evenly spaced in work order), config 5
+    forward full (Newton all-pairs, N = 65536) and backward on a 4096-i
+    slice.  Interactions per second each, with what was timed."""
+    import oracle
+    out = {}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    n = 1024
+    x, y, z = synth.plummer(n, 101)
+    m = synth.equal_masses(n)
+    e2 = np.full(n, np.float32(1.0 / 64) ** 2, np.float32)
+    dt = timed(lambda: oracle.newton(x, y, z, e2, x, y, z, m))
+    out["newton_allpairs_N1024"] = {"interactions_per_s": n * n / dt, "sample": "full"}
+    n = 262144
+    x, y, z = synth.uniform_box(n, 103)
+    m = synth.equal_masses(n)
+    s = synth.cell_grid_items(x, y, z, m, ncell=64, block=4)
+    rcut, eps = 3.0 / 256, 1.0 / 1280
+    tab = oracle.table_build(4, 6, float(np.float32(rcut)), oracle.SHAPE_S2PP, eps)
+    dt = timed(lambda: oracle.lut_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, 4, 6,
+                                        float(np.float32(rcut)), tab))
+    out["table_cell_lists_block4"] = {"interactions_per_s": s.interactions / dt, "sample": "full"}
+    del s
+    t = synth.tree_style_items(1 << 22, 16384, 104)
+    cost = t.items[:, 1].astype(np.int64) * t.items[:, 3]
+    order = np.argsort(cost)
+    pick = order[np.unique(np.linspace(0, len(order) - 1, 512).round().astype(np.int64))]
+    # the sampled lists' i-rows and j-ranges copied out compactly, so the
+    # timed call widens only the sample to FP64
+    it = t.items[pick].astype(np.int64)
+    rows = np.concatenate([np.arange(a, a + b) for a, b in it[:, :2]])
+    cols = np.concatenate([np.arange(a, a + b) for a, b in it[:, 2:]])
+    ci = np.stack([np.concatenate([[0], np.cumsum(it[:, 1])[:-1]]), it[:, 1],
+                   np.concatenate([[0], np.cumsum(it[:, 3])[:-1]]), it[:, 3]], 1)
+    xi, yi, zi = t.xi[rows], t.yi[rows], t.zi[rows]
+    xj, yj, zj, mj = t.xj[cols], t.yj[cols], t.zj[cols], t.mj[cols]
+    e2 = np.full(rows.size, np.float32(1e-3) ** 2, np.float32)
+    dt = timed(lambda: oracle.newton_items(ci, xi, yi, zi, e2, xj, yj, zj, mj))
+    inter = float((it[:, 1] * it[:, 3]).sum())
+    out["newton_batched_tree_lists"] = {"interactions_per_s": inter / dt,
+                                        "sample": f"{len(pick)} of {len(t.items)} lists, {inter:.3e} interactions"}
+    del t
+    n = 65536
+    x, y, z = synth.plummer(n, 105)
+    m = synth.equal_masses(n)
+    wx, wy, wz = synth.weights(n, 106)
+    e2 = np.full(n, np.float32(0.01) ** 2, np.float32)
+    dt = timed(lambda: oracle.newton(x, y, z, e2, x, y, z, m))
+    out["adjoint_forward_N65536"] = {"interactions_per_s": float(n) * n / dt, "sample": "full"}
+    k = 4096
+    dt = timed(lambda: oracle.newton_bwd(x[:k], y[:k], z[:k], e2[:k], x, y, z, m,
+                                         wx[:k], wy[:k], wz[:k]))
+    out["adjoint_backward_N65536"] = {"interactions_per_s": float(k) * n / dt,
+                                      "sample": f"{k} i-particles x {n} j-particles"}
+    return out
 
 
 def cpu_model():
@@ -698,7 +765,7 @@ def main():
         line["extras"] = ex
     if not args.no_cpu:
         x, y, z, m = r["x"]
-        line["cpu_baseline"] = cpu_baseline(x, y, z, m, 0.01, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(x, y, z, m, 0.01, args.cpu_seconds, synth)
     print(json.dumps(line))
 
 
