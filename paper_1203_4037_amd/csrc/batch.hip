@@ -164,10 +164,19 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
         };
         const int list = second ? 1 : 0;  // this lane's list
         load(0);
-        // vmcnt(0): the i-particle and first-tile loads.  Waiting here keeps
-        // the compiler from placing a full wait inside the pair loop, where
-        // it would also wait for the prefetch of the next tile.
+        // vmcnt(0): the i-particle and first-tile loads (and the counter's
+        // atomic).  Waiting here keeps the compiler from placing a full wait
+        // inside the pair loop, where it would also wait for the prefetch of
+        // the next tile.
         __builtin_amdgcn_s_waitcnt(0x0F70);
+        // The next task's index is known now: its 12 fields are fetched with
+        // one vector load (field k in lane k) while this task runs, instead
+        // of by scalar loads after it, whose latency the next task would
+        // wait for (scalar loads inside the loop would also hold up its LDS
+        // waits, which share their counter).
+        const unsigned t_next = __builtin_amdgcn_readfirstlane(tn);
+        int fld = 0;
+        if (t_next < n_tasks && lane < 12) fld = ((const int *)(tasks + t_next))[lane];
         if (NB == 2) {
             store(0);
             wave_sync();
@@ -266,8 +275,20 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
             // parts of the chunk in order after this launch
             a.partial[(size_t)(tk.slot + tk.part) * 64 + lane] = make_float4(tx, ty, tz, tp);
         }
-        t = __builtin_amdgcn_readfirstlane(tn);
-        if (t < n_tasks) tk_next = tasks[t];
+        t = t_next;
+        if (t < n_tasks) {
+            tk_next.i_off = __builtin_amdgcn_readlane(fld, 0);
+            tk_next.n_i = __builtin_amdgcn_readlane(fld, 1);
+            tk_next.j_off = __builtin_amdgcn_readlane(fld, 2);
+            tk_next.n_j = __builtin_amdgcn_readlane(fld, 3);
+            tk_next.part = __builtin_amdgcn_readlane(fld, 4);
+            tk_next.n_parts = __builtin_amdgcn_readlane(fld, 5);
+            tk_next.slot = __builtin_amdgcn_readlane(fld, 6);
+            tk_next.i_off2 = __builtin_amdgcn_readlane(fld, 7);
+            tk_next.n_i2 = __builtin_amdgcn_readlane(fld, 8);
+            tk_next.j_off2 = __builtin_amdgcn_readlane(fld, 9);
+            tk_next.n_j2 = __builtin_amdgcn_readlane(fld, 10);
+        }
     }
 }
 

@@ -57,6 +57,7 @@ struct Task {
     int i_off2, n_i2, j_off2, n_j2;
     int pad;
 };
+static_assert(sizeof(Task) == 12 * sizeof(int), "the batched kernel loads a task as 12 ints");
 
 // A chunk of i-particles whose j-list is split into parts; its partial sums
 // sit in lanes [lane0, lane0 + n_i) of its slots (lane0 > 0 for the second
