@@ -3,8 +3,9 @@
     python paper_1203_4037_amd/build.py     (run by path: importing the package
                                              needs the library it builds)
 
-Every .hip file under csrc/ is compiled to an object in csrc/_build/ (in
-parallel) and linked into paper_1203_4037_amd/libpgh.so.  Packed FP32 VALU
+Every .hip file under csrc/ (hipcc) and .cpp file (the host planner, the
+system C++ compiler) is compiled to an object in csrc/_build/ (in parallel)
+and linked into paper_1203_4037_amd/libpgh.so.  Packed FP32 VALU
 instructions are disabled for the whole library (-packed-fp32-ops).
 """
 from __future__ import annotations
@@ -43,18 +44,26 @@ def _hipcc() -> str:
     return p
 
 
+# plain C++ sources (the host planner): the system compiler, no offload
+CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall",
+             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *FLAGS, "-c", src, "-o", obj]
+    if src.endswith(".cpp"):
+        cmd = [shutil.which("g++") or "g++", *CXX_FLAGS, "-c", src, "-o", obj]
+    else:
+        cmd = [_hipcc(), *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        raise RuntimeError(f"compiling {src} failed:\n{r.stderr}")
     return obj
 
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "pgh_internal.h"
+#include "planner.h"
 
 using namespace pgh;
 
@@ -171,42 +172,6 @@ int zero_outputs(pgh_ctx *c, int n, float *a, float *b, float *d, float *e)
 {
     PGH_HIP(c, launch_fill_zero(n, a, b, d, e, c->stream));
     return PGH_OK;
-}
-
-// Orders idx stably by key(idx) (descending if asked): a counting sort when
-// the keys are small non-negative integers (list lengths, wave-iterations),
-// else a comparison sort.
-template <class Key>
-void stable_order(std::vector<int> &idx, Key key, bool descending)
-{
-    long long kmax = 0;
-    bool small = true;
-    for (int k : idx) {
-        const long long v = key(k);
-        if (v < 0 || v > (1LL << 22)) {
-            small = false;
-            break;
-        }
-        kmax = std::max(kmax, v);
-    }
-    if (!small) {
-        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-            return descending ? key(a) > key(b) : key(a) < key(b);
-        });
-        return;
-    }
-    std::vector<int> start((size_t)kmax + 2, 0);
-    for (int k : idx) {
-        const long long v = key(k);
-        ++start[(size_t)(descending ? kmax - v : v) + 1];
-    }
-    for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
-    std::vector<int> out(idx.size());
-    for (int k : idx) {
-        const long long v = key(k);
-        out[(size_t)start[(size_t)(descending ? kmax - v : v)]++] = k;
-    }
-    idx.swap(out);
 }
 
 }  // namespace
@@ -563,177 +528,20 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     if (!c) return PGH_EINVAL;
     if (!out) return fail(c, PGH_EINVAL, "out is NULL");
     *out = nullptr;
-    if (n_items < 0 || ni_total < 0 || nj_total < 0)
-        return fail(c, PGH_EINVAL, "counts must be >= 0");
-    if (n_items > 0 && !items) return fail(c, PGH_EINVAL, "NULL item array");
-    // ranges and disjointness of the i-groups
-    std::vector<int> order;
-    order.reserve(n_items);
-    long long inter = 0;
-    for (int t = 0; t < n_items; ++t) {
-        const pgh_item &it = items[t];
-        if (it.i_off < 0 || it.n_i < 0 || it.j_off < 0 || it.n_j < 0)
-            return fail(c, PGH_EINVAL, "item " + std::to_string(t) + " has a negative field");
-        if ((long long)it.i_off + it.n_i > ni_total || (long long)it.j_off + it.n_j > nj_total)
-            return fail(c, PGH_ERANGE, "item " + std::to_string(t) + " exceeds the arrays");
-        if (it.n_i > 0) order.push_back(t);
-        inter += (long long)it.n_i * it.n_j;
-    }
-    std::sort(order.begin(), order.end(),
-              [&](int a, int b) { return items[a].i_off < items[b].i_off; });
-    for (size_t k = 1; k < order.size(); ++k) {
-        const pgh_item &p0 = items[order[k - 1]], &p1 = items[order[k]];
-        if (p1.i_off < p0.i_off + p0.n_i)
-            return fail(c, PGH_EINVAL, "i-ranges of items " + std::to_string(order[k - 1]) +
-                                           " and " + std::to_string(order[k]) + " overlap");
-    }
-
-    // Wave tasks: chunks of <= 64 i-particles; a chunk of <= 32 (<= 16) runs
-    // js = 2 (4) lanes per i-particle.  When chunks of 64 fill less than half
-    // of the waves the device holds (a small plan), the groups are cut into
-    // chunks of 32 or 16 instead: more waves to hide latency, each lane's
-    // j-list shorter, and no partial sums (the lanes of an i-particle are
-    // added inside the wave).
-    struct Chunk {
-        int i_off, n_i, j_off, n_j, js;
-    };
-    const int waves = std::max(1, batch_resident_waves(c->num_cu));
-    int csize = 64;
-    for (;;) {
-        long long n = 0;
-        for (int t : order) n += (items[t].n_i + csize - 1) / csize;
-        if (n >= waves || csize == 16) break;
-        csize /= 2;
-    }
-    std::vector<Chunk> chunks;
-    long long total = 0;  // wave-iterations
-    for (int t : order) {
-        const pgh_item &it = items[t];
-        for (int s0 = 0; s0 < it.n_i; s0 += csize) {
-            const int n = std::min(csize, it.n_i - s0);
-            const int js = n <= 16 ? 4 : (n <= 32 ? 2 : 1);
-            chunks.push_back({it.i_off + s0, n, it.j_off, it.n_j, js});
-            total += std::max(1LL, (long long)(it.n_j + js - 1) / js);
-        }
-    }
-    // Cut j-lists longer than an eighth of the average work of a resident
-    // wave, so each wave takes several tasks and the longest-first queue
-    // ends with short ones.  (Equal tasks of half a wave's work leave the
-    // last round of the queue mostly idle whenever the task count is just
-    // above a multiple of the wave count.)
-    const long long part_iters = std::max(512LL, (total / waves / 8 + 63) / 64 * 64);
-    std::vector<Task> tasks;
-    std::vector<long long> cost;
-    std::vector<SplitChunk> split;
-    int n_slots = 0;
-    // Pair partly filled chunks: in order of j-list length, each takes the
-    // first later one (within a short window) whose i-particles fit beside
-    // its own in 64 lanes, when one wavefront running the longer list costs
-    // fewer lane-iterations than the two apart.  A pair is cut along j like
-    // any long list (both lists at the same offsets).
-    struct Work {
-        Chunk a, b;  // b.n_i == 0: a single chunk
-    };
-    std::vector<Work> work;
+    HostPlan hp;
     {
-        auto lane_iters = [](const Chunk &ch) {
-            return 64LL * std::max(1LL, (long long)(ch.n_j + ch.js - 1) / ch.js);
-        };
-        std::vector<char> taken(chunks.size(), 0);
-        std::vector<int> cand;
-        for (size_t k = 0; k < chunks.size(); ++k)
-            if (chunks[k].n_i < 64 && chunks[k].n_j > 0) cand.push_back((int)k);
-        stable_order(cand, [&](int k) { return (long long)chunks[k].n_j; }, false);
-        // the scan reads candidates in this order: keep their fields contiguous
-        const size_t nc = cand.size();
-        std::vector<int> c_ni(nc), c_nj(nc);
-        std::vector<long long> c_it(nc);
-        std::vector<char> c_taken(nc, 0);
-        for (size_t u = 0; u < nc; ++u) {
-            const Chunk &ch = chunks[cand[u]];
-            c_ni[u] = ch.n_i;
-            c_nj[u] = ch.n_j;
-            c_it[u] = lane_iters(ch);
-        }
-        // beside a chunk of more than 32 only one of at most 31 fits: such
-        // chunks scan the later small ones only (next_small skips the rest)
-        std::vector<size_t> next_small(nc + 1, nc);
-        for (size_t v = nc; v-- > 0;) next_small[v] = c_ni[v] <= 31 ? v : next_small[v + 1];
-        constexpr size_t kWindow = 64;
-        for (size_t u = 0; u < nc; ++u) {
-            if (c_taken[u]) continue;
-            const int room = 64 - c_ni[u];
-            const size_t v_end = std::min(nc, u + 1 + kWindow);
-            const bool big = room <= 31;
-            for (size_t v = big ? next_small[u + 1] : u + 1; v < v_end;
-                 v = big ? next_small[v + 1] : v + 1) {
-                if (c_taken[v] || c_ni[v] > room) continue;
-                if (64LL * std::max(c_nj[u], c_nj[v]) >= c_it[u] + c_it[v]) continue;
-                c_taken[u] = c_taken[v] = 1;
-                taken[cand[u]] = taken[cand[v]] = 1;
-                work.push_back({chunks[cand[u]], chunks[cand[v]]});
-                break;
-            }
-        }
-        for (size_t k = 0; k < chunks.size(); ++k)
-            if (!taken[k]) work.push_back({chunks[k], Chunk{0, 0, 0, 0, 1}});
+        std::string err;
+        const int st = plan_tasks(items, n_items, ni_total, nj_total,
+                                  batch_resident_waves(c->num_cu), hp, err);
+        if (st) return fail(c, st, err);
     }
-    for (const Work &w : work) {
-        const Chunk &ch = w.a;
-        const bool pair = w.b.n_i > 0;
-        const int js = pair ? 1 : ch.js;
-        const int njm = pair ? std::max(ch.n_j, w.b.n_j) : ch.n_j;
-        const long long iters = (njm + js - 1) / js;
-        int parts = (int)std::max(1LL, (iters + part_iters - 1) / part_iters);
-        long long per = njm;
-        if (parts > 1) {
-            // equal parts, each a multiple of 64 j-particles except the last
-            per = (njm + parts - 1) / parts;
-            per = (per + 63) / 64 * 64;
-            parts = (int)((njm + per - 1) / per);
-        }
-        auto cut = [&](int n_j, int q) {
-            return (int)std::max(0LL, std::min<long long>(per, n_j - q * per));
-        };
-        if (parts <= 1) {
-            tasks.push_back({ch.i_off, ch.n_i, ch.j_off, ch.n_j, 0, 1, 0, w.b.i_off, w.b.n_i,
-                             w.b.j_off, w.b.n_j, 0});
-            cost.push_back(std::max(1LL, iters));
-            continue;
-        }
-        for (int q = 0; q < parts; ++q) {
-            const int nja = cut(ch.n_j, q), njb = pair ? cut(w.b.n_j, q) : 0;
-            tasks.push_back({ch.i_off, ch.n_i, ch.j_off + (int)(q * per), nja, q, parts, n_slots,
-                             w.b.i_off, w.b.n_i, w.b.j_off + (int)(q * per), njb, 0});
-            cost.push_back((std::max(nja, njb) + js - 1) / js);
-        }
-        split.push_back({ch.i_off, ch.n_i, n_slots, parts, 0});
-        if (pair) split.push_back({w.b.i_off, w.b.n_i, n_slots, parts, ch.n_i});
-        n_slots += parts;
-    }
+    const std::vector<Task> &sorted = hp.tasks;
+    const std::vector<SplitChunk> &split = hp.split;
+    const int nq = hp.nq;
+    const int *q_begin = hp.q_begin;
+    const long long inter = hp.interactions;
     const int n_chunks = (int)split.size();
-    // longest tasks first
-    std::vector<int> idx(tasks.size());
-    for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
-    stable_order(idx, [&](int k) { return cost[k]; }, true);
-    // Deal the longest-first list into nq sublists, a group of kBatchWaves
-    // consecutive tasks at a time, round-robin: each sublist stays longest
-    // first with an equal share of every size class, and workgroup b (which
-    // serves sublist b mod nq) takes tasks 4b .. 4b+3 of the whole list in
-    // its first round, one of similar length per SIMD.
-    const int nq = (int)std::min<size_t>(
-        kQueues, std::max<size_t>(1, (idx.size() + kBatchWaves - 1) / kBatchWaves));
-    std::vector<Task> sorted;
-    sorted.reserve(tasks.size());
-    int q_begin[kQueues + 1] = {0};
-    for (int q = 0; q < nq; ++q) {
-        q_begin[q] = (int)sorted.size();
-        for (size_t g0 = (size_t)q * kBatchWaves; g0 < idx.size(); g0 += (size_t)nq * kBatchWaves)
-            for (size_t k = g0; k < std::min(idx.size(), g0 + kBatchWaves); ++k)
-                sorted.push_back(tasks[idx[k]]);
-    }
-    q_begin[nq] = (int)sorted.size();
-
+    const int n_slots = hp.n_slots;
     pgh_plan *p = new (std::nothrow) pgh_plan;
     if (!p) return fail(c, PGH_ENOMEM, "out of host memory");
     p->owner = c;
@@ -755,8 +563,7 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     p->itasks = nullptr;
     p->adj_built = false;
     p->n_jtasks = p->n_itasks = 0;
-    p->ordered.reserve(order.size());
-    for (int t : order) p->ordered.push_back(items[t]);
+    p->ordered.swap(hp.ordered);
     DeviceGuard g(c->device);
     auto cleanup = [&](int code, const char *msg) {
         free_plan_memory(p);
@@ -819,38 +626,8 @@ int check_plan(pgh_ctx *c, const pgh_plan *p)
 int build_adjoint_tasks(pgh_ctx *c, pgh_plan *p)
 {
     if (p->adj_built) return PGH_OK;
-    const std::vector<pgh_item> &ord = p->ordered;
-    const int waves = std::max(1, batch_resident_waves(c->num_cu));
-    // i-major tasks of the table adjoint (the i-side position gradient, its
-    // own list independent of the forward's chunking): i-chunks of <= 64
-    // against j-ranges of <= 512, added with atomics, so no partial sums
-    std::vector<Task> it_tasks;
-    for (const pgh_item &it : ord) {
-        for (int s0 = 0; s0 < it.n_i; s0 += 64)
-            for (int q0 = 0; q0 < it.n_j; q0 += 512)
-                it_tasks.push_back({it.i_off + s0, std::min(64, it.n_i - s0), it.j_off + q0,
-                                    std::min(512, it.n_j - q0), 0, 1, 0, 0, 0, 0, 0, 0});
-    }
-    std::stable_sort(it_tasks.begin(), it_tasks.end(), [](const Task &a, const Task &b) {
-        return (long long)a.n_j * ((a.n_i + 15) / 16) > (long long)b.n_j * ((b.n_i + 15) / 16);
-    });
-    // j-major tasks of the table adjoint: chunks of <= 64 j-entries of a
-    // list against its i-group (chunks of 32 or 16, 2 or 4 lanes per entry,
-    // when chunks of 64 would fill less than half of the resident waves)
-    int jc = 64;
-    for (;;) {
-        long long n = 0;
-        for (const pgh_item &it : ord) n += (it.n_j + jc - 1) / jc;
-        if (2 * n >= waves || jc == 16) break;
-        jc /= 2;
-    }
-    std::vector<Task> jt;
-    for (const pgh_item &it : ord) {
-        for (int s0 = 0; s0 < it.n_j; s0 += jc)
-            jt.push_back({it.j_off + s0, std::min(jc, it.n_j - s0), it.i_off, it.n_i, 0, 1, 0, 0, 0,
-                          0, 0, 0});
-    }
-    std::stable_sort(jt.begin(), jt.end(), [](const Task &a, const Task &b) { return a.n_j > b.n_j; });
+    std::vector<Task> jt, it_tasks;
+    plan_adjoint_tasks(p->ordered, batch_resident_waves(c->num_cu), jt, it_tasks);
     if (hipMalloc((void **)&p->jqueue, 2 * sizeof(unsigned)) != hipSuccess ||
         (!jt.empty() && hipMalloc((void **)&p->jtasks, jt.size() * sizeof(Task)) != hipSuccess) ||
         (!it_tasks.empty() &&
