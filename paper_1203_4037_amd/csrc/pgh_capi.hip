@@ -528,7 +528,7 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     if (!c) return PGH_EINVAL;
     if (!out) return fail(c, PGH_EINVAL, "out is NULL");
     *out = nullptr;
-    HostPlan hp;
+    static thread_local HostPlan hp;  // its vectors keep their capacity between plans
     {
         std::string err;
         const int st = plan_tasks(items, n_items, ni_total, nj_total,
@@ -563,7 +563,7 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     p->itasks = nullptr;
     p->adj_built = false;
     p->n_jtasks = p->n_itasks = 0;
-    p->ordered.swap(hp.ordered);
+    p->ordered = hp.ordered;
     DeviceGuard g(c->device);
     auto cleanup = [&](int code, const char *msg) {
         free_plan_memory(p);

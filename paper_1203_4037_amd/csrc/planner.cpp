@@ -21,7 +21,8 @@ int fail_msg(std::string &err, int code, const std::string &msg)
 // the keys are small non-negative integers (list lengths, wave-iterations),
 // else a comparison sort.
 template <class Key>
-void stable_order(std::vector<int> &idx, Key key, bool descending)
+void stable_order(std::vector<int> &idx, Key key, bool descending, std::vector<int> &start,
+                  std::vector<int> &out)
 {
     long long kmax = 0;
     bool small = true;
@@ -39,18 +40,48 @@ void stable_order(std::vector<int> &idx, Key key, bool descending)
         });
         return;
     }
-    std::vector<int> start((size_t)kmax + 2, 0);
+    start.assign((size_t)kmax + 2, 0);
     for (int k : idx) {
         const long long v = key(k);
         ++start[(size_t)(descending ? kmax - v : v) + 1];
     }
     for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
-    std::vector<int> out(idx.size());
+    out.resize(idx.size());
     for (int k : idx) {
         const long long v = key(k);
         out[(size_t)start[(size_t)(descending ? kmax - v : v)]++] = k;
     }
     idx.swap(out);
+}
+
+// A chunk of at most 64 i-particles of one item (js lanes per i-particle).
+struct Chunk {
+    int i_off, n_i, j_off, n_j, js;
+};
+
+// A wave's work before splitting: one chunk, or two that share the wave.
+struct Work {
+    int a, b;  // chunk indices; b < 0: a single chunk
+};
+
+// The planner's temporaries, kept between calls on a host thread: plans of
+// 10^5 tasks are rebuilt at every tree walk, and fresh vectors of that size
+// cost more in first-touch page faults than the planning itself.
+struct Scratch {
+    std::vector<int> order, cand, idx, so_start, so_out;
+    std::vector<Chunk> chunks;
+    std::vector<Work> work;
+    std::vector<Task> tasks;
+    std::vector<long long> cost, c_it;
+    std::vector<char> taken, c_taken;
+    std::vector<int> c_ni, c_nj;
+    std::vector<size_t> next_small;
+};
+
+Scratch &scratch()
+{
+    static thread_local Scratch s;
+    return s;
 }
 
 }  // namespace
@@ -61,9 +92,10 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
     if (n_items < 0 || ni_total < 0 || nj_total < 0)
         return fail_msg(err, PGH_EINVAL, "counts must be >= 0");
     if (n_items > 0 && !items) return fail_msg(err, PGH_EINVAL, "NULL item array");
+    Scratch &S = scratch();
     // ranges and disjointness of the i-groups
-    std::vector<int> order;
-    order.reserve(n_items);
+    std::vector<int> &order = S.order;
+    order.clear();
     long long inter = 0;
     for (int t = 0; t < n_items; ++t) {
         const pgh_item &it = items[t];
@@ -89,9 +121,6 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
     // chunks of 32 or 16 instead: more waves to hide latency, each lane's
     // j-list shorter, and no partial sums (the lanes of an i-particle are
     // added inside the wave).
-    struct Chunk {
-        int i_off, n_i, j_off, n_j, js;
-    };
     waves = std::max(1, waves);
     int csize = 64;
     for (;;) {
@@ -100,7 +129,8 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
         if (n >= waves || csize == 16) break;
         csize /= 2;
     }
-    std::vector<Chunk> chunks;
+    std::vector<Chunk> &chunks = S.chunks;
+    chunks.clear();
     long long total = 0;  // wave-iterations
     for (int t : order) {
         const pgh_item &it = items[t];
@@ -117,33 +147,41 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
     // last round of the queue mostly idle whenever the task count is just
     // above a multiple of the wave count.)
     const long long part_iters = std::max(512LL, (total / waves / 8 + 63) / 64 * 64);
-    std::vector<Task> tasks;
-    std::vector<long long> cost;
-    std::vector<SplitChunk> split;
+    std::vector<Task> &tasks = S.tasks;
+    std::vector<long long> &cost = S.cost;
+    tasks.clear();
+    cost.clear();
+    std::vector<SplitChunk> &split = out.split;
+    split.clear();
     int n_slots = 0;
     // Pair partly filled chunks: in order of j-list length, each takes the
     // first later one (within a short window) whose i-particles fit beside
     // its own in 64 lanes, when one wavefront running the longer list costs
     // fewer lane-iterations than the two apart.  A pair is cut along j like
     // any long list (both lists at the same offsets).
-    struct Work {
-        Chunk a, b;  // b.n_i == 0: a single chunk
-    };
-    std::vector<Work> work;
+    std::vector<Work> &work = S.work;
+    work.clear();
     {
         auto lane_iters = [](const Chunk &ch) {
             return 64LL * std::max(1LL, (long long)(ch.n_j + ch.js - 1) / ch.js);
         };
-        std::vector<char> taken(chunks.size(), 0);
-        std::vector<int> cand;
+        std::vector<char> &taken = S.taken;
+        taken.assign(chunks.size(), 0);
+        std::vector<int> &cand = S.cand;
+        cand.clear();
         for (size_t k = 0; k < chunks.size(); ++k)
             if (chunks[k].n_i < 64 && chunks[k].n_j > 0) cand.push_back((int)k);
-        stable_order(cand, [&](int k) { return (long long)chunks[k].n_j; }, false);
+        stable_order(cand, [&](int k) { return (long long)chunks[k].n_j; }, false, S.so_start,
+                     S.so_out);
         // the scan reads candidates in this order: keep their fields contiguous
         const size_t nc = cand.size();
-        std::vector<int> c_ni(nc), c_nj(nc);
-        std::vector<long long> c_it(nc);
-        std::vector<char> c_taken(nc, 0);
+        std::vector<int> &c_ni = S.c_ni, &c_nj = S.c_nj;
+        std::vector<long long> &c_it = S.c_it;
+        std::vector<char> &c_taken = S.c_taken;
+        c_ni.resize(nc);
+        c_nj.resize(nc);
+        c_it.resize(nc);
+        c_taken.assign(nc, 0);
         for (size_t u = 0; u < nc; ++u) {
             const Chunk &ch = chunks[cand[u]];
             c_ni[u] = ch.n_i;
@@ -152,7 +190,8 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
         }
         // beside a chunk of more than 32 only one of at most 31 fits: such
         // chunks scan the later small ones only (next_small skips the rest)
-        std::vector<size_t> next_small(nc + 1, nc);
+        std::vector<size_t> &next_small = S.next_small;
+        next_small.assign(nc + 1, nc);
         for (size_t v = nc; v-- > 0;) next_small[v] = c_ni[v] <= 31 ? v : next_small[v + 1];
         constexpr size_t kWindow = 64;
         for (size_t u = 0; u < nc; ++u) {
@@ -166,16 +205,20 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
                 if (64LL * std::max(c_nj[u], c_nj[v]) >= c_it[u] + c_it[v]) continue;
                 c_taken[u] = c_taken[v] = 1;
                 taken[cand[u]] = taken[cand[v]] = 1;
-                work.push_back({chunks[cand[u]], chunks[cand[v]]});
+                work.push_back({cand[u], cand[v]});
                 break;
             }
         }
         for (size_t k = 0; k < chunks.size(); ++k)
-            if (!taken[k]) work.push_back({chunks[k], Chunk{0, 0, 0, 0, 1}});
+            if (!taken[k]) work.push_back({(int)k, -1});
     }
-    for (const Work &w : work) {
-        const Chunk &ch = w.a;
-        const bool pair = w.b.n_i > 0;
+    static const Chunk kNone{0, 0, 0, 0, 1};
+    for (const Work &wk : work) {
+        const Chunk &ch = chunks[wk.a];
+        const bool pair = wk.b >= 0;
+        struct {
+            const Chunk &b;
+        } w{pair ? chunks[wk.b] : kNone};
         const int js = pair ? 1 : ch.js;
         const int njm = pair ? std::max(ch.n_j, w.b.n_j) : ch.n_j;
         const long long iters = (njm + js - 1) / js;
@@ -211,9 +254,10 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
         n_slots += parts;
     }
     // longest tasks first
-    std::vector<int> idx(tasks.size());
+    std::vector<int> &idx = S.idx;
+    idx.resize(tasks.size());
     for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
-    stable_order(idx, [&](int k) { return cost[k]; }, true);
+    stable_order(idx, [&](int k) { return cost[k]; }, true, S.so_start, S.so_out);
     // Deal the longest-first list into nq sublists, a group of kBatchWaves
     // consecutive tasks at a time, round-robin: each sublist stays longest
     // first with an equal share of every size class, and workgroup b (which
@@ -221,8 +265,8 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
     // its first round, one of similar length per SIMD.
     const int nq = (int)std::min<size_t>(
         kQueues, std::max<size_t>(1, (idx.size() + kBatchWaves - 1) / kBatchWaves));
-    std::vector<Task> sorted;
-    sorted.reserve(tasks.size());
+    std::vector<Task> &sorted = out.tasks;
+    sorted.clear();
     int *q_begin = out.q_begin;
     std::fill(q_begin, q_begin + kQueues + 1, 0);
     for (int q = 0; q < nq; ++q) {
@@ -233,9 +277,7 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
     }
     q_begin[nq] = (int)sorted.size();
 
-    out.tasks.swap(sorted);
     out.nq = nq;
-    out.split.swap(split);
     out.n_slots = n_slots;
     out.interactions = inter;
     out.ordered.clear();
