@@ -391,3 +391,54 @@ def test_king_model_sampled(pgh, ctx):
             checked += 1
         assert checked >= 30
         t.free()
+
+
+@pytest.mark.parametrize("theta,n_leaf,quad", [(0.3, 16, False), (0.5, 4, True), (1.0, 1, False),
+                                               (0.75, 64, True)])
+def test_theta_and_leaf_variants(pgh, ctx, theta, n_leaf, quad):
+    """Other opening angles and leaf sizes: lists entry by entry against the
+    oracle (groups without borderline decisions), forces against the
+    oracle's sum over the GPU's lists."""
+    n, eps = 20000, 1.0 / 256
+    x, y, z = synth.plummer(n, 340)
+    m = synth.equal_masses(n)
+    t, _ = _build(ctx, x, y, z, m, n_leaf, max(64, n_leaf), quad)
+    t.walk(theta, record_src=True)
+    o = oracle.tree_build(x, y, z, m, n_leaf=n_leaf, quad=quad)
+    g = o.find_groups(max(64, n_leaf))
+    items = t.get("items")
+    src = t.get("list_src").astype(np.int64)
+    exact = 0
+    for k, gn in enumerate(g):
+        ref, margin = o.walk(gn, theta)
+        if margin > BORDER:
+            assert np.array_equal(src[items[k, 2]:items[k, 2] + items[k, 3]], ref), k
+            exact += 1
+    assert exact >= 0.9 * len(g)
+    ctx.set_eps_to_all(eps)
+    got = np.stack(to_host(*t.newton()))[:, o.perm]
+    lists = [t.get(f).astype(np.float64) for f in ("list_x", "list_y", "list_z", "list_m")]
+    e2 = np.full(n, float(np.float32(eps)) ** 2)
+    ref = np.stack(oracle.newton_items(items, o.x, o.y, o.z, e2, *lists))
+    ea = rel_vec_err(got[:3], ref[:3])
+    assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, (rms(ea), ea.max())
+    t.free()
+
+
+def test_lists_beyond_int32_are_an_error(pgh, ctx):
+    """2^24 particles in groups of at most 8 with quadrupole pseudo-particles
+    need more than 2^31 - 1 list entries: the walk reports PGH_ERANGE after its
+    counting pass (no list memory is allocated), and a coarser walk of the
+    same tree still works."""
+    n = 1 << 24
+    x, y, z = synth.plummer(n, 350)
+    d = to_dev(x, y, z, synth.equal_masses(n))
+    t = ctx.tree()
+    t.build(*d, n_leaf=8, n_crit=8, quad=True)
+    with pytest.raises(pgh.PGHError) as e:
+        t.walk(0.75)
+    assert e.value.code == pgh.PGH_ERANGE and "2^31" in str(e.value)
+    t.build(*d, n_leaf=8, n_crit=256, quad=False)
+    t.walk(0.75)
+    assert 0 < t.stats()["n_entries"] < 2 ** 31
+    t.free()
