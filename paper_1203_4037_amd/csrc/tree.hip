@@ -982,6 +982,16 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
         const long long cap = total + total / 4 + 1024;
         TREE_ALLOC(grow(&t.src, &t.src_cap, cap));
     }
+    // The items are complete once the lists are counted: they go to the host
+    // now, and the writing pass runs while the caller plans the batched
+    // launch from them (the plan's upload is ordered after it on the stream).
+    hipLaunchKernelGGL(k_items_j, dim3(blocks_of(t.n_groups, 256)), dim3(256), 0, s, t.n_groups,
+                       t.goff, t.glen, t.items);
+    TREE_HIP(hipGetLastError());
+    t.host_items.resize(t.n_groups);
+    TREE_HIP(hipMemcpyAsync(t.host_items.data(), t.items, sizeof(pgh_item) * t.n_groups,
+                            hipMemcpyDeviceToHost, s));
+    TREE_HIP(hipStreamSynchronize(s));
     a.xj = t.xj, a.yj = t.yj, a.zj = t.zj, a.mj = t.mj;
     a.src = record_src ? t.src : nullptr;
     if (large)
@@ -990,13 +1000,7 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
     else
         hipLaunchKernelGGL((k_walk<true, kWalkFrontier / 2>), dim3(grid_small),
                            dim3(64 * kWalkWaves), 0, s, a);
-    hipLaunchKernelGGL(k_items_j, dim3(blocks_of(t.n_groups, 256)), dim3(256), 0, s, t.n_groups,
-                       t.goff, t.glen, t.items);
     TREE_HIP(hipGetLastError());
-    t.host_items.resize(t.n_groups);
-    TREE_HIP(hipMemcpyAsync(t.host_items.data(), t.items, sizeof(pgh_item) * t.n_groups,
-                            hipMemcpyDeviceToHost, s));
-    TREE_HIP(hipStreamSynchronize(s));
     long long inter = 0;
     for (const pgh_item &it : t.host_items) inter += (long long)it.n_i * it.n_j;
     t.n_entries = total;
