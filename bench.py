@@ -707,7 +707,7 @@ def main():
                   "newton_batched": batched_newton, "table_batched": batched_table,
                   "adjoint_newton": adjoint_newton, "adjoint_table": adjoint_table,
                   "ni_nj_sweep": ni_nj_sweep, "grape5_host": grape5_host,
-                  "tree_code": lambda t, p, s: tree_code(t, p, s, n_crit=256)}
+                  "tree_code": lambda t, p, s: tree_code(t, p, s, n_crit=1024)}
         if args.only_extra not in extras:
             print(f"unknown workload {args.only_extra}; one of {sorted(extras)}", file=sys.stderr)
             sys.exit(2)
@@ -760,7 +760,7 @@ def main():
               "adjoint_table": adjoint_table(torch, pgh, synth),
               "ni_nj_sweep": ni_nj_sweep(torch, pgh, synth),
               "grape5_host": grape5_host(torch, pgh, synth),
-              "tree_code": tree_code(torch, pgh, synth, n_crit=256)}
+              "tree_code": tree_code(torch, pgh, synth, n_crit=1024)}
         ex["batched_over_allpairs"] = ex["newton_batched"]["interactions_per_s"] / value
         line["extras"] = ex
     if not args.no_cpu:
