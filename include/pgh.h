@@ -396,7 +396,7 @@ PGH_API int pgh_tree_free(pgh_ctx *c, pgh_tree *t);
 
 /* Builds the octree of n particles (device arrays, read during the call),
  * their moments, pseudo-particles (quad != 0: three per node) and the
- * i-groups.  Synchronous: waits for the stream once per tree level.
+ * i-groups.  Synchronous: waits for the stream at its end.
  * n_leaf in [1, 64], n_crit >= n_leaf (PGH_ERANGE otherwise); positions must
  * be finite (PGH_ERANGE).  Invalidates the lists of an earlier walk. */
 PGH_API int pgh_tree_build(pgh_ctx *c, pgh_tree *t, int n, const float *x, const float *y,

@@ -173,7 +173,9 @@ struct TreeState {
     int *mark = nullptr;  // group id at the first particle of each group, else -1
     // sorted-order outputs of the force (scattered back through perm)
     float *axs = nullptr, *ays = nullptr, *azs = nullptr, *phs = nullptr;
-    // nodes, capacity node_cap (breadth first, each level in key order)
+    // nodes, capacity node_cap (breadth first, each level in key order); the
+    // moment, centre-of-mass and walk-record arrays have node_cap entries too,
+    // the pseudo-particles 3 node_cap
     int node_cap = 0;
     int *begin = nullptr, *count = nullptr, *level = nullptr, *first_child = nullptr,
         *n_child = nullptr, *parent = nullptr;
@@ -183,7 +185,6 @@ struct TreeState {
     float4 *com = nullptr;    // FP32 centre of mass per node (w unused)
     int4 *nrec = nullptr;     // walk record per node: begin, count, first child, n_child | level << 16
     float4 *pp = nullptr;     // pseudo-particles (x, y, z, m), npp per node
-    int pp_cap = 0;
     // groups, capacity group_cap
     int group_cap = 0;
     int *groups = nullptr;
@@ -201,6 +202,7 @@ struct TreeState {
     unsigned *word = nullptr;  // 16 words: min/max frame, leaf count, walk overflow, frontier
     int *count_out = nullptr;
     float *rc2 = nullptr;      // (l_L / theta)^2 per level for the walk
+    int *lvl = nullptr;        // first node of each level (device), kTreeMaxLevel + 3 entries
     // results of the last build / walk
     int n = 0, n_nodes = 0, n_leaves = 0, depth = 0, n_groups = 0, max_level_nodes = 0;
     int max_frontier = 0;  // largest walk frontier of the last walk

@@ -27,8 +27,9 @@
 //           distance from its com to the group's bounding box, and adds its
 //           pseudo-particles; an opened leaf adds its particles.
 //
-// Host-driven: the build waits for the stream once per level (a level's node
-// count sizes the next launch), so it is not meant for graph capture.
+// The build launches every level with its size in a device table and waits
+// for the stream once, at its end (the walk waits after its counting pass);
+// neither is meant for graph capture.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -154,12 +155,22 @@ __global__ void __launch_bounds__(256) k_gather(int n, const int *__restrict__ p
     xm[r] = v;
 }
 
-__global__ void k_root(int n, int *begin, int *count, int *level, int *parent)
+// Level table of the octree build: level L holds nodes [lvl[L], lvl[L + 1]);
+// the write kernel of level L sets lvl[L + 2].  All sizes stay on the device:
+// the host launches every level without waiting for the one before.
+constexpr int kLvl = kTreeMaxLevel + 3;
+// word indices in TreeState::word
+constexpr int kWordLeaves = 6, kWordOverflow = 9, kWordMaxLevel = 10;
+
+__global__ void k_root(int n, int *begin, int *count, int *level, int *parent, int *lvl)
 {
     begin[0] = 0;
     count[0] = n;
     level[0] = 0;
     parent[0] = -1;
+    lvl[0] = 0;
+    lvl[1] = 1;
+    for (int L = 2; L < kLvl; ++L) lvl[L] = 1;
 }
 
 __device__ inline int digit_of(unsigned long long k, int L)
@@ -181,69 +192,161 @@ __device__ inline int lower_digit(const unsigned long long *key, int lo, int hi,
     return lo;
 }
 
-// nc[i] = non-empty children of node off + i (0 for a leaf); nc[n_level] = 0.
-// w[6] counts the leaves.
-__global__ void __launch_bounds__(256) k_split_count(int n_level, int off, int L, int n_leaf,
+// nc[i] = non-empty children of the i-th node of level L (0 for a leaf).
+// w[kWordLeaves] counts the leaves.
+__global__ void __launch_bounds__(256) k_split_count(int L, int n_leaf,
+                                                     const int *__restrict__ lvl,
                                                      const int *__restrict__ begin,
                                                      const int *__restrict__ count,
                                                      const unsigned long long *__restrict__ key,
                                                      int *__restrict__ nc, unsigned *w)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i > n_level) return;
-    if (i == n_level) {
-        nc[i] = 0;
-        return;
-    }
-    const int b = begin[off + i], c = count[off + i];
-    int k = 0;
-    if (c > n_leaf && L < kTreeMaxLevel) {
-        int prev = b;
-        for (int d = 1; d <= 8; ++d) {
-            const int p = (d == 8) ? b + c : lower_digit(key, prev, b + c, d, L + 1);
-            k += p > prev;
-            prev = p;
+    if (w[kWordOverflow]) return;
+    const int off = lvl[L], n_level = lvl[L + 1] - off;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n_level; i += gridDim.x * 256) {
+        const int b = begin[off + i], c = count[off + i];
+        int k = 0;
+        if (c > n_leaf && L < kTreeMaxLevel) {
+            int prev = b;
+            for (int d = 1; d <= 8; ++d) {
+                const int p = (d == 8) ? b + c : lower_digit(key, prev, b + c, d, L + 1);
+                k += p > prev;
+                prev = p;
+            }
         }
+        if (k == 0) atomicAdd(&w[kWordLeaves], 1u);
+        nc[i] = k;
     }
-    nc[i] = k;
-    if (k == 0) atomicAdd(&w[6], 1u);
 }
 
-__global__ void __launch_bounds__(256) k_split_write(int n_level, int off, int L, int n_leaf,
-                                                     int next_off,
+// Exclusive scan of the n = lvl[L + 1] - lvl[L] counts of level L into
+// out[0 .. n] (out[n] = the total), with n read on the device: chunk sums
+// (kScanBlocks chunks), a scan of those in one workgroup, then each chunk
+// scanned in tiles of 256 from its offset.
+constexpr int kScanBlocks = 512;
+
+// Inclusive scan over a workgroup of 256 (wave scans, then the wave totals);
+// *total receives the workgroup's sum.  Every thread of the workgroup calls it.
+__device__ inline int block_incl_scan(int v, int *sh, int *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    if (lane == 63) sh[wv] = v;
+    __syncthreads();
+    int add = 0;
+    for (int k = 0; k < wv; ++k) add += sh[k];
+    *total = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return v + add;
+}
+
+__global__ void __launch_bounds__(256) k_scan_sums(int L, const int *__restrict__ lvl,
+                                                   const unsigned *__restrict__ w,
+                                                   const int *__restrict__ in, int *bsum)
+{
+    __shared__ int sh[4];
+    if (w[kWordOverflow]) return;
+    const int n = lvl[L + 1] - lvl[L];
+    const int chunk = (n + kScanBlocks - 1) / kScanBlocks;
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    int v = 0;
+    for (int i = lo + threadIdx.x; i < hi; i += 256) v += in[i];
+    int tot = 0;
+    block_incl_scan(v, sh, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(256) k_scan_top(const unsigned *__restrict__ w, int *bsum)
+{
+    __shared__ int sh[4];
+    if (w[kWordOverflow]) return;
+    // kScanBlocks = 2 x 256 entries: two per thread
+    const int a = bsum[2 * threadIdx.x], b = bsum[2 * threadIdx.x + 1];
+    int tot = 0;
+    const int incl = block_incl_scan(a + b, sh, &tot);
+    bsum[2 * threadIdx.x] = incl - a - b;
+    bsum[2 * threadIdx.x + 1] = incl - b;
+    if (threadIdx.x == 0) bsum[kScanBlocks] = tot;
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(int L, const int *__restrict__ lvl,
+                                                    const unsigned *__restrict__ w,
+                                                    const int *__restrict__ in,
+                                                    const int *__restrict__ bsum, int *out)
+{
+    __shared__ int sh[4];
+    if (w[kWordOverflow]) return;
+    const int n = lvl[L + 1] - lvl[L];
+    const int chunk = (n + kScanBlocks - 1) / kScanBlocks;
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    int run = bsum[blockIdx.x];
+    for (int t0 = lo; t0 < hi; t0 += 256) {  // uniform trip count for the workgroup
+        const int i = t0 + threadIdx.x;
+        const int v = i < hi ? in[i] : 0;
+        int tot = 0;
+        const int incl = block_incl_scan(v, sh, &tot);
+        if (i < hi) out[i] = run + incl - v;
+        run += tot;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[kScanBlocks];
+}
+
+// Writes the children of level L at lvl[L + 1] + scan[i] and sets lvl[L + 2].
+// Children that would pass the node capacity are not written: the overflow
+// word is set, every later kernel of the build returns at once, and the host
+// builds again with more room.
+__global__ void __launch_bounds__(256) k_split_write(int L, int n_leaf, int cap, int *lvl,
                                                      const unsigned long long *__restrict__ key,
                                                      const int *__restrict__ scan, int *begin,
                                                      int *count, int *level, int *first_child,
-                                                     int *n_child, int *parent)
+                                                     int *n_child, int *parent, unsigned *w)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n_level) return;
-    const int node = off + i;
-    const int b = begin[node], c = count[node];
-    const int fc = next_off + scan[i];
-    int k = 0;
-    if (c > n_leaf && L < kTreeMaxLevel) {
-        int prev = b;
-        for (int d = 1; d <= 8; ++d) {
-            const int p = (d == 8) ? b + c : lower_digit(key, prev, b + c, d, L + 1);
-            if (p > prev) {
-                const int ch = fc + k;
-                begin[ch] = prev;
-                count[ch] = p - prev;
-                level[ch] = L + 1;
-                parent[ch] = node;
-                ++k;
-            }
-            prev = p;
+    if (w[kWordOverflow]) return;
+    const int off = lvl[L], n_level = lvl[L + 1] - off, next_off = lvl[L + 1];
+    const int total = scan[n_level];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if ((long long)next_off + total > cap) {
+            atomicOr(&w[kWordOverflow], 1u);
+            lvl[L + 2] = next_off;
+        } else {
+            lvl[L + 2] = next_off + total;
+            atomicMax(&w[kWordMaxLevel], (unsigned)total);
         }
     }
-    first_child[node] = k ? fc : -1;
-    n_child[node] = k;
+    if ((long long)next_off + total > cap) return;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n_level; i += gridDim.x * 256) {
+        const int node = off + i;
+        const int b = begin[node], c = count[node];
+        const int fc = next_off + scan[i];
+        int k = 0;
+        if (c > n_leaf && L < kTreeMaxLevel) {
+            int prev = b;
+            for (int d = 1; d <= 8; ++d) {
+                const int p = (d == 8) ? b + c : lower_digit(key, prev, b + c, d, L + 1);
+                if (p > prev) {
+                    const int ch = fc + k;
+                    begin[ch] = prev;
+                    count[ch] = p - prev;
+                    level[ch] = L + 1;
+                    parent[ch] = node;
+                    ++k;
+                }
+                prev = p;
+            }
+        }
+        first_child[node] = k ? fc : -1;
+        n_child[node] = k;
+    }
 }
 
 // Moments of the nodes of one level: a leaf from its particles, an internal
 // node from its children (parallel-axis theorem), all in FP64.
-__global__ void __launch_bounds__(256) k_moments(int n_level, int off,
+__global__ void __launch_bounds__(256) k_moments(int L, const int *__restrict__ lvl,
+                                                 const unsigned *__restrict__ w,
                                                  const int *__restrict__ begin,
                                                  const int *__restrict__ count,
                                                  const int *__restrict__ first_child,
@@ -253,8 +356,9 @@ __global__ void __launch_bounds__(256) k_moments(int n_level, int off,
                                                  const float *__restrict__ zs,
                                                  const float *__restrict__ ms, NodeMoments *mom)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n_level) return;
+    if (w[kWordOverflow]) return;
+    const int off = lvl[L], n_level = lvl[L + 1] - off;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n_level; i += gridDim.x * 256) {
     const int node = off + i;
     const int nch = n_child[node];
     NodeMoments r;
@@ -308,6 +412,7 @@ __global__ void __launch_bounds__(256) k_moments(int n_level, int off,
         r = {M, sx, sy, sz, a0, a1, a2, a3, a4, a5};
     }
     mom[node] = r;
+    }
 }
 
 // Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (the symmetric
@@ -355,17 +460,19 @@ __device__ void jacobi3(const NodeMoments &q, double w[3], double V[3][3])
     }
 }
 
-__global__ void __launch_bounds__(256) k_pseudo(int n_nodes, const NodeMoments *__restrict__ mom,
-                                                int quad, float4 *__restrict__ pp,
-                                                float4 *__restrict__ com)
+__global__ void __launch_bounds__(256) k_pseudo(const int *__restrict__ lvl,
+                                                const unsigned *__restrict__ w,
+                                                const NodeMoments *__restrict__ mom, int quad,
+                                                float4 *__restrict__ pp, float4 *__restrict__ com)
 {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_nodes) return;
+    if (w[kWordOverflow]) return;
+    const int n_nodes = lvl[kTreeMaxLevel + 1];
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < n_nodes; t += gridDim.x * 256) {
     const NodeMoments q = mom[t];
     com[t] = make_float4((float)q.cx, (float)q.cy, (float)q.cz, 0.f);
     if (!quad) {
         pp[t] = make_float4((float)q.cx, (float)q.cy, (float)q.cz, (float)q.m);
-        return;
+        continue;
     }
     double w[3], V[3][3];
     jacobi3(q, w, V);
@@ -383,19 +490,23 @@ __global__ void __launch_bounds__(256) k_pseudo(int n_nodes, const NodeMoments *
                                     (float)(q.cy + u * V[1][0] + v * V[1][1]),
                                     (float)(q.cz + u * V[2][0] + v * V[2][1]), (float)(q.m / 3.0));
     }
+    }
 }
 
 // Walk record of a node: (begin, count, first child, n_child | level << 16).
-__global__ void __launch_bounds__(256) k_pack_nodes(int n_nodes, const int *__restrict__ begin,
+__global__ void __launch_bounds__(256) k_pack_nodes(const int *__restrict__ lvl,
+                                                    const unsigned *__restrict__ w,
+                                                    const int *__restrict__ begin,
                                                     const int *__restrict__ count,
                                                     const int *__restrict__ first_child,
                                                     const int *__restrict__ n_child,
                                                     const int *__restrict__ level,
                                                     int4 *__restrict__ rec)
 {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_nodes) return;
-    rec[t] = make_int4(begin[t], count[t], first_child[t], n_child[t] | (level[t] << 16));
+    if (w[kWordOverflow]) return;
+    const int n_nodes = lvl[kTreeMaxLevel + 1];
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < n_nodes; t += gridDim.x * 256)
+        rec[t] = make_int4(begin[t], count[t], first_child[t], n_child[t] | (level[t] << 16));
 }
 
 __global__ void __launch_bounds__(256) k_fill_int(int n, int *a, int v)
@@ -404,18 +515,22 @@ __global__ void __launch_bounds__(256) k_fill_int(int n, int *a, int v)
     if (i < n) a[i] = v;
 }
 
-__global__ void __launch_bounds__(256) k_group_mark(int n_nodes, const int *__restrict__ begin,
+__global__ void __launch_bounds__(256) k_group_mark(const int *__restrict__ lvl,
+                                                    const unsigned *__restrict__ w,
+                                                    const int *__restrict__ begin,
                                                     const int *__restrict__ count,
                                                     const int *__restrict__ n_child,
                                                     const int *__restrict__ parent, int n_crit,
                                                     int *__restrict__ mark)
 {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_nodes) return;
-    const bool small = count[t] <= n_crit || n_child[t] == 0;
-    const int p = parent[t];
-    const bool top = p < 0 || count[p] > n_crit;
-    if (small && top) mark[begin[t]] = t;
+    if (w[kWordOverflow]) return;
+    const int n_nodes = lvl[kTreeMaxLevel + 1];
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < n_nodes; t += gridDim.x * 256) {
+        const bool small = count[t] <= n_crit || n_child[t] == 0;
+        const int p = parent[t];
+        const bool top = p < 0 || count[p] > n_crit;
+        if (small && top) mark[begin[t]] = t;
+    }
 }
 
 struct NonNegative {
@@ -423,7 +538,8 @@ struct NonNegative {
 };
 
 // One wave per group: bounding box of its particles and the i-side of its item.
-__global__ void __launch_bounds__(256) k_group_info(int n_groups, const int *__restrict__ groups,
+__global__ void __launch_bounds__(256) k_group_info(const int *__restrict__ n_groups_dev,
+                                                    const int *__restrict__ groups,
                                                     const int *__restrict__ begin,
                                                     const int *__restrict__ count,
                                                     const float *__restrict__ xs,
@@ -431,9 +547,9 @@ __global__ void __launch_bounds__(256) k_group_info(int n_groups, const int *__r
                                                     const float *__restrict__ zs, float4 *glo,
                                                     float4 *ghi, pgh_item *items)
 {
-    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int n_groups = *n_groups_dev;
     const int lane = threadIdx.x & 63;
-    if (g >= n_groups) return;
+    for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < n_groups; g += gridDim.x * 4) {
     const int t = groups[g];
     const int b = begin[t], c = count[t];
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -456,6 +572,7 @@ __global__ void __launch_bounds__(256) k_group_info(int n_groups, const int *__r
         ghi[g] = make_float4(hi[0], hi[1], hi[2], 0.f);
         items[g].i_off = b;
         items[g].n_i = c;
+    }
     }
 }
 
@@ -649,21 +766,6 @@ bool grow(T **p, long long *cap_now, long long cap_new)
     return true;
 }
 
-// Reallocates a node array keeping its first `keep` entries.
-template <class T>
-bool grow_keep(T **p, long long keep, long long cap_new, hipStream_t s)
-{
-    T *q = nullptr;
-    if (hipMalloc((void **)&q, sizeof(T) * (size_t)cap_new) != hipSuccess) return false;
-    if (keep > 0 &&
-        hipMemcpyAsync(q, *p, sizeof(T) * (size_t)keep, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return false;
-    if (hipStreamSynchronize(s) != hipSuccess) return false;
-    (void)hipFree(*p);
-    *p = q;
-    return true;
-}
-
 #define TREE_HIP(call)                                                    \
     do {                                                                  \
         hipError_t e_ = (call);                                           \
@@ -714,7 +816,7 @@ void tree_release(TreeState &t)
     void *ps[] = {t.key, t.key_in, t.perm, t.iota, t.xs, t.ys, t.zs, t.ms, t.mark, t.axs,
                   t.ays, t.azs, t.phs, t.begin, t.count, t.level, t.first_child, t.n_child,
                   t.parent, t.nc, t.mom, t.com, t.pp, t.groups, t.glo, t.ghi, t.glen, t.goff,
-                  t.items, t.xj, t.yj, t.zj, t.mj, t.src, t.tmp, t.word, t.count_out, t.rc2,
+                  t.items, t.xj, t.yj, t.zj, t.mj, t.src, t.tmp, t.word, t.count_out, t.rc2, t.lvl,
                   t.xm, t.nrec};
     for (void *p : ps) (void)hipFree(p);
     t = TreeState();
@@ -738,6 +840,7 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
         TREE_ALLOC(hipMalloc((void **)&t.word, 16 * sizeof(unsigned)) == hipSuccess);
         TREE_ALLOC(hipMalloc((void **)&t.count_out, sizeof(int)) == hipSuccess);
         TREE_ALLOC(hipMalloc((void **)&t.rc2, (kTreeMaxLevel + 1) * sizeof(float)) == hipSuccess);
+        TREE_ALLOC(hipMalloc((void **)&t.lvl, kLvl * sizeof(int)) == hipSuccess);
     }
     if (n == 0) {
         t.built = 1;
@@ -794,87 +897,12 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
     hipLaunchKernelGGL(k_gather, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, t.perm, x, y, z, m,
                        t.xs, t.ys, t.zs, t.ms, t.xm);
     TREE_HIP(hipGetLastError());
-    // 3. octree, level by level
-    if (t.node_cap < 1) {
-        const long long cap = std::max(1024, n / 2 + 1024);
-        long long dummy = 0;
-        TREE_ALLOC(grow(&t.begin, &dummy, cap) && grow(&t.count, &dummy, cap) &&
-                   grow(&t.level, &dummy, cap) && grow(&t.first_child, &dummy, cap) &&
-                   grow(&t.n_child, &dummy, cap) && grow(&t.parent, &dummy, cap));
-        t.node_cap = (int)cap;
-    }
-    hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, n, t.begin, t.count, t.level, t.parent);
-    TREE_HIP(hipGetLastError());
-    int off = 0, n_level = 1, L = 0;
-    t.level_off[0] = 0;
-    for (;;) {
-        t.max_level_nodes = std::max(t.max_level_nodes, n_level);
-        if (2 * (n_level + 1) > t.nc_cap) {
-            long long cap = 2LL * std::max(n_level + 1, 1024), dummy = 0;
-            TREE_ALLOC(grow(&t.nc, &dummy, cap));
-            t.nc_cap = (int)cap;
-        }
-        int *cnt = t.nc, *scan = t.nc + (n_level + 1);
-        hipLaunchKernelGGL(k_split_count, dim3(blocks_of(n_level + 1, 256)), dim3(256), 0, s,
-                           n_level, off, L, n_leaf, t.begin, t.count, t.key, cnt, t.word);
-        TREE_HIP(hipGetLastError());
-        tb = t.tmp_bytes;
-        TREE_HIP(hipcub::DeviceScan::ExclusiveSum(t.tmp, tb, cnt, scan, n_level + 1, s));
-        int total = 0;
-        TREE_HIP(hipMemcpyAsync(&total, scan + n_level, sizeof(int), hipMemcpyDeviceToHost, s));
-        TREE_HIP(hipStreamSynchronize(s));
-        const int next_off = off + n_level;
-        if ((long long)next_off + total > t.node_cap) {
-            const long long cap = std::max<long long>((long long)t.node_cap * 3 / 2,
-                                                      (long long)next_off + total + 1024);
-            if (cap > INT_MAX) {
-                err = "tree: too many nodes";
-                return PGH_ERANGE;
-            }
-            TREE_ALLOC(grow_keep(&t.begin, next_off, cap, s) &&
-                       grow_keep(&t.count, next_off, cap, s) &&
-                       grow_keep(&t.level, next_off, cap, s) &&
-                       grow_keep(&t.first_child, next_off, cap, s) &&
-                       grow_keep(&t.n_child, next_off, cap, s) &&
-                       grow_keep(&t.parent, next_off, cap, s));
-            t.node_cap = (int)cap;
-        }
-        hipLaunchKernelGGL(k_split_write, dim3(blocks_of(n_level, 256)), dim3(256), 0, s, n_level,
-                           off, L, n_leaf, next_off, t.key, scan, t.begin, t.count, t.level,
-                           t.first_child, t.n_child, t.parent);
-        TREE_HIP(hipGetLastError());
-        t.level_off[L + 1] = next_off;  // level L is [level_off[L], level_off[L + 1])
-        if (total == 0) break;
-        off = next_off;
-        n_level = total;
-        ++L;
-    }
-    t.depth = L;
-    t.n_nodes = t.level_off[L + 1];
-    // 4. moments bottom-up, then pseudo-particles
-    if (t.n_nodes > t.pp_cap) {  // mom, com: pp_cap entries; pp: 3 pp_cap
-        const long long cap = (long long)t.n_nodes * 3 / 2 + 1024;
-        long long dummy = 0;
-        TREE_ALLOC(grow(&t.mom, &dummy, cap) && grow(&t.com, &dummy, cap) &&
-                   grow(&t.pp, &dummy, 3 * cap) && grow(&t.nrec, &dummy, cap));
-        t.pp_cap = (int)cap;
-    }
-    for (int l = t.depth; l >= 0; --l) {
-        const int o = t.level_off[l], k = t.level_off[l + 1] - o;
-        hipLaunchKernelGGL(k_moments, dim3(blocks_of(k, 256)), dim3(256), 0, s, k, o, t.begin,
-                           t.count, t.first_child, t.n_child, t.xs, t.ys, t.zs, t.ms, t.mom);
-    }
-    hipLaunchKernelGGL(k_pseudo, dim3(blocks_of(t.n_nodes, 256)), dim3(256), 0, s, t.n_nodes,
-                       t.mom, t.quad, t.pp, t.com);
-    hipLaunchKernelGGL(k_pack_nodes, dim3(blocks_of(t.n_nodes, 256)), dim3(256), 0, s, t.n_nodes,
-                       t.begin, t.count, t.first_child, t.n_child, t.level, t.nrec);
-    TREE_HIP(hipGetLastError());
-    // 5. groups in key order
-    hipLaunchKernelGGL(k_fill_int, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, t.mark, -1);
-    hipLaunchKernelGGL(k_group_mark, dim3(blocks_of(t.n_nodes, 256)), dim3(256), 0, s, t.n_nodes,
-                       t.begin, t.count, t.n_child, t.parent, n_crit, t.mark);
-    TREE_HIP(hipGetLastError());
-    if (n > t.group_cap) {
+    // 3-5. octree, moments, pseudo-particles and groups, launched with no
+    // wait: the level sizes stay in a device table (lvl).  The node arrays
+    // start at 2n (a tree needs about n / 2 with leaves of 8); a build that
+    // outgrows them sets the overflow word, returns from every later kernel,
+    // and runs again with twice the room.
+    if (t.group_cap < n) {
         const long long cap = std::max(n, 1024);
         long long dummy = 0;
         TREE_ALLOC(grow(&t.groups, &dummy, cap) && grow(&t.glo, &dummy, cap) &&
@@ -882,17 +910,97 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
                    grow(&t.goff, &dummy, cap + 1) && grow(&t.items, &dummy, cap));
         t.group_cap = (int)cap;
     }
-    tb = t.tmp_bytes;
-    TREE_HIP(hipcub::DeviceSelect::If(t.tmp, tb, t.mark, t.groups, t.count_out, n, NonNegative(),
-                                      s));
-    unsigned leaves = 0;
-    TREE_HIP(hipMemcpyAsync(&t.n_groups, t.count_out, sizeof(int), hipMemcpyDeviceToHost, s));
-    TREE_HIP(hipMemcpyAsync(&leaves, t.word + 6, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-    TREE_HIP(hipStreamSynchronize(s));
-    t.n_leaves = (int)leaves;
-    hipLaunchKernelGGL(k_group_info, dim3(blocks_of(t.n_groups, 4)), dim3(256), 0, s, t.n_groups,
-                       t.groups, t.begin, t.count, t.xs, t.ys, t.zs, t.glo, t.ghi, t.items);
-    TREE_HIP(hipGetLastError());
+    if (t.nc_cap < 2 * (n + 1) + kScanBlocks + 1) {  // counts, scan, chunk sums
+        long long dummy = 0;
+        const long long cap = 2LL * (std::max(n, 1024) + 1) + kScanBlocks + 1;
+        TREE_ALLOC(grow(&t.nc, &dummy, cap));
+        t.nc_cap = (int)cap;
+    }
+    long long want = std::max<long long>(2LL * n + 64, 4096);
+    for (;;) {
+        if (want > INT_MAX) {
+            err = "tree: too many nodes";
+            return PGH_ERANGE;
+        }
+        if (t.node_cap < want) {
+            const long long cap = want;
+            long long dummy = 0;
+            TREE_ALLOC(grow(&t.begin, &dummy, cap) && grow(&t.count, &dummy, cap) &&
+                       grow(&t.level, &dummy, cap) && grow(&t.first_child, &dummy, cap) &&
+                       grow(&t.n_child, &dummy, cap) && grow(&t.parent, &dummy, cap) &&
+                       grow(&t.mom, &dummy, cap) && grow(&t.com, &dummy, cap) &&
+                       grow(&t.pp, &dummy, 3 * cap) && grow(&t.nrec, &dummy, cap));
+            t.node_cap = (int)cap;
+        }
+        const int cap = t.node_cap;
+        hipLaunchKernelGGL(k_init_words, dim3(1), dim3(64), 0, s, t.word);
+        hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, n, t.begin, t.count, t.level, t.parent,
+                           t.lvl);
+        TREE_HIP(hipGetLastError());
+        // level L has at most min(n, 8^L) nodes: the scan's length
+        auto level_bound = [&](int L) {
+            long long b = 1;
+            for (int k = 0; k < L && b < n; ++k) b *= 8;
+            return (int)std::min<long long>(b, n);
+        };
+        int *cnt = t.nc, *scan = t.nc + (n + 1), *bsum = t.nc + 2 * (n + 1);
+        for (int L = 0; L <= kTreeMaxLevel; ++L) {
+            const int grid = std::min(blocks_of(level_bound(L), 256), 16 * num_cu);
+            hipLaunchKernelGGL(k_split_count, dim3(grid), dim3(256), 0, s, L, n_leaf, t.lvl,
+                               t.begin, t.count, t.key, cnt, t.word);
+            hipLaunchKernelGGL(k_scan_sums, dim3(kScanBlocks), dim3(256), 0, s, L, t.lvl, t.word,
+                               cnt, bsum);
+            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, t.word, bsum);
+            hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(256), 0, s, L, t.lvl, t.word,
+                               cnt, bsum, scan);
+            hipLaunchKernelGGL(k_split_write, dim3(grid), dim3(256), 0, s, L, n_leaf, cap, t.lvl,
+                               t.key, scan, t.begin, t.count, t.level, t.first_child, t.n_child,
+                               t.parent, t.word);
+            TREE_HIP(hipGetLastError());
+        }
+        for (int L = kTreeMaxLevel; L >= 0; --L) {
+            const int grid = std::min(blocks_of(level_bound(L), 256), 16 * num_cu);
+            hipLaunchKernelGGL(k_moments, dim3(grid), dim3(256), 0, s, L, t.lvl, t.word, t.begin,
+                               t.count, t.first_child, t.n_child, t.xs, t.ys, t.zs, t.ms, t.mom);
+        }
+        const int gnodes = std::min(blocks_of(cap, 256), 16 * num_cu);
+        hipLaunchKernelGGL(k_pseudo, dim3(gnodes), dim3(256), 0, s, t.lvl, t.word, t.mom, t.quad,
+                           t.pp, t.com);
+        hipLaunchKernelGGL(k_pack_nodes, dim3(gnodes), dim3(256), 0, s, t.lvl, t.word, t.begin,
+                           t.count, t.first_child, t.n_child, t.level, t.nrec);
+        hipLaunchKernelGGL(k_fill_int, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, t.mark, -1);
+        hipLaunchKernelGGL(k_group_mark, dim3(gnodes), dim3(256), 0, s, t.lvl, t.word, t.begin,
+                           t.count, t.n_child, t.parent, n_crit, t.mark);
+        TREE_HIP(hipGetLastError());
+        tb = t.tmp_bytes;
+        TREE_HIP(hipcub::DeviceSelect::If(t.tmp, tb, t.mark, t.groups, t.count_out, n,
+                                          NonNegative(), s));
+        hipLaunchKernelGGL(k_group_info, dim3(std::min(blocks_of(n, 4), 16 * num_cu)), dim3(256), 0,
+                           s, t.count_out, t.groups, t.begin, t.count, t.xs, t.ys, t.zs, t.glo,
+                           t.ghi, t.items);
+        TREE_HIP(hipGetLastError());
+        // the one wait of the build: sizes and flags
+        int lv[kLvl];
+        unsigned wv2[16];
+        TREE_HIP(hipMemcpyAsync(lv, t.lvl, sizeof lv, hipMemcpyDeviceToHost, s));
+        TREE_HIP(hipMemcpyAsync(wv2, t.word, sizeof wv2, hipMemcpyDeviceToHost, s));
+        TREE_HIP(hipMemcpyAsync(&t.n_groups, t.count_out, sizeof(int), hipMemcpyDeviceToHost, s));
+        TREE_HIP(hipStreamSynchronize(s));
+        if (wv2[kWordOverflow]) {
+            want = 2LL * cap;
+            continue;
+        }
+        t.n_nodes = lv[kTreeMaxLevel + 1];
+        t.depth = 0;
+        for (int L = 0; L <= kTreeMaxLevel; ++L) {
+            t.level_off[L] = lv[L];
+            if (lv[L + 1] > lv[L]) t.depth = L;
+        }
+        t.level_off[kTreeMaxLevel + 1] = lv[kTreeMaxLevel + 1];
+        t.n_leaves = (int)wv2[kWordLeaves];
+        t.max_level_nodes = std::max(1, (int)wv2[kWordMaxLevel]);
+        break;
+    }
     t.built = 1;
     return PGH_OK;
 }

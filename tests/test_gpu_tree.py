@@ -442,3 +442,34 @@ def test_lists_beyond_int32_are_an_error(pgh, ctx):
     t.walk(0.75)
     assert 0 < t.stats()["n_entries"] < 2 ** 31
     t.free()
+
+
+def test_deep_chains_grow_the_node_arrays(pgh, ctx):
+    """500 tight pairs with leaves of one particle: every pair hangs from a
+    chain of single-child nodes down to level 20 or 21, some 10^4 nodes for
+    10^3 particles, more than the node arrays first hold (2n), so the build
+    runs again with more room; the tree still matches the oracle's."""
+    rng = np.random.default_rng(360)
+    c = rng.random((500, 3))
+    off = rng.standard_normal((500, 3)) * 1e-6
+    p = np.concatenate([c, c + off]).astype(np.float32)
+    x, y, z = p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy()
+    m = synth.equal_masses(1000)
+    t, _ = _build(ctx, x, y, z, m, 1, 1, False)
+    o = oracle.tree_build(x, y, z, m, n_leaf=1)
+    assert o.n_nodes > 2 * 1000 + 64
+    assert t.stats()["n_nodes"] == o.n_nodes
+    for f, ref in (("node_begin", o.begin), ("node_count", o.count), ("node_level", o.level),
+                   ("node_first_child", o.first_child), ("node_parent", o.parent)):
+        assert np.array_equal(t.get(f), ref), f
+    assert np.array_equal(t.get("groups"), o.find_groups(1))
+    ctx.set_eps_to_all(1e-3)
+    t.walk(0.75)
+    got = np.stack(to_host(*t.newton()))[:, o.perm]
+    items = t.get("items")
+    lists = [t.get(f).astype(np.float64) for f in ("list_x", "list_y", "list_z", "list_m")]
+    e2 = np.full(1000, float(np.float32(1e-3)) ** 2)
+    ref = np.stack(oracle.newton_items(items, o.x, o.y, o.z, e2, *lists))
+    ea = rel_vec_err(got[:3], ref[:3])
+    assert rms(ea) <= 1e-5 and ea.max() <= 1e-3
+    t.free()
