@@ -319,3 +319,68 @@ def test_two_contexts_on_two_streams(pgh):
         assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, (key, rms(ea), ea.max())
     ca.close()
     cb.close()
+
+
+def _random_items(rng, n_items, ni_max, nj_max, long_frac):
+    """Items in random order over disjoint i-ranges with gaps, j-ranges
+    anywhere in the j-arrays (lists may share entries), some empty groups
+    and empty lists, a fraction of long lists (split into parts)."""
+    items, i_at = [], 0
+    for _ in range(n_items):
+        i_at += int(rng.integers(0, 3))
+        ni = 0 if rng.random() < 0.05 else int(rng.integers(1, ni_max + 1))
+        nj = 0 if rng.random() < 0.05 else int(rng.integers(1, nj_max + 1))
+        if rng.random() < long_frac:
+            nj = int(rng.integers(4 * nj_max, 12 * nj_max))
+        items.append((i_at, ni, 0, nj))
+        i_at += ni
+    ni_total = i_at + 5
+    nj_total = max(1, max(it[3] for it in items) + 100)
+    items = [(a, b, int(rng.integers(0, nj_total - d + 1)), d) for a, b, _, d in items]
+    order = rng.permutation(len(items))
+    return np.array(items, dtype=np.int32)[order], ni_total, nj_total
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_item_sets(pgh, ctx, seed):
+    """Random plans (group sizes 1..200, list lengths up to ~10^4, empty
+    groups and lists, shared j-entries, long lists cut into parts, several
+    device fill levels): Newton and table forces of every covered row against
+    the oracle, and uncovered rows left untouched."""
+    import torch
+    rng = np.random.default_rng(1000 + seed)
+    n_items = [3, 40, 300, 1500][seed % 4]
+    items, ni_total, nj_total = _random_items(rng, n_items, 200, 900, 0.05)
+    xi, yi, zi = (rng.random(ni_total).astype(np.float32) for _ in range(3))
+    xj, yj, zj = (rng.random(nj_total).astype(np.float32) for _ in range(3))
+    mj = rng.uniform(0.5, 1.5, nj_total).astype(np.float32) / nj_total
+    di, dj = to_dev(xi, yi, zi), to_dev(xj, yj, zj, mj)
+    eps = 0.01
+    ctx.set_eps_to_all(eps)
+    plan = ctx.plan(items, ni_total, nj_total)
+    out = [torch.full((ni_total,), 777.0, device="cuda") for _ in range(4)]
+    plan.newton(*di, *dj, out=out)
+    got = np.stack(to_host(*out))
+    e2 = np.full(ni_total, np.float32(eps) ** 2, np.float32)
+    ref = np.stack(oracle.newton_items(items, xi, yi, zi, e2, xj, yj, zj, mj))
+    covered = np.zeros(ni_total, bool)
+    for a, b, _, _ in items:
+        covered[a:a + b] = True
+    assert np.all(got[:, ~covered] == 777.0)
+    rows = covered & (ref[3] != 0)
+    ea = rel_vec_err(got[:3, rows], ref[:3, rows])
+    assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, (seed, rms(ea), ea.max())
+    ep = np.abs(got[3, rows] - ref[3, rows]) / np.abs(ref[3, rows])
+    assert rms(ep) <= 1e-5 and ep.max() <= 1e-3
+    assert np.all(got[:, covered & (ref[3] == 0)] == 0)  # empty lists give zeros
+    rcut = 0.2
+    table = ctx.build_table(4, 6, rcut, eps=rcut / 15)
+    out_t = [torch.full((ni_total,), 777.0, device="cuda") for _ in range(3)]
+    plan.table(*di, *dj, out=out_t)
+    a = np.stack(to_host(*out_t))
+    rt = oracle.lut_items(items, xi, yi, zi, xj, yj, zj, mj, 4, 6, float(np.float32(rcut)), table)
+    has = covered & (rt[3] > 0)
+    e1 = norm_vec_err(a[:, has], np.stack(rt[:3])[:, has], rt[3][has])
+    assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (seed, rms(e1), e1.max())
+    assert np.all(a[:, ~covered] == 777.0)
+    plan.free()
