@@ -473,3 +473,32 @@ def test_deep_chains_grow_the_node_arrays(pgh, ctx):
     ea = rel_vec_err(got[:3], ref[:3])
     assert rms(ea) <= 1e-5 and ea.max() <= 1e-3
     t.free()
+
+
+def test_handle_errors(pgh, ctx):
+    """A tree is used only with its own context; unknown fields, NULL
+    arguments and a second free are errors, not crashes."""
+    other = pgh.Context(0)
+    t = ctx.tree()
+    x, y, z = synth.plummer(1000, 370)
+    d = to_dev(x, y, z, synth.equal_masses(1000))
+    with pytest.raises(pgh.PGHError) as e:
+        pgh.pgh_tree_build(other.h, t.h, 1000, *d)
+    assert e.value.code == pgh.PGH_EINVAL
+    t.build(*d)
+    with pytest.raises(pgh.PGHError) as e:
+        pgh.pgh_tree_walk(other.h, t.h, 0.75)
+    assert e.value.code == pgh.PGH_EINVAL
+    cnt = pgh.ctypes.c_longlong()
+    assert pgh.lib.pgh_tree_get(ctx.h, t.h, 99, None, 0, pgh.ctypes.byref(cnt)) == pgh.PGH_ERANGE
+    assert pgh.lib.pgh_tree_build(ctx.h, None, 10, None, None, None, None, 8, 64, 0) == pgh.PGH_EINVAL
+    assert pgh.lib.pgh_tree_build(ctx.h, t.h, 10, None, None, None, None, 8, 64, 0) == pgh.PGH_EINVAL
+    assert pgh.lib.pgh_tree_stats_get(None, None) == pgh.PGH_EINVAL
+    assert pgh.lib.pgh_tree_plan(None) is None
+    assert pgh.lib.pgh_tree_free(other.h, t.h) == pgh.PGH_EINVAL  # not other's tree
+    t.free()
+    assert pgh.lib.pgh_tree_free(ctx.h, None) == pgh.PGH_OK
+    # a tree left alive is freed with its context
+    t2 = other.tree().build(*d).walk(0.75)
+    assert t2.stats()["walked"] == 1
+    other.close()
