@@ -635,8 +635,8 @@ def tree_code(torch, pgh, synth, sizes=(1 << 20, 1 << 22), n_crit=64,
     monopole and quadrupole pseudo-particles.  Wall-clock per phase, each
     call synchronous except the force (timed with events, then waited for):
     build (keys, sort, octree, moments, groups), walk (both passes and the
-    batched plan of the lists), force (batched Newton + scatter to input
-    order).  Median of 3 after one warm-up."""
+    batched plan of the lists), force (batched Newton, results written in
+    the input order).  Median of 3 after one warm-up."""
     res = {}
     ctx = pgh.Context(0)
     ctx.set_eps_to_all(1.0 / 512)

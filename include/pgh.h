@@ -412,9 +412,9 @@ PGH_API int pgh_tree_walk(pgh_ctx *c, pgh_tree *t, float theta, int record_src);
 
 /* Newton's force and raw potential on every particle from the lists of the
  * last walk, with the context's eps (pgh_set_eps_to_all): the batched kernel
- * in key order, then scattered back to the input order into ax, ay, az, phi
- * (device float[n]; phi may be NULL).  Asynchronous.  PGH_ESTATE before a
- * walk. */
+ * runs over the particles in key order and writes each result to the
+ * particle's input position in ax, ay, az, phi (device float[n]; phi may be
+ * NULL).  Asynchronous.  PGH_ESTATE before a walk. */
 PGH_API int pgh_tree_newton(pgh_ctx *c, pgh_tree *t, float *ax, float *ay, float *az,
                             float *phi);
 

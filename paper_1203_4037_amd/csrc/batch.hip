@@ -265,10 +265,11 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
 
         if (tk.n_parts <= 1) {
             if (active && ph == 0) {
-                a.ax[i] = tx;
-                a.ay[i] = ty;
-                a.az[i] = tz;
-                if (PHI) a.phi[i] = tp;
+                const int io = a.out_perm ? a.out_perm[i] : i;  // output row
+                a.ax[io] = tx;
+                a.ay[io] = ty;
+                a.az[io] = tz;
+                if (PHI) a.phi[io] = tp;
             }
         } else if (ph == 0) {
             // partial sums of one part of a split j-list; k_combine adds the
@@ -310,7 +311,7 @@ __global__ void __launch_bounds__(64) k_combine(CombineArgs a)
         s.z += v.z;
         s.w += v.w;
     }
-    const int i = ch.i_off + lane;
+    const int i = a.out_perm ? a.out_perm[ch.i_off + lane] : ch.i_off + lane;
     a.ax[i] = s.x;
     a.ay[i] = s.y;
     a.az[i] = s.z;
@@ -372,7 +373,8 @@ hipError_t launch(BatchKernel k, const BatchArgs &a0, size_t lds, int num_cu, hi
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (a.n_chunks == 0) return hipSuccess;
-    CombineArgs c{a.n_chunks, a.chunks, a.partial, a.ax, a.ay, a.az, phi ? a.phi : nullptr};
+    CombineArgs c{a.n_chunks, a.chunks, a.partial, a.ax, a.ay, a.az, phi ? a.phi : nullptr,
+                  a.out_perm};
     hipLaunchKernelGGL(k_combine, dim3(a.n_chunks), dim3(64), 0, s, c);
     return hipGetLastError();
 }

@@ -1086,11 +1086,15 @@ int pgh_tree_newton(pgh_ctx *c, pgh_tree *t, float *ax, float *ay, float *az, fl
     if (s.n == 0) return PGH_OK;
     if (!ax || !ay || !az) return fail(c, PGH_EINVAL, "NULL output array");
     DeviceGuard g(c->device);
-    st = pgh_batch_newton(c, t->plan, s.xs, s.ys, s.zs, nullptr, s.xj, s.yj, s.zj, s.mj, s.axs,
-                          s.ays, s.azs, phi ? s.phs : nullptr);
-    if (st) return st;
-    PGH_HIP(c, launch_unpermute(s.n, s.perm, s.axs, s.ays, s.azs, phi ? s.phs : nullptr, ax, ay,
-                                az, phi, c->stream));
+    // the batched kernel writes each particle's row straight to its input position
+    BatchArgs a = batch_args(c, t->plan);
+    a.xi = s.xs, a.yi = s.ys, a.zi = s.zs, a.eps2i = nullptr;
+    a.xj = s.xj, a.yj = s.yj, a.zj = s.zj, a.mj = s.mj;
+    a.ax = ax, a.ay = ay, a.az = az, a.phi = phi;
+    a.out_perm = s.perm;
+    const bool guard = !(c->eps2_all > 0.f);
+    const int v = std::max(0, c->variant[PGH_FAMILY_NEWTON_BATCH]);
+    PGH_HIP(c, launch_newton_batch(a, v, c->refine != 0, guard, c->num_cu, c->stream));
     return PGH_OK;
 }
 

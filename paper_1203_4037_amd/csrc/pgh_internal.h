@@ -65,6 +65,9 @@ struct BatchArgs {
     int E, F;
     float c, smax;
     const float2 *ptable;  // potential table (with phi), or NULL
+    // NULL, or the output row of each i-particle: row i is written to
+    // out_perm[i] (the tree's key order back to the caller's order)
+    const int *out_perm;
 };
 
 struct CombineArgs {
@@ -72,6 +75,7 @@ struct CombineArgs {
     const SplitChunk *chunks;
     const float4 *partial;
     float *ax, *ay, *az, *phi;
+    const int *out_perm;  // as in BatchArgs
 };
 
 // Copies of the table gradient that the workgroups of the adjoint add into
@@ -171,8 +175,6 @@ struct TreeState {
     float *xs = nullptr, *ys = nullptr, *zs = nullptr, *ms = nullptr;
     float4 *xm = nullptr;  // the same particles packed (x, y, z, m)
     int *mark = nullptr;  // group id at the first particle of each group, else -1
-    // sorted-order outputs of the force (scattered back through perm)
-    float *axs = nullptr, *ays = nullptr, *azs = nullptr, *phs = nullptr;
     // nodes, capacity node_cap (breadth first, each level in key order); the
     // moment, centre-of-mass and walk-record arrays have node_cap entries too,
     // the pseudo-particles 3 node_cap
@@ -224,8 +226,5 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
 int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t s,
               std::string &err);
 void tree_release(TreeState &t);
-hipError_t launch_unpermute(int n, const int *perm, const float *a, const float *b,
-                            const float *c, const float *d, float *oa, float *ob, float *oc,
-                            float *od, hipStream_t s);
 
 }  // namespace pgh

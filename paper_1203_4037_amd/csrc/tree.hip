@@ -736,22 +736,6 @@ __global__ void __launch_bounds__(256) k_items_j(int n_groups, const long long *
     items[g].n_j = (int)glen[g];
 }
 
-__global__ void __launch_bounds__(256) k_unpermute(int n, const int *__restrict__ perm,
-                                                   const float *__restrict__ a,
-                                                   const float *__restrict__ b,
-                                                   const float *__restrict__ c,
-                                                   const float *__restrict__ d, float *oa,
-                                                   float *ob, float *oc, float *od)
-{
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= n) return;
-    const int i = perm[r];
-    oa[i] = a[r];
-    ob[i] = b[r];
-    oc[i] = c[r];
-    if (od) od[i] = d[r];
-}
-
 int blocks_of(long long n, int per) { return (int)std::max(1LL, (n + per - 1) / per); }
 
 template <class T>
@@ -813,8 +797,7 @@ int ensure_tmp(TreeState &t, int n, std::string &err)
 
 void tree_release(TreeState &t)
 {
-    void *ps[] = {t.key, t.key_in, t.perm, t.iota, t.xs, t.ys, t.zs, t.ms, t.mark, t.axs,
-                  t.ays, t.azs, t.phs, t.begin, t.count, t.level, t.first_child, t.n_child,
+    void *ps[] = {t.key, t.key_in, t.perm, t.iota, t.xs, t.ys, t.zs, t.ms, t.mark, t.begin, t.count, t.level, t.first_child, t.n_child,
                   t.parent, t.nc, t.mom, t.com, t.pp, t.groups, t.glo, t.ghi, t.glen, t.goff,
                   t.items, t.xj, t.yj, t.zj, t.mj, t.src, t.tmp, t.word, t.count_out, t.rc2, t.lvl,
                   t.xm, t.nrec};
@@ -853,9 +836,7 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
                   grow(&t.perm, &dummy, cap) && grow(&t.iota, &dummy, cap) &&
                   grow(&t.xs, &dummy, cap) && grow(&t.ys, &dummy, cap) &&
                   grow(&t.zs, &dummy, cap) && grow(&t.ms, &dummy, cap) &&
-                  grow(&t.mark, &dummy, cap) && grow(&t.axs, &dummy, cap) &&
-                  grow(&t.ays, &dummy, cap) && grow(&t.azs, &dummy, cap) &&
-                  grow(&t.phs, &dummy, cap) && grow(&t.xm, &dummy, cap);
+                  grow(&t.mark, &dummy, cap) && grow(&t.xm, &dummy, cap);
         if (!ok) {
             t.n_cap = 0;
             err = "tree: device allocation failed";
@@ -1115,16 +1096,6 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
     t.interactions = inter;
     t.walked = 1;
     return PGH_OK;
-}
-
-hipError_t launch_unpermute(int n, const int *perm, const float *a, const float *b,
-                            const float *c, const float *d, float *oa, float *ob, float *oc,
-                            float *od, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_unpermute, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, perm, a, b, c, d,
-                       oa, ob, oc, od);
-    return hipGetLastError();
 }
 
 }  // namespace pgh
