@@ -431,8 +431,11 @@ typedef struct pgh_tree_stats {
 /* Counts of the last build and walk (host struct). */
 PGH_API int pgh_tree_stats_get(const pgh_tree *t, pgh_tree_stats *out);
 
-/* The plan of the last walk (owned by the tree; NULL before a walk), for
- * pgh_batch_newton / pgh_batch_table with the arrays of pgh_tree_get. */
+/* The plan of the last walk (owned by the tree; NULL before a walk and after
+ * a build), for pgh_batch_newton / pgh_batch_table with the arrays of
+ * pgh_tree_get.  Every walk writes its plan into the same object, reusing
+ * its device memory, so launches captured in a graph before a walk must be
+ * captured again after it. */
 PGH_API const pgh_plan *pgh_tree_plan(const pgh_tree *t);
 
 /* Arrays of a tree, for pgh_tree_get: element type and count. */

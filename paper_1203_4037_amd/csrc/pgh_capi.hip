@@ -21,6 +21,9 @@ struct pgh_plan {
     long long interactions;
     int n_chunks, n_slots;  // chunks whose j-list is split, and their parts
     Task *tasks;            // device, sublist-major, each sublist longest first
+    // allocated sizes (records) of tasks, partial and chunks: a plan that is
+    // filled again (a tree's, at every walk) reuses them when large enough
+    size_t tasks_cap, partial_cap, chunks_cap;
     int nq;                 // task sublists
     int q_begin[kQueues + 1];
     unsigned *queue;        // device, one counter per sublist, zero between launches
@@ -64,6 +67,10 @@ struct pgh_ctx {
     size_t scr_a_cap = 0, scr_b_cap = 0;
     std::vector<pgh_plan *> plans;
     std::vector<pgh_tree *> trees;
+    // planner output and the pinned host buffer plans are uploaded from
+    HostPlan hp;
+    void *pin = nullptr;
+    size_t pin_bytes = 0;
     std::string err;
 };
 
@@ -176,6 +183,100 @@ int zero_outputs(pgh_ctx *c, int n, float *a, float *b, float *d, float *e)
 
 }  // namespace
 
+namespace {
+
+// Grows a device array to at least n records (n + n/4 when it grows; the old
+// contents are dropped).
+template <class T>
+bool grow_records(T **buf, size_t *cap, size_t n)
+{
+    if (n <= *cap) return true;
+    (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    const size_t want = n + n / 4;
+    if (hipMalloc((void **)buf, want * sizeof(T)) != hipSuccess) {
+        *buf = nullptr;
+        return false;
+    }
+    *cap = want;
+    return true;
+}
+
+// Plans the items into p, reusing its device arrays when they are large
+// enough.  The tasks are written straight into the context's pinned buffer
+// and copied from there; waits for the stream.  On failure p keeps no tasks.
+int plan_fill(pgh_ctx *c, pgh_plan *p, int n_items, const pgh_item *items, int ni_total,
+              int nj_total)
+{
+    HostPlan &hp = c->hp;
+    {
+        std::string err;
+        const int st = plan_tasks(items, n_items, ni_total, nj_total,
+                                  batch_resident_waves(c->num_cu), hp, err);
+        if (st) return fail(c, st, err);
+    }
+    DeviceGuard g(c->device);
+    // the table adjoint's task lists belong to the previous items
+    (void)hipFree(p->jtasks);
+    (void)hipFree(p->jqueue);
+    (void)hipFree(p->itasks);
+    p->jtasks = p->itasks = nullptr;
+    p->jqueue = nullptr;
+    p->adj_built = false;
+    p->n_jtasks = p->n_itasks = 0;
+    p->n_tasks = 0;
+    p->n_chunks = 0;
+    const size_t n_t = (size_t)hp.n_tasks, n_c = hp.split.size();
+    const size_t queue_bytes = (size_t)kQueues * kQueueStride * sizeof(unsigned);
+    if (!p->queue && hipMalloc((void **)&p->queue, queue_bytes) != hipSuccess) {
+        p->queue = nullptr;
+        return fail(c, PGH_ENOMEM, "hipMalloc(queue) failed");
+    }
+    if (!grow_records(&p->tasks, &p->tasks_cap, n_t))
+        return fail(c, PGH_ENOMEM, "hipMalloc(tasks) failed");
+    if (!grow_records(&p->partial, &p->partial_cap, (size_t)hp.n_slots * 64))
+        return fail(c, PGH_ENOMEM, "hipMalloc(partial sums) failed");
+    if (!grow_records(&p->chunks, &p->chunks_cap, n_c))
+        return fail(c, PGH_ENOMEM, "hipMalloc(split chunks) failed");
+    const size_t bytes = n_t * sizeof(Task) + n_c * sizeof(SplitChunk);
+    if (bytes > c->pin_bytes) {
+        // every upload waits for the stream, so nothing reads the old buffer
+        (void)hipHostFree(c->pin);
+        c->pin = nullptr;
+        c->pin_bytes = 0;
+        const size_t want = bytes + bytes / 4;
+        if (hipHostMalloc(&c->pin, want, hipHostMallocDefault) != hipSuccess) {
+            c->pin = nullptr;
+            return fail(c, PGH_ENOMEM, "hipHostMalloc(plan upload buffer) failed");
+        }
+        c->pin_bytes = want;
+    }
+    char *pin = (char *)c->pin;
+    if (n_t) write_tasks(hp, (Task *)pin);
+    if (n_c) std::memcpy(pin + n_t * sizeof(Task), hp.split.data(), n_c * sizeof(SplitChunk));
+    if (hipMemsetAsync(p->queue, 0, queue_bytes, c->stream) != hipSuccess ||
+        (n_t && hipMemcpyAsync(p->tasks, pin, n_t * sizeof(Task), hipMemcpyHostToDevice,
+                               c->stream) != hipSuccess) ||
+        (n_c && hipMemcpyAsync(p->chunks, pin + n_t * sizeof(Task), n_c * sizeof(SplitChunk),
+                               hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, PGH_EHIP, "uploading the plan failed");
+    p->n_items = n_items;
+    p->n_tasks = (int)n_t;
+    p->nq = hp.nq;
+    std::copy(hp.q_begin, hp.q_begin + kQueues + 1, p->q_begin);
+    p->ni_total = ni_total;
+    p->nj_total = nj_total;
+    p->interactions = hp.interactions;
+    p->n_chunks = (int)n_c;
+    p->n_slots = hp.n_slots;
+    p->ordered = hp.ordered;
+    return PGH_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int pgh_version(void) { return 100; }
@@ -249,6 +350,7 @@ int pgh_close(pgh_ctx *c)
     (void)hipFree(c->tab);
     (void)hipFree(c->gcopy);
     (void)hipFree(c->ptab);
+    (void)hipHostFree(c->pin);
     delete c;
     return PGH_OK;
 }
@@ -528,69 +630,16 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     if (!c) return PGH_EINVAL;
     if (!out) return fail(c, PGH_EINVAL, "out is NULL");
     *out = nullptr;
-    static thread_local HostPlan hp;  // its vectors keep their capacity between plans
-    {
-        std::string err;
-        const int st = plan_tasks(items, n_items, ni_total, nj_total,
-                                  batch_resident_waves(c->num_cu), hp, err);
-        if (st) return fail(c, st, err);
-    }
-    const std::vector<Task> &sorted = hp.tasks;
-    const std::vector<SplitChunk> &split = hp.split;
-    const int nq = hp.nq;
-    const int *q_begin = hp.q_begin;
-    const long long inter = hp.interactions;
-    const int n_chunks = (int)split.size();
-    const int n_slots = hp.n_slots;
-    pgh_plan *p = new (std::nothrow) pgh_plan;
+    pgh_plan *p = new (std::nothrow) pgh_plan{};
     if (!p) return fail(c, PGH_ENOMEM, "out of host memory");
     p->owner = c;
-    p->n_items = n_items;
-    p->n_tasks = (int)sorted.size();
-    p->nq = nq;
-    std::copy(q_begin, q_begin + kQueues + 1, p->q_begin);
-    p->ni_total = ni_total;
-    p->nj_total = nj_total;
-    p->interactions = inter;
-    p->n_chunks = n_chunks;
-    p->n_slots = n_slots;
-    p->tasks = nullptr;
-    p->queue = nullptr;
-    p->partial = nullptr;
-    p->chunks = nullptr;
-    p->jtasks = nullptr;
-    p->jqueue = nullptr;
-    p->itasks = nullptr;
-    p->adj_built = false;
-    p->n_jtasks = p->n_itasks = 0;
-    p->ordered = hp.ordered;
-    DeviceGuard g(c->device);
-    auto cleanup = [&](int code, const char *msg) {
+    const int st = plan_fill(c, p, n_items, items, ni_total, nj_total);
+    if (st) {
+        DeviceGuard g(c->device);
         free_plan_memory(p);
         delete p;
-        return fail(c, code, msg);
-    };
-    const size_t queue_bytes = (size_t)kQueues * kQueueStride * sizeof(unsigned);
-    if (hipMalloc((void **)&p->queue, queue_bytes) != hipSuccess)
-        return cleanup(PGH_ENOMEM, "hipMalloc(queue) failed");
-    if (!sorted.empty() &&
-        hipMalloc((void **)&p->tasks, sorted.size() * sizeof(Task)) != hipSuccess)
-        return cleanup(PGH_ENOMEM, "hipMalloc(tasks) failed");
-    if (n_slots > 0 &&
-        hipMalloc((void **)&p->partial, (size_t)n_slots * 64 * sizeof(float4)) != hipSuccess)
-        return cleanup(PGH_ENOMEM, "hipMalloc(partial sums) failed");
-    if (n_chunks > 0 &&
-        hipMalloc((void **)&p->chunks, (size_t)n_chunks * sizeof(SplitChunk)) != hipSuccess)
-        return cleanup(PGH_ENOMEM, "hipMalloc(split chunks) failed");
-    if (hipMemsetAsync(p->queue, 0, queue_bytes, c->stream) != hipSuccess ||
-        (n_chunks > 0 &&
-         hipMemcpyAsync(p->chunks, split.data(), split.size() * sizeof(SplitChunk),
-                        hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
-        (!sorted.empty() &&
-         hipMemcpyAsync(p->tasks, sorted.data(), sorted.size() * sizeof(Task),
-                        hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
-        return cleanup(PGH_EHIP, "uploading the plan failed");
+        return st;
+    }
     c->plans.push_back(p);
     *out = p;
     return PGH_OK;
@@ -1040,10 +1089,6 @@ int pgh_tree_build(pgh_ctx *c, pgh_tree *t, int n, const float *x, const float *
     if (n_leaf < 1 || n_leaf > 64) return fail(c, PGH_ERANGE, "n_leaf must be in [1, 64]");
     if (n_crit < n_leaf) return fail(c, PGH_ERANGE, "n_crit must be >= n_leaf");
     DeviceGuard g(c->device);
-    if (t->plan) {
-        (void)pgh_plan_free(c, t->plan);
-        t->plan = nullptr;
-    }
     std::string err;
     st = tree_build(t->st, n, x, y, z, m, n_leaf, n_crit, quad, c->num_cu, c->stream, err);
     if (st) return fail(c, st, err);
@@ -1058,20 +1103,31 @@ int pgh_tree_walk(pgh_ctx *c, pgh_tree *t, float theta, int record_src)
     if (!t->st.built) return fail(c, PGH_ESTATE, "build the tree first");
     if (!(theta >= 0.f) || !std::isfinite(theta)) return fail(c, PGH_ERANGE, "theta must be >= 0");
     DeviceGuard g(c->device);
-    if (t->plan) {
-        (void)pgh_plan_free(c, t->plan);
+    // The tree keeps its plan from walk to walk: the plan of the new lists
+    // is written into it, reusing its device memory.
+    auto drop_plan = [&] {
+        if (t->plan) (void)pgh_plan_free(c, t->plan);
         t->plan = nullptr;
-    }
+    };
     std::string err;
     st = tree_walk(t->st, theta, record_src, c->num_cu, c->stream, err);
-    if (st) return fail(c, st, err);
+    if (st) {
+        drop_plan();
+        return fail(c, st, err);
+    }
     const TreeState &s = t->st;
     if (s.n_groups > 0) {
-        st = pgh_plan_create(c, s.n_groups, s.host_items.data(), s.n, (int)s.n_entries, &t->plan);
+        st = t->plan ? plan_fill(c, t->plan, s.n_groups, s.host_items.data(), s.n,
+                                 (int)s.n_entries)
+                     : pgh_plan_create(c, s.n_groups, s.host_items.data(), s.n,
+                                       (int)s.n_entries, &t->plan);
         if (st) {
+            drop_plan();
             t->st.walked = 0;
             return st;
         }
+    } else {
+        drop_plan();
     }
     return PGH_OK;
 }
@@ -1120,7 +1176,7 @@ int pgh_tree_stats_get(const pgh_tree *t, pgh_tree_stats *out)
     return PGH_OK;
 }
 
-const pgh_plan *pgh_tree_plan(const pgh_tree *t) { return t ? t->plan : nullptr; }
+const pgh_plan *pgh_tree_plan(const pgh_tree *t) { return t && t->st.walked ? t->plan : nullptr; }
 
 int pgh_tree_get(pgh_ctx *c, const pgh_tree *t, int field, void *dst, long long capacity,
                  long long *count)

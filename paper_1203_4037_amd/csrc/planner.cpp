@@ -54,29 +54,21 @@ void stable_order(std::vector<int> &idx, Key key, bool descending, std::vector<i
     idx.swap(out);
 }
 
-// A chunk of at most 64 i-particles of one item (js lanes per i-particle).
-struct Chunk {
-    int i_off, n_i, j_off, n_j, js;
-};
-
-// A wave's work before splitting: one chunk, or two that share the wave.
-struct Work {
-    int a, b;  // chunk indices; b < 0: a single chunk
-};
-
 // The planner's temporaries, kept between calls on a host thread: plans of
 // 10^5 tasks are rebuilt at every tree walk, and fresh vectors of that size
 // cost more in first-touch page faults than the planning itself.
 struct Scratch {
-    std::vector<int> order, cand, idx, so_start, so_out;
-    std::vector<Chunk> chunks;
-    std::vector<Work> work;
-    std::vector<Task> tasks;
-    std::vector<long long> cost, c_it;
-    std::vector<char> taken, c_taken;
+    std::vector<int> order, cand, so_start, so_out;
+    std::vector<PlanRef> refs;
+    std::vector<int> cost;
+    std::vector<long long> c_it;
+    std::vector<char> taken;
     std::vector<int> c_ni, c_nj;
-    std::vector<size_t> next_small;
+    std::vector<unsigned long long> fits, big, used;  // bit sets over the candidates
 };
+
+// ceil(n / js) for js = 1, 2 or 4 lanes per i-particle
+inline long long lane_steps(long long n, int js) { return (n + js - 1) >> (js >> 1); }
 
 Scratch &scratch()
 {
@@ -115,6 +107,10 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
                                            " and " + std::to_string(order[k]) + " overlap");
     }
 
+    out.ordered.clear();
+    out.ordered.reserve(order.size());
+    for (int t : order) out.ordered.push_back(items[t]);
+
     // Wave tasks: chunks of <= 64 i-particles; a chunk of <= 32 (<= 16) runs
     // js = 2 (4) lanes per i-particle.  When chunks of 64 fill less than half
     // of the waves the device holds (a small plan), the groups are cut into
@@ -129,7 +125,7 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
         if (n >= waves || csize == 16) break;
         csize /= 2;
     }
-    std::vector<Chunk> &chunks = S.chunks;
+    std::vector<PlanChunk> &chunks = out.chunks;
     chunks.clear();
     long long total = 0;  // wave-iterations
     for (int t : order) {
@@ -138,32 +134,65 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
             const int n = std::min(csize, it.n_i - s0);
             const int js = n <= 16 ? 4 : (n <= 32 ? 2 : 1);
             chunks.push_back({it.i_off + s0, n, it.j_off, it.n_j, js});
-            total += std::max(1LL, (long long)(it.n_j + js - 1) / js);
+            total += std::max(1LL, lane_steps(it.n_j, js));
         }
     }
     // Cut j-lists longer than an eighth of the average work of a resident
     // wave, so each wave takes several tasks and the longest-first queue
     // ends with short ones.  (Equal tasks of half a wave's work leave the
     // last round of the queue mostly idle whenever the task count is just
-    // above a multiple of the wave count.)
+    // above a multiple of the wave count.)  add_work records a wave's work
+    // (chunk a, and chunk b sharing the wave, or b < 0), its cut and its
+    // tasks with their costs (lane-iterations / 64).
     const long long part_iters = std::max(512LL, (total / waves / 8 + 63) / 64 * 64);
-    std::vector<Task> &tasks = S.tasks;
-    std::vector<long long> &cost = S.cost;
-    tasks.clear();
+    std::vector<PlanWork> &work = out.work;
+    work.clear();
+    std::vector<PlanRef> &refs = S.refs;
+    std::vector<int> &cost = S.cost;
+    refs.clear();
     cost.clear();
     std::vector<SplitChunk> &split = out.split;
     split.clear();
     int n_slots = 0;
+    auto add_work = [&](int a, int b) {
+        const int w = (int)work.size();
+        const PlanChunk &ch = chunks[a];
+        const bool pair = b >= 0;
+        const int njb_all = pair ? chunks[b].n_j : 0;
+        const int js = pair ? 1 : ch.js;
+        const int njm = std::max(ch.n_j, njb_all);
+        const long long iters = lane_steps(njm, js);
+        int parts = iters <= part_iters ? 1 : (int)((iters + part_iters - 1) / part_iters);
+        long long per = njm;
+        if (parts <= 1) {
+            work.push_back({a, b, 1, njm, 0});
+            refs.push_back({w, 0});
+            cost.push_back((int)std::max(1LL, iters));
+            return;
+        }
+        // equal parts, each a multiple of 64 j-particles except the last
+        per = (njm + parts - 1) / parts;
+        per = (per + 63) / 64 * 64;
+        parts = (int)((njm + per - 1) / per);
+        work.push_back({a, b, parts, (int)per, n_slots});
+        for (int q = 0; q < parts; ++q) {
+            const long long nja = std::max(0LL, std::min(per, ch.n_j - q * per));
+            const long long njb = pair ? std::max(0LL, std::min(per, njb_all - q * per)) : 0;
+            refs.push_back({w, q});
+            cost.push_back((int)lane_steps(std::max(nja, njb), js));
+        }
+        split.push_back({ch.i_off, ch.n_i, n_slots, parts, 0});
+        if (pair) split.push_back({chunks[b].i_off, chunks[b].n_i, n_slots, parts, ch.n_i});
+        n_slots += parts;
+    };
     // Pair partly filled chunks: in order of j-list length, each takes the
-    // first later one (within a short window) whose i-particles fit beside
+    // first later one (within a window of 64) whose i-particles fit beside
     // its own in 64 lanes, when one wavefront running the longer list costs
     // fewer lane-iterations than the two apart.  A pair is cut along j like
     // any long list (both lists at the same offsets).
-    std::vector<Work> &work = S.work;
-    work.clear();
     {
-        auto lane_iters = [](const Chunk &ch) {
-            return 64LL * std::max(1LL, (long long)(ch.n_j + ch.js - 1) / ch.js);
+        auto lane_iters = [](const PlanChunk &ch) {
+            return 64LL * std::max(1LL, lane_steps(ch.n_j, ch.js));
         };
         std::vector<char> &taken = S.taken;
         taken.assign(chunks.size(), 0);
@@ -173,117 +202,151 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
             if (chunks[k].n_i < 64 && chunks[k].n_j > 0) cand.push_back((int)k);
         stable_order(cand, [&](int k) { return (long long)chunks[k].n_j; }, false, S.so_start,
                      S.so_out);
-        // the scan reads candidates in this order: keep their fields contiguous
         const size_t nc = cand.size();
         std::vector<int> &c_ni = S.c_ni, &c_nj = S.c_nj;
         std::vector<long long> &c_it = S.c_it;
-        std::vector<char> &c_taken = S.c_taken;
         c_ni.resize(nc);
         c_nj.resize(nc);
         c_it.resize(nc);
-        c_taken.assign(nc, 0);
         for (size_t u = 0; u < nc; ++u) {
-            const Chunk &ch = chunks[cand[u]];
+            const PlanChunk &ch = chunks[cand[u]];
             c_ni[u] = ch.n_i;
             c_nj[u] = ch.n_j;
             c_it[u] = lane_iters(ch);
         }
-        // beside a chunk of more than 32 only one of at most 31 fits: such
-        // chunks scan the later small ones only (next_small skips the rest)
-        std::vector<size_t> &next_small = S.next_small;
-        next_small.assign(nc + 1, nc);
-        for (size_t v = nc; v-- > 0;) next_small[v] = c_ni[v] <= 31 ? v : next_small[v + 1];
+        // Bit sets over the candidates (in this order): fits[r] holds those
+        // of at most r i-particles, big those of more than 32 (one lane each),
+        // used those already paired.  A candidate's partners are then the
+        // set bits of fits[room] & ~used in its window, in order.  Two chunks
+        // of at most 32 (two or four lanes each) can only gain by sharing
+        // when their lists differ by at most one entry (rounding of the lane
+        // counts), so past that point a small chunk looks at big ones only.
+        const size_t nw = (nc + 63) / 64 + 1;
+        std::vector<unsigned long long> &fits = S.fits, &big = S.big, &used = S.used;
+        fits.assign(64 * nw, 0ULL);
+        big.assign(nw, 0ULL);
+        used.assign(nw, 0ULL);
+        for (size_t u = 0; u < nc; ++u) {
+            fits[(size_t)c_ni[u] * nw + u / 64] |= 1ULL << (u % 64);
+            if (c_ni[u] > 32) big[u / 64] |= 1ULL << (u % 64);
+        }
+        for (int r = 1; r < 64; ++r)
+            for (size_t w = 0; w < nw; ++w) fits[(size_t)r * nw + w] |= fits[(size_t)(r - 1) * nw + w];
+        // the bits [from, from + len) of a set, len <= 64
+        auto window = [&](const unsigned long long *set, size_t from, size_t len) {
+            const size_t w = from / 64, sh = from % 64;
+            unsigned long long m = set[w] >> sh;
+            if (sh) m |= set[w + 1] << (64 - sh);
+            return len < 64 ? m & ((1ULL << len) - 1) : m;
+        };
         constexpr size_t kWindow = 64;
         for (size_t u = 0; u < nc; ++u) {
-            if (c_taken[u]) continue;
+            if (used[u / 64] >> (u % 64) & 1) continue;
+            const size_t from = u + 1, len = std::min(nc, u + 1 + kWindow) - from;
+            if (len == 0) break;
             const int room = 64 - c_ni[u];
-            const size_t v_end = std::min(nc, u + 1 + kWindow);
-            const bool big = room <= 31;
-            for (size_t v = big ? next_small[u + 1] : u + 1; v < v_end;
-                 v = big ? next_small[v + 1] : v + 1) {
-                if (c_taken[v] || c_ni[v] > room) continue;
+            unsigned long long m = window(&fits[(size_t)room * nw], from, len) &
+                                   ~window(used.data(), from, len);
+            if (c_ni[u] <= 32) {
+                // small candidates only up to list length c_nj[u] + 1
+                const size_t near =
+                    std::upper_bound(c_nj.begin() + from, c_nj.begin() + from + len,
+                                     (long long)c_nj[u] + 1) -
+                    (c_nj.begin() + from);
+                const unsigned long long head = near < 64 ? (1ULL << near) - 1 : ~0ULL;
+                m &= head | window(big.data(), from, len);
+            }
+            for (; m; m &= m - 1) {
+                const size_t v = from + (size_t)__builtin_ctzll(m);
                 if (64LL * std::max(c_nj[u], c_nj[v]) >= c_it[u] + c_it[v]) continue;
-                c_taken[u] = c_taken[v] = 1;
+                used[u / 64] |= 1ULL << (u % 64);
+                used[v / 64] |= 1ULL << (v % 64);
                 taken[cand[u]] = taken[cand[v]] = 1;
-                work.push_back({cand[u], cand[v]});
+                add_work(cand[u], cand[v]);
                 break;
             }
         }
         for (size_t k = 0; k < chunks.size(); ++k)
-            if (!taken[k]) work.push_back({(int)k, -1});
+            if (!taken[k]) add_work((int)k, -1);
     }
-    static const Chunk kNone{0, 0, 0, 0, 1};
-    for (const Work &wk : work) {
-        const Chunk &ch = chunks[wk.a];
-        const bool pair = wk.b >= 0;
-        struct {
-            const Chunk &b;
-        } w{pair ? chunks[wk.b] : kNone};
-        const int js = pair ? 1 : ch.js;
-        const int njm = pair ? std::max(ch.n_j, w.b.n_j) : ch.n_j;
-        const long long iters = (njm + js - 1) / js;
-        int parts = (int)std::max(1LL, (iters + part_iters - 1) / part_iters);
-        long long per = njm;
-        if (parts > 1) {
-            // equal parts, each a multiple of 64 j-particles except the last
-            per = (njm + parts - 1) / parts;
-            per = (per + 63) / 64 * 64;
-            parts = (int)((njm + per - 1) / per);
-        }
-        auto cut = [&](int n_j, int q) {
-            return (int)std::max(0LL, std::min<long long>(per, n_j - q * per));
-        };
-        // where part q starts in a list of n_j entries (its end for the
-        // empty parts of the shorter list of a pair)
-        auto start = [&](int n_j, int q) { return (int)std::min<long long>((long long)q * per, n_j); };
-        if (parts <= 1) {
-            tasks.push_back({ch.i_off, ch.n_i, ch.j_off, ch.n_j, 0, 1, 0, w.b.i_off, w.b.n_i,
-                             w.b.j_off, w.b.n_j, 0});
-            cost.push_back(std::max(1LL, iters));
-            continue;
-        }
-        for (int q = 0; q < parts; ++q) {
-            const int nja = cut(ch.n_j, q), njb = pair ? cut(w.b.n_j, q) : 0;
-            tasks.push_back({ch.i_off, ch.n_i, ch.j_off + start(ch.n_j, q), nja, q, parts, n_slots,
-                             w.b.i_off, w.b.n_i, w.b.j_off + (pair ? start(w.b.n_j, q) : 0), njb,
-                             0});
-            cost.push_back((std::max(nja, njb) + js - 1) / js);
-        }
-        split.push_back({ch.i_off, ch.n_i, n_slots, parts, 0});
-        if (pair) split.push_back({w.b.i_off, w.b.n_i, n_slots, parts, ch.n_i});
-        n_slots += parts;
-    }
-    // longest tasks first
-    std::vector<int> &idx = S.idx;
-    idx.resize(tasks.size());
-    for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
-    stable_order(idx, [&](int k) { return cost[k]; }, true, S.so_start, S.so_out);
-    // Deal the longest-first list into nq sublists, a group of kBatchWaves
+    // Longest tasks first, dealt into nq sublists a group of kBatchWaves
     // consecutive tasks at a time, round-robin: each sublist stays longest
     // first with an equal share of every size class, and workgroup b (which
     // serves sublist b mod nq) takes tasks 4b .. 4b+3 of the whole list in
     // its first round, one of similar length per SIMD.
-    const int nq = (int)std::min<size_t>(
-        kQueues, std::max<size_t>(1, (idx.size() + kBatchWaves - 1) / kBatchWaves));
-    std::vector<Task> &sorted = out.tasks;
-    sorted.clear();
+    const size_t n = refs.size();
+    const int nq = (int)std::min<size_t>(kQueues, std::max<size_t>(1, (n + kBatchWaves - 1) / kBatchWaves));
     int *q_begin = out.q_begin;
     std::fill(q_begin, q_begin + kQueues + 1, 0);
-    for (int q = 0; q < nq; ++q) {
-        q_begin[q] = (int)sorted.size();
-        for (size_t g0 = (size_t)q * kBatchWaves; g0 < idx.size(); g0 += (size_t)nq * kBatchWaves)
-            for (size_t k = g0; k < std::min(idx.size(), g0 + kBatchWaves); ++k)
-                sorted.push_back(tasks[idx[k]]);
+    {
+        // sublist q holds the groups g = q, q + nq, ...; only the last group
+        // of all may be partial
+        const size_t groups = (n + kBatchWaves - 1) / kBatchWaves;
+        for (int q = 0; q < nq; ++q) {
+            size_t size = (groups / nq + ((size_t)q < groups % nq ? 1 : 0)) * kBatchWaves;
+            if (groups > 0 && (size_t)q == (groups - 1) % nq) size -= groups * kBatchWaves - n;
+            q_begin[q + 1] = q_begin[q] + (int)size;
+        }
     }
-    q_begin[nq] = (int)sorted.size();
+    // the final position of the task of rank r in the longest-first order
+    // (all kQueues sublists in use unless the plan is tiny: shifts, not divisions)
+    const bool all_q = nq == kQueues;
+    auto place = [&](size_t r) {
+        const size_t g = r / kBatchWaves;
+        const size_t q = all_q ? g % kQueues : g % nq, row = all_q ? g / kQueues : g / nq;
+        return (size_t)q_begin[q] + row * kBatchWaves + r % kBatchWaves;
+    };
+    std::vector<PlanRef> &dealt = out.dealt;
+    dealt.resize(n);
+    int kmax = 0;
+    for (int c : cost) kmax = std::max(kmax, c);
+    const bool small = kmax <= (1 << 22);
+    if (small) {
+        // stable counting sort, longest first, scattered straight to the
+        // dealt positions
+        std::vector<int> &start = S.so_start;
+        start.assign((size_t)kmax + 2, 0);
+        for (int c : cost) ++start[(size_t)(kmax - c) + 1];
+        for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
+        for (size_t k = 0; k < n; ++k) dealt[place((size_t)start[(size_t)(kmax - cost[k])]++)] = refs[k];
+    } else {
+        std::vector<int> &idx = S.order;  // the item order is no longer needed below
+        idx.resize(n);
+        for (size_t k = 0; k < n; ++k) idx[k] = (int)k;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        for (size_t r = 0; r < n; ++r) dealt[place(r)] = refs[idx[r]];
+    }
+    q_begin[nq] = (int)n;
 
+    out.n_tasks = (int)n;
     out.nq = nq;
     out.n_slots = n_slots;
     out.interactions = inter;
-    out.ordered.clear();
-    out.ordered.reserve(order.size());
-    for (int t : order) out.ordered.push_back(items[t]);
     return PGH_OK;
+}
+
+void write_tasks(const HostPlan &hp, Task *dst)
+{
+    const std::vector<PlanChunk> &chunks = hp.chunks;
+    for (size_t k = 0; k < hp.dealt.size(); ++k) {
+        const PlanRef &r = hp.dealt[k];
+        const PlanWork &wk = hp.work[r.work];
+        const PlanChunk &a = chunks[wk.a];
+        const bool pair = wk.b >= 0;
+        static const PlanChunk kNone{0, 0, 0, 0, 1};
+        const PlanChunk &b = pair ? chunks[wk.b] : kNone;
+        if (wk.parts <= 1) {
+            dst[k] = {a.i_off, a.n_i, a.j_off, a.n_j, 0, 1, 0, b.i_off, b.n_i, b.j_off, b.n_j, 0};
+            continue;
+        }
+        // part q starts at q * per (at the list's end for the empty parts of
+        // the shorter list of a pair)
+        const long long per = wk.per, q = r.part;
+        auto cut = [&](int n_j) { return (int)std::max(0LL, std::min(per, n_j - q * per)); };
+        auto start = [&](int n_j) { return (int)std::min(q * per, (long long)n_j); };
+        dst[k] = {a.i_off, a.n_i, a.j_off + start(a.n_j), cut(a.n_j), r.part, wk.parts, wk.slot,
+                  b.i_off, b.n_i, b.j_off + (pair ? start(b.n_j) : 0), pair ? cut(b.n_j) : 0, 0};
+    }
 }
 
 void plan_adjoint_tasks(const std::vector<pgh_item> &ordered, int waves, std::vector<Task> &out_j,

@@ -1022,12 +1022,16 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
     a.goff = t.goff;
     a.overflow = t.word + 7;
     a.max_frontier = t.word + 8;
-    // Pass 1 with the small frontier (LDS for 2 walking waves per SIMD); if
-    // a group's frontier outgrows it, again with the large one (1 per SIMD).
+    // Pass 1 counts the lists; their scan, the items and the status words
+    // come back to the host in one wait.  It runs with the small frontier
+    // (LDS for 2 walking waves per SIMD); if a group's frontier outgrew it,
+    // it runs again with the large one (1 per SIMD).
     const int grid_small = std::min(blocks_of(t.n_groups, kWalkWaves), 4 * num_cu);
     const int grid_large = std::min(blocks_of(t.n_groups, kWalkWaves), 2 * num_cu);
     bool large = false;
     unsigned over = 0, maxf = 0;
+    long long total = 0;
+    t.host_items.resize(t.n_groups);
     for (;;) {
         if (large)
             hipLaunchKernelGGL((k_walk<false, kWalkFrontier>), dim3(grid_large),
@@ -1036,7 +1040,18 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
             hipLaunchKernelGGL((k_walk<false, kWalkFrontier / 2>), dim3(grid_small),
                                dim3(64 * kWalkWaves), 0, s, a);
         TREE_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_tail_zero, dim3(1), dim3(1), 0, s, t.glen + t.n_groups);
+        TREE_HIP(hipGetLastError());
+        size_t tb = t.tmp_bytes;
+        TREE_HIP(hipcub::DeviceScan::ExclusiveSum(t.tmp, tb, t.glen, t.goff, t.n_groups + 1, s));
+        hipLaunchKernelGGL(k_items_j, dim3(blocks_of(t.n_groups, 256)), dim3(256), 0, s,
+                           t.n_groups, t.goff, t.glen, t.items);
+        TREE_HIP(hipGetLastError());
         TREE_HIP(hipMemcpyAsync(&over, t.word + 7, sizeof over, hipMemcpyDeviceToHost, s));
+        TREE_HIP(hipMemcpyAsync(&maxf, t.word + 8, sizeof maxf, hipMemcpyDeviceToHost, s));
+        TREE_HIP(hipMemcpyAsync(&total, t.goff + t.n_groups, sizeof total, hipMemcpyDeviceToHost, s));
+        TREE_HIP(hipMemcpyAsync(t.host_items.data(), t.items, sizeof(pgh_item) * t.n_groups,
+                                hipMemcpyDeviceToHost, s));
         TREE_HIP(hipStreamSynchronize(s));
         if (!over || large) break;
         large = true;
@@ -1047,14 +1062,6 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
               " nodes (theta too small for this tree)";
         return PGH_ERANGE;
     }
-    hipLaunchKernelGGL(k_tail_zero, dim3(1), dim3(1), 0, s, t.glen + t.n_groups);
-    TREE_HIP(hipGetLastError());
-    size_t tb = t.tmp_bytes;
-    TREE_HIP(hipcub::DeviceScan::ExclusiveSum(t.tmp, tb, t.glen, t.goff, t.n_groups + 1, s));
-    long long total = 0;
-    TREE_HIP(hipMemcpyAsync(&total, t.goff + t.n_groups, sizeof total, hipMemcpyDeviceToHost, s));
-    TREE_HIP(hipMemcpyAsync(&maxf, t.word + 8, sizeof maxf, hipMemcpyDeviceToHost, s));
-    TREE_HIP(hipStreamSynchronize(s));
     t.max_frontier = (int)maxf;
     if (total > INT_MAX) {
         err = "tree walk: the lists exceed 2^31 - 1 entries";
@@ -1071,16 +1078,8 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
         const long long cap = total + total / 4 + 1024;
         TREE_ALLOC(grow(&t.src, &t.src_cap, cap));
     }
-    // The items are complete once the lists are counted: they go to the host
-    // now, and the writing pass runs while the caller plans the batched
-    // launch from them (the plan's upload is ordered after it on the stream).
-    hipLaunchKernelGGL(k_items_j, dim3(blocks_of(t.n_groups, 256)), dim3(256), 0, s, t.n_groups,
-                       t.goff, t.glen, t.items);
-    TREE_HIP(hipGetLastError());
-    t.host_items.resize(t.n_groups);
-    TREE_HIP(hipMemcpyAsync(t.host_items.data(), t.items, sizeof(pgh_item) * t.n_groups,
-                            hipMemcpyDeviceToHost, s));
-    TREE_HIP(hipStreamSynchronize(s));
+    // The writing pass runs while the caller plans the batched launch from
+    // the items (the plan's upload is ordered after it on the stream).
     a.xj = t.xj, a.yj = t.yj, a.zj = t.zj, a.mj = t.mj;
     a.src = record_src ? t.src : nullptr;
     if (large)

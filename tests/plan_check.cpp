@@ -104,7 +104,8 @@ void check_plan(const std::vector<pgh_item> &items, int ni_total, int nj_total, 
     long long inter = 0;
     for (const pgh_item &it : items) inter += (long long)it.n_i * it.n_j;
     if (inter != hp.interactions) fail(std::string(what) + ": interaction count");
-    const std::vector<Task> &T = hp.tasks;
+    std::vector<Task> T(hp.n_tasks);
+    write_tasks(hp, T.data());
     if (!T.empty()) {
         if (hp.nq < 1 || hp.nq > kQueues) fail(std::string(what) + ": sublist count");
         if (hp.q_begin[0] != 0 || hp.q_begin[hp.nq] != (int)T.size())

@@ -272,6 +272,35 @@ def test_rebuild_smaller_and_larger(pgh, ctx):
     t.free()
 
 
+def test_rewalk_refills_the_plan(pgh, ctx):
+    """Walks of one build with a wider and a narrower opening angle write
+    their plans into the same plan object (grown, then reused); a build
+    hides the plan until the next walk.  Each walk's force matches the
+    oracle's sum over the lists it wrote."""
+    n = 20000
+    x, y, z = synth.plummer(n, 340)
+    m = synth.equal_masses(n)
+    ctx.set_eps_to_all(0.02)
+    t = ctx.tree().build(*to_dev(x, y, z, m), n_leaf=8, n_crit=64)
+    o = oracle.tree_build(x, y, z, m, n_leaf=8)
+    plan = None
+    for theta in (0.9, 0.3, 0.75):
+        t.walk(theta)
+        p = pgh.lib.pgh_tree_plan(t.h)
+        assert p is not None and (plan is None or p == plan)
+        plan = p
+        got = np.stack(to_host(*t.newton()))[:, o.perm]
+        items = t.get("items")
+        lists = [t.get(f).astype(np.float64) for f in ("list_x", "list_y", "list_z", "list_m")]
+        e2 = np.full(n, float(np.float32(0.02)) ** 2)
+        ref = np.stack(oracle.newton_items(items, o.x, o.y, o.z, e2, *lists))
+        ea = rel_vec_err(got[:3], ref[:3])
+        assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, theta
+    t.build(*to_dev(x, y, z, m), n_leaf=8, n_crit=64)
+    assert pgh.lib.pgh_tree_plan(t.h) is None
+    t.free()
+
+
 def test_errors(pgh, ctx):
     import torch
     t = ctx.tree()
