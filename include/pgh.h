@@ -405,6 +405,9 @@ PGH_API int pgh_tree_build(pgh_ctx *c, pgh_tree *t, int n, const float *x, const
 /* Walks the tree for every group with opening parameter theta >= 0 and
  * writes the lists (device memory owned by the tree) and a batched plan for
  * them.  record_src != 0 also keeps each entry's source (PGH_TREE_LIST_SRC).
+ * The plan is made in compact form on the host (one entry per group or pair
+ * of partly filled chunks) and expanded into its tasks on the device; it
+ * holds the same tasks as pgh_plan_create would make from the lists.
  * Synchronous.  PGH_ESTATE before a build; PGH_ERANGE when theta is too
  * small for the walk's frontier (more than 4096 nodes to test on one level
  * for one group) or the lists exceed 2^31 - 1 entries. */

@@ -38,6 +38,13 @@ struct pgh_plan {
     int n_itasks;           // i-major tasks of the table adjoint (i-side positions)
     Task *itasks;           // device
     unsigned *jqueue;       // device, counter of the j-major tasks
+    // device expansion of the compact form (tree plans): the entries, the
+    // sort keys and task indices (and their sorted copies), sort temp storage
+    PlanDesc *desc;
+    unsigned *keys, *keys_out;
+    int *vals, *order;
+    void *sort_temp;
+    size_t desc_cap, keys_cap, keys_out_cap, vals_cap, order_cap, sort_temp_cap;
 };
 
 struct pgh_ctx {
@@ -69,6 +76,7 @@ struct pgh_ctx {
     std::vector<pgh_tree *> trees;
     // planner output and the pinned host buffer plans are uploaded from
     HostPlan hp;
+    DescPlan dp;
     void *pin = nullptr;
     size_t pin_bytes = 0;
     std::string err;
@@ -138,6 +146,12 @@ void free_plan_memory(pgh_plan *p)
     (void)hipFree(p->jtasks);
     (void)hipFree(p->jqueue);
     (void)hipFree(p->itasks);
+    (void)hipFree(p->desc);
+    (void)hipFree(p->keys);
+    (void)hipFree(p->keys_out);
+    (void)hipFree(p->vals);
+    (void)hipFree(p->order);
+    (void)hipFree(p->sort_temp);
 }
 
 // Grows a scratch buffer of float4 records (synchronises before freeing).
@@ -203,9 +217,76 @@ bool grow_records(T **buf, size_t *cap, size_t n)
     return true;
 }
 
-// Plans the items into p, reusing its device arrays when they are large
-// enough.  The tasks are written straight into the context's pinned buffer
-// and copied from there; waits for the stream.  On failure p keeps no tasks.
+// Drops what a plan holds for its previous items before it is filled
+// again: the table adjoint's task lists and the task counts.
+void reset_plan(pgh_plan *p)
+{
+    (void)hipFree(p->jtasks);
+    (void)hipFree(p->jqueue);
+    (void)hipFree(p->itasks);
+    p->jtasks = p->itasks = nullptr;
+    p->jqueue = nullptr;
+    p->adj_built = false;
+    p->n_jtasks = p->n_itasks = 0;
+    p->n_tasks = 0;
+    p->n_chunks = 0;
+}
+
+// The context's pinned upload buffer, at least `bytes` long.  Every upload
+// from it waits for the stream, so nothing reads the old buffer.
+int ensure_pinned(pgh_ctx *c, size_t bytes)
+{
+    if (bytes <= c->pin_bytes) return PGH_OK;
+    (void)hipHostFree(c->pin);
+    c->pin = nullptr;
+    c->pin_bytes = 0;
+    const size_t want = bytes + bytes / 4;
+    if (hipHostMalloc(&c->pin, want, hipHostMallocDefault) != hipSuccess) {
+        c->pin = nullptr;
+        return fail(c, PGH_ENOMEM, "hipHostMalloc(plan upload buffer) failed");
+    }
+    c->pin_bytes = want;
+    return PGH_OK;
+}
+
+// The device arrays every plan has: the sublist counters, tasks, partial
+// sums and split chunks.
+int ensure_plan_arrays(pgh_ctx *c, pgh_plan *p, size_t n_tasks, size_t n_slots, size_t n_split)
+{
+    const size_t queue_bytes = (size_t)kQueues * kQueueStride * sizeof(unsigned);
+    if (!p->queue && hipMalloc((void **)&p->queue, queue_bytes) != hipSuccess) {
+        p->queue = nullptr;
+        return fail(c, PGH_ENOMEM, "hipMalloc(queue) failed");
+    }
+    if (!grow_records(&p->tasks, &p->tasks_cap, n_tasks))
+        return fail(c, PGH_ENOMEM, "hipMalloc(tasks) failed");
+    if (!grow_records(&p->partial, &p->partial_cap, n_slots * 64))
+        return fail(c, PGH_ENOMEM, "hipMalloc(partial sums) failed");
+    if (!grow_records(&p->chunks, &p->chunks_cap, n_split))
+        return fail(c, PGH_ENOMEM, "hipMalloc(split chunks) failed");
+    return PGH_OK;
+}
+
+void set_plan_counts(pgh_plan *p, int n_items, int ni_total, int nj_total, int n_tasks, int nq,
+                     const int *q_begin, long long interactions, int n_split, int n_slots,
+                     const std::vector<pgh_item> &ordered)
+{
+    p->n_items = n_items;
+    p->n_tasks = n_tasks;
+    p->nq = nq;
+    std::copy(q_begin, q_begin + kQueues + 1, p->q_begin);
+    p->ni_total = ni_total;
+    p->nj_total = nj_total;
+    p->interactions = interactions;
+    p->n_chunks = n_split;
+    p->n_slots = n_slots;
+    p->ordered = ordered;
+}
+
+// Plans the items into p on the host, reusing its device arrays when they
+// are large enough.  The tasks are written straight into the context's
+// pinned buffer and copied from there; waits for the stream.  On failure p
+// keeps no tasks.
 int plan_fill(pgh_ctx *c, pgh_plan *p, int n_items, const pgh_item *items, int ni_total,
               int nj_total)
 {
@@ -217,61 +298,86 @@ int plan_fill(pgh_ctx *c, pgh_plan *p, int n_items, const pgh_item *items, int n
         if (st) return fail(c, st, err);
     }
     DeviceGuard g(c->device);
-    // the table adjoint's task lists belong to the previous items
-    (void)hipFree(p->jtasks);
-    (void)hipFree(p->jqueue);
-    (void)hipFree(p->itasks);
-    p->jtasks = p->itasks = nullptr;
-    p->jqueue = nullptr;
-    p->adj_built = false;
-    p->n_jtasks = p->n_itasks = 0;
-    p->n_tasks = 0;
-    p->n_chunks = 0;
+    reset_plan(p);
     const size_t n_t = (size_t)hp.n_tasks, n_c = hp.split.size();
-    const size_t queue_bytes = (size_t)kQueues * kQueueStride * sizeof(unsigned);
-    if (!p->queue && hipMalloc((void **)&p->queue, queue_bytes) != hipSuccess) {
-        p->queue = nullptr;
-        return fail(c, PGH_ENOMEM, "hipMalloc(queue) failed");
-    }
-    if (!grow_records(&p->tasks, &p->tasks_cap, n_t))
-        return fail(c, PGH_ENOMEM, "hipMalloc(tasks) failed");
-    if (!grow_records(&p->partial, &p->partial_cap, (size_t)hp.n_slots * 64))
-        return fail(c, PGH_ENOMEM, "hipMalloc(partial sums) failed");
-    if (!grow_records(&p->chunks, &p->chunks_cap, n_c))
-        return fail(c, PGH_ENOMEM, "hipMalloc(split chunks) failed");
-    const size_t bytes = n_t * sizeof(Task) + n_c * sizeof(SplitChunk);
-    if (bytes > c->pin_bytes) {
-        // every upload waits for the stream, so nothing reads the old buffer
-        (void)hipHostFree(c->pin);
-        c->pin = nullptr;
-        c->pin_bytes = 0;
-        const size_t want = bytes + bytes / 4;
-        if (hipHostMalloc(&c->pin, want, hipHostMallocDefault) != hipSuccess) {
-            c->pin = nullptr;
-            return fail(c, PGH_ENOMEM, "hipHostMalloc(plan upload buffer) failed");
-        }
-        c->pin_bytes = want;
-    }
+    int st = ensure_plan_arrays(c, p, n_t, (size_t)hp.n_slots, n_c);
+    if (st) return st;
+    st = ensure_pinned(c, n_t * sizeof(Task) + n_c * sizeof(SplitChunk));
+    if (st) return st;
     char *pin = (char *)c->pin;
     if (n_t) write_tasks(hp, (Task *)pin);
     if (n_c) std::memcpy(pin + n_t * sizeof(Task), hp.split.data(), n_c * sizeof(SplitChunk));
-    if (hipMemsetAsync(p->queue, 0, queue_bytes, c->stream) != hipSuccess ||
+    if (hipMemsetAsync(p->queue, 0, (size_t)kQueues * kQueueStride * sizeof(unsigned),
+                       c->stream) != hipSuccess ||
         (n_t && hipMemcpyAsync(p->tasks, pin, n_t * sizeof(Task), hipMemcpyHostToDevice,
                                c->stream) != hipSuccess) ||
         (n_c && hipMemcpyAsync(p->chunks, pin + n_t * sizeof(Task), n_c * sizeof(SplitChunk),
                                hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, PGH_EHIP, "uploading the plan failed");
-    p->n_items = n_items;
-    p->n_tasks = (int)n_t;
-    p->nq = hp.nq;
-    std::copy(hp.q_begin, hp.q_begin + kQueues + 1, p->q_begin);
-    p->ni_total = ni_total;
-    p->nj_total = nj_total;
-    p->interactions = hp.interactions;
-    p->n_chunks = (int)n_c;
-    p->n_slots = hp.n_slots;
-    p->ordered = hp.ordered;
+    set_plan_counts(p, n_items, ni_total, nj_total, (int)n_t, hp.nq, hp.q_begin, hp.interactions,
+                    (int)n_c, hp.n_slots, hp.ordered);
+    return PGH_OK;
+}
+
+// The same plan with its tasks expanded on the device from the compact form
+// (plan_descs): the host decides the pairing and the cut of each item's
+// chunks, the device writes the tasks.  Plans too small for chunks of 64 go
+// to plan_fill.  Waits for the stream.
+int plan_fill_device(pgh_ctx *c, pgh_plan *p, int n_items, const pgh_item *items, int ni_total,
+                     int nj_total)
+{
+    DescPlan &dp = c->dp;
+    {
+        std::string err;
+        const int st = plan_descs(items, n_items, ni_total, nj_total,
+                                  batch_resident_waves(c->num_cu), dp, err);
+        if (st == kPlanOnHost) return plan_fill(c, p, n_items, items, ni_total, nj_total);
+        if (st) return fail(c, st, err);
+    }
+    DeviceGuard g(c->device);
+    reset_plan(p);
+    const size_t n_t = (size_t)dp.n_tasks, n_c = (size_t)dp.n_split, n_d = dp.desc.size();
+    int st = ensure_plan_arrays(c, p, n_t, (size_t)dp.n_slots, n_c);
+    if (st) return st;
+    size_t tb = 0;
+    PGH_HIP(c, plan_expand_temp_bytes((int)n_t, dp.kmax, &tb));
+    char *temp = (char *)p->sort_temp;
+    const bool ok = grow_records(&p->desc, &p->desc_cap, n_d) &&
+                    grow_records(&p->keys, &p->keys_cap, n_t) &&
+                    grow_records(&p->keys_out, &p->keys_out_cap, n_t) &&
+                    grow_records(&p->vals, &p->vals_cap, n_t) &&
+                    grow_records(&p->order, &p->order_cap, n_t) &&
+                    grow_records(&temp, &p->sort_temp_cap, tb);
+    p->sort_temp = temp;
+    if (!ok) return fail(c, PGH_ENOMEM, "hipMalloc(plan expansion arrays) failed");
+    st = ensure_pinned(c, n_d * sizeof(PlanDesc));
+    if (st) return st;
+    if (n_d) std::memcpy(c->pin, dp.desc.data(), n_d * sizeof(PlanDesc));
+    PlanExpandArgs a{};
+    a.n_tasks = (int)n_t;
+    a.n_desc = (int)n_d;
+    a.n_split = (int)n_c;
+    a.nq = dp.nq;
+    a.desc = p->desc;
+    a.part_iters = dp.part_iters;
+    a.kmax = dp.kmax;
+    a.keys = p->keys;
+    a.keys_out = p->keys_out;
+    a.vals = p->vals;
+    a.order = p->order;
+    a.tasks = p->tasks;
+    a.split = p->chunks;
+    std::copy(dp.q_begin, dp.q_begin + kQueues + 1, a.q_begin);
+    if (hipMemsetAsync(p->queue, 0, (size_t)kQueues * kQueueStride * sizeof(unsigned),
+                       c->stream) != hipSuccess ||
+        (n_d && hipMemcpyAsync(p->desc, c->pin, n_d * sizeof(PlanDesc), hipMemcpyHostToDevice,
+                               c->stream) != hipSuccess) ||
+        launch_plan_expand(a, p->sort_temp, tb, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, PGH_EHIP, "expanding the plan failed");
+    set_plan_counts(p, n_items, ni_total, nj_total, (int)n_t, dp.nq, dp.q_begin, dp.interactions,
+                    (int)n_c, dp.n_slots, dp.ordered);
     return PGH_OK;
 }
 
@@ -1117,10 +1223,14 @@ int pgh_tree_walk(pgh_ctx *c, pgh_tree *t, float theta, int record_src)
     }
     const TreeState &s = t->st;
     if (s.n_groups > 0) {
-        st = t->plan ? plan_fill(c, t->plan, s.n_groups, s.host_items.data(), s.n,
-                                 (int)s.n_entries)
-                     : pgh_plan_create(c, s.n_groups, s.host_items.data(), s.n,
-                                       (int)s.n_entries, &t->plan);
+        if (!t->plan) {
+            t->plan = new (std::nothrow) pgh_plan{};
+            if (!t->plan) return fail(c, PGH_ENOMEM, "out of host memory");
+            t->plan->owner = c;
+            c->plans.push_back(t->plan);
+        }
+        st = plan_fill_device(c, t->plan, s.n_groups, s.host_items.data(), s.n,
+                              (int)s.n_entries);
         if (st) {
             drop_plan();
             t->st.walked = 0;

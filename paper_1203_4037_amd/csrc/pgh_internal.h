@@ -129,6 +129,26 @@ hipError_t launch_table_allpairs(const TableArgs &a, int variant, int S, hipStre
 int batch_resident_waves(int num_cu);  // waves of the persistent grid
 int batch_variants(int family);
 const char *batch_variant_name(int family, int v);
+// Device expansion of a compact plan (plan_expand.hip): the tasks of the
+// n_desc entries sorted longest first (keys/vals and their sorted copies
+// keys_out/order, n_tasks each; a hipCUB radix sort with temp storage of
+// plan_expand_temp_bytes) and written to their dealt positions in tasks,
+// with the split chunks in split.
+struct PlanDesc;
+struct PlanExpandArgs {
+    int n_tasks, n_desc, n_split, nq;
+    const PlanDesc *desc;
+    long long part_iters;
+    unsigned kmax;
+    unsigned *keys, *keys_out;
+    int *vals, *order;
+    Task *tasks;
+    SplitChunk *split;
+    int q_begin[kQueues + 1];
+};
+hipError_t plan_expand_temp_bytes(int n_tasks, unsigned kmax, size_t *bytes);
+hipError_t launch_plan_expand(PlanExpandArgs a, void *temp, size_t temp_bytes, hipStream_t s);
+
 hipError_t launch_newton_batch(const BatchArgs &a, int variant, bool refine, bool guard,
                                int num_cu, hipStream_t s);
 hipError_t launch_table_batch(const BatchArgs &a, int variant, int num_cu, hipStream_t s);

@@ -1,5 +1,6 @@
 // Host planning of batched launches: wave tasks, pairing, splitting of long
-// lists, longest-first order and the task sublists (see plan_tasks), and the
+// lists, longest-first order and the task sublists (plan_tasks), the compact
+// form of the same plan whose tasks the device expands (plan_descs), and the
 // task lists of the table adjoint.  Plain C++: no HIP types, so the planner
 // is also built on its own for host-side checks.
 #include "planner.h"
@@ -65,10 +66,8 @@ struct Scratch {
     std::vector<char> taken;
     std::vector<int> c_ni, c_nj;
     std::vector<unsigned long long> fits, big, used;  // bit sets over the candidates
+    std::vector<std::pair<int, int>> pairs;
 };
-
-// ceil(n / js) for js = 1, 2 or 4 lanes per i-particle
-inline long long lane_steps(long long n, int js) { return (n + js - 1) >> (js >> 1); }
 
 Scratch &scratch()
 {
@@ -76,41 +75,162 @@ Scratch &scratch()
     return s;
 }
 
-}  // namespace
-
-int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, int waves,
-               HostPlan &out, std::string &err)
+// Checks the items (non-negative fields, inside the arrays, disjoint
+// i-ranges), and lists those with n_i > 0 by i_off in `order` and `ordered`.
+int validate_items(const pgh_item *items, int n_items, int ni_total, int nj_total,
+                   std::vector<int> &order, std::vector<pgh_item> &ordered, long long *inter,
+                   std::string &err)
 {
     if (n_items < 0 || ni_total < 0 || nj_total < 0)
         return fail_msg(err, PGH_EINVAL, "counts must be >= 0");
     if (n_items > 0 && !items) return fail_msg(err, PGH_EINVAL, "NULL item array");
-    Scratch &S = scratch();
-    // ranges and disjointness of the i-groups
-    std::vector<int> &order = S.order;
     order.clear();
-    long long inter = 0;
+    *inter = 0;
+    bool sorted = true;
     for (int t = 0; t < n_items; ++t) {
         const pgh_item &it = items[t];
         if (it.i_off < 0 || it.n_i < 0 || it.j_off < 0 || it.n_j < 0)
             return fail_msg(err, PGH_EINVAL, "item " + std::to_string(t) + " has a negative field");
         if ((long long)it.i_off + it.n_i > ni_total || (long long)it.j_off + it.n_j > nj_total)
             return fail_msg(err, PGH_ERANGE, "item " + std::to_string(t) + " exceeds the arrays");
-        if (it.n_i > 0) order.push_back(t);
-        inter += (long long)it.n_i * it.n_j;
+        if (it.n_i > 0) {
+            if (!order.empty() && it.i_off < items[order.back()].i_off) sorted = false;
+            order.push_back(t);
+        }
+        *inter += (long long)it.n_i * it.n_j;
     }
-    std::sort(order.begin(), order.end(),
-              [&](int a, int b) { return items[a].i_off < items[b].i_off; });
+    if (!sorted)
+        std::sort(order.begin(), order.end(),
+                  [&](int a, int b) { return items[a].i_off < items[b].i_off; });
     for (size_t k = 1; k < order.size(); ++k) {
         const pgh_item &p0 = items[order[k - 1]], &p1 = items[order[k]];
         if (p1.i_off < p0.i_off + p0.n_i)
             return fail_msg(err, PGH_EINVAL, "i-ranges of items " + std::to_string(order[k - 1]) +
                                            " and " + std::to_string(order[k]) + " overlap");
     }
+    ordered.clear();
+    ordered.reserve(order.size());
+    for (int t : order) ordered.push_back(items[t]);
+    return PGH_OK;
+}
 
-    out.ordered.clear();
-    out.ordered.reserve(order.size());
-    for (int t : order) out.ordered.push_back(items[t]);
+// Pairs partly filled chunks.  cand lists the candidates (chunks of fewer
+// than 64 i-particles with a non-empty list) in chunk order, with their
+// i-particle counts ni[k] and list lengths nj[k] (indexed by the values in
+// cand).  In order of list length, each candidate takes the first later one
+// (within a window of 64) whose i-particles fit beside its own in 64 lanes,
+// when one wavefront running the longer list costs fewer lane-iterations
+// than the two apart.  Appends the pairs (chunk indices, the earlier first)
+// in the order they are formed.
+template <class NI, class NJ>
+void pair_chunks(Scratch &S, std::vector<int> &cand, NI ni, NJ nj,
+                 std::vector<std::pair<int, int>> &pairs)
+{
+    pairs.clear();
+    stable_order(cand, [&](int k) { return (long long)nj(k); }, false, S.so_start, S.so_out);
+    const size_t nc = cand.size();
+    std::vector<int> &c_ni = S.c_ni, &c_nj = S.c_nj;
+    std::vector<long long> &c_it = S.c_it;
+    c_ni.resize(nc);
+    c_nj.resize(nc);
+    c_it.resize(nc);
+    for (size_t u = 0; u < nc; ++u) {
+        c_ni[u] = ni(cand[u]);
+        c_nj[u] = nj(cand[u]);
+        c_it[u] = 64LL * std::max(1LL, lane_steps(c_nj[u], chunk_js(c_ni[u])));
+    }
+    // Bit sets over the candidates (in this order): fits[r] holds those of
+    // at most r i-particles, big those of more than 32 (one lane each), used
+    // those already paired.  A candidate's partners are then the set bits of
+    // fits[room] & ~used in its window, in order.  Two chunks of at most 32
+    // (two or four lanes each) can only gain by sharing when their lists
+    // differ by at most one entry (rounding of the lane counts), so past
+    // that point a small chunk looks at big ones only.
+    const size_t nw = (nc + 63) / 64 + 1;
+    std::vector<unsigned long long> &fits = S.fits, &big = S.big, &used = S.used;
+    fits.assign(64 * nw, 0ULL);
+    big.assign(nw, 0ULL);
+    used.assign(nw, 0ULL);
+    for (size_t u = 0; u < nc; ++u) {
+        fits[(size_t)c_ni[u] * nw + u / 64] |= 1ULL << (u % 64);
+        if (c_ni[u] > 32) big[u / 64] |= 1ULL << (u % 64);
+    }
+    for (int r = 1; r < 64; ++r)
+        for (size_t w = 0; w < nw; ++w) fits[(size_t)r * nw + w] |= fits[(size_t)(r - 1) * nw + w];
+    // the bits [from, from + len) of a set, len <= 64
+    auto window = [&](const unsigned long long *set, size_t from, size_t len) {
+        const size_t w = from / 64, sh = from % 64;
+        unsigned long long m = set[w] >> sh;
+        if (sh) m |= set[w + 1] << (64 - sh);
+        return len < 64 ? m & ((1ULL << len) - 1) : m;
+    };
+    constexpr size_t kWindow = 64;
+    for (size_t u = 0; u < nc; ++u) {
+        if (used[u / 64] >> (u % 64) & 1) continue;
+        const size_t from = u + 1, len = std::min(nc, u + 1 + kWindow) - from;
+        if (len == 0) break;
+        const int room = 64 - c_ni[u];
+        unsigned long long m =
+            window(&fits[(size_t)room * nw], from, len) & ~window(used.data(), from, len);
+        if (c_ni[u] <= 32) {
+            // small candidates only up to list length c_nj[u] + 1
+            const size_t near =
+                std::upper_bound(c_nj.begin() + from, c_nj.begin() + from + len,
+                                 (long long)c_nj[u] + 1) -
+                (c_nj.begin() + from);
+            const unsigned long long head = near < 64 ? (1ULL << near) - 1 : ~0ULL;
+            m &= head | window(big.data(), from, len);
+        }
+        for (; m; m &= m - 1) {
+            const size_t v = from + (size_t)__builtin_ctzll(m);
+            if (64LL * std::max(c_nj[u], c_nj[v]) >= c_it[u] + c_it[v]) continue;
+            used[u / 64] |= 1ULL << (u % 64);
+            used[v / 64] |= 1ULL << (v % 64);
+            pairs.push_back({cand[u], cand[v]});
+            break;
+        }
+    }
+}
 
+// Sublists of a plan of n tasks: their count and starts (q_begin[nq] = n).
+// Sublist q holds the groups of kBatchWaves ranks g = q, q + nq, ...; only
+// the last group of all may be partial.
+int deal_layout(size_t n, int *q_begin)
+{
+    const int nq = (int)std::min<size_t>(kQueues, std::max<size_t>(1, (n + kBatchWaves - 1) / kBatchWaves));
+    std::fill(q_begin, q_begin + kQueues + 1, 0);
+    const size_t groups = (n + kBatchWaves - 1) / kBatchWaves;
+    for (int q = 0; q < nq; ++q) {
+        size_t size = (groups / nq + ((size_t)q < groups % nq ? 1 : 0)) * kBatchWaves;
+        if (groups > 0 && (size_t)q == (groups - 1) % nq) size -= groups * kBatchWaves - n;
+        q_begin[q + 1] = q_begin[q] + (int)size;
+    }
+    return nq;
+}
+
+// Part length of the lists: an eighth of the average work of a resident
+// wave, so each wave takes several tasks and the longest-first queue ends
+// with short ones.  (Equal tasks of half a wave's work leave the last round
+// of the queue mostly idle whenever the task count is just above a multiple
+// of the wave count.)
+long long part_length(long long wave_iters, int waves)
+{
+    return std::max(512LL, (wave_iters / waves / 8 + 63) / 64 * 64);
+}
+
+}  // namespace
+
+int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, int waves,
+               HostPlan &out, std::string &err)
+{
+    Scratch &S = scratch();
+    std::vector<int> &order = S.order;
+    long long inter = 0;
+    {
+        const int st = validate_items(items, n_items, ni_total, nj_total, order, out.ordered,
+                                      &inter, err);
+        if (st) return st;
+    }
     // Wave tasks: chunks of <= 64 i-particles; a chunk of <= 32 (<= 16) runs
     // js = 2 (4) lanes per i-particle.  When chunks of 64 fill less than half
     // of the waves the device holds (a small plan), the groups are cut into
@@ -132,19 +252,14 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
         const pgh_item &it = items[t];
         for (int s0 = 0; s0 < it.n_i; s0 += csize) {
             const int n = std::min(csize, it.n_i - s0);
-            const int js = n <= 16 ? 4 : (n <= 32 ? 2 : 1);
+            const int js = chunk_js(n);
             chunks.push_back({it.i_off + s0, n, it.j_off, it.n_j, js});
             total += std::max(1LL, lane_steps(it.n_j, js));
         }
     }
-    // Cut j-lists longer than an eighth of the average work of a resident
-    // wave, so each wave takes several tasks and the longest-first queue
-    // ends with short ones.  (Equal tasks of half a wave's work leave the
-    // last round of the queue mostly idle whenever the task count is just
-    // above a multiple of the wave count.)  add_work records a wave's work
-    // (chunk a, and chunk b sharing the wave, or b < 0), its cut and its
-    // tasks with their costs (lane-iterations / 64).
-    const long long part_iters = std::max(512LL, (total / waves / 8 + 63) / 64 * 64);
+    const long long part_iters = part_length(total, waves);
+    // add_work records a wave's work (chunk a, and chunk b sharing the wave,
+    // or b < 0), its cut and its tasks with their costs
     std::vector<PlanWork> &work = out.work;
     work.clear();
     std::vector<PlanRef> &refs = S.refs;
@@ -158,113 +273,33 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
         const int w = (int)work.size();
         const PlanChunk &ch = chunks[a];
         const bool pair = b >= 0;
-        const int njb_all = pair ? chunks[b].n_j : 0;
-        const int js = pair ? 1 : ch.js;
-        const int njm = std::max(ch.n_j, njb_all);
-        const long long iters = lane_steps(njm, js);
-        int parts = iters <= part_iters ? 1 : (int)((iters + part_iters - 1) / part_iters);
-        long long per = njm;
-        if (parts <= 1) {
-            work.push_back({a, b, 1, njm, 0});
-            refs.push_back({w, 0});
-            cost.push_back((int)std::max(1LL, iters));
-            return;
-        }
-        // equal parts, each a multiple of 64 j-particles except the last
-        per = (njm + parts - 1) / parts;
-        per = (per + 63) / 64 * 64;
-        parts = (int)((njm + per - 1) / per);
-        work.push_back({a, b, parts, (int)per, n_slots});
-        for (int q = 0; q < parts; ++q) {
-            const long long nja = std::max(0LL, std::min(per, ch.n_j - q * per));
-            const long long njb = pair ? std::max(0LL, std::min(per, njb_all - q * per)) : 0;
+        const int njb = pair ? chunks[b].n_j : 0;
+        const WorkCut c = cut_work(std::max(ch.n_j, njb), pair ? 1 : ch.js, part_iters);
+        work.push_back({a, b, c.parts, c.per, c.parts > 1 ? n_slots : 0});
+        for (int q = 0; q < c.parts; ++q) {
             refs.push_back({w, q});
-            cost.push_back((int)lane_steps(std::max(nja, njb), js));
+            cost.push_back(work_task_cost(ch.n_i, ch.n_j, pair, njb, c, q));
         }
-        split.push_back({ch.i_off, ch.n_i, n_slots, parts, 0});
-        if (pair) split.push_back({chunks[b].i_off, chunks[b].n_i, n_slots, parts, ch.n_i});
-        n_slots += parts;
+        if (c.parts > 1) {
+            split.push_back({ch.i_off, ch.n_i, n_slots, c.parts, 0});
+            if (pair) split.push_back({chunks[b].i_off, chunks[b].n_i, n_slots, c.parts, ch.n_i});
+            n_slots += c.parts;
+        }
     };
-    // Pair partly filled chunks: in order of j-list length, each takes the
-    // first later one (within a window of 64) whose i-particles fit beside
-    // its own in 64 lanes, when one wavefront running the longer list costs
-    // fewer lane-iterations than the two apart.  A pair is cut along j like
-    // any long list (both lists at the same offsets).
+    // paired works first, in the order the pairs form, then every other
+    // chunk in chunk order
     {
-        auto lane_iters = [](const PlanChunk &ch) {
-            return 64LL * std::max(1LL, lane_steps(ch.n_j, ch.js));
-        };
-        std::vector<char> &taken = S.taken;
-        taken.assign(chunks.size(), 0);
         std::vector<int> &cand = S.cand;
         cand.clear();
         for (size_t k = 0; k < chunks.size(); ++k)
             if (chunks[k].n_i < 64 && chunks[k].n_j > 0) cand.push_back((int)k);
-        stable_order(cand, [&](int k) { return (long long)chunks[k].n_j; }, false, S.so_start,
-                     S.so_out);
-        const size_t nc = cand.size();
-        std::vector<int> &c_ni = S.c_ni, &c_nj = S.c_nj;
-        std::vector<long long> &c_it = S.c_it;
-        c_ni.resize(nc);
-        c_nj.resize(nc);
-        c_it.resize(nc);
-        for (size_t u = 0; u < nc; ++u) {
-            const PlanChunk &ch = chunks[cand[u]];
-            c_ni[u] = ch.n_i;
-            c_nj[u] = ch.n_j;
-            c_it[u] = lane_iters(ch);
-        }
-        // Bit sets over the candidates (in this order): fits[r] holds those
-        // of at most r i-particles, big those of more than 32 (one lane each),
-        // used those already paired.  A candidate's partners are then the
-        // set bits of fits[room] & ~used in its window, in order.  Two chunks
-        // of at most 32 (two or four lanes each) can only gain by sharing
-        // when their lists differ by at most one entry (rounding of the lane
-        // counts), so past that point a small chunk looks at big ones only.
-        const size_t nw = (nc + 63) / 64 + 1;
-        std::vector<unsigned long long> &fits = S.fits, &big = S.big, &used = S.used;
-        fits.assign(64 * nw, 0ULL);
-        big.assign(nw, 0ULL);
-        used.assign(nw, 0ULL);
-        for (size_t u = 0; u < nc; ++u) {
-            fits[(size_t)c_ni[u] * nw + u / 64] |= 1ULL << (u % 64);
-            if (c_ni[u] > 32) big[u / 64] |= 1ULL << (u % 64);
-        }
-        for (int r = 1; r < 64; ++r)
-            for (size_t w = 0; w < nw; ++w) fits[(size_t)r * nw + w] |= fits[(size_t)(r - 1) * nw + w];
-        // the bits [from, from + len) of a set, len <= 64
-        auto window = [&](const unsigned long long *set, size_t from, size_t len) {
-            const size_t w = from / 64, sh = from % 64;
-            unsigned long long m = set[w] >> sh;
-            if (sh) m |= set[w + 1] << (64 - sh);
-            return len < 64 ? m & ((1ULL << len) - 1) : m;
-        };
-        constexpr size_t kWindow = 64;
-        for (size_t u = 0; u < nc; ++u) {
-            if (used[u / 64] >> (u % 64) & 1) continue;
-            const size_t from = u + 1, len = std::min(nc, u + 1 + kWindow) - from;
-            if (len == 0) break;
-            const int room = 64 - c_ni[u];
-            unsigned long long m = window(&fits[(size_t)room * nw], from, len) &
-                                   ~window(used.data(), from, len);
-            if (c_ni[u] <= 32) {
-                // small candidates only up to list length c_nj[u] + 1
-                const size_t near =
-                    std::upper_bound(c_nj.begin() + from, c_nj.begin() + from + len,
-                                     (long long)c_nj[u] + 1) -
-                    (c_nj.begin() + from);
-                const unsigned long long head = near < 64 ? (1ULL << near) - 1 : ~0ULL;
-                m &= head | window(big.data(), from, len);
-            }
-            for (; m; m &= m - 1) {
-                const size_t v = from + (size_t)__builtin_ctzll(m);
-                if (64LL * std::max(c_nj[u], c_nj[v]) >= c_it[u] + c_it[v]) continue;
-                used[u / 64] |= 1ULL << (u % 64);
-                used[v / 64] |= 1ULL << (v % 64);
-                taken[cand[u]] = taken[cand[v]] = 1;
-                add_work(cand[u], cand[v]);
-                break;
-            }
+        pair_chunks(S, cand, [&](int k) { return chunks[k].n_i; },
+                    [&](int k) { return chunks[k].n_j; }, S.pairs);
+        std::vector<char> &taken = S.taken;
+        taken.assign(chunks.size(), 0);
+        for (const auto &pr : S.pairs) {
+            taken[pr.first] = taken[pr.second] = 1;
+            add_work(pr.first, pr.second);
         }
         for (size_t k = 0; k < chunks.size(); ++k)
             if (!taken[k]) add_work((int)k, -1);
@@ -275,49 +310,28 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
     // serves sublist b mod nq) takes tasks 4b .. 4b+3 of the whole list in
     // its first round, one of similar length per SIMD.
     const size_t n = refs.size();
-    const int nq = (int)std::min<size_t>(kQueues, std::max<size_t>(1, (n + kBatchWaves - 1) / kBatchWaves));
     int *q_begin = out.q_begin;
-    std::fill(q_begin, q_begin + kQueues + 1, 0);
-    {
-        // sublist q holds the groups g = q, q + nq, ...; only the last group
-        // of all may be partial
-        const size_t groups = (n + kBatchWaves - 1) / kBatchWaves;
-        for (int q = 0; q < nq; ++q) {
-            size_t size = (groups / nq + ((size_t)q < groups % nq ? 1 : 0)) * kBatchWaves;
-            if (groups > 0 && (size_t)q == (groups - 1) % nq) size -= groups * kBatchWaves - n;
-            q_begin[q + 1] = q_begin[q] + (int)size;
-        }
-    }
-    // the final position of the task of rank r in the longest-first order
-    // (all kQueues sublists in use unless the plan is tiny: shifts, not divisions)
-    const bool all_q = nq == kQueues;
-    auto place = [&](size_t r) {
-        const size_t g = r / kBatchWaves;
-        const size_t q = all_q ? g % kQueues : g % nq, row = all_q ? g / kQueues : g / nq;
-        return (size_t)q_begin[q] + row * kBatchWaves + r % kBatchWaves;
-    };
+    const int nq = deal_layout(n, q_begin);
     std::vector<PlanRef> &dealt = out.dealt;
     dealt.resize(n);
     int kmax = 0;
     for (int c : cost) kmax = std::max(kmax, c);
-    const bool small = kmax <= (1 << 22);
-    if (small) {
+    if (kmax <= (1 << 22)) {
         // stable counting sort, longest first, scattered straight to the
         // dealt positions
         std::vector<int> &start = S.so_start;
         start.assign((size_t)kmax + 2, 0);
         for (int c : cost) ++start[(size_t)(kmax - c) + 1];
         for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
-        for (size_t k = 0; k < n; ++k) dealt[place((size_t)start[(size_t)(kmax - cost[k])]++)] = refs[k];
+        for (size_t k = 0; k < n; ++k)
+            dealt[dealt_position(start[(size_t)(kmax - cost[k])]++, nq, q_begin)] = refs[k];
     } else {
         std::vector<int> &idx = S.order;  // the item order is no longer needed below
         idx.resize(n);
         for (size_t k = 0; k < n; ++k) idx[k] = (int)k;
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        for (size_t r = 0; r < n; ++r) dealt[place(r)] = refs[idx[r]];
+        for (size_t r = 0; r < n; ++r) dealt[dealt_position((long long)r, nq, q_begin)] = refs[idx[r]];
     }
-    q_begin[nq] = (int)n;
-
     out.n_tasks = (int)n;
     out.nq = nq;
     out.n_slots = n_slots;
@@ -335,18 +349,86 @@ void write_tasks(const HostPlan &hp, Task *dst)
         const bool pair = wk.b >= 0;
         static const PlanChunk kNone{0, 0, 0, 0, 1};
         const PlanChunk &b = pair ? chunks[wk.b] : kNone;
-        if (wk.parts <= 1) {
-            dst[k] = {a.i_off, a.n_i, a.j_off, a.n_j, 0, 1, 0, b.i_off, b.n_i, b.j_off, b.n_j, 0};
-            continue;
-        }
-        // part q starts at q * per (at the list's end for the empty parts of
-        // the shorter list of a pair)
-        const long long per = wk.per, q = r.part;
-        auto cut = [&](int n_j) { return (int)std::max(0LL, std::min(per, n_j - q * per)); };
-        auto start = [&](int n_j) { return (int)std::min(q * per, (long long)n_j); };
-        dst[k] = {a.i_off, a.n_i, a.j_off + start(a.n_j), cut(a.n_j), r.part, wk.parts, wk.slot,
-                  b.i_off, b.n_i, b.j_off + (pair ? start(b.n_j) : 0), pair ? cut(b.n_j) : 0, 0};
+        dst[k] = work_task(a.i_off, a.n_i, a.j_off, a.n_j, pair, b.i_off, b.n_i, b.j_off, b.n_j,
+                           WorkCut{wk.parts, wk.per, 0}, r.part, wk.slot);
     }
+}
+
+int plan_descs(const pgh_item *items, int n_items, int ni_total, int nj_total, int waves,
+               DescPlan &out, std::string &err)
+{
+    Scratch &S = scratch();
+    std::vector<int> &order = S.order;
+    long long inter = 0;
+    {
+        const int st = validate_items(items, n_items, ni_total, nj_total, order, out.ordered,
+                                      &inter, err);
+        if (st) return st;
+    }
+    // the same chunks as plan_tasks, which must be of 64 here
+    waves = std::max(1, waves);
+    long long n64 = 0, total = 0;
+    for (int t : order) {
+        const pgh_item &it = items[t];
+        const int n_full = it.n_i >> 6, n_last = it.n_i & 63;
+        n64 += n_full + (n_last ? 1 : 0);
+        total += n_full * std::max(1LL, (long long)it.n_j);
+        if (n_last) total += std::max(1LL, lane_steps(it.n_j, chunk_js(n_last)));
+    }
+    if (n64 < waves) return kPlanOnHost;
+    const long long part_iters = part_length(total, waves);
+    // every cost is at most part_iters + 64 (a part of at most part_iters
+    // steps rounded up to whole tiles), so kmax - cost fits the sort keys
+    const long long kmax = part_iters + 64;
+    if (kmax >= (1LL << 31)) return kPlanOnHost;
+    // the partly filled chunk of each item is its last; those with a list
+    // are the pairing candidates, by item (the chunk order)
+    std::vector<int> &cand = S.cand;
+    cand.clear();
+    for (size_t k = 0; k < order.size(); ++k) {
+        const pgh_item &it = items[order[k]];
+        if ((it.n_i & 63) && it.n_j > 0) cand.push_back((int)k);
+    }
+    pair_chunks(S, cand, [&](int k) { return items[order[k]].n_i & 63; },
+                [&](int k) { return items[order[k]].n_j; }, S.pairs);
+    std::vector<char> &taken = S.taken;
+    taken.assign(order.size(), 0);
+    std::vector<PlanDesc> &desc = out.desc;
+    desc.clear();
+    long long n_tasks = 0, n_slots = 0, n_split = 0;
+    auto add = [&](PlanDesc d) {
+        int tasks = 0, slots = 0, splits = 0;
+        desc_counts(d, part_iters, &tasks, &slots, &splits);
+        d.task0 = (int)n_tasks;
+        d.slot0 = (int)n_slots;
+        d.split0 = (int)n_split;
+        n_tasks += tasks;
+        n_slots += slots;
+        n_split += splits;
+        desc.push_back(d);
+    };
+    for (const auto &pr : S.pairs) {
+        const pgh_item &a = items[order[pr.first]], &b = items[order[pr.second]];
+        const int na = a.n_i & 63, nb = b.n_i & 63;
+        taken[pr.first] = taken[pr.second] = 1;
+        add({a.i_off + a.n_i - na, na, a.j_off, a.n_j, b.i_off + b.n_i - nb, nb, b.j_off, b.n_j,
+             0, 0, 0, 0});
+    }
+    for (size_t k = 0; k < order.size(); ++k) {
+        const pgh_item &it = items[order[k]];
+        const int n = taken[k] ? it.n_i - (it.n_i & 63) : it.n_i;
+        if (n > 0) add({it.i_off, n, it.j_off, it.n_j, 0, 0, 0, 0, 0, 0, 0, 0});
+        if (n_tasks > (1LL << 30) || n_slots > (1LL << 30))
+            return fail_msg(err, PGH_ERANGE, "the plan exceeds 2^30 tasks");
+    }
+    out.n_tasks = (int)n_tasks;
+    out.n_slots = (int)n_slots;
+    out.n_split = (int)n_split;
+    out.nq = deal_layout((size_t)n_tasks, out.q_begin);
+    out.part_iters = part_iters;
+    out.kmax = (unsigned)kmax;
+    out.interactions = inter;
+    return PGH_OK;
 }
 
 void plan_adjoint_tasks(const std::vector<pgh_item> &ordered, int waves, std::vector<Task> &out_j,

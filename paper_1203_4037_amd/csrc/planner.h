@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "pgh.h"
+#include "plan_expand.h"
 #include "plan_types.h"
 
 namespace pgh {
@@ -54,6 +55,30 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
 // Writes the plan's hp.n_tasks tasks to dst, sublist after sublist, each
 // sublist longest first.
 void write_tasks(const HostPlan &hp, Task *dst);
+
+// The compact form of a plan (plan_descs): the works of plan_tasks grouped
+// into entries whose tasks the device expands, sorts longest first and
+// deals into the same sublists, giving the same task list as plan_tasks.
+struct DescPlan {
+    std::vector<PlanDesc> desc;
+    int n_tasks = 0, n_slots = 0, n_split = 0;
+    int nq = 0;
+    int q_begin[kQueues + 1] = {0};
+    long long part_iters = 0;       // the part length of cut_work
+    unsigned kmax = 0;              // every task cost is at most kmax
+    long long interactions = 0;
+    std::vector<pgh_item> ordered;  // the items with n_i > 0, by i_off
+};
+
+// plan_descs' status when the plan should be made by plan_tasks instead
+// (chunks of 64 would fill less than the device's resident waves)
+constexpr int kPlanOnHost = 1;
+
+// Validates the items as plan_tasks does and makes the compact form of the
+// same plan.  Returns PGH_OK, kPlanOnHost, or an error status with a
+// message in err.
+int plan_descs(const pgh_item *items, int n_items, int ni_total, int nj_total, int waves,
+               DescPlan &out, std::string &err);
 
 // Task lists of the table adjoint: j-major (a chunk of j-entries against the
 // item's i-range) and i-major (an i-chunk against a j-range).

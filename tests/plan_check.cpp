@@ -31,6 +31,7 @@ using namespace pgh;
 namespace {
 
 int failures = 0;
+int compact_checked = 0;  // plans whose compact form was checked
 
 void fail(const std::string &what)
 {
@@ -81,6 +82,77 @@ bool check_cover(const std::vector<pgh_item> &items, int ni_total,
         }
     }
     return true;
+}
+
+// The compact form of the plan (plan_descs) expanded here as the device
+// expands it (every task from its entry, a stable sort by kmax - cost, the
+// dealt positions) gives the same tasks, split chunks and sublists.
+void check_compact(const std::vector<pgh_item> &items, int ni_total, int nj_total, int waves,
+                   const HostPlan &hp, const std::vector<Task> &T, const char *what)
+{
+    DescPlan dp;
+    std::string err;
+    const int st = plan_descs(items.data(), (int)items.size(), ni_total, nj_total, waves, dp, err);
+    if (st == kPlanOnHost) return;
+    if (st != PGH_OK) {
+        fail(std::string(what) + ": plan_descs failed: " + err);
+        return;
+    }
+    if (dp.n_tasks != hp.n_tasks || dp.n_slots != hp.n_slots ||
+        dp.n_split != (int)hp.split.size() || dp.nq != hp.nq ||
+        !std::equal(dp.q_begin, dp.q_begin + kQueues + 1, hp.q_begin) ||
+        dp.interactions != hp.interactions) {
+        fail(std::string(what) + ": compact plan counts differ");
+        return;
+    }
+    const int n = dp.n_tasks;
+    std::vector<Task> raw(n);
+    std::vector<unsigned> key(n);
+    std::vector<SplitChunk> split(dp.n_split, SplitChunk{-1, -1, -1, -1, -1});
+    size_t d = 0;
+    for (int t = 0; t < n; ++t) {
+        while (d + 1 < dp.desc.size() && dp.desc[d + 1].task0 <= t) ++d;
+        int cost = 0, ns = 0, at = 0;
+        SplitChunk sc[2];
+        raw[t] = desc_task(dp.desc[d], t - dp.desc[d].task0, dp.part_iters, &cost, sc, &ns, &at);
+        if (cost < 1 || (unsigned)cost > dp.kmax) {
+            fail(std::string(what) + ": compact plan cost outside [1, kmax]");
+            return;
+        }
+        key[t] = dp.kmax - (unsigned)cost;
+        for (int k = 0; k < ns; ++k) {
+            if (at + k < 0 || at + k >= dp.n_split) {
+                fail(std::string(what) + ": compact plan split index out of range");
+                return;
+            }
+            split[at + k] = sc[k];
+        }
+    }
+    std::vector<int> idx(n);
+    for (int t = 0; t < n; ++t) idx[t] = t;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::vector<Task> dealt(n);
+    for (int r = 0; r < n; ++r) dealt[dealt_position(r, dp.nq, dp.q_begin)] = raw[idx[r]];
+    auto same_task = [](const Task &a, const Task &b) {
+        return a.i_off == b.i_off && a.n_i == b.n_i && a.j_off == b.j_off && a.n_j == b.n_j &&
+               a.part == b.part && a.n_parts == b.n_parts && a.slot == b.slot &&
+               a.i_off2 == b.i_off2 && a.n_i2 == b.n_i2 && a.j_off2 == b.j_off2 &&
+               a.n_j2 == b.n_j2;
+    };
+    for (int k = 0; k < n; ++k)
+        if (!same_task(dealt[k], T[k])) {
+            fail(std::string(what) + ": compact plan task " + std::to_string(k) + " differs");
+            return;
+        }
+    for (size_t k = 0; k < split.size(); ++k) {
+        const SplitChunk &a = split[k], &b = hp.split[k];
+        if (a.i_off != b.i_off || a.n_i != b.n_i || a.slot != b.slot || a.n_parts != b.n_parts ||
+            a.lane0 != b.lane0) {
+            fail(std::string(what) + ": compact plan split chunk " + std::to_string(k) + " differs");
+            return;
+        }
+    }
+    ++compact_checked;
 }
 
 long long task_cost(const Task &t)
@@ -146,6 +218,7 @@ void check_plan(const std::vector<pgh_item> &items, int ni_total, int nj_total, 
             fail(std::string(what) + ": split chunk outside its slots");
     if (failures) return;
     check_cover(items, ni_total, rows, what);
+    check_compact(items, ni_total, nj_total, waves, hp, T, what);
     // the table adjoint's tasks: j-major (j-chunk against the item's i-range)
     // and i-major (i-chunk against a j-range) each cover every pair once
     std::vector<Task> jt, it;
@@ -221,6 +294,18 @@ int main()
             check_plan({}, 10, 10, waves, "empty");
         }
     }
+    // tree-code sized item sets (groups of up to 1024, long lists, a few very
+    // long ones): chunks of 64 fill the device, so their compact form is used
+    for (int rep = 0; rep < 3 && !failures; ++rep) {
+        for (int waves : {1024, 4096}) {
+            int ni_total = 0, nj_total = 0;
+            std::vector<pgh_item> items = make_items(
+                rng, U(300, 900), [&] { return rng() % 5 == 0 ? U(1, 63) : U(1, 1024); },
+                [&] { return rng() % 50 == 0 ? U(20000, 200000) : U(0, 6000); }, &ni_total,
+                &nj_total);
+            check_plan(items, ni_total, nj_total, waves, "tree-code");
+        }
+    }
     // invalid items: overlapping i-ranges, out of range, negative fields
     {
         HostPlan hp;
@@ -240,6 +325,10 @@ int main()
         std::printf("%d failures\n", failures);
         return 1;
     }
-    std::printf("planner checks passed\n");
+    if (compact_checked < 20) {
+        std::printf("only %d compact plans checked\n", compact_checked);
+        return 1;
+    }
+    std::printf("planner checks passed (%d compact plans)\n", compact_checked);
     return 0;
 }
