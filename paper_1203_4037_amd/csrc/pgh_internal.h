@@ -201,8 +201,8 @@ struct TreeState {
     int node_cap = 0;
     int *begin = nullptr, *count = nullptr, *level = nullptr, *first_child = nullptr,
         *n_child = nullptr, *parent = nullptr;
-    int *nc = nullptr;        // children per node of one level, then their scan
-    int nc_cap = 0;
+    int *nc = nullptr;        // per level: children per node, chunk sums, child bounds
+    long long nc_cap = 0;
     NodeMoments *mom = nullptr;
     float4 *com = nullptr;    // FP32 centre of mass per node (w unused)
     int4 *nrec = nullptr;     // walk record per node: begin, count, first child, n_child | level << 16

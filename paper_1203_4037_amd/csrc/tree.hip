@@ -192,38 +192,12 @@ __device__ inline int lower_digit(const unsigned long long *key, int lo, int hi,
     return lo;
 }
 
-// nc[i] = non-empty children of the i-th node of level L (0 for a leaf).
-// w[kWordLeaves] counts the leaves.
-__global__ void __launch_bounds__(256) k_split_count(int L, int n_leaf,
-                                                     const int *__restrict__ lvl,
-                                                     const int *__restrict__ begin,
-                                                     const int *__restrict__ count,
-                                                     const unsigned long long *__restrict__ key,
-                                                     int *__restrict__ nc, unsigned *w)
-{
-    if (w[kWordOverflow]) return;
-    const int off = lvl[L], n_level = lvl[L + 1] - off;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n_level; i += gridDim.x * 256) {
-        const int b = begin[off + i], c = count[off + i];
-        int k = 0;
-        if (c > n_leaf && L < kTreeMaxLevel) {
-            int prev = b;
-            for (int d = 1; d <= 8; ++d) {
-                const int p = (d == 8) ? b + c : lower_digit(key, prev, b + c, d, L + 1);
-                k += p > prev;
-                prev = p;
-            }
-        }
-        if (k == 0) atomicAdd(&w[kWordLeaves], 1u);
-        nc[i] = k;
-    }
-}
-
-// Exclusive scan of the n = lvl[L + 1] - lvl[L] counts of level L into
-// out[0 .. n] (out[n] = the total), with n read on the device: chunk sums
-// (kScanBlocks chunks), a scan of those in one workgroup, then each chunk
-// scanned in tiles of 256 from its offset.
-constexpr int kScanBlocks = 512;
+// The split of level L in three kernels, with the level's size read on the
+// device: k_split_count (block b takes the b-th of kSplitBlocks contiguous
+// chunks of the level's nodes), k_split_scan (one workgroup: the chunks'
+// offsets and the next level's size), k_split_write (the same chunks again:
+// each node's children go to the next level at its offset).
+constexpr int kSplitBlocks = 2048;
 
 // Inclusive scan over a workgroup of 256 (wave scans, then the wave totals);
 // *total receives the workgroup's sum.  Every thread of the workgroup calls it.
@@ -244,107 +218,159 @@ __device__ inline int block_incl_scan(int v, int *sh, int *total)
     return v + add;
 }
 
-__global__ void __launch_bounds__(256) k_scan_sums(int L, const int *__restrict__ lvl,
-                                                   const unsigned *__restrict__ w,
-                                                   const int *__restrict__ in, int *bsum)
+__device__ inline void split_chunk(int n, int *lo, int *hi)
 {
-    __shared__ int sh[4];
-    if (w[kWordOverflow]) return;
-    const int n = lvl[L + 1] - lvl[L];
-    const int chunk = (n + kScanBlocks - 1) / kScanBlocks;
-    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-    int v = 0;
-    for (int i = lo + threadIdx.x; i < hi; i += 256) v += in[i];
-    int tot = 0;
-    block_incl_scan(v, sh, &tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    const int chunk = (n + kSplitBlocks - 1) / kSplitBlocks;
+    *lo = min(n, (int)blockIdx.x * chunk);
+    *hi = min(n, *lo + chunk);
 }
 
-__global__ void __launch_bounds__(256) k_scan_top(const unsigned *__restrict__ w, int *bsum)
-{
-    __shared__ int sh[4];
-    if (w[kWordOverflow]) return;
-    // kScanBlocks = 2 x 256 entries: two per thread
-    const int a = bsum[2 * threadIdx.x], b = bsum[2 * threadIdx.x + 1];
-    int tot = 0;
-    const int incl = block_incl_scan(a + b, sh, &tot);
-    bsum[2 * threadIdx.x] = incl - a - b;
-    bsum[2 * threadIdx.x + 1] = incl - b;
-    if (threadIdx.x == 0) bsum[kScanBlocks] = tot;
-}
-
-__global__ void __launch_bounds__(256) k_scan_apply(int L, const int *__restrict__ lvl,
-                                                    const unsigned *__restrict__ w,
-                                                    const int *__restrict__ in,
-                                                    const int *__restrict__ bsum, int *out)
-{
-    __shared__ int sh[4];
-    if (w[kWordOverflow]) return;
-    const int n = lvl[L + 1] - lvl[L];
-    const int chunk = (n + kScanBlocks - 1) / kScanBlocks;
-    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-    int run = bsum[blockIdx.x];
-    for (int t0 = lo; t0 < hi; t0 += 256) {  // uniform trip count for the workgroup
-        const int i = t0 + threadIdx.x;
-        const int v = i < hi ? in[i] : 0;
-        int tot = 0;
-        const int incl = block_incl_scan(v, sh, &tot);
-        if (i < hi) out[i] = run + incl - v;
-        run += tot;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[kScanBlocks];
-}
-
-// Writes the children of level L at lvl[L + 1] + scan[i] and sets lvl[L + 2].
-// Children that would pass the node capacity are not written: the overflow
-// word is set, every later kernel of the build returns at once, and the host
-// builds again with more room.
-__global__ void __launch_bounds__(256) k_split_write(int L, int n_leaf, int cap, int *lvl,
+// nc[i] = non-empty children of the i-th node of level L (0 for a leaf),
+// bnd[7 i + d - 1] = the first particle of its child digits >= d (d = 1..7;
+// for split nodes only), bsum[b] = the children of chunk b;
+// w[kWordLeaves] counts the leaves (one atomic per workgroup).  Eight lanes
+// take a node, lane d - 1 searching boundary d over the whole node (the
+// searches are independent, so a node costs one binary search of latency).
+__global__ void __launch_bounds__(256) k_split_count(int L, int n_leaf,
+                                                     const int *__restrict__ lvl,
+                                                     const int *__restrict__ begin,
+                                                     const int *__restrict__ count,
                                                      const unsigned long long *__restrict__ key,
-                                                     const int *__restrict__ scan, int *begin,
-                                                     int *count, int *level, int *first_child,
-                                                     int *n_child, int *parent, unsigned *w)
+                                                     int *__restrict__ nc, int *__restrict__ bnd,
+                                                     int *__restrict__ bsum, unsigned *w)
 {
+    __shared__ int sh[4];
     if (w[kWordOverflow]) return;
-    const int off = lvl[L], n_level = lvl[L + 1] - off, next_off = lvl[L + 1];
-    const int total = scan[n_level];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if ((long long)next_off + total > cap) {
+    const int off = lvl[L], n_level = lvl[L + 1] - off;
+    int lo, hi;
+    split_chunk(n_level, &lo, &hi);
+    const int g = (int)threadIdx.x >> 3, j = (int)threadIdx.x & 7;
+    int kids = 0, leaves = 0;
+    for (int i0 = lo; i0 < hi; i0 += 32) {  // uniform trip count for the workgroup
+        const int i = i0 + g;
+        int b = 0, c = 0;
+        if (i < hi) {
+            b = begin[off + i];
+            c = count[off + i];
+        }
+        const bool split = i < hi && c > n_leaf && L < kTreeMaxLevel;
+        int p = b + c;  // lane 7: the node's end
+        if (split && j < 7) p = lower_digit(key, b, b + c, j + 1, L + 1);
+        // child j of the node is [boundary j, boundary j + 1), boundary 0 = b
+        const int q = __shfl_up(p, 1, 8);
+        const int start = j == 0 ? b : q;
+        int k = (split && p > start) ? 1 : 0;
+        k += __shfl_xor(k, 1, 8);
+        k += __shfl_xor(k, 2, 8);
+        k += __shfl_xor(k, 4, 8);
+        if (split && j < 7) bnd[7 * (size_t)i + j] = p;
+        if (i < hi && j == 0) {
+            nc[i] = k;
+            kids += k;
+            leaves += k == 0;
+        }
+    }
+    int tot = 0;
+    block_incl_scan(kids, sh, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    block_incl_scan(leaves, sh, &tot);
+    if (threadIdx.x == 0 && tot) atomicAdd(&w[kWordLeaves], (unsigned)tot);
+}
+
+// The chunks' exclusive offsets in bsum, and the next level's size in
+// lvl[L + 2].  Children that would pass the node capacity set the overflow
+// word instead: every later kernel of the build returns at once, and the
+// host builds again with more room.
+__global__ void __launch_bounds__(256) k_split_scan(int L, int cap, int *lvl, int *bsum,
+                                                    unsigned *w)
+{
+    __shared__ int sh[4];
+    if (w[kWordOverflow]) return;
+    constexpr int per = kSplitBlocks / 256;
+    int v[per], sum = 0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        v[k] = bsum[per * threadIdx.x + k];
+        sum += v[k];
+    }
+    int tot = 0;
+    int run = block_incl_scan(sum, sh, &tot) - sum;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        bsum[per * threadIdx.x + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) {
+        const int next_off = lvl[L + 1];
+        if ((long long)next_off + tot > cap) {
             atomicOr(&w[kWordOverflow], 1u);
             lvl[L + 2] = next_off;
         } else {
-            lvl[L + 2] = next_off + total;
-            atomicMax(&w[kWordMaxLevel], (unsigned)total);
+            lvl[L + 2] = next_off + tot;
+            atomicMax(&w[kWordMaxLevel], (unsigned)tot);
         }
-    }
-    if ((long long)next_off + total > cap) return;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n_level; i += gridDim.x * 256) {
-        const int node = off + i;
-        const int b = begin[node], c = count[node];
-        const int fc = next_off + scan[i];
-        int k = 0;
-        if (c > n_leaf && L < kTreeMaxLevel) {
-            int prev = b;
-            for (int d = 1; d <= 8; ++d) {
-                const int p = (d == 8) ? b + c : lower_digit(key, prev, b + c, d, L + 1);
-                if (p > prev) {
-                    const int ch = fc + k;
-                    begin[ch] = prev;
-                    count[ch] = p - prev;
-                    level[ch] = L + 1;
-                    parent[ch] = node;
-                    ++k;
-                }
-                prev = p;
-            }
-        }
-        first_child[node] = k ? fc : -1;
-        n_child[node] = k;
     }
 }
 
-// Moments of the nodes of one level: a leaf from its particles, an internal
-// node from its children (parallel-axis theorem), all in FP64.
+// Writes the children of level L (from the bounds k_split_count kept) at
+// lvl[L + 1] + the node's offset.
+__global__ void __launch_bounds__(256) k_split_write(int L, const int *__restrict__ lvl,
+                                                     const int *__restrict__ nc,
+                                                     const int *__restrict__ bnd,
+                                                     const int *__restrict__ bsum, int *begin,
+                                                     int *count, int *level, int *first_child,
+                                                     int *n_child, int *parent,
+                                                     const unsigned *w)
+{
+    __shared__ int sh[4];
+    if (w[kWordOverflow]) return;
+    const int off = lvl[L], n_level = lvl[L + 1] - off, next_off = lvl[L + 1];
+    int lo, hi;
+    split_chunk(n_level, &lo, &hi);
+    int run = bsum[blockIdx.x];
+    for (int t0 = lo; t0 < hi; t0 += 256) {  // uniform trip count for the workgroup
+        const int i = t0 + (int)threadIdx.x;
+        const int k = i < hi ? nc[i] : 0;
+        int tot = 0;
+        const int incl = block_incl_scan(k, sh, &tot);
+        if (i < hi) {
+            const int node = off + i;
+            const int fc = next_off + run + incl - k;
+            if (k) {
+                const int b = begin[node], c = count[node];
+                int prev = b, j = fc;
+                for (int d = 1; d <= 8; ++d) {
+                    const int p = d == 8 ? b + c : bnd[7 * (size_t)i + d - 1];
+                    if (p > prev) {
+                        begin[j] = prev;
+                        count[j] = p - prev;
+                        level[j] = L + 1;
+                        parent[j] = node;
+                        ++j;
+                    }
+                    prev = p;
+                }
+            }
+            first_child[node] = k ? fc : -1;
+            n_child[node] = k;
+        }
+        run += tot;
+    }
+}
+
+// Sum over the 8 lanes of a node's lane group.
+__device__ inline double group_sum(double v)
+{
+    v += __shfl_xor(v, 1, 8);
+    v += __shfl_xor(v, 2, 8);
+    v += __shfl_xor(v, 4, 8);
+    return v;
+}
+
+// Moments of the nodes of one level, in FP64: a leaf from its particles, an
+// internal node from its children (parallel-axis theorem).  Eight lanes take
+// a node, each a share of its particles or children; the centre is the
+// mass-weighted mean (the particle-count-weighted mean when the mass is zero).
 __global__ void __launch_bounds__(256) k_moments(int L, const int *__restrict__ lvl,
                                                  const unsigned *__restrict__ w,
                                                  const int *__restrict__ begin,
@@ -358,60 +384,64 @@ __global__ void __launch_bounds__(256) k_moments(int L, const int *__restrict__ 
 {
     if (w[kWordOverflow]) return;
     const int off = lvl[L], n_level = lvl[L + 1] - off;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n_level; i += gridDim.x * 256) {
-    const int node = off + i;
-    const int nch = n_child[node];
-    NodeMoments r;
-    if (nch == 0) {
-        const int b = begin[node], c = count[node];
-        double M = 0, sx = 0, sy = 0, sz = 0;
-        for (int k = b; k < b + c; ++k) {
-            const double m = ms[k];
+    const int g = (int)threadIdx.x >> 3, j = (int)threadIdx.x & 7;
+    for (int i0 = (int)blockIdx.x * 32; i0 < n_level; i0 += (int)gridDim.x * 32) {
+        const int i = i0 + g;
+        const bool valid = i < n_level;
+        const int node = off + (valid ? i : 0);
+        const int nch = valid ? n_child[node] : 0;
+        // this lane's items: particles [k0, k1) of a leaf, or children
+        const int k0 = nch ? first_child[node] : begin[node];
+        const int k1 = valid ? k0 + (nch ? nch : count[node]) : k0;
+        auto item = [&](int k, double *m, double *x, double *y, double *z, double *cnt) {
+            if (nch) {
+                const NodeMoments &q = mom[k];
+                *m = q.m, *x = q.cx, *y = q.cy, *z = q.cz, *cnt = count[k];
+            } else {
+                *m = ms[k], *x = xs[k], *y = ys[k], *z = zs[k], *cnt = 1.0;
+            }
+        };
+        double M = 0, sx = 0, sy = 0, sz = 0, np = 0, px = 0, py = 0, pz = 0;
+        for (int k = k0 + j; k < k1; k += 8) {
+            double m, x, y, z, cnt;
+            item(k, &m, &x, &y, &z, &cnt);
             M += m;
-            sx += m * xs[k];
-            sy += m * ys[k];
-            sz += m * zs[k];
+            sx += m * x, sy += m * y, sz += m * z;
+            np += cnt;
+            px += cnt * x, py += cnt * y, pz += cnt * z;
         }
-        if (M != 0.0) {
+        M = group_sum(M);
+        sx = group_sum(sx), sy = group_sum(sy), sz = group_sum(sz);
+        np = group_sum(np);
+        px = group_sum(px), py = group_sum(py), pz = group_sum(pz);
+        if (M != 0.0)
             sx /= M, sy /= M, sz /= M;
-        } else {
-            sx = sy = sz = 0.0;
-            for (int k = b; k < b + c; ++k) sx += xs[k], sy += ys[k], sz += zs[k];
-            sx /= c, sy /= c, sz /= c;
-        }
+        else if (np != 0.0)
+            sx = px / np, sy = py / np, sz = pz / np;
         double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
-        for (int k = b; k < b + c; ++k) {
-            const double m = ms[k];
-            const double dx = xs[k] - sx, dy = ys[k] - sy, dz = zs[k] - sz;
+        for (int k = k0 + j; k < k1; k += 8) {
+            double m, x, y, z, cnt;
+            item(k, &m, &x, &y, &z, &cnt);
+            if (nch) {
+                const NodeMoments &q = mom[k];
+                a0 += q.sxx, a1 += q.syy, a2 += q.szz, a3 += q.sxy, a4 += q.sxz, a5 += q.syz;
+            }
+            const double dx = x - sx, dy = y - sy, dz = z - sz;
             a0 += m * dx * dx, a1 += m * dy * dy, a2 += m * dz * dz;
             a3 += m * dx * dy, a4 += m * dx * dz, a5 += m * dy * dz;
         }
-        r = {M, sx, sy, sz, a0, a1, a2, a3, a4, a5};
-    } else {
-        const int fc = first_child[node];
-        double M = 0, sx = 0, sy = 0, sz = 0, np = 0, px = 0, py = 0, pz = 0;
-        for (int k = fc; k < fc + nch; ++k) {
-            const NodeMoments &q = mom[k];
-            M += q.m;
-            sx += q.m * q.cx, sy += q.m * q.cy, sz += q.m * q.cz;
-            const double cnt = count[k];
-            np += cnt;
-            px += cnt * q.cx, py += cnt * q.cy, pz += cnt * q.cz;
+        a0 = group_sum(a0), a1 = group_sum(a1), a2 = group_sum(a2);
+        a3 = group_sum(a3), a4 = group_sum(a4), a5 = group_sum(a5);
+        // the group stores the 10 doubles side by side: lane j field j, lanes 0
+        // and 1 also fields 8 and 9
+        if (valid) {
+            static_assert(sizeof(NodeMoments) == 10 * sizeof(double), "NodeMoments layout");
+            double *dst = reinterpret_cast<double *>(mom + node);
+            const double v = j == 0 ? M : j == 1 ? sx : j == 2 ? sy : j == 3 ? sz
+                           : j == 4 ? a0 : j == 5 ? a1 : j == 6 ? a2 : a3;
+            dst[j] = v;
+            if (j < 2) dst[8 + j] = j == 0 ? a4 : a5;
         }
-        if (M != 0.0)
-            sx /= M, sy /= M, sz /= M;
-        else
-            sx = px / np, sy = py / np, sz = pz / np;
-        double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
-        for (int k = fc; k < fc + nch; ++k) {
-            const NodeMoments &q = mom[k];
-            const double dx = q.cx - sx, dy = q.cy - sy, dz = q.cz - sz;
-            a0 += q.sxx + q.m * dx * dx, a1 += q.syy + q.m * dy * dy, a2 += q.szz + q.m * dz * dz;
-            a3 += q.sxy + q.m * dx * dy, a4 += q.sxz + q.m * dx * dz, a5 += q.syz + q.m * dy * dz;
-        }
-        r = {M, sx, sy, sz, a0, a1, a2, a3, a4, a5};
-    }
-    mom[node] = r;
     }
 }
 
@@ -891,11 +921,13 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
                    grow(&t.goff, &dummy, cap + 1) && grow(&t.items, &dummy, cap));
         t.group_cap = (int)cap;
     }
-    if (t.nc_cap < 2 * (n + 1) + kScanBlocks + 1) {  // counts, scan, chunk sums
+    // per level: children per node, chunk sums, child bounds (7 per node)
+    const long long nc_need = 8LL * (n + 1) + kSplitBlocks + 1;
+    if (t.nc_cap < nc_need) {
         long long dummy = 0;
-        const long long cap = 2LL * (std::max(n, 1024) + 1) + kScanBlocks + 1;
+        const long long cap = 8LL * (std::max(n, 1024) + 1) + kSplitBlocks + 1;
         TREE_ALLOC(grow(&t.nc, &dummy, cap));
-        t.nc_cap = (int)cap;
+        t.nc_cap = cap;
     }
     long long want = std::max<long long>(2LL * n + 64, 4096);
     for (;;) {
@@ -918,29 +950,25 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
         hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, n, t.begin, t.count, t.level, t.parent,
                            t.lvl);
         TREE_HIP(hipGetLastError());
-        // level L has at most min(n, 8^L) nodes: the scan's length
+        // level L has at most min(n, 8^L) nodes
         auto level_bound = [&](int L) {
             long long b = 1;
             for (int k = 0; k < L && b < n; ++k) b *= 8;
             return (int)std::min<long long>(b, n);
         };
-        int *cnt = t.nc, *scan = t.nc + (n + 1), *bsum = t.nc + 2 * (n + 1);
+        int *cnt = t.nc, *bsum = t.nc + (n + 1), *bnd = bsum + kSplitBlocks + 1;
         for (int L = 0; L <= kTreeMaxLevel; ++L) {
-            const int grid = std::min(blocks_of(level_bound(L), 256), 16 * num_cu);
-            hipLaunchKernelGGL(k_split_count, dim3(grid), dim3(256), 0, s, L, n_leaf, t.lvl,
-                               t.begin, t.count, t.key, cnt, t.word);
-            hipLaunchKernelGGL(k_scan_sums, dim3(kScanBlocks), dim3(256), 0, s, L, t.lvl, t.word,
-                               cnt, bsum);
-            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, t.word, bsum);
-            hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(256), 0, s, L, t.lvl, t.word,
-                               cnt, bsum, scan);
-            hipLaunchKernelGGL(k_split_write, dim3(grid), dim3(256), 0, s, L, n_leaf, cap, t.lvl,
-                               t.key, scan, t.begin, t.count, t.level, t.first_child, t.n_child,
+            hipLaunchKernelGGL(k_split_count, dim3(kSplitBlocks), dim3(256), 0, s, L, n_leaf,
+                               t.lvl, t.begin, t.count, t.key, cnt, bnd, bsum, t.word);
+            hipLaunchKernelGGL(k_split_scan, dim3(1), dim3(256), 0, s, L, cap, t.lvl, bsum,
+                               t.word);
+            hipLaunchKernelGGL(k_split_write, dim3(kSplitBlocks), dim3(256), 0, s, L, t.lvl, cnt,
+                               bnd, bsum, t.begin, t.count, t.level, t.first_child, t.n_child,
                                t.parent, t.word);
             TREE_HIP(hipGetLastError());
         }
         for (int L = kTreeMaxLevel; L >= 0; --L) {
-            const int grid = std::min(blocks_of(level_bound(L), 256), 16 * num_cu);
+            const int grid = std::min(blocks_of(level_bound(L), 32), 16 * num_cu);
             hipLaunchKernelGGL(k_moments, dim3(grid), dim3(256), 0, s, L, t.lvl, t.word, t.begin,
                                t.count, t.first_child, t.n_child, t.xs, t.ys, t.zs, t.ms, t.mom);
         }
