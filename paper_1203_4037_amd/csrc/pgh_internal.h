@@ -194,6 +194,7 @@ struct TreeState {
     int *perm = nullptr, *iota = nullptr;
     float *xs = nullptr, *ys = nullptr, *zs = nullptr, *ms = nullptr;
     float4 *xm = nullptr;  // the same particles packed (x, y, z, m)
+    float4 *xin = nullptr;  // the input particles packed, in input order
     int *mark = nullptr;  // group id at the first particle of each group, else -1
     // nodes, capacity node_cap (breadth first, each level in key order); the
     // moment, centre-of-mass and walk-record arrays have node_cap entries too,

@@ -122,32 +122,33 @@ __device__ inline unsigned long long cell_of(float v, float lo, float scale)
     return (unsigned long long)f;
 }
 
+// Keys in input order, with the particles packed (x, y, z, m) in input order
+// for the gather (one 16-byte load per particle instead of four 4-byte ones).
 __global__ void __launch_bounds__(256) k_keys(int n, const float *__restrict__ x,
                                               const float *__restrict__ y,
-                                              const float *__restrict__ z, float lox, float loy,
+                                              const float *__restrict__ z,
+                                              const float *__restrict__ m, float lox, float loy,
                                               float loz, float scale,
                                               unsigned long long *__restrict__ key,
-                                              int *__restrict__ iota)
+                                              int *__restrict__ iota, float4 *__restrict__ xin)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const unsigned long long kx = cell_of(x[i], lox, scale), ky = cell_of(y[i], loy, scale),
-                             kz = cell_of(z[i], loz, scale);
+    const float px = x[i], py = y[i], pz = z[i];
+    const unsigned long long kx = cell_of(px, lox, scale), ky = cell_of(py, loy, scale),
+                             kz = cell_of(pz, loz, scale);
     key[i] = (spread3(kx) << 2) | (spread3(ky) << 1) | spread3(kz);
     iota[i] = i;
+    xin[i] = make_float4(px, py, pz, m[i]);
 }
 
 __global__ void __launch_bounds__(256) k_gather(int n, const int *__restrict__ perm,
-                                                const float *__restrict__ x,
-                                                const float *__restrict__ y,
-                                                const float *__restrict__ z,
-                                                const float *__restrict__ m, float *xs, float *ys,
-                                                float *zs, float *ms, float4 *xm)
+                                                const float4 *__restrict__ xin, float *xs,
+                                                float *ys, float *zs, float *ms, float4 *xm)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= n) return;
-    const int i = perm[r];
-    const float4 v = make_float4(x[i], y[i], z[i], m[i]);
+    const float4 v = xin[perm[r]];
     xs[r] = v.x;
     ys[r] = v.y;
     zs[r] = v.z;
@@ -827,8 +828,8 @@ int ensure_tmp(TreeState &t, int n, std::string &err)
 
 void tree_release(TreeState &t)
 {
-    void *ps[] = {t.key, t.key_in, t.perm, t.iota, t.xs, t.ys, t.zs, t.ms, t.mark, t.begin, t.count, t.level, t.first_child, t.n_child,
-                  t.parent, t.nc, t.mom, t.com, t.pp, t.groups, t.glo, t.ghi, t.glen, t.goff,
+    void *ps[] = {t.key, t.key_in, t.perm, t.iota, t.xs, t.ys, t.zs, t.ms, t.mark, t.xin,
+                  t.begin, t.count, t.level, t.first_child, t.n_child, t.parent, t.nc, t.mom, t.com, t.pp, t.groups, t.glo, t.ghi, t.glen, t.goff,
                   t.items, t.xj, t.yj, t.zj, t.mj, t.src, t.tmp, t.word, t.count_out, t.rc2, t.lvl,
                   t.xm, t.nrec};
     for (void *p : ps) (void)hipFree(p);
@@ -866,7 +867,8 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
                   grow(&t.perm, &dummy, cap) && grow(&t.iota, &dummy, cap) &&
                   grow(&t.xs, &dummy, cap) && grow(&t.ys, &dummy, cap) &&
                   grow(&t.zs, &dummy, cap) && grow(&t.ms, &dummy, cap) &&
-                  grow(&t.mark, &dummy, cap) && grow(&t.xm, &dummy, cap);
+                  grow(&t.mark, &dummy, cap) && grow(&t.xm, &dummy, cap) &&
+                  grow(&t.xin, &dummy, cap);
         if (!ok) {
             t.n_cap = 0;
             err = "tree: device allocation failed";
@@ -899,13 +901,13 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
     t.frame[0] = lo[0], t.frame[1] = lo[1], t.frame[2] = lo[2], t.frame[3] = ext;
     t.frame[4] = scale;
     // 2. keys, sort, gather
-    hipLaunchKernelGGL(k_keys, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, x, y, z, lo[0], lo[1],
-                       lo[2], scale, t.key_in, t.iota);
+    hipLaunchKernelGGL(k_keys, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, x, y, z, m, lo[0],
+                       lo[1], lo[2], scale, t.key_in, t.iota, t.xin);
     TREE_HIP(hipGetLastError());
     size_t tb = t.tmp_bytes;
     TREE_HIP(hipcub::DeviceRadixSort::SortPairs(t.tmp, tb, t.key_in, t.key, t.iota, t.perm, n, 0,
                                                 63, s));
-    hipLaunchKernelGGL(k_gather, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, t.perm, x, y, z, m,
+    hipLaunchKernelGGL(k_gather, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, t.perm, t.xin,
                        t.xs, t.ys, t.zs, t.ms, t.xm);
     TREE_HIP(hipGetLastError());
     // 3-5. octree, moments, pseudo-particles and groups, launched with no
