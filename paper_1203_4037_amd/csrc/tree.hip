@@ -378,10 +378,7 @@ __global__ void __launch_bounds__(256) k_moments(int L, const int *__restrict__ 
                                                  const int *__restrict__ count,
                                                  const int *__restrict__ first_child,
                                                  const int *__restrict__ n_child,
-                                                 const float *__restrict__ xs,
-                                                 const float *__restrict__ ys,
-                                                 const float *__restrict__ zs,
-                                                 const float *__restrict__ ms, NodeMoments *mom)
+                                                 const float4 *__restrict__ xm, NodeMoments *mom)
 {
     if (w[kWordOverflow]) return;
     const int off = lvl[L], n_level = lvl[L + 1] - off;
@@ -399,7 +396,8 @@ __global__ void __launch_bounds__(256) k_moments(int L, const int *__restrict__ 
                 const NodeMoments &q = mom[k];
                 *m = q.m, *x = q.cx, *y = q.cy, *z = q.cz, *cnt = count[k];
             } else {
-                *m = ms[k], *x = xs[k], *y = ys[k], *z = zs[k], *cnt = 1.0;
+                const float4 p = xm[k];
+                *m = p.w, *x = p.x, *y = p.y, *z = p.z, *cnt = 1.0;
             }
         };
         double M = 0, sx = 0, sy = 0, sz = 0, np = 0, px = 0, py = 0, pz = 0;
@@ -972,7 +970,7 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
         for (int L = kTreeMaxLevel; L >= 0; --L) {
             const int grid = std::min(blocks_of(level_bound(L), 32), 16 * num_cu);
             hipLaunchKernelGGL(k_moments, dim3(grid), dim3(256), 0, s, L, t.lvl, t.word, t.begin,
-                               t.count, t.first_child, t.n_child, t.xs, t.ys, t.zs, t.ms, t.mom);
+                               t.count, t.first_child, t.n_child, t.xm, t.mom);
         }
         const int gnodes = std::min(blocks_of(cap, 256), 16 * num_cu);
         hipLaunchKernelGGL(k_pseudo, dim3(gnodes), dim3(256), 0, s, t.lvl, t.word, t.mom, t.quad,
