@@ -454,7 +454,10 @@ __device__ void jacobi3(const NodeMoments &q, double w[3], double V[3][3])
     for (int sweep = 0; sweep < 32; ++sweep) {
         const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
         const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
-        if (off == 0.0 || off <= 1e-40 * dia) break;
+        // converged when the off-diagonal elements are at FP64 rounding of the
+        // diagonal (rotations leave residues of that size, so a tighter
+        // bound only runs sweeps that change nothing)
+        if (off == 0.0 || off <= 1e-30 * dia) break;
         for (int p = 0; p < 2; ++p)
             for (int r = p + 1; r < 3; ++r) {
                 const double apr = A[p][r];
