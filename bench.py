@@ -42,14 +42,16 @@ TABLE_FLOPS = 20  # per interaction, this project's count of the FP32 ops of the
 MEASURED_TRAFFIC = {
     "variant": "ki=1 jt=256 u=8", "rsqrt_refine": 0,
     "sources_sha256": "45767ac6423b39e480e1c3d03f700d07d892f8f3123becd602779e5c99a40e2b",
-    "fetch_kib": 22724.7, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
+    "fetch_kib": 22725.8, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
+    # SQ_INSTS_VALU_FLOPS_FP32 x 64 / interactions of the same kernel (FMA = 2, rsq = 1)
+    "valu_flops_per_interaction": 21.0,
 }
 KERNEL_SOURCES = ("paper_1203_4037_amd/csrc/newton.hip", "paper_1203_4037_amd/csrc/pairs.h")
 
 
-def measured_traffic(variant_name, refine):
-    """HBM bytes per launch of the headline kernel, or None when the counters
-    were taken on another variant, rsqrt mode or kernel sources."""
+def counters_valid(variant_name, refine):
+    """Whether the recorded counters were taken on this variant, rsqrt mode
+    and kernel sources."""
     import hashlib
     h = hashlib.sha256()
     root = os.path.dirname(os.path.abspath(__file__))
@@ -57,9 +59,16 @@ def measured_traffic(variant_name, refine):
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
     t = MEASURED_TRAFFIC
-    if (variant_name != t["variant"] or refine != t["rsqrt_refine"]
-            or h.hexdigest() != t["sources_sha256"]):
+    return (variant_name == t["variant"] and refine == t["rsqrt_refine"]
+            and h.hexdigest() == t["sources_sha256"])
+
+
+def measured_traffic(variant_name, refine):
+    """HBM bytes per launch of the headline kernel, or None when the counters
+    were taken on another variant, rsqrt mode or kernel sources."""
+    if not counters_valid(variant_name, refine):
         return None
+    t = MEASURED_TRAFFIC
     return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0
 
 
@@ -725,6 +734,9 @@ def main():
     inter = float(n) * n
     value = inter / r["sec"]
     achieved = NEWTON_FLOPS * inter / (r["kern_ms"] / 1e3) / 1e12
+    hw_flops = (MEASURED_TRAFFIC["valu_flops_per_interaction"]
+                if counters_valid(r["variant_name"], r["refine"]) else None)
+    hw_tflops = hw_flops * inter / (r["kern_ms"] / 1e3) / 1e12 if hw_flops else None
     line = {
         "metric": "interactions/sec on 1 MI355X (Newton, LUT) + % FP32 VALU peak; batched vs all-pairs; fwd+bwd/fwd",
         "value": value,
@@ -749,7 +761,13 @@ def main():
                      "kernel": "k_newton_allpairs", "kernel_ms": r["kern_ms"],
                      "kernel_ms_median": r["kern_ms_median"], "kernel_ms_min": r["kern_ms_min"],
                      "flops_per_interaction": NEWTON_FLOPS,
-                     "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS},
+                     # the FP32 flops the VALU counters count for this kernel (21 per
+                     # interaction, not the paper's 38), against the unpacked-instruction
+                     # ceiling; null when the counters were taken on other sources
+                     "valu_flops_per_interaction": hw_flops,
+                     "valu_tflops": hw_tflops,
+                     "valu_frac_of_unpacked_peak": (hw_tflops / PEAK_FP32_UNPACKED_TFLOPS
+                                                    if hw_tflops else None)},
     }
     if not args.no_extras:
         ex = {"newton_small": newton_small(torch, pgh, synth),
