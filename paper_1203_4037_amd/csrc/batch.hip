@@ -265,11 +265,14 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
 
         if (tk.n_parts <= 1) {
             if (active && ph == 0) {
-                const int io = a.out_perm ? a.out_perm[i] : i;  // output row
-                a.ax[io] = tx;
-                a.ay[io] = ty;
-                a.az[io] = tz;
-                if (PHI) a.phi[io] = tp;
+                if (a.out4) {
+                    a.out4[i] = make_float4(tx, ty, tz, tp);
+                } else {
+                    a.ax[i] = tx;
+                    a.ay[i] = ty;
+                    a.az[i] = tz;
+                    if (PHI) a.phi[i] = tp;
+                }
             }
         } else if (ph == 0) {
             // partial sums of one part of a split j-list; k_combine adds the
@@ -311,7 +314,11 @@ __global__ void __launch_bounds__(64) k_combine(CombineArgs a)
         s.z += v.z;
         s.w += v.w;
     }
-    const int i = a.out_perm ? a.out_perm[ch.i_off + lane] : ch.i_off + lane;
+    const int i = ch.i_off + lane;
+    if (a.out4) {
+        a.out4[i] = s;
+        return;
+    }
     a.ax[i] = s.x;
     a.ay[i] = s.y;
     a.az[i] = s.z;
@@ -374,7 +381,7 @@ hipError_t launch(BatchKernel k, const BatchArgs &a0, size_t lds, int num_cu, hi
     if (e != hipSuccess) return e;
     if (a.n_chunks == 0) return hipSuccess;
     CombineArgs c{a.n_chunks, a.chunks, a.partial, a.ax, a.ay, a.az, phi ? a.phi : nullptr,
-                  a.out_perm};
+                  a.out4};
     hipLaunchKernelGGL(k_combine, dim3(a.n_chunks), dim3(64), 0, s, c);
     return hipGetLastError();
 }
@@ -400,8 +407,9 @@ const char *batch_variant_name(int family, int v)
 hipError_t launch_newton_batch(const BatchArgs &a, int variant, bool refine, bool guard,
                                int num_cu, hipStream_t s)
 {
-    return launch(newton_kernel(refine, guard, a.phi != nullptr, variant == 1), a, 0, num_cu, s,
-                  a.phi != nullptr);
+    // packed outputs always carry the potential
+    const bool phi = a.phi != nullptr || a.out4 != nullptr;
+    return launch(newton_kernel(refine, guard, phi, variant == 1), a, 0, num_cu, s, phi);
 }
 
 hipError_t launch_table_batch(const BatchArgs &a, int variant, int num_cu, hipStream_t s)

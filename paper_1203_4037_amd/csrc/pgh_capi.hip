@@ -1252,15 +1252,16 @@ int pgh_tree_newton(pgh_ctx *c, pgh_tree *t, float *ax, float *ay, float *az, fl
     if (s.n == 0) return PGH_OK;
     if (!ax || !ay || !az) return fail(c, PGH_EINVAL, "NULL output array");
     DeviceGuard g(c->device);
-    // the batched kernel writes each particle's row straight to its input position
+    // the batched kernel writes packed results in key order (coalesced), and
+    // one gather per particle puts them in the input order
     BatchArgs a = batch_args(c, t->plan);
     a.xi = s.xs, a.yi = s.ys, a.zi = s.zs, a.eps2i = nullptr;
     a.xj = s.xj, a.yj = s.yj, a.zj = s.zj, a.mj = s.mj;
-    a.ax = ax, a.ay = ay, a.az = az, a.phi = phi;
-    a.out_perm = s.perm;
+    a.out4 = s.res;
     const bool guard = !(c->eps2_all > 0.f);
     const int v = std::max(0, c->variant[PGH_FAMILY_NEWTON_BATCH]);
     PGH_HIP(c, launch_newton_batch(a, v, c->refine != 0, guard, c->num_cu, c->stream));
+    PGH_HIP(c, launch_tree_outputs(s, ax, ay, az, phi, c->stream));
     return PGH_OK;
 }
 

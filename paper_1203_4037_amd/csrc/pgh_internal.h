@@ -65,9 +65,9 @@ struct BatchArgs {
     int E, F;
     float c, smax;
     const float2 *ptable;  // potential table (with phi), or NULL
-    // NULL, or the output row of each i-particle: row i is written to
-    // out_perm[i] (the tree's key order back to the caller's order)
-    const int *out_perm;
+    // NULL, or packed outputs (ax, ay, az, phi) per i-particle in place of
+    // the four arrays (Newton only; the potential is then always computed)
+    float4 *out4;
 };
 
 struct CombineArgs {
@@ -75,7 +75,7 @@ struct CombineArgs {
     const SplitChunk *chunks;
     const float4 *partial;
     float *ax, *ay, *az, *phi;
-    const int *out_perm;  // as in BatchArgs
+    float4 *out4;  // as in BatchArgs
 };
 
 // Copies of the table gradient that the workgroups of the adjoint add into
@@ -195,6 +195,8 @@ struct TreeState {
     float *xs = nullptr, *ys = nullptr, *zs = nullptr, *ms = nullptr;
     float4 *xm = nullptr;  // the same particles packed (x, y, z, m)
     float4 *xin = nullptr;  // the input particles packed, in input order
+    int *inv = nullptr;     // the key-order rank of each input particle
+    float4 *res = nullptr;  // the force in key order (ax, ay, az, phi)
     int *mark = nullptr;  // group id at the first particle of each group, else -1
     // nodes, capacity node_cap (breadth first, each level in key order); the
     // moment, centre-of-mass and walk-record arrays have node_cap entries too,
@@ -247,5 +249,9 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
 int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t s,
               std::string &err);
 void tree_release(TreeState &t);
+// Writes the force held in t.res (key order) to the caller's arrays in the
+// input order (phi may be NULL).
+hipError_t launch_tree_outputs(const TreeState &t, float *ax, float *ay, float *az, float *phi,
+                               hipStream_t s);
 
 }  // namespace pgh

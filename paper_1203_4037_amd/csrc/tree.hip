@@ -142,13 +142,17 @@ __global__ void __launch_bounds__(256) k_keys(int n, const float *__restrict__ x
     xin[i] = make_float4(px, py, pz, m[i]);
 }
 
+// The particles in key order, and each particle's rank (inv[perm[r]] = r).
 __global__ void __launch_bounds__(256) k_gather(int n, const int *__restrict__ perm,
                                                 const float4 *__restrict__ xin, float *xs,
-                                                float *ys, float *zs, float *ms, float4 *xm)
+                                                float *ys, float *zs, float *ms, float4 *xm,
+                                                int *__restrict__ inv)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= n) return;
-    const float4 v = xin[perm[r]];
+    const int i = perm[r];
+    inv[i] = r;
+    const float4 v = xin[i];
     xs[r] = v.x;
     ys[r] = v.y;
     zs[r] = v.z;
@@ -829,7 +833,7 @@ int ensure_tmp(TreeState &t, int n, std::string &err)
 
 void tree_release(TreeState &t)
 {
-    void *ps[] = {t.key, t.key_in, t.perm, t.iota, t.xs, t.ys, t.zs, t.ms, t.mark, t.xin,
+    void *ps[] = {t.key, t.key_in, t.perm, t.iota, t.xs, t.ys, t.zs, t.ms, t.mark, t.xin, t.inv, t.res,
                   t.begin, t.count, t.level, t.first_child, t.n_child, t.parent, t.nc, t.mom, t.com, t.pp, t.groups, t.glo, t.ghi, t.glen, t.goff,
                   t.items, t.xj, t.yj, t.zj, t.mj, t.src, t.tmp, t.word, t.count_out, t.rc2, t.lvl,
                   t.xm, t.nrec};
@@ -869,7 +873,8 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
                   grow(&t.xs, &dummy, cap) && grow(&t.ys, &dummy, cap) &&
                   grow(&t.zs, &dummy, cap) && grow(&t.ms, &dummy, cap) &&
                   grow(&t.mark, &dummy, cap) && grow(&t.xm, &dummy, cap) &&
-                  grow(&t.xin, &dummy, cap);
+                  grow(&t.xin, &dummy, cap) && grow(&t.inv, &dummy, cap) &&
+                  grow(&t.res, &dummy, cap);
         if (!ok) {
             t.n_cap = 0;
             err = "tree: device allocation failed";
@@ -909,7 +914,7 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
     TREE_HIP(hipcub::DeviceRadixSort::SortPairs(t.tmp, tb, t.key_in, t.key, t.iota, t.perm, n, 0,
                                                 63, s));
     hipLaunchKernelGGL(k_gather, dim3(blocks_of(n, 256)), dim3(256), 0, s, n, t.perm, t.xin,
-                       t.xs, t.ys, t.zs, t.ms, t.xm);
+                       t.xs, t.ys, t.zs, t.ms, t.xm, t.inv);
     TREE_HIP(hipGetLastError());
     // 3-5. octree, moments, pseudo-particles and groups, launched with no
     // wait: the level sizes stay in a device table (lvl).  The node arrays
@@ -1126,6 +1131,31 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
     t.interactions = inter;
     t.walked = 1;
     return PGH_OK;
+}
+
+// The tree force in the input order: particle i's packed result (ax, ay, az,
+// phi) sits at its rank inv[i]; a coalesced write of each output array from
+// one 16-byte gather.
+__global__ void __launch_bounds__(256) k_tree_out(int n, const int *__restrict__ inv,
+                                                  const float4 *__restrict__ res, float *ax,
+                                                  float *ay, float *az, float *phi)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float4 v = res[inv[i]];
+    ax[i] = v.x;
+    ay[i] = v.y;
+    az[i] = v.z;
+    if (phi) phi[i] = v.w;
+}
+
+hipError_t launch_tree_outputs(const TreeState &t, float *ax, float *ay, float *az, float *phi,
+                               hipStream_t s)
+{
+    if (t.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tree_out, dim3(blocks_of(t.n, 256)), dim3(256), 0, s, t.n, t.inv, t.res,
+                       ax, ay, az, phi);
+    return hipGetLastError();
 }
 
 }  // namespace pgh
