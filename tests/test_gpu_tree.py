@@ -388,28 +388,31 @@ def test_full_size_plummer_sampled(pgh, ctx):
         t.free()
 
 
-@pytest.mark.parametrize("n,n_crit,theta,quad", [(1 << 19, 64, 0.75, False),
-                                                  (1 << 20, 1024, 0.5, True)])
-def test_device_expanded_plan_matches_host_plan(pgh, ctx, n, n_crit, theta, quad):
+@pytest.mark.parametrize("n,n_crit,thetas,quad", [(1 << 19, 64, (0.75, 0.4), False),
+                                                   (1 << 20, 1024, (0.5,), True)])
+def test_device_expanded_plan_matches_host_plan(pgh, ctx, n, n_crit, thetas, quad):
     """A walk's plan is expanded on the device from its compact form; a plan
     of the same lists made on the host (pgh_plan_create) holds the same tasks,
     so the batched force over the tree's key-ordered arrays with it gives the
     tree force bit for bit (groups of 64 pair their partly filled chunks,
-    groups of 1024 with theta = 0.5 cut their long lists into parts)."""
+    groups of 1024 with theta = 0.5 cut their long lists into parts; a second
+    walk of one build writes a larger plan into the same plan object)."""
     x, y, z = synth.plummer(n, 345)
     m = synth.equal_masses(n)
     ctx.set_eps_to_all(1.0 / 512)
-    t = ctx.tree().build(*to_dev(x, y, z, m), n_leaf=8, n_crit=n_crit, quad=quad).walk(theta)
-    got = np.stack(to_host(*t.newton()))
-    items = t.get("items")
+    t = ctx.tree().build(*to_dev(x, y, z, m), n_leaf=8, n_crit=n_crit, quad=quad)
     perm = t.get("perm")
     keyed = to_dev(*(t.get(f) for f in ("x", "y", "z")))
-    lists = to_dev(*(t.get(f) for f in ("list_x", "list_y", "list_z", "list_m")))
-    plan = ctx.plan(items, n, int((items[:, 2].astype(np.int64) + items[:, 3]).max()))
-    ref = np.stack(to_host(*plan.newton(*keyed, *lists)))
-    assert plan.interactions == int((items[:, 1].astype(np.int64) * items[:, 3]).sum())
-    assert np.array_equal(got[:, perm], ref)
-    plan.free()
+    for theta in thetas:
+        t.walk(theta)
+        got = np.stack(to_host(*t.newton()))
+        items = t.get("items")
+        lists = to_dev(*(t.get(f) for f in ("list_x", "list_y", "list_z", "list_m")))
+        plan = ctx.plan(items, n, int((items[:, 2].astype(np.int64) + items[:, 3]).max()))
+        ref = np.stack(to_host(*plan.newton(*keyed, *lists)))
+        assert plan.interactions == int((items[:, 1].astype(np.int64) * items[:, 3]).sum())
+        assert np.array_equal(got[:, perm], ref), theta
+        plan.free()
     t.free()
 
 
