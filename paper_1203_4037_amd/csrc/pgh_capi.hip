@@ -313,8 +313,10 @@ int plan_fill(pgh_ctx *c, pgh_plan *p, int n_items, const pgh_item *items, int n
                                c->stream) != hipSuccess) ||
         (n_c && hipMemcpyAsync(p->chunks, pin + n_t * sizeof(Task), n_c * sizeof(SplitChunk),
                                hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipStreamSynchronize(c->stream);  // no copy may still read the pinned buffer
         return fail(c, PGH_EHIP, "uploading the plan failed");
+    }
     set_plan_counts(p, n_items, ni_total, nj_total, (int)n_t, hp.nq, hp.q_begin, hp.interactions,
                     (int)n_c, hp.n_slots, hp.ordered);
     return PGH_OK;
@@ -374,8 +376,10 @@ int plan_fill_device(pgh_ctx *c, pgh_plan *p, int n_items, const pgh_item *items
         (n_d && hipMemcpyAsync(p->desc, c->pin, n_d * sizeof(PlanDesc), hipMemcpyHostToDevice,
                                c->stream) != hipSuccess) ||
         launch_plan_expand(a, p->sort_temp, tb, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipStreamSynchronize(c->stream);  // no copy may still read the pinned buffer
         return fail(c, PGH_EHIP, "expanding the plan failed");
+    }
     set_plan_counts(p, n_items, ni_total, nj_total, (int)n_t, dp.nq, dp.q_begin, dp.interactions,
                     (int)n_c, dp.n_slots, dp.ordered);
     return PGH_OK;
