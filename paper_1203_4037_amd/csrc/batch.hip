@@ -145,17 +145,19 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
         float4 pre, pre2;
         auto load = [&](int tile) {
             const int jj = tile * 64 + lane;
+            auto record = [&](int j) {
+                if (a.jxm) {
+                    float4 v = a.jxm[j];
+                    v.w *= mscale;
+                    return v;
+                }
+                return make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j] * mscale);
+            };
             pre = make_float4(kFar, kFar, kFar, 0.f);
-            if (jj < tk.n_j) {
-                const int j = tk.j_off + jj;
-                pre = make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j] * mscale);
-            }
+            if (jj < tk.n_j) pre = record(tk.j_off + jj);
             if (paired) {
                 pre2 = make_float4(kFar, kFar, kFar, 0.f);
-                if (jj < tk.n_j2) {
-                    const int j = tk.j_off2 + jj;
-                    pre2 = make_float4(a.xj[j], a.yj[j], a.zj[j], a.mj[j] * mscale);
-                }
+                if (jj < tk.n_j2) pre2 = record(tk.j_off2 + jj);
             }
         };
         auto store = [&](int b) {

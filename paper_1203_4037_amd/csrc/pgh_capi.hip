@@ -1260,7 +1260,7 @@ int pgh_tree_newton(pgh_ctx *c, pgh_tree *t, float *ax, float *ay, float *az, fl
     // one gather per particle puts them in the input order
     BatchArgs a = batch_args(c, t->plan);
     a.xi = s.xs, a.yi = s.ys, a.zi = s.zs, a.eps2i = nullptr;
-    a.xj = s.xj, a.yj = s.yj, a.zj = s.zj, a.mj = s.mj;
+    a.jxm = s.xmj;
     a.out4 = s.res;
     const bool guard = !(c->eps2_all > 0.f);
     const int v = std::max(0, c->variant[PGH_FAMILY_NEWTON_BATCH]);
@@ -1327,10 +1327,10 @@ int pgh_tree_get(pgh_ctx *c, const pgh_tree *t, int field, void *dst, long long 
         if (!s.walked) return fail(c, PGH_ESTATE, "walk the tree first");
         src = s.items, n = s.n_groups, elem = sizeof(pgh_item);
         break;
-    case PGH_TREE_LIST_X: src = s.xj, n = s.n_entries; break;
-    case PGH_TREE_LIST_Y: src = s.yj, n = s.n_entries; break;
-    case PGH_TREE_LIST_Z: src = s.zj, n = s.n_entries; break;
-    case PGH_TREE_LIST_M: src = s.mj, n = s.n_entries; break;
+    case PGH_TREE_LIST_X:
+    case PGH_TREE_LIST_Y:
+    case PGH_TREE_LIST_Z:
+    case PGH_TREE_LIST_M: n = s.n_entries; break;  // one component of the packed entries
     case PGH_TREE_LIST_SRC:
         if (!s.record_src) return fail(c, PGH_ESTATE, "walk with record_src to keep sources");
         src = s.src, n = s.n_entries;
@@ -1342,6 +1342,19 @@ int pgh_tree_get(pgh_ctx *c, const pgh_tree *t, int field, void *dst, long long 
     if (capacity < n) return fail(c, PGH_ERANGE, "destination too small for the tree field");
     if (!dst) return fail(c, PGH_EINVAL, "NULL destination");
     DeviceGuard g(c->device);
+    if (field >= PGH_TREE_LIST_X && field <= PGH_TREE_LIST_M) {
+        float *tmp = nullptr;
+        if (hipMalloc((void **)&tmp, sizeof(float) * (size_t)n) != hipSuccess)
+            return fail(c, PGH_ENOMEM, "hipMalloc(list component) failed");
+        hipError_t e = launch_list_component(s, field - PGH_TREE_LIST_X, tmp, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dst, tmp, sizeof(float) * (size_t)n, hipMemcpyDefault, c->stream);
+        const hipError_t e2 = hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return hip_fail(c, "copying a list component", e);
+        if (e2 != hipSuccess) return hip_fail(c, "copying a list component", e2);
+        return PGH_OK;
+    }
     PGH_HIP(c, hipMemcpyAsync(dst, src, elem * (size_t)n, hipMemcpyDefault, c->stream));
     PGH_HIP(c, hipStreamSynchronize(c->stream));
     return PGH_OK;

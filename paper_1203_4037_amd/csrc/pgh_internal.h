@@ -59,6 +59,7 @@ struct BatchArgs {
     const float *xi, *yi, *zi, *eps2i;
     float eps2_all;
     const float *xj, *yj, *zj, *mj;
+    const float4 *jxm;  // NULL, or the j-records packed (x, y, z, m) in place of xj .. mj
     float *ax, *ay, *az, *phi;
     // table force only
     const float2 *table;
@@ -218,7 +219,7 @@ struct TreeState {
     pgh_item *items = nullptr;  // device copy of the items
     // interaction lists, capacity entry_cap
     long long entry_cap = 0;
-    float *xj = nullptr, *yj = nullptr, *zj = nullptr, *mj = nullptr;
+    float4 *xmj = nullptr;  // the lists, (x, y, z, m) per entry
     int *src = nullptr;  // entry source (with record_src), capacity src_cap
     long long src_cap = 0;
     // scratch of the library scans and sorts
@@ -249,6 +250,9 @@ int tree_build(TreeState &t, int n, const float *x, const float *y, const float 
 int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t s,
               std::string &err);
 void tree_release(TreeState &t);
+// Copies component comp (0..3: x, y, z, m) of the list entries to out
+// (device float[n_entries]).
+hipError_t launch_list_component(const TreeState &t, int comp, float *out, hipStream_t s);
 // Writes the force held in t.res (key order) to the caller's arrays in the
 // input order (phi may be NULL).
 hipError_t launch_tree_outputs(const TreeState &t, float *ax, float *ay, float *az, float *phi,

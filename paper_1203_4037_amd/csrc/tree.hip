@@ -623,7 +623,7 @@ struct WalkArgs {
     const float4 *xm;  // particles (x, y, z, m) in key order
     long long *glen;        // pass 1 output: list length per group
     const long long *goff;  // pass 2 input: list offset per group
-    float *xj, *yj, *zj, *mj;
+    float4 *xmj;  // the lists: (x, y, z, m) per entry
     int *src;               // pass 2, optional
     unsigned *overflow;
     unsigned *max_frontier; // pass 1: the largest frontier met
@@ -732,11 +732,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(WalkArgs a)
                         }
                         const int k = e - (l0 ? s_inc[w][l0 - 1] : 0);
                         const int cd = s_src[w][l0];
-                        const float4 q = cd >= 0 ? a.pp[cd + k] : a.xm[-1 - cd + k];
-                        a.xj[base + e] = q.x;
-                        a.yj[base + e] = q.y;
-                        a.zj[base + e] = q.z;
-                        a.mj[base + e] = q.w;
+                        a.xmj[base + e] = cd >= 0 ? a.pp[cd + k] : a.xm[-1 - cd + k];
                         if (a.src) a.src[base + e] = cd >= 0 ? -(1 + cd + k) : -1 - cd + k;
                     }
                     wave_sync_lds();
@@ -835,7 +831,7 @@ void tree_release(TreeState &t)
 {
     void *ps[] = {t.key, t.key_in, t.perm, t.iota, t.xs, t.ys, t.zs, t.ms, t.mark, t.xin, t.inv, t.res,
                   t.begin, t.count, t.level, t.first_child, t.n_child, t.parent, t.nc, t.mom, t.com, t.pp, t.groups, t.glo, t.ghi, t.glen, t.goff,
-                  t.items, t.xj, t.yj, t.zj, t.mj, t.src, t.tmp, t.word, t.count_out, t.rc2, t.lvl,
+                  t.items, t.xmj, t.src, t.tmp, t.word, t.count_out, t.rc2, t.lvl,
                   t.xm, t.nrec};
     for (void *p : ps) (void)hipFree(p);
     t = TreeState();
@@ -1106,8 +1102,7 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
     if (total > t.entry_cap) {
         const long long cap = total + total / 4 + 1024;
         long long c1 = 0;
-        TREE_ALLOC(grow(&t.xj, &c1, cap) && grow(&t.yj, &c1, cap) &&
-                   grow(&t.zj, &c1, cap) && grow(&t.mj, &c1, cap));
+        TREE_ALLOC(grow(&t.xmj, &c1, cap));
         t.entry_cap = cap;
     }
     if (record_src && total > t.src_cap) {
@@ -1116,7 +1111,7 @@ int tree_walk(TreeState &t, float theta, int record_src, int num_cu, hipStream_t
     }
     // The writing pass runs while the caller plans the batched launch from
     // the items (the plan's upload is ordered after it on the stream).
-    a.xj = t.xj, a.yj = t.yj, a.zj = t.zj, a.mj = t.mj;
+    a.xmj = t.xmj;
     a.src = record_src ? t.src : nullptr;
     if (large)
         hipLaunchKernelGGL((k_walk<true, kWalkFrontier>), dim3(grid_large),
@@ -1155,6 +1150,25 @@ hipError_t launch_tree_outputs(const TreeState &t, float *ax, float *ay, float *
     if (t.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tree_out, dim3(blocks_of(t.n, 256)), dim3(256), 0, s, t.n, t.inv, t.res,
                        ax, ay, az, phi);
+    return hipGetLastError();
+}
+
+// One component (0..3: x, y, z, m) of the packed list entries.
+__global__ void __launch_bounds__(256) k_list_component(long long n, const float4 *__restrict__ xmj,
+                                                        int comp, float *__restrict__ out)
+{
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const float4 v = xmj[e];
+    out[e] = comp == 0 ? v.x : comp == 1 ? v.y : comp == 2 ? v.z : v.w;
+}
+
+hipError_t launch_list_component(const TreeState &t, int comp, float *out, hipStream_t s)
+{
+    if (t.n_entries <= 0) return hipSuccess;
+    const long long blocks = (t.n_entries + 255) / 256;
+    hipLaunchKernelGGL(k_list_component, dim3((unsigned)blocks), dim3(256), 0, s, t.n_entries,
+                       t.xmj, comp, out);
     return hipGetLastError();
 }
 
