@@ -214,6 +214,14 @@ PGH_API int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int 
                     pgh_plan **out);
 PGH_API int pgh_plan_free(pgh_ctx *c, pgh_plan *p);
 
+/* Where plans (pgh_plan_create, and the plan of each tree walk) get their
+ * task list: 1 (default) = the host decides the pairing and the cut of each
+ * list's chunks and the device writes the tasks from one compact entry per
+ * list or pair; 0 = the host writes every task.  Both give the same tasks;
+ * plans whose chunks of 64 would fill less than the device's resident waves
+ * are always made on the host. */
+PGH_API int pgh_set_plan_expansion(pgh_ctx *c, int on_device);
+
 /* Number of interactions sum n_i n_j of a plan (host value, no sync). */
 PGH_API long long pgh_plan_interactions(const pgh_plan *p);
 

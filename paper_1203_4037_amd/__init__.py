@@ -84,6 +84,7 @@ SIGNATURES = {
     "pgh_set_n": (_I, [_P, _I]),
     "pgh_set_xmj": (_I, [_P, _I, _I, _P, _P, _P, _P]),
     "pgh_set_rsqrt_refine": (_I, [_P, _I]),
+    "pgh_set_plan_expansion": (_I, [_P, _I]),
     "pgh_calc_newton": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pgh_build_table": (_I, [_P, _I, _I, _F, _P, _P, _P]),
     "pgh_table_compute": (_I, [_I, _I, _F, _P, _P, _P]),
@@ -211,6 +212,10 @@ def pgh_set_n(ctx, nj):
 
 def pgh_set_rsqrt_refine(ctx, on):
     _check(ctx, lib.pgh_set_rsqrt_refine(ctx, int(bool(on))))
+
+
+def pgh_set_plan_expansion(ctx, on_device):
+    _check(ctx, lib.pgh_set_plan_expansion(ctx, int(bool(on_device))))
 
 
 def pgh_set_xmj(ctx, adr, nj, x, y, z, m):
@@ -614,6 +619,10 @@ class Context:
     def set_rsqrt_refine(self, on):
         pgh_set_rsqrt_refine(self.h, on)
         self.refine = int(bool(on))
+
+    def set_plan_expansion(self, on_device):
+        """Plans' task lists written on the device (True, default) or the host."""
+        pgh_set_plan_expansion(self.h, on_device)
 
     def set_j(self, x, y, z, m, adr=0):
         """Copies j-particles into the j-memory at adr and sets n to adr + len."""

@@ -57,6 +57,7 @@ struct pgh_ctx {
     int jfill = 0;  // records written so far (the upper bound of pgh_set_n)
     float4 *jmem = nullptr;
     int refine = 0;  // Newton-Raphson step after v_rsq_f32 (pgh_set_rsqrt_refine)
+    int plan_device = 1;  // plans expanded on the device (pgh_set_plan_expansion)
     // look-up table
     int tab_set = 0;
     int tab_E = 0, tab_F = 0;
@@ -495,6 +496,13 @@ int pgh_set_rsqrt_refine(pgh_ctx *c, int on)
     return PGH_OK;
 }
 
+int pgh_set_plan_expansion(pgh_ctx *c, int on_device)
+{
+    if (!c) return PGH_EINVAL;
+    c->plan_device = on_device ? 1 : 0;
+    return PGH_OK;
+}
+
 int pgh_set_xmj(pgh_ctx *c, int adr, int nj, const float *x, const float *y, const float *z,
                 const float *m)
 {
@@ -743,7 +751,8 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     pgh_plan *p = new (std::nothrow) pgh_plan{};
     if (!p) return fail(c, PGH_ENOMEM, "out of host memory");
     p->owner = c;
-    const int st = plan_fill(c, p, n_items, items, ni_total, nj_total);
+    const int st = c->plan_device ? plan_fill_device(c, p, n_items, items, ni_total, nj_total)
+                                  : plan_fill(c, p, n_items, items, ni_total, nj_total);
     if (st) {
         DeviceGuard g(c->device);
         free_plan_memory(p);
@@ -1233,8 +1242,10 @@ int pgh_tree_walk(pgh_ctx *c, pgh_tree *t, float theta, int record_src)
             t->plan->owner = c;
             c->plans.push_back(t->plan);
         }
-        st = plan_fill_device(c, t->plan, s.n_groups, s.host_items.data(), s.n,
-                              (int)s.n_entries);
+        st = c->plan_device ? plan_fill_device(c, t->plan, s.n_groups, s.host_items.data(), s.n,
+                                               (int)s.n_entries)
+                            : plan_fill(c, t->plan, s.n_groups, s.host_items.data(), s.n,
+                                        (int)s.n_entries);
         if (st) {
             drop_plan();
             t->st.walked = 0;

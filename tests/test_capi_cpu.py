@@ -67,6 +67,7 @@ def test_open_without_gpu_returns_status(pgh):
 
 def test_null_context_is_rejected(pgh):
     assert pgh.lib.pgh_set_n(None, 1) == pgh.PGH_EINVAL
+    assert pgh.lib.pgh_set_plan_expansion(None, 1) == pgh.PGH_EINVAL
     assert pgh.lib.pgh_calc_newton(None, 1, *([None] * 8)) == pgh.PGH_EINVAL
     assert pgh.lib.pgh_close(None) == pgh.PGH_OK
 

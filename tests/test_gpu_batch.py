@@ -341,6 +341,49 @@ def _random_items(rng, n_items, ni_max, nj_max, long_frac):
     return np.array(items, dtype=np.int32)[order], ni_total, nj_total
 
 
+@pytest.mark.parametrize("seed", range(2))
+def test_device_and_host_plans_agree(pgh, ctx, seed):
+    """Plans large enough for chunks of 64 (12000 random lists, empty groups
+    and lists, long lists cut into parts, shared j-entries) get their tasks
+    written on the device from compact entries; the same items planned on
+    the host hold the same tasks, so both plans give bit-identical Newton and
+    table forces, and the device plan's forces match the oracle on sampled
+    rows."""
+    import torch
+    rng = np.random.default_rng(2000 + seed)
+    items, ni_total, nj_total = _random_items(rng, 12000, 140, 700, 0.03)
+    xi, yi, zi = (rng.random(ni_total).astype(np.float32) for _ in range(3))
+    xj, yj, zj = (rng.random(nj_total).astype(np.float32) for _ in range(3))
+    mj = rng.uniform(0.5, 1.5, nj_total).astype(np.float32) / nj_total
+    di, dj = to_dev(xi, yi, zi), to_dev(xj, yj, zj, mj)
+    ctx.set_eps_to_all(0.01)
+    ctx.build_table(4, 6, rcut=0.05, eps=0.005)
+    res = {}
+    for on_device in (True, False):
+        ctx.set_plan_expansion(on_device)
+        plan = ctx.plan(items, ni_total, nj_total)
+        outs = []
+        for kind in ("newton", "table"):
+            out = [torch.full((ni_total,), 777.0, device="cuda") for _ in range(4 if kind == "newton" else 3)]
+            getattr(plan, kind)(*di, *dj, out=out)
+            outs.append(np.stack(to_host(*out)))
+        res[on_device] = outs
+        plan.free()
+    ctx.set_plan_expansion(True)
+    for a, b in zip(res[True], res[False]):
+        assert np.array_equal(a, b)
+    # sampled rows of the device plan against the oracle
+    pick = items[rng.choice(len(items), 40, replace=False)]
+    pick = pick[(pick[:, 1] > 0)]
+    e2 = np.full(ni_total, np.float32(0.01) ** 2, np.float32)
+    ref = np.stack(oracle.newton_items(pick, xi, yi, zi, e2, xj, yj, zj, mj))
+    rows = np.concatenate([np.arange(a, a + b) for a, b, _, _ in pick])
+    rows = rows[ref[3, rows] != 0]
+    got = res[True][0]
+    ea = rel_vec_err(got[:3, rows], ref[:3, rows])
+    assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, (rms(ea), ea.max())
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_random_item_sets(pgh, ctx, seed):
     """Random plans (group sizes 1..200, list lengths up to ~10^4, empty

@@ -408,7 +408,9 @@ def test_device_expanded_plan_matches_host_plan(pgh, ctx, n, n_crit, thetas, qua
         got = np.stack(to_host(*t.newton()))
         items = t.get("items")
         lists = to_dev(*(t.get(f) for f in ("list_x", "list_y", "list_z", "list_m")))
+        ctx.set_plan_expansion(False)  # every task written on the host
         plan = ctx.plan(items, n, int((items[:, 2].astype(np.int64) + items[:, 3]).max()))
+        ctx.set_plan_expansion(True)
         ref = np.stack(to_host(*plan.newton(*keyed, *lists)))
         assert plan.interactions == int((items[:, 1].astype(np.int64) * items[:, 3]).sum())
         assert np.array_equal(got[:, perm], ref), theta
