@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
         auto load = [&](int tile) {
             const int jj = tile * 64 + lane;
             auto record = [&](int j) {
-                if (a.jxm) {
+                if (KIND == 0 && a.jxm) {  // packed j-records: Newton only
                     float4 v = a.jxm[j];
                     v.w *= mscale;
                     return v;
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
 
         if (tk.n_parts <= 1) {
             if (active && ph == 0) {
-                if (a.out4) {
+                if (KIND == 0 && a.out4) {  // packed outputs: Newton only
                     a.out4[i] = make_float4(tx, ty, tz, tp);
                 } else {
                     a.ax[i] = tx;

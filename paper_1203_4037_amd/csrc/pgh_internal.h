@@ -59,13 +59,15 @@ struct BatchArgs {
     const float *xi, *yi, *zi, *eps2i;
     float eps2_all;
     const float *xj, *yj, *zj, *mj;
-    const float4 *jxm;  // NULL, or the j-records packed (x, y, z, m) in place of xj .. mj
     float *ax, *ay, *az, *phi;
     // table force only
     const float2 *table;
     int E, F;
     float c, smax;
     const float2 *ptable;  // potential table (with phi), or NULL
+    // Newton only: NULL, or the j-records packed (x, y, z, m) in place of
+    // xj .. mj
+    const float4 *jxm;
     // NULL, or packed outputs (ax, ay, az, phi) per i-particle in place of
     // the four arrays (Newton only; the potential is then always computed)
     float4 *out4;
