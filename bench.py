@@ -700,7 +700,7 @@ def tree_code(torch, pgh, synth, sizes=(1 << 20, 1 << 22), n_crit=64,
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus must be 1).", file=sys.stderr)
         sys.exit(2)
     import torch
