@@ -4,7 +4,8 @@
 // moments carried by pseudo-particles after Kawai & Makino) for the batched
 // force kernels.
 //
-// Definitions (shared with the FP64 reference the tests compare against):
+// Definitions (the FP64 oracle the tests compare against implements the same
+// definitions in code of its own):
 //   frame   lo = componentwise minimum of the positions, extent = the largest
 //           axis range, scale = 2^21 / extent, all FP32;
 //   keys    per axis min(floor((x - lo) * scale), 2^21 - 1) (FP32 subtract and
