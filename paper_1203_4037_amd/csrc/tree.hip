@@ -649,6 +649,7 @@ __device__ inline void wave_sync_lds()
 }
 
 constexpr int kWalkWaves = 2;  // waves per workgroup, each walking its own groups
+constexpr int kMapSeg = 256;  // entries per segment of the write pass's map
 
 // Breadth-first walk of one group per wave.  The 64 lanes test 64 frontier
 // nodes at a time; wave prefix sums place each lane's contributions in the
@@ -662,7 +663,10 @@ template <bool WRITE, int FCAP>
 __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(WalkArgs a)
 {
     __shared__ int fr[kWalkWaves][2][FCAP];
-    __shared__ int s_inc[kWalkWaves][64], s_src[kWalkWaves][64];
+    // write pass: each lane's first entry and source code, and the lane that
+    // owns each entry of a segment of kMapSeg entries
+    __shared__ int s_start[kWalkWaves][64], s_src[kWalkWaves][64];
+    __shared__ unsigned char s_map[kWalkWaves][kMapSeg];
     __shared__ float rc2[kTreeMaxLevel + 1];
     if (threadIdx.x <= kTreeMaxLevel) rc2[threadIdx.x] = a.rc2[threadIdx.x];
     __syncthreads();
@@ -718,25 +722,27 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(WalkArgs a)
                 }
                 for (int k = 0; k < push; ++k) fr[w][cur ^ 1][nnext + p_inc - push + k] = fc + k;
                 if (WRITE && e_tot > 0) {
-                    s_inc[w][lane] = e_inc;
+                    const int r0 = e_inc - emit;  // this lane's first entry
+                    s_start[w][lane] = r0;
                     s_src[w][lane] = code;
-                    wave_sync_lds();
                     const long long base = out + len;
-                    for (int e = lane; e < e_tot; e += 64) {
-                        int l0 = 0, l1 = 63;  // first lane whose inclusive count exceeds e
-                        while (l0 < l1) {
-                            const int mid = (l0 + l1) >> 1;
-                            if (s_inc[w][mid] > e)
-                                l1 = mid;
-                            else
-                                l0 = mid + 1;
+                    // segment by segment: every lane marks its entries in the
+                    // map, then the entries are written 64 at a time, each lane
+                    // finding its entry's source through the map
+                    for (int seg = 0; seg < e_tot; seg += kMapSeg) {
+                        const int m0 = max(r0, seg), m1 = min(e_inc, seg + kMapSeg);
+                        for (int e = m0; e < m1; ++e) s_map[w][e - seg] = (unsigned char)lane;
+                        wave_sync_lds();
+                        const int seg_end = min(e_tot, seg + kMapSeg);
+                        for (int e = seg + lane; e < seg_end; e += 64) {
+                            const int l = s_map[w][e - seg];
+                            const int k = e - s_start[w][l];
+                            const int cd = s_src[w][l];
+                            a.xmj[base + e] = cd >= 0 ? a.pp[cd + k] : a.xm[-1 - cd + k];
+                            if (a.src) a.src[base + e] = cd >= 0 ? -(1 + cd + k) : -1 - cd + k;
                         }
-                        const int k = e - (l0 ? s_inc[w][l0 - 1] : 0);
-                        const int cd = s_src[w][l0];
-                        a.xmj[base + e] = cd >= 0 ? a.pp[cd + k] : a.xm[-1 - cd + k];
-                        if (a.src) a.src[base + e] = cd >= 0 ? -(1 + cd + k) : -1 - cd + k;
+                        wave_sync_lds();
                     }
-                    wave_sync_lds();
                 }
                 len += e_tot;
                 nnext += p_tot;
