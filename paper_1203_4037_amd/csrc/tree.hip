@@ -364,12 +364,25 @@ __global__ void __launch_bounds__(256) k_split_write(int L, const int *__restric
     }
 }
 
-// Sum over the 8 lanes of a node's lane group.
+// v from another lane of the same 8-lane group by a DPP lane pattern (a
+// VALU move, no LDS round trip): both 32-bit halves.
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 8 lanes of a node's lane group, the same in every lane: the
+// lane pairs i ^ 1 and i ^ 2 inside each quad (quad_perm [1,0,3,2] and
+// [2,3,0,1]), then the two quads (the half-row mirror, i <-> 7 - i).
 __device__ inline double group_sum(double v)
 {
-    v += __shfl_xor(v, 1, 8);
-    v += __shfl_xor(v, 2, 8);
-    v += __shfl_xor(v, 4, 8);
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
     return v;
 }
 
