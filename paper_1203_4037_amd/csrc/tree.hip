@@ -643,13 +643,20 @@ struct WalkArgs {
     unsigned *max_frontier; // pass 1: the largest frontier met
 };
 
-__device__ inline int wave_incl_scan(int v, int lane)
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active) by DPP
+// lane moves: the sums of up to four lanes inside each row of 16 (row shifts
+// by 1, 2 and 3 of the value), then of eight and of the whole row (row shifts
+// by 4 and 8 of the partial sums into the upper banks), then across rows (lane
+// 15 of row 0 and 2 broadcast into rows 1 and 3, lane 31 into rows 2 and 3).
+__device__ inline int wave_incl_scan(int x)
 {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
+    int v = x + __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);          // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, x, 0x113, 0xF, 0xF, true);          // row_shr:3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xE, false);         // row_shr:4, banks 1-3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xC, false);         // row_shr:8, banks 2-3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);         // row_bcast:15, rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);         // row_bcast:31, rows 2, 3
     return v;
 }
 
@@ -726,9 +733,10 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(WalkArgs a)
                         push = nch;
                     }
                 }
-                const int e_inc = wave_incl_scan(emit, lane);
-                const int p_inc = wave_incl_scan(push, lane);
-                const int e_tot = __shfl(e_inc, 63, 64), p_tot = __shfl(p_inc, 63, 64);
+                const int e_inc = wave_incl_scan(emit);
+                const int p_inc = wave_incl_scan(push);
+                const int e_tot = __builtin_amdgcn_readlane(e_inc, 63);
+                const int p_tot = __builtin_amdgcn_readlane(p_inc, 63);
                 if (nnext + p_tot > FCAP) {
                     over = true;
                     break;
