@@ -205,16 +205,29 @@ __device__ inline int lower_digit(const unsigned long long *key, int lo, int hi,
 // each node's children go to the next level at its offset).
 constexpr int kSplitBlocks = 2048;
 
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active) by DPP
+// lane moves: the sums of up to four lanes inside each row of 16 (row shifts
+// by 1, 2 and 3 of the value), then of eight and of the whole row (row shifts
+// by 4 and 8 of the partial sums into the upper banks), then across rows (lane
+// 15 of row 0 and 2 broadcast into rows 1 and 3, lane 31 into rows 2 and 3).
+__device__ inline int wave_incl_scan(int x)
+{
+    int v = x + __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);          // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, x, 0x113, 0xF, 0xF, true);          // row_shr:3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xE, false);         // row_shr:4, banks 1-3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xC, false);         // row_shr:8, banks 2-3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);         // row_bcast:15, rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);         // row_bcast:31, rows 2, 3
+    return v;
+}
+
 // Inclusive scan over a workgroup of 256 (wave scans, then the wave totals);
 // *total receives the workgroup's sum.  Every thread of the workgroup calls it.
 __device__ inline int block_incl_scan(int v, int *sh, int *total)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
+    v = wave_incl_scan(v);
     if (lane == 63) sh[wv] = v;
     __syncthreads();
     int add = 0;
@@ -263,12 +276,14 @@ __global__ void __launch_bounds__(256) k_split_count(int L, int n_leaf,
         int p = b + c;  // lane 7: the node's end
         if (split && j < 7) p = lower_digit(key, b, b + c, j + 1, L + 1);
         // child j of the node is [boundary j, boundary j + 1), boundary 0 = b
-        const int q = __shfl_up(p, 1, 8);
+        // (DPP lane moves: the lane before, then the sum over the group by
+        // the pairs inside each quad and the half-row mirror)
+        const int q = __builtin_amdgcn_update_dpp(0, p, 0x111, 0xF, 0xF, true);  // row_shr:1
         const int start = j == 0 ? b : q;
         int k = (split && p > start) ? 1 : 0;
-        k += __shfl_xor(k, 1, 8);
-        k += __shfl_xor(k, 2, 8);
-        k += __shfl_xor(k, 4, 8);
+        k += __builtin_amdgcn_update_dpp(0, k, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        k += __builtin_amdgcn_update_dpp(0, k, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+        k += __builtin_amdgcn_update_dpp(0, k, 0x141, 0xF, 0xF, false);  // row_half_mirror
         if (split && j < 7) bnd[7 * (size_t)i + j] = p;
         if (i < hi && j == 0) {
             nc[i] = k;
@@ -643,22 +658,6 @@ struct WalkArgs {
     unsigned *max_frontier; // pass 1: the largest frontier met
 };
 
-// Inclusive prefix sum over the 64 lanes of a wave (all lanes active) by DPP
-// lane moves: the sums of up to four lanes inside each row of 16 (row shifts
-// by 1, 2 and 3 of the value), then of eight and of the whole row (row shifts
-// by 4 and 8 of the partial sums into the upper banks), then across rows (lane
-// 15 of row 0 and 2 broadcast into rows 1 and 3, lane 31 into rows 2 and 3).
-__device__ inline int wave_incl_scan(int x)
-{
-    int v = x + __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);  // row_shr:1
-    v += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);          // row_shr:2
-    v += __builtin_amdgcn_update_dpp(0, x, 0x113, 0xF, 0xF, true);          // row_shr:3
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xE, false);         // row_shr:4, banks 1-3
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xC, false);         // row_shr:8, banks 2-3
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);         // row_bcast:15, rows 1, 3
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);         // row_bcast:31, rows 2, 3
-    return v;
-}
 
 // LDS written by some lanes of a wave and then read by others.
 __device__ inline void wave_sync_lds()
