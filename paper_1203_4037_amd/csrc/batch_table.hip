@@ -1,0 +1,327 @@
+// Table force over interaction lists in one persistent launch: the force
+// procedure of Sec. 3.4.2 on the (i-group, j-list) items of a tree or TreePM
+// code (Sec. 5.1), over the same plans as the batched Newton kernel
+// (batch.hip: wave tasks of at most 64 i-particles, pairs of partly filled
+// chunks sharing a wave, long lists cut into parts, longest-first sublists).
+//
+// What differs from the Newton kernel:
+//   * KI i-particles per lane (1 or 2).  Each lane reads one j-record from
+//     LDS per step and uses it for KI pairs: the j-record broadcast and the
+//     table gather share the CU's LDS bandwidth, and with one i-particle per
+//     lane the LDS, not the VALU, would bound the pair rate.  A chunk of n
+//     i-particles with js lanes per i-particle (chunk_js) runs P = KI js
+//     phases of R = 64 / P lanes; lane (phase p, row r) holds the chunk's
+//     slots r + k R (k < KI) and takes the list's entries p, p + P, ...  A
+//     paired task runs P = KI phases; its first chunk holds rows
+//     [0, ceil(n_1 / KI)), the second the rows after them (the planner pairs
+//     two chunks only when both fit in that many rows).
+//   * The j-tile of a task without a second list is 64 TW records (TW
+//     records per lane per tile), so short steps (P = 8) still get long
+//     tiles.
+//   * The pair arithmetic (table_pair_v) keeps every uniform operand in a
+//     VGPR and finds the bin's byte offset with a shift and a mask; the
+//     table sits in static LDS (2^TB entries at most), so its base folds
+//     into the LDS read's offset field.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <type_traits>
+#include <utility>
+
+#include "batch_queue.h"
+#include "pairs.h"
+
+namespace pgh {
+namespace {
+
+// plans of at most this many tasks per wave run in the static order
+constexpr int kStaticRounds = 4;
+
+// The lanes of one task: lane (phase, row) holds slots q + k stride
+// (k < KI) of its chunk (i-particles i0 + slot, the chunk's partial-sum
+// lanes from lane0), and takes the list's entries phase, phase + P, ...
+template <int KI>
+struct TaskLanes {
+    bool paired, second;
+    int plog, P, R, phase, q, stride, nl, i0, lane0;
+    int T, nj, ntiles;  // records per tile and list, entries, tiles
+    bool act[KI];
+    float px[KI], py[KI], pz[KI];
+};
+
+// KI i-particles per lane, TW j-records per lane per tile (unpaired tasks),
+// 2^TB table entries at most, HT the (H, G1) form, PHI the potential table,
+// WPB waves per workgroup (one table copy per workgroup).
+template <int KI, int TW, int TB, bool HT, bool PHI, int WPB>
+// eight waves per SIMD whatever the workgroup size (64 VGPRs at most)
+__global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_batch_table(BatchArgs a)
+{
+    using Entry = std::conditional_t<PHI, float4, float2>;
+    constexpr int kEntryLog = PHI ? 4 : 3;
+    __shared__ Entry stab[1 << TB];
+    __shared__ float4 jt[WPB][128];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    // Task order: static (few tasks per wave: no atomics, and the next
+    // task's fields load while the current task runs) or the sublists.
+    const bool stat = a.static_order != 0;
+    const TaskStream ts = task_stream(a, WPB);
+    const unsigned G = gridDim.x * WPB;
+    const unsigned gw = __builtin_amdgcn_readfirstlane(blockIdx.x * WPB + wave);
+    const Task *const tbase = stat ? a.tasks : ts.tasks;
+    const unsigned n_t = stat ? (unsigned)a.n_tasks : ts.n_tasks;
+    unsigned round = 0;
+    unsigned t = stat ? static_task(a, 0, gw, G) : first_task(a, WPB, wave);
+    float4 *tile = jt[wave];
+
+    // j-records of tile tl of a task, TW per lane (a paired task: one of each
+    // list); entries past a list's end are zero-mass records far away
+    float4 pre[2];
+    auto record = [&](int j_off, int n, int j) {
+        float4 v = make_float4(kFar, kFar, kFar, 0.f);
+        if (j < n) {
+            const int jj = j_off + j;
+            v = make_float4(a.xj[jj], a.yj[jj], a.zj[jj], a.mj[jj]);
+        }
+        return v;
+    };
+    auto load = [&](const Task &tk, const TaskLanes<KI> &L, int tl) {
+        if (L.paired) {
+            pre[0] = record(tk.j_off, tk.n_j, tl * 64 + lane);
+            pre[1] = record(tk.j_off2, tk.n_j2, tl * 64 + lane);
+        } else {
+#pragma unroll
+            for (int w = 0; w < TW; ++w) pre[w] = record(tk.j_off, tk.n_j, tl * L.T + w * 64 + lane);
+        }
+    };
+    auto store = [&](const TaskLanes<KI> &L) {
+        tile[lane] = pre[0];
+        if (L.paired || TW == 2) tile[64 + lane] = pre[1];
+    };
+    // lane -> (phase, row) -> (list, slots); issues the task's i-particle
+    // loads and the loads of its first tile
+    auto begin = [&](const Task &tk) {
+        TaskLanes<KI> L;
+        L.paired = tk.n_i2 > 0;
+        L.plog = (KI == 2 ? 1 : 0) + (L.paired ? 0 : (tk.n_i <= 16 ? 2 : (tk.n_i <= 32 ? 1 : 0)));
+        L.P = 1 << L.plog;
+        L.R = 64 >> L.plog;
+        L.phase = lane >> (6 - L.plog);
+        const int row = lane & (L.R - 1);
+        L.stride = L.R, L.q = row, L.nl = tk.n_i, L.i0 = tk.i_off, L.lane0 = 0;
+        L.second = false;
+        if (L.paired) {
+            const int ra = (tk.n_i + KI - 1) / KI, rb = (tk.n_i2 + KI - 1) / KI;
+            L.second = row >= ra;
+            L.stride = L.second ? rb : ra;
+            L.q = L.second ? row - ra : row;
+            L.nl = L.second ? tk.n_i2 : tk.n_i;
+            L.i0 = L.second ? tk.i_off2 : tk.i_off;
+            L.lane0 = L.second ? tk.n_i : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            const int slot = L.q + k * L.stride;
+            L.act[k] = L.q < L.stride && slot < L.nl;
+            const int i = L.i0 + (L.act[k] ? slot : 0);
+            L.px[k] = a.xi[i];
+            L.py[k] = a.yi[i];
+            L.pz[k] = a.zi[i];
+        }
+        L.T = L.paired ? 64 : 64 * TW;
+        L.nj = L.paired ? max(tk.n_j, tk.n_j2) : tk.n_j;
+        L.ntiles = (L.nj + L.T - 1) / L.T;
+        load(tk, L, 0);
+        return L;
+    };
+
+    // The first task's fields, i-particles and first tile are loaded before
+    // the table copy, whose latency they share.
+    Task tk{};
+    TaskLanes<KI> L{};
+    if (t < n_t) {
+        tk = tbase[t];
+        L = begin(tk);
+    }
+    {
+        const int K = 1 << (a.E + a.F);
+        const unsigned shift = 23u - (unsigned)a.F;
+        if (PHI)
+            tables_to_lds<HT>((float4 *)stab, a.table, a.ptable, K, shift);
+        else
+            table_to_lds<HT>((float2 *)stab, a.table, K, shift);
+    }
+    const TableConsts kc = table_consts(a.c, a.smax, a.E, a.F, kEntryLog);
+    const char *tab = (const char *)stab;
+    __syncthreads();  // the only workgroup barrier: waves are independent after it
+
+    while (t < n_t) {
+        const unsigned tn = stat ? 0u : pop_task(ts, lane);
+        // vmcnt(0): the i-particle and first-tile loads (and the ticket's
+        // atomic).  Waiting here keeps the compiler from placing a full wait
+        // inside the pair loop, where it would also wait for the prefetch of
+        // the next tile.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        const unsigned t_next =
+            stat ? static_task(a, ++round, gw, G) : __builtin_amdgcn_readfirstlane(tn);
+        int fld = 0;
+        if (t_next < n_t && lane < 12) fld = ((const int *)(tbase + t_next))[lane];
+
+        float tx[KI], ty[KI], tz[KI], tp[KI];
+#pragma unroll
+        for (int k = 0; k < KI; ++k) tx[k] = ty[k] = tz[k] = tp[k] = 0.f;
+        const float4 *src = tile + (L.second ? 64 : 0) + L.phase;
+        for (int tl = 0; tl < L.ntiles; ++tl) {
+            wave_sync();  // the previous tile's reads are done
+            store(L);
+            wave_sync();
+            if (tl + 1 < L.ntiles) load(tk, L, tl + 1);
+            const int cnt = min(L.T, L.nj - tl * L.T);
+            auto step = [&](const float4 p) {
+                table_pairs_v<KI, HT, PHI>(p, L.px, L.py, L.pz, tab, kc, tx, ty, tz, tp);
+            };
+            if (cnt == L.T) {
+                // a full tile: T / P records per lane with a compile-time
+                // stride, so the LDS reads take immediate offsets
+                auto full = [&](auto stride_c, auto trips_c) {
+                    constexpr int S = decltype(stride_c)::value;
+                    constexpr int N = decltype(trips_c)::value;
+#pragma unroll 2
+                    for (int it = 0; it < N; ++it) step(src[it * S]);
+                };
+                using std::integral_constant;
+                if (L.paired) {
+                    full(integral_constant<int, KI>{}, integral_constant<int, 64 / KI>{});
+                } else if (L.plog == (KI == 2 ? 1 : 0)) {
+                    full(integral_constant<int, KI>{}, integral_constant<int, 64 * TW / KI>{});
+                } else if (L.plog == (KI == 2 ? 2 : 1)) {
+                    full(integral_constant<int, 2 * KI>{}, integral_constant<int, 32 * TW / KI>{});
+                } else {
+                    full(integral_constant<int, 4 * KI>{}, integral_constant<int, 16 * TW / KI>{});
+                }
+            } else {
+                const int trips = (cnt + L.P - 1) >> L.plog;
+#pragma unroll 2
+                for (int it = 0; it < trips; ++it) step(src[it * L.P]);
+            }
+        }
+
+        // add the phases of each row (lanes row, row + R, ...)
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            for (int d = L.R; d < 64; d <<= 1) {
+                tx[k] += __shfl_xor(tx[k], d);
+                ty[k] += __shfl_xor(ty[k], d);
+                tz[k] += __shfl_xor(tz[k], d);
+                if (PHI) tp[k] += __shfl_xor(tp[k], d);
+            }
+        }
+        if (L.phase == 0) {
+#pragma unroll
+            for (int k = 0; k < KI; ++k) {
+                if (!L.act[k]) continue;
+                const int slot = L.q + k * L.stride;
+                if (tk.n_parts <= 1) {
+                    const int i = L.i0 + slot;
+                    a.ax[i] = tx[k];
+                    a.ay[i] = ty[k];
+                    a.az[i] = tz[k];
+                    if (PHI) a.phi[i] = tp[k];
+                } else {
+                    // partial sums of one part of a split j-list; k_combine
+                    // adds the parts of the chunk in order after this launch
+                    a.partial[(size_t)(tk.slot + tk.part) * 64 + L.lane0 + slot] =
+                        make_float4(tx[k], ty[k], tz[k], tp[k]);
+                }
+            }
+        }
+        t = t_next;
+        if (t < n_t) {
+            tk = task_of_fields(fld);
+            L = begin(tk);
+        }
+    }
+}
+
+using TableKernel = void (*)(BatchArgs);
+
+template <int KI, int TW, bool HT, int WPB>
+TableKernel pick(int tb, bool phi)
+{
+    if (tb <= 10)
+        return phi ? k_batch_table<KI, TW, 10, HT, true, WPB>
+                   : k_batch_table<KI, TW, 10, HT, false, WPB>;
+    return phi ? k_batch_table<KI, TW, 12, HT, true, WPB>
+               : k_batch_table<KI, TW, 12, HT, false, WPB>;
+}
+
+struct TableBatchVariant {
+    const char *name;
+    int wpb;  // waves per workgroup
+    TableKernel (*pick)(int tb, bool phi);
+};
+
+// The tile shapes the autotuner chooses among: i-particles per lane (KI),
+// j-records per lane per tile (TW) and waves per workgroup.  All use the
+// paper's (G0, G1) form: the (H, G1) form of the all-pairs variants saves two
+// instructions per pair, but its rounding of H_k = G0_k - G1_k s_k is
+// relative to G1_k s_k, not to g, and near rcut, where g goes to zero, it can
+// exceed the table's 1e-3 error for a particle whose only neighbours lie
+// there.
+const TableBatchVariant kTableBatchVariants[] = {
+    {"ki=1 tw=1 wg=4", 4, pick<1, 1, false, 4>},
+    {"ki=2 tw=1 wg=4", 4, pick<2, 1, false, 4>},
+    {"ki=2 tw=2 wg=4", 4, pick<2, 2, false, 4>},
+    {"ki=1 tw=1 wg=16", 16, pick<1, 1, false, 16>},
+    {"ki=2 tw=2 wg=16", 16, pick<2, 2, false, 16>},
+};
+constexpr int kNumTableBatchVariants = sizeof(kTableBatchVariants) / sizeof(kTableBatchVariants[0]);
+
+int resident_blocks(TableKernel k, int wpb)
+{
+    static std::mutex mu;
+    static std::map<const void *, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find((const void *)k);
+    if (it != cache.end()) return it->second;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * wpb, 0) != hipSuccess || n < 1)
+        n = 1;
+    cache[(const void *)k] = n;
+    return n;
+}
+
+}  // namespace
+
+int table_batch_variants() { return kNumTableBatchVariants; }
+
+const char *table_batch_variant_name(int v)
+{
+    return (v >= 0 && v < kNumTableBatchVariants) ? kTableBatchVariants[v].name : nullptr;
+}
+
+int table_batch_default() { return 2; }
+
+hipError_t launch_table_batch(const BatchArgs &a0, int variant, int num_cu, hipStream_t s)
+{
+    if (a0.n_tasks <= 0) return hipSuccess;
+    if (variant < 0 || variant >= kNumTableBatchVariants) variant = table_batch_default();
+    const bool phi = a0.phi && a0.ptable;
+    const TableBatchVariant &v = kTableBatchVariants[variant];
+    const TableKernel k = v.pick(a0.E + a0.F, phi);
+    BatchArgs a = a0;
+    // one resident wave of workgroups, or fewer when there are fewer tasks
+    // than waves; at least one workgroup per task sublist
+    const int cap = num_cu * resident_blocks(k, v.wpb);
+    const int blocks = std::max(a.nq, std::min(cap, (a.n_tasks + v.wpb - 1) / v.wpb));
+    a.n_waves = blocks * v.wpb;
+    a.static_order = (long long)a.n_tasks <= kStaticRounds * (long long)a.n_waves ? 1 : 0;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * v.wpb), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.n_chunks == 0) return e;
+    return launch_combine(a, phi, s);
+}
+
+}  // namespace pgh

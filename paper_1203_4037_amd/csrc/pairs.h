@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace pgh {
 
 // 1/q from the transcendental unit (v_rcp_f32), which issues alongside the
@@ -176,6 +178,102 @@ __device__ __forceinline__ void tables_to_lds(float4 *stab, const float2 *__rest
             e.z = __builtin_fmaf(-e.w, sk, e.z);
         }
         stab[k] = e;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The table pair of the batched kernels, written for gfx950's issue rates
+// (measured on the device): FP32 add, sub, mul and FMA, and the integer
+// shift, and, or, xor and add, issue at twice the rate of v_min/v_max,
+// v_bfe_u32 and v_lshl_add_u32, and any VALU instruction that reads an SGPR
+// operand issues at the lower rate.  So every uniform operand is held in a
+// VGPR, and the bin's byte offset in the LDS table is a shift and a mask of
+// bits(s) (two fast instructions) rather than v_bfe_u32 and v_lshl_add_u32
+// (two slow ones); the clamp at s_max is the one slow instruction per pair.
+// ---------------------------------------------------------------------------
+
+// A uniform value moved into a VGPR, so that the compiler does not read it
+// from an SGPR in every pair.
+__device__ __forceinline__ float in_vgpr(float x)
+{
+    float r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+__device__ __forceinline__ unsigned in_vgpr(unsigned x)
+{
+    unsigned r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+// Operands of table_pair_v (each in a VGPR).  For an LDS table of entries
+// of 2^eb bytes (eb = 3: (G0, G1); eb = 4: (G0, G1, P0, P1)):
+//   sh = 23 - F - eb: (bits(s) >> sh) & am is the byte offset of s's node,
+//   am = (2^(E+F) - 1) << eb,
+//   hm = ~(2^(23-F) - 1): bits(s) & hm are the bits of the node s_k.
+struct TableConsts {
+    float c;
+    unsigned smax_bits;  // bits(s_max)
+    unsigned sh, am, hm;
+};
+
+__device__ __forceinline__ TableConsts table_consts(float c, float smax, int E, int F, int eb)
+{
+    TableConsts k;
+    k.c = in_vgpr(c);
+    k.smax_bits = in_vgpr(__float_as_uint(smax));
+    k.sh = in_vgpr((unsigned)(23 - F - eb));
+    k.am = in_vgpr((((1u << (E + F)) - 1u) << eb));
+    k.hm = in_vgpr(~((1u << (23 - F)) - 1u));
+    return k;
+}
+
+// KI pairs of Eq. arbitrary_force through the table (the steps of
+// Sec. 3.4.2): one j-record p against the lane's KI i-particles, with the
+// table at byte address `tab` in LDS; with PHI the entries are
+// (G0, G1, P0, P1) and sp accumulates m_j p(s).  HT: the constant terms are
+// in the (H, G1) form, g = H_k + G1_k s.  The KI pairs are written step by
+// step side by side so that their LDS gathers are in flight together.  The
+// clamp at s_max compares the bit patterns (v_min_u32): for s >= 2 their
+// order is the order of the numbers, and unlike v_min_f32 it needs no
+// quieting of its operands.
+template <int KI, bool HT, bool PHI>
+__device__ __forceinline__ void table_pairs_v(const float4 p, const float *px, const float *py,
+                                              const float *pz, const char *__restrict__ tab,
+                                              const TableConsts &k, float *sx, float *sy,
+                                              float *sz, float *sp)
+{
+    float dx[KI], dy[KI], dz[KI], s[KI];
+    unsigned u[KI];
+#pragma unroll
+    for (int q = 0; q < KI; ++q) {
+        dx[q] = p.x - px[q];
+        dy[q] = p.y - py[q];
+        dz[q] = p.z - pz[q];
+    }
+#pragma unroll
+    for (int q = 0; q < KI; ++q) {
+        float r2 = dx[q] * dx[q];
+        r2 = __builtin_fmaf(dy[q], dy[q], r2);
+        r2 = __builtin_fmaf(dz[q], dz[q], r2);
+        u[q] = min(__float_as_uint(__builtin_fmaf(r2, k.c, 2.0f)), k.smax_bits);
+        s[q] = __uint_as_float(u[q]);
+    }
+    using Entry = std::conditional_t<PHI, float4, float2>;
+    Entry t[KI];
+#pragma unroll
+    for (int q = 0; q < KI; ++q) t[q] = *(const Entry *)(tab + ((u[q] >> k.sh) & k.am));
+#pragma unroll
+    for (int q = 0; q < KI; ++q) {
+        const float ds = HT ? s[q] : s[q] - __uint_as_float(u[q] & k.hm);
+        const float g = __builtin_fmaf(t[q].y, ds, t[q].x);
+        const float mg = p.w * g;
+        sx[q] = __builtin_fmaf(mg, dx[q], sx[q]);
+        sy[q] = __builtin_fmaf(mg, dy[q], sy[q]);
+        sz[q] = __builtin_fmaf(mg, dz[q], sz[q]);
+        if constexpr (PHI) sp[q] = __builtin_fmaf(p.w, __builtin_fmaf(t[q].w, ds, t[q].z), sp[q]);
     }
 }
 

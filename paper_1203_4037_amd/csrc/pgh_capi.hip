@@ -16,6 +16,9 @@ using namespace pgh;
 
 struct pgh_plan {
     pgh_ctx *owner;
+    // the plan of a tree's lists, owned by the tree (pgh_tree_plan hands it
+    // out read-only; pgh_plan_free rejects it, pgh_tree_free frees it)
+    bool tree_owned;
     int n_items, n_tasks;
     int ni_total, nj_total;
     long long interactions;
@@ -764,17 +767,32 @@ int pgh_plan_create(pgh_ctx *c, int n_items, const pgh_item *items, int ni_total
     return PGH_OK;
 }
 
+namespace {
+
+// Frees a plan of the context (a caller's or a tree's) once the stream has
+// finished with it.
+void destroy_plan(pgh_ctx *c, pgh_plan *p)
+{
+    auto it = std::find(c->plans.begin(), c->plans.end(), p);
+    if (it == c->plans.end()) return;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_plan_memory(p);
+    c->plans.erase(it);
+    delete p;
+}
+
+}  // namespace
+
 int pgh_plan_free(pgh_ctx *c, pgh_plan *p)
 {
     if (!c) return PGH_EINVAL;
     if (!p) return PGH_OK;
     auto it = std::find(c->plans.begin(), c->plans.end(), p);
     if (it == c->plans.end()) return fail(c, PGH_EINVAL, "plan does not belong to this context");
-    DeviceGuard g(c->device);
-    (void)hipStreamSynchronize(c->stream);
-    free_plan_memory(p);
-    c->plans.erase(it);
-    delete p;
+    if (p->tree_owned)
+        return fail(c, PGH_EINVAL, "the plan belongs to a tree and is freed with it");
+    destroy_plan(c, p);
     return PGH_OK;
 }
 
@@ -782,10 +800,13 @@ long long pgh_plan_interactions(const pgh_plan *p) { return p ? p->interactions 
 
 namespace {
 
+// A plan handle is used only once it is found among the context's live
+// plans: a freed or foreign handle is never dereferenced.
 int check_plan(pgh_ctx *c, const pgh_plan *p)
 {
     if (!p) return fail(c, PGH_EINVAL, "NULL plan");
-    if (p->owner != c) return fail(c, PGH_EINVAL, "plan belongs to another context");
+    if (std::find(c->plans.begin(), c->plans.end(), p) == c->plans.end())
+        return fail(c, PGH_EINVAL, "plan does not belong to this context");
     return PGH_OK;
 }
 
@@ -889,8 +910,8 @@ int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, const float 
     a.F = c->tab_F;
     a.c = (float)((smax - 2.0) / (rc * rc));
     a.smax = (float)smax;
-    const int v = std::max(0, c->variant[PGH_FAMILY_TABLE_BATCH]);
-    PGH_HIP(c, launch_table_batch(a, v, c->num_cu, c->stream));
+    const int v = c->variant[PGH_FAMILY_TABLE_BATCH];
+    PGH_HIP(c, launch_table_batch(a, v < 0 ? table_batch_default() : v, c->num_cu, c->stream));
     return PGH_OK;
 }
 
@@ -1015,8 +1036,8 @@ int pgh_variant_count(int family)
     switch (family) {
         case PGH_FAMILY_NEWTON_ALLPAIRS: return newton_allpairs_variants();
         case PGH_FAMILY_TABLE_ALLPAIRS: return table_allpairs_variants();
-        case PGH_FAMILY_NEWTON_BATCH:
-        case PGH_FAMILY_TABLE_BATCH: return batch_variants(family);
+        case PGH_FAMILY_NEWTON_BATCH: return newton_batch_variants();
+        case PGH_FAMILY_TABLE_BATCH: return table_batch_variants();
         default: return 0;
     }
 }
@@ -1026,8 +1047,8 @@ const char *pgh_variant_name(int family, int v)
     switch (family) {
         case PGH_FAMILY_NEWTON_ALLPAIRS: return newton_allpairs_variant_name(v);
         case PGH_FAMILY_TABLE_ALLPAIRS: return table_allpairs_variant_name(v);
-        case PGH_FAMILY_NEWTON_BATCH:
-        case PGH_FAMILY_TABLE_BATCH: return batch_variant_name(family, v);
+        case PGH_FAMILY_NEWTON_BATCH: return newton_batch_variant_name(v);
+        case PGH_FAMILY_TABLE_BATCH: return table_batch_variant_name(v);
         default: return nullptr;
     }
 }
@@ -1132,7 +1153,7 @@ int pgh_autotune_plan(pgh_ctx *c, int family, const pgh_plan *p, const float *xi
     if (!c) return PGH_EINVAL;
     if (family != PGH_FAMILY_NEWTON_BATCH && family != PGH_FAMILY_TABLE_BATCH)
         return fail(c, PGH_ERANGE, "pgh_autotune_plan tunes the batched families");
-    if (!p || p->owner != c) return fail(c, PGH_EINVAL, "plan does not belong to this context");
+    if (int st = check_plan(c, p)) return st;
     if (p->ni_total > 0 && (!xi || !yi || !zi)) return fail(c, PGH_EINVAL, "null i-arrays");
     if (p->nj_total > 0 && (!xj || !yj || !zj || !mj)) return fail(c, PGH_EINVAL, "null j-arrays");
     if (family == PGH_FAMILY_TABLE_BATCH && !c->tab_set)
@@ -1160,10 +1181,13 @@ int pgh_autotune_plan(pgh_ctx *c, int family, const pgh_plan *p, const float *xi
 
 namespace {
 
+// As check_plan: a tree handle is used only once found among the context's
+// live trees.
 int check_tree(pgh_ctx *c, const pgh_tree *t)
 {
     if (!t) return fail(c, PGH_EINVAL, "NULL tree");
-    if (t->owner != c) return fail(c, PGH_EINVAL, "tree belongs to another context");
+    if (std::find(c->trees.begin(), c->trees.end(), t) == c->trees.end())
+        return fail(c, PGH_EINVAL, "tree does not belong to this context");
     return PGH_OK;
 }
 
@@ -1190,7 +1214,7 @@ int pgh_tree_free(pgh_ctx *c, pgh_tree *t)
     if (it == c->trees.end()) return fail(c, PGH_EINVAL, "tree does not belong to this context");
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
-    if (t->plan) (void)pgh_plan_free(c, t->plan);
+    if (t->plan) destroy_plan(c, t->plan);
     tree_release(t->st);
     c->trees.erase(it);
     delete t;
@@ -1225,7 +1249,7 @@ int pgh_tree_walk(pgh_ctx *c, pgh_tree *t, float theta, int record_src)
     // The tree keeps its plan from walk to walk: the plan of the new lists
     // is written into it, reusing its device memory.
     auto drop_plan = [&] {
-        if (t->plan) (void)pgh_plan_free(c, t->plan);
+        if (t->plan) destroy_plan(c, t->plan);
         t->plan = nullptr;
     };
     std::string err;
@@ -1240,6 +1264,7 @@ int pgh_tree_walk(pgh_ctx *c, pgh_tree *t, float theta, int record_src)
             t->plan = new (std::nothrow) pgh_plan{};
             if (!t->plan) return fail(c, PGH_ENOMEM, "out of host memory");
             t->plan->owner = c;
+            t->plan->tree_owned = true;
             c->plans.push_back(t->plan);
         }
         st = c->plan_device ? plan_fill_device(c, t->plan, s.n_groups, s.host_items.data(), s.n,

@@ -53,6 +53,11 @@ struct BatchArgs {
     int q_begin[kQueues + 1];
     unsigned *queue;    // counter of sublist q at queue[q * kQueueStride]; zero between launches
     int n_waves;        // waves in the grid (set by the launcher)
+    // 1: every task is assigned statically (set by the launcher when the
+    // plan holds few tasks per wave): wave g of G runs the tasks of
+    // longest-first ranks g, 2G-1-g, 2G+g, 4G-1-g, ... and the counters are
+    // not used; 0: the sublists and their counters
+    int static_order;
     int n_chunks;     // split chunks
     const SplitChunk *chunks;
     float4 *partial;  // 64 partial sums per slot of a split chunk
@@ -130,8 +135,13 @@ int table_allpairs_split(int ni, int nj, int variant, size_t part_cap);
 hipError_t launch_table_allpairs(const TableArgs &a, int variant, int S, hipStream_t s);
 
 int batch_resident_waves(int num_cu);  // waves of the persistent grid
-int batch_variants(int family);
-const char *batch_variant_name(int family, int v);
+int newton_batch_variants();
+const char *newton_batch_variant_name(int v);
+int table_batch_variants();
+const char *table_batch_variant_name(int v);
+int table_batch_default();  // the variant used when none is chosen
+// k_combine over the split chunks of a batched launch (after it, same stream)
+hipError_t launch_combine(const BatchArgs &a, bool phi, hipStream_t s);
 // Device expansion of a compact plan (plan_expand.hip): the tasks of the
 // n_desc entries sorted longest first (keys/vals and their sorted copies
 // keys_out/order, n_tasks each; a hipCUB radix sort with temp storage of

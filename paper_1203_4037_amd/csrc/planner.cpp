@@ -118,7 +118,8 @@ int validate_items(const pgh_item *items, int n_items, int ni_total, int nj_tota
 // than 64 i-particles with a non-empty list) in chunk order, with their
 // i-particle counts ni[k] and list lengths nj[k] (indexed by the values in
 // cand).  In order of list length, each candidate takes the first later one
-// (within a window of 64) whose i-particles fit beside its own in 64 lanes,
+// (within a window of 64) whose i-particles fit beside its own in 32 lane
+// rows of two (at most 64 i-particles, at most 62 when both counts are odd),
 // when one wavefront running the longer list costs fewer lane-iterations
 // than the two apart.  Appends the pairs (chunk indices, the earlier first)
 // in the order they are formed.
@@ -169,7 +170,11 @@ void pair_chunks(Scratch &S, std::vector<int> &cand, NI ni, NJ nj,
         if (used[u / 64] >> (u % 64) & 1) continue;
         const size_t from = u + 1, len = std::min(nc, u + 1 + kWindow) - from;
         if (len == 0) break;
-        const int room = 64 - c_ni[u];
+        // two chunks share a wave when their i-particles fit in 32 lane rows
+        // of two slots each (ceil(n_1 / 2) + ceil(n_2 / 2) <= 32), so a
+        // kernel holding two i-particles per lane can run the pair as one
+        // lane per i-particle can
+        const int room = 64 - 2 * ((c_ni[u] + 1) / 2);
         unsigned long long m =
             window(&fits[(size_t)room * nw], from, len) & ~window(used.data(), from, len);
         if (c_ni[u] <= 32) {

@@ -8,7 +8,8 @@
 //   * every (i, j) pair of every item is in exactly one task (a split list's
 //     parts, and both chunks of a paired task, included), and every row of
 //     an item with n_i > 0 is in some task, so each output row is written;
-//   * tasks fit a wave (n_i <= 64; two paired chunks share 64 lanes);
+//   * tasks fit a wave (n_i <= 64; two paired chunks fit in 32 lane rows of
+//     two i-particles each);
 //   * split parts: each (slot, part) is used once, slots below n_slots, and
 //     each split chunk's lanes fit in its slots;
 //   * sublists: q_begin covers the tasks in order, at most 16 sublists, each
@@ -193,7 +194,8 @@ void check_plan(const std::vector<pgh_item> &items, int ni_total, int nj_total, 
     std::vector<int> used;  // (slot, part) uses
     for (const Task &t : T) {
         if (t.n_i < 1 || t.n_i > 64) fail(std::string(what) + ": task n_i out of [1, 64]");
-        if (t.n_i2 < 0 || t.n_i + t.n_i2 > 64) fail(std::string(what) + ": paired chunks exceed 64 lanes");
+        if (t.n_i2 < 0 || t.n_i + t.n_i2 > 64 || (t.n_i + 1) / 2 + (t.n_i2 + 1) / 2 > 32)
+            fail(std::string(what) + ": paired chunks exceed 32 rows of two lanes");
         if (t.n_parts < 1 || t.part < 0 || t.part >= t.n_parts) fail(std::string(what) + ": part fields");
         if (t.i_off < 0 || t.i_off + t.n_i > ni_total || t.j_off < 0 || t.j_off + t.n_j > nj_total)
             fail(std::string(what) + ": task outside the arrays");

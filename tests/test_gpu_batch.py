@@ -176,11 +176,12 @@ def test_graph_capture_replays(pgh, ctx):
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", range(5))
 def test_cell_list_table_force(pgh, ctx, variant):
     """Cell-grid neighbour lists in a periodic unit box (the PP part of a
     TreePM step) with the S2 table: N = 32768, 32^3 cells, 4^3-cell groups;
-    both table forms of the batched kernel."""
+    every tile shape of the batched kernel."""
+    assert pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH) == 5
     ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, variant)
     n = 32768
     x, y, z = synth.uniform_box(n, 103)
@@ -418,12 +419,16 @@ def test_random_item_sets(pgh, ctx, seed):
     assert np.all(got[:, covered & (ref[3] == 0)] == 0)  # empty lists give zeros
     rcut = 0.2
     table = ctx.build_table(4, 6, rcut, eps=rcut / 15)
-    out_t = [torch.full((ni_total,), 777.0, device="cuda") for _ in range(3)]
-    plan.table(*di, *dj, out=out_t)
-    a = np.stack(to_host(*out_t))
     rt = oracle.lut_items(items, xi, yi, zi, xj, yj, zj, mj, 4, 6, float(np.float32(rcut)), table)
     has = covered & (rt[3] > 0)
-    e1 = norm_vec_err(a[:, has], np.stack(rt[:3])[:, has], rt[3][has])
-    assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (seed, rms(e1), e1.max())
-    assert np.all(a[:, ~covered] == 777.0)
+    # every tile shape of the batched table kernel
+    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH)):
+        ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, v)
+        out_t = [torch.full((ni_total,), 777.0, device="cuda") for _ in range(3)]
+        plan.table(*di, *dj, out=out_t)
+        a = np.stack(to_host(*out_t))
+        e1 = norm_vec_err(a[:, has], np.stack(rt[:3])[:, has], rt[3][has])
+        assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (seed, v, rms(e1), e1.max())
+        assert np.all(a[:, ~covered] == 777.0)
+        assert np.all(a[:, covered & (rt[3] == 0)] == 0)
     plan.free()
