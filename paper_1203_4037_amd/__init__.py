@@ -682,30 +682,11 @@ class Context:
         x, y, z against the current j-memory (and table).  With a cache path
         (JSON) a previous choice for the same device, family and shape is
         reused without timing.  Returns the variant index."""
-        import json
         self._sync_stream()
-        key = None
-        if cache:
-            props = torch.cuda.get_device_properties(self.device)
-            key = "|".join(str(k) for k in (props.name, family, x.numel(), self.nj,
-                                             self.table if family == PGH_FAMILY_TABLE_ALLPAIRS else "",
-                                             self.refine))
-            try:
-                with open(cache) as f:
-                    table = json.load(f)
-            except (OSError, ValueError):
-                table = {}
-            if key in table and 0 <= table[key] < pgh_variant_count(family):
-                pgh_set_variant(self.h, family, table[key])
-                return table[key]
-        v, _ = pgh_autotune(self.h, family, x.numel(), x, y, z, reps)
-        if cache:
-            table[key] = v
-            tmp = cache + ".tmp"
-            with open(tmp, "w") as f:
-                json.dump(table, f, indent=1, sort_keys=True)
-            os.replace(tmp, cache)
-        return v
+        key = ("allpairs", family, x.numel(), self.nj,
+               self.table if family == PGH_FAMILY_TABLE_ALLPAIRS else "", self.refine)
+        return _cached_tune(self, family, key, cache,
+                            lambda: pgh_autotune(self.h, family, x.numel(), x, y, z, reps)[0])
 
     # interaction lists ------------------------------------------------------
 
@@ -718,6 +699,35 @@ class Context:
         return Tree(self)
 
 
+def _cached_tune(ctx, family, key, cache, tune):
+    """Runs tune() (which times the variants and selects the fastest), or,
+    with a JSON cache path holding a choice for this device and key, selects
+    that variant without timing.  Choices are stored by variant name, so a
+    library with other variants re-tunes instead of misreading an index."""
+    import json
+    if not cache:
+        return tune()
+    props = torch.cuda.get_device_properties(ctx.device)
+    k = "|".join(str(x) for x in (props.name,) + tuple(key))
+    try:
+        with open(cache) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        table = {}
+    names = [pgh_variant_name(family, v) for v in range(pgh_variant_count(family))]
+    if k in table and table[k] in names:
+        v = names.index(table[k])
+        pgh_set_variant(ctx.h, family, v)
+        return v
+    v = tune()
+    table[k] = names[v]
+    tmp = cache + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, cache)
+    return v
+
+
 class Plan:
     """Execution plan of a set of interaction lists (pgh_plan_create)."""
 
@@ -727,6 +737,13 @@ class Plan:
         self.ni_total, self.nj_total = int(ni_total), int(nj_total)
         self.h = pgh_plan_create(ctx.h, a.shape[0], a, ni_total, nj_total)
         self.interactions = pgh_plan_interactions(self.h)
+
+        def pow2(v):
+            return 1 << max(0, int(round(np.log2(max(1.0, float(v))))))
+        live = a[a[:, 1] > 0] if a.shape[0] else a
+        self.shape_class = (pow2(live.shape[0]),
+                            pow2(np.median(live[:, 1])) if live.shape[0] else 0,
+                            pow2(np.median(live[:, 3])) if live.shape[0] else 0)
 
     def free(self):
         if self.h and self.ctx.h:
@@ -766,14 +783,21 @@ class Plan:
         pgh_batch_table(c.h, self.h, xi, yi, zi, xj, yj, zj, mj, out[0], out[1], out[2], phi)
         return out
 
-    def autotune(self, family, xi, yi, zi, xj, yj, zj, mj, reps=3):
-        """Selects the fastest variant of a batched family on this plan
-        (PGH_FAMILY_NEWTON_BATCH uses the context's eps_to_all) and returns
-        its index."""
-        self.ctx._sync_stream()
+    def autotune(self, family, xi, yi, zi, xj, yj, zj, mj, reps=3, cache=None):
+        """Selects the fastest variant (tile shape) of a batched family on this
+        plan (PGH_FAMILY_NEWTON_BATCH uses the context's eps_to_all) and
+        returns its index.  With a cache path (JSON) a previous choice for a
+        plan of the same shape class on the same device is reused without
+        timing: the class is the number of lists and the median group size
+        and list length, each rounded to a power of two, with the table and
+        the rsqrt mode."""
+        c = self.ctx
+        c._sync_stream()
         self._check_sizes((xi, yi, zi), (xj, yj, zj, mj))
-        v, _ = pgh_autotune_plan(self.ctx.h, family, self.h, xi, yi, zi, xj, yj, zj, mj, reps)
-        return v
+        key = ("plan", family) + self.shape_class + (
+            c.table if family == PGH_FAMILY_TABLE_BATCH else "", c.refine)
+        return _cached_tune(c, family, key, cache, lambda: pgh_autotune_plan(
+            c.h, family, self.h, xi, yi, zi, xj, yj, zj, mj, reps)[0])
 
 
 # --------------------------------------------------------------------------

@@ -92,7 +92,9 @@ int split_count(int ni, int nj, int ki, int jt, int target_waves, size_t part_ca
 {
     const long waves = ((long)ni + 64L * ki - 1) / (64L * ki);
     long S = (target_waves + waves - 1) / waves;
-    S = std::min(S, std::max(1L, (long)nj / (2L * jt)));  // at least two tiles per share
+    // at least two tiles per share, or one of 64 records (small i-sets,
+    // whose waves come from the split alone)
+    S = std::min(S, std::max(1L, (long)nj / (jt > 64 ? 2L * jt : (long)jt)));
     if (ni > 0) S = std::min(S, (long)(part_cap / (4 * (size_t)ni)));
     return (int)std::max(1L, S);
 }
@@ -120,8 +122,8 @@ namespace {
 template <int KI, int JT, int U, bool RCP, bool REFINE, bool GUARD, bool PHI>
 __global__ void __launch_bounds__(256) k_newton_allpairs(NewtonArgs a)
 {
-    static_assert(JT % 256 == 0, "tile must be a multiple of the workgroup");
-    constexpr int PER = JT / 256;
+    static_assert(JT % 256 == 0 || JT == 64, "a tile is 64 records or whole workgroup rounds");
+    constexpr int PER = JT >= 256 ? JT / 256 : 1;  // records each thread loads per tile
     __shared__ float4 tile[2][JT];
 
     const int tid = threadIdx.x;
@@ -148,12 +150,13 @@ __global__ void __launch_bounds__(256) k_newton_allpairs(NewtonArgs a)
     const int ntiles = (nj + JT - 1) / JT;
     float4 pre[PER];
 
+    // (a 64-record tile is loaded by the first wave of the workgroup)
     auto load_tile = [&](int t) {
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
             const int j = t * JT + r * 256 + tid;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (j < nj) v = jm[j];
+            if ((JT >= 256 || tid < JT) && j < nj) v = jm[j];
             pre[r] = v;  // not touched until stored, so the load stays in flight
         }
     };
@@ -162,7 +165,7 @@ __global__ void __launch_bounds__(256) k_newton_allpairs(NewtonArgs a)
         for (int r = 0; r < PER; ++r) {
             float4 v = pre[r];
             v.w *= mscale;
-            tile[buf][r * 256 + tid] = v;
+            if (JT >= 256 || tid < JT) tile[buf][r * 256 + tid] = v;
         }
     };
 
@@ -263,6 +266,7 @@ struct NewtonVariant {
 
 const NewtonVariant kNewtonVariants[] = {
     {"ki=1 jt=256 u=8", 1, 256, &NewtonSet<1, 256, 8, false>::get},
+    {"ki=1 jt=64 u=8", 1, 64, &NewtonSet<1, 64, 8, false>::get},
     {"ki=2 jt=256 u=4", 2, 256, &NewtonSet<2, 256, 4, false>::get},
     {"ki=4 jt=256 u=2", 4, 256, &NewtonSet<4, 256, 2, false>::get},
     {"ki=2 jt=512 u=8", 2, 512, &NewtonSet<2, 512, 8, false>::get},
@@ -283,11 +287,13 @@ const char *newton_allpairs_variant_name(int v)
 
 int newton_allpairs_default(int ni, int nj, int num_cu)
 {
-    (void)ni, (void)nj, (void)num_cu;
+    (void)nj;
     // One i per lane, 256-record tiles, unrolled by 8: the fastest measured
-    // at every size (small ni is spread over the j-split); pgh_autotune
-    // confirms or replaces it for a given workload.
-    return 0;
+    // from a few thousand i-particles up.  An i-set of at most 16 waves per
+    // 256 CUs takes the 64-record tiles, so that the j-split (one tile per
+    // share at least) gives it a wave per CU or more.  pgh_autotune confirms
+    // or replaces the choice for a given workload.
+    return ni <= 4 * num_cu ? 1 : 0;
 }
 
 int newton_allpairs_split(int ni, int nj, int variant, size_t part_cap)

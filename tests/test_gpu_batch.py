@@ -290,6 +290,41 @@ def test_plan_autotuner_table_family(pgh, ctx):
     assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
 
 
+def test_plan_autotuner_cache(pgh, ctx, tmp_path):
+    """The plan autotuner's JSON cache: the first plan is timed and its
+    choice stored by variant name under its shape class; a second plan of the
+    same class (another seed) takes the stored variant without timing, and a
+    plan of another class is timed again."""
+    import json
+    fam = pgh.PGH_FAMILY_TABLE_BATCH
+    cache = str(tmp_path / "tune.json")
+    rcut = 1.0 / 32
+    ctx.build_table(4, 6, rcut, eps=rcut / 15)
+    plans = []
+    for seed, block in ((91, 4), (92, 4), (93, 8)):
+        x, y, z = synth.uniform_box(16384, seed)
+        s = synth.cell_grid_items(x, y, z, synth.equal_masses(16384), ncell=32, block=block)
+        di, dj = _dev_set(s)
+        plans.append((ctx.plan(s.items, 16384, s.xj.size), di, dj))
+    p0, p1, p2 = plans
+    assert p0[0].shape_class == p1[0].shape_class != p2[0].shape_class
+    v0 = p0[0].autotune(fam, *p0[1], *p0[2], reps=2, cache=cache)
+    with open(cache) as f:
+        stored = json.load(f)
+    assert list(stored.values()) == [pgh.pgh_variant_name(fam, v0)]
+    # a stored choice is taken as is: mark it with another variant and see it come back
+    other = (v0 + 1) % pgh.pgh_variant_count(fam)
+    key = next(iter(stored))
+    stored[key] = pgh.pgh_variant_name(fam, other)
+    with open(cache, "w") as f:
+        json.dump(stored, f)
+    assert p1[0].autotune(fam, *p1[1], *p1[2], cache=cache) == other
+    assert pgh.pgh_get_variant(ctx.h, fam) == other
+    p2[0].autotune(fam, *p2[1], *p2[2], reps=2, cache=cache)
+    with open(cache) as f:
+        assert len(json.load(f)) == 2
+
+
 def test_two_contexts_on_two_streams(pgh):
     """Two contexts, each on its own stream with its own j-memory, table and
     plans, launched interleaved: no state leaks from one to the other."""

@@ -49,10 +49,13 @@ def test_sample_code_sequence_newton(pgh):
     ep = np.abs(p - ref[3]) / np.abs(ref[3])
     assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, (rms(ea), ea.max())
     assert rms(ep) <= 1e-5 and ep.max() <= 1e-3, (rms(ep), ep.max())
-    # a subset of i-particles, and no potential array
+    # a subset of i-particles, and no potential array: the same sums (the
+    # j-range is split into shares by the size of the i-set, so the order of
+    # the additions, and the last bits, may differ from the call above)
     a2 = np.zeros((100, 3))
     pgh.g5_calculate_force_on_x(np.ascontiguousarray(x[:100]), a2, None, 100)
-    assert np.array_equal(a2, a[:100])
+    ea2 = rel_vec_err(a2.T, np.stack(ref[:3])[:, :100])
+    assert rms(ea2) <= 1e-5 and ea2.max() <= 1e-3, (rms(ea2), ea2.max())
     pgh.g5_calculate_force_on_x(x, a2, None, 0)  # ni = 0 is a no-op
 
 
