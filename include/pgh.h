@@ -129,6 +129,25 @@ PGH_API int pgh_set_rsqrt_refine(pgh_ctx *c, int on);
 PGH_API int pgh_calc_newton(pgh_ctx *c, int ni, const float *xi, const float *yi, const float *zi,
                     const float *eps2_i, float *ax, float *ay, float *az, float *phi);
 
+/* pgh_calc_newton for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as pgh_calc_newton, and it
+ * calls no hipMalloc, hipFree or allocating library routine.  Where
+ * pgh_calc_newton grows a context buffer for the partial sums of its
+ * j-split, this entry point uses a fixed device array of 2^20 floats
+ * (4 MiB) that the library holds on each GPU it runs on until the process
+ * ends (located at pgh_open; PGH_ESTATE if that failed): the split is
+ * limited to the shares whose partial sums (S x 4 x ni floats) fit it, and a
+ * launch that cannot be split uses none of it, so no input size is
+ * rejected.  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (two contexts or streams at once) race and must be ordered by the
+ * caller.  Nothing in the array has to start at zero; each call overwrites
+ * the part it reads.  The j-memory must already hold the j-particles
+ * (pgh_set_xmj, which may allocate, is called before). */
+PGH_API int pgh_calc_newton_noalloc(pgh_ctx *c, int ni, const float *xi, const float *yi,
+                                    const float *zi, const float *eps2_i, float *ax, float *ay,
+                                    float *az, float *phi);
+
 /* ---------------------------------------------------------------------- */
 /* Central force of arbitrary shape through the bit-binned table (Sec. 3.4) */
 /* ---------------------------------------------------------------------- */

@@ -86,6 +86,7 @@ SIGNATURES = {
     "pgh_set_rsqrt_refine": (_I, [_P, _I]),
     "pgh_set_plan_expansion": (_I, [_P, _I]),
     "pgh_calc_newton": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "pgh_calc_newton_noalloc": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pgh_build_table": (_I, [_P, _I, _I, _F, _P, _P, _P]),
     "pgh_table_compute": (_I, [_I, _I, _F, _P, _P, _P]),
     "pgh_set_table": (_I, [_P, _I, _I, _F, _P]),
@@ -225,6 +226,13 @@ def pgh_set_xmj(ctx, adr, nj, x, y, z, m):
 
 def pgh_calc_newton(ctx, ni, xi, yi, zi, eps2_i, ax, ay, az, phi):
     _check(ctx, lib.pgh_calc_newton(ctx, ni, _ptr(xi, ni, "xi"), _ptr(yi, ni, "yi"),
+                                    _ptr(zi, ni, "zi"), _ptr(eps2_i, ni, "eps2_i"),
+                                    _ptr(ax, ni, "ax"), _ptr(ay, ni, "ay"), _ptr(az, ni, "az"),
+                                    _ptr(phi, ni, "phi")))
+
+
+def pgh_calc_newton_noalloc(ctx, ni, xi, yi, zi, eps2_i, ax, ay, az, phi):
+    _check(ctx, lib.pgh_calc_newton_noalloc(ctx, ni, _ptr(xi, ni, "xi"), _ptr(yi, ni, "yi"),
                                     _ptr(zi, ni, "zi"), _ptr(eps2_i, ni, "eps2_i"),
                                     _ptr(ax, ni, "ax"), _ptr(ay, ni, "ay"), _ptr(az, ni, "az"),
                                     _ptr(phi, ni, "phi")))

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -177,6 +178,31 @@ int ensure_scratch(pgh_ctx *c, float4 **buf, size_t *cap, size_t n)
 
 // Upper bound of the partial-sum buffer of j-split launches (floats).
 constexpr size_t kMaxSplitFloats = (size_t)64 << 20;
+
+// Scratch of the allocation-free entry point (pgh_calc_newton_noalloc): the
+// partial sums of its j-split, in a device array of fixed size that each GPU
+// holds for the life of the process.  Host code never passes the array's name
+// to a kernel (on the host it is a stand-in, not a device address): the
+// device address is looked up once per device, with that device current, and
+// kept in g_scratch_ptr.
+constexpr size_t kNoAllocFloats = (size_t)1 << 20;  // 4 MiB
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Looks up this device's copy of the scratch array (device current).
+int resolve_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return PGH_ERANGE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return PGH_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PGH_EHIP;
+    g_scratch_ptr[device] = (float *)ptr;
+    return PGH_OK;
+}
 
 int ensure_part(pgh_ctx *c, size_t n)
 {
@@ -429,6 +455,9 @@ int pgh_open(pgh_ctx **out, int device, void *hip_stream)
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         ncu > 0)
         c->num_cu = ncu;
+    // the allocation-free entry point's scratch on this device (a failure
+    // is reported by that entry point, which then refuses to run)
+    (void)resolve_scratch(device);
     e = hipMalloc((void **)&c->tab, sizeof(float2) << kMaxTableBits);
     if (e == hipSuccess)
         e = hipMalloc((void **)&c->gcopy, (sizeof(float2) << kMaxTableBits) * kGradCopies);
@@ -554,6 +583,35 @@ int pgh_calc_newton(pgh_ctx *c, int ni, const float *xi, const float *yi, const 
         int st = ensure_part(c, (size_t)S * 4 * ni);
         if (st) return st;
         a.part = c->part;
+    }
+    PGH_HIP(c, launch_newton_allpairs(a, v, c->refine != 0, guard, S, c->stream));
+    return PGH_OK;
+}
+
+int pgh_calc_newton_noalloc(pgh_ctx *c, int ni, const float *xi, const float *yi,
+                            const float *zi, const float *eps2_i, float *ax, float *ay, float *az,
+                            float *phi)
+{
+    if (!c) return PGH_EINVAL;
+    if (ni < 0) return fail(c, PGH_EINVAL, "ni must be >= 0");
+    if (ni == 0) return PGH_OK;
+    if (!xi || !yi || !zi || !ax || !ay || !az)
+        return fail(c, PGH_EINVAL, "NULL i-particle or output array");
+    if (c->device < 0 || c->device >= kMaxDevices || !g_scratch_ptr[c->device])
+        return fail(c, PGH_ESTATE, "the device's scratch array could not be located at pgh_open");
+    DeviceGuard g(c->device);
+    if (c->nj == 0) return zero_outputs(c, ni, ax, ay, az, phi);
+    NewtonArgs a{ni, xi, yi, zi, eps2_i, c->eps2_all, c->nj, c->jmem, ax, ay, az, phi, 0, nullptr};
+    const bool guard = (eps2_i == nullptr) && !(c->eps2_all > 0.f);
+    int v = c->variant[PGH_FAMILY_NEWTON_ALLPAIRS];
+    if (v < 0) v = newton_allpairs_default(ni, c->nj, c->num_cu);
+    // the split is limited to the shares whose partial sums fit the array
+    // (S * 4 * ni floats); a launch that cannot be split needs no scratch
+    const int S = newton_allpairs_split(ni, c->nj, v, kNoAllocFloats);
+    if (S > 1) {
+        if ((size_t)S * 4 * (size_t)ni > kNoAllocFloats)
+            return fail(c, PGH_ERANGE, "the j-split exceeds the scratch array");
+        a.part = g_scratch_ptr[c->device];
     }
     PGH_HIP(c, launch_newton_allpairs(a, v, c->refine != 0, guard, S, c->stream));
     return PGH_OK;
