@@ -27,8 +27,9 @@ import time
 
 import numpy as np
 
-PEAK_FP32_TFLOPS = 157.3  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
-PEAK_FP32_UNPACKED_TFLOPS = 78.6
+# 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 x 2.4 GHz: the factor 2 is packed FP32 or, as these
+# kernels use it, the dual issue of two single FP32 instructions per quad-cycle
+PEAK_FP32_TFLOPS = 157.3
 NEWTON_FLOPS = 38  # per interaction, the paper's count (Sec. 5.1)
 TABLE_FLOPS = 20  # per interaction, this project's count of the FP32 ops of the table loop
 
@@ -306,9 +307,13 @@ def newton_allpairs(torch, pgh, synth, args):
 REPLAYS = {"override": 0}
 
 
-def graph_ms(torch, fn, reps):
-    """Captures fn() in a graph (a hipGraph under ROCm) and returns the mean
-    replay time in ms, from events on the replay stream."""
+def graph_ms(torch, fn, reps, calls=1):
+    """Captures `calls` consecutive calls of fn() in one graph (a hipGraph
+    under ROCm) and returns the mean time per call in ms over `reps` replays,
+    from events on the replay stream.  A replay of a one-call graph costs
+    about 17 us of host time on this stack, so microsecond kernels are timed
+    from graphs of several calls, where only the device's dispatch gaps remain
+    between them."""
     reps = REPLAYS["override"] or reps
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -318,7 +323,8 @@ def graph_ms(torch, fn, reps):
     torch.cuda.current_stream().wait_stream(side)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        fn()
+        for _ in range(calls):
+            fn()
     g.replay()
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
@@ -328,12 +334,56 @@ def graph_ms(torch, fn, reps):
         g.replay()
     b.record()
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps
+    return a.elapsed_time(b) / (reps * calls)
+
+
+CALLS_PER_GRAPH = 10
+
+
+def call_times(torch, fn, reps):
+    """Per-call ms from a graph of CALLS_PER_GRAPH calls (the rate the device
+    sustains when the caller keeps it fed) and per replay of a one-call graph
+    (which adds the host's replay cost)."""
+    return {"ms_per_call": graph_ms(torch, fn, max(2, reps // CALLS_PER_GRAPH), CALLS_PER_GRAPH),
+            "ms_per_replay_1call": graph_ms(torch, fn, reps)}
+
+
+def newton_refined(torch, pgh, synth):
+    """The headline workload (Plummer N = 262144, eps = 0.01) with one
+    Newton-Raphson step after v_rsq_f32 (pgh_set_rsqrt_refine(1)), the
+    literal form of the rsqrt refinement of Sec. 2: the variant the
+    autotuner picks with the step on, kernel time from events on the launch
+    stream (5 calls after 2)."""
+    n = 262144
+    x, y, z = synth.plummer(n, 102)
+    m = synth.equal_masses(n)
+    dev = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+    out = [torch.empty(n, device="cuda") for _ in range(4)]
+    ctx = pgh.Context(0)
+    ctx.set_eps_to_all(0.01)
+    ctx.set_rsqrt_refine(1)
+    ctx.set_j(*dev)
+    fam = pgh.PGH_FAMILY_NEWTON_ALLPAIRS
+    v = ctx.autotune(fam, dev[0], dev[1], dev[2], reps=2)
+    timer = KernelTimer(torch)
+    for k in range(7):
+        if k < 2:
+            pgh.pgh_calc_newton(ctx.h, n, dev[0], dev[1], dev[2], None, *out)
+            continue
+        with timer:
+            pgh.pgh_calc_newton(ctx.h, n, dev[0], dev[1], dev[2], None, *out)
+    ms = timer.mean_ms()
+    ctx.close()
+    inter = float(n) * n
+    return {"workload": "newton_allpairs_plummer_N262144_eps0.01_rsqrt_newton_step",
+            "rsqrt_refine": 1, "kernel_variant": pgh.pgh_variant_name(fam, v), "kernel_ms": ms,
+            "interactions_per_s": inter / (ms / 1e3),
+            "frac_of_peak_38flop": NEWTON_FLOPS * inter / (ms / 1e3) / (PEAK_FP32_TFLOPS * 1e12)}
 
 
 def newton_small(torch, pgh, synth):
     """Newton all-pairs at N = 1024 (Plummer, seed 101, eps = 1/64): a
-    launch-bound size; the set_xmj + calc_newton pair replayed from a graph."""
+    launch-bound size; the set_xmj + calc_newton pair, timed from graphs."""
     n = 1024
     x, y, z = synth.plummer(n, 101)
     m = synth.equal_masses(n)
@@ -346,10 +396,10 @@ def newton_small(torch, pgh, synth):
         ctx.set_j(*dev)
         pgh.pgh_calc_newton(ctx.h, n, dev[0], dev[1], dev[2], None, *out)
 
-    ms = graph_ms(torch, call, 200)
+    t = call_times(torch, call, 200)
     ctx.close()
-    return {"workload": "newton_allpairs_plummer_N1024_eps1/64", "ms_per_call": ms,
-            "interactions_per_s": n * n / (ms / 1e3)}
+    return {"workload": "newton_allpairs_plummer_N1024_eps1/64", **t,
+            "interactions_per_s": n * n / (t["ms_per_call"] / 1e3)}
 
 
 def grape5_host(torch, pgh, synth, n=262144):
@@ -386,9 +436,9 @@ def ni_nj_sweep(torch, pgh, synth):
     Plummer sphere of 2^21, consecutive groups) against n_j j-particles
     (consecutive windows of the same sphere), eps = 1e-3, about 2^31
     interactions per launch (at most 131072 lists).  Each point runs the
-    lists two ways: GRAPE-style, one pgh_set_n + pgh_calc_newton per list
-    against a j-memory holding the whole pool (timed over a sample of
-    lists), and all lists in one persistent batched launch (graph replay)."""
+    lists two ways: GRAPE-style, one pgh_set_xmj + pgh_calc_newton per list
+    (ten lists captured in one graph, so the time per list is the device's,
+    not Python's), and all lists in one persistent batched launch."""
     n = 1 << 21
     x, y, z = synth.plummer(n, 106)
     m = synth.equal_masses(n)
@@ -407,16 +457,17 @@ def ni_nj_sweep(torch, pgh, synth):
             inter = float(plan.interactions)
             plan.free()
             # GRAPE-style calls: one list per call, j-memory = that list's window
-            sample = min(n_items, 256)
-            t = KernelTimer(torch)
-            with t:
-                for k in range(sample):
-                    i0, _, j0, _ = items[k]
-                    pgh.pgh_set_xmj(ctx.h, 0, nj, d[0][j0:], d[1][j0:], d[2][j0:], d[3][j0:])
+            calls = [(int(items[k][0]), int(items[k][2])) for k in range(min(n_items, 10))]
+            views = [([t[j0:j0 + nj] for t in d], [t[i0:i0 + ni] for t in d[:3]],
+                      [t[i0:i0 + ni] for t in out]) for i0, j0 in calls]
+
+            def grape_calls():
+                for jv, iv, ov in views:
+                    pgh.pgh_set_xmj(ctx.h, 0, nj, *jv)
                     pgh.pgh_set_n(ctx.h, nj)
-                    pgh.pgh_calc_newton(ctx.h, ni, d[0][i0:], d[1][i0:], d[2][i0:], None,
-                                        out[0][i0:], out[1][i0:], out[2][i0:], out[3][i0:])
-            call_ms = t.mean_ms() / sample
+                    pgh.pgh_calc_newton(ctx.h, ni, *iv, None, *ov)
+
+            call_ms = graph_ms(torch, grape_calls, 20) / len(views)
             res.append({"n_i": ni, "n_j": nj, "lists": n_items,
                         "batched_interactions_per_s": inter / (ms / 1e3),
                         "per_call_interactions_per_s": ni * nj / (call_ms / 1e3),
@@ -473,8 +524,10 @@ def batched_table(torch, pgh, synth):
     """Cell-grid lists of a TreePM PP step: N = 262144 uniform in the unit
     periodic box, 64^3 cells, i-groups of 4^3 cells with their 6^3-cell halo
     (4096 lists; and 8^3-cell groups with a 10^3-cell halo, 512 lists),
-    S2 PP shape rcut = 3/256, eps = 1/1280, E = 4, F = 6; replayed from a
-    graph.  Also the rate of useful pairs (closer than rcut)."""
+    S2 PP shape rcut = 3/256, eps = 1/1280, E = 4, F = 6 (and F = 5).  Every
+    tile shape of the batched kernel is timed, the autotuner's choice is
+    reported with its per-call time from a graph of ten calls and per replay
+    of a one-call graph; also the rate of useful pairs (closer than rcut)."""
     n = 262144
     rcut = 3.0 / 256
     x, y, z = synth.uniform_box(n, 103)
@@ -492,21 +545,24 @@ def batched_table(torch, pgh, synth):
         per = {}
         for v in range(pgh.pgh_variant_count(fam)):
             ctx.set_variant(fam, v)
-            per[pgh.pgh_variant_name(fam, v)] = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 200)
+            per[pgh.pgh_variant_name(fam, v)] = graph_ms(
+                torch, lambda: plan.table(*di, *dj, out=out), 20, CALLS_PER_GRAPH)
         tuned = plan.autotune(fam, *di, *dj, reps=20)
-        ms = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 200)
+        t = call_times(torch, lambda: plan.table(*di, *dj, out=out), 200)
         inter = float(plan.interactions)
         plan.free()
         ctx.close()
+        ms = t["ms_per_call"]
         rate = inter / (ms / 1e3)
         useful = useful_pairs(s, rcut)
         res[f"block{block}" + ("" if F == 6 else f"_F{F}")] = {
             "workload": f"table_batched_cell_lists_N262144_E4F{F}_block{block}",
-            "lists": int(len(s.items)), "interactions": inter, "useful_pairs": useful,
-            "ms_per_launch": ms, "interactions_per_s": rate,
-            "useful_pairs_per_s": useful / (ms / 1e3),
+            "lists": int(len(s.items)), "interactions": inter, "useful_pairs": useful, **t,
+            "interactions_per_s": rate, "useful_pairs_per_s": useful / (ms / 1e3),
             "frac_of_peak_20flop": TABLE_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12),
-            "autotuned_variant": pgh.pgh_variant_name(fam, tuned), "ms_per_variant": per}
+            "frac_of_peak_20flop_1call_replay":
+                TABLE_FLOPS * inter / (t["ms_per_replay_1call"] / 1e3) / (PEAK_FP32_TFLOPS * 1e12),
+            "autotuned_variant": pgh.pgh_variant_name(fam, tuned), "ms_per_call_per_variant": per}
     return res
 
 
@@ -559,7 +615,8 @@ def adjoint_table(torch, pgh, synth):
     """Table-force forward and adjoint on cell lists: N = 65536 uniform in the
     unit periodic box, 64^3 cells, 8^3-cell groups, S2 PP shape (rcut = 3/256,
     eps = 1/1280, E = 4, F = 6); the adjoint with respect to the table entries
-    and masses, and also with the i- and j-position gradients."""
+    and masses, and also with the i- and j-position gradients; per call from
+    graphs of ten calls."""
     n = 65536
     x, y, z = synth.uniform_box(n, 105)
     m = synth.equal_masses(n)
@@ -573,12 +630,13 @@ def adjoint_table(torch, pgh, synth):
     out = [torch.empty(n, device="cuda") for _ in range(3)]
     gt = torch.empty(table.size, device="cuda")
     gm = torch.empty(s.xj.size, device="cuda")
-    f_ms = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 50)
-    b_ms = graph_ms(torch, lambda: pgh.pgh_batch_table_bwd(ctx.h, plan.h, *di, *dj, *w, gt, gm), 50)
+    f_ms = graph_ms(torch, lambda: plan.table(*di, *dj, out=out), 10, CALLS_PER_GRAPH)
+    b_ms = graph_ms(torch, lambda: pgh.pgh_batch_table_bwd(ctx.h, plan.h, *di, *dj, *w, gt, gm), 10,
+                    CALLS_PER_GRAPH)
     gi = [torch.empty(n, device="cuda") for _ in range(3)]
     gj = [torch.empty(s.xj.size, device="cuda") for _ in range(3)]
     bx_ms = graph_ms(torch, lambda: pgh.pgh_batch_table_bwd(ctx.h, plan.h, *di, *dj, *w, gt, gm,
-                                                            *gi, *gj), 50)
+                                                            *gi, *gj), 10, CALLS_PER_GRAPH)
     inter = float(plan.interactions)
     plan.free()
     ctx.close()
@@ -712,7 +770,8 @@ def main():
         sys.exit(1)
     REPLAYS["override"] = args.replays
     if args.only_extra:
-        extras = {"newton_small": newton_small, "table_allpairs": table_allpairs,
+        extras = {"newton_small": newton_small, "newton_refined": newton_refined,
+                  "table_allpairs": table_allpairs,
                   "newton_batched": batched_newton, "table_batched": batched_table,
                   "adjoint_newton": adjoint_newton, "adjoint_table": adjoint_table,
                   "ni_nj_sweep": ni_nj_sweep, "grape5_host": grape5_host,
@@ -761,16 +820,16 @@ def main():
                      "kernel": "k_newton_allpairs", "kernel_ms": r["kern_ms"],
                      "kernel_ms_median": r["kern_ms_median"], "kernel_ms_min": r["kern_ms_min"],
                      "flops_per_interaction": NEWTON_FLOPS,
-                     # the FP32 flops the VALU counters count for this kernel (21 per
-                     # interaction, not the paper's 38), against the unpacked-instruction
-                     # ceiling; null when the counters were taken on other sources
+                     # the FP32 flops the VALU counters count for this kernel (FMA = 2;
+                     # 21 per interaction, not the paper's 38) against the same peak;
+                     # null when the counters were taken on other sources
                      "valu_flops_per_interaction": hw_flops,
                      "valu_tflops": hw_tflops,
-                     "valu_frac_of_unpacked_peak": (hw_tflops / PEAK_FP32_UNPACKED_TFLOPS
-                                                    if hw_tflops else None)},
+                     "valu_frac_of_peak": (hw_tflops / PEAK_FP32_TFLOPS if hw_tflops else None)},
     }
     if not args.no_extras:
-        ex = {"newton_small": newton_small(torch, pgh, synth),
+        ex = {"newton_refined": newton_refined(torch, pgh, synth),
+              "newton_small": newton_small(torch, pgh, synth),
               "table_allpairs": table_allpairs(torch, pgh, synth),
               "newton_batched": batched_newton(torch, pgh, synth),
               "table_batched": batched_table(torch, pgh, synth),

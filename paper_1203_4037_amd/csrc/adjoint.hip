@@ -411,18 +411,33 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
             gt[2 * k + 1] = 0.f;
         }
     __syncthreads();
-    const unsigned shift = 23u - (unsigned)a.F, nbits = (unsigned)(a.E + a.F);
-    const unsigned hmask = ~((1u << shift) - 1u);
-    const unsigned klast = (unsigned)K - 1u;
-    const float c = a.c, smax = a.smax, c2 = 2.0f * a.c;
+    // bins as byte offsets into the (G0, G1) table, uniform operands in
+    // VGPRs (the forward's table_pairs_v); offset `last` is the clamped node
+    const TableConsts kc = table_consts(a.c, a.smax, a.E, a.F, 3);
+    const unsigned last = kc.am;
+    const char *tab = (const char *)stab;
+    char *gtb = (char *)gt;
+    const float c2 = 2.0f * a.c;
     float4 *tile = buf[wave];
     float last0 = 0.f;  // clamped pairs: dL/dG0 of the last node
 
     const unsigned n_all = (unsigned)(n_m + n_i);
     const unsigned n_waves = gridDim.x * 4;
-    for (unsigned t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wave); t < n_all;) {
+    // At most four tasks per wave: a static order (round k of wave g takes
+    // task k G + g, or k G + G - 1 - g for odd k, pairing long tasks with
+    // short ones) with no atomics; else the first round by index and later
+    // ones from the counter.
+    const bool stat = n_all <= 4u * n_waves;
+    const unsigned gw = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wave);
+    unsigned round = 0;
+    for (unsigned t = gw; t < n_all;) {
         unsigned tn = n_all;
-        if (n_all > n_waves && lane == 0) {
+        if (stat) {
+            ++round;
+            const unsigned long long r =
+                (unsigned long long)round * n_waves + ((round & 1u) ? n_waves - 1u - gw : gw);
+            tn = r < n_all ? (unsigned)r : n_all;
+        } else if (n_all > n_waves && lane == 0) {
             // one pop per task executed: the pop that draws n_all-1 is the
             // launch's last and puts the counter back to zero
             const unsigned k =
@@ -462,15 +477,14 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
                 float r2 = dx * dx;
                 r2 = __builtin_fmaf(dy, dy, r2);
                 r2 = __builtin_fmaf(dz, dz, r2);
-                const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
-                const unsigned u = __float_as_uint(s);
-                const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
-                const float ds = s - __uint_as_float(u & hmask);
+                const unsigned u = min(__float_as_uint(__builtin_fmaf(r2, kc.c, 2.0f)), kc.smax_bits);
+                const unsigned off = (u >> kc.sh) & kc.am;  // 8 k for bin k
+                const float ds = __uint_as_float(u) - __uint_as_float(u & kc.hm);
                 float wd = p.w * dx;
                 wd = __builtin_fmaf(w.x, dy, wd);
                 wd = __builtin_fmaf(w.y, dz, wd);
                 if (want_m || want_xj) {
-                    const float2 g01 = stab[k];
+                    const float2 g01 = *(const float2 *)(tab + off);
                     const float g = __builtin_fmaf(g01.y, ds, g01.x);
                     if (want_m) G = __builtin_fmaf(g, wd, G);
                     if (want_xj) {
@@ -485,11 +499,11 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
                 }
                 if (want_tab) {
                     const float v0 = mj * wd;
-                    if (k == klast) {
+                    if (off == last) {
                         last0 += v0;
                     } else if (active) {
-                        atomicAdd(&gt[2 * k], v0);
-                        atomicAdd(&gt[2 * k + 1], v0 * ds);
+                        atomicAdd((float *)(gtb + off), v0);
+                        atomicAdd((float *)(gtb + off + 4), v0 * ds);
                     }
                 }
             };
@@ -551,11 +565,9 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
                 float r2 = dx * dx;
                 r2 = __builtin_fmaf(dy, dy, r2);
                 r2 = __builtin_fmaf(dz, dz, r2);
-                const float s = __builtin_fminf(__builtin_fmaf(r2, c, 2.0f), smax);
-                const unsigned u = __float_as_uint(s);
-                const unsigned k = __builtin_amdgcn_ubfe(u, shift, nbits);
-                const float ds = s - __uint_as_float(u & hmask);
-                const float2 g01 = stab[k];
+                const unsigned u = min(__float_as_uint(__builtin_fmaf(r2, kc.c, 2.0f)), kc.smax_bits);
+                const float ds = __uint_as_float(u) - __uint_as_float(u & kc.hm);
+                const float2 g01 = *(const float2 *)(tab + ((u >> kc.sh) & kc.am));
                 const float g = __builtin_fmaf(g01.y, ds, g01.x);
                 float wd = wx * dx;
                 wd = __builtin_fmaf(wy, dy, wd);
@@ -598,7 +610,7 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
     if (want_tab) {
         // wave sum of the clamped-bin register, then flush this workgroup's bins
         for (int off = 32; off > 0; off >>= 1) last0 += __shfl_xor(last0, off);
-        if (lane == 0 && last0 != 0.f) atomicAdd(&gt[2 * klast], last0);
+        if (lane == 0 && last0 != 0.f) atomicAdd(&gt[2 * (K - 1)], last0);
         __syncthreads();
         float *dst = A.gcopies + (size_t)(blockIdx.x % kGradCopies) * 2 * K;
         for (int k = threadIdx.x; k < 2 * K; k += 256)

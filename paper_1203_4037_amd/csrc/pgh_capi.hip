@@ -466,6 +466,7 @@ int pgh_open(pgh_ctx **out, int device, void *hip_stream)
         g_open_error = std::string("hipMalloc(table): ") + hipGetErrorString(e);
         (void)hipFree(c->tab);
         (void)hipFree(c->gcopy);
+        (void)hipFree(c->ptab);
         delete c;
         return PGH_ENOMEM;
     }

@@ -441,30 +441,43 @@ void plan_adjoint_tasks(const std::vector<pgh_item> &ordered, int waves, std::ve
 {
     const std::vector<pgh_item> &ord = ordered;
     waves = std::max(1, waves);
-    // i-major tasks of the table adjoint (the i-side position gradient, its
-    // own list independent of the forward's chunking): i-chunks of <= 64
-    // against j-ranges of <= 512, added with atomics, so no partial sums
-    std::vector<Task> &it_tasks = out_i;
-    it_tasks.clear();
-    for (const pgh_item &it : ord) {
-        for (int s0 = 0; s0 < it.n_i; s0 += 64)
-            for (int q0 = 0; q0 < it.n_j; q0 += 512)
-                it_tasks.push_back({it.i_off + s0, std::min(64, it.n_i - s0), it.j_off + q0,
-                                    std::min(512, it.n_j - q0), 0, 1, 0, 0, 0, 0, 0, 0});
-    }
-    std::stable_sort(it_tasks.begin(), it_tasks.end(), [](const Task &a, const Task &b) {
-        return (long long)a.n_j * ((a.n_i + 15) / 16) > (long long)b.n_j * ((b.n_i + 15) / 16);
-    });
     // j-major tasks of the table adjoint: chunks of <= 64 j-entries of a
     // list against its i-group (chunks of 32 or 16, 2 or 4 lanes per entry,
     // when chunks of 64 would fill less than half of the resident waves)
     int jc = 64;
+    long long n_j = 0;
     for (;;) {
-        long long n = 0;
-        for (const pgh_item &it : ord) n += (it.n_j + jc - 1) / jc;
-        if (2 * n >= waves || jc == 16) break;
+        n_j = 0;
+        for (const pgh_item &it : ord) n_j += (it.n_j + jc - 1) / jc;
+        if (2 * n_j >= waves || jc == 16) break;
         jc /= 2;
     }
+    // i-major tasks (the i-side position gradient, its own list independent
+    // of the forward's chunking): i-chunks of <= 64 against j-ranges of
+    // <= 512, added with atomics, so no partial sums; chunks of 32 or 16 (2
+    // or 4 lanes per i-particle) while the two kinds together would fill
+    // less than the resident waves twice over
+    int ic = 64;
+    for (;;) {
+        long long n_i = 0;
+        for (const pgh_item &it : ord)
+            n_i += (long long)((it.n_i + ic - 1) / ic) * ((it.n_j + 511) / 512);
+        if (n_i + n_j >= 2LL * waves || ic == 16) break;
+        ic /= 2;
+    }
+    std::vector<Task> &it_tasks = out_i;
+    it_tasks.clear();
+    for (const pgh_item &it : ord) {
+        for (int s0 = 0; s0 < it.n_i; s0 += ic)
+            for (int q0 = 0; q0 < it.n_j; q0 += 512)
+                it_tasks.push_back({it.i_off + s0, std::min(ic, it.n_i - s0), it.j_off + q0,
+                                    std::min(512, it.n_j - q0), 0, 1, 0, 0, 0, 0, 0, 0});
+    }
+    // longest first, a task's length in lane steps (n_j over the lanes per
+    // i-particle)
+    std::stable_sort(it_tasks.begin(), it_tasks.end(), [](const Task &a, const Task &b) {
+        return lane_steps(a.n_j, chunk_js(a.n_i)) > lane_steps(b.n_j, chunk_js(b.n_i));
+    });
     std::vector<Task> &jt = out_j;
     jt.clear();
     for (const pgh_item &it : ord) {
