@@ -133,6 +133,22 @@ struct DeviceGuard {
 
 double smax_of(int E, int F) { return std::ldexp(1.0, 1 << E) * (2.0 - std::ldexp(1.0, -F)); }
 
+// The FP32 scale c of s = fma(|d|^2, c, 2) (Sec. 3.4.2 with the scale applied
+// to |d|^2): (s_max - 2) / rcut^2 rounded to FP32, then raised to the
+// smallest FP32 value at which a pair at distance rcut (|d|^2 = fl(rcut^2))
+// reaches s_max.  Rounded to nearest, about one cutoff in five would put
+// such a pair one FP32 step below s_max, in the next-to-last bin, with a
+// force of the size of a rounding instead of zero; since the FMA is monotone
+// in |d|^2, every pair at or beyond rcut now clamps to the last node, whose
+// entries are zero.
+float table_scale(double smax, float rcut)
+{
+    const float r2 = rcut * rcut;
+    float c = (float)((smax - 2.0) / ((double)rcut * (double)rcut));
+    while (std::fmaf(r2, c, 2.0f) < (float)smax) c = std::nextafterf(c, INFINITY);
+    return c;
+}
+
 int check_table_shape(pgh_ctx *c, int E, int F, float rcut)
 {
     if (E < 0 || E > 6) return fail(c, PGH_ERANGE, "E must be in [0, 6]");
@@ -761,9 +777,8 @@ int pgh_calc_table(pgh_ctx *c, int ni, const float *xi, const float *yi, const f
     DeviceGuard g(c->device);
     if (c->nj == 0) return zero_outputs(c, ni, ax, ay, az, phi);
     const double smax = smax_of(c->tab_E, c->tab_F);
-    const double rc = c->tab_rcut;
     TableArgs a{ni, xi, yi, zi, c->nj, c->jmem, c->tab, c->tab_E, c->tab_F,
-                (float)((smax - 2.0) / (rc * rc)), (float)smax, ax, ay, az, 0, nullptr,
+                table_scale(smax, c->tab_rcut), (float)smax, ax, ay, az, 0, nullptr,
                 phi ? c->ptab : nullptr, phi};
     int v = c->variant[PGH_FAMILY_TABLE_ALLPAIRS];
     if (v < 0) v = table_allpairs_default(ni, c->nj, c->num_cu);
@@ -963,11 +978,10 @@ int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, const float 
     a.phi = phi;
     a.ptable = phi ? c->ptab : nullptr;
     const double smax = smax_of(c->tab_E, c->tab_F);
-    const double rc = c->tab_rcut;
     a.table = c->tab;
     a.E = c->tab_E;
     a.F = c->tab_F;
-    a.c = (float)((smax - 2.0) / (rc * rc));
+    a.c = table_scale(smax, c->tab_rcut);
     a.smax = (float)smax;
     const int v = c->variant[PGH_FAMILY_TABLE_BATCH];
     PGH_HIP(c, launch_table_batch(a, v < 0 ? table_batch_default() : v, c->num_cu, c->stream));
@@ -1067,11 +1081,10 @@ int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const fl
     A.b.xi = xi, A.b.yi = yi, A.b.zi = zi;
     A.b.xj = xj, A.b.yj = yj, A.b.zj = zj, A.b.mj = mj;
     const double smax = smax_of(c->tab_E, c->tab_F);
-    const double rc = c->tab_rcut;
     A.b.table = c->tab;
     A.b.E = c->tab_E;
     A.b.F = c->tab_F;
-    A.b.c = (float)((smax - 2.0) / (rc * rc));
+    A.b.c = table_scale(smax, c->tab_rcut);
     A.b.smax = (float)smax;
     A.wx = wx, A.wy = wy, A.wz = wz;
     A.gtable = gtable;

@@ -46,6 +46,9 @@ def _table_case(pgh, ctx, n, box, E, F, eps, rcut, seed, variants=None):
     ctx.set_j(*dj)
     items = np.array([[0, n, 0, n]], np.int32)
     rt = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, float(np.float32(rcut)), table)
+    # the oracle through its own table (built by its own builder): the same
+    # gate without the library's host table builder in the chain
+    ro = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, float(np.float32(rcut)), ref_tab)
     rx = oracle.central_items(items, x, y, z, x, y, z, m, oracle.SHAPE_S2PP, eps,
                               float(np.float32(rcut)))
     vs = variants if variants is not None else range(
@@ -56,6 +59,8 @@ def _table_case(pgh, ctx, n, box, E, F, eps, rcut, seed, variants=None):
         has = rt[3] > 0
         e1 = norm_vec_err(a[:, has], np.stack(rt[:3])[:, has], rt[3][has])
         assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (v, rms(e1), e1.max())
+        eo = norm_vec_err(a[:, has], np.stack(ro[:3])[:, has], ro[3][has])
+        assert rms(eo) <= 1e-5 and eo.max() <= 1e-3, (v, rms(eo), eo.max())
         hx = rx[4] > 0
         e2 = norm_vec_err(a[:, hx], np.stack(rx[:3])[:, hx], rx[4][hx])
         assert e2.max() <= 1e-3, (v, e2.max())
@@ -76,6 +81,54 @@ def test_s2_table_force_dense_box(pgh, ctx, E, F):
     pgh.pgh_table_compute(E, F, np.float32(3.0 / 256), pgh.s2pp_callback(),
                           ctypes.cast(params, ctypes.c_void_p), host)
     assert np.array_equal(table, host)
+
+
+def test_table4_bins_and_cutoff_on_device(pgh, ctx):
+    """Table 4 (Sec. 3.4.1, E = 4, F = 6) on the device: single pairs at
+    r = 0, rcut/2 and rcut fall in bins 0, 895 and 1023 (tests/golden), read
+    through a potential table whose nodes hold their own indices (P0_k = k,
+    P1_k = 0, so phi = m_j k exactly), in the all-pairs and the batched
+    kernels; and with the S2 table a pair at, just beyond and well beyond
+    rcut adds exactly zero force (the last node, Sec. 3.4.2), whatever the
+    cutoff's FP32 rounding."""
+    import json
+    import os
+    import torch
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table4_E4F6.json")))
+    E, F = gold["E"], gold["F"]
+    K = 1 << (E + F)
+    for rcut in (3.0 / 256, 0.2, 0.0117, 0.1):
+        ctx.build_table(E, F, rcut, eps=rcut / 15)
+        pot = np.zeros(2 * K, np.float32)
+        pot[0::2] = np.arange(K, dtype=np.float32)
+        pot_d = torch.from_numpy(pot).cuda()
+        ctx._sync_stream()
+        pgh.pgh_set_pot_table(ctx.h, pot_d)
+        rc = np.float32(rcut)
+        r = np.array([row["r_over_rcut"] * rc for row in gold["rows"]]
+                     + [np.nextafter(rc, np.float32(1)), 1.5 * rc, 10 * rc], np.float32)
+        want = [row["index"] for row in gold["rows"]] + [K - 1] * 3
+        n = r.size
+        z0 = np.zeros(n, np.float32)
+        di = to_dev(r, z0, z0)  # i-particles at (r, 0, 0)
+        dj = to_dev(np.zeros(1, np.float32), np.zeros(1, np.float32), np.zeros(1, np.float32),
+                    np.ones(1, np.float32))  # one j-particle of mass 1 at the origin
+        ctx.set_j(*dj)
+        ax, ay, az, phi = ctx.table_force(*di, with_phi=True)
+        got = [to_host(ax, ay, az, phi)]
+        plan = ctx.plan(np.array([[i, 1, 0, 1] for i in range(n)], np.int32), n, 1)
+        for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH)):
+            ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, v)
+            got.append(to_host(*plan.table(*di, *dj, with_phi=True)))
+        plan.free()
+        for gx, gy, gz, gp in got:
+            assert list(gp) == want, (rcut, gp)
+            assert np.all(gx[2:] == 0) and np.all(gy == 0) and np.all(gz == 0), (rcut, gx)
+        # the same pairs with the force table: zero at and beyond rcut, and
+        # the rcut/2 pair non-zero
+        ax, _, _ = ctx.table_force(*di)
+        a = to_host(ax)[0]
+        assert a[1] != 0 and np.all(a[2:] == 0), (rcut, a)
 
 
 @pytest.mark.parametrize("E,F", [(0, 3), (2, 3), (6, 6), (4, 8), (3, 0)])

@@ -123,6 +123,7 @@ def test_lists_match_oracle(pgh, ctx, quad):
     assert np.array_equal(items[:, 2][1:], np.cumsum(items[:, 3])[:-1]) and items[0, 2] == 0
     pp = t.get("pseudo")
     xs = t.get("x")
+    leaf_of = _leaf_of(o)
     exact = border = 0
     for k, gn in enumerate(g):
         s_gpu = src[items[k, 2]:items[k, 2] + items[k, 3]]
@@ -143,7 +144,57 @@ def test_lists_match_oracle(pgh, ctx, quad):
         for nd in np.unique(nodes):
             cover[o.begin[nd]:o.begin[nd] + o.count[nd]] += 1
         assert np.all(cover == 1), k
+        _check_decisions(o, gn, np.unique(nodes), s_gpu[part], 0.75, leaf_of, k)
     assert exact >= 0.9 * len(g), (exact, border)
+    assert border > 0  # the borderline branch is exercised
+
+
+def _leaf_of(o):
+    """The leaf holding each sorted particle rank."""
+    leaf = np.full(o.x.size, -1, np.int64)
+    for t in np.nonzero(o.n_child == 0)[0]:
+        leaf[o.begin[t]:o.begin[t] + o.count[t]] = t
+    assert np.all(leaf >= 0)
+    return leaf
+
+
+def _check_decisions(o, g, accepted, particles, theta, leaf_of, what):
+    """Every decision behind a GPU list taken near a threshold agrees with the
+    criterion of the FP64 oracle to within BORDER: with crit(t) = (d - l /
+    theta) / s (d the distance from the node's FP64 centre of mass to the
+    group's box, l the node size, s the largest magnitude among the
+    coordinates involved, as the oracle's margin is measured), each accepted
+    node has crit > -BORDER, and each opened node that is neither the group
+    nor one of its ancestors (the nodes above an accepted node, and the
+    leaves of the particle entries with the nodes above them) has
+    crit < +BORDER."""
+    b0, b1 = o.begin[g], o.begin[g] + o.count[g]
+    lo = np.array([o.x[b0:b1].min(), o.y[b0:b1].min(), o.z[b0:b1].min()])
+    hi = np.array([o.x[b0:b1].max(), o.y[b0:b1].max(), o.z[b0:b1].max()])
+
+    def crit(t):
+        c = o.com[t]
+        e = np.where(c < lo, lo - c, np.where(c > hi, c - hi, 0.0))
+        d = np.sqrt((e * e).sum(-1))
+        sc = np.maximum(1.0, np.maximum(np.abs(c).max(-1), max(np.abs(lo).max(), np.abs(hi).max())))
+        l = o.extent / 2.0 ** o.level[t]
+        return (d - l / theta) / sc
+
+    def is_anc(t):  # the group and its ancestors: opened without a test
+        return (o.level[t] <= o.level[g]) & (o.begin[t] <= b0) & (b0 < o.begin[t] + o.count[t])
+
+    accepted = np.asarray(accepted, np.int64)
+    assert not np.any(is_anc(accepted)), what
+    assert np.all(crit(accepted) > -BORDER), what
+    opened = set()
+    for t in list(accepted) + list(np.unique(leaf_of[particles])):
+        u = int(o.parent[t]) if t in accepted else int(t)
+        while u >= 0 and u not in opened:
+            opened.add(u)
+            u = int(o.parent[u])
+    opened = np.array(sorted(opened), np.int64)
+    opened = opened[~is_anc(opened)]
+    assert np.all(crit(opened) < BORDER), what
 
 
 @pytest.mark.parametrize("quad", [False, True])
@@ -296,6 +347,14 @@ def test_rewalk_refills_the_plan(pgh, ctx):
         ref = np.stack(oracle.newton_items(items, o.x, o.y, o.z, e2, *lists))
         ea = rel_vec_err(got[:3], ref[:3])
         assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, theta
+    # the walk's plan belongs to the tree: pgh_plan_free refuses it, and the
+    # tree's next walk and force still use it
+    assert pgh.lib.pgh_plan_free(ctx.h, plan) == pgh.PGH_EINVAL
+    t.walk(0.75)
+    assert pgh.lib.pgh_tree_plan(t.h) == plan
+    again = np.stack(to_host(*t.newton()))[:, o.perm]
+    ea = rel_vec_err(again[:3], ref[:3])
+    assert rms(ea) <= 1e-5 and ea.max() <= 1e-3
     t.build(*to_dev(x, y, z, m), n_leaf=8, n_crit=64)
     assert pgh.lib.pgh_tree_plan(t.h) is None
     t.free()
