@@ -41,8 +41,8 @@ constexpr int kWaves = kBatchWaves;
 
 // REFINE: the Newton-Raphson step after v_rsq_f32; GUARD: zero softening
 // (a coincident pair adds nothing); PHI: the potential; RCP: rho^2 from
-// v_rcp_f32.
-template <bool RCP, bool REFINE, bool GUARD, bool PHI>
+// v_rcp_f32; U: pairs per lane unrolled in a full tile.
+template <bool RCP, bool REFINE, bool GUARD, bool PHI, int U>
 __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
 {
     // [wave][buffer][list][record], double-buffered
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(256, 8) k_batch(BatchArgs a)
                 auto full_tile = [&](auto stride) {
                     constexpr int S = decltype(stride)::value;
                     const float4 *b = src + ph;
-#pragma unroll 4
+#pragma unroll U
                     for (int it = 0; it < 64 / S; ++it)
                         newton_pair<REFINE, GUARD, PHI, RCP>(b[it * S], px, py, pz, pe, sx, sy,
                                                              sz, sp);
@@ -232,25 +232,43 @@ __global__ void __launch_bounds__(64) k_combine(CombineArgs a)
 
 using BatchKernel = void (*)(BatchArgs);
 
-template <bool RCP>
+template <bool RCP, int U>
 BatchKernel newton_kernel_t(bool refine, bool guard, bool phi)
 {
     const int sel = (refine ? 4 : 0) | (guard ? 2 : 0) | (phi ? 1 : 0);
     switch (sel) {
-        case 0: return k_batch<RCP, false, false, false>;
-        case 1: return k_batch<RCP, false, false, true>;
-        case 2: return k_batch<RCP, false, true, false>;
-        case 3: return k_batch<RCP, false, true, true>;
-        case 4: return k_batch<RCP, true, false, false>;
-        case 5: return k_batch<RCP, true, false, true>;
-        case 6: return k_batch<RCP, true, true, false>;
-        default: return k_batch<RCP, true, true, true>;
+        case 0: return k_batch<RCP, false, false, false, U>;
+        case 1: return k_batch<RCP, false, false, true, U>;
+        case 2: return k_batch<RCP, false, true, false, U>;
+        case 3: return k_batch<RCP, false, true, true, U>;
+        case 4: return k_batch<RCP, true, false, false, U>;
+        case 5: return k_batch<RCP, true, false, true, U>;
+        case 6: return k_batch<RCP, true, true, false, U>;
+        default: return k_batch<RCP, true, true, true, U>;
     }
 }
 
-BatchKernel newton_kernel(bool refine, bool guard, bool phi, bool rcp = false)
+// The tile shapes the autotuner chooses among: the unroll of the pair loop
+// over a 64-record j-tile (pairs per lane in flight) and the rho^2 form
+// (v_rsq_f32 squared, or v_rcp_f32 of r^2).
+struct NewtonBatchVariant {
+    const char *name;
+    BatchKernel (*pick)(bool refine, bool guard, bool phi);
+};
+const NewtonBatchVariant kNewtonBatchVariants[] = {
+    {"ki=1 jt=64 u=8", newton_kernel_t<false, 8>},  // the default
+    {"ki=1 jt=64 u=8 rcp", newton_kernel_t<true, 8>},
+    {"ki=1 jt=64 u=4", newton_kernel_t<false, 4>},
+    {"ki=1 jt=64 u=2", newton_kernel_t<false, 2>},
+    {"ki=1 jt=64 u=16", newton_kernel_t<false, 16>},
+};
+constexpr int kNumNewtonBatchVariants =
+    sizeof(kNewtonBatchVariants) / sizeof(kNewtonBatchVariants[0]);
+
+BatchKernel newton_kernel(bool refine, bool guard, bool phi, int variant = 0)
 {
-    return rcp ? newton_kernel_t<true>(refine, guard, phi) : newton_kernel_t<false>(refine, guard, phi);
+    if (variant < 0 || variant >= kNumNewtonBatchVariants) variant = 0;
+    return kNewtonBatchVariants[variant].pick(refine, guard, phi);
 }
 
 // Workgroups that fit on one CU at once (registers, LDS), so the persistent
@@ -302,13 +320,11 @@ int batch_resident_waves(int num_cu)
     return num_cu * kWaves * resident_blocks(newton_kernel(true, false, true), 0);
 }
 
-const char *const kNewtonBatchNames[] = {"lds j-tiles", "lds j-tiles rcp"};
-
-int newton_batch_variants() { return 2; }
+int newton_batch_variants() { return kNumNewtonBatchVariants; }
 
 const char *newton_batch_variant_name(int v)
 {
-    return (v >= 0 && v < 2) ? kNewtonBatchNames[v] : nullptr;
+    return (v >= 0 && v < kNumNewtonBatchVariants) ? kNewtonBatchVariants[v].name : nullptr;
 }
 
 hipError_t launch_newton_batch(const BatchArgs &a, int variant, bool refine, bool guard,
@@ -316,7 +332,7 @@ hipError_t launch_newton_batch(const BatchArgs &a, int variant, bool refine, boo
 {
     // packed outputs always carry the potential
     const bool phi = a.phi != nullptr || a.out4 != nullptr;
-    return launch(newton_kernel(refine, guard, phi, variant == 1), a, num_cu, s, phi);
+    return launch(newton_kernel(refine, guard, phi, variant), a, num_cu, s, phi);
 }
 
 }  // namespace pgh

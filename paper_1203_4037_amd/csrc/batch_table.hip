@@ -52,7 +52,7 @@ struct TaskLanes {
 // KI i-particles per lane, TW j-records per lane per tile (unpaired tasks),
 // 2^TB table entries at most, HT the (H, G1) form, PHI the potential table,
 // WPB waves per workgroup (one table copy per workgroup).
-template <int KI, int TW, int TB, bool HT, bool PHI, int WPB>
+template <int KI, int TW, int TB, bool HT, bool PHI, int WPB, bool PF>
 // eight waves per SIMD whatever the workgroup size (64 VGPRs at most)
 __global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_batch_table(BatchArgs a)
@@ -60,7 +60,9 @@ k_batch_table(BatchArgs a)
     using Entry = std::conditional_t<PHI, float4, float2>;
     constexpr int kEntryLog = PHI ? 4 : 3;
     __shared__ Entry stab[1 << TB];
-    __shared__ float4 jt[WPB][128];
+    // a wave's j-tile: 128 records and 8 of padding, read (and unused) by
+    // the prefetch after a tile's last step
+    __shared__ float4 jt[WPB][136];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -188,8 +190,26 @@ k_batch_table(BatchArgs a)
                 auto full = [&](auto stride_c, auto trips_c) {
                     constexpr int S = decltype(stride_c)::value;
                     constexpr int N = decltype(trips_c)::value;
+                    if constexpr (PF) {
+                        // the next record is read before this step's
+                        // table gathers are waited for, so one LDS round
+                        // trip per step remains on the wave's path
+                        float4 p = src[0];
 #pragma unroll 2
-                    for (int it = 0; it < N; ++it) step(src[it * S]);
+                        for (int it = 0; it < N; ++it) {
+                            TableGather<KI, PHI> q;
+                            table_head<KI, HT, PHI>(p, L.px, L.py, L.pz, tab, kc, q);
+                            const float4 pn = src[(it + 1) * S];
+                            // nothing of the sums moves above the next
+                            // record's read
+                            __builtin_amdgcn_sched_barrier(0);
+                            table_tail<KI, PHI>(p.w, q, tx, ty, tz, tp);
+                            p = pn;
+                        }
+                    } else {
+#pragma unroll 2
+                        for (int it = 0; it < N; ++it) step(src[it * S]);
+                    }
                 };
                 using std::integral_constant;
                 if (L.paired) {
@@ -247,14 +267,14 @@ k_batch_table(BatchArgs a)
 
 using TableKernel = void (*)(BatchArgs);
 
-template <int KI, int TW, bool HT, int WPB>
+template <int KI, int TW, bool HT, int WPB, bool PF = false>
 TableKernel pick(int tb, bool phi)
 {
     if (tb <= 10)
-        return phi ? k_batch_table<KI, TW, 10, HT, true, WPB>
-                   : k_batch_table<KI, TW, 10, HT, false, WPB>;
-    return phi ? k_batch_table<KI, TW, 12, HT, true, WPB>
-               : k_batch_table<KI, TW, 12, HT, false, WPB>;
+        return phi ? k_batch_table<KI, TW, 10, HT, true, WPB, PF>
+                   : k_batch_table<KI, TW, 10, HT, false, WPB, PF>;
+    return phi ? k_batch_table<KI, TW, 12, HT, true, WPB, PF>
+               : k_batch_table<KI, TW, 12, HT, false, WPB, PF>;
 }
 
 struct TableBatchVariant {
@@ -276,6 +296,7 @@ const TableBatchVariant kTableBatchVariants[] = {
     {"ki=2 tw=2 wg=4", 4, pick<2, 2, false, 4>},
     {"ki=1 tw=1 wg=16", 16, pick<1, 1, false, 16>},
     {"ki=2 tw=2 wg=16", 16, pick<2, 2, false, 16>},
+    {"ki=1 tw=1 wg=4 pf", 4, pick<1, 1, false, 4, true>},
 };
 constexpr int kNumTableBatchVariants = sizeof(kTableBatchVariants) / sizeof(kTableBatchVariants[0]);
 

@@ -239,42 +239,68 @@ __device__ __forceinline__ TableConsts table_consts(float c, float smax, int E, 
 // clamp at s_max compares the bit patterns (v_min_u32): for s >= 2 their
 // order is the order of the numbers, and unlike v_min_f32 it needs no
 // quieting of its operands.
+// The pairs' state between issuing their table gathers and using them.
+template <int KI, bool PHI>
+struct TableGather {
+    using Entry = std::conditional_t<PHI, float4, float2>;
+    float dx[KI], dy[KI], dz[KI], ds[KI];
+    Entry t[KI];
+};
+
+// First half of table_pairs_v: differences, s, the bin's offset and its LDS
+// gather (issued, not waited for) and s - s_k.
+template <int KI, bool HT, bool PHI>
+__device__ __forceinline__ void table_head(const float4 p, const float *px, const float *py,
+                                           const float *pz, const char *__restrict__ tab,
+                                           const TableConsts &k, TableGather<KI, PHI> &q)
+{
+    using Entry = typename TableGather<KI, PHI>::Entry;
+    unsigned u[KI];
+#pragma unroll
+    for (int i = 0; i < KI; ++i) {
+        q.dx[i] = p.x - px[i];
+        q.dy[i] = p.y - py[i];
+        q.dz[i] = p.z - pz[i];
+    }
+#pragma unroll
+    for (int i = 0; i < KI; ++i) {
+        float r2 = q.dx[i] * q.dx[i];
+        r2 = __builtin_fmaf(q.dy[i], q.dy[i], r2);
+        r2 = __builtin_fmaf(q.dz[i], q.dz[i], r2);
+        u[i] = min(__float_as_uint(__builtin_fmaf(r2, k.c, 2.0f)), k.smax_bits);
+    }
+#pragma unroll
+    for (int i = 0; i < KI; ++i) q.t[i] = *(const Entry *)(tab + ((u[i] >> k.sh) & k.am));
+#pragma unroll
+    for (int i = 0; i < KI; ++i)
+        q.ds[i] = HT ? __uint_as_float(u[i]) : __uint_as_float(u[i]) - __uint_as_float(u[i] & k.hm);
+}
+
+// Second half: the interpolated g (and p) and the sums; mj the j-mass.
+template <int KI, bool PHI>
+__device__ __forceinline__ void table_tail(const float mj, const TableGather<KI, PHI> &q,
+                                           float *sx, float *sy, float *sz, float *sp)
+{
+#pragma unroll
+    for (int i = 0; i < KI; ++i) {
+        const float g = __builtin_fmaf(q.t[i].y, q.ds[i], q.t[i].x);
+        const float mg = mj * g;
+        sx[i] = __builtin_fmaf(mg, q.dx[i], sx[i]);
+        sy[i] = __builtin_fmaf(mg, q.dy[i], sy[i]);
+        sz[i] = __builtin_fmaf(mg, q.dz[i], sz[i]);
+        if constexpr (PHI) sp[i] = __builtin_fmaf(mj, __builtin_fmaf(q.t[i].w, q.ds[i], q.t[i].z), sp[i]);
+    }
+}
+
 template <int KI, bool HT, bool PHI>
 __device__ __forceinline__ void table_pairs_v(const float4 p, const float *px, const float *py,
                                               const float *pz, const char *__restrict__ tab,
                                               const TableConsts &k, float *sx, float *sy,
                                               float *sz, float *sp)
 {
-    float dx[KI], dy[KI], dz[KI], s[KI];
-    unsigned u[KI];
-#pragma unroll
-    for (int q = 0; q < KI; ++q) {
-        dx[q] = p.x - px[q];
-        dy[q] = p.y - py[q];
-        dz[q] = p.z - pz[q];
-    }
-#pragma unroll
-    for (int q = 0; q < KI; ++q) {
-        float r2 = dx[q] * dx[q];
-        r2 = __builtin_fmaf(dy[q], dy[q], r2);
-        r2 = __builtin_fmaf(dz[q], dz[q], r2);
-        u[q] = min(__float_as_uint(__builtin_fmaf(r2, k.c, 2.0f)), k.smax_bits);
-        s[q] = __uint_as_float(u[q]);
-    }
-    using Entry = std::conditional_t<PHI, float4, float2>;
-    Entry t[KI];
-#pragma unroll
-    for (int q = 0; q < KI; ++q) t[q] = *(const Entry *)(tab + ((u[q] >> k.sh) & k.am));
-#pragma unroll
-    for (int q = 0; q < KI; ++q) {
-        const float ds = HT ? s[q] : s[q] - __uint_as_float(u[q] & k.hm);
-        const float g = __builtin_fmaf(t[q].y, ds, t[q].x);
-        const float mg = p.w * g;
-        sx[q] = __builtin_fmaf(mg, dx[q], sx[q]);
-        sy[q] = __builtin_fmaf(mg, dy[q], sy[q]);
-        sz[q] = __builtin_fmaf(mg, dz[q], sz[q]);
-        if constexpr (PHI) sp[q] = __builtin_fmaf(p.w, __builtin_fmaf(t[q].w, ds, t[q].z), sp[q]);
-    }
+    TableGather<KI, PHI> q;
+    table_head<KI, HT, PHI>(p, px, py, pz, tab, k, q);
+    table_tail<KI, PHI>(p.w, q, sx, sy, sz, sp);
 }
 
 }  // namespace pgh

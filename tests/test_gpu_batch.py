@@ -10,6 +10,11 @@ from _helpers import norm_vec_err, rel_vec_err, rms, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
+# tile shapes of the batched table kernel (each is run by the cell-list test)
+TABLE_BATCH_VARIANTS = 6
+# tile shapes of the batched Newton kernel
+NEWTON_BATCH_VARIANTS = 5
+
 
 @pytest.fixture(scope="module")
 def pgh():
@@ -57,7 +62,7 @@ def _newton_case(pgh, ctx, s, eps, sample_items=None):
     return plan, di, dj, out, got
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", range(NEWTON_BATCH_VARIANTS))
 @pytest.mark.parametrize("refine", [1, 0])
 def test_tree_style_small(pgh, ctx, variant, refine):
     """A small instance of the batched tree workload: Morton-sorted Plummer
@@ -69,7 +74,7 @@ def test_tree_style_small(pgh, ctx, variant, refine):
     _newton_case(pgh, ctx, s, 1e-3)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", range(NEWTON_BATCH_VARIANTS))
 def test_group_size_edges_and_split_lists(pgh, ctx, variant):
     """Group sizes around the lane-sharing thresholds (16, 32, 64) and j-lists
     of 0, 1, 63, 64, 65 and long ones that the plan cuts into parts."""
@@ -176,12 +181,12 @@ def test_graph_capture_replays(pgh, ctx):
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("variant", range(5))
+@pytest.mark.parametrize("variant", range(TABLE_BATCH_VARIANTS))
 def test_cell_list_table_force(pgh, ctx, variant):
     """Cell-grid neighbour lists in a periodic unit box (the PP part of a
     TreePM step) with the S2 table: N = 32768, 32^3 cells, 4^3-cell groups;
     every tile shape of the batched kernel."""
-    assert pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH) == 5
+    assert pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH) == TABLE_BATCH_VARIANTS
     ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, variant)
     n = 32768
     x, y, z = synth.uniform_box(n, 103)
