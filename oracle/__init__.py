@@ -188,6 +188,35 @@ def lut_eval(s, E, F, table):
     return lib().pgo_lut_eval(float(s), E, F, _ptr(t))
 
 
+def _round_f32(fr):
+    """The FP32 number nearest to the rational fr (ties to an even last bit)."""
+    from fractions import Fraction
+    f = np.float32(float(fr))
+    cands = [np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))]
+    return min(cands, key=lambda c: (abs(Fraction(float(c)) - fr),
+                                     int(np.array(c, np.float32).view(np.uint32)) & 1))
+
+
+def table_ht(table, E, F):
+    """The (H, G1) form of an interleaved FP32 table (force or potential):
+    the interpolant G0_k + G1_k (s - s_k) of Sec. 3.4.2 rewritten as
+    H_k + G1_k s, with H_k = G0_k - G1_k s_k rounded once to FP32 (the form
+    the "htab" kernel variants keep in LDS).  Returned as a float64 table in
+    the paper's form, (H_k + G1_k s_k, G1_k), so the paper-form evaluators
+    (lut_items, lut_pot_items) interpolate H_k + G1_k s with it."""
+    from fractions import Fraction
+    K = 1 << (E + F)
+    t = np.asarray(table, dtype=np.float32).reshape(K, 2)
+    out = np.zeros((K, 2), dtype=np.float64)
+    for k in range(K):
+        g0, g1 = Fraction(float(t[k, 0])), Fraction(float(t[k, 1]))
+        sk = Fraction(node_s(E, F, k))
+        h = _round_f32(g0 - g1 * sk)
+        out[k, 0] = float(Fraction(float(h)) + g1 * sk)
+        out[k, 1] = float(g1)
+    return out.reshape(-1)
+
+
 def lut_items(items, xi, yi, zi, xj, yj, zj, mj, E, F, rcut, table):
     """Table force over interaction lists. Returns (ax, ay, az, absum)."""
     it = _items32(items)

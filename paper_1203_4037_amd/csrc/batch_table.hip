@@ -284,12 +284,14 @@ struct TableBatchVariant {
 };
 
 // The tile shapes the autotuner chooses among: i-particles per lane (KI),
-// j-records per lane per tile (TW) and waves per workgroup.  All use the
-// paper's (G0, G1) form: the (H, G1) form of the all-pairs variants saves two
-// instructions per pair, but its rounding of H_k = G0_k - G1_k s_k is
-// relative to G1_k s_k, not to g, and near rcut, where g goes to zero, it can
-// exceed the table's 1e-3 error for a particle whose only neighbours lie
-// there.
+// j-records per lane per tile (TW), waves per workgroup, the one-record
+// prefetch (pf) and the table form.  The "htab" variants keep the (H, G1)
+// form in LDS (two instructions fewer per pair): the same interpolant with
+// one more FP32 rounding per node, of H_k = G0_k - G1_k s_k, which is
+// relative to G1_k s_k rather than to g; near rcut, where g goes to zero,
+// that rounding can be a large part of the little force there, so these
+// variants are parity-checked against the oracle's (H, G1) table and, for the
+// method's accuracy, against the analytic force.
 const TableBatchVariant kTableBatchVariants[] = {
     {"ki=1 tw=1 wg=4", 4, pick<1, 1, false, 4>},
     {"ki=2 tw=1 wg=4", 4, pick<2, 1, false, 4>},
@@ -297,6 +299,8 @@ const TableBatchVariant kTableBatchVariants[] = {
     {"ki=1 tw=1 wg=16", 16, pick<1, 1, false, 16>},
     {"ki=2 tw=2 wg=16", 16, pick<2, 2, false, 16>},
     {"ki=1 tw=1 wg=4 pf", 4, pick<1, 1, false, 4, true>},
+    {"ki=2 tw=1 wg=4 htab", 4, pick<2, 1, true, 4>},
+    {"ki=2 tw=2 wg=4 htab", 4, pick<2, 2, true, 4>},
 };
 constexpr int kNumTableBatchVariants = sizeof(kTableBatchVariants) / sizeof(kTableBatchVariants[0]);
 

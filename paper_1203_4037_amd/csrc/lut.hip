@@ -181,7 +181,7 @@ int table_allpairs_default(int ni, int nj, int num_cu)
 int table_allpairs_split(int ni, int nj, int variant, size_t part_cap)
 {
     const TableVariant &v = kTableVariants[variant];
-    return split_count(ni, nj, v.ki, v.jt, 4 * kSplitTargetWaves, part_cap);
+    return split_count(ni, nj, v.ki, v.jt, kSplitTargetWaves, part_cap);
 }
 
 hipError_t launch_table_allpairs(const TableArgs &a0, int variant, int S, hipStream_t s)

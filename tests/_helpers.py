@@ -32,3 +32,12 @@ def to_dev(*arrays):
 
 def to_host(*tensors):
     return [t.detach().cpu().numpy().astype(np.float64) for t in tensors]
+
+
+def oracle_table(pgh, family, variant, table, E, F):
+    """The table the oracle interpolates to check a table-kernel variant: the
+    (H, G1) form (oracle.table_ht) for the "htab" variants, whose LDS copy
+    holds H_k = fl32(G0_k - G1_k s_k); the table itself for the others."""
+    import oracle
+    name = pgh.pgh_variant_name(family, variant)
+    return oracle.table_ht(table, E, F) if "htab" in name else table

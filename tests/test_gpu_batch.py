@@ -6,12 +6,12 @@ import pytest
 
 import oracle
 import synth
-from _helpers import norm_vec_err, rel_vec_err, rms, to_dev, to_host
+from _helpers import oracle_table, norm_vec_err, rel_vec_err, rms, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
 # tile shapes of the batched table kernel (each is run by the cell-list test)
-TABLE_BATCH_VARIANTS = 6
+TABLE_BATCH_VARIANTS = 8
 # tile shapes of the batched Newton kernel
 NEWTON_BATCH_VARIANTS = 5
 
@@ -198,7 +198,8 @@ def test_cell_list_table_force(pgh, ctx, variant):
     plan = ctx.plan(s.items, n, s.xj.size)
     a = np.stack(to_host(*plan.table(*di, *dj)))
     rt = oracle.lut_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, 4, 6,
-                          float(np.float32(rcut)), table)
+                          float(np.float32(rcut)),
+                          oracle_table(pgh, pgh.PGH_FAMILY_TABLE_BATCH, variant, table, 4, 6))
     rx = oracle.central_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj,
                               oracle.SHAPE_S2PP, eps, float(np.float32(rcut)))
     has = rt[3] > 0
@@ -227,12 +228,13 @@ def test_cell_list_table_config_full(pgh, ctx):
     rng = np.random.default_rng(0)
     pick = np.unique(np.concatenate([[0, len(s.items) - 1], rng.integers(0, len(s.items), 94)]))
     items = s.items[pick]
-    rt = oracle.lut_items(items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, 4, 6,
-                          float(np.float32(rcut)), table)
     rows = np.concatenate([np.arange(i0, i0 + ni) for i0, ni, _, _ in items])
-    has = rt[3][rows] > 0
-    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH)):
-        ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, v)
+    fam = pgh.PGH_FAMILY_TABLE_BATCH
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        rt = oracle.lut_items(items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, 4, 6,
+                              float(np.float32(rcut)), oracle_table(pgh, fam, v, table, 4, 6))
+        has = rt[3][rows] > 0
         a = np.stack(to_host(*plan.table(*di, *dj)))
         e1 = norm_vec_err(a[:, rows][:, has], np.stack(rt[:3])[:, rows][:, has], rt[3][rows][has])
         assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (v, rms(e1), e1.max())
@@ -289,7 +291,8 @@ def test_plan_autotuner_table_family(pgh, ctx):
     assert pgh.pgh_get_variant(ctx.h, pgh.PGH_FAMILY_TABLE_BATCH) == v
     a = np.stack(to_host(*plan.table(*di, *dj)))
     rt = oracle.lut_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, 4, 6,
-                          float(np.float32(rcut)), table)
+                          float(np.float32(rcut)),
+                          oracle_table(pgh, pgh.PGH_FAMILY_TABLE_BATCH, v, table, 4, 6))
     has = rt[3] > 0
     e = norm_vec_err(a[:, has], np.stack(rt[:3])[:, has], rt[3][has])
     assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
@@ -459,11 +462,13 @@ def test_random_item_sets(pgh, ctx, seed):
     assert np.all(got[:, covered & (ref[3] == 0)] == 0)  # empty lists give zeros
     rcut = 0.2
     table = ctx.build_table(4, 6, rcut, eps=rcut / 15)
-    rt = oracle.lut_items(items, xi, yi, zi, xj, yj, zj, mj, 4, 6, float(np.float32(rcut)), table)
-    has = covered & (rt[3] > 0)
     # every tile shape of the batched table kernel
-    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH)):
-        ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, v)
+    fam = pgh.PGH_FAMILY_TABLE_BATCH
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        rt = oracle.lut_items(items, xi, yi, zi, xj, yj, zj, mj, 4, 6, float(np.float32(rcut)),
+                              oracle_table(pgh, fam, v, table, 4, 6))
+        has = covered & (rt[3] > 0)
         out_t = [torch.full((ni_total,), 777.0, device="cuda") for _ in range(3)]
         plan.table(*di, *dj, out=out_t)
         a = np.stack(to_host(*out_t))

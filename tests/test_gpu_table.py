@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import synth
-from _helpers import norm_vec_err, rms, to_dev, to_host
+from _helpers import norm_vec_err, oracle_table, rms, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -45,16 +45,18 @@ def _table_case(pgh, ctx, n, box, E, F, eps, rcut, seed, variants=None):
     dj = to_dev(x, y, z, m)
     ctx.set_j(*dj)
     items = np.array([[0, n, 0, n]], np.int32)
-    rt = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, float(np.float32(rcut)), table)
-    # the oracle through its own table (built by its own builder): the same
-    # gate without the library's host table builder in the chain
-    ro = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, float(np.float32(rcut)), ref_tab)
-    rx = oracle.central_items(items, x, y, z, x, y, z, m, oracle.SHAPE_S2PP, eps,
-                              float(np.float32(rcut)))
-    vs = variants if variants is not None else range(
-        pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_ALLPAIRS))
+    rc = float(np.float32(rcut))
+    fam = pgh.PGH_FAMILY_TABLE_ALLPAIRS
+    rx = oracle.central_items(items, x, y, z, x, y, z, m, oracle.SHAPE_S2PP, eps, rc)
+    vs = variants if variants is not None else range(pgh.pgh_variant_count(fam))
     for v in vs:
-        ctx.set_variant(pgh.PGH_FAMILY_TABLE_ALLPAIRS, v)
+        ctx.set_variant(fam, v)
+        rt = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rc,
+                              oracle_table(pgh, fam, v, table, E, F))
+        # the oracle through its own table (built by its own builder): the
+        # same gate without the library's host table builder in the chain
+        ro = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rc,
+                              oracle_table(pgh, fam, v, ref_tab, E, F))
         a = np.stack(to_host(*ctx.table_force(dj[0], dj[1], dj[2])))
         has = rt[3] > 0
         e1 = norm_vec_err(a[:, has], np.stack(rt[:3])[:, has], rt[3][has])
@@ -252,11 +254,13 @@ def test_potential_table_allpairs(pgh, ctx):
     ctx.set_j(*d)
     items = np.array([[0, n, 0, n]], np.int32)
     rc = float(np.float32(rcut))
-    ra = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rc, ft)
-    rp, sp = oracle.lut_pot_items(items, x, y, z, x, y, z, m, E, F, rc, pt)
     fam = pgh.PGH_FAMILY_TABLE_ALLPAIRS
     for v in range(pgh.pgh_variant_count(fam)):
         ctx.set_variant(fam, v)
+        ra = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rc,
+                              oracle_table(pgh, fam, v, ft, E, F))
+        rp, sp = oracle.lut_pot_items(items, x, y, z, x, y, z, m, E, F, rc,
+                                      oracle_table(pgh, fam, v, pt, E, F))
         ax, ay, az, phi = ctx.table_force(d[0], d[1], d[2], with_phi=True)
         a = np.stack(to_host(ax, ay, az))
         has = ra[3] > 0
@@ -282,10 +286,13 @@ def test_potential_table_cell_lists(pgh, ctx):
     dj = to_dev(s.xj, s.yj, s.zj, s.mj)
     plan = ctx.plan(s.items, n, s.xj.size)
     rc = float(np.float32(rcut))
-    ra = oracle.lut_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, E, F, rc, ft)
-    rp, sp = oracle.lut_pot_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, E, F, rc, pt)
-    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH)):
-        ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, v)
+    fam = pgh.PGH_FAMILY_TABLE_BATCH
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        ra = oracle.lut_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, E, F, rc,
+                              oracle_table(pgh, fam, v, ft, E, F))
+        rp, sp = oracle.lut_pot_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, E, F,
+                                      rc, oracle_table(pgh, fam, v, pt, E, F))
         out = plan.table(*di, *dj, with_phi=True)
         a = np.stack(to_host(*out[:3]))
         has = ra[3] > 0
@@ -329,11 +336,14 @@ def test_largest_tables_with_potential(pgh, ctx, E, F):
     ctx.set_j(*d)
     rc = float(np.float32(rcut))
     items = np.array([[0, n // 2, 0, n], [n // 2, n // 2, n // 4, n // 2]], np.int32)
-    ra = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rc, ft)
-    rp, sp = oracle.lut_pot_items(items, x, y, z, x, y, z, m, E, F, rc, pt)
     plan = ctx.plan(items, n, n)
-    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_BATCH)):
-        ctx.set_variant(pgh.PGH_FAMILY_TABLE_BATCH, v)
+    fam = pgh.PGH_FAMILY_TABLE_BATCH
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        ra = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rc,
+                              oracle_table(pgh, fam, v, ft, E, F))
+        rp, sp = oracle.lut_pot_items(items, x, y, z, x, y, z, m, E, F, rc,
+                                      oracle_table(pgh, fam, v, pt, E, F))
         out = plan.table(*d[:3], *d, with_phi=True)
         a = np.stack(to_host(*out[:3]))
         has = ra[3] > 0
@@ -342,10 +352,13 @@ def test_largest_tables_with_potential(pgh, ctx, E, F):
         ep = np.abs(to_host(out[3])[0] - rp)[sp > 0] / sp[sp > 0]
         assert rms(ep) <= 1e-5 and ep.max() <= 1e-3, (v, rms(ep), ep.max())
     whole = np.array([[0, n, 0, n]], np.int32)
-    ra = oracle.lut_items(whole, x, y, z, x, y, z, m, E, F, rc, ft)
-    rp, sp = oracle.lut_pot_items(whole, x, y, z, x, y, z, m, E, F, rc, pt)
-    for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_TABLE_ALLPAIRS)):
-        ctx.set_variant(pgh.PGH_FAMILY_TABLE_ALLPAIRS, v)
+    fam = pgh.PGH_FAMILY_TABLE_ALLPAIRS
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        ra = oracle.lut_items(whole, x, y, z, x, y, z, m, E, F, rc,
+                              oracle_table(pgh, fam, v, ft, E, F))
+        rp, sp = oracle.lut_pot_items(whole, x, y, z, x, y, z, m, E, F, rc,
+                                      oracle_table(pgh, fam, v, pt, E, F))
         ax, ay, az, phi = ctx.table_force(d[0], d[1], d[2], with_phi=True)
         a = np.stack(to_host(ax, ay, az))
         has = ra[3] > 0

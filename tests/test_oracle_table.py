@@ -249,3 +249,41 @@ def test_potential_table_nodes_continuity_and_accuracy(E, F):
     far, _ = oracle.lut_pot_items(np.array([[0, 1, 0, 1]], np.int32), [0.0], [0.0], [0.0],
                                   [1.5 * rcut], [0.0], [0.0], [2.0], E, F, rcut, t)
     assert far[0] == 0.0
+
+
+def test_ht_form_is_one_rounding_of_the_paper_form():
+    """The (H, G1) form of the table (the "htab" kernel variants): g =
+    H_k + G1_k s with H_k = G0_k - G1_k s_k rounded once to FP32.  For the
+    S2 table (E = 4, F = 6): every H_k is an FP32 number, it equals the
+    rounding computed independently in extended precision, it lies within
+    half an ulp of the exact G0_k - G1_k s_k, the last node stays zero, and
+    the form still meets the accuracy measure of Sec. 4.2 (1e-3 of the
+    softened force, over 4096 log-uniform pairs)."""
+    from fractions import Fraction
+    E, F, eps, rcut = 4, 6, 3.125e-3, 4.6875e-2
+    K = 1 << (E + F)
+    t = oracle.table_build(E, F, rcut, oracle.SHAPE_S2PP, eps)
+    h = oracle.table_ht(t, E, F)
+    g0, g1 = t[0::2], t[1::2]
+    sk = [oracle.node_s(E, F, k) for k in range(K)]
+    for k in range(K):
+        H = Fraction(float(h[2 * k])) - Fraction(float(g1[k])) * Fraction(sk[k])
+        assert float(H) == float(np.float32(float(H))) and Fraction(float(H)) == H, k
+        exact = Fraction(float(g0[k])) - Fraction(float(g1[k])) * Fraction(sk[k])
+        half_ulp = Fraction(abs(float(np.spacing(np.float32(float(H)))))) / 2
+        assert abs(H - exact) <= half_ulp, k
+        ld = np.float32(np.longdouble(g0[k]) - np.longdouble(g1[k]) * np.longdouble(sk[k]))
+        assert ld == np.float32(float(H)), k
+        assert h[2 * k + 1] == g1[k]
+    assert h[-2] == 0.0 and h[-1] == 0.0
+    dx, dy, dz, r = synth.log_uniform_pairs(4096, 2012, 5e-3 * rcut, rcut)
+    n = r.size
+    items = np.array([[k, 1, 0, 1] for k in range(n)], np.int32)
+    o = np.zeros(1)
+    a = oracle.lut_items(items, dx, dy, dz, o, o, o, np.ones(1), E, F, rcut, h)
+    rr = np.sqrt(dx.astype(np.float64) ** 2 + dy.astype(np.float64) ** 2
+                 + dz.astype(np.float64) ** 2)
+    pp = np.sqrt(a[0] ** 2 + a[1] ** 2 + a[2] ** 2)
+    total = pp + np.array([oracle.s2_R(v, rcut) for v in rr])
+    exact = np.array([oracle.s2_R(v, eps) for v in rr])
+    assert np.max(np.abs(total - exact) / exact) < 1e-3
