@@ -34,43 +34,57 @@ NEWTON_FLOPS = 38  # per interaction, the paper's count (Sec. 5.1)
 TABLE_FLOPS = 20  # per interaction, this project's count of the FP32 ops of the table loop
 
 
-# HBM traffic of the headline kernel, from two rocprofv3 --pmc runs of
-# `bench.py --no-extras --no-cpu --copy-calibration 256` (FETCH_SIZE, then
-# WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads for a
-# 256 MiB device-to-device copy (FETCH_SIZE 131093 KiB -> x2.0, WRITE_SIZE
-# 262144 KiB -> x1.0).  Valid only for the variant and kernel sources the
-# counters were taken on; otherwise the bench reports traffic as null.
-MEASURED_TRAFFIC = {
-    "variant": "ki=1 jt=256 u=8", "rsqrt_refine": 0,
-    "sources_sha256": "45767ac6423b39e480e1c3d03f700d07d892f8f3123becd602779e5c99a40e2b",
-    "fetch_kib": 22725.8, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
-    # SQ_INSTS_VALU_FLOPS_FP32 x 64 / interactions of the same kernel (FMA = 2, rsq = 1)
-    "valu_flops_per_interaction": 21.0,
+# Counters of the headline kernel per variant, from rocprofv3 --pmc runs of
+# `bench.py --no-extras --no-cpu --variant NAME --copy-calibration 256`:
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch of k_newton_allpairs), each
+# scaled by what the counter reads for a 256 MiB device-to-device copy, and
+# SQ_INSTS_VALU_FLOPS_FP32 (x 64 per dispatch / interactions).  Valid only for
+# the kernel sources they were taken on (their SHA-256); otherwise the bench
+# reports them as null.
+MEASURED = {
+    "sources_sha256": "45ead3d32277a92de1d5434b010497a01c2ec978f5d399ea590d5c9a28da81b3",
+    # the 256 MiB copy: FETCH_SIZE 131094 KiB (x2.0), WRITE_SIZE 262144 KiB (x1.0)
+    "fetch_factor": 2.0, "write_factor": 1.0,
+    "by_variant": {
+        # j split in 8 shares: 32 MiB of partial sums written, read back by k_combine_split
+        "ki=4 jt=256 u=2": {"fetch_kib": 17951.5, "write_kib": 32768,
+                            "valu_flops_per_interaction": 21.0},
+        # j split in 2 shares
+        "ki=1 jt=256 u=8": {"fetch_kib": 17943.0, "write_kib": 8192,
+                            "valu_flops_per_interaction": 21.0},
+    },
 }
-KERNEL_SOURCES = ("paper_1203_4037_amd/csrc/newton.hip", "paper_1203_4037_amd/csrc/pairs.h")
+KERNEL_SOURCES = ("paper_1203_4037_amd/csrc/newton.hip", "paper_1203_4037_amd/csrc/newton_pair.h",
+                  "paper_1203_4037_amd/csrc/pgh_internal.h")
 
 
-def counters_valid(variant_name, refine):
-    """Whether the recorded counters were taken on this variant, rsqrt mode
-    and kernel sources."""
+def sources_sha256():
     import hashlib
     h = hashlib.sha256()
     root = os.path.dirname(os.path.abspath(__file__))
     for f in KERNEL_SOURCES:
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
-    t = MEASURED_TRAFFIC
-    return (variant_name == t["variant"] and refine == t["rsqrt_refine"]
-            and h.hexdigest() == t["sources_sha256"])
+    return h.hexdigest()
+
+
+def counters_for(variant_name, refine):
+    """The recorded counters of this variant (no rsqrt refinement), or None
+    when they were taken on other kernel sources or not at all."""
+    t = MEASURED
+    c = t["by_variant"].get(variant_name)
+    if c is None or refine != 0 or t["sources_sha256"] != sources_sha256():
+        return None
+    return c
 
 
 def measured_traffic(variant_name, refine):
-    """HBM bytes per launch of the headline kernel, or None when the counters
-    were taken on another variant, rsqrt mode or kernel sources."""
-    if not counters_valid(variant_name, refine):
+    """HBM bytes per dispatch of the headline kernel, or None."""
+    c = counters_for(variant_name, refine)
+    if c is None:
         return None
-    t = MEASURED_TRAFFIC
-    return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0
+    t = MEASURED
+    return (c["fetch_kib"] * t["fetch_factor"] + c["write_kib"] * t["write_factor"]) * 1024.0
 
 
 def parse():
@@ -83,6 +97,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the built-in default variant instead of the autotuned one")
+    ap.add_argument("--variant", default=None, metavar="NAME",
+                    help="time this all-pairs Newton variant instead of the autotuned one "
+                         "(for profiling one variant)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target wall time of the CPU baseline sample")
     ap.add_argument("--replays", type=int, default=0,
@@ -272,7 +289,14 @@ def newton_allpairs(torch, pgh, synth, args):
     ctx.set_eps_to_all(0.01)
     pgh.pgh_set_stream(ctx.h, torch.cuda.current_stream().cuda_stream)
     tuned = None
-    if not args.no_tune:
+    if args.variant:
+        fam = pgh.PGH_FAMILY_NEWTON_ALLPAIRS
+        names = [pgh.pgh_variant_name(fam, v) for v in range(pgh.pgh_variant_count(fam))]
+        if args.variant not in names:
+            print(f"unknown variant {args.variant!r}; one of {names}", file=sys.stderr)
+            sys.exit(2)
+        ctx.set_variant(fam, names.index(args.variant))
+    elif not args.no_tune:
         # the library's autotuner picks the tile shape on this very workload
         ctx.set_j(*dev)
         tuned = ctx.autotune(pgh.PGH_FAMILY_NEWTON_ALLPAIRS, dev[0], dev[1], dev[2], reps=2)
@@ -793,8 +817,8 @@ def main():
     inter = float(n) * n
     value = inter / r["sec"]
     achieved = NEWTON_FLOPS * inter / (r["kern_ms"] / 1e3) / 1e12
-    hw_flops = (MEASURED_TRAFFIC["valu_flops_per_interaction"]
-                if counters_valid(r["variant_name"], r["refine"]) else None)
+    cnt = counters_for(r["variant_name"], r["refine"])
+    hw_flops = cnt["valu_flops_per_interaction"] if cnt else None
     hw_tflops = hw_flops * inter / (r["kern_ms"] / 1e3) / 1e12 if hw_flops else None
     line = {
         "metric": "interactions/sec on 1 MI355X (Newton, LUT) + % FP32 VALU peak; batched vs all-pairs; fwd+bwd/fwd",
@@ -817,7 +841,10 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic(r["variant_name"], r["refine"]),
                      "traffic_unit": "bytes/launch",
-                     "kernel": "k_newton_allpairs", "kernel_ms": r["kern_ms"],
+                     "kernel": "k_newton_allpairs",
+                     # HIP events around pgh_calc_newton on its stream: the kernel and,
+                     # when the j-range is split, k_combine_split (a few microseconds)
+                     "kernel_ms": r["kern_ms"],
                      "kernel_ms_median": r["kern_ms_median"], "kernel_ms_min": r["kern_ms_min"],
                      "flops_per_interaction": NEWTON_FLOPS,
                      # the FP32 flops the VALU counters count for this kernel (FMA = 2;

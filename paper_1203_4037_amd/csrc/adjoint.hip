@@ -30,7 +30,7 @@
 // atomic), and dL/dm_j is each lane's own sum.
 #include <algorithm>
 
-#include "pairs.h"
+#include "table_pairs.h"
 #include "pgh_internal.h"
 
 namespace pgh {

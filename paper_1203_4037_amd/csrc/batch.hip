@@ -32,7 +32,7 @@
 #include <utility>
 
 #include "batch_queue.h"
-#include "pairs.h"
+#include "newton_pair.h"
 
 namespace pgh {
 namespace {

@@ -29,7 +29,7 @@
 #include <utility>
 
 #include "batch_queue.h"
-#include "pairs.h"
+#include "table_pairs.h"
 
 namespace pgh {
 namespace {

@@ -19,7 +19,7 @@
 // last one, where G0 = G1 = 0, so they add exactly zero.
 #include <algorithm>
 
-#include "pairs.h"
+#include "table_pairs.h"
 #include "pgh_internal.h"
 
 namespace pgh {

@@ -31,7 +31,7 @@
 // JT + nj/JT rather than nj.
 #include <algorithm>
 
-#include "pairs.h"
+#include "newton_pair.h"
 #include "pgh_internal.h"
 
 namespace pgh {
