@@ -517,16 +517,20 @@ def batched_newton(torch, pgh, synth):
     for v in range(pgh.pgh_variant_count(fam)):
         ctx.set_variant(fam, v)
         per[pgh.pgh_variant_name(fam, v)] = graph_ms(torch, lambda: plan.newton(*di, *dj, out=out), 10)
-    tuned = plan.autotune(fam, *di, *dj, reps=3)
-    ms = graph_ms(torch, lambda: plan.newton(*di, *dj, out=out), 10)
     inter = float(plan.interactions)
+    plan.free()
+    # the library's tuner: plans cut for 0.5, 1 and 2 times the resident
+    # waves, every variant timed on each
+    plan, tuned, scale = ctx.plan_tuned(s.items, s.xi.size, s.xj.size, fam, *di, *dj, reps=3)
+    ms = graph_ms(torch, lambda: plan.newton(*di, *dj, out=out), 10)
     plan.free()
     ctx.close()
     rate = inter / (ms / 1e3)
     return {"workload": "newton_batched_tree_style_16384_lists_N4194304", "interactions": inter,
             "ms_per_launch": ms, "interactions_per_s": rate,
             "frac_of_peak_38flop": NEWTON_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12),
-            "autotuned_variant": pgh.pgh_variant_name(fam, tuned), "ms_per_variant": per}
+            "autotuned_variant": pgh.pgh_variant_name(fam, tuned),
+            "autotuned_plan_waves_scale": scale, "ms_per_variant": per}
 
 
 def useful_pairs(s, rcut):
@@ -549,9 +553,11 @@ def batched_table(torch, pgh, synth):
     periodic box, 64^3 cells, i-groups of 4^3 cells with their 6^3-cell halo
     (4096 lists; and 8^3-cell groups with a 10^3-cell halo, 512 lists),
     S2 PP shape rcut = 3/256, eps = 1/1280, E = 4, F = 6 (and F = 5).  Every
-    tile shape of the batched kernel is timed, the autotuner's choice is
-    reported with its per-call time from a graph of ten calls and per replay
-    of a one-call graph; also the rate of useful pairs (closer than rcut)."""
+    tile shape of the batched kernel is timed on the default plan; the
+    library's tuner (Context.plan_tuned: plan wave target x tile shape)
+    chooses, and its choice is reported with its per-call time from a graph
+    of ten calls and per replay of a one-call graph; also the rate of useful
+    pairs (closer than rcut)."""
     n = 262144
     rcut = 3.0 / 256
     x, y, z = synth.uniform_box(n, 103)
@@ -571,9 +577,12 @@ def batched_table(torch, pgh, synth):
             ctx.set_variant(fam, v)
             per[pgh.pgh_variant_name(fam, v)] = graph_ms(
                 torch, lambda: plan.table(*di, *dj, out=out), 20, CALLS_PER_GRAPH)
-        tuned = plan.autotune(fam, *di, *dj, reps=20)
-        t = call_times(torch, lambda: plan.table(*di, *dj, out=out), 200)
         inter = float(plan.interactions)
+        plan.free()
+        # the library's tuner: plans cut for 0.5, 1 and 2 times the resident
+        # waves, every variant timed on each
+        plan, tuned, scale = ctx.plan_tuned(s.items, n, s.xj.size, fam, *di, *dj, reps=20)
+        t = call_times(torch, lambda: plan.table(*di, *dj, out=out), 200)
         plan.free()
         ctx.close()
         ms = t["ms_per_call"]
@@ -586,7 +595,8 @@ def batched_table(torch, pgh, synth):
             "frac_of_peak_20flop": TABLE_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12),
             "frac_of_peak_20flop_1call_replay":
                 TABLE_FLOPS * inter / (t["ms_per_replay_1call"] / 1e3) / (PEAK_FP32_TFLOPS * 1e12),
-            "autotuned_variant": pgh.pgh_variant_name(fam, tuned), "ms_per_call_per_variant": per}
+            "autotuned_variant": pgh.pgh_variant_name(fam, tuned),
+            "autotuned_plan_waves_scale": scale, "ms_per_call_per_variant": per}
     return res
 
 

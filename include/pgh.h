@@ -241,6 +241,20 @@ PGH_API int pgh_plan_free(pgh_ctx *c, pgh_plan *p);
  * are always made on the host. */
 PGH_API int pgh_set_plan_expansion(pgh_ctx *c, int on_device);
 
+/* The number of waves the planner cuts the work of later plans (and tree
+ * walks) for: groups are cut into chunks of 64, or of 32 or 16 i-particles
+ * while fewer tasks than this would result, and long j-lists into parts of
+ * an eighth of this count's average share of the work (the schedule of
+ * Sec. 5.1's lists; it changes no result beyond FP32 summation order).  0
+ * (default) = the resident waves of the batched kernels on the context's
+ * device; PGH_EINVAL if negative.  A tuning dimension for callers that
+ * time plans (the binding's Context.plan_tuned). */
+PGH_API int pgh_set_plan_waves(pgh_ctx *c, int waves);
+
+/* The wave target later plans will be cut for (the setting, or the device's
+ * resident waves when it is 0); a negative status on error. */
+PGH_API int pgh_get_plan_waves(pgh_ctx *c);
+
 /* Number of interactions sum n_i n_j of a plan (host value, no sync). */
 PGH_API long long pgh_plan_interactions(const pgh_plan *p);
 

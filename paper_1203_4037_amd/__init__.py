@@ -85,6 +85,8 @@ SIGNATURES = {
     "pgh_set_xmj": (_I, [_P, _I, _I, _P, _P, _P, _P]),
     "pgh_set_rsqrt_refine": (_I, [_P, _I]),
     "pgh_set_plan_expansion": (_I, [_P, _I]),
+    "pgh_set_plan_waves": (_I, [_P, _I]),
+    "pgh_get_plan_waves": (_I, [_P]),
     "pgh_calc_newton": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pgh_calc_newton_noalloc": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pgh_build_table": (_I, [_P, _I, _I, _F, _P, _P, _P]),
@@ -217,6 +219,17 @@ def pgh_set_rsqrt_refine(ctx, on):
 
 def pgh_set_plan_expansion(ctx, on_device):
     _check(ctx, lib.pgh_set_plan_expansion(ctx, int(bool(on_device))))
+
+
+def pgh_set_plan_waves(ctx, waves):
+    _check(ctx, lib.pgh_set_plan_waves(ctx, int(waves)))
+
+
+def pgh_get_plan_waves(ctx):
+    v = lib.pgh_get_plan_waves(ctx)
+    if v < 0:
+        _check(ctx, v)
+    return v
 
 
 def pgh_set_xmj(ctx, adr, nj, x, y, z, m):
@@ -603,6 +616,7 @@ class Context:
         self.nj = 0
         self.table = None
         self.refine = 0
+        self.plan_waves = 0
 
     def close(self):
         if self.h:
@@ -698,9 +712,90 @@ class Context:
 
     # interaction lists ------------------------------------------------------
 
+    def set_plan_waves(self, waves):
+        """The wave count later plans are cut for (0: the device's)."""
+        pgh_set_plan_waves(self.h, waves)
+        self.plan_waves = int(waves)
+
     def plan(self, items, ni_total, nj_total):
         """A Plan for host items [n, 4] = (i_off, n_i, j_off, n_j)."""
         return Plan(self, items, ni_total, nj_total)
+
+    def plan_tuned(self, items, ni_total, nj_total, family, xi, yi, zi, xj, yj, zj, mj,
+                   scales=(0.5, 1.0, 2.0), reps=3, cache=None):
+        """A Plan whose schedule and kernel variant are chosen by timing: for
+        each wave target (the device's resident waves times each scale) a
+        plan is made and every variant of the batched family is timed on it
+        (pgh_autotune_plan); the fastest pair is kept and its variant
+        selected.  With a cache path (JSON) a previous choice for lists of
+        the same shape class on the same device is made without timing.
+        Returns (plan, variant index, scale)."""
+        import json
+        a = _items_array(items)
+        for t in (xi, yi, zi):
+            if t.numel() < ni_total:
+                raise ValueError("an i-array is shorter than ni_total")
+        for t in (xj, yj, zj, mj):
+            if t.numel() < nj_total:
+                raise ValueError("a j-array is shorter than nj_total")
+        self._sync_stream()
+        user_waves = self.plan_waves
+        pgh_set_plan_waves(self.h, 0)
+        base = pgh_get_plan_waves(self.h)
+        names = [pgh_variant_name(family, v) for v in range(pgh_variant_count(family))]
+        key = None
+        if cache:
+            props = torch.cuda.get_device_properties(self.device)
+            key = "|".join(str(x) for x in (props.name, "plan_tuned", family) + _shape_class(a)
+                           + (self.table if family == PGH_FAMILY_TABLE_BATCH else "",
+                              self.refine, tuple(scales)))
+            try:
+                with open(cache) as f:
+                    stored = json.load(f)
+            except (OSError, ValueError):
+                stored = {}
+            hit = stored.get(key)
+            if hit and hit.get("variant") in names and hit.get("scale") in scales:
+                pgh_set_plan_waves(self.h, max(1, int(round(base * hit["scale"]))))
+                try:
+                    p = Plan(self, a, ni_total, nj_total)
+                finally:
+                    pgh_set_plan_waves(self.h, user_waves)
+                v = names.index(hit["variant"])
+                pgh_set_variant(self.h, family, v)
+                return p, v, hit["scale"]
+        best = None
+        try:
+            for sc in scales:
+                pgh_set_plan_waves(self.h, max(1, int(round(base * sc))))
+                p = Plan(self, a, ni_total, nj_total)
+                try:
+                    v, ms = pgh_autotune_plan(self.h, family, p.h, xi, yi, zi, xj, yj, zj, mj,
+                                              reps)
+                except Exception:
+                    p.free()
+                    raise
+                if best is None or ms < best[2]:
+                    if best is not None:
+                        best[0].free()
+                    best = (p, v, ms, sc)
+                else:
+                    p.free()
+        except Exception:
+            if best is not None:
+                best[0].free()
+            raise
+        finally:
+            pgh_set_plan_waves(self.h, user_waves)
+        p, v, _, sc = best
+        pgh_set_variant(self.h, family, v)
+        if cache:
+            stored[key] = {"scale": sc, "variant": names[v]}
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(stored, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return p, v, sc
 
     def tree(self):
         """An empty device Barnes-Hut tree of this context."""
@@ -736,6 +831,17 @@ def _cached_tune(ctx, family, key, cache, tune):
     return v
 
 
+def _shape_class(a):
+    """A plan's shape class: its number of lists and its median group size
+    and list length, each rounded to a power of two."""
+    def pow2(v):
+        return 1 << max(0, int(round(np.log2(max(1.0, float(v))))))
+    live = a[a[:, 1] > 0] if a.shape[0] else a
+    return (pow2(live.shape[0]),
+            pow2(np.median(live[:, 1])) if live.shape[0] else 0,
+            pow2(np.median(live[:, 3])) if live.shape[0] else 0)
+
+
 class Plan:
     """Execution plan of a set of interaction lists (pgh_plan_create)."""
 
@@ -746,12 +852,8 @@ class Plan:
         self.h = pgh_plan_create(ctx.h, a.shape[0], a, ni_total, nj_total)
         self.interactions = pgh_plan_interactions(self.h)
 
-        def pow2(v):
-            return 1 << max(0, int(round(np.log2(max(1.0, float(v))))))
-        live = a[a[:, 1] > 0] if a.shape[0] else a
-        self.shape_class = (pow2(live.shape[0]),
-                            pow2(np.median(live[:, 1])) if live.shape[0] else 0,
-                            pow2(np.median(live[:, 3])) if live.shape[0] else 0)
+        self.shape_class = _shape_class(a)
+        self.waves = pgh_get_plan_waves(ctx.h)
 
     def free(self):
         if self.h and self.ctx.h:

@@ -22,6 +22,7 @@ struct pgh_plan {
     bool tree_owned;
     int n_items, n_tasks;
     int ni_total, nj_total;
+    int waves;              // the planner's wave target when the plan was made
     long long interactions;
     int n_chunks, n_slots;  // chunks whose j-list is split, and their parts
     Task *tasks;            // device, sublist-major, each sublist longest first
@@ -62,6 +63,7 @@ struct pgh_ctx {
     float4 *jmem = nullptr;
     int refine = 0;  // Newton-Raphson step after v_rsq_f32 (pgh_set_rsqrt_refine)
     int plan_device = 1;  // plans expanded on the device (pgh_set_plan_expansion)
+    int plan_waves = 0;   // the planner's wave target (pgh_set_plan_waves; 0: the device's)
     // look-up table
     int tab_set = 0;
     int tab_E = 0, tab_F = 0;
@@ -329,6 +331,13 @@ void set_plan_counts(pgh_plan *p, int n_items, int ni_total, int nj_total, int n
     p->ordered = ordered;
 }
 
+// The wave count the planner cuts work for: the context's setting, else the
+// resident waves of the batched kernels on this device.
+int planner_waves(const pgh_ctx *c)
+{
+    return c->plan_waves > 0 ? c->plan_waves : batch_resident_waves(c->num_cu);
+}
+
 // Plans the items into p on the host, reusing its device arrays when they
 // are large enough.  The tasks are written straight into the context's
 // pinned buffer and copied from there; waits for the stream.  On failure p
@@ -337,10 +346,10 @@ int plan_fill(pgh_ctx *c, pgh_plan *p, int n_items, const pgh_item *items, int n
               int nj_total)
 {
     HostPlan &hp = c->hp;
+    p->waves = planner_waves(c);
     {
         std::string err;
-        const int st = plan_tasks(items, n_items, ni_total, nj_total,
-                                  batch_resident_waves(c->num_cu), hp, err);
+        const int st = plan_tasks(items, n_items, ni_total, nj_total, p->waves, hp, err);
         if (st) return fail(c, st, err);
     }
     DeviceGuard g(c->device);
@@ -376,10 +385,10 @@ int plan_fill_device(pgh_ctx *c, pgh_plan *p, int n_items, const pgh_item *items
                      int nj_total)
 {
     DescPlan &dp = c->dp;
+    p->waves = planner_waves(c);
     {
         std::string err;
-        const int st = plan_descs(items, n_items, ni_total, nj_total,
-                                  batch_resident_waves(c->num_cu), dp, err);
+        const int st = plan_descs(items, n_items, ni_total, nj_total, p->waves, dp, err);
         if (st == kPlanOnHost) return plan_fill(c, p, n_items, items, ni_total, nj_total);
         if (st) return fail(c, st, err);
     }
@@ -550,6 +559,20 @@ int pgh_set_plan_expansion(pgh_ctx *c, int on_device)
     if (!c) return PGH_EINVAL;
     c->plan_device = on_device ? 1 : 0;
     return PGH_OK;
+}
+
+int pgh_set_plan_waves(pgh_ctx *c, int waves)
+{
+    if (!c) return PGH_EINVAL;
+    if (waves < 0) return fail(c, PGH_EINVAL, "the wave target must be >= 0");
+    c->plan_waves = waves;
+    return PGH_OK;
+}
+
+int pgh_get_plan_waves(pgh_ctx *c)
+{
+    if (!c) return PGH_EINVAL;
+    return planner_waves(c);
 }
 
 int pgh_set_xmj(pgh_ctx *c, int adr, int nj, const float *x, const float *y, const float *z,
@@ -890,7 +913,7 @@ int build_adjoint_tasks(pgh_ctx *c, pgh_plan *p)
 {
     if (p->adj_built) return PGH_OK;
     std::vector<Task> jt, it_tasks;
-    plan_adjoint_tasks(p->ordered, batch_resident_waves(c->num_cu), jt, it_tasks);
+    plan_adjoint_tasks(p->ordered, p->waves > 0 ? p->waves : planner_waves(c), jt, it_tasks);
     if (hipMalloc((void **)&p->jqueue, 2 * sizeof(unsigned)) != hipSuccess ||
         (!jt.empty() && hipMalloc((void **)&p->jtasks, jt.size() * sizeof(Task)) != hipSuccess) ||
         (!it_tasks.empty() &&

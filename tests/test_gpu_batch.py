@@ -477,3 +477,76 @@ def test_random_item_sets(pgh, ctx, seed):
         assert np.all(a[:, ~covered] == 777.0)
         assert np.all(a[:, covered & (rt[3] == 0)] == 0)
     plan.free()
+
+
+def test_plan_wave_targets_and_tuned_plan(pgh, ctx, tmp_path):
+    """Plans cut for other wave counts (pgh_set_plan_waves: chunk sizes and
+    list parts follow the target) give the same forces up to FP32 summation
+    order (the oracle gate); Context.plan_tuned times plans of three wave
+    targets with every variant, returns the fastest pair, and takes it from
+    its JSON cache the second time.  Cell lists of 16384 particles (table
+    family) and tree-style lists (Newton family)."""
+    import json
+    n = 16384
+    x, y, z = synth.uniform_box(n, 92)
+    m = synth.equal_masses(n)
+    rcut = 1.0 / 32
+    s = synth.cell_grid_items(x, y, z, m, ncell=32, block=4)
+    table = ctx.build_table(4, 6, rcut, eps=rcut / 15)
+    di, dj = _dev_set(s)
+    fam = pgh.PGH_FAMILY_TABLE_BATCH
+    base = pgh.pgh_get_plan_waves(ctx.h)
+    assert base > 0
+    with pytest.raises(pgh.PGHError) as e:
+        pgh.pgh_set_plan_waves(ctx.h, -1)
+    assert e.value.code == pgh.PGH_EINVAL
+
+    def table_gate(a, v):
+        rt = oracle.lut_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, 4, 6,
+                              float(np.float32(rcut)), oracle_table(pgh, fam, v, table, 4, 6))
+        has = rt[3] > 0
+        e1 = norm_vec_err(a[:, has], np.stack(rt[:3])[:, has], rt[3][has])
+        assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (v, rms(e1), e1.max())
+        assert np.all(a[:, ~has] == 0.0)
+
+    ctx.set_variant(fam, 2)
+    tasks = []
+    for w in (max(1, base // 4), base, 4 * base):
+        ctx.set_plan_waves(w)
+        assert pgh.pgh_get_plan_waves(ctx.h) == w
+        plan = ctx.plan(s.items, n, s.xj.size)
+        assert plan.waves == w
+        table_gate(np.stack(to_host(*plan.table(*di, *dj))), 2)
+        tasks.append(plan)
+    for plan in tasks:
+        plan.free()
+    ctx.set_plan_waves(0)
+    assert pgh.pgh_get_plan_waves(ctx.h) == base
+
+    cache = str(tmp_path / "tuned.json")
+    p, v, sc = ctx.plan_tuned(s.items, n, s.xj.size, fam, *di, *dj, reps=1, cache=cache)
+    assert sc in (0.5, 1.0, 2.0) and pgh.pgh_get_variant(ctx.h, fam) == v
+    assert p.waves == max(1, int(round(base * sc)))
+    table_gate(np.stack(to_host(*p.table(*di, *dj))), v)
+    p.free()
+    with open(cache) as f:
+        stored = json.load(f)
+    assert list(stored.values()) == [{"scale": sc, "variant": pgh.pgh_variant_name(fam, v)}]
+    ctx.set_variant(fam, 0)
+    p2, v2, sc2 = ctx.plan_tuned(s.items, n, s.xj.size, fam, *di, *dj, reps=1, cache=cache)
+    assert (v2, sc2) == (v, sc) and pgh.pgh_get_variant(ctx.h, fam) == v
+    p2.free()
+
+    st = synth.tree_style_items(1 << 15, 150, 12, nj_median=400, nj_lo=50, nj_hi=3000)
+    ti, tj = _dev_set(st)
+    ctx.set_eps_to_all(1e-3)
+    p3, v3, _ = ctx.plan_tuned(st.items, st.xi.size, st.xj.size, pgh.PGH_FAMILY_NEWTON_BATCH,
+                               *ti, *tj, reps=1)
+    got = np.stack(to_host(*p3.newton(*ti, *tj)))
+    rows = np.concatenate([np.arange(i0, i0 + k) for i0, k, _, _ in st.items])
+    e2 = np.full(st.xi.size, np.float32(1e-3) ** 2, np.float32)
+    ref = np.stack(oracle.newton_items(st.items, st.xi, st.yi, st.zi, e2, st.xj, st.yj, st.zj,
+                                       st.mj))
+    ea = rel_vec_err(got[:3, rows], ref[:3, rows])
+    assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, (v3, rms(ea), ea.max())
+    p3.free()
