@@ -42,15 +42,20 @@ TABLE_FLOPS = 20  # per interaction, this project's count of the FP32 ops of the
 # the kernel sources they were taken on (their SHA-256); otherwise the bench
 # reports them as null.
 MEASURED = {
-    "sources_sha256": "45ead3d32277a92de1d5434b010497a01c2ec978f5d399ea590d5c9a28da81b3",
-    # the 256 MiB copy: FETCH_SIZE 131094 KiB (x2.0), WRITE_SIZE 262144 KiB (x1.0)
+    "sources_sha256": "1421fd40e596154d122a54b4609e28ca0aa0e28829e046d684a404382697fc12",
+    # the 256 MiB copy: FETCH_SIZE 131093 KiB (x2.0), WRITE_SIZE 262144 KiB (x1.0)
     "fetch_factor": 2.0, "write_factor": 1.0,
     "by_variant": {
         # j split in 8 shares: 32 MiB of partial sums written, read back by k_combine_split
-        "ki=4 jt=256 u=2": {"fetch_kib": 17951.5, "write_kib": 32768,
+        "ki=4 jt=256 u=2": {"fetch_kib": 17951.3, "write_kib": 32768,
                             "valu_flops_per_interaction": 21.0},
         # j split in 2 shares
-        "ki=1 jt=256 u=8": {"fetch_kib": 17943.0, "write_kib": 8192,
+        "ki=1 jt=256 u=8": {"fetch_kib": 17943.1, "write_kib": 8192,
+                            "valu_flops_per_interaction": 21.0},
+        "ki=1 jt=64 u=8": {"fetch_kib": 17941.5, "write_kib": 8192,
+                           "valu_flops_per_interaction": 21.1},
+        # j split in 4 shares
+        "ki=2 jt=256 u=4": {"fetch_kib": 17947.2, "write_kib": 16384,
                             "valu_flops_per_interaction": 21.0},
     },
 }

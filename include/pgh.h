@@ -131,8 +131,10 @@ PGH_API int pgh_calc_newton(pgh_ctx *c, int ni, const float *xi, const float *yi
 
 /* pgh_calc_newton for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops, harnesses that forbid
- * hipMalloc.  Same arguments, results and errors as pgh_calc_newton, and it
- * calls no hipMalloc, hipFree or allocating library routine.  Where
+ * hipMalloc.  Same arguments and errors as pgh_calc_newton, the same
+ * results up to FP32 summation order (its j-split, and with no variant
+ * selected its tile shape, can differ), and it calls no hipMalloc, hipFree
+ * or allocating library routine.  Where
  * pgh_calc_newton grows a context buffer for the partial sums of its
  * j-split, this entry point uses a fixed device array of 2^20 floats
  * (4 MiB) that the library holds on each GPU it runs on until the process

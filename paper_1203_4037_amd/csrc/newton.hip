@@ -288,12 +288,15 @@ const char *newton_allpairs_variant_name(int v)
 int newton_allpairs_default(int ni, int nj, int num_cu)
 {
     (void)nj;
-    // One i per lane, 256-record tiles, unrolled by 8: the fastest measured
-    // from a few thousand i-particles up.  An i-set of at most 16 waves per
+    // Measured with the j-split that holds 8 waves per SIMD: from 2^17
+    // i-particles up, four per lane (fewer j-tile reads per pair) are the
+    // fastest (N = 262144: 20.3 ms against 21.5 for one per lane); below, one
+    // per lane keeps the shares long enough; an i-set of at most 16 waves per
     // 256 CUs takes the 64-record tiles, so that the j-split (one tile per
     // share at least) gives it a wave per CU or more.  pgh_autotune confirms
     // or replaces the choice for a given workload.
-    return ni <= 4 * num_cu ? 1 : 0;
+    if (ni <= 4 * num_cu) return 1;
+    return ni >= (1 << 17) ? 3 : 0;
 }
 
 int newton_allpairs_split(int ni, int nj, int variant, size_t part_cap)

@@ -644,7 +644,12 @@ int pgh_calc_newton_noalloc(pgh_ctx *c, int ni, const float *xi, const float *yi
     NewtonArgs a{ni, xi, yi, zi, eps2_i, c->eps2_all, c->nj, c->jmem, ax, ay, az, phi, 0, nullptr};
     const bool guard = (eps2_i == nullptr) && !(c->eps2_all > 0.f);
     int v = c->variant[PGH_FAMILY_NEWTON_ALLPAIRS];
-    if (v < 0) v = newton_allpairs_default(ni, c->nj, c->num_cu);
+    if (v < 0) {
+        v = newton_allpairs_default(ni, c->nj, c->num_cu);
+        // four i-particles per lane take their waves from the j-split, which
+        // the array caps: the default here keeps one per lane
+        if (v == 3) v = 0;
+    }
     // the split is limited to the shares whose partial sums fit the array
     // (S * 4 * ni floats); a launch that cannot be split needs no scratch
     const int S = newton_allpairs_split(ni, c->nj, v, kNoAllocFloats);
