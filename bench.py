@@ -654,7 +654,8 @@ def adjoint_table(torch, pgh, synth):
     """Table-force forward and adjoint on cell lists: N = 65536 uniform in the
     unit periodic box, 64^3 cells, 8^3-cell groups, S2 PP shape (rcut = 3/256,
     eps = 1/1280, E = 4, F = 6); the adjoint with respect to the table entries
-    and masses, and also with the i- and j-position gradients; per call from
+    and masses, and also with the i- and j-position gradients (two passes over
+    the pairs, or one with the moments kept by the forward); per call from
     graphs of ten calls."""
     n = 65536
     x, y, z = synth.uniform_box(n, 105)
@@ -676,6 +677,13 @@ def adjoint_table(torch, pgh, synth):
     gj = [torch.empty(s.xj.size, device="cuda") for _ in range(3)]
     bx_ms = graph_ms(torch, lambda: pgh.pgh_batch_table_bwd(ctx.h, plan.h, *di, *dj, *w, gt, gm,
                                                             *gi, *gj), 10, CALLS_PER_GRAPH)
+    # the training path for position gradients: a forward that keeps the
+    # i-side moments, a backward that forms the i-side gradient from them
+    mom = torch.empty(7 * n, device="cuda")
+    fm_ms = graph_ms(torch, lambda: pgh.pgh_batch_table_moments(ctx.h, plan.h, *di, *dj, *out, mom),
+                     10, CALLS_PER_GRAPH)
+    bm_ms = graph_ms(torch, lambda: pgh.pgh_batch_table_bwd_moments(
+        ctx.h, plan.h, *di, *dj, *w, mom, gt, gm, *gi, *gj), 10, CALLS_PER_GRAPH)
     inter = float(plan.interactions)
     plan.free()
     ctx.close()
@@ -683,7 +691,10 @@ def adjoint_table(torch, pgh, synth):
             "interactions": inter, "fwd_ms": f_ms, "bwd_ms": b_ms,
             "fwd_plus_bwd_over_fwd": (f_ms + b_ms) / f_ms,
             "bwd_with_positions_ms": bx_ms,
-            "fwd_plus_bwd_with_positions_over_fwd": (f_ms + bx_ms) / f_ms}
+            "fwd_plus_bwd_with_positions_over_fwd": (f_ms + bx_ms) / f_ms,
+            "fwd_with_moments_ms": fm_ms, "bwd_with_positions_from_moments_ms": bm_ms,
+            # (forward keeping the moments + backward with every gradient) over the plain forward
+            "fwd_moments_plus_bwd_with_positions_over_fwd": (fm_ms + bm_ms) / f_ms}
 
 
 def table_allpairs(torch, pgh, synth):

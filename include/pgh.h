@@ -334,6 +334,38 @@ PGH_API int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, 
                                 float *gxi, float *gyi, float *gzi, float *gxj, float *gyj,
                                 float *gzj);
 
+/* pgh_batch_table (no potential) that also writes the i-side moments of the
+ * adjoint of L = sum_i w_i . a_i (derived from Sec. 3.4.2: inside a bin the
+ * interpolant is linear in s = c |d|^2 + 2, so the derivative of m_j g d
+ * with respect to r_i is -m_j (g I + 2c G1_k d d^T)).  For each i-row of an
+ * item, mom[k * ni_total + i] holds, for k = 0 .. 6, S_i = sum_j m_j g_ij
+ * and the symmetric M_i = sum_j m_j G1_k(ij) d d^T as Mxx, Mxy, Mxz, Myy,
+ * Myz, Mzz; rows in no item are left untouched.  mom: device float
+ * [7 * ni_total], caller-owned.  With them pgh_batch_table_bwd_moments forms
+ * dL/dr_i = -(S_i w_i + 2c M_i w_i) per row instead of evaluating every pair
+ * a second time.  One i-particle per lane and the paper's (G0, G1) form
+ * whatever the selected variant.  The first call on a plan with split lists
+ * allocates the plan's partial moments (and waits); later calls allocate
+ * nothing.  PGH_ESTATE without a force table. */
+PGH_API int pgh_batch_table_moments(pgh_ctx *c, pgh_plan *p, const float *xi, const float *yi,
+                                    const float *zi, const float *xj, const float *yj,
+                                    const float *zj, const float *mj, float *ax, float *ay,
+                                    float *az, float *mom);
+
+/* pgh_batch_table_bwd with the i-side position gradient formed from the
+ * moments that pgh_batch_table_moments wrote for the same plan, positions,
+ * masses and table (mom, device float[7 * ni_total]): each i-row of an item
+ * gets -(S_i w_i + 2c M_i w_i), rows in no item 0, and the pairs are
+ * evaluated once (the j-major pass) instead of twice.  The other gradients
+ * and every argument as in pgh_batch_table_bwd; PGH_EINVAL for a NULL mom. */
+PGH_API int pgh_batch_table_bwd_moments(pgh_ctx *c, const pgh_plan *p, const float *xi,
+                                        const float *yi, const float *zi, const float *xj,
+                                        const float *yj, const float *zj, const float *mj,
+                                        const float *wx, const float *wy, const float *wz,
+                                        const float *mom, float *gtable, float *gmj, float *gxi,
+                                        float *gyi, float *gzi, float *gxj, float *gyj,
+                                        float *gzj);
+
 /* Removes the self term from raw potentials (Sec. 4.1): phi[i] += m[i] /
  * eps_i for i in [0, n), with eps_i^2 from eps2_i (device, may be NULL: the
  * context's pgh_set_eps_to_all value).  For i-particles that are also

@@ -104,6 +104,8 @@ SIGNATURES = {
     "pgh_newton_allpairs_bwd": (_I, [_P, _I, _P, _P, _P, _P, _F, _P, _P, _P, _P, _P, _P, _P]),
     "pgh_newton_ij_bwd": (_I, [_P, _I, _P, _P, _P, _P, _I] + [_P] * 14),
     "pgh_batch_table_bwd": (_I, [_P, _P] + [_P] * 18),
+    "pgh_batch_table_moments": (_I, [_P, _P] + [_P] * 11),
+    "pgh_batch_table_bwd_moments": (_I, [_P, _P] + [_P] * 19),
     "pgh_variant_count": (_I, [_I]),
     "pgh_variant_name": (ctypes.c_char_p, [_I, _I]),
     "pgh_set_variant": (_I, [_P, _I, _I]),
@@ -365,6 +367,26 @@ def pgh_batch_table_bwd(ctx, plan, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, gtabl
         _ptr(xj, None, "xj"), _ptr(yj, None, "yj"), _ptr(zj, None, "zj"), _ptr(mj, None, "mj"),
         _ptr(wx, None, "wx"), _ptr(wy, None, "wy"), _ptr(wz, None, "wz"),
         _ptr(gtable, None, "gtable"), _ptr(gmj, None, "gmj"),
+        _ptr(gxi, None, "gxi"), _ptr(gyi, None, "gyi"), _ptr(gzi, None, "gzi"),
+        _ptr(gxj, None, "gxj"), _ptr(gyj, None, "gyj"), _ptr(gzj, None, "gzj")))
+
+
+def pgh_batch_table_moments(ctx, plan, xi, yi, zi, xj, yj, zj, mj, ax, ay, az, mom):
+    _check(ctx, lib.pgh_batch_table_moments(
+        ctx, plan, _ptr(xi, None, "xi"), _ptr(yi, None, "yi"), _ptr(zi, None, "zi"),
+        _ptr(xj, None, "xj"), _ptr(yj, None, "yj"), _ptr(zj, None, "zj"), _ptr(mj, None, "mj"),
+        _ptr(ax, None, "ax"), _ptr(ay, None, "ay"), _ptr(az, None, "az"),
+        _ptr(mom, None, "mom")))
+
+
+def pgh_batch_table_bwd_moments(ctx, plan, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, mom, gtable,
+                                gmj, gxi=None, gyi=None, gzi=None, gxj=None, gyj=None,
+                                gzj=None):
+    _check(ctx, lib.pgh_batch_table_bwd_moments(
+        ctx, plan, _ptr(xi, None, "xi"), _ptr(yi, None, "yi"), _ptr(zi, None, "zi"),
+        _ptr(xj, None, "xj"), _ptr(yj, None, "yj"), _ptr(zj, None, "zj"), _ptr(mj, None, "mj"),
+        _ptr(wx, None, "wx"), _ptr(wy, None, "wy"), _ptr(wz, None, "wz"),
+        _ptr(mom, None, "mom"), _ptr(gtable, None, "gtable"), _ptr(gmj, None, "gmj"),
         _ptr(gxi, None, "gxi"), _ptr(gyi, None, "gyi"), _ptr(gzi, None, "gzi"),
         _ptr(gxj, None, "gxj"), _ptr(gyj, None, "gyj"), _ptr(gzj, None, "gzj")))
 
@@ -893,6 +915,21 @@ class Plan:
         pgh_batch_table(c.h, self.h, xi, yi, zi, xj, yj, zj, mj, out[0], out[1], out[2], phi)
         return out
 
+    def table_moments(self, xi, yi, zi, xj, yj, zj, mj, out=None, mom=None):
+        """Table force with the i-side moments of its adjoint
+        (pgh_batch_table_moments): returns [ax, ay, az] and mom [7 * ni_total]
+        (S, Mxx, Mxy, Mxz, Myy, Myz, Mzz, each a row of ni_total)."""
+        c = self.ctx
+        c._sync_stream()
+        self._check_sizes((xi, yi, zi), (xj, yj, zj, mj))
+        if out is None:
+            out = [c._empty(self.ni_total) for _ in range(3)]
+        if mom is None:
+            mom = c._empty(7 * self.ni_total)
+        pgh_batch_table_moments(c.h, self.h, xi, yi, zi, xj, yj, zj, mj, out[0], out[1], out[2],
+                                mom)
+        return out, mom
+
     def autotune(self, family, xi, yi, zi, xj, yj, zj, mj, reps=3, cache=None):
         """Selects the fastest variant (tile shape) of a batched family on this
         plan (PGH_FAMILY_NEWTON_BATCH uses the context's eps_to_all) and
@@ -993,14 +1030,21 @@ class TableForceBatch(torch.autograd.Function):
     table entries (G0 and G1 as independent leaves, interleaved like the
     table), the j masses and the i- and j-positions through
     pgh_batch_table_bwd (the interpolant is linear in s inside a bin, so its
-    s-derivative is the bin's G1; zero beyond the cutoff)."""
+    s-derivative is the bin's G1; zero beyond the cutoff).  When the
+    i-positions need a gradient the forward also keeps the i-side moments
+    (pgh_batch_table_moments) and the backward forms that gradient from them
+    (pgh_batch_table_bwd_moments) instead of a second pass over the pairs."""
 
     @staticmethod
     def forward(fctx, plan, E, F, rcut, table, xi, yi, zi, xj, yj, zj, mj):
         c = plan.ctx
         c.set_table(E, F, rcut, table)
-        out = plan.table(xi, yi, zi, xj, yj, zj, mj)
+        if any(fctx.needs_input_grad[5:8]):
+            out, mom = plan.table_moments(xi, yi, zi, xj, yj, zj, mj)
+        else:
+            out, mom = plan.table(xi, yi, zi, xj, yj, zj, mj), None
         fctx.save_for_backward(table, xi, yi, zi, xj, yj, zj, mj)
+        fctx.mom = mom
         fctx.plan = plan
         fctx.shape = (E, F, float(rcut))
         return tuple(out)
@@ -1018,7 +1062,13 @@ class TableForceBatch(torch.autograd.Function):
         gm = c._empty(plan.nj_total) if need[11] else None
         gi = [c._empty(plan.ni_total) for _ in range(3)] if any(need[5:8]) else [None] * 3
         gj = [c._empty(plan.nj_total) for _ in range(3)] if any(need[8:11]) else [None] * 3
-        pgh_batch_table_bwd(c.h, plan.h, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, gt, gm, *gi, *gj)
+        if fctx.mom is not None:
+            pgh_batch_table_bwd_moments(c.h, plan.h, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz,
+                                        fctx.mom, gt, gm, *gi, *gj)
+        else:
+            pgh_batch_table_bwd(c.h, plan.h, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, gt, gm, *gi,
+                                *gj)
+        fctx.mom = None
         return (None, None, None, None, gt, *gi, *gj, gm)
 
 

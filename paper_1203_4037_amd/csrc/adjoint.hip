@@ -535,17 +535,29 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
                 if (jlog >= 2) v += __shfl_xor(v, 16);
                 if (jlog >= 1) v += __shfl_xor(v, 32);
             };
+            // one task per entry when the lists' j-ranges are disjoint:
+            // stores; otherwise the entry's lists add up
             if (want_m) {
                 lanes_sum(G);
-                if (active && ph == 0) atomicAdd(&A.gmj[j], G);
+                if (active && ph == 0) {
+                    if (A.jdisjoint) A.gmj[j] = G;
+                    else atomicAdd(&A.gmj[j], G);
+                }
             }
             if (want_xj) {
                 lanes_sum(Ux), lanes_sum(Uy), lanes_sum(Uz);
                 lanes_sum(Vx), lanes_sum(Vy), lanes_sum(Vz);
                 if (active && ph == 0) {
-                    atomicAdd(&A.gxj[j], mj * __builtin_fmaf(c2, Vx, Ux));
-                    atomicAdd(&A.gyj[j], mj * __builtin_fmaf(c2, Vy, Uy));
-                    atomicAdd(&A.gzj[j], mj * __builtin_fmaf(c2, Vz, Uz));
+                    const float gx = mj * __builtin_fmaf(c2, Vx, Ux);
+                    const float gy = mj * __builtin_fmaf(c2, Vy, Uy);
+                    const float gz = mj * __builtin_fmaf(c2, Vz, Uz);
+                    if (A.jdisjoint) {
+                        A.gxj[j] = gx, A.gyj[j] = gy, A.gzj[j] = gz;
+                    } else {
+                        atomicAdd(&A.gxj[j], gx);
+                        atomicAdd(&A.gyj[j], gy);
+                        atomicAdd(&A.gzj[j], gz);
+                    }
                 }
             }
         } else {
@@ -618,21 +630,10 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
     }
 }
 
-// gtable[k] = sum of the kGradCopies partial copies, in copy order.
-__global__ void __launch_bounds__(256) k_table_bwd_sum(int n, const float *__restrict__ copies,
-                                                       float *__restrict__ gtable)
-{
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= n) return;
-    float v = 0.f;
-#pragma unroll
-    for (int q = 0; q < kGradCopies; ++q) v += copies[(size_t)q * n + k];
-    gtable[k] = v;
-}
-
-// Zeroes the gradient copies, the per-entry gradients and the task counter
-// ahead of k_table_bwd (a kernel rather than memsets, so the sequence can be
-// captured in a graph).  Up to 8 arrays of the given lengths (NULL: skipped).
+// Zeroes the per-entry gradients that are added up (lists sharing
+// j-entries; the i-major pass) and the task counter ahead of k_table_bwd (a
+// kernel rather than memsets, so the sequence can be captured in a graph).
+// Up to 8 arrays of the given lengths (NULL: skipped).
 struct ZeroList {
     float *p[8];
     int n[8];
@@ -647,6 +648,79 @@ __global__ void __launch_bounds__(256) k_table_bwd_prologue(ZeroList z, unsigned
     for (int q = 0; q < 8; ++q)
         if (z.p[q])
             for (int k = t0; k < z.n[q]; k += stride) z.p[q][k] = 0.f;
+}
+
+// The work after k_table_bwd, in one launch:
+//   * gtable[k] = the sum of the kGradCopies partial copies, in copy order;
+//     the copies are put back to zero for the next call;
+//   * with disjoint j-ranges, the per-entry gradients of j-entries in no
+//     list (which no task stored) are set to zero;
+//   * with the forward's moments (TableBwdArgs::mom), the i-side position
+//     gradient: row i of an item gets dL/dr_i = -(S_i w_i + 2c M_i w_i), rows
+//     in no item 0.
+struct BwdTail {
+    int n_tab;  // 2K, or 0 without a table gradient
+    float *copies, *gtable;
+    int nj;  // j-entries to check against the ranges, or 0
+    const int2 *jrange;
+    int n_jrange;
+    float *gmj, *gxj, *gyj, *gzj;
+    int ni;  // i-rows of the moment gradient, or 0
+    const float *mom;  // [7][ni]
+    const float *wx, *wy, *wz;
+    float *gxi, *gyi, *gzi;
+    const int2 *irange;
+    int n_irange;
+    int icover;  // every i-row is in an item
+    float c2;    // 2c
+};
+
+// Whether index r lies in one of the n ranges (off, len) sorted by off.
+__device__ __forceinline__ bool in_ranges(const int2 *rg, int n, int r)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rg[mid].x <= r) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo > 0 && r < rg[lo - 1].x + rg[lo - 1].y;
+}
+
+__global__ void __launch_bounds__(256) k_table_bwd_tail(BwdTail t)
+{
+    const int stride = gridDim.x * 256;
+    const int t0 = blockIdx.x * 256 + threadIdx.x;
+    for (int k = t0; k < t.n_tab; k += stride) {
+        float v = 0.f;
+#pragma unroll
+        for (int q = 0; q < kGradCopies; ++q) {
+            v += t.copies[(size_t)q * t.n_tab + k];
+            t.copies[(size_t)q * t.n_tab + k] = 0.f;
+        }
+        t.gtable[k] = v;
+    }
+    for (int j = t0; j < t.nj; j += stride) {
+        if (in_ranges(t.jrange, t.n_jrange, j)) continue;
+        if (t.gmj) t.gmj[j] = 0.f;
+        if (t.gxj) t.gxj[j] = t.gyj[j] = t.gzj[j] = 0.f;
+    }
+    for (int i = t0; i < t.ni; i += stride) {
+        float gx = 0.f, gy = 0.f, gz = 0.f;
+        if (t.icover || in_ranges(t.irange, t.n_irange, i)) {
+            const float *m = t.mom + i;
+            const size_t n = (size_t)t.ni;
+            const float S = m[0], mxx = m[n], mxy = m[2 * n], mxz = m[3 * n], myy = m[4 * n],
+                        myz = m[5 * n], mzz = m[6 * n];
+            const float wx = t.wx[i], wy = t.wy[i], wz = t.wz[i];
+            gx = -__builtin_fmaf(t.c2, mxx * wx + mxy * wy + mxz * wz, S * wx);
+            gy = -__builtin_fmaf(t.c2, mxy * wx + myy * wy + myz * wz, S * wy);
+            gz = -__builtin_fmaf(t.c2, mxz * wx + myz * wy + mzz * wz, S * wz);
+        }
+        t.gxi[i] = gx;
+        t.gyi[i] = gy;
+        t.gzi[i] = gz;
+    }
 }
 
 int resident(const void *k, size_t lds)
@@ -720,6 +794,10 @@ hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int
                                   hipStream_t s)
 {
     const int K = 1 << (A.b.E + A.b.F);
+    // the i-side gradient: from the forward's moments in the tail kernel
+    // (each row written once), or accumulated by the i-major tasks
+    const bool from_mom = A.gxi && A.mom;
+    const bool store_j = A.jdisjoint != 0;
     ZeroList z{};
     int nz = 0, longest = 0;
     auto add = [&](float *p, int n) {
@@ -728,17 +806,20 @@ hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int
         z.n[nz++] = n;
         longest = std::max(longest, n);
     };
-    add(A.gtable ? A.gcopies : nullptr, kGradCopies * 2 * K);
-    add(A.gmj, A.nj_total);
-    add(A.gxj, A.nj_total), add(A.gyj, A.nj_total), add(A.gzj, A.nj_total);
-    add(A.gxi, A.ni_total), add(A.gyi, A.ni_total), add(A.gzi, A.ni_total);
-    const int zb = std::max(1, std::min(1024, (longest + 255) / 256));
-    hipLaunchKernelGGL(k_table_bwd_prologue, dim3(zb), dim3(256), 0, s, z, queue);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (!store_j) {
+        add(A.gmj, A.nj_total);
+        add(A.gxj, A.nj_total), add(A.gyj, A.nj_total), add(A.gzj, A.nj_total);
+    }
+    if (!from_mom) add(A.gxi, A.ni_total), add(A.gyi, A.ni_total), add(A.gzi, A.ni_total);
+    hipError_t e = hipSuccess;
+    if (nz > 0) {
+        const int zb = std::max(1, std::min(1024, (longest + 255) / 256));
+        hipLaunchKernelGGL(k_table_bwd_prologue, dim3(zb), dim3(256), 0, s, z, queue);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     const bool jside = A.gtable || A.gmj || A.gxj;
     const int n_m = jside ? n_jtasks : 0;
-    const int n_i = A.gxi ? n_itasks : 0;
+    const int n_i = (A.gxi && !from_mom) ? n_itasks : 0;
     if (n_m + n_i > 0) {
         const size_t lds = (size_t)K * 4 * sizeof(float);
         const int cap = num_cu * resident((const void *)k_table_bwd, lds);
@@ -747,9 +828,22 @@ hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int
                            n_i, queue);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (A.gtable) {
-        hipLaunchKernelGGL(k_table_bwd_sum, dim3((2 * K + 255) / 256), dim3(256), 0, s, 2 * K,
-                           (const float *)A.gcopies, A.gtable);
+    BwdTail t{};
+    if (A.gtable) t.n_tab = 2 * K, t.copies = A.gcopies, t.gtable = A.gtable;
+    if (store_j && !A.jcover && (A.gmj || A.gxj)) {
+        t.nj = A.nj_total, t.jrange = A.jrange, t.n_jrange = A.n_jrange;
+        t.gmj = A.gmj, t.gxj = A.gxj, t.gyj = A.gyj, t.gzj = A.gzj;
+    }
+    if (from_mom) {
+        t.ni = A.ni_total, t.mom = A.mom, t.wx = A.wx, t.wy = A.wy, t.wz = A.wz;
+        t.gxi = A.gxi, t.gyi = A.gyi, t.gzi = A.gzi;
+        t.irange = A.irange, t.n_irange = A.n_irange, t.icover = A.icover;
+        t.c2 = 2.0f * A.b.c;
+    }
+    const int work = std::max(t.n_tab, std::max(t.nj, t.ni));
+    if (work > 0) {
+        const int tb = std::max(1, std::min(1024, (work + 255) / 256));
+        hipLaunchKernelGGL(k_table_bwd_tail, dim3(tb), dim3(256), 0, s, t);
         e = hipGetLastError();
     }
     return e;

@@ -228,6 +228,19 @@ __global__ void __launch_bounds__(64) k_combine(CombineArgs a)
     a.ay[i] = s.y;
     a.az[i] = s.z;
     if (a.phi) a.phi[i] = s.w;
+    if (a.mom) {
+        // the i-side moments of the table adjoint, two float4 per partial sum
+        float m[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        const size_t at = (size_t)ch.slot * 64 + ch.lane0 + lane;
+        for (int q = 0; q < ch.n_parts; ++q) {
+            const float4 u = a.mpartial[2 * (at + (size_t)q * 64)];
+            const float4 v = a.mpartial[2 * (at + (size_t)q * 64) + 1];
+            m[0] += u.x, m[1] += u.y, m[2] += u.z, m[3] += u.w;
+            m[4] += v.x, m[5] += v.y, m[6] += v.z;
+        }
+#pragma unroll
+        for (int c = 0; c < 7; ++c) a.mom[(size_t)c * a.ni_total + i] = m[c];
+    }
 }
 
 using BatchKernel = void (*)(BatchArgs);
@@ -310,7 +323,7 @@ hipError_t launch_combine(const BatchArgs &a, bool phi, hipStream_t s)
 {
     if (a.n_chunks == 0) return hipSuccess;
     CombineArgs c{a.n_chunks, a.chunks, a.partial, a.ax, a.ay, a.az, phi ? a.phi : nullptr,
-                  a.out4};
+                  a.out4, a.mpartial, a.mom, a.ni_total};
     hipLaunchKernelGGL(k_combine, dim3(a.n_chunks), dim3(64), 0, s, c);
     return hipGetLastError();
 }

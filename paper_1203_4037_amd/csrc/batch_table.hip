@@ -52,11 +52,14 @@ struct TaskLanes {
 // KI i-particles per lane, TW j-records per lane per tile (unpaired tasks),
 // 2^TB table entries at most, HT the (H, G1) form, PHI the potential table,
 // WPB waves per workgroup (one table copy per workgroup).
-template <int KI, int TW, int TB, bool HT, bool PHI, int WPB, bool PF>
+template <int KI, int TW, int TB, bool HT, bool PHI, int WPB, bool PF, bool MOM = false>
 // eight waves per SIMD whatever the workgroup size (64 VGPRs at most)
 __global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_batch_table(BatchArgs a)
 {
+    // MOM: also the i-side moments of the adjoint (table_pairs_mom), in the
+    // paper's form, without a potential
+    static_assert(!MOM || (!HT && !PHI), "moments take the paper's form, no potential");
     using Entry = std::conditional_t<PHI, float4, float2>;
     constexpr int kEntryLog = PHI ? 4 : 3;
     __shared__ Entry stab[1 << TB];
@@ -172,8 +175,13 @@ k_batch_table(BatchArgs a)
         if (t_next < n_t && lane < 12) fld = ((const int *)(tbase + t_next))[lane];
 
         float tx[KI], ty[KI], tz[KI], tp[KI];
+        float tm[MOM ? 7 : 1][KI];
 #pragma unroll
-        for (int k = 0; k < KI; ++k) tx[k] = ty[k] = tz[k] = tp[k] = 0.f;
+        for (int k = 0; k < KI; ++k) {
+            tx[k] = ty[k] = tz[k] = tp[k] = 0.f;
+#pragma unroll
+            for (int c = 0; c < (MOM ? 7 : 1); ++c) tm[c][k] = 0.f;
+        }
         const float4 *src = tile + (L.second ? 64 : 0) + L.phase;
         for (int tl = 0; tl < L.ntiles; ++tl) {
             wave_sync();  // the previous tile's reads are done
@@ -182,7 +190,10 @@ k_batch_table(BatchArgs a)
             if (tl + 1 < L.ntiles) load(tk, L, tl + 1);
             const int cnt = min(L.T, L.nj - tl * L.T);
             auto step = [&](const float4 p) {
-                table_pairs_v<KI, HT, PHI>(p, L.px, L.py, L.pz, tab, kc, tx, ty, tz, tp);
+                if constexpr (MOM)
+                    table_pairs_mom<KI>(p, L.px, L.py, L.pz, tab, kc, tx, ty, tz, tm);
+                else
+                    table_pairs_v<KI, HT, PHI>(p, L.px, L.py, L.pz, tab, kc, tx, ty, tz, tp);
             };
             if (cnt == L.T) {
                 // a full tile: T / P records per lane with a compile-time
@@ -203,7 +214,10 @@ k_batch_table(BatchArgs a)
                             // nothing of the sums moves above the next
                             // record's read
                             __builtin_amdgcn_sched_barrier(0);
-                            table_tail<KI, PHI>(p.w, q, tx, ty, tz, tp);
+                            if constexpr (MOM)
+                                table_tail_mom<KI>(p.w, q, tx, ty, tz, tm);
+                            else
+                                table_tail<KI, PHI>(p.w, q, tx, ty, tz, tp);
                             p = pn;
                         }
                     } else {
@@ -236,6 +250,10 @@ k_batch_table(BatchArgs a)
                 ty[k] += __shfl_xor(ty[k], d);
                 tz[k] += __shfl_xor(tz[k], d);
                 if (PHI) tp[k] += __shfl_xor(tp[k], d);
+                if constexpr (MOM) {
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) tm[c][k] += __shfl_xor(tm[c][k], d);
+                }
             }
         }
         if (L.phase == 0) {
@@ -249,11 +267,19 @@ k_batch_table(BatchArgs a)
                     a.ay[i] = ty[k];
                     a.az[i] = tz[k];
                     if (PHI) a.phi[i] = tp[k];
+                    if constexpr (MOM) {
+#pragma unroll
+                        for (int c = 0; c < 7; ++c) a.mom[(size_t)c * a.ni_total + i] = tm[c][k];
+                    }
                 } else {
                     // partial sums of one part of a split j-list; k_combine
                     // adds the parts of the chunk in order after this launch
-                    a.partial[(size_t)(tk.slot + tk.part) * 64 + L.lane0 + slot] =
-                        make_float4(tx[k], ty[k], tz[k], tp[k]);
+                    const size_t at = (size_t)(tk.slot + tk.part) * 64 + L.lane0 + slot;
+                    a.partial[at] = make_float4(tx[k], ty[k], tz[k], tp[k]);
+                    if constexpr (MOM) {
+                        a.mpartial[2 * at] = make_float4(tm[0][k], tm[1][k], tm[2][k], tm[3][k]);
+                        a.mpartial[2 * at + 1] = make_float4(tm[4][k], tm[5][k], tm[6][k], 0.f);
+                    }
                 }
             }
         }
@@ -328,6 +354,26 @@ const char *table_batch_variant_name(int v)
 }
 
 int table_batch_default() { return 2; }
+
+hipError_t launch_table_batch_moments(const BatchArgs &a0, int num_cu, hipStream_t s)
+{
+    if (a0.n_tasks <= 0) return hipSuccess;
+    constexpr int kWpb = 4;
+    const TableKernel k = a0.E + a0.F <= 10
+                              ? k_batch_table<1, 1, 10, false, false, kWpb, false, true>
+                              : k_batch_table<1, 1, 12, false, false, kWpb, false, true>;
+    BatchArgs a = a0;
+    a.phi = nullptr;
+    a.ptable = nullptr;
+    const int cap = num_cu * resident_blocks(k, kWpb);
+    const int blocks = std::max(a.nq, std::min(cap, (a.n_tasks + kWpb - 1) / kWpb));
+    a.n_waves = blocks * kWpb;
+    a.static_order = (long long)a.n_tasks <= kStaticRounds * (long long)a.n_waves ? 1 : 0;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * kWpb), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.n_chunks == 0) return e;
+    return launch_combine(a, false, s);
+}
 
 hipError_t launch_table_batch(const BatchArgs &a0, int variant, int num_cu, hipStream_t s)
 {

@@ -43,6 +43,20 @@ struct pgh_plan {
     int n_itasks;           // i-major tasks of the table adjoint (i-side positions)
     Task *itasks;           // device
     unsigned *jqueue;       // device, counter of the j-major tasks
+    int2 *irange;           // device, the items' i-ranges (i_off, n_i) by i_off
+    int n_irange;
+    // the items' j-ranges (j_off, n_j) by j_off, and whether they are
+    // disjoint (every j-entry in at most one list: the adjoint then stores
+    // the per-entry gradients instead of adding them)
+    int2 *jrange;
+    int n_jrange;
+    bool j_disjoint;
+    // the ranges cover every row / entry (no gap to test against them)
+    bool i_cover, j_cover;
+    // partial moments of split chunks (pgh_batch_table_moments), grown on
+    // its first call on the plan: two float4 per partial sum
+    float4 *mpartial;
+    size_t mpartial_cap;
     // device expansion of the compact form (tree plans): the entries, the
     // sort keys and task indices (and their sorted copies), sort temp storage
     PlanDesc *desc;
@@ -169,6 +183,9 @@ void free_plan_memory(pgh_plan *p)
     (void)hipFree(p->jtasks);
     (void)hipFree(p->jqueue);
     (void)hipFree(p->itasks);
+    (void)hipFree(p->irange);
+    (void)hipFree(p->jrange);
+    (void)hipFree(p->mpartial);
     (void)hipFree(p->desc);
     (void)hipFree(p->keys);
     (void)hipFree(p->keys_out);
@@ -272,8 +289,13 @@ void reset_plan(pgh_plan *p)
     (void)hipFree(p->jtasks);
     (void)hipFree(p->jqueue);
     (void)hipFree(p->itasks);
+    (void)hipFree(p->irange);
+    (void)hipFree(p->jrange);
     p->jtasks = p->itasks = nullptr;
     p->jqueue = nullptr;
+    p->irange = p->jrange = nullptr;
+    p->n_irange = p->n_jrange = 0;
+    p->j_disjoint = p->i_cover = p->j_cover = false;
     p->adj_built = false;
     p->n_jtasks = p->n_itasks = 0;
     p->n_tasks = 0;
@@ -494,6 +516,18 @@ int pgh_open(pgh_ctx **out, int device, void *hip_stream)
         (void)hipFree(c->ptab);
         delete c;
         return PGH_ENOMEM;
+    }
+    // the table adjoint's gradient copies start at zero and are put back to
+    // zero by the kernel that sums them (k_table_bwd_tail)
+    if (hipMemsetAsync(c->gcopy, 0, (sizeof(float2) << kMaxTableBits) * kGradCopies,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        g_open_error = "clearing the table-gradient scratch failed";
+        (void)hipFree(c->tab);
+        (void)hipFree(c->gcopy);
+        (void)hipFree(c->ptab);
+        delete c;
+        return PGH_EHIP;
     }
     *out = c;
     return PGH_OK;
@@ -919,15 +953,35 @@ int build_adjoint_tasks(pgh_ctx *c, pgh_plan *p)
     if (p->adj_built) return PGH_OK;
     std::vector<Task> jt, it_tasks;
     plan_adjoint_tasks(p->ordered, p->waves > 0 ? p->waves : planner_waves(c), jt, it_tasks);
+    // the items' i-ranges (p->ordered is sorted by i_off), for the i-side
+    // gradient formed from the forward's moments
+    std::vector<int2> ir, jr;
+    ir.reserve(p->ordered.size());
+    for (const pgh_item &it : p->ordered) {
+        ir.push_back(make_int2(it.i_off, it.n_i));
+        if (it.n_j > 0) jr.push_back(make_int2(it.j_off, it.n_j));
+    }
+    std::sort(jr.begin(), jr.end(), [](const int2 &a, const int2 &b) { return a.x < b.x; });
+    bool disjoint = true;
+    for (size_t k = 1; k < jr.size(); ++k)
+        if ((long long)jr[k - 1].x + jr[k - 1].y > jr[k].x) disjoint = false;
+    long long ni_sum = 0, nj_sum = 0;
+    for (const int2 &r : ir) ni_sum += r.y;
+    for (const int2 &r : jr) nj_sum += r.y;
     if (hipMalloc((void **)&p->jqueue, 2 * sizeof(unsigned)) != hipSuccess ||
         (!jt.empty() && hipMalloc((void **)&p->jtasks, jt.size() * sizeof(Task)) != hipSuccess) ||
         (!it_tasks.empty() &&
-         hipMalloc((void **)&p->itasks, it_tasks.size() * sizeof(Task)) != hipSuccess)) {
+         hipMalloc((void **)&p->itasks, it_tasks.size() * sizeof(Task)) != hipSuccess) ||
+        (!ir.empty() && hipMalloc((void **)&p->irange, ir.size() * sizeof(int2)) != hipSuccess) ||
+        (!jr.empty() && hipMalloc((void **)&p->jrange, jr.size() * sizeof(int2)) != hipSuccess)) {
         (void)hipFree(p->jqueue);
         (void)hipFree(p->jtasks);
         (void)hipFree(p->itasks);
+        (void)hipFree(p->irange);
+        (void)hipFree(p->jrange);
         p->jqueue = nullptr;
         p->jtasks = p->itasks = nullptr;
+        p->irange = p->jrange = nullptr;
         return fail(c, PGH_ENOMEM, "hipMalloc(adjoint tasks) failed");
     }
     if (hipMemsetAsync(p->jqueue, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
@@ -936,10 +990,20 @@ int build_adjoint_tasks(pgh_ctx *c, pgh_plan *p)
         (!it_tasks.empty() &&
          hipMemcpyAsync(p->itasks, it_tasks.data(), it_tasks.size() * sizeof(Task),
                         hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+        (!ir.empty() && hipMemcpyAsync(p->irange, ir.data(), ir.size() * sizeof(int2),
+                                       hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+        (!jr.empty() && hipMemcpyAsync(p->jrange, jr.data(), jr.size() * sizeof(int2),
+                                       hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, PGH_EHIP, "uploading the adjoint tasks failed");
     p->n_jtasks = (int)jt.size();
     p->n_itasks = (int)it_tasks.size();
+    p->n_irange = (int)ir.size();
+    p->n_jrange = (int)jr.size();
+    p->j_disjoint = disjoint;
+    // disjoint ranges inside [0, total) whose lengths add up to it cover it
+    p->i_cover = ni_sum == p->ni_total;
+    p->j_cover = disjoint && nj_sum == p->nj_total;
     p->adj_built = true;
     return PGH_OK;
 }
@@ -1016,6 +1080,39 @@ int pgh_batch_table(pgh_ctx *c, const pgh_plan *p, const float *xi, const float 
     return PGH_OK;
 }
 
+int pgh_batch_table_moments(pgh_ctx *c, pgh_plan *p, const float *xi, const float *yi,
+                            const float *zi, const float *xj, const float *yj, const float *zj,
+                            const float *mj, float *ax, float *ay, float *az, float *mom)
+{
+    if (!c) return PGH_EINVAL;
+    int st = check_plan(c, p);
+    if (st) return st;
+    if (!c->tab_set) return fail(c, PGH_ESTATE, "no force table set");
+    if (p->n_tasks == 0) return PGH_OK;
+    if (!xi || !yi || !zi || !ax || !ay || !az || !mom)
+        return fail(c, PGH_EINVAL, "NULL i-particle, output or moment array");
+    if (p->nj_total > 0 && (!xj || !yj || !zj || !mj))
+        return fail(c, PGH_EINVAL, "NULL j-particle array");
+    DeviceGuard g(c->device);
+    if (!grow_records(&p->mpartial, &p->mpartial_cap, (size_t)p->n_slots * 64 * 2))
+        return fail(c, PGH_ENOMEM, "hipMalloc(partial moments) failed");
+    BatchArgs a = batch_args(c, p);
+    a.xi = xi, a.yi = yi, a.zi = zi;
+    a.xj = xj, a.yj = yj, a.zj = zj, a.mj = mj;
+    a.ax = ax, a.ay = ay, a.az = az;
+    const double smax = smax_of(c->tab_E, c->tab_F);
+    a.table = c->tab;
+    a.E = c->tab_E;
+    a.F = c->tab_F;
+    a.c = table_scale(smax, c->tab_rcut);
+    a.smax = (float)smax;
+    a.mom = mom;
+    a.mpartial = p->mpartial;
+    a.ni_total = p->ni_total;
+    PGH_HIP(c, launch_table_batch_moments(a, c->num_cu, c->stream));
+    return PGH_OK;
+}
+
 int pgh_newton_allpairs_bwd(pgh_ctx *c, int n, const float *x, const float *y, const float *z,
                             const float *m, float eps2, const float *wx, const float *wy,
                             const float *wz, float *gx, float *gy, float *gz, float *gm)
@@ -1084,11 +1181,13 @@ int pgh_newton_ij_bwd(pgh_ctx *c, int ni, const float *xi, const float *yi, cons
     return PGH_OK;
 }
 
-int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
-                        const float *zi, const float *xj, const float *yj, const float *zj,
-                        const float *mj, const float *wx, const float *wy, const float *wz,
-                        float *gtable, float *gmj, float *gxi, float *gyi, float *gzi,
-                        float *gxj, float *gyj, float *gzj)
+namespace {
+
+int table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi, const float *zi,
+              const float *xj, const float *yj, const float *zj, const float *mj,
+              const float *wx, const float *wy, const float *wz, const float *mom,
+              float *gtable, float *gmj, float *gxi, float *gyi, float *gzi, float *gxj,
+              float *gyj, float *gzj)
 {
     if (!c) return PGH_EINVAL;
     int st = check_plan(c, p);
@@ -1122,9 +1221,41 @@ int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const fl
     A.gxj = gxj, A.gyj = gyj, A.gzj = gzj;
     A.ni_total = p->ni_total;
     A.nj_total = p->nj_total;
+    A.mom = mom;
+    A.irange = p->irange;
+    A.n_irange = p->n_irange;
+    A.jdisjoint = p->j_disjoint ? 1 : 0;
+    A.icover = p->i_cover ? 1 : 0;
+    A.jcover = p->j_cover ? 1 : 0;
+    A.jrange = p->jrange;
+    A.n_jrange = p->n_jrange;
     PGH_HIP(c, launch_table_batch_bwd(A, p->jtasks, p->n_jtasks, p->itasks, p->n_itasks, p->jqueue,
                                       c->num_cu, c->stream));
     return PGH_OK;
+}
+
+}  // namespace
+
+int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
+                        const float *zi, const float *xj, const float *yj, const float *zj,
+                        const float *mj, const float *wx, const float *wy, const float *wz,
+                        float *gtable, float *gmj, float *gxi, float *gyi, float *gzi,
+                        float *gxj, float *gyj, float *gzj)
+{
+    return table_bwd(c, p, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, nullptr, gtable, gmj, gxi, gyi,
+                     gzi, gxj, gyj, gzj);
+}
+
+int pgh_batch_table_bwd_moments(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
+                                const float *zi, const float *xj, const float *yj,
+                                const float *zj, const float *mj, const float *wx,
+                                const float *wy, const float *wz, const float *mom,
+                                float *gtable, float *gmj, float *gxi, float *gyi, float *gzi,
+                                float *gxj, float *gyj, float *gzj)
+{
+    if (c && !mom) return fail(c, PGH_EINVAL, "NULL moment array");
+    return table_bwd(c, p, xi, yi, zi, xj, yj, zj, mj, wx, wy, wz, mom, gtable, gmj, gxi, gyi,
+                     gzi, gxj, gyj, gzj);
 }
 
 // ---------------------------------------------------------------------------

@@ -9,6 +9,7 @@
 
 #include "pgh.h"
 #include "plan_types.h"
+#include "split.h"
 
 namespace pgh {
 
@@ -76,6 +77,12 @@ struct BatchArgs {
     // NULL, or packed outputs (ax, ay, az, phi) per i-particle in place of
     // the four arrays (Newton only; the potential is then always computed)
     float4 *out4;
+    // table force only: NULL, or the i-side moments of the adjoint,
+    // mom[k * ni_total + i] for k = 0 .. 6 (S, Mxx, Mxy, Mxz, Myy, Myz, Mzz),
+    // and the partial moments of split chunks (two float4 per partial sum)
+    float *mom;
+    float4 *mpartial;
+    int ni_total;
 };
 
 struct CombineArgs {
@@ -84,6 +91,9 @@ struct CombineArgs {
     const float4 *partial;
     float *ax, *ay, *az, *phi;
     float4 *out4;  // as in BatchArgs
+    const float4 *mpartial;  // as in BatchArgs
+    float *mom;
+    int ni_total;
 };
 
 // Copies of the table gradient that the workgroups of the adjoint add into
@@ -98,6 +108,20 @@ struct TableBwdArgs {
     float *gmj;
     float *gcopies;  // kGradCopies x 2K floats (context scratch)
     float *gxi, *gyi, *gzi;  // i-side position gradient (or NULL)
+    // NULL, or the forward's i-side moments (BatchArgs::mom): the i-side
+    // position gradient is then formed from them per row, with no i-major
+    // pass; the rows of the plan's items are the ranges irange (i_off, n_i)
+    // sorted by i_off
+    const float *mom;
+    const int2 *irange;
+    int n_irange;
+    // the items' j-ranges (j_off, n_j) sorted by j_off; jdisjoint: no two
+    // overlap, so every j-entry is written by one j-major task (stores, no
+    // zeroing) and entries outside every range are set to zero at the end
+    int jdisjoint;
+    const int2 *jrange;
+    int n_jrange;
+    int icover, jcover;  // the i- (j-) ranges cover every row (entry)
     float *gxj, *gyj, *gzj;  // j-side position gradient (or NULL)
     int ni_total, nj_total;
 };
@@ -110,17 +134,6 @@ hipError_t launch_self_potential(int n, const float *m, const float *eps2i, floa
                                  float *phi, hipStream_t s);
 hipError_t launch_table_grad_chain(int E, int F, const float *g, float *out, hipStream_t s);
 
-// All-pairs launches split the j-range over S workgroup rows when the i-range
-// alone gives too few waves; the shares write partial sums [S][4][ni] that
-// k_combine_split adds in order.  The split aims for 8 waves per SIMD of a
-// 256-CU part (the most that are resident at 64 VGPRs): gfx950 issues two
-// FP32 VALU instructions per cycle pair only from different waves, and with
-// 4 waves per SIMD the pair rate of the Newton kernel is about 6% lower
-// (N = 262144: 22.4 ms unsplit, 21.1 ms split in 2 or more).
-constexpr int kSplitTargetWaves = 8192;
-int split_count(int ni, int nj, int ki, int jt, int target_waves, size_t part_cap);
-hipError_t launch_combine_split(int n, int S, const float *part, float *ax, float *ay, float *az,
-                                float *phi, hipStream_t s);
 
 int newton_allpairs_variants();
 const char *newton_allpairs_variant_name(int v);
@@ -166,6 +179,9 @@ hipError_t launch_plan_expand(PlanExpandArgs a, void *temp, size_t temp_bytes, h
 hipError_t launch_newton_batch(const BatchArgs &a, int variant, bool refine, bool guard,
                                int num_cu, hipStream_t s);
 hipError_t launch_table_batch(const BatchArgs &a, int variant, int num_cu, hipStream_t s);
+// The table force with the i-side moments of its adjoint (a.mom, a.mpartial
+// set; one i-particle per lane, the paper's (G0, G1) form).
+hipError_t launch_table_batch_moments(const BatchArgs &a, int num_cu, hipStream_t s);
 
 // Records of two float4: (x, y, z, s or s_all) and (wx, wy, wz, 0).
 hipError_t launch_pack_xw(int n, const float *x, const float *y, const float *z, const float *s,

@@ -244,6 +244,45 @@ __device__ __forceinline__ void table_tail(const float mj, const TableGather<KI,
     }
 }
 
+// table_tail in the paper's form with the i-side moments of the adjoint of
+// L = sum_i w_i . a_i: the derivative of m_j g d with respect to r_i is
+// -m_j (g I + 2c G1_k d d^T) inside a bin, so dL/dr_i = -(S_i w_i +
+// 2c M_i w_i) with S_i = sum_j m_j g and M_i = sum_j m_j G1_k d d^T
+// (sm[0][.] = S, sm[1..6][.] = Mxx, Mxy, Mxz, Myy, Myz, Mzz).
+template <int KI>
+__device__ __forceinline__ void table_tail_mom(const float mj, const TableGather<KI, false> &q,
+                                               float *sx, float *sy, float *sz, float (*sm)[KI])
+{
+#pragma unroll
+    for (int i = 0; i < KI; ++i) {
+        const float g = __builtin_fmaf(q.t[i].y, q.ds[i], q.t[i].x);
+        const float mg = mj * g;
+        sx[i] = __builtin_fmaf(mg, q.dx[i], sx[i]);
+        sy[i] = __builtin_fmaf(mg, q.dy[i], sy[i]);
+        sz[i] = __builtin_fmaf(mg, q.dz[i], sz[i]);
+        sm[0][i] += mg;
+        const float mg1 = mj * q.t[i].y;
+        const float ux = mg1 * q.dx[i], uy = mg1 * q.dy[i];
+        sm[1][i] = __builtin_fmaf(ux, q.dx[i], sm[1][i]);
+        sm[2][i] = __builtin_fmaf(ux, q.dy[i], sm[2][i]);
+        sm[3][i] = __builtin_fmaf(ux, q.dz[i], sm[3][i]);
+        sm[4][i] = __builtin_fmaf(uy, q.dy[i], sm[4][i]);
+        sm[5][i] = __builtin_fmaf(uy, q.dz[i], sm[5][i]);
+        sm[6][i] = __builtin_fmaf(mg1 * q.dz[i], q.dz[i], sm[6][i]);
+    }
+}
+
+template <int KI>
+__device__ __forceinline__ void table_pairs_mom(const float4 p, const float *px, const float *py,
+                                                const float *pz, const char *__restrict__ tab,
+                                                const TableConsts &k, float *sx, float *sy,
+                                                float *sz, float (*sm)[KI])
+{
+    TableGather<KI, false> q;
+    table_head<KI, false, false>(p, px, py, pz, tab, k, q);
+    table_tail_mom<KI>(p.w, q, sx, sy, sz, sm);
+}
+
 template <int KI, bool HT, bool PHI>
 __device__ __forceinline__ void table_pairs_v(const float4 p, const float *px, const float *py,
                                               const float *pz, const char *__restrict__ tab,

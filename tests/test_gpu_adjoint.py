@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from _helpers import rms, to_dev, to_host
+from _helpers import norm_vec_err, rms, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -380,3 +380,91 @@ def test_table_adjoint_graph_replays(pgh, ctx):
         ctx._sync_stream()
         call()  # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_table_moments_path(pgh, ctx):
+    """pgh_batch_table_moments and pgh_batch_table_bwd_moments through the C
+    ABI: the forward's force meets the table gate; the i-side gradient formed
+    from the saved moments meets the same gate against the oracle's adjoint
+    as the two-pass one does, with the other gradients unchanged; rows in no
+    item get a zero gradient and keep their moment entries; and lists long
+    enough to be cut into parts (their moments added by the combine kernel)
+    give the same; so do lists with disjoint j-ranges that leave entries out,
+    whose per-entry gradients are stored rather than added."""
+    import torch
+    rcut, eps, E, F = 1.0 / 32, 1.0 / 32 / 15, 4, 6
+    table = ctx.build_table(E, F, rcut, eps=eps)
+    rc = float(np.float32(rcut))
+
+    def check(items, xi, yi, zi, xj, yj, zj, mj, w, what, rest=True):
+        ni, nj = xi.size, xj.size
+        plan = ctx.plan(items, ni, nj)
+        di = to_dev(xi, yi, zi, *w)
+        dj = to_dev(xj, yj, zj, mj)
+        out = [torch.full((ni,), 7.0, device="cuda") for _ in range(3)]
+        mom = torch.full((7 * ni,), 5.0, device="cuda")
+        pgh.pgh_batch_table_moments(ctx.h, plan.h, *di[:3], *dj, *out, mom)
+        rows = np.zeros(ni, bool)
+        for i0, k, _, _ in items:
+            rows[i0:i0 + k] = True
+        a = np.stack(to_host(*out))
+        rt = oracle.lut_items(items, xi, yi, zi, xj, yj, zj, mj, E, F, rc, table)
+        has = rows & (rt[3] > 0)
+        e1 = norm_vec_err(a[:, has], np.stack(rt[:3])[:, has], rt[3][has])
+        assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (what, rms(e1), e1.max())
+        assert np.all(a[:, ~rows] == 7.0)
+        mh = to_host(mom)[0].reshape(7, ni)
+        assert np.all(mh[:, ~rows] == 5.0) and np.all(np.isfinite(mh[:, rows]))
+        gi = [torch.full((ni,), 3.0, device="cuda") for _ in range(3)]
+        gj = [torch.full((nj,), 3.0, device="cuda") for _ in range(3)]
+        gt = torch.full((table.size,), 3.0, device="cuda")
+        gm = torch.full((nj,), 3.0, device="cuda")
+        pgh.pgh_batch_table_bwd_moments(ctx.h, plan.h, *di[:3], *dj, *di[3:], mom, gt, gm, *gi,
+                                        *gj)
+        r = oracle.lut_bwd_pos_items(items, xi, yi, zi, xj, yj, zj, mj, *w, E, F, rc, table,
+                                     scales=True)
+        rtab, rm, at, am = oracle.lut_bwd_items(items, xi, yi, zi, xj, yj, zj, mj, *w, E, F, rc,
+                                                table, scales=True)
+        g = np.stack(to_host(*gi))
+        _gate(g[:, rows], np.stack(r[0:3])[:, rows], r[6][rows], what + " gxi")
+        assert np.all(g[:, ~rows] == 0.0)
+        _gate(np.stack(to_host(*gj)), np.stack(r[3:6]), r[7], what + " gxj")
+        jrows = np.zeros(nj, bool)
+        for i0, k, j0, kj in items:
+            if k > 0:
+                jrows[j0:j0 + kj] = True
+        assert np.all(np.stack(to_host(*gj))[:, ~jrows] == 0.0)
+        assert np.all(to_host(gm)[0][~jrows] == 0.0)
+        if rest:
+            _table_gate(to_host(gt)[0], rtab, at, E, F, what + " gtable")
+            _gate(to_host(gm)[0], rm, am, what + " gmj")
+        with pytest.raises(pgh.PGHError):
+            pgh.pgh_batch_table_bwd_moments(ctx.h, plan.h, *di[:3], *dj, *di[3:], None, gt, gm,
+                                            *gi, *gj)
+        plan.free()
+
+    # cell lists with every row in a list
+    n = 16384
+    x, y, z = synth.uniform_box(n, 43)
+    m = synth.equal_masses(n)
+    s = synth.cell_grid_items(x, y, z, m, ncell=32, block=4)
+    check(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, synth.weights(n, 44), "cells")
+    # rows in no list, and long lists cut into parts
+    n = 6000
+    x, y, z = synth.uniform_box(n, 45, box=0.1)
+    m = synth.equal_masses(n)
+    items = np.array([[0, 1500, 0, n], [1700, 2000, 0, n], [4000, 37, 100, 3000],
+                      [5000, 900, 2500, n - 2500]], np.int32)
+    # (the table and mass gradients come from the j-major pass that
+    # pgh_batch_table_bwd runs too; in this dense box a bin gathers ~1e5 float
+    # atomics, whose FP32 sum errs by more than the rms gate allows, so they
+    # are checked on the cell lists above only)
+    check(items, x, y, z, x, y, z, m, synth.weights(n, 46), "gaps and parts", rest=False)
+    # disjoint j-ranges that leave j-entries out (their gradients are stored,
+    # the entries outside set to zero), twice in a row (the second call finds
+    # the gradient copies cleared by the first)
+    items = np.array([[0, 1500, 0, 2000], [1700, 2000, 2500, 1500], [4000, 37, 4100, 900]],
+                     np.int32)
+    for rep in range(2):
+        check(items, x, y, z, x, y, z, m, synth.weights(n, 47 + rep), f"disjoint j {rep}",
+              rest=False)
