@@ -327,6 +327,7 @@ const TableBatchVariant kTableBatchVariants[] = {
     {"ki=1 tw=1 wg=4 pf", 4, pick<1, 1, false, 4, true>},
     {"ki=2 tw=1 wg=4 htab", 4, pick<2, 1, true, 4>},
     {"ki=2 tw=2 wg=4 htab", 4, pick<2, 2, true, 4>},
+    {"ki=2 tw=2 wg=2 htab", 2, pick<2, 2, true, 2>},
 };
 constexpr int kNumTableBatchVariants = sizeof(kTableBatchVariants) / sizeof(kTableBatchVariants[0]);
 

@@ -11,7 +11,7 @@ from _helpers import oracle_table, norm_vec_err, rel_vec_err, rms, to_dev, to_ho
 pytestmark = pytest.mark.gpu
 
 # tile shapes of the batched table kernel (each is run by the cell-list test)
-TABLE_BATCH_VARIANTS = 8
+TABLE_BATCH_VARIANTS = 9
 # tile shapes of the batched Newton kernel
 NEWTON_BATCH_VARIANTS = 5
 
