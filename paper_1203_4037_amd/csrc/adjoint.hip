@@ -391,6 +391,9 @@ __device__ __forceinline__ void wave_sync()
 // Tasks of each kind are sorted longest first; the first round is taken by
 // index, later ones from the counter, which the launch's last pop puts back
 // to zero.
+// IMAJ: the i-major tasks are compiled in (the j-major-only instantiation
+// holds fewer registers, so more waves fit).
+template <bool IMAJ>
 __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *jtasks, int n_m,
                                                    const Task *itasks, int n_i, unsigned *queue)
 {
@@ -399,7 +402,10 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
     const int K = 1 << (a.E + a.F);
     float2 *stab = (float2 *)dyn;  // K (G0, G1)
     float *gt = dyn + 2 * K;       // 2K gradient accumulators
-    __shared__ float4 buf[4][128];
+    // per wave: 64 i-records (x, y, z, wx) or j-records, and the (wy, wz)
+    // of the i-records
+    __shared__ float4 buf[4][64];
+    __shared__ float2 wbuf[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool want_tab = A.gtable != nullptr, want_m = A.gmj != nullptr;
     const bool want_xj = A.gxj != nullptr;
@@ -419,6 +425,7 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
     char *gtb = (char *)gt;
     const float c2 = 2.0f * a.c;
     float4 *tile = buf[wave];
+    float2 *wtile = wbuf[wave];
     float last0 = 0.f;  // clamped pairs: dL/dG0 of the last node
 
     const unsigned n_all = (unsigned)(n_m + n_i);
@@ -445,7 +452,7 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
             if (k == n_all - 1u) __hip_atomic_store(queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tn = n_waves + k;
         }
-        const bool jmajor = t < (unsigned)n_m;
+        const bool jmajor = !IMAJ || t < (unsigned)n_m;
         // jmajor: i_off/n_i = the j-chunk, j_off/n_j = the i-range; else an
         // i-chunk and a part of its j-list
         const Task tk = jmajor ? jtasks[t] : itasks[t - (unsigned)n_m];
@@ -461,18 +468,19 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
             const float qx = a.xj[j], qy = a.yj[j], qz = a.zj[j];
             const float mj = active ? a.mj[j] : 0.f;
             float G = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, Vx = 0.f, Vy = 0.f, Vz = 0.f;
-            float4 pp, pw;
+            float4 pp;
+            float2 pw;
             // i-records past the range: far away with zero weight
             auto load = [&](int base) {
                 pp = make_float4(1.0e10f, 1.0e10f, 1.0e10f, 0.f);
-                pw = make_float4(0.f, 0.f, 0.f, 0.f);
+                pw = make_float2(0.f, 0.f);
                 const int i = tk.j_off + base + lane;
                 if (base + lane < tk.n_j) {
                     pp = make_float4(a.xi[i], a.yi[i], a.zi[i], A.wx[i]);
-                    pw = make_float4(A.wy[i], A.wz[i], 0.f, 0.f);
+                    pw = make_float2(A.wy[i], A.wz[i]);
                 }
             };
-            auto pair = [&](const float4 p, const float4 w) {
+            auto pair = [&](const float4 p, const float2 w) {
                 const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
                 float r2 = dx * dx;
                 r2 = __builtin_fmaf(dy, dy, r2);
@@ -511,7 +519,7 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
             for (int base = 0; base < tk.n_j; base += 64) {
                 wave_sync();
                 tile[lane] = pp;
-                tile[64 + lane] = pw;
+                wtile[lane] = pw;
                 wave_sync();
                 if (base + 64 < tk.n_j) load(base + 64);
                 const int cnt = min(64, tk.n_j - base);
@@ -520,14 +528,14 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
 #pragma unroll 4
                     for (int ii = 0; ii < full; ++ii) {
                         const int r = (ii << jlog) + ph;
-                        pair(tile[r], tile[64 + r]);
+                        pair(tile[r], wtile[r]);
                     }
                 } else {
                     // records past cnt are zero-weight padding
                     const int trips = (cnt + js - 1) >> jlog;
                     for (int ii = 0; ii < trips; ++ii) {
                         const int r = (ii << jlog) + ph;
-                        pair(tile[r], tile[64 + r]);
+                        pair(tile[r], wtile[r]);
                     }
                 }
             }
@@ -822,9 +830,10 @@ hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int
     const int n_i = (A.gxi && !from_mom) ? n_itasks : 0;
     if (n_m + n_i > 0) {
         const size_t lds = (size_t)K * 4 * sizeof(float);
-        const int cap = num_cu * resident((const void *)k_table_bwd, lds);
+        const auto kern = n_i > 0 ? k_table_bwd<true> : k_table_bwd<false>;
+        const int cap = num_cu * resident((const void *)kern, lds);
         const int blocks = std::max(1, std::min(cap, (n_m + n_i + 3) / 4));
-        hipLaunchKernelGGL(k_table_bwd, dim3(blocks), dim3(256), lds, s, A, jtasks, n_m, itasks,
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, s, A, jtasks, n_m, itasks,
                            n_i, queue);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

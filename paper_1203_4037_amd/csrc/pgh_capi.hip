@@ -1094,8 +1094,13 @@ int pgh_batch_table_moments(pgh_ctx *c, pgh_plan *p, const float *xi, const floa
     if (p->nj_total > 0 && (!xj || !yj || !zj || !mj))
         return fail(c, PGH_EINVAL, "NULL j-particle array");
     DeviceGuard g(c->device);
-    if (!grow_records(&p->mpartial, &p->mpartial_cap, (size_t)p->n_slots * 64 * 2))
-        return fail(c, PGH_ENOMEM, "hipMalloc(partial moments) failed");
+    const size_t n_mp = (size_t)p->n_slots * 64 * 2;
+    if (n_mp > p->mpartial_cap) {
+        // a smaller array may still be read by launches in flight
+        PGH_HIP(c, hipStreamSynchronize(c->stream));
+        if (!grow_records(&p->mpartial, &p->mpartial_cap, n_mp))
+            return fail(c, PGH_ENOMEM, "hipMalloc(partial moments) failed");
+    }
     BatchArgs a = batch_args(c, p);
     a.xi = xi, a.yi = yi, a.zi = zi;
     a.xj = xj, a.yj = yj, a.zj = zj, a.mj = mj;
