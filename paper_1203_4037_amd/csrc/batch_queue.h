@@ -109,6 +109,36 @@ __device__ __forceinline__ unsigned static_task(const BatchArgs &a, unsigned k, 
     return (unsigned)dealt_position((long long)r, a.nq, a.q_begin);
 }
 
+// The number of rounds of wave g of G in the static order over n tasks.
+__device__ __forceinline__ unsigned static_rounds(unsigned n, unsigned g, unsigned G)
+{
+    const unsigned k = n / G, rest = n % G;
+    return k + ((((k & 1u) ? G - 1u - g : g) < rest) ? 1u : 0u);
+}
+
+// Issue priority by remaining work.  A SIMD issues from its oldest ready
+// wave first, so in a launch of about one task per wave the waves that
+// arrived first finish well ahead of the last ones, which then end the
+// launch running alone at a low issue rate.  Instead each wave sets its
+// priority (s_setprio, 3 the highest) at every tile from the pair-slots it
+// still has to process (rem: the rest of its task, and in the static order
+// its later tasks at the plan's mean task size) against quarters of the
+// launch's mean per wave: the waves with the most work left issue first, and
+// the waves of a SIMD finish close together.  quarter = 0: no change.
+__device__ __forceinline__ void set_wave_prio(unsigned long long rem, unsigned long long quarter)
+{
+    if (quarter == 0) return;
+    const int lvl = (rem > quarter) + (rem > 2 * quarter) + (rem > 3 * quarter);
+    if (lvl >= 3)
+        __builtin_amdgcn_s_setprio(3);
+    else if (lvl == 2)
+        __builtin_amdgcn_s_setprio(2);
+    else if (lvl == 1)
+        __builtin_amdgcn_s_setprio(1);
+    else
+        __builtin_amdgcn_s_setprio(0);
+}
+
 // LDS operations of one wave complete in order; this keeps the compiler
 // from moving reads of a wave's tile above the writes of its other lanes.
 __device__ __forceinline__ void wave_sync()

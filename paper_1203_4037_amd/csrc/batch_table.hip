@@ -18,6 +18,9 @@
 //   * The j-tile of a task without a second list is 64 TW records (TW
 //     records per lane per tile), so short steps (P = 8) still get long
 //     tiles.
+//   * Each wave sets its issue priority from the work it has left
+//     (set_wave_prio), so the waves of a SIMD finish together instead of in
+//     the order they arrived.
 //   * The pair arithmetic (table_pair_v) keeps every uniform operand in a
 //     VGPR and finds the bin's byte offset with a shift and a mask; the
 //     table sits in static LDS (2^TB entries at most), so its base folds
@@ -79,6 +82,7 @@ k_batch_table(BatchArgs a)
     const unsigned n_t = stat ? (unsigned)a.n_tasks : ts.n_tasks;
     unsigned round = 0;
     unsigned t = stat ? static_task(a, 0, gw, G) : first_task(a, WPB, wave);
+    const unsigned rounds_g = stat ? static_rounds(n_t, gw, G) : 0u;  // the wave's static tasks
     float4 *tile = jt[wave];
 
     // j-records of tile tl of a task, TW per lane (a paired task: one of each
@@ -161,6 +165,7 @@ k_batch_table(BatchArgs a)
     const TableConsts kc = table_consts(a.c, a.smax, a.E, a.F, kEntryLog);
     const char *tab = (const char *)stab;
     __syncthreads();  // the only workgroup barrier: waves are independent after it
+    if (a.prio_quarter) __builtin_amdgcn_s_setprio(3);
 
     while (t < n_t) {
         const unsigned tn = stat ? 0u : pop_task(ts, lane);
@@ -183,7 +188,15 @@ k_batch_table(BatchArgs a)
             for (int c = 0; c < (MOM ? 7 : 1); ++c) tm[c][k] = 0.f;
         }
         const float4 *src = tile + (L.second ? 64 : 0) + L.phase;
+        // the wave's static tasks after this one (round is this task's + 1)
+        const unsigned more = stat ? rounds_g - round : 0u;
         for (int tl = 0; tl < L.ntiles; ++tl) {
+            // pair-slots left: the task's remaining records times the i-slots
+            // each serves (64 over the lanes per i-particle), and the later
+            // tasks at the mean size
+            set_wave_prio(((unsigned long long)(L.nj - tl * L.T) << (6 - (L.plog - (KI == 2 ? 1 : 0)))) +
+                              (unsigned long long)more * a.prio_task,
+                          a.prio_quarter);
             wave_sync();  // the previous tile's reads are done
             store(L);
             wave_sync();
@@ -356,6 +369,15 @@ const char *table_batch_variant_name(int v)
 
 int table_batch_default() { return 2; }
 
+// The pair-slot figures of set_wave_prio: a quarter of the plan's
+// interactions per wave of the launch, and its mean task.
+static void set_prio_args(BatchArgs &a)
+{
+    const unsigned long long inter = a.interactions > 0 ? (unsigned long long)a.interactions : 0ull;
+    a.prio_quarter = inter / (4ull * (unsigned long long)std::max(1, a.n_waves));
+    a.prio_task = inter / (unsigned long long)std::max(1, a.n_tasks);
+}
+
 hipError_t launch_table_batch_moments(const BatchArgs &a0, int num_cu, hipStream_t s)
 {
     if (a0.n_tasks <= 0) return hipSuccess;
@@ -370,6 +392,7 @@ hipError_t launch_table_batch_moments(const BatchArgs &a0, int num_cu, hipStream
     const int blocks = std::max(a.nq, std::min(cap, (a.n_tasks + kWpb - 1) / kWpb));
     a.n_waves = blocks * kWpb;
     a.static_order = (long long)a.n_tasks <= kStaticRounds * (long long)a.n_waves ? 1 : 0;
+    set_prio_args(a);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * kWpb), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.n_chunks == 0) return e;
@@ -390,6 +413,7 @@ hipError_t launch_table_batch(const BatchArgs &a0, int variant, int num_cu, hipS
     const int blocks = std::max(a.nq, std::min(cap, (a.n_tasks + v.wpb - 1) / v.wpb));
     a.n_waves = blocks * v.wpb;
     a.static_order = (long long)a.n_tasks <= kStaticRounds * (long long)a.n_waves ? 1 : 0;
+    set_prio_args(a);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * v.wpb), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.n_chunks == 0) return e;

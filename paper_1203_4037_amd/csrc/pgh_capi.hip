@@ -1020,6 +1020,7 @@ BatchArgs batch_args(pgh_ctx *c, const pgh_plan *p)
     a.n_chunks = p->n_chunks;
     a.chunks = p->chunks;
     a.eps2_all = c->eps2_all;
+    a.interactions = p->interactions;
     return a;
 }
 

@@ -83,6 +83,12 @@ struct BatchArgs {
     float *mom;
     float4 *mpartial;
     int ni_total;
+    // the plan's interactions, and the figures of set_wave_prio that a
+    // launcher derives from them: the pair-slots of a quarter of the mean
+    // work per wave of the launch and of the plan's mean task (0: wave
+    // priorities are left alone)
+    long long interactions;
+    unsigned long long prio_quarter, prio_task;
 };
 
 struct CombineArgs {

@@ -315,6 +315,7 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
     // serves sublist b mod nq) takes tasks 4b .. 4b+3 of the whole list in
     // its first round, one of similar length per SIMD.
     const size_t n = refs.size();
+    if (n > (size_t)(1 << 30)) return fail_msg(err, PGH_ERANGE, "the plan exceeds 2^30 tasks");
     int *q_begin = out.q_begin;
     const int nq = deal_layout(n, q_begin);
     std::vector<PlanRef> &dealt = out.dealt;
