@@ -150,6 +150,7 @@ __global__ void __launch_bounds__(256) k_newton_allpairs_bwd(int n, const float4
     __syncthreads();
     for (int t = 0; t < ntiles; ++t) {
         const int cur = t & 1;
+        set_tile_prio(ntiles - t, ntiles);
         if (t + 1 < ntiles) load(t + 1);
         const int cnt = min(JT, nj - t * JT);
         float ax = 0.f, ay = 0.f, az = 0.f, b = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, gg = 0.f;
@@ -247,6 +248,7 @@ __global__ void __launch_bounds__(256) k_newton_bwd_i(int ni, const float4 *__re
     __syncthreads();
     for (int t = 0; t < ntiles; ++t) {
         const int cur = t & 1;
+        set_tile_prio(ntiles - t, ntiles);
         if (t + 1 < ntiles) load(t + 1);
         const int cnt = min(JT, nj - t * JT);
         float b = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
@@ -320,6 +322,7 @@ __global__ void __launch_bounds__(256) k_newton_bwd_j(int nj, const float4 *__re
     __syncthreads();
     for (int t = 0; t < ntiles; ++t) {
         const int cur = t & 1;
+        set_tile_prio(ntiles - t, ntiles);
         if (t + 1 < ntiles) load(t + 1);
         const int cnt = min(IT, ni - t * IT);
         float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, gg = 0.f;

@@ -89,6 +89,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
 
     for (int t = 0; t < ntiles; ++t) {
         const int cur = t & 1;
+        set_tile_prio(ntiles - t, ntiles);
         if (t + 1 < ntiles) load_tile(t + 1);
         const int cnt = min(JT, nj - t * JT);
         float sx[KI], sy[KI], sz[KI], sp[KI];
