@@ -639,8 +639,10 @@ def adjoint_newton(torch, pgh, synth):
         ax, ay, az, _ = pgh.newton_allpairs(*req, 0.01, ctx)
         (ax * w[0] + ay * w[1] + az * w[2]).sum().backward()
 
-    t_f = time_steps(torch, fwd_only, 5, 2)
-    t_fb = time_steps(torch, fwd_bwd, 5, 2)
+    # host-timed: the fastest of three runs of five steps each, so that a
+    # host stall in one run does not decide the ratio
+    t_f = min(time_steps(torch, fwd_only, 5, 2) for _ in range(3))
+    t_fb = min(time_steps(torch, fwd_bwd, 5, 2) for _ in range(3))
     ctx.close()
     inter = float(n) * n
     return {"workload": "newton_allpairs_adjoint_plummer_N65536_eps0.01",
