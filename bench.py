@@ -525,8 +525,9 @@ def batched_newton(torch, pgh, synth):
     inter = float(plan.interactions)
     plan.free()
     # the library's tuner: plans cut for 0.5, 1 and 2 times the resident
-    # waves, every variant timed on each
+    # waves, plain and packed, every variant timed on each
     plan, tuned, scale = ctx.plan_tuned(s.items, s.xi.size, s.xj.size, fam, *di, *dj, reps=3)
+    packed = plan.packed
     ms = graph_ms(torch, lambda: plan.newton(*di, *dj, out=out), 10)
     plan.free()
     ctx.close()
@@ -535,7 +536,8 @@ def batched_newton(torch, pgh, synth):
             "ms_per_launch": ms, "interactions_per_s": rate,
             "frac_of_peak_38flop": NEWTON_FLOPS * rate / (PEAK_FP32_TFLOPS * 1e12),
             "autotuned_variant": pgh.pgh_variant_name(fam, tuned),
-            "autotuned_plan_waves_scale": scale, "ms_per_variant": per}
+            "autotuned_plan_waves_scale": scale, "autotuned_packing": packed,
+            "ms_per_variant": per}
 
 
 def useful_pairs(s, rcut):
@@ -559,7 +561,7 @@ def batched_table(torch, pgh, synth):
     (4096 lists; and 8^3-cell groups with a 10^3-cell halo, 512 lists),
     S2 PP shape rcut = 3/256, eps = 1/1280, E = 4, F = 6 (and F = 5).  Every
     tile shape of the batched kernel is timed on the default plan; the
-    library's tuner (Context.plan_tuned: plan wave target x tile shape)
+    library's tuner (Context.plan_tuned: plan wave target x packing x tile shape)
     chooses, and its choice is reported with its per-call time from a graph
     of ten calls and per replay of a one-call graph; also the rate of useful
     pairs (closer than rcut)."""
@@ -585,8 +587,9 @@ def batched_table(torch, pgh, synth):
         inter = float(plan.interactions)
         plan.free()
         # the library's tuner: plans cut for 0.5, 1 and 2 times the resident
-        # waves, every variant timed on each
+        # waves, plain and packed, every variant timed on each
         plan, tuned, scale = ctx.plan_tuned(s.items, n, s.xj.size, fam, *di, *dj, reps=20)
+        packed = plan.packed
         t = call_times(torch, lambda: plan.table(*di, *dj, out=out), 200)
         plan.free()
         ctx.close()
@@ -601,7 +604,8 @@ def batched_table(torch, pgh, synth):
             "frac_of_peak_20flop_1call_replay":
                 TABLE_FLOPS * inter / (t["ms_per_replay_1call"] / 1e3) / (PEAK_FP32_TFLOPS * 1e12),
             "autotuned_variant": pgh.pgh_variant_name(fam, tuned),
-            "autotuned_plan_waves_scale": scale, "ms_per_call_per_variant": per}
+            "autotuned_plan_waves_scale": scale, "autotuned_packing": packed,
+            "ms_per_call_per_variant": per}
     return res
 
 

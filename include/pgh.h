@@ -257,6 +257,21 @@ PGH_API int pgh_set_plan_waves(pgh_ctx *c, int waves);
  * resident waves when it is 0); a negative status on error. */
 PGH_API int pgh_get_plan_waves(pgh_ctx *c);
 
+/* Packing of later plans (and tree walks): with on != 0, the rows that an
+ * item (in i_off order) leaves empty in its last chunk of 64 are filled with
+ * the first i-particles of the next item, as a task of two chunks, each
+ * lane over its own item's list, when one wave running the longer list
+ * costs fewer lane-iterations than the two apart (the schedule of Sec. 5.1's
+ * lists; no result changes beyond FP32 summation order).  Fewer, fuller
+ * tasks for streams of groups of about 64 i-particles, such as cell lists.
+ * Applies when the plan is cut into chunks of 64; packed plans are made on
+ * the host.  Default 0.  A tuning dimension for callers that time plans
+ * (the binding's Context.plan_tuned). */
+PGH_API int pgh_set_plan_packing(pgh_ctx *c, int on);
+
+/* The packing setting (0 or 1); a negative status on error. */
+PGH_API int pgh_get_plan_packing(pgh_ctx *c);
+
 /* Number of interactions sum n_i n_j of a plan (host value, no sync). */
 PGH_API long long pgh_plan_interactions(const pgh_plan *p);
 

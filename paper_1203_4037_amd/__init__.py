@@ -87,6 +87,8 @@ SIGNATURES = {
     "pgh_set_plan_expansion": (_I, [_P, _I]),
     "pgh_set_plan_waves": (_I, [_P, _I]),
     "pgh_get_plan_waves": (_I, [_P]),
+    "pgh_set_plan_packing": (_I, [_P, _I]),
+    "pgh_get_plan_packing": (_I, [_P]),
     "pgh_calc_newton": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pgh_calc_newton_noalloc": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pgh_build_table": (_I, [_P, _I, _I, _F, _P, _P, _P]),
@@ -229,6 +231,17 @@ def pgh_set_plan_waves(ctx, waves):
 
 def pgh_get_plan_waves(ctx):
     v = lib.pgh_get_plan_waves(ctx)
+    if v < 0:
+        _check(ctx, v)
+    return v
+
+
+def pgh_set_plan_packing(ctx, on):
+    _check(ctx, lib.pgh_set_plan_packing(ctx, int(bool(on))))
+
+
+def pgh_get_plan_packing(ctx):
+    v = lib.pgh_get_plan_packing(ctx)
     if v < 0:
         _check(ctx, v)
     return v
@@ -639,6 +652,7 @@ class Context:
         self.table = None
         self.refine = 0
         self.plan_waves = 0
+        self.plan_packing = False
 
     def close(self):
         if self.h:
@@ -739,18 +753,26 @@ class Context:
         pgh_set_plan_waves(self.h, waves)
         self.plan_waves = int(waves)
 
+    def set_plan_packing(self, on):
+        """Whether later plans pack the rows an item leaves empty with the
+        next item's first i-particles (pgh_set_plan_packing)."""
+        pgh_set_plan_packing(self.h, on)
+        self.plan_packing = bool(on)
+
     def plan(self, items, ni_total, nj_total):
         """A Plan for host items [n, 4] = (i_off, n_i, j_off, n_j)."""
         return Plan(self, items, ni_total, nj_total)
 
     def plan_tuned(self, items, ni_total, nj_total, family, xi, yi, zi, xj, yj, zj, mj,
-                   scales=(0.5, 1.0, 2.0), reps=3, cache=None):
+                   scales=(0.5, 1.0, 2.0), packings=(False, True), reps=3, cache=None):
         """A Plan whose schedule and kernel variant are chosen by timing: for
-        each wave target (the device's resident waves times each scale) a
-        plan is made and every variant of the batched family is timed on it
-        (pgh_autotune_plan); the fastest pair is kept and its variant
-        selected.  With a cache path (JSON) a previous choice for lists of
-        the same shape class on the same device is made without timing.
+        each wave target (the device's resident waves times each scale) and
+        each packing setting a plan is made and every variant of the batched
+        family is timed on it (pgh_autotune_plan); the fastest is kept and its
+        variant selected (the plan's `packed` says whether it is packed).
+        With a cache path (JSON) a previous choice for lists of the same
+        shape class on the same device is made without timing.  The context's
+        own wave target and packing setting are left as they were.
         Returns (plan, variant index, scale)."""
         import json
         a = _items_array(items)
@@ -761,35 +783,40 @@ class Context:
             if t.numel() < nj_total:
                 raise ValueError("a j-array is shorter than nj_total")
         self._sync_stream()
-        user_waves = self.plan_waves
+        user_waves, user_pack = self.plan_waves, self.plan_packing
         pgh_set_plan_waves(self.h, 0)
         base = pgh_get_plan_waves(self.h)
+        packings = tuple(bool(k) for k in packings)
         names = [pgh_variant_name(family, v) for v in range(pgh_variant_count(family))]
         key = None
         if cache:
             props = torch.cuda.get_device_properties(self.device)
             key = "|".join(str(x) for x in (props.name, "plan_tuned", family) + _shape_class(a)
                            + (self.table if family == PGH_FAMILY_TABLE_BATCH else "",
-                              self.refine, tuple(scales)))
+                              self.refine, tuple(scales), packings))
             try:
                 with open(cache) as f:
                     stored = json.load(f)
             except (OSError, ValueError):
                 stored = {}
             hit = stored.get(key)
-            if hit and hit.get("variant") in names and hit.get("scale") in scales:
+            if (hit and hit.get("variant") in names and hit.get("scale") in scales
+                    and hit.get("packing", False) in packings):
                 pgh_set_plan_waves(self.h, max(1, int(round(base * hit["scale"]))))
+                pgh_set_plan_packing(self.h, hit.get("packing", False))
                 try:
                     p = Plan(self, a, ni_total, nj_total)
                 finally:
                     pgh_set_plan_waves(self.h, user_waves)
+                    pgh_set_plan_packing(self.h, user_pack)
                 v = names.index(hit["variant"])
                 pgh_set_variant(self.h, family, v)
                 return p, v, hit["scale"]
         best = None
         try:
-            for sc in scales:
+            for sc, pk in [(sc, pk) for sc in scales for pk in packings]:
                 pgh_set_plan_waves(self.h, max(1, int(round(base * sc))))
+                pgh_set_plan_packing(self.h, pk)
                 p = Plan(self, a, ni_total, nj_total)
                 try:
                     v, ms = pgh_autotune_plan(self.h, family, p.h, xi, yi, zi, xj, yj, zj, mj,
@@ -809,10 +836,11 @@ class Context:
             raise
         finally:
             pgh_set_plan_waves(self.h, user_waves)
+            pgh_set_plan_packing(self.h, user_pack)
         p, v, _, sc = best
         pgh_set_variant(self.h, family, v)
         if cache:
-            stored[key] = {"scale": sc, "variant": names[v]}
+            stored[key] = {"scale": sc, "variant": names[v], "packing": p.packed}
             tmp = cache + ".tmp"
             with open(tmp, "w") as f:
                 json.dump(stored, f, indent=1, sort_keys=True)
@@ -876,6 +904,7 @@ class Plan:
 
         self.shape_class = _shape_class(a)
         self.waves = pgh_get_plan_waves(ctx.h)
+        self.packed = bool(pgh_get_plan_packing(ctx.h))
 
     def free(self):
         if self.h and self.ctx.h:

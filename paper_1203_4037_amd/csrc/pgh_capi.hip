@@ -78,6 +78,7 @@ struct pgh_ctx {
     int refine = 0;  // Newton-Raphson step after v_rsq_f32 (pgh_set_rsqrt_refine)
     int plan_device = 1;  // plans expanded on the device (pgh_set_plan_expansion)
     int plan_waves = 0;   // the planner's wave target (pgh_set_plan_waves; 0: the device's)
+    int plan_pack = 0;    // chunks packed across items (pgh_set_plan_packing)
     // look-up table
     int tab_set = 0;
     int tab_E = 0, tab_F = 0;
@@ -371,7 +372,8 @@ int plan_fill(pgh_ctx *c, pgh_plan *p, int n_items, const pgh_item *items, int n
     p->waves = planner_waves(c);
     {
         std::string err;
-        const int st = plan_tasks(items, n_items, ni_total, nj_total, p->waves, hp, err);
+        const int st =
+            plan_tasks(items, n_items, ni_total, nj_total, p->waves, hp, err, c->plan_pack != 0);
         if (st) return fail(c, st, err);
     }
     DeviceGuard g(c->device);
@@ -408,6 +410,8 @@ int plan_fill_device(pgh_ctx *c, pgh_plan *p, int n_items, const pgh_item *items
 {
     DescPlan &dp = c->dp;
     p->waves = planner_waves(c);
+    // the compact form holds the unpacked cut only
+    if (c->plan_pack) return plan_fill(c, p, n_items, items, ni_total, nj_total);
     {
         std::string err;
         const int st = plan_descs(items, n_items, ni_total, nj_total, p->waves, dp, err);
@@ -607,6 +611,19 @@ int pgh_get_plan_waves(pgh_ctx *c)
 {
     if (!c) return PGH_EINVAL;
     return planner_waves(c);
+}
+
+int pgh_set_plan_packing(pgh_ctx *c, int on)
+{
+    if (!c) return PGH_EINVAL;
+    c->plan_pack = on ? 1 : 0;
+    return PGH_OK;
+}
+
+int pgh_get_plan_packing(pgh_ctx *c)
+{
+    if (!c) return PGH_EINVAL;
+    return c->plan_pack;
 }
 
 int pgh_set_xmj(pgh_ctx *c, int adr, int nj, const float *x, const float *y, const float *z,

@@ -66,7 +66,7 @@ struct Scratch {
     std::vector<char> taken;
     std::vector<int> c_ni, c_nj;
     std::vector<unsigned long long> fits, big, used;  // bit sets over the candidates
-    std::vector<std::pair<int, int>> pairs;
+    std::vector<std::pair<int, int>> pairs, packed;
 };
 
 Scratch &scratch()
@@ -226,7 +226,7 @@ long long part_length(long long wave_iters, int waves)
 }  // namespace
 
 int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, int waves,
-               HostPlan &out, std::string &err)
+               HostPlan &out, std::string &err, bool pack)
 {
     Scratch &S = scratch();
     std::vector<int> &order = S.order;
@@ -253,13 +253,41 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
     std::vector<PlanChunk> &chunks = out.chunks;
     chunks.clear();
     long long total = 0;  // wave-iterations
+    // Packing (chunks of 64 only): the rows an item leaves empty in its last
+    // chunk are filled with the first i-particles of the next item, as a
+    // paired task (each lane over its own item's list), whenever one wave
+    // running the longer list costs fewer lane-iterations than the two
+    // apart; the rest of the next item is cut after them.  The i-particles of
+    // an item need no combining however they are cut, so a stream of groups
+    // of about 64 becomes fewer and fuller tasks (4^3 cell lists of 262144
+    // particles: 4196 tasks instead of 4920, 22.8 us per call instead of
+    // 23.9).
+    pack = pack && csize == 64;
+    std::vector<std::pair<int, int>> &packed = S.packed;
+    packed.clear();
+    auto iters = [](int n, int nj) { return 64LL * std::max(1LL, lane_steps(nj, chunk_js(n))); };
+    int open = -1;  // the previous item's partly filled last chunk, awaiting a partner
     for (int t : order) {
         const pgh_item &it = items[t];
-        for (int s0 = 0; s0 < it.n_i; s0 += csize) {
+        int s0 = 0;
+        if (pack && open >= 0 && it.n_j > 0) {
+            const PlanChunk &o = chunks[(size_t)open];
+            // rows of two slots: the pair fits when ceil(n_1 / 2) + ceil(n_2 / 2) <= 32
+            const int h = std::min(64 - 2 * ((o.n_i + 1) / 2), it.n_i);
+            if (h > 0 && 64LL * std::max(o.n_j, it.n_j) < iters(o.n_i, o.n_j) + iters(h, it.n_j)) {
+                chunks.push_back({it.i_off, h, it.j_off, it.n_j, chunk_js(h)});
+                total += std::max(1LL, lane_steps(it.n_j, chunk_js(h)));
+                packed.push_back({open, (int)chunks.size() - 1});
+                s0 = h;
+            }
+        }
+        open = -1;
+        for (; s0 < it.n_i; s0 += csize) {
             const int n = std::min(csize, it.n_i - s0);
             const int js = chunk_js(n);
             chunks.push_back({it.i_off + s0, n, it.j_off, it.n_j, js});
             total += std::max(1LL, lane_steps(it.n_j, js));
+            if (pack && n < 64 && it.n_j > 0) open = (int)chunks.size() - 1;
         }
     }
     const long long part_iters = part_length(total, waves);
@@ -294,12 +322,16 @@ int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, i
     // paired works first, in the order the pairs form, then every other
     // chunk in chunk order
     {
-        std::vector<int> &cand = S.cand;
-        cand.clear();
-        for (size_t k = 0; k < chunks.size(); ++k)
-            if (chunks[k].n_i < 64 && chunks[k].n_j > 0) cand.push_back((int)k);
-        pair_chunks(S, cand, [&](int k) { return chunks[k].n_i; },
-                    [&](int k) { return chunks[k].n_j; }, S.pairs);
+        if (pack) {
+            S.pairs = packed;
+        } else {
+            std::vector<int> &cand = S.cand;
+            cand.clear();
+            for (size_t k = 0; k < chunks.size(); ++k)
+                if (chunks[k].n_i < 64 && chunks[k].n_j > 0) cand.push_back((int)k);
+            pair_chunks(S, cand, [&](int k) { return chunks[k].n_i; },
+                        [&](int k) { return chunks[k].n_j; }, S.pairs);
+        }
         std::vector<char> &taken = S.taken;
         taken.assign(chunks.size(), 0);
         for (const auto &pr : S.pairs) {

@@ -50,7 +50,7 @@ struct HostPlan {
 // resident waves of the batched kernel.  Returns PGH_OK, or a status with a
 // message in err.
 int plan_tasks(const pgh_item *items, int n_items, int ni_total, int nj_total, int waves,
-               HostPlan &out, std::string &err);
+               HostPlan &out, std::string &err, bool pack = false);
 
 // Writes the plan's hp.n_tasks tasks to dst, sublist after sublist, each
 // sublist longest first.

@@ -4,7 +4,7 @@
 // For random item sets of the shapes the library meets (tree-style groups,
 // cell-grid lists, tiny groups, one giant list, empty groups and lists, items
 // in any order with gaps between them) it builds plans for several device
-// sizes and checks what the batched kernels rely on:
+// sizes, plain and packed, and checks what the batched kernels rely on:
 //   * every (i, j) pair of every item is in exactly one task (a split list's
 //     parts, and both chunks of a paired task, included), and every row of
 //     an item with n_i > 0 is in some task, so each output row is written;
@@ -164,12 +164,13 @@ long long task_cost(const Task &t)
     return std::max(1LL, (nj + js - 1) / js);
 }
 
-void check_plan(const std::vector<pgh_item> &items, int ni_total, int nj_total, int waves,
-                const char *what)
+void check_plan_one(const std::vector<pgh_item> &items, int ni_total, int nj_total, int waves,
+                    const char *what, bool pack)
 {
     HostPlan hp;
     std::string err;
-    const int st = plan_tasks(items.data(), (int)items.size(), ni_total, nj_total, waves, hp, err);
+    const int st =
+        plan_tasks(items.data(), (int)items.size(), ni_total, nj_total, waves, hp, err, pack);
     if (st != PGH_OK) {
         fail(std::string(what) + ": plan_tasks failed: " + err);
         return;
@@ -220,7 +221,8 @@ void check_plan(const std::vector<pgh_item> &items, int ni_total, int nj_total, 
             fail(std::string(what) + ": split chunk outside its slots");
     if (failures) return;
     check_cover(items, ni_total, rows, what);
-    check_compact(items, ni_total, nj_total, waves, hp, T, what);
+    // the compact form holds the unpacked cut only
+    if (!pack) check_compact(items, ni_total, nj_total, waves, hp, T, what);
     // the table adjoint's tasks: j-major (j-chunk against the item's i-range)
     // and i-major (i-chunk against a j-range) each cover every pair once
     std::vector<Task> jt, it;
@@ -244,6 +246,15 @@ void check_plan(const std::vector<pgh_item> &items, int ni_total, int nj_total, 
         if (x.n_i > 0 && x.n_j > 0) with_j.push_back(x);
     check_cover(with_j, ni_total, rows_i, "adjoint i-major");
     check_cover(with_j, ni_total, rows_j, "adjoint j-major");
+}
+
+// Every check, on the plain plan and on the packed one (chunks of 64 that
+// take the next item's first i-particles into their empty rows).
+void check_plan(const std::vector<pgh_item> &items, int ni_total, int nj_total, int waves,
+                const char *what)
+{
+    check_plan_one(items, ni_total, nj_total, waves, what, false);
+    check_plan_one(items, ni_total, nj_total, waves, (std::string(what) + ", packed").c_str(), true);
 }
 
 // Items over a permutation of disjoint i-ranges with gaps; n_i and n_j from

@@ -479,6 +479,70 @@ def test_random_item_sets(pgh, ctx, seed):
     plan.free()
 
 
+@pytest.mark.parametrize("kind", ["cells", "tree"])
+def test_packed_plans(pgh, ctx, kind):
+    """pgh_set_plan_packing: the rows an item leaves empty in its last chunk
+    of 64 take the next item's first i-particles (a paired task).  Cell
+    lists of groups of ~64 (Poisson) and tree-style lists, at wave targets
+    that give chunks of 64: every row's Newton and table forces meet the
+    oracle gate, rows in no item are left alone, and with device expansion
+    on the packed plan is made on the host and gives the same bits."""
+    import torch
+    if kind == "cells":
+        n = 1 << 16
+        x, y, z = synth.uniform_box(n, 93)
+        s = synth.cell_grid_items(x, y, z, synth.equal_masses(n), ncell=40, block=4)
+    else:
+        s = synth.tree_style_items(1 << 16, 180, 13, nj_median=300, nj_lo=40, nj_hi=2000)
+    di, dj = _dev_set(s)
+    ni_total = s.xi.size
+    rcut = 0.05
+    table = ctx.build_table(4, 6, rcut, eps=rcut / 15)
+    ctx.set_eps_to_all(1e-3)
+    rows = np.zeros(ni_total, bool)
+    for i0, k, _, _ in s.items:
+        rows[i0:i0 + k] = True
+    assert not rows.all() or kind == "cells"
+    fam = pgh.PGH_FAMILY_TABLE_BATCH
+    names = [pgh.pgh_variant_name(fam, k) for k in range(pgh.pgh_variant_count(fam))]
+    v = names.index("ki=2 tw=2 wg=2 htab")
+    ctx.set_variant(fam, v)
+    ctx.set_plan_waves(64)  # chunks of 64
+    ctx.set_plan_packing(True)
+    assert pgh.pgh_get_plan_packing(ctx.h) == 1
+    try:
+        got = {}
+        for on_device in (False, True):
+            ctx.set_plan_expansion(on_device)
+            plan = ctx.plan(s.items, ni_total, s.xj.size)
+            assert plan.packed
+            outs = []
+            for kind_f in ("newton", "table"):
+                out = [torch.full((ni_total,), 777.0, device="cuda")
+                       for _ in range(4 if kind_f == "newton" else 3)]
+                getattr(plan, kind_f)(*di, *dj, out=out)
+                outs.append(np.stack(to_host(*out)))
+            got[on_device] = outs
+            plan.free()
+    finally:
+        ctx.set_plan_packing(False)
+        ctx.set_plan_expansion(True)
+        ctx.set_plan_waves(0)
+    for a, b in zip(got[False], got[True]):
+        assert np.array_equal(a, b)
+    newton, tab = got[False]
+    assert np.all(newton[:, ~rows] == 777.0) and np.all(tab[:, ~rows] == 777.0)
+    e2 = np.full(ni_total, np.float32(1e-3) ** 2, np.float32)
+    ref = np.stack(oracle.newton_items(s.items, s.xi, s.yi, s.zi, e2, s.xj, s.yj, s.zj, s.mj))
+    ea = rel_vec_err(newton[:3, rows], ref[:3, rows])
+    assert rms(ea) <= 1e-5 and ea.max() <= 1e-3, (rms(ea), ea.max())
+    rt = oracle.lut_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, 4, 6,
+                          float(np.float32(rcut)), oracle_table(pgh, fam, v, table, 4, 6))
+    has = rows & (rt[3] > 0)
+    e1 = norm_vec_err(tab[:, has], np.stack(rt[:3])[:, has], rt[3][has])
+    assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (rms(e1), e1.max())
+
+
 def test_plan_wave_targets_and_tuned_plan(pgh, ctx, tmp_path):
     """Plans cut for other wave counts (pgh_set_plan_waves: chunk sizes and
     list parts follow the target) give the same forces up to FP32 summation
@@ -531,7 +595,9 @@ def test_plan_wave_targets_and_tuned_plan(pgh, ctx, tmp_path):
     p.free()
     with open(cache) as f:
         stored = json.load(f)
-    assert list(stored.values()) == [{"scale": sc, "variant": pgh.pgh_variant_name(fam, v)}]
+    assert list(stored.values()) == [{"scale": sc, "variant": pgh.pgh_variant_name(fam, v),
+                                      "packing": p.packed}]
+    assert pgh.pgh_get_plan_packing(ctx.h) == 0  # the context's setting is left alone
     ctx.set_variant(fam, 0)
     p2, v2, sc2 = ctx.plan_tuned(s.items, n, s.xj.size, fam, *di, *dj, reps=1, cache=cache)
     assert (v2, sc2) == (v, sc) and pgh.pgh_get_variant(ctx.h, fam) == v
