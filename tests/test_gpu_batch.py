@@ -216,7 +216,10 @@ def test_cell_list_table_force(pgh, ctx, variant):
 def test_cell_list_table_config_full(pgh, ctx):
     """Full-size table workload: N = 262144 uniform in the unit periodic box,
     64^3 cells, 4^3-cell groups (4096 lists), S2 PP shape with rcut = 3/256,
-    eps = rcut/15, E = 4, F = 6.  The oracle recomputes 96 sampled lists."""
+    eps = rcut/15, E = 4, F = 6.  The oracle recomputes 96 sampled lists,
+    for every variant on the default plan and for the configurations the
+    bench's tuner picks among (plans for 0.5 and 1 times the resident waves,
+    plain and packed, with the two-wave (H, G1) variant)."""
     n = 262144
     x, y, z = synth.uniform_box(n, 103)
     m = synth.equal_masses(n)
@@ -240,13 +243,36 @@ def test_cell_list_table_config_full(pgh, ctx):
         assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (v, rms(e1), e1.max())
         assert np.all(a[:, rows][:, ~has] == 0.0)
         assert np.all(np.isfinite(a))
+    plan.free()
+    names = [pgh.pgh_variant_name(fam, k) for k in range(pgh.pgh_variant_count(fam))]
+    v = names.index("ki=2 tw=2 wg=2 htab")
+    ctx.set_variant(fam, v)
+    rt = oracle.lut_items(items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, 4, 6,
+                          float(np.float32(rcut)), oracle_table(pgh, fam, v, table, 4, 6))
+    has = rt[3][rows] > 0
+    base = pgh.pgh_get_plan_waves(ctx.h)
+    try:
+        for scale, pack in ((0.5, True), (1.0, True), (0.5, False)):
+            ctx.set_plan_waves(max(1, int(round(base * scale))))
+            ctx.set_plan_packing(pack)
+            plan = ctx.plan(s.items, n, s.xj.size)
+            a = np.stack(to_host(*plan.table(*di, *dj)))
+            plan.free()
+            e1 = norm_vec_err(a[:, rows][:, has], np.stack(rt[:3])[:, rows][:, has],
+                              rt[3][rows][has])
+            assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (scale, pack, rms(e1), e1.max())
+            assert np.all(a[:, rows][:, ~has] == 0.0) and np.all(np.isfinite(a))
+    finally:
+        ctx.set_plan_waves(0)
+        ctx.set_plan_packing(False)
 
 
 def test_tree_style_config_full(pgh, ctx):
     """Full-size batched Newton workload: 16384 lists over a Morton-sorted
     Plummer sphere of 2^22 particles, eps = 1e-3, i-groups of 32..256,
     j-lists log-normal (median 2000, clipped to [200, 20000]).  The oracle
-    recomputes 48 lists: the longest, the shortest and random ones."""
+    recomputes 48 lists: the longest, the shortest and random ones; every
+    variant on the default plan, and the last one on a packed plan."""
     s = synth.tree_style_items(1 << 22, 16384, 104)
     cost = s.items[:, 1].astype(np.int64) * s.items[:, 3]
     rng = np.random.default_rng(1)
@@ -255,6 +281,12 @@ def test_tree_style_config_full(pgh, ctx):
     for v in range(pgh.pgh_variant_count(pgh.PGH_FAMILY_NEWTON_BATCH)):
         ctx.set_variant(pgh.PGH_FAMILY_NEWTON_BATCH, v)
         _newton_case(pgh, ctx, s, 1e-3, sample_items=pick)
+    # a packed plan (a tuning choice of the bench's tuner)
+    ctx.set_plan_packing(True)
+    try:
+        _newton_case(pgh, ctx, s, 1e-3, sample_items=pick)
+    finally:
+        ctx.set_plan_packing(False)
 
 
 def test_plan_autotuner(pgh, ctx):
