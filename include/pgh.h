@@ -160,7 +160,7 @@ PGH_API int pgh_calc_newton_noalloc(pgh_ctx *c, int ni, const float *xi, const f
 typedef double (*pgh_f_over_r)(double r, void *user);
 
 /* Builds the table for exponent bits E (0..6), fraction bits F (0..10),
- * E + F <= 12, and cutoff rcut > 0 from a host callback (the table setter of
+ * E + F <= 14, and cutoff rcut > 0 from a host callback (the table setter of
  * Sec. 3.6) and makes it the context's table.  Node k = 2^F bE + bF sits at
  * s_k = 2^{bE+1}(1 + bF/2^F) (the node equation of Sec. 3.4.1), i.e. at
  * r_k = rcut ((s_k - 2)/(s_max - 2))^{1/2} with s_max = 2^{2^E}(2 - 2^-F);
@@ -196,11 +196,14 @@ PGH_API double pgh_s2pp_f_over_r(double r, void *user);
  * the first node; p must vanish at rcut: the last node is set to 0), nodes
  * P0_k = fl32(p(r_k)) and chords P1_k as for the force table.  table_out:
  * NULL or host float[2 * 2^(E+F)].  PGH_ESTATE before a force table is set;
- * setting a new force table discards the potential table.  Synchronous. */
+ * PGH_ERANGE when the force table has E + F > 13 (the two tables share the
+ * kernels' LDS); setting a new force table discards the potential table.
+ * Synchronous. */
 PGH_API int pgh_build_pot_table(pgh_ctx *c, pgh_f_over_r pot, void *user, float *table_out);
 
 /* The potential table from a device array of 2 * 2^(E+F) floats (P0_0,
- * P1_0, P0_1, ...), on the current force table's bins. */
+ * P1_0, P0_1, ...), on the current force table's bins; the same states and
+ * the same E + F <= 13 as pgh_build_pot_table. */
 PGH_API int pgh_set_pot_table(pgh_ctx *c, const float *table);
 
 /* Table-force accelerations of ni i-particles from the nj = pgh_set_n
@@ -341,7 +344,9 @@ PGH_API int pgh_newton_ij_bwd(pgh_ctx *c, int ni, const float *xi, const float *
  * (PGH_EINVAL otherwise).  The sums use float atomics, so their order (and
  * last bits) may vary from call to call.  The first call on a plan builds
  * the plan's adjoint task lists (allocates, uploads and waits for the
- * stream); later calls allocate nothing and may be captured in a graph. */
+ * stream); later calls allocate nothing and may be captured in a graph.
+ * PGH_ERANGE when the force table has E + F > 13 (the LDS holds the table
+ * and its gradient sums). */
 PGH_API int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi,
                                 const float *zi, const float *xj, const float *yj,
                                 const float *zj, const float *mj, const float *wx,
@@ -361,7 +366,8 @@ PGH_API int pgh_batch_table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, 
  * a second time.  One i-particle per lane and the paper's (G0, G1) form
  * whatever the selected variant.  The first call on a plan with split lists
  * allocates the plan's partial moments (and waits); later calls allocate
- * nothing.  PGH_ESTATE without a force table. */
+ * nothing.  PGH_ESTATE without a force table; PGH_ERANGE for one with
+ * E + F > 13, as for the adjoint. */
 PGH_API int pgh_batch_table_moments(pgh_ctx *c, pgh_plan *p, const float *xi, const float *yi,
                                     const float *zi, const float *xj, const float *yj,
                                     const float *zj, const float *mj, float *ax, float *ay,

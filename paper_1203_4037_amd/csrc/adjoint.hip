@@ -834,6 +834,7 @@ hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int
     if (n_m + n_i > 0) {
         const size_t lds = (size_t)K * 4 * sizeof(float);
         const auto kern = n_i > 0 ? k_table_bwd<true> : k_table_bwd<false>;
+        if ((e = allow_dynamic_lds((const void *)kern, lds)) != hipSuccess) return e;
         const int cap = num_cu * resident((const void *)kern, lds);
         const int blocks = std::max(1, std::min(cap, (n_m + n_i + 3) / 4));
         hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, s, A, jtasks, n_m, itasks,

@@ -306,20 +306,33 @@ k_batch_table(BatchArgs a)
 
 using TableKernel = void (*)(BatchArgs);
 
+// A kernel of a variant for a table of 2^tb nodes, and its waves per
+// workgroup: tables of more than 2^12 nodes (128 KiB of LDS at 2^14, or
+// 2^13 with the potential) leave room for one workgroup per CU of at most 8
+// waves, so the 16-wave variants run 8-wave workgroups there.
+struct TableKernelPick {
+    TableKernel k;
+    int wpb;
+};
+
 template <int KI, int TW, bool HT, int WPB, bool PF = false>
-TableKernel pick(int tb, bool phi)
+TableKernelPick pick(int tb, bool phi)
 {
     if (tb <= 10)
-        return phi ? k_batch_table<KI, TW, 10, HT, true, WPB, PF>
-                   : k_batch_table<KI, TW, 10, HT, false, WPB, PF>;
-    return phi ? k_batch_table<KI, TW, 12, HT, true, WPB, PF>
-               : k_batch_table<KI, TW, 12, HT, false, WPB, PF>;
+        return {phi ? k_batch_table<KI, TW, 10, HT, true, WPB, PF>
+                    : k_batch_table<KI, TW, 10, HT, false, WPB, PF>, WPB};
+    if (tb <= 12)
+        return {phi ? k_batch_table<KI, TW, 12, HT, true, WPB, PF>
+                    : k_batch_table<KI, TW, 12, HT, false, WPB, PF>, WPB};
+    constexpr int W = WPB > 8 ? 8 : WPB;
+    return {phi ? k_batch_table<KI, TW, 13, HT, true, W, PF>
+                : k_batch_table<KI, TW, 14, HT, false, W, PF>, W};
 }
 
 struct TableBatchVariant {
     const char *name;
-    int wpb;  // waves per workgroup
-    TableKernel (*pick)(int tb, bool phi);
+    int wpb;  // waves per workgroup (tables of at most 2^12 nodes)
+    TableKernelPick (*pick)(int tb, bool phi);
 };
 
 // The tile shapes the autotuner chooses among: i-particles per lane (KI),
@@ -386,9 +399,10 @@ hipError_t launch_table_batch_moments(const BatchArgs &a0, int num_cu, hipStream
     // (16.3 us against 18.1 us with four-wave workgroups on 8^3 cell lists
     // of 65536 particles)
     constexpr int kWpb = 2;
-    const TableKernel k = a0.E + a0.F <= 10
-                              ? k_batch_table<1, 2, 10, false, false, kWpb, false, true>
-                              : k_batch_table<1, 2, 12, false, false, kWpb, false, true>;
+    const int tb = a0.E + a0.F;
+    const TableKernel k = tb <= 10   ? k_batch_table<1, 2, 10, false, false, kWpb, false, true>
+                          : tb <= 12 ? k_batch_table<1, 2, 12, false, false, kWpb, false, true>
+                                     : k_batch_table<1, 2, 13, false, false, kWpb, false, true>;
     BatchArgs a = a0;
     a.phi = nullptr;
     a.ptable = nullptr;
@@ -408,17 +422,18 @@ hipError_t launch_table_batch(const BatchArgs &a0, int variant, int num_cu, hipS
     if (a0.n_tasks <= 0) return hipSuccess;
     if (variant < 0 || variant >= kNumTableBatchVariants) variant = table_batch_default();
     const bool phi = a0.phi && a0.ptable;
-    const TableBatchVariant &v = kTableBatchVariants[variant];
-    const TableKernel k = v.pick(a0.E + a0.F, phi);
+    const TableKernelPick pk = kTableBatchVariants[variant].pick(a0.E + a0.F, phi);
+    const TableKernel k = pk.k;
+    const int wpb = pk.wpb;
     BatchArgs a = a0;
     // one resident wave of workgroups, or fewer when there are fewer tasks
     // than waves; at least one workgroup per task sublist
-    const int cap = num_cu * resident_blocks(k, v.wpb);
-    const int blocks = std::max(a.nq, std::min(cap, (a.n_tasks + v.wpb - 1) / v.wpb));
-    a.n_waves = blocks * v.wpb;
+    const int cap = num_cu * resident_blocks(k, wpb);
+    const int blocks = std::max(a.nq, std::min(cap, (a.n_tasks + wpb - 1) / wpb));
+    a.n_waves = blocks * wpb;
     a.static_order = (long long)a.n_tasks <= kStaticRounds * (long long)a.n_waves ? 1 : 0;
     set_prio_args(a);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * v.wpb), 0, s, a);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * wpb), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.n_chunks == 0) return e;
     return launch_combine(a, phi, s);

@@ -1,5 +1,8 @@
 // Small kernels around the force path: the self-term correction of raw
 // potentials (Sec. 4.1).
+#include <map>
+#include <mutex>
+
 #include "pgh_internal.h"
 
 namespace pgh {
@@ -28,6 +31,20 @@ hipError_t launch_self_potential(int n, const float *m, const float *eps2i, floa
     hipLaunchKernelGGL(k_self_potential, dim3((n + 255) / 256), dim3(256), 0, s, n, m, eps2i,
                        eps2_all, phi);
     return hipGetLastError();
+}
+
+hipError_t allow_dynamic_lds(const void *kernel, size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    static std::mutex mu;
+    static std::map<const void *, size_t> allowed;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &have = allowed[kernel];
+    if (bytes <= have) return hipSuccess;
+    const hipError_t e =
+        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) have = bytes;
+    return e;
 }
 
 }  // namespace pgh

@@ -13,7 +13,7 @@
 //   (G0, G1) = T[k], one ds_read_b64 from the LDS copy of the table
 //   g = G0 + G1 (s - s_k)                                sub, fma
 //   a += (m g) d                                         mul, 3 fma
-// The table (2^(E+F) (G0, G1) pairs, at most 32 KiB) is copied into LDS once
+// The table (2^(E+F) (G0, G1) pairs, at most 128 KiB) is copied into LDS once
 // per workgroup; j-particles stream through LDS tiles exactly as in the
 // Newton kernel.  Pairs beyond the cutoff clamp to s_max, whose node is the
 // last one, where G0 = G1 = 0, so they add exactly zero.
@@ -197,8 +197,11 @@ hipError_t launch_table_allpairs(const TableArgs &a0, int variant, int S, hipStr
     const dim3 grid((a.ni + per_block - 1) / per_block, S);
     const bool phi = a.phi && a.ptable;
     const size_t lds = (phi ? sizeof(float4) : sizeof(float2)) << (a.E + a.F);
-    hipLaunchKernelGGL(phi ? v.fn_phi : v.fn, grid, dim3(256), lds, s, a);
-    hipError_t e = hipGetLastError();
+    const auto kern = phi ? v.fn_phi : v.fn;
+    hipError_t e = allow_dynamic_lds((const void *)kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, a);
+    e = hipGetLastError();
     if (e != hipSuccess || S == 1) return e;
     return launch_combine_split(a.ni, S, a.part, a0.ax, a0.ay, a0.az, phi ? a0.phi : nullptr, s);
 }

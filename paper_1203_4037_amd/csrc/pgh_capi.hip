@@ -84,7 +84,7 @@ struct pgh_ctx {
     int tab_E = 0, tab_F = 0;
     float tab_rcut = 0.f;
     float2 *tab = nullptr;  // device, 2^kMaxTableBits entries
-    float *gcopy = nullptr;  // device, kGradCopies x 2^(kMaxTableBits+1): table-adjoint scratch
+    float *gcopy = nullptr;  // device, kGradCopies x 2^(kMaxAdjTableBits+1): table-adjoint scratch
     float2 *ptab = nullptr;  // device, potential table on the force table's bins
     int pot_set = 0;         // ptab matches the current force table
     int variant[4] = {-1, -1, -1, -1};
@@ -170,7 +170,7 @@ int check_table_shape(pgh_ctx *c, int E, int F, float rcut)
 {
     if (E < 0 || E > 6) return fail(c, PGH_ERANGE, "E must be in [0, 6]");
     if (F < 0 || F > 10) return fail(c, PGH_ERANGE, "F must be in [0, 10]");
-    if (E + F > kMaxTableBits) return fail(c, PGH_ERANGE, "E + F must be <= 12");
+    if (E + F > kMaxTableBits) return fail(c, PGH_ERANGE, "E + F must be <= 14");
     if (!(rcut > 0.f) || !std::isfinite(rcut)) return fail(c, PGH_ERANGE, "rcut must be > 0");
     return PGH_OK;
 }
@@ -511,8 +511,8 @@ int pgh_open(pgh_ctx **out, int device, void *hip_stream)
     (void)resolve_scratch(device);
     e = hipMalloc((void **)&c->tab, sizeof(float2) << kMaxTableBits);
     if (e == hipSuccess)
-        e = hipMalloc((void **)&c->gcopy, (sizeof(float2) << kMaxTableBits) * kGradCopies);
-    if (e == hipSuccess) e = hipMalloc((void **)&c->ptab, sizeof(float2) << kMaxTableBits);
+        e = hipMalloc((void **)&c->gcopy, (sizeof(float2) << kMaxAdjTableBits) * kGradCopies);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->ptab, sizeof(float2) << kMaxPotTableBits);
     if (e != hipSuccess) {
         g_open_error = std::string("hipMalloc(table): ") + hipGetErrorString(e);
         (void)hipFree(c->tab);
@@ -523,7 +523,7 @@ int pgh_open(pgh_ctx **out, int device, void *hip_stream)
     }
     // the table adjoint's gradient copies start at zero and are put back to
     // zero by the kernel that sums them (k_table_bwd_tail)
-    if (hipMemsetAsync(c->gcopy, 0, (sizeof(float2) << kMaxTableBits) * kGradCopies,
+    if (hipMemsetAsync(c->gcopy, 0, (sizeof(float2) << kMaxAdjTableBits) * kGradCopies,
                        c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         g_open_error = "clearing the table-gradient scratch failed";
@@ -818,6 +818,8 @@ int pgh_build_pot_table(pgh_ctx *c, pgh_f_over_r pot, void *user, float *table_o
     if (!c) return PGH_EINVAL;
     if (!pot) return fail(c, PGH_EINVAL, "NULL callback");
     if (!c->tab_set) return fail(c, PGH_ESTATE, "set the force table first");
+    if (c->tab_E + c->tab_F > kMaxPotTableBits)
+        return fail(c, PGH_ERANGE, "a potential table needs E + F <= 13");
     std::vector<float> t(2u << (c->tab_E + c->tab_F));
     // the same nodes and chords as the force table, from p(r) instead of f/r
     int st = pgh_table_compute(c->tab_E, c->tab_F, c->tab_rcut, pot, user, t.data());
@@ -836,6 +838,8 @@ int pgh_set_pot_table(pgh_ctx *c, const float *table)
     if (!c) return PGH_EINVAL;
     if (!table) return fail(c, PGH_EINVAL, "NULL table");
     if (!c->tab_set) return fail(c, PGH_ESTATE, "set the force table first");
+    if (c->tab_E + c->tab_F > kMaxPotTableBits)
+        return fail(c, PGH_ERANGE, "a potential table needs E + F <= 13");
     DeviceGuard g(c->device);
     PGH_HIP(c, hipMemcpyAsync(c->ptab, table, sizeof(float2) << (c->tab_E + c->tab_F),
                               hipMemcpyDeviceToDevice, c->stream));
@@ -1106,6 +1110,8 @@ int pgh_batch_table_moments(pgh_ctx *c, pgh_plan *p, const float *xi, const floa
     int st = check_plan(c, p);
     if (st) return st;
     if (!c->tab_set) return fail(c, PGH_ESTATE, "no force table set");
+    if (c->tab_E + c->tab_F > kMaxAdjTableBits)
+        return fail(c, PGH_ERANGE, "the table adjoint needs E + F <= 13");
     if (p->n_tasks == 0) return PGH_OK;
     if (!xi || !yi || !zi || !ax || !ay || !az || !mom)
         return fail(c, PGH_EINVAL, "NULL i-particle, output or moment array");
@@ -1216,6 +1222,8 @@ int table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi, c
     int st = check_plan(c, p);
     if (st) return st;
     if (!c->tab_set) return fail(c, PGH_ESTATE, "no force table set");
+    if (c->tab_E + c->tab_F > kMaxAdjTableBits)
+        return fail(c, PGH_ERANGE, "the table adjoint needs E + F <= 13");
     if ((!gxi) != (!gyi) || (!gxi) != (!gzi) || (!gxj) != (!gyj) || (!gxj) != (!gzj))
         return fail(c, PGH_EINVAL, "position gradients come in x, y, z triples");
     if (!gtable && !gmj && !gxi && !gxj) return PGH_OK;

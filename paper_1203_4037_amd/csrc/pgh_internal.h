@@ -13,8 +13,13 @@
 
 namespace pgh {
 
-// Largest table the kernels hold in LDS: 2^12 (G0, G1) pairs = 32 KiB.
-constexpr int kMaxTableBits = 12;
+// Largest table the kernels hold in LDS: 2^14 (G0, G1) pairs = 128 KiB of
+// the 160 KiB of a gfx950 CU (one workgroup per CU at that size).  With the
+// potential table (16 bytes per node) and for the table adjoint (whose LDS
+// also holds the table-gradient sums) the limit is 2^13 nodes.
+constexpr int kMaxTableBits = 14;
+constexpr int kMaxPotTableBits = 13;
+constexpr int kMaxAdjTableBits = 13;
 
 // Arguments of the all-pairs Newton kernels.  jmem holds (x, y, z, m)
 // records; eps2i may be null (then eps2_all applies to every i).
@@ -139,6 +144,9 @@ hipError_t launch_fill_zero(int n, float *a, float *b, float *c, float *d, hipSt
 hipError_t launch_self_potential(int n, const float *m, const float *eps2i, float eps2_all,
                                  float *phi, hipStream_t s);
 hipError_t launch_table_grad_chain(int E, int F, const float *g, float *out, hipStream_t s);
+// Lets a kernel launch with `bytes` of dynamic LDS when that exceeds 64 KiB
+// (tables of 2^13 nodes and more); a no-op below.
+hipError_t allow_dynamic_lds(const void *kernel, size_t bytes);
 
 
 int newton_allpairs_variants();

@@ -72,7 +72,7 @@ def test_null_context_is_rejected(pgh):
     assert pgh.lib.pgh_close(None) == pgh.PGH_OK
 
 
-@pytest.mark.parametrize("E,F", [(4, 6), (4, 5), (4, 2), (0, 3), (6, 6), (2, 10)])
+@pytest.mark.parametrize("E,F", [(4, 6), (4, 5), (4, 2), (0, 3), (6, 6), (2, 10), (6, 8), (4, 10)])
 def test_host_table_builder_matches_oracle(pgh, E, F):
     eps, rcut = 1.0 / 1280, np.float32(3.0 / 256)
     t = np.zeros(2 << (E + F), np.float32)
@@ -112,7 +112,7 @@ def test_table_compute_rejects_bad_shapes(pgh):
     cb = pgh.s2pp_callback()
     params = (ctypes.c_double * 2)(1e-3, 0.1)
     user = ctypes.cast(params, ctypes.c_void_p)
-    for E, F, rc in [(7, 2, 0.1), (4, 11, 0.1), (6, 7, 0.1), (-1, 2, 0.1), (4, 6, 0.0), (4, 6, -1.0)]:
+    for E, F, rc in [(7, 2, 0.1), (4, 11, 0.1), (6, 9, 0.1), (5, 10, 0.1), (-1, 2, 0.1), (4, 6, 0.0), (4, 6, -1.0)]:
         with pytest.raises(pgh.PGHError) as e:
             pgh.pgh_table_compute(E, F, rc, cb, user, t)
         assert e.value.code == pgh.PGH_ERANGE

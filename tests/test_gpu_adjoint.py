@@ -333,6 +333,53 @@ def test_table_position_gradients_cell_lists(pgh, ctx, block):
                                 None, None, gi[0], None, None)
 
 
+def test_table_adjoint_largest_table(pgh, ctx):
+    """E + F = 13, the largest table the adjoint holds in LDS (8192 nodes and
+    their gradient sums, 128 KiB: one workgroup per CU): table, mass and
+    both position gradients, and the moments path, on cell lists (N = 16384
+    uniform in the unit periodic box, 32^3 cells, S2 table with rcut = 1/32,
+    E = 5, F = 8) against the oracle."""
+    import torch
+    n = 16384
+    x, y, z = synth.uniform_box(n, 46)
+    m = synth.equal_masses(n)
+    rcut, eps, E, F = 1.0 / 32, 1.0 / 32 / 15, 5, 8
+    rc = float(np.float32(rcut))
+    s = synth.cell_grid_items(x, y, z, m, ncell=32, block=4)
+    table = ctx.build_table(E, F, rcut, eps=eps)
+    w = synth.weights(n, 47)
+    plan = ctx.plan(s.items, n, s.xj.size)
+    di = to_dev(s.xi, s.yi, s.zi, *w)
+    dj = to_dev(s.xj, s.yj, s.zj, s.mj)
+    r = oracle.lut_bwd_pos_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, *w, E, F,
+                                 rc, table, scales=True)
+    rt, rm, at, am = oracle.lut_bwd_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, *w,
+                                          E, F, rc, table, scales=True)
+    gi = [torch.full((n,), 7.0, device="cuda") for _ in range(3)]
+    gj = [torch.full((s.xj.size,), 7.0, device="cuda") for _ in range(3)]
+    gt = torch.empty(table.size, device="cuda")
+    gm = torch.empty(s.xj.size, device="cuda")
+    pgh.pgh_batch_table_bwd(ctx.h, plan.h, di[0], di[1], di[2], *dj, di[3], di[4], di[5],
+                            gt, gm, *gi, *gj)
+    _gate(np.stack(to_host(*gi)), np.stack(r[0:3]), r[6], "gxi")
+    _gate(np.stack(to_host(*gj)), np.stack(r[3:6]), r[7], "gxj")
+    _table_gate(to_host(gt)[0], rt, at, E, F, "gtable")
+    _gate(to_host(gm)[0], rm, am, "gmj")
+    # the moments path: its forward meets the force gate, its i-side
+    # gradient the adjoint's
+    out = [torch.empty(n, device="cuda") for _ in range(3)]
+    mom = torch.empty(7 * n, device="cuda")
+    pgh.pgh_batch_table_moments(ctx.h, plan.h, *di[:3], *dj, *out, mom)
+    ra = oracle.lut_items(s.items, s.xi, s.yi, s.zi, s.xj, s.yj, s.zj, s.mj, E, F, rc, table)
+    e1 = norm_vec_err(np.stack(to_host(*out)), np.stack(ra[:3]), ra[3])
+    assert rms(e1) <= 1e-5 and e1.max() <= 1e-3, (rms(e1), e1.max())
+    gi2 = [torch.full((n,), 7.0, device="cuda") for _ in range(3)]
+    pgh.pgh_batch_table_bwd_moments(ctx.h, plan.h, *di[:3], *dj, *di[3:], mom, None, None,
+                                    *gi2, None, None, None)
+    _gate(np.stack(to_host(*gi2)), np.stack(r[0:3]), r[6], "gxi (moments)")
+    plan.free()
+
+
 def test_table_adjoint_graph_replays(pgh, ctx):
     """The table adjoint (zeroing prologue, persistent kernel, summing kernel)
     captured in a graph and replayed several times with eager work in

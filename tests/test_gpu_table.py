@@ -323,9 +323,10 @@ def test_potential_table_state_errors(pgh, ctx):
     assert e.value.code == pgh.PGH_ESTATE
 
 
-@pytest.mark.parametrize("E,F", [(6, 6), (4, 8)])
+@pytest.mark.parametrize("E,F", [(6, 6), (4, 8), (6, 7), (3, 10)])
 def test_largest_tables_with_potential(pgh, ctx, E, F):
-    """E + F = 12 (4096 nodes, 64 KiB of force and potential table in LDS),
+    """E + F = 12 (4096 nodes, 64 KiB of force and potential table in LDS)
+    and 13, the largest with the potential (128 KiB, one workgroup per CU),
     all-pairs and batched, both table forms, against the oracle."""
     n = 4096
     rcut, eps = 0.2, 0.01
@@ -366,3 +367,61 @@ def test_largest_tables_with_potential(pgh, ctx, E, F):
         assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
         ep = np.abs(to_host(phi)[0] - rp)[sp > 0] / sp[sp > 0]
         assert rms(ep) <= 1e-5 and ep.max() <= 1e-3, (v, rms(ep), ep.max())
+
+
+@pytest.mark.parametrize("E,F", [(6, 8), (4, 10)])
+def test_largest_force_tables(pgh, ctx, E, F):
+    """E + F = 14 (16384 nodes, 128 KiB of force table in LDS): every
+    all-pairs and batched variant against the oracle on the same table; a
+    potential table and the table adjoint are refused there (PGH_ERANGE),
+    and a table of 2^15 nodes is refused outright."""
+    import torch
+    n = 4096
+    rcut, eps = 0.2, 0.01
+    x, y, z = synth.uniform_box(n, 74 + E, box=0.4)
+    m = synth.equal_masses(n)
+    rc = float(np.float32(rcut))
+    ft = ctx.build_table(E, F, rcut, f_over_r=lambda r: oracle.shape_h(oracle.SHAPE_SOFT_CUT, r, eps, rc))
+    _same_table(ft, oracle.table_build(E, F, rc, oracle.SHAPE_SOFT_CUT, eps), E, F)
+    d = to_dev(x, y, z, m)
+    ctx.set_j(*d)
+    items = np.array([[0, n // 2, 0, n], [n // 2, n // 2, n // 4, n // 2]], np.int32)
+    plan = ctx.plan(items, n, n)
+    fam = pgh.PGH_FAMILY_TABLE_BATCH
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        ra = oracle.lut_items(items, x, y, z, x, y, z, m, E, F, rc,
+                              oracle_table(pgh, fam, v, ft, E, F))
+        a = np.stack(to_host(*plan.table(*d[:3], *d)))
+        has = ra[3] > 0
+        e = norm_vec_err(a[:, has], np.stack(ra[:3])[:, has], ra[3][has])
+        assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
+    whole = np.array([[0, n, 0, n]], np.int32)
+    fam = pgh.PGH_FAMILY_TABLE_ALLPAIRS
+    for v in range(pgh.pgh_variant_count(fam)):
+        ctx.set_variant(fam, v)
+        ra = oracle.lut_items(whole, x, y, z, x, y, z, m, E, F, rc,
+                              oracle_table(pgh, fam, v, ft, E, F))
+        a = np.stack(to_host(*ctx.table_force(d[0], d[1], d[2])))
+        has = ra[3] > 0
+        e = norm_vec_err(a[:, has], np.stack(ra[:3])[:, has], ra[3][has])
+        assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
+    # what needs more LDS than a CU has is refused before any launch
+    with pytest.raises(pgh.PGHError) as er:
+        ctx.build_pot_table(lambda r: 1.0 - r / rc)
+    assert er.value.code == pgh.PGH_ERANGE
+    pt = torch.zeros(2 << (E + F), device="cuda")
+    assert pgh.lib.pgh_set_pot_table(ctx.h, pt.data_ptr()) == pgh.PGH_ERANGE
+    w = to_dev(*synth.weights(n, 75))
+    gt = torch.empty(ft.size, device="cuda")
+    with pytest.raises(pgh.PGHError) as er:
+        pgh.pgh_batch_table_bwd(ctx.h, plan.h, *d[:3], *d, *w, gt, None)
+    assert er.value.code == pgh.PGH_ERANGE
+    out = [torch.empty(n, device="cuda") for _ in range(3)]
+    mom = torch.empty(7 * n, device="cuda")
+    with pytest.raises(pgh.PGHError) as er:
+        pgh.pgh_batch_table_moments(ctx.h, plan.h, *d[:3], *d, *out, mom)
+    assert er.value.code == pgh.PGH_ERANGE
+    plan.free()
+    big = torch.zeros(4 << 14, device="cuda")
+    assert pgh.lib.pgh_set_table(ctx.h, 6, 9, rcut, big.data_ptr()) == pgh.PGH_ERANGE
