@@ -370,7 +370,8 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The table-force adjoint over the lists of a plan.  Task kinds (one queue):
+// The table-force adjoint over the lists of a plan.  Task kinds (one index
+// space):
 //
 // [0, n_m): j-major tasks, a chunk of <= 64 j-entries of a list (one per
 // lane; chunks of <= 32 or <= 16 run 2 or 4 lanes per entry on alternate
@@ -391,31 +392,40 @@ __device__ __forceinline__ void wave_sync()
 //   dL/dr_i   -= m_j [ g w_i + 2c G1_k (w_i . d) d ]
 // summed per lane and added to gxi with one atomic per i and task.
 //
-// Tasks of each kind are sorted longest first; the first round is taken by
-// index, later ones from the counter, which the launch's last pop puts back
-// to zero.
+// Tasks of each kind are sorted longest first.  With at most four per wave
+// every wave follows a static order; with more, the waves of a workgroup
+// share its own static sequence of tasks through an LDS counter, so they
+// balance among themselves without a chip-wide atomic per task.  (One global
+// counter for all tasks serialised the pops: on 4^3-cell lists of 262144
+// particles with E = 4, F = 7 the whole adjoint took 290 us, its passes run
+// alone 160 us; 103 us with the workgroup counters.)
 // IMAJ: the i-major tasks are compiled in (the j-major-only instantiation
-// holds fewer registers, so more waves fit).
-template <bool IMAJ>
-__global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *jtasks, int n_m,
-                                                   const Task *itasks, int n_i, unsigned *queue)
+// holds fewer registers, so more waves fit).  W waves per workgroup.
+template <bool IMAJ, int W>
+__global__ void __launch_bounds__(64 * W) k_table_bwd(TableBwdArgs A, const Task *jtasks,
+                                                      int n_m, const Task *itasks, int n_i)
 {
-    extern __shared__ float dyn[];
+    // declared as float4 so that the dynamic region, placed after the
+    // static arrays, starts 16-byte aligned for the 8-byte table reads
+    extern __shared__ float4 dyn4[];
+    float *dyn = (float *)dyn4;
     const BatchArgs &a = A.b;
     const int K = 1 << (a.E + a.F);
     float2 *stab = (float2 *)dyn;  // K (G0, G1)
     float *gt = dyn + 2 * K;       // 2K gradient accumulators
     // per wave: 64 i-records (x, y, z, wx) or j-records, and the (wy, wz)
     // of the i-records
-    __shared__ float4 buf[4][64];
-    __shared__ float2 wbuf[4][64];
+    __shared__ float4 buf[W][64];
+    __shared__ float2 wbuf[W][64];
+    __shared__ unsigned wg_next;  // the next position in the workgroup's sequence
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) wg_next = W;
     const bool want_tab = A.gtable != nullptr, want_m = A.gmj != nullptr;
     const bool want_xj = A.gxj != nullptr;
     const bool need_g = want_m || want_xj || n_i > 0;
     if (need_g) table_to_lds<false>(stab, a.table, K, 0u);
     if (want_tab)
-        for (int k = threadIdx.x; k < K; k += 256) {
+        for (int k = threadIdx.x; k < K; k += 64 * W) {
             gt[2 * k] = 0.f;
             gt[2 * k + 1] = 0.f;
         }
@@ -432,28 +442,35 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
     float last0 = 0.f;  // clamped pairs: dL/dG0 of the last node
 
     const unsigned n_all = (unsigned)(n_m + n_i);
-    const unsigned n_waves = gridDim.x * 4;
-    // At most four tasks per wave: a static order (round k of wave g takes
-    // task k G + g, or k G + G - 1 - g for odd k, pairing long tasks with
-    // short ones) with no atomics; else the first round by index and later
-    // ones from the counter.
+    const unsigned n_waves = gridDim.x * W;
+    // The static orders zig-zag (round k of member g of G takes task
+    // k G + g, or k G + G - 1 - g for odd k), pairing long tasks with short
+    // ones.  At most four tasks per wave: the waves are the members, with no
+    // atomics; else the workgroups are, and the waves of one take the rounds
+    // of its sequence in turn from wg_next (rounds 0 .. W-1 by wave index).
+    // Either sequence rises with the round, so a wave stops at its first
+    // task beyond n_all.
     const bool stat = n_all <= 4u * n_waves;
-    const unsigned gw = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wave);
+    const unsigned gw = __builtin_amdgcn_readfirstlane(blockIdx.x * W + wave);
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    auto wg_task = [&](unsigned k) {
+        const unsigned long long r =
+            (unsigned long long)k * nb + ((k & 1u) ? nb - 1u - b : b);
+        return r < n_all ? (unsigned)r : n_all;
+    };
     unsigned round = 0;
-    for (unsigned t = gw; t < n_all;) {
+    // (read as uniform: the compiler cannot tell that the wave index is, and
+    // would otherwise keep the task index and its decoding in vector registers)
+    for (unsigned t = __builtin_amdgcn_readfirstlane(stat ? gw : wg_task((unsigned)wave));
+         t < n_all;) {
         unsigned tn = n_all;
         if (stat) {
             ++round;
             const unsigned long long r =
                 (unsigned long long)round * n_waves + ((round & 1u) ? n_waves - 1u - gw : gw);
             tn = r < n_all ? (unsigned)r : n_all;
-        } else if (n_all > n_waves && lane == 0) {
-            // one pop per task executed: the pop that draws n_all-1 is the
-            // launch's last and puts the counter back to zero
-            const unsigned k =
-                __hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (k == n_all - 1u) __hip_atomic_store(queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            tn = n_waves + k;
+        } else if (lane == 0) {
+            tn = wg_task(atomicAdd(&wg_next, 1u));
         }
         const bool jmajor = !IMAJ || t < (unsigned)n_m;
         // jmajor: i_off/n_i = the j-chunk, j_off/n_j = the i-range; else an
@@ -636,25 +653,24 @@ __global__ void __launch_bounds__(256) k_table_bwd(TableBwdArgs A, const Task *j
         if (lane == 0 && last0 != 0.f) atomicAdd(&gt[2 * (K - 1)], last0);
         __syncthreads();
         float *dst = A.gcopies + (size_t)(blockIdx.x % kGradCopies) * 2 * K;
-        for (int k = threadIdx.x; k < 2 * K; k += 256)
+        for (int k = threadIdx.x; k < 2 * K; k += 64 * W)
             if (gt[k] != 0.f) atomicAdd(&dst[k], gt[k]);
     }
 }
 
 // Zeroes the per-entry gradients that are added up (lists sharing
-// j-entries; the i-major pass) and the task counter ahead of k_table_bwd (a
-// kernel rather than memsets, so the sequence can be captured in a graph).
+// j-entries; the i-major pass) ahead of k_table_bwd (a kernel rather than
+// memsets, so the sequence can be captured in a graph).
 // Up to 8 arrays of the given lengths (NULL: skipped).
 struct ZeroList {
     float *p[8];
     int n[8];
 };
 
-__global__ void __launch_bounds__(256) k_table_bwd_prologue(ZeroList z, unsigned *queue)
+__global__ void __launch_bounds__(256) k_table_bwd_prologue(ZeroList z)
 {
     const int stride = gridDim.x * 256;
     const int t0 = blockIdx.x * 256 + threadIdx.x;
-    if (t0 == 0) *queue = 0u;
 #pragma unroll
     for (int q = 0; q < 8; ++q)
         if (z.p[q])
@@ -734,10 +750,11 @@ __global__ void __launch_bounds__(256) k_table_bwd_tail(BwdTail t)
     }
 }
 
-int resident(const void *k, size_t lds)
+int resident(const void *k, size_t lds, int threads = 256)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, lds) != hipSuccess || n < 1) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess || n < 1)
+        n = 1;
     return n;
 }
 
@@ -801,8 +818,7 @@ hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 
 }
 
 hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int n_jtasks,
-                                  const Task *itasks, int n_itasks, unsigned *queue, int num_cu,
-                                  hipStream_t s)
+                                  const Task *itasks, int n_itasks, int num_cu, hipStream_t s)
 {
     const int K = 1 << (A.b.E + A.b.F);
     // the i-side gradient: from the forward's moments in the tail kernel
@@ -825,20 +841,27 @@ hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int
     hipError_t e = hipSuccess;
     if (nz > 0) {
         const int zb = std::max(1, std::min(1024, (longest + 255) / 256));
-        hipLaunchKernelGGL(k_table_bwd_prologue, dim3(zb), dim3(256), 0, s, z, queue);
+        hipLaunchKernelGGL(k_table_bwd_prologue, dim3(zb), dim3(256), 0, s, z);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const bool jside = A.gtable || A.gmj || A.gxj;
     const int n_m = jside ? n_jtasks : 0;
     const int n_i = (A.gxi && !from_mom) ? n_itasks : 0;
     if (n_m + n_i > 0) {
+        // the table and its gradient sums: 16 bytes per node.  From 2^12
+        // nodes (64 KiB) on they leave room for at most two workgroups per
+        // CU, which then run 16 waves each (24 KiB of record buffers beside
+        // 128 KiB of table at 2^13 nodes) rather than 4.
         const size_t lds = (size_t)K * 4 * sizeof(float);
-        const auto kern = n_i > 0 ? k_table_bwd<true> : k_table_bwd<false>;
+        const bool wide = lds >= 65536;
+        const int W = wide ? 16 : 4;
+        const auto kern = n_i > 0 ? (wide ? k_table_bwd<true, 16> : k_table_bwd<true, 4>)
+                                  : (wide ? k_table_bwd<false, 16> : k_table_bwd<false, 4>);
         if ((e = allow_dynamic_lds((const void *)kern, lds)) != hipSuccess) return e;
-        const int cap = num_cu * resident((const void *)kern, lds);
-        const int blocks = std::max(1, std::min(cap, (n_m + n_i + 3) / 4));
-        hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, s, A, jtasks, n_m, itasks,
-                           n_i, queue);
+        const int cap = num_cu * resident((const void *)kern, lds, 64 * W);
+        const int blocks = std::max(1, std::min(cap, (n_m + n_i + W - 1) / W));
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * W), lds, s, A, jtasks, n_m, itasks,
+                           n_i);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     BwdTail t{};

@@ -307,9 +307,16 @@ k_batch_table(BatchArgs a)
 using TableKernel = void (*)(BatchArgs);
 
 // A kernel of a variant for a table of 2^tb nodes, and its waves per
-// workgroup: tables of more than 2^12 nodes (128 KiB of LDS at 2^14, or
-// 2^13 with the potential) leave room for one workgroup per CU of at most 8
-// waves, so the 16-wave variants run 8-wave workgroups there.
+// workgroup.  The table's LDS bounds the workgroups per CU, so larger tables
+// take wider workgroups whatever the variant's own width: up to 2^10 nodes
+// the variant's; up to 2^12 (32 KiB, 64 KiB with the potential) 16 waves,
+// two workgroups per CU (one with the potential); beyond (128 KiB at 2^14,
+// or at 2^13 with the potential) 12 waves, the most whose j-tiles (2176
+// bytes each) fit beside the table in the 160 KiB of a CU.  With its own two
+// waves per workgroup a variant would leave SIMDs idle there.
+constexpr int kMidWaves = 16;
+constexpr int kWideWaves = 12;
+
 struct TableKernelPick {
     TableKernel k;
     int wpb;
@@ -322,16 +329,15 @@ TableKernelPick pick(int tb, bool phi)
         return {phi ? k_batch_table<KI, TW, 10, HT, true, WPB, PF>
                     : k_batch_table<KI, TW, 10, HT, false, WPB, PF>, WPB};
     if (tb <= 12)
-        return {phi ? k_batch_table<KI, TW, 12, HT, true, WPB, PF>
-                    : k_batch_table<KI, TW, 12, HT, false, WPB, PF>, WPB};
-    constexpr int W = WPB > 8 ? 8 : WPB;
-    return {phi ? k_batch_table<KI, TW, 13, HT, true, W, PF>
-                : k_batch_table<KI, TW, 14, HT, false, W, PF>, W};
+        return {phi ? k_batch_table<KI, TW, 12, HT, true, kMidWaves, PF>
+                    : k_batch_table<KI, TW, 12, HT, false, kMidWaves, PF>, kMidWaves};
+    return {phi ? k_batch_table<KI, TW, 13, HT, true, kWideWaves, PF>
+                : k_batch_table<KI, TW, 14, HT, false, kWideWaves, PF>, kWideWaves};
 }
 
 struct TableBatchVariant {
     const char *name;
-    int wpb;  // waves per workgroup (tables of at most 2^12 nodes)
+    int wpb;  // waves per workgroup (tables of at most 2^10 nodes)
     TableKernelPick (*pick)(int tb, bool phi);
 };
 
@@ -397,21 +403,22 @@ hipError_t launch_table_batch_moments(const BatchArgs &a0, int num_cu, hipStream
     // two-wave workgroups: their LDS holds a CU to six waves per SIMD, so
     // the seven moment sums per i-particle fit in registers without spills
     // (16.3 us against 18.1 us with four-wave workgroups on 8^3 cell lists
-    // of 65536 particles)
-    constexpr int kWpb = 2;
+    // of 65536 particles); a table of 2^12 nodes or more leaves room for two
+    // workgroups per CU or one, which then run 16 waves each
     const int tb = a0.E + a0.F;
-    const TableKernel k = tb <= 10   ? k_batch_table<1, 2, 10, false, false, kWpb, false, true>
-                          : tb <= 12 ? k_batch_table<1, 2, 12, false, false, kWpb, false, true>
-                                     : k_batch_table<1, 2, 13, false, false, kWpb, false, true>;
+    const int wpb = tb <= 10 ? 2 : 16;
+    const TableKernel k = tb <= 10   ? k_batch_table<1, 2, 10, false, false, 2, false, true>
+                          : tb <= 12 ? k_batch_table<1, 2, 12, false, false, 16, false, true>
+                                     : k_batch_table<1, 2, 13, false, false, 16, false, true>;
     BatchArgs a = a0;
     a.phi = nullptr;
     a.ptable = nullptr;
-    const int cap = num_cu * resident_blocks(k, kWpb);
-    const int blocks = std::max(a.nq, std::min(cap, (a.n_tasks + kWpb - 1) / kWpb));
-    a.n_waves = blocks * kWpb;
+    const int cap = num_cu * resident_blocks(k, wpb);
+    const int blocks = std::max(a.nq, std::min(cap, (a.n_tasks + wpb - 1) / wpb));
+    a.n_waves = blocks * wpb;
     a.static_order = (long long)a.n_tasks <= kStaticRounds * (long long)a.n_waves ? 1 : 0;
     set_prio_args(a);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * kWpb), 0, s, a);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * wpb), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.n_chunks == 0) return e;
     return launch_combine(a, false, s);

@@ -26,19 +26,19 @@ namespace pgh {
 namespace {
 
 // PHI: also the potential from the second table (a.ptable, a.phi); the LDS
-// table then holds (G0, G1, P0, P1) per node.
-template <int KI, int JT, int U, bool HT, bool PHI>
-__global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
+// table then holds (G0, G1, P0, P1) per node.  NT threads per workgroup.
+template <int KI, int JT, int U, bool HT, bool PHI, int NT = 256>
+__global__ void __launch_bounds__(NT) k_table_allpairs(TableArgs a)
 {
-    static_assert(JT % 256 == 0, "tile must be a multiple of the workgroup");
-    constexpr int PER = JT / 256;
+    static_assert(JT % NT == 0, "tile must be a multiple of the workgroup");
+    constexpr int PER = JT / NT;
     extern __shared__ float4 dyn4[];
     float2 *stab = (float2 *)dyn4;  // (G0, G1) per node
     float4 *stab4 = dyn4;           // (G0, G1, P0, P1) per node, with PHI
     __shared__ float4 tile[2][JT];
 
     const int tid = threadIdx.x;
-    const int ibase = blockIdx.x * (256 * KI) + tid;
+    const int ibase = blockIdx.x * (NT * KI) + tid;
     const int K = 1 << (a.E + a.F);
     const unsigned shift = 23u - (unsigned)a.F;
     const unsigned nbits = (unsigned)(a.E + a.F);
@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
     float tx[KI], ty[KI], tz[KI], tp[KI];
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
-        int i = ibase + k * 256;
+        int i = ibase + k * NT;
         i = i < a.ni ? i : a.ni - 1;
         px[k] = a.xi[i];
         py[k] = a.yi[i];
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
     auto load_tile = [&](int t) {
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            const int j = t * JT + r * 256 + tid;
+            const int j = t * JT + r * NT + tid;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             if (j < nj) v = jm[j];
             pre[r] = v;
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
     };
     auto store_tile = [&](int buf) {
 #pragma unroll
-        for (int r = 0; r < PER; ++r) tile[buf][r * 256 + tid] = pre[r];
+        for (int r = 0; r < PER; ++r) tile[buf][r * NT + tid] = pre[r];
     };
 
     load_tile(0);
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
     }
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
-        const int i = ibase + k * 256;
+        const int i = ibase + k * NT;
         if (i < a.ni) {
             ox[i] = tx[k];
             oy[i] = ty[k];
@@ -145,14 +145,33 @@ __global__ void __launch_bounds__(256) k_table_allpairs(TableArgs a)
 
 using TableKernel = void (*)(TableArgs);
 
+// Tables of more than 32 KiB in LDS (2^13 nodes and more, or 2^12 with the
+// potential) leave room for one or two workgroups per CU, so they run
+// workgroups of 12 waves (three per SIMD) over 768-record j-tiles: 128 KiB
+// of table and 24 KiB of tiles fit the 160 KiB of a CU.  With four-wave
+// workgroups such a table left one or two waves per SIMD, too few to hide
+// the LDS latency of the table reads or to pair FP32 issue.
+constexpr int kWideNT = 768;
+constexpr size_t kWideTableBytes = 32768;
+// the j-split target of wide launches: three rounds of one workgroup on each
+// of 256 CUs
+constexpr int kWideTargetWaves = 3 * (kWideNT / 64) * 256;
+
 struct TableVariant {
     const char *name;
     int ki, jt;
-    TableKernel fn, fn_phi;  // force only; force and potential
+    TableKernel fn, fn_phi;      // force only; force and potential
+    TableKernel wide, wide_phi;  // the same with kWideNT threads and tiles
 };
 
-#define PGH_TABLE_VARIANT(name, KI, JT, U, HT) \
-    {name, KI, JT, k_table_allpairs<KI, JT, U, HT, false>, k_table_allpairs<KI, JT, U, HT, true>}
+#define PGH_TABLE_VARIANT(name, KI, JT, U, HT)                                                   \
+    {name,                                                                                     \
+     KI,                                                                                       \
+     JT,                                                                                       \
+     k_table_allpairs<KI, JT, U, HT, false>,                                                   \
+     k_table_allpairs<KI, JT, U, HT, true>,                                                    \
+     k_table_allpairs<KI, kWideNT, U, HT, false, kWideNT>,                                     \
+     k_table_allpairs<KI, kWideNT, U, HT, true, kWideNT>}
 const TableVariant kTableVariants[] = {
     PGH_TABLE_VARIANT("ki=1 jt=256 u=4", 1, 256, 4, false),
     PGH_TABLE_VARIANT("ki=2 jt=256 u=4", 2, 256, 4, false),
@@ -162,6 +181,13 @@ const TableVariant kTableVariants[] = {
 };
 #undef PGH_TABLE_VARIANT
 constexpr int kNumTableVariants = sizeof(kTableVariants) / sizeof(kTableVariants[0]);
+
+bool is_phi(const TableArgs &a) { return a.phi && a.ptable; }
+
+size_t table_lds_bytes(const TableArgs &a)
+{
+    return (is_phi(a) ? sizeof(float4) : sizeof(float2)) << (a.E + a.F);
+}
 
 }  // namespace
 
@@ -179,10 +205,12 @@ int table_allpairs_default(int ni, int nj, int num_cu)
     return waves_ki2 >= 4L * num_cu ? 1 : 0;
 }
 
-int table_allpairs_split(int ni, int nj, int variant, size_t part_cap)
+int table_allpairs_split(const TableArgs &a, int variant, size_t part_cap)
 {
     const TableVariant &v = kTableVariants[variant];
-    return split_count(ni, nj, v.ki, v.jt, kSplitTargetWaves, part_cap);
+    if (table_lds_bytes(a) > kWideTableBytes)
+        return split_count(a.ni, a.nj, v.ki, kWideNT, kWideTargetWaves, part_cap);
+    return split_count(a.ni, a.nj, v.ki, v.jt, kSplitTargetWaves, part_cap);
 }
 
 hipError_t launch_table_allpairs(const TableArgs &a0, int variant, int S, hipStream_t s)
@@ -190,17 +218,19 @@ hipError_t launch_table_allpairs(const TableArgs &a0, int variant, int S, hipStr
     if (a0.ni <= 0) return hipSuccess;
     const TableVariant &v = kTableVariants[variant];
     TableArgs a = a0;
+    const bool phi = is_phi(a);
+    const size_t lds = table_lds_bytes(a);
+    const bool wide = lds > kWideTableBytes;
+    const int nt = wide ? kWideNT : 256, jt = wide ? kWideNT : v.jt;
     S = std::max(1, S);
-    a.jchunk = (int)(((long)a.nj + (long)S * v.jt - 1) / ((long)S * v.jt) * v.jt);
+    a.jchunk = (int)(((long)a.nj + (long)S * jt - 1) / ((long)S * jt) * jt);
     S = std::max(1, (a.nj + a.jchunk - 1) / a.jchunk);
-    const int per_block = 256 * v.ki;
+    const int per_block = nt * v.ki;
     const dim3 grid((a.ni + per_block - 1) / per_block, S);
-    const bool phi = a.phi && a.ptable;
-    const size_t lds = (phi ? sizeof(float4) : sizeof(float2)) << (a.E + a.F);
-    const auto kern = phi ? v.fn_phi : v.fn;
+    const auto kern = wide ? (phi ? v.wide_phi : v.wide) : (phi ? v.fn_phi : v.fn);
     hipError_t e = allow_dynamic_lds((const void *)kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, a);
+    hipLaunchKernelGGL(kern, grid, dim3(nt), lds, s, a);
     e = hipGetLastError();
     if (e != hipSuccess || S == 1) return e;
     return launch_combine_split(a.ni, S, a.part, a0.ax, a0.ay, a0.az, phi ? a0.phi : nullptr, s);

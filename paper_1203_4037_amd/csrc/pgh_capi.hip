@@ -42,7 +42,6 @@ struct pgh_plan {
     Task *jtasks;           // device
     int n_itasks;           // i-major tasks of the table adjoint (i-side positions)
     Task *itasks;           // device
-    unsigned *jqueue;       // device, counter of the j-major tasks
     int2 *irange;           // device, the items' i-ranges (i_off, n_i) by i_off
     int n_irange;
     // the items' j-ranges (j_off, n_j) by j_off, and whether they are
@@ -182,7 +181,6 @@ void free_plan_memory(pgh_plan *p)
     (void)hipFree(p->partial);
     (void)hipFree(p->chunks);
     (void)hipFree(p->jtasks);
-    (void)hipFree(p->jqueue);
     (void)hipFree(p->itasks);
     (void)hipFree(p->irange);
     (void)hipFree(p->jrange);
@@ -288,12 +286,10 @@ bool grow_records(T **buf, size_t *cap, size_t n)
 void reset_plan(pgh_plan *p)
 {
     (void)hipFree(p->jtasks);
-    (void)hipFree(p->jqueue);
     (void)hipFree(p->itasks);
     (void)hipFree(p->irange);
     (void)hipFree(p->jrange);
     p->jtasks = p->itasks = nullptr;
-    p->jqueue = nullptr;
     p->irange = p->jrange = nullptr;
     p->n_irange = p->n_jrange = 0;
     p->j_disjoint = p->i_cover = p->j_cover = false;
@@ -865,7 +861,7 @@ int pgh_calc_table(pgh_ctx *c, int ni, const float *xi, const float *yi, const f
                 phi ? c->ptab : nullptr, phi};
     int v = c->variant[PGH_FAMILY_TABLE_ALLPAIRS];
     if (v < 0) v = table_allpairs_default(ni, c->nj, c->num_cu);
-    const int S = table_allpairs_split(ni, c->nj, v, kMaxSplitFloats);
+    const int S = table_allpairs_split(a, v, kMaxSplitFloats);
     if (S > 1) {
         int st = ensure_part(c, (size_t)S * 4 * ni);
         if (st) return st;
@@ -989,24 +985,20 @@ int build_adjoint_tasks(pgh_ctx *c, pgh_plan *p)
     long long ni_sum = 0, nj_sum = 0;
     for (const int2 &r : ir) ni_sum += r.y;
     for (const int2 &r : jr) nj_sum += r.y;
-    if (hipMalloc((void **)&p->jqueue, 2 * sizeof(unsigned)) != hipSuccess ||
-        (!jt.empty() && hipMalloc((void **)&p->jtasks, jt.size() * sizeof(Task)) != hipSuccess) ||
+    if ((!jt.empty() && hipMalloc((void **)&p->jtasks, jt.size() * sizeof(Task)) != hipSuccess) ||
         (!it_tasks.empty() &&
          hipMalloc((void **)&p->itasks, it_tasks.size() * sizeof(Task)) != hipSuccess) ||
         (!ir.empty() && hipMalloc((void **)&p->irange, ir.size() * sizeof(int2)) != hipSuccess) ||
         (!jr.empty() && hipMalloc((void **)&p->jrange, jr.size() * sizeof(int2)) != hipSuccess)) {
-        (void)hipFree(p->jqueue);
         (void)hipFree(p->jtasks);
         (void)hipFree(p->itasks);
         (void)hipFree(p->irange);
         (void)hipFree(p->jrange);
-        p->jqueue = nullptr;
         p->jtasks = p->itasks = nullptr;
         p->irange = p->jrange = nullptr;
         return fail(c, PGH_ENOMEM, "hipMalloc(adjoint tasks) failed");
     }
-    if (hipMemsetAsync(p->jqueue, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
-        (!jt.empty() && hipMemcpyAsync(p->jtasks, jt.data(), jt.size() * sizeof(Task),
+    if ((!jt.empty() && hipMemcpyAsync(p->jtasks, jt.data(), jt.size() * sizeof(Task),
                                        hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
         (!it_tasks.empty() &&
          hipMemcpyAsync(p->itasks, it_tasks.data(), it_tasks.size() * sizeof(Task),
@@ -1260,7 +1252,7 @@ int table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi, c
     A.jcover = p->j_cover ? 1 : 0;
     A.jrange = p->jrange;
     A.n_jrange = p->n_jrange;
-    PGH_HIP(c, launch_table_batch_bwd(A, p->jtasks, p->n_jtasks, p->itasks, p->n_itasks, p->jqueue,
+    PGH_HIP(c, launch_table_batch_bwd(A, p->jtasks, p->n_jtasks, p->itasks, p->n_itasks,
                                       c->num_cu, c->stream));
     return PGH_OK;
 }

@@ -159,7 +159,7 @@ hipError_t launch_newton_allpairs(const NewtonArgs &a, int variant, bool refine,
 int table_allpairs_variants();
 const char *table_allpairs_variant_name(int v);
 int table_allpairs_default(int ni, int nj, int num_cu);
-int table_allpairs_split(int ni, int nj, int variant, size_t part_cap);
+int table_allpairs_split(const TableArgs &a, int variant, size_t part_cap);
 hipError_t launch_table_allpairs(const TableArgs &a, int variant, int S, hipStream_t s);
 
 int batch_resident_waves(int num_cu);  // waves of the persistent grid
@@ -212,11 +212,10 @@ hipError_t launch_newton_bwd_i(int ni, const float4 *irec, int nj, const float4 
 hipError_t launch_newton_bwd_j(int nj, const float4 *jmem, int ni, const float4 *irec,
                                bool refine, float *gx, float *gy, float *gz, float *gm, int S,
                                float *part, hipStream_t s);
-// Zeroes gtable / gmj and `queue`, then runs both adjoint passes in one
-// persistent launch that takes tasks from `queue`.
+// Zeroes the accumulated per-entry gradients, then runs both adjoint passes
+// in one persistent launch.
 hipError_t launch_table_batch_bwd(const TableBwdArgs &a, const Task *jtasks, int n_jtasks,
-                                  const Task *itasks, int n_itasks, unsigned *queue, int num_cu,
-                                  hipStream_t s);
+                                  const Task *itasks, int n_itasks, int num_cu, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Barnes-Hut tree (tree.hip): device state and the host steps that drive it.
