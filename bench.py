@@ -741,12 +741,27 @@ def table_allpairs(torch, pgh, synth):
 
     sec = time_steps(torch, step, 10, 2)
     ms = timer.mean_ms()
+    # the largest tables (wider workgroups: the table fills most of a CU's
+    # LDS), the (H, G1) form: 2^14 nodes, and 2^13 with the potential
+    names = [pgh.pgh_variant_name(fam, v) for v in range(pgh.pgh_variant_count(fam))]
+    ctx.set_variant(fam, names.index("ki=1 jt=256 u=4 htab"))
+    large = {}
+    for F, with_phi in ((10, False), (9, True)):
+        ctx.build_table(4, F, 3.0 / 256, eps=1.0 / 1280)
+        if with_phi:
+            ctx.build_pot_table(lambda r: -1.0 / (r + 1.0 / 1280) + 1.0 / (3.0 / 256 + 1.0 / 1280))
+        tl = KernelTimer(torch)
+        for _ in range(4):
+            with tl:
+                pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out, phi if with_phi else None)
+        large[f"E4F{F}" + ("_with_potential" if with_phi else "")] = tl.mean_ms()
     ctx.close()
     inter = float(n) * n
     return {"workload": "table_allpairs_uniform_N65536_E4F6", "interactions_per_s": inter / (ms / 1e3),
             "kernel_ms": ms, "step_ms": sec * 1e3,
             "frac_of_peak_20flop": TABLE_FLOPS * inter / (ms / 1e3) / (PEAK_FP32_TFLOPS * 1e12),
-            "ms_per_variant": per, "kernel_ms_with_potential_last_variant": tp.mean_ms()}
+            "ms_per_variant": per, "kernel_ms_with_potential_last_variant": tp.mean_ms(),
+            "kernel_ms_large_tables_htab": large}
 
 
 def tree_code(torch, pgh, synth, sizes=(1 << 20, 1 << 22), n_crit=64,
