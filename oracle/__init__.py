@@ -61,6 +61,8 @@ def lib():
             "pgo_node_s": [i, i, l],
             "pgo_node_r": [i, i, d, l],
             "pgo_lut_index": [d, i, i, P],
+            "pgo_scale_f32": [i, i, d],
+            "pgo_pair_bin": [d, d, d, d, d, d, ctypes.c_float, i, i, P, P],
             "pgo_table_build": [i, i, d, i, P, P],
             "pgo_lut_eval": [d, i, i, P],
             "pgo_lut_items": [l, P, P, P, P, P, P, P, P, i, i, d, P, P, P, P, P],
@@ -85,6 +87,7 @@ def lib():
         }
         ret = {"pgo_s2_R": d, "pgo_s2pp_f": d, "pgo_shape_h": d, "pgo_shape_p": d, "pgo_smax": d,
                "pgo_node_s": d, "pgo_node_r": d, "pgo_lut_index": l, "pgo_lut_eval": d,
+               "pgo_scale_f32": ctypes.c_float, "pgo_pair_bin": l,
                "pgo_tree_build": l, "pgo_tree_groups": l, "pgo_tree_walk": l}
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -172,6 +175,22 @@ def lut_index(s, E, F):
     sk = ctypes.c_double()
     k = lib().pgo_lut_index(float(s), E, F, ctypes.byref(sk))
     return int(k), sk.value
+
+
+def scale_f32(E, F, rcut):
+    """The FP32 scale c_f of the pair's s: the smallest float with
+    fl(fl(rcut^2) c_f + 2) >= s_max."""
+    return float(np.float32(lib().pgo_scale_f32(E, F, float(rcut))))
+
+
+def pair_bin(xi, yi, zi, xj, yj, zj, E, F, rcut):
+    """(k, s_k, clamped) of a pair, the bin taken from its FP32 s (the
+    decision every table function of the oracle makes)."""
+    sk, cl = ctypes.c_double(), ctypes.c_int()
+    k = lib().pgo_pair_bin(float(xi), float(yi), float(zi), float(xj), float(yj), float(zj),
+                           ctypes.c_float(scale_f32(E, F, rcut)), E, F, ctypes.byref(sk),
+                           ctypes.byref(cl))
+    return int(k), sk.value, bool(cl.value)
 
 
 def table_build(E, F, rcut, shape, eps):

@@ -23,6 +23,9 @@
  *     GPU receives, widened exactly, so the quantisation of the inputs is
  *     shared and is not counted as error; finite-difference checks perturb
  *     them in double.
+ *   - The table bin of a pair is the one integer decision of the table
+ *     force: it is taken from the pair's single-precision s, whose bits the
+ *     method reads (pgo_pair_bin); everything else is in double.
  *
  * Parallelism: OpenMP over i-particles (or over independent items), which is
  * how the paper spreads groups of i-particles over cores (Sec. 3.5).
@@ -235,6 +238,53 @@ PGO_EXPORT long pgo_lut_index(double s, int E, int F, double *s_node)
 }
 
 /*
+ * The single-precision scale of the pair's s: the smallest FP32 number c_f
+ * with fl(fl(rcut^2) c_f + 2) >= s_max, so that a pair at exactly rcut lands
+ * on the last node, where the node equation of Sec. 3.4.1 puts rcut.  Found
+ * from the rounded quotient by stepping one float at a time either way.
+ */
+PGO_EXPORT float pgo_scale_f32(int E, int F, double rcut)
+{
+    const double smax = pgo_smax(E, F);
+    const float smaxf = (float)smax;
+    const float rf = (float)rcut;
+    const float r2 = rf * rf;
+    float c = (float)((smax - 2.0) / ((double)rf * (double)rf));
+    while (fmaf(r2, c, 2.0f) < smaxf) c = nextafterf(c, INFINITY);
+    while (fmaf(r2, nextafterf(c, 0.0f), 2.0f) >= smaxf) c = nextafterf(c, 0.0f);
+    return c;
+}
+
+/*
+ * The bin of a pair as the method takes it.  The force procedure of
+ * Sec. 3.4.2 reads the table index off the bits of the single-precision s,
+ * so for a pair whose s lies within a rounding of a node the bin is a
+ * single-precision decision.  It is made here from s formed in FP32 the way
+ * the pair step forms it (d = fl(x_j - x_i) per component, |d|^2 by fused
+ * multiply-adds, s = fl(|d|^2 c_f + 2) with c_f from pgo_scale_f32, clamped
+ * to s_max), while the callers interpolate with s in double.  The force does
+ * not depend on the choice (the interpolant is continuous at the nodes); its
+ * derivatives, which take the bin's slope G1, and the table gradient, which
+ * lands in the bin, do.  Returns k; its node s_k goes to *sk, and whether the
+ * FP32 s sits on the clamp to *clamped.
+ */
+PGO_EXPORT long pgo_pair_bin(double xi, double yi, double zi, double xj, double yj, double zj,
+                             float c_f, int E, int F, double *sk, int *clamped)
+{
+    const float smaxf = (float)pgo_smax(E, F);
+    const float dx = (float)xj - (float)xi;
+    const float dy = (float)yj - (float)yi;
+    const float dz = (float)zj - (float)zi;
+    float r2 = dx * dx;
+    r2 = fmaf(dy, dy, r2);
+    r2 = fmaf(dz, dz, r2);
+    float s = fmaf(r2, c_f, 2.0f);
+    *clamped = s >= smaxf;
+    if (*clamped) s = smaxf;
+    return pgo_lut_index((double)s, E, F, sk);
+}
+
+/*
  * Table of (G0_k, G1_k), interleaved as float[2K] (the paper's
  * Force_table[K][2]).  G0_k = fl32(h(r_k)); G0 at the last node, r = rcut, is
  * set to 0 because f(rcut) = 0.  G1_k = fl32((G0_{k+1} - G0_k)/(s_{k+1} - s_k))
@@ -282,6 +332,7 @@ PGO_EXPORT void pgo_lut_items(long n_items, const int32_t *items, const double *
 {
     const double smax = pgo_smax(E, F);
     const double c = (smax - 2.0) / (rcut * rcut);
+    const float c_f = pgo_scale_f32(E, F, rcut);
     long t;
 #pragma omp parallel for schedule(dynamic, 1)
     for (t = 0; t < n_items; t++) {
@@ -295,9 +346,11 @@ PGO_EXPORT void pgo_lut_items(long n_items, const int32_t *items, const double *
                 const double dz = (double)zj[j] - (double)zi[i];
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 double s = c * r2 + 2.0;
-                if (s > smax) s = smax;
                 double sk;
-                const long k = pgo_lut_index(s, E, F, &sk);
+                int clamped;
+                const long k = pgo_pair_bin(xi[i], yi[i], zi[i], xj[j], yj[j], zj[j], c_f, E, F,
+                                            &sk, &clamped);
+                if (clamped) s = smax;
                 const double g = (double)table[2 * k] + (double)table[2 * k + 1] * (s - sk);
                 const double m = mj[j];
                 sx += m * g * dx;
@@ -492,6 +545,7 @@ PGO_EXPORT void pgo_lut_bwd_items(long n_items, const int32_t *items, const doub
     const long K = 1L << (E + F);
     const double smax = pgo_smax(E, F);
     const double c = (smax - 2.0) / (rcut * rcut);
+    const float c_f = pgo_scale_f32(E, F, rcut);
     memset(gtab, 0, sizeof(double) * 2 * K);
     if (gmj) memset(gmj, 0, sizeof(double) * nj_total);
     if (gtab_abs) memset(gtab_abs, 0, sizeof(double) * 2 * K);
@@ -505,9 +559,11 @@ PGO_EXPORT void pgo_lut_bwd_items(long n_items, const int32_t *items, const doub
                 const double dy = (double)yj[j] - (double)yi[i];
                 const double dz = (double)zj[j] - (double)zi[i];
                 double s = c * (dx * dx + dy * dy + dz * dz) + 2.0;
-                if (s > smax) s = smax;
                 double sk;
-                const long k = pgo_lut_index(s, E, F, &sk);
+                int clamped;
+                const long k = pgo_pair_bin(xi[i], yi[i], zi[i], xj[j], yj[j], zj[j], c_f, E, F,
+                                            &sk, &clamped);
+                if (clamped) s = smax;
                 const double g = (double)table[2 * k] + (double)table[2 * k + 1] * (s - sk);
                 const double wd = (double)wx[i] * dx + (double)wy[i] * dy + (double)wz[i] * dz;
                 const double m = mj[j];
@@ -574,6 +630,7 @@ PGO_EXPORT void pgo_lut_bwd_pos_items(long n_items, const int32_t *items, const 
     const long K = 1L << (E + F);
     const double smax = pgo_smax(E, F);
     const double c = (smax - 2.0) / (rcut * rcut);
+    const float c_f = pgo_scale_f32(E, F, rcut);
     memset(gxi, 0, sizeof(double) * ni_total);
     memset(gyi, 0, sizeof(double) * ni_total);
     memset(gzi, 0, sizeof(double) * ni_total);
@@ -591,10 +648,11 @@ PGO_EXPORT void pgo_lut_bwd_pos_items(long n_items, const int32_t *items, const 
                 const double dy = (double)yj[j] - (double)yi[i];
                 const double dz = (double)zj[j] - (double)zi[i];
                 double s = c * (dx * dx + dy * dy + dz * dz) + 2.0;
-                const int clamped = s >= smax;
-                if (clamped) s = smax;
                 double sk;
-                const long k = pgo_lut_index(s, E, F, &sk);
+                int clamped;
+                const long k = pgo_pair_bin(xi[i], yi[i], zi[i], xj[j], yj[j], zj[j], c_f, E, F,
+                                            &sk, &clamped);
+                if (clamped) s = smax;
                 const double G0 = table[2 * k], G1 = table[2 * k + 1];
                 const double g = G0 + G1 * (s - sk);
                 const double dgds = clamped ? 0.0 : G1;
@@ -663,6 +721,7 @@ PGO_EXPORT void pgo_lut_pot_items(long n_items, const int32_t *items, const doub
     const long K = 1L << (E + F);
     const double smax = pgo_smax(E, F);
     const double c = (smax - 2.0) / (rcut * rcut);
+    const float c_f = pgo_scale_f32(E, F, rcut);
     memset(phi, 0, sizeof(double) * ni_total);
     if (absum) memset(absum, 0, sizeof(double) * ni_total);
     for (long t = 0; t < n_items; t++) {
@@ -676,9 +735,11 @@ PGO_EXPORT void pgo_lut_pot_items(long n_items, const int32_t *items, const doub
                 const double dy = (double)yj[j] - (double)yi[i];
                 const double dz = (double)zj[j] - (double)zi[i];
                 double s = c * (dx * dx + dy * dy + dz * dz) + 2.0;
-                if (s > smax) s = smax;
                 double sk;
-                const long k = pgo_lut_index(s, E, F, &sk);
+                int clamped;
+                const long k = pgo_pair_bin(xi[i], yi[i], zi[i], xj[j], yj[j], zj[j], c_f, E, F,
+                                            &sk, &clamped);
+                if (clamped) s = smax;
                 const double P0 = ptable[2 * k], P1 = ptable[2 * k + 1];
                 sp += mj[j] * (P0 + P1 * (s - sk));
                 const double width = (k + 1 < K) ? pgo_node_s(E, F, k + 1) - sk : 0.0;

@@ -380,6 +380,59 @@ def test_table_adjoint_largest_table(pgh, ctx):
     plan.free()
 
 
+@pytest.mark.parametrize("E,F", [(4, 6), (4, 7), (5, 8)])
+def test_table_adjoint_many_small_lists(pgh, ctx, E, F):
+    """40000 short lists (1..8 rows against 1..24 shared j-entries): about
+    80000 adjoint tasks, more than four per resident wave, so the waves of
+    each workgroup take their tasks from its LDS counter; for E + F = 10, 11
+    and 13 (four, two and one workgroup per CU).  Every gradient, and the
+    i-side gradient from the moments, against the oracle."""
+    import torch
+    rng = np.random.default_rng(48 + F)
+    items, i_at = [], 0
+    for _ in range(40000):
+        i_at += int(rng.integers(0, 2))
+        ni, nj = int(rng.integers(1, 9)), int(rng.integers(1, 25))
+        items.append((i_at, ni, 0, nj))
+        i_at += ni
+    ni_total, nj_total = i_at, 20000
+    items = np.array([(a, b, int(rng.integers(0, nj_total - d + 1)), d) for a, b, _, d in items],
+                     np.int32)[rng.permutation(len(items))]
+    xi, yi, zi = (rng.random(ni_total).astype(np.float32) * 0.1 for _ in range(3))
+    xj, yj, zj = (rng.random(nj_total).astype(np.float32) * 0.1 for _ in range(3))
+    mj = rng.uniform(0.5, 1.5, nj_total).astype(np.float32) / nj_total
+    w = [rng.standard_normal(ni_total).astype(np.float32) for _ in range(3)]
+    rcut, eps = 0.06, 0.004
+    rc = float(np.float32(rcut))
+    table = ctx.build_table(E, F, rcut, eps=eps)
+    plan = ctx.plan(items, ni_total, nj_total)
+    di = to_dev(xi, yi, zi, *w)
+    dj = to_dev(xj, yj, zj, mj)
+    gi = [torch.full((ni_total,), 7.0, device="cuda") for _ in range(3)]
+    gj = [torch.full((nj_total,), 7.0, device="cuda") for _ in range(3)]
+    gt = torch.empty(table.size, device="cuda")
+    gm = torch.empty(nj_total, device="cuda")
+    pgh.pgh_batch_table_bwd(ctx.h, plan.h, *di[:3], *dj, *di[3:], gt, gm, *gi, *gj)
+    r = oracle.lut_bwd_pos_items(items, xi, yi, zi, xj, yj, zj, mj, *w, E, F, rc, table,
+                                 scales=True)
+    rt, rm, at, am = oracle.lut_bwd_items(items, xi, yi, zi, xj, yj, zj, mj, *w, E, F, rc, table,
+                                          scales=True)
+    _gate(np.stack(to_host(*gi)), np.stack(r[0:3]), r[6], "gxi")
+    _gate(np.stack(to_host(*gj)), np.stack(r[3:6]), r[7], "gxj")
+    _table_gate(to_host(gt)[0], rt, at, E, F, "gtable")
+    _gate(to_host(gm)[0], rm, am, "gmj")
+    out = [torch.empty(ni_total, device="cuda") for _ in range(3)]
+    mom = torch.empty(7 * ni_total, device="cuda")
+    pgh.pgh_batch_table_moments(ctx.h, plan.h, *di[:3], *dj, *out, mom)
+    gi2 = [torch.full((ni_total,), 7.0, device="cuda") for _ in range(3)]
+    pgh.pgh_batch_table_bwd_moments(ctx.h, plan.h, *di[:3], *dj, *di[3:], mom, gt, gm, *gi2,
+                                    None, None, None)
+    _gate(np.stack(to_host(*gi2)), np.stack(r[0:3]), r[6], "gxi (moments)")
+    _table_gate(to_host(gt)[0], rt, at, E, F, "gtable (moments call)")
+    _gate(to_host(gm)[0], rm, am, "gmj (moments call)")
+    plan.free()
+
+
 def test_table_adjoint_graph_replays(pgh, ctx):
     """The table adjoint (zeroing prologue, persistent kernel, summing kernel)
     captured in a graph and replayed several times with eager work in

@@ -287,3 +287,82 @@ def test_ht_form_is_one_rounding_of_the_paper_form():
     total = pp + np.array([oracle.s2_R(v, rcut) for v in rr])
     exact = np.array([oracle.s2_R(v, eps) for v in rr])
     assert np.max(np.abs(total - exact) / exact) < 1e-3
+
+
+def _nearest_f32(fr):
+    """The FP32 number nearest to the rational fr, ties to an even last bit
+    (one correctly rounded operation, as IEEE arithmetic gives)."""
+    from fractions import Fraction
+    f = np.float32(float(fr))
+    best = None
+    for c in (np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))):
+        key = (abs(Fraction(float(c)) - fr), _bits(c) & 1)
+        if best is None or key < best[0]:
+            best = (key, c)
+    return best[1]
+
+
+@pytest.mark.parametrize("E,F,rcut", [(4, 6, 3.0 / 256), (4, 5, 4.6875e-2), (3, 8, 0.2),
+                                      (6, 7, 1.0 / 32), (2, 10, 0.06)])
+def test_fp32_scale_is_the_smallest_float_reaching_smax(E, F, rcut):
+    """The oracle's FP32 scale c_f: fl(fl(rcut^2) c_f + 2) reaches s_max and
+    the next smaller float does not (one rounding, from exact rationals),
+    and c_f lies within a few ulps of (s_max - 2)/rcut^2."""
+    from fractions import Fraction
+    r = np.float32(rcut)
+    r2 = _nearest_f32(Fraction(float(r)) ** 2)
+    smaxf = np.float32(oracle.smax(E, F))
+    c = np.float32(oracle.scale_f32(E, F, float(r)))
+
+    def s_of(cv):
+        return _nearest_f32(Fraction(float(r2)) * Fraction(float(cv)) + 2)
+
+    assert s_of(c) >= smaxf
+    assert s_of(np.nextafter(c, np.float32(0))) < smaxf
+    exact = (Fraction(oracle.smax(E, F)) - 2) / Fraction(float(r)) ** 2
+    assert abs(Fraction(float(c)) - exact) <= 4 * Fraction(float(np.spacing(c)))
+
+
+@pytest.mark.parametrize("E,F,rcut", [(4, 6, 3.0 / 256), (3, 8, 0.2)])
+def test_pair_bin_is_the_fp32_decision(E, F, rcut):
+    """The bin every table function of the oracle uses is the bit index of
+    the FP32 s (Sec. 3.4.2 reads it off the bits): d by FP32 subtractions,
+    |d|^2 and s by single-rounding fused multiply-adds (emulated here from
+    exact rationals), clamped at s_max.  Random pairs, and pairs placed at
+    node radii, where the FP32 and the double s can fall on either side of a
+    node: there the two decisions differ, and only there (s within a few FP32
+    roundings of the node)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(11 + F)
+    r = np.float32(rcut)
+    c = np.float32(oracle.scale_f32(E, F, float(r)))
+    smax = oracle.smax(E, F)
+    smaxf = np.float32(smax)
+    K = 1 << (E + F)
+    pairs = [rng.random(6).astype(np.float32) * np.float32(0.8 * rcut) for _ in range(1500)]
+    for k in range(1, K, max(1, K // 300)):  # along x at the radius of node k
+        xj = np.float32(oracle.node_r(E, F, float(r), k))
+        pairs.append(np.array([0, 0, 0, xj, 0, 0], np.float32))
+    pairs.append(np.array([0, 0, 0, r, 0, 0], np.float32))          # exactly rcut
+    pairs.append(np.array([0, 0, 0, r * np.float32(1.5), 0, 0], np.float32))
+    flips = 0
+    for p in pairs:
+        d = [np.float32(p[3 + a] - p[a]) for a in range(3)]
+        r2 = _nearest_f32(Fraction(float(d[0])) ** 2)
+        r2 = _nearest_f32(Fraction(float(d[1])) ** 2 + Fraction(float(r2)))
+        r2 = _nearest_f32(Fraction(float(d[2])) ** 2 + Fraction(float(r2)))
+        s = _nearest_f32(Fraction(float(r2)) * Fraction(float(c)) + 2)
+        clamped = bool(s >= smaxf)
+        s = min(s, smaxf)
+        want = _bit_index(s, E, F)
+        k, sk, cl = oracle.pair_bin(*[float(v) for v in p], E, F, float(r))
+        assert (k, cl) == (want, clamped), (p, k, want)
+        assert sk == oracle.node_s(E, F, k)
+        # the decision from s in double (the pair's own d, the exact scale)
+        sd = (smax - 2.0) / float(r) ** 2 * sum(float(v) ** 2 for v in d) + 2.0
+        kd, _ = oracle.lut_index(min(sd, smax), E, F)
+        if kd != k:
+            flips += 1
+            edge = oracle.node_s(E, F, max(k, kd))
+            assert abs(sd - edge) <= 4 * float(np.spacing(np.float32(edge))), (p, k, kd)
+    assert flips > 0  # the node-radius pairs reach both sides
