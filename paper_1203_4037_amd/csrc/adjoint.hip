@@ -390,7 +390,9 @@ __device__ __forceinline__ void wave_sync()
 // [n_m, n_m + n_i): i-major tasks (only for the i-side position gradient),
 // an i-chunk of <= 64 against a part of its j-list, j-records streamed:
 //   dL/dr_i   -= m_j [ g w_i + 2c G1_k (w_i . d) d ]
-// summed per lane and added to gxi with one atomic per i and task.
+// summed per lane and added to gxi with one atomic per i and task, or
+// stored when every row is in exactly one such task (A.istore: no list cut
+// into parts and no row left out, so no zeroing pass either).
 //
 // Tasks of each kind are sorted longest first.  With at most four per wave
 // every wave follows a static order; with more, the waves of a workgroup
@@ -640,9 +642,18 @@ __global__ void __launch_bounds__(64 * W) k_table_bwd(TableBwdArgs A, const Task
             };
             lanes_sum(S), lanes_sum(Vx), lanes_sum(Vy), lanes_sum(Vz);
             if (active && ph == 0) {
-                atomicAdd(&A.gxi[i], -__builtin_fmaf(c2, Vx, S * wx));
-                atomicAdd(&A.gyi[i], -__builtin_fmaf(c2, Vy, S * wy));
-                atomicAdd(&A.gzi[i], -__builtin_fmaf(c2, Vz, S * wz));
+                const float gx = -__builtin_fmaf(c2, Vx, S * wx);
+                const float gy = -__builtin_fmaf(c2, Vy, S * wy);
+                const float gz = -__builtin_fmaf(c2, Vz, S * wz);
+                if (A.istore) {
+                    A.gxi[i] = gx;
+                    A.gyi[i] = gy;
+                    A.gzi[i] = gz;
+                } else {
+                    atomicAdd(&A.gxi[i], gx);
+                    atomicAdd(&A.gyi[i], gy);
+                    atomicAdd(&A.gzi[i], gz);
+                }
             }
         }
         t = __builtin_amdgcn_readfirstlane(tn);
@@ -837,7 +848,8 @@ hipError_t launch_table_batch_bwd(const TableBwdArgs &A, const Task *jtasks, int
         add(A.gmj, A.nj_total);
         add(A.gxj, A.nj_total), add(A.gyj, A.nj_total), add(A.gzj, A.nj_total);
     }
-    if (!from_mom) add(A.gxi, A.ni_total), add(A.gyi, A.ni_total), add(A.gzi, A.ni_total);
+    if (!from_mom && !A.istore)
+        add(A.gxi, A.ni_total), add(A.gyi, A.ni_total), add(A.gzi, A.ni_total);
     hipError_t e = hipSuccess;
     if (nz > 0) {
         const int zb = std::max(1, std::min(1024, (longest + 255) / 256));

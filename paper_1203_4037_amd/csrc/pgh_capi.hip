@@ -52,6 +52,8 @@ struct pgh_plan {
     bool j_disjoint;
     // the ranges cover every row / entry (no gap to test against them)
     bool i_cover, j_cover;
+    // every i-row is in exactly one i-major task of the table adjoint
+    bool i_once;
     // partial moments of split chunks (pgh_batch_table_moments), grown on
     // its first call on the plan: two float4 per partial sum
     float4 *mpartial;
@@ -292,7 +294,7 @@ void reset_plan(pgh_plan *p)
     p->jtasks = p->itasks = nullptr;
     p->irange = p->jrange = nullptr;
     p->n_irange = p->n_jrange = 0;
-    p->j_disjoint = p->i_cover = p->j_cover = false;
+    p->j_disjoint = p->i_cover = p->j_cover = p->i_once = false;
     p->adj_built = false;
     p->n_jtasks = p->n_itasks = 0;
     p->n_tasks = 0;
@@ -506,8 +508,8 @@ int pgh_open(pgh_ctx **out, int device, void *hip_stream)
     // is reported by that entry point, which then refuses to run)
     (void)resolve_scratch(device);
     e = hipMalloc((void **)&c->tab, sizeof(float2) << kMaxTableBits);
-    if (e == hipSuccess)
-        e = hipMalloc((void **)&c->gcopy, (sizeof(float2) << kMaxAdjTableBits) * kGradCopies);
+    const size_t gcopy_bytes = (sizeof(float2) << kMaxAdjTableBits) * kGradCopies;
+    if (e == hipSuccess) e = hipMalloc((void **)&c->gcopy, gcopy_bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&c->ptab, sizeof(float2) << kMaxPotTableBits);
     if (e != hipSuccess) {
         g_open_error = std::string("hipMalloc(table): ") + hipGetErrorString(e);
@@ -519,8 +521,7 @@ int pgh_open(pgh_ctx **out, int device, void *hip_stream)
     }
     // the table adjoint's gradient copies start at zero and are put back to
     // zero by the kernel that sums them (k_table_bwd_tail)
-    if (hipMemsetAsync(c->gcopy, 0, (sizeof(float2) << kMaxAdjTableBits) * kGradCopies,
-                       c->stream) != hipSuccess ||
+    if (hipMemsetAsync(c->gcopy, 0, gcopy_bytes, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         g_open_error = "clearing the table-gradient scratch failed";
         (void)hipFree(c->tab);
@@ -1017,6 +1018,19 @@ int build_adjoint_tasks(pgh_ctx *c, pgh_plan *p)
     // disjoint ranges inside [0, total) whose lengths add up to it cover it
     p->i_cover = ni_sum == p->ni_total;
     p->j_cover = disjoint && nj_sum == p->nj_total;
+    // each row in exactly one i-major task (no list cut into parts, no empty
+    // list): the i-side gradient is then stored, with no zeroing pass
+    p->i_once = p->i_cover;
+    if (p->i_once) {
+        std::vector<unsigned char> seen((size_t)p->ni_total, 0);
+        for (const Task &t : it_tasks)
+            for (int r = t.i_off; r < t.i_off + t.n_i; ++r) {
+                if (seen[(size_t)r]) p->i_once = false;
+                seen[(size_t)r] = 1;
+            }
+        for (size_t r = 0; r < seen.size() && p->i_once; ++r)
+            if (!seen[r]) p->i_once = false;
+    }
     p->adj_built = true;
     return PGH_OK;
 }
@@ -1250,6 +1264,7 @@ int table_bwd(pgh_ctx *c, const pgh_plan *p, const float *xi, const float *yi, c
     A.jdisjoint = p->j_disjoint ? 1 : 0;
     A.icover = p->i_cover ? 1 : 0;
     A.jcover = p->j_cover ? 1 : 0;
+    A.istore = p->i_once ? 1 : 0;
     A.jrange = p->jrange;
     A.n_jrange = p->n_jrange;
     PGH_HIP(c, launch_table_batch_bwd(A, p->jtasks, p->n_jtasks, p->itasks, p->n_itasks,

@@ -133,6 +133,9 @@ struct TableBwdArgs {
     const int2 *jrange;
     int n_jrange;
     int icover, jcover;  // the i- (j-) ranges cover every row (entry)
+    // every i-row is in exactly one i-major task: the i-side gradient is
+    // stored, not added, and needs no zeroing
+    int istore;
     float *gxj, *gyj, *gzj;  // j-side position gradient (or NULL)
     int ni_total, nj_total;
 };
