@@ -717,8 +717,13 @@ def table_allpairs(torch, pgh, synth):
     out = [torch.empty(n, device="cuda") for _ in range(3)]
     fam = pgh.PGH_FAMILY_TABLE_ALLPAIRS
     per = {}
+    # ten untimed calls first: after the idle table upload the first
+    # launches run up to a quarter slower
+    for _ in range(10):
+        pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out, None)
     for v in range(pgh.pgh_variant_count(fam)):
         ctx.set_variant(fam, v)
+        pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out, None)  # untimed
         t = KernelTimer(torch)
         for _ in range(4):
             with t:
@@ -728,6 +733,7 @@ def table_allpairs(torch, pgh, synth):
     # not needed for timing: any table on the same bins costs the same)
     ctx.build_pot_table(lambda r: -1.0 / (r + 1.0 / 1280) + 1.0 / (3.0 / 256 + 1.0 / 1280))
     phi = torch.empty(n, device="cuda")
+    pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out, phi)  # untimed
     tp = KernelTimer(torch)
     for _ in range(4):
         with tp:
@@ -750,6 +756,8 @@ def table_allpairs(torch, pgh, synth):
         ctx.build_table(4, F, 3.0 / 256, eps=1.0 / 1280)
         if with_phi:
             ctx.build_pot_table(lambda r: -1.0 / (r + 1.0 / 1280) + 1.0 / (3.0 / 256 + 1.0 / 1280))
+        for _ in range(3):  # untimed
+            pgh.pgh_calc_table(ctx.h, n, dev[0], dev[1], dev[2], *out, phi if with_phi else None)
         tl = KernelTimer(torch)
         for _ in range(4):
             with tl:
