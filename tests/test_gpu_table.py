@@ -327,7 +327,8 @@ def test_potential_table_state_errors(pgh, ctx):
 def test_largest_tables_with_potential(pgh, ctx, E, F):
     """E + F = 12 (4096 nodes, 64 KiB of force and potential table in LDS)
     and 13, the largest with the potential (128 KiB, one workgroup per CU),
-    all-pairs and batched, both table forms, against the oracle."""
+    all-pairs and batched, both table forms, with and without the potential,
+    against the oracle."""
     n = 4096
     rcut, eps = 0.2, 0.01
     x, y, z = synth.uniform_box(n, 73, box=0.4)
@@ -352,6 +353,10 @@ def test_largest_tables_with_potential(pgh, ctx, E, F):
         assert rms(e) <= 1e-5 and e.max() <= 1e-3, (v, rms(e), e.max())
         ep = np.abs(to_host(out[3])[0] - rp)[sp > 0] / sp[sp > 0]
         assert rms(ep) <= 1e-5 and ep.max() <= 1e-3, (v, rms(ep), ep.max())
+        # the force alone (the kernels without the potential table)
+        a2 = np.stack(to_host(*plan.table(*d[:3], *d)))
+        e2 = norm_vec_err(a2[:, has], np.stack(ra[:3])[:, has], ra[3][has])
+        assert rms(e2) <= 1e-5 and e2.max() <= 1e-3, (v, rms(e2), e2.max())
     whole = np.array([[0, n, 0, n]], np.int32)
     fam = pgh.PGH_FAMILY_TABLE_ALLPAIRS
     for v in range(pgh.pgh_variant_count(fam)):
