@@ -403,11 +403,13 @@ hipError_t launch_table_batch_moments(const BatchArgs &a0, int num_cu, hipStream
     // two-wave workgroups: their LDS holds a CU to six waves per SIMD, so
     // the seven moment sums per i-particle fit in registers without spills
     // (16.3 us against 18.1 us with four-wave workgroups on 8^3 cell lists
-    // of 65536 particles); a table of 2^12 nodes or more leaves room for two
-    // workgroups per CU or one, which then run 16 waves each
+    // of 65536 particles), and the next record read from LDS before the
+    // current pair's table gathers are waited for (16.0 against 16.3 us); a
+    // table of 2^12 nodes or more leaves room for two workgroups per CU or
+    // one, which then run 16 waves each
     const int tb = a0.E + a0.F;
     const int wpb = tb <= 10 ? 2 : 16;
-    const TableKernel k = tb <= 10   ? k_batch_table<1, 2, 10, false, false, 2, false, true>
+    const TableKernel k = tb <= 10   ? k_batch_table<1, 2, 10, false, false, 2, true, true>
                           : tb <= 12 ? k_batch_table<1, 2, 12, false, false, 16, false, true>
                                      : k_batch_table<1, 2, 13, false, false, 16, false, true>;
     BatchArgs a = a0;
