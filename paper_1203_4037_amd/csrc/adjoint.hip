@@ -417,8 +417,10 @@ __global__ void __launch_bounds__(64 * W) k_table_bwd(TableBwdArgs A, const Task
     float *gt = dyn + 2 * K;       // 2K gradient accumulators
     // per wave: 64 i-records (x, y, z, wx) or j-records, and the (wy, wz)
     // of the i-records
-    __shared__ float4 buf[W][64];
-    __shared__ float2 wbuf[W][64];
+    // (4 records of padding: the j-major loop reads one record ahead, up to
+    // record 64 + 3, and leaves it unused)
+    __shared__ float4 buf[W][68];
+    __shared__ float2 wbuf[W][68];
     __shared__ unsigned wg_next;  // the next position in the workgroup's sequence
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x == 0) wg_next = W;
@@ -502,19 +504,34 @@ __global__ void __launch_bounds__(64 * W) k_table_bwd(TableBwdArgs A, const Task
                     pw = make_float2(A.wy[i], A.wz[i]);
                 }
             };
-            auto pair = [&](const float4 p, const float2 w) {
-                const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
-                float r2 = dx * dx;
-                r2 = __builtin_fmaf(dy, dy, r2);
-                r2 = __builtin_fmaf(dz, dz, r2);
+            // a pair in two halves: the head forms s and issues the table
+            // gather, the tail uses it, so that the next record can be read
+            // from LDS in between
+            struct Head {
+                float dx, dy, dz, ds, wd;
+                unsigned off;
+                float2 g01;
+            };
+            auto head = [&](const float4 p, const float2 w) {
+                Head h;
+                h.dx = qx - p.x, h.dy = qy - p.y, h.dz = qz - p.z;
+                float r2 = h.dx * h.dx;
+                r2 = __builtin_fmaf(h.dy, h.dy, r2);
+                r2 = __builtin_fmaf(h.dz, h.dz, r2);
                 const unsigned u = min(__float_as_uint(__builtin_fmaf(r2, kc.c, 2.0f)), kc.smax_bits);
-                const unsigned off = (u >> kc.sh) & kc.am;  // 8 k for bin k
-                const float ds = __uint_as_float(u) - __uint_as_float(u & kc.hm);
-                float wd = p.w * dx;
-                wd = __builtin_fmaf(w.x, dy, wd);
-                wd = __builtin_fmaf(w.y, dz, wd);
+                h.off = (u >> kc.sh) & kc.am;  // 8 k for bin k
+                h.ds = __uint_as_float(u) - __uint_as_float(u & kc.hm);
+                float wd = p.w * h.dx;
+                wd = __builtin_fmaf(w.x, h.dy, wd);
+                h.wd = __builtin_fmaf(w.y, h.dz, wd);
+                if (want_m || want_xj) h.g01 = *(const float2 *)(tab + h.off);
+                return h;
+            };
+            auto tail = [&](const Head &h, const float4 p, const float2 w) {
+                const float dx = h.dx, dy = h.dy, dz = h.dz, ds = h.ds, wd = h.wd;
+                const unsigned off = h.off;
                 if (want_m || want_xj) {
-                    const float2 g01 = *(const float2 *)(tab + off);
+                    const float2 g01 = h.g01;
                     const float g = __builtin_fmaf(g01.y, ds, g01.x);
                     if (want_m) G = __builtin_fmaf(g, wd, G);
                     if (want_xj) {
@@ -537,6 +554,7 @@ __global__ void __launch_bounds__(64 * W) k_table_bwd(TableBwdArgs A, const Task
                     }
                 }
             };
+            auto pair = [&](const float4 p, const float2 w) { tail(head(p, w), p, w); };
             load(0);
             for (int base = 0; base < tk.n_j; base += 64) {
                 wave_sync();
@@ -546,11 +564,22 @@ __global__ void __launch_bounds__(64 * W) k_table_bwd(TableBwdArgs A, const Task
                 if (base + 64 < tk.n_j) load(base + 64);
                 const int cnt = min(64, tk.n_j - base);
                 if (cnt == 64) {
+                    // the next record is read before this pair's table gather
+                    // is waited for (the last read, past the tile's 64
+                    // records, lands in its padding and goes unused)
                     const int full = 64 >> jlog;
-#pragma unroll 4
+                    float4 p = tile[ph];
+                    float2 w = wtile[ph];
+#pragma unroll 2
                     for (int ii = 0; ii < full; ++ii) {
-                        const int r = (ii << jlog) + ph;
-                        pair(tile[r], wtile[r]);
+                        const Head h = head(p, w);
+                        const int rn = ((ii + 1) << jlog) + ph;
+                        const float4 pn = tile[rn];
+                        const float2 wn = wtile[rn];
+                        __builtin_amdgcn_sched_barrier(0);
+                        tail(h, p, w);
+                        p = pn;
+                        w = wn;
                     }
                 } else {
                     // records past cnt are zero-weight padding
